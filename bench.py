@@ -1,0 +1,209 @@
+"""Throughput of plane-wise multi-view Richardson-Lucy deconvolution on one GPU.
+
+One step = one whole deconvolution of the workload (reslice + convert the
+uint16 observations, ψ^0, then every RL iteration) with the inputs already
+resident in device memory.  Prints one JSON line (see the keys below).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config vol512]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+# fp32 vector FMA without packed instructions: 256 CUs × 4 SIMDs × 16 lanes ×
+# 2 flop × 2.4 GHz (the library is built with packed FP32 disabled)
+ALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pass_work(spec, kind, Y, Z, X):
+    """Algorithmic bytes and flops of one forward / backward launch over all planes.
+
+    forward (all V views from one ψ): read ψ, read φ_v, write r_v:
+        bytes = 4 + 8V per voxel;  flops = V · 2 · (kz + kx) (two 1D passes of FMAs)
+    backward: read r_v, read ψ, write ψ:  bytes = 4V + 8;  same flops.
+    """
+    V = spec.n_views
+    vox = Y * Z * X
+    k = spec.psf_k
+    if spec.update == "simultaneous":
+        b = (4 + 8 * V) if kind == "forward" else (4 * V + 8)
+        f = V * 2 * (k + k)
+    else:
+        b = 12 if kind == "forward" else 12
+        f = 2 * (k + k)
+    return vox * b, vox * f
+
+
+def cpu_baseline(spec, vol, iters):
+    import numpy as np
+
+    import oracle
+
+    y = spec.n_planes // 2
+    sub = [np.ascontiguousarray(s[:, y:y + 1, :]) for s in vol["stacks"]]
+    t0 = time.perf_counter()
+    oracle.deconvolve(sub, [p.astype(np.float64) for p in vol["psfs"]], iters, update=spec.update)
+    dt = time.perf_counter() - t0
+    vox_it = spec.n_z * spec.n_x * iters
+    return {"value": vox_it / dt, "unit": "voxel-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 of {spec.n_planes} planes (plane {y}), all {iters} iterations, "
+                      f"{spec.n_views} views, direct FP64 convolution, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="vol512")
+    ap.add_argument("--update", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    from synthetic import CONFIGS, make_volume
+
+    spec = CONFIGS[args.config]
+    if args.update:
+        spec.update = args.update
+    log(f"generating {spec.name}: {spec.n_views} views, {spec.n_planes} planes of {spec.n_z}x{spec.n_x}")
+    t0 = time.perf_counter()
+    vol = make_volume(spec, truth=False)
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+
+    import numpy as np
+    import torch
+
+    from paper_1503_07998_amd import api
+
+    dev = torch.device("cuda:0")
+    obs = [torch.from_numpy(s).to(dev) for s in vol["stacks"]]
+    Y, Z, X = spec.n_planes, spec.n_z, spec.n_x
+    layout = "stack_zyx"
+    d = api.Deconvolver(spec.n_views, Z, X, 0)
+    for v, p in enumerate(vol["psfs"]):
+        d.set_psf(v, p)
+    est = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
+    obs_dtype = "u16" if spec.obs_dtype == "u16" else "f32"
+
+    def make(timing):
+        return api.make_run(Y, spec.iters, update=spec.update, boundary=spec.boundary,
+                            obs_dtype=obs_dtype, layout=layout, timing=timing)
+
+    run = make(False)
+    nbytes = api.mvd_workspace_bytes(d.ctx, run)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    wptr = (ws.data_ptr() + 255) // 256 * 256
+    runs = {}
+    for timing in (False, True):
+        r = make(timing)
+        r.workspace = wptr
+        r.workspace_bytes = nbytes
+        runs[timing] = r
+    stream = torch.cuda.current_stream()
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        api.mvd_deconvolve_planes(d.ctx, obs, est, runs[False], stream)
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps, launch durations recorded with HIP events
+    api.mvd_get_timing(d.ctx, reset=True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        api.mvd_deconvolve_planes(d.ctx, obs, est, runs[True], stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tim = api.mvd_get_timing(d.ctx, reset=True)
+    ms_step = wall * 1e3 / args.steps
+    vox_it = spec.voxels * spec.iters
+    value = vox_it / (ms_step / 1e3)
+
+    # untimed-event check of the same step (events themselves cost a little)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        api.mvd_deconvolve_planes(d.ctx, obs, est, runs[False], stream)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t1) * 1e3 / args.steps
+
+    kinds = {}
+    for kind in ("forward", "backward"):
+        n, ms = tim[kind]
+        if n:
+            b, f = pass_work(spec, kind, Y, Z, X)
+            avg = ms / n / 1e3
+            kinds[kind] = dict(launches=n, avg_ms=avg * 1e3, bytes=b, flops=f,
+                               gbs=b / avg / 1e9, tflops=f / avg / 1e12)
+    dom = max(kinds, key=lambda k: kinds[k]["avg_ms"] * kinds[k]["launches"])
+    kd = kinds[dom]
+    t_hbm = kd["bytes"] / HBM_PEAK
+    t_alu = kd["flops"] / ALU_PEAK
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": kd["flops"] / (kd["avg_ms"] / 1e3) / 1e12,
+                "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": kd["bytes"] / (kd["avg_ms"] / 1e3) / 1e9,
+                "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"{dom} pass (sep_{dom}_kernel, K={spec.psf_k})"
+    roof["hbm_frac_algorithmic"] = kd["bytes"] / (kd["avg_ms"] / 1e3) / HBM_PEAK
+
+    it_ms = sum(kinds[k]["avg_ms"] * kinds[k]["launches"] for k in kinds) / args.steps
+    out = {
+        "metric": "voxel-iterations/s",
+        "value": value,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{spec.name}: {spec.n_views} views, {Y} planes of {Z}x{X}, "
+                         f"{spec.psf_k}x{spec.psf_k} Gaussian PSFs (sx={spec.psf_sigma[0]}, "
+                         f"sz={spec.psf_sigma[1]}, view 1 rotated 90 deg), {spec.obs_dtype} Poisson "
+                         f"observations of blob nuclei, {spec.iters} iterations, {spec.update}, "
+                         f"{spec.boundary} boundary"),
+            "voxels": spec.voxels, "iterations": spec.iters, "views": spec.n_views,
+            "psf": spec.psf_k, "update": spec.update, "parallelism": "single GPU",
+        },
+        "ms_per_step_without_events": ms_plain,
+        "iterations_only_value": vox_it / (it_ms / 1e3),
+        "kernels": kinds,
+        "roofline": roof,
+        "paper_context": "GTX TITAN Black, 512^3 padded, 2 views, 10 iterations: 4.0 s "
+                         "(3.36e8 voxel-iterations/s), Supplementary Table 1",
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(spec, vol, spec.iters)
+    d.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

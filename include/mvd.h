@@ -1,0 +1,203 @@
+/*
+ * mvd.h — C ABI of the plane-wise multi-view Richardson-Lucy deconvolution
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * Method (Schmid & Huisken, "Real-time multi-view deconvolution"):
+ *   ψ^{t+1} = ψ^t · Π_v [ (φ_v / (ψ^t ∗ P_v)) ∗ X_v ]
+ * (Supplementary Note 1, update equation; Supplementary Note 2 §1 for the
+ * back-projector X_v), applied independently to every plane orthogonal to the
+ * rotation axis with a 2D PSF per view (Results, second paragraph; Fig. 1a).
+ *
+ * Conventions shared by every entry point
+ *   - A volume is Y planes of Z rows × X columns.  The rotation axis is Y, the
+ *     camera row axis: plane y is the Z×X image made of camera row y of every
+ *     slice z.  Plane data is row-major "[Y][Z][X]" (X fastest).  Camera-ordered
+ *     stacks are "[Z][Y][X]".
+ *   - PSF taps are host float32 "[kz][kx]" (rows = Z offsets, columns = X
+ *     offsets), odd sides in [1, MVD_MAX_K], finite, non-negative, not all 0.
+ *     The centre tap is (kz-1)/2, (kx-1)/2.  Taps are used as given (no
+ *     renormalisation).
+ *   - Convolution (a ∗ k)[z][x] = Σ_j Σ_i k[j][i] · ã[z+Rz−j][x+Rx−i] with ã
+ *     zero outside the plane (MVD_BOUNDARY_ZERO: the linear convolution that a
+ *     Fourier convolution padded to data + PSF size computes, Supplementary
+ *     Table 1 caption) or wrapped (MVD_BOUNDARY_PERIODIC).
+ *   - Ratio guard: φ/b where b > 1e-6, else 1.
+ *   - Every call that takes a stream only enqueues work on it (the library's
+ *     calls are asynchronous, Supplementary Note 2 §3); the caller keeps the
+ *     buffers alive until the stream has completed.  stream may be NULL (the
+ *     device's null stream).
+ *   - Device buffers (observations, estimate, checkpoints, workspace,
+ *     gradients) belong to the caller.  A context owns only host copies of the
+ *     taps, their derived 1D factors and a few KB of device memory for taps.
+ *   - Errors: every call returns an mvd_status.  On MVD_ERR_ARG, MVD_ERR_STATE
+ *     or MVD_ERR_WORKSPACE nothing has been enqueued.  mvd_last_error() gives a
+ *     message.  A context is not thread-safe; separate contexts may be used
+ *     from separate threads and streams.
+ */
+#ifndef MVD_H
+#define MVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MVD_ABI_VERSION 1
+#define MVD_MAX_VIEWS 8
+#define MVD_MAX_K 63
+#define MVD_DEVICE_NONE (-1) /* host-only context: PSF setup and validation only */
+
+typedef struct mvd_ctx mvd_ctx;
+
+typedef enum {
+  MVD_OK = 0,
+  MVD_ERR_ARG = -1,         /* invalid argument; nothing enqueued */
+  MVD_ERR_STATE = -2,       /* call out of order (e.g. a PSF not set) */
+  MVD_ERR_WORKSPACE = -3,   /* workspace missing or too small */
+  MVD_ERR_DEVICE = -4,      /* no usable GPU / host-only context */
+  MVD_ERR_LAUNCH = -5,      /* HIP launch or runtime failure */
+  MVD_ERR_UNSUPPORTED = -6, /* valid but not supported combination */
+  MVD_ERR_ALLOC = -7        /* small internal allocation failed */
+} mvd_status;
+
+typedef enum { MVD_U16 = 1, MVD_F32 = 2 } mvd_dtype;
+
+typedef enum {
+  MVD_STACK_ZYX = 1,  /* camera-ordered stack [Z][Y][X]; resliced on the device */
+  MVD_PLANES_YZX = 2  /* already planes [Y][Z][X] */
+} mvd_layout;
+
+/* Back-projector X_v (Supplementary Note 2 §1).  Compound kernels are built
+ * on the host in float64 from all views' PSFs, cropped to the view's PSF size
+ * and normalised to unit sum:
+ *   FLIPPED          X_v = P_v^*  ("Independent")
+ *   EFFICIENT_BAYES  X_v = N( P_v^* ⊙ Π_{w≠v} C(P_v^* ⊛ P_w ⊛ P_w^*) )
+ *   OPT1             X_v = N( P_v^* ⊙ Π_{w≠v} C(P_v^* ⊛ P_w) )
+ *   OPT2             X_v = N( (P_v^*)^{⊙V} )
+ *   EXPLICIT         X_v given by the caller, used as is.                    */
+typedef enum {
+  MVD_BACK_FLIPPED = 0,
+  MVD_BACK_EFFICIENT_BAYES = 1,
+  MVD_BACK_OPT1 = 2,
+  MVD_BACK_OPT2 = 3,
+  MVD_BACK_EXPLICIT = 4
+} mvd_back;
+
+/* SIMULTANEOUS: all views' corrections from the same ψ^t, multiplied together
+ * (the printed update).  SEQUENTIAL: each view's correction is multiplied
+ * into ψ before the next view is blurred (stable for V ≥ 3). */
+typedef enum { MVD_UPDATE_SIMULTANEOUS = 0, MVD_UPDATE_SEQUENTIAL = 1 } mvd_update;
+typedef enum { MVD_BOUNDARY_ZERO = 0, MVD_BOUNDARY_PERIODIC = 1 } mvd_boundary;
+
+/* ψ^0: mean of the views' observations (averaging fusion), the estimate
+ * passed in `est`, or a constant. */
+typedef enum { MVD_INIT_MEAN = 0, MVD_INIT_GIVEN = 1, MVD_INIT_CONST = 2 } mvd_init;
+
+/* mvd_run.flags */
+#define MVD_FLAG_FORCE_2D 0x1u /* use the general K×K kernels even for rank-1 PSFs */
+#define MVD_FLAG_TIMING 0x2u   /* record HIP events around every launch (see mvd_get_timing) */
+
+/* Parameters of one deconvolution run.  struct_size must be sizeof(mvd_run). */
+typedef struct {
+  uint32_t struct_size;
+  uint32_t flags;             /* MVD_FLAG_* */
+  int32_t n_planes;           /* Y ≥ 1 */
+  int32_t n_iters;            /* T ≥ 0 (chosen by the user; no convergence test) */
+  int32_t update;             /* mvd_update */
+  int32_t boundary;           /* mvd_boundary */
+  int32_t init;               /* mvd_init */
+  float init_const;           /* ψ^0 for MVD_INIT_CONST, must be > 0 */
+  int32_t obs_dtype;          /* mvd_dtype of the observations */
+  int32_t obs_layout;         /* mvd_layout of the observations */
+  const float *view_weights;  /* host [V] in [0,1], or NULL = all 1.  Each view's
+                                 correction c is tempered as w·c + (1 − w). */
+  float *checkpoints;         /* device [T][Y][Z][X] float32 receiving ψ^0..ψ^{T−1},
+                                 or NULL.  Needed later by mvd_backward. */
+  void *workspace;            /* device scratch of mvd_workspace_bytes() bytes */
+  size_t workspace_bytes;
+} mvd_run;
+
+/* Library version (MVD_ABI_VERSION). */
+int mvd_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char *mvd_status_string(mvd_status s);
+
+/* Create a context for V views of Z×X planes on HIP device `device`
+ * (or MVD_DEVICE_NONE for a host-only context).  *out receives the context,
+ * owned by the caller and released with mvd_destroy().
+ * Errors: MVD_ERR_ARG (null out, V outside [1, MVD_MAX_VIEWS], Z or X < 1),
+ * MVD_ERR_DEVICE (device does not exist). */
+mvd_status mvd_create(mvd_ctx **out, int n_views, int n_z, int n_x, int device);
+
+/* Release a context (NULL is ignored).  Waits for nothing: the caller must
+ * have synchronised the streams it used with this context. */
+void mvd_destroy(mvd_ctx *ctx);
+
+/* Set view `view`'s PSF P_v (host float32 [kz][kx], copied) and its
+ * back-projector mode (mvd_back).  back_taps: host float32 [kz][kx] for
+ * MVD_BACK_EXPLICIT, else ignored (may be NULL).  Compound back-projectors are
+ * (re)built when a run starts, once every view's PSF is set.  Rank-one taps
+ * (to 1e-6 relative) are run as two 1D passes; others as K×K passes.
+ * Errors: MVD_ERR_ARG (bad view, sides even or outside [1, MVD_MAX_K], taps
+ * negative/non-finite/all zero, missing explicit taps), MVD_ERR_ALLOC. */
+mvd_status mvd_set_psf(mvd_ctx *ctx, int view, const float *taps, int kz, int kx,
+                       int back_mode, const float *back_taps);
+
+/* Host copy of the effective back-projector X_v (float32 [kz][kx] of view v's
+ * PSF size) after compound kernels are built.  `out` holds kz·kx floats.
+ * Errors: MVD_ERR_ARG, MVD_ERR_STATE (some view has no PSF). */
+mvd_status mvd_get_back_taps(mvd_ctx *ctx, int view, float *out);
+
+/* Whether view v's forward PSF and back-projector run as rank-one (1) or
+ * K×K (0) passes.  Either pointer may be NULL. */
+mvd_status mvd_psf_info(mvd_ctx *ctx, int view, int *separable_psf, int *separable_back);
+
+/* Device workspace needed by mvd_deconvolve_planes() for `run`, in bytes
+ * (0 is possible).  Errors: MVD_ERR_ARG. */
+mvd_status mvd_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, size_t *bytes);
+
+/* Reslice one camera-ordered stack (device [Z][Y][X], u16 or f32) into device
+ * float32 planes [Y][Z][X] (Fig. 1a: one plane per camera line).  uint16
+ * converts exactly; float values are clamped below at 0 (NaN → 0).
+ * Errors: MVD_ERR_ARG, MVD_ERR_DEVICE, MVD_ERR_LAUNCH. */
+mvd_status mvd_reslice(mvd_ctx *ctx, const void *stack, int dtype, int n_planes,
+                       float *planes, void *stream);
+
+/* Plane-wise MV-RL on all planes.
+ *   obs: host array of V device pointers, one per view, in run->obs_layout
+ *        and run->obs_dtype (Y = run->n_planes).  Read only.
+ *   est: device float32 [Y][Z][X]; ψ^0 on entry for MVD_INIT_GIVEN, ψ^T on exit.
+ * Steps: reslice/convert the observations into the workspace when needed,
+ * ψ^0, then T iterations (2 passes per iteration for SIMULTANEOUS, 2V for
+ * SEQUENTIAL).  ψ stays ≥ 0 for non-negative data.
+ * Errors: MVD_ERR_ARG, MVD_ERR_STATE (PSF missing), MVD_ERR_WORKSPACE,
+ * MVD_ERR_DEVICE, MVD_ERR_LAUNCH. */
+mvd_status mvd_deconvolve_planes(mvd_ctx *ctx, const void *const *obs, float *est,
+                                 const mvd_run *run, void *stream);
+
+/* Launch timings of runs made with MVD_FLAG_TIMING since the last reset:
+ * summed HIP-event durations (ms) and launch counts per kind.  Kinds: 0 forward
+ * pass (blur + ratio), 1 backward pass (back-projection + update), 2 the rest
+ * (reslice/convert, ψ^0).  Events are recorded on the run's stream around each
+ * launch; this call waits for the last of them.  reset ≠ 0 clears the record.
+ * Errors: MVD_ERR_ARG, MVD_ERR_LAUNCH. */
+typedef struct {
+  uint32_t struct_size;
+  int32_t count[3];
+  double ms[3];
+} mvd_timing;
+mvd_status mvd_get_timing(mvd_ctx *ctx, mvd_timing *out, int reset);
+
+/* Per-context message of the last failing call (empty if none); valid until
+ * the next call on the context.  ctx NULL gives the last message of a call
+ * that had no context (mvd_create). */
+const char *mvd_last_error(const mvd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MVD_H */

@@ -1,0 +1,236 @@
+"""Python binding of the plane-wise MV-RL library (same names as the C ABI).
+
+The ``mvd_*`` functions marshal arguments for the C entry points of
+``include/mvd.h``; PyTorch supplies device memory and the current HIP stream
+only.  ``Deconvolver`` and ``deconvolve`` are conveniences over them.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, c_float, c_int, c_size_t, c_void_p
+
+import numpy as np
+
+from . import _native as N
+
+__all__ = [
+    "mvd_version", "mvd_create", "mvd_destroy", "mvd_set_psf", "mvd_get_back_taps",
+    "mvd_psf_info", "mvd_workspace_bytes", "mvd_reslice", "mvd_deconvolve_planes",
+    "mvd_get_timing", "mvd_last_error", "make_run", "Deconvolver", "deconvolve",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA/HIP device tensor")
+    if not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous")
+    return c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# Thin wrappers of the C entry points
+# ---------------------------------------------------------------------------
+def mvd_version() -> int:
+    return N.lib().mvd_version()
+
+
+def mvd_last_error(ctx=None) -> str:
+    return N.last_error(ctx)
+
+
+def mvd_create(n_views: int, n_z: int, n_x: int, device: int = 0):
+    ctx = c_void_p()
+    N.check(N.lib().mvd_create(ctypes.byref(ctx), int(n_views), int(n_z), int(n_x), int(device)))
+    return ctx
+
+
+def mvd_destroy(ctx) -> None:
+    N.lib().mvd_destroy(ctx)
+
+
+def _host_f32(a, shape=None):
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape is not None and arr.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {arr.shape}")
+    return arr
+
+
+def mvd_set_psf(ctx, view: int, taps, back_mode="flipped", back_taps=None) -> None:
+    t = _host_f32(taps)
+    if t.ndim != 2:
+        raise ValueError("taps must be 2D [kz][kx]")
+    mode = N.BACK[back_mode] if isinstance(back_mode, str) else int(back_mode)
+    bt = None
+    if back_taps is not None:
+        bt = _host_f32(back_taps, t.shape)
+    st = N.lib().mvd_set_psf(ctx, int(view), t.ctypes.data_as(POINTER(c_float)), t.shape[0], t.shape[1],
+                             mode, bt.ctypes.data_as(POINTER(c_float)) if bt is not None else None)
+    N.check(st, ctx)
+
+
+def mvd_get_back_taps(ctx, view: int, kz: int, kx: int) -> np.ndarray:
+    out = np.zeros((kz, kx), dtype=np.float32)
+    N.check(N.lib().mvd_get_back_taps(ctx, int(view), out.ctypes.data_as(POINTER(c_float))), ctx)
+    return out
+
+
+def mvd_psf_info(ctx, view: int):
+    sp, sx = c_int(), c_int()
+    N.check(N.lib().mvd_psf_info(ctx, int(view), ctypes.byref(sp), ctypes.byref(sx)), ctx)
+    return bool(sp.value), bool(sx.value)
+
+
+def make_run(n_planes, n_iters, *, update="simultaneous", boundary="zero", init="mean",
+             init_const=1.0, obs_dtype="f32", layout="stack_zyx", weights=None,
+             checkpoints=None, workspace=None, workspace_bytes=0, force_2d=False, timing=False):
+    """Build an ``mvd_run``; keeps host weight storage alive on the object."""
+    r = N.MvdRun()
+    r.struct_size = ctypes.sizeof(N.MvdRun)
+    r.flags = (N.MVD_FLAG_FORCE_2D if force_2d else 0) | (N.MVD_FLAG_TIMING if timing else 0)
+    r.n_planes = int(n_planes)
+    r.n_iters = int(n_iters)
+    r.update = N.UPDATE[update]
+    r.boundary = N.BOUNDARY[boundary]
+    r.init = N.INIT[init]
+    r.init_const = float(init_const)
+    r.obs_dtype = {"u16": N.MVD_U16, "f32": N.MVD_F32}[obs_dtype]
+    r.obs_layout = {"stack_zyx": N.MVD_STACK_ZYX, "planes_yzx": N.MVD_PLANES_YZX}[layout]
+    if weights is not None:
+        w = (c_float * len(weights))(*[float(x) for x in weights])
+        r._weights_keepalive = w
+        r.view_weights = ctypes.cast(w, POINTER(c_float))
+    r.checkpoints = checkpoints
+    r.workspace = workspace
+    r.workspace_bytes = int(workspace_bytes)
+    return r
+
+
+def mvd_workspace_bytes(ctx, run) -> int:
+    n = c_size_t()
+    N.check(N.lib().mvd_workspace_bytes(ctx, ctypes.byref(run), ctypes.byref(n)), ctx)
+    return n.value
+
+
+def mvd_reslice(ctx, stack, n_planes: int, planes, stream=None) -> None:
+    torch = _torch()
+    dtype = {torch.uint16: N.MVD_U16, torch.float32: N.MVD_F32}[stack.dtype]
+    N.check(N.lib().mvd_reslice(ctx, _dev_ptr(stack), dtype, int(n_planes), _dev_ptr(planes),
+                                _stream_handle(stream)), ctx)
+
+
+def mvd_get_timing(ctx, reset: bool = True) -> dict:
+    """Summed launch times (ms) and counts of timed runs: forward, backward, other."""
+    t = N.MvdTiming()
+    t.struct_size = ctypes.sizeof(N.MvdTiming)
+    N.check(N.lib().mvd_get_timing(ctx, ctypes.byref(t), 1 if reset else 0), ctx)
+    names = ("forward", "backward", "other")
+    return {n: (int(t.count[i]), float(t.ms[i])) for i, n in enumerate(names)}
+
+
+def mvd_deconvolve_planes(ctx, obs, est, run, stream=None) -> None:
+    ptrs = (c_void_p * len(obs))(*[_dev_ptr(o).value for o in obs])
+    N.check(N.lib().mvd_deconvolve_planes(ctx, ptrs, _dev_ptr(est), ctypes.byref(run),
+                                          _stream_handle(stream)), ctx)
+
+
+# ---------------------------------------------------------------------------
+# Convenience layer
+# ---------------------------------------------------------------------------
+class Deconvolver:
+    """A context for V views of Z×X planes with its PSFs set."""
+
+    def __init__(self, n_views: int, n_z: int, n_x: int, device: int = 0):
+        self.n_views, self.n_z, self.n_x, self.device = n_views, n_z, n_x, device
+        self.ctx = mvd_create(n_views, n_z, n_x, device)
+        self.psf_shapes = [None] * n_views
+
+    def close(self):
+        if self.ctx is not None:
+            mvd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_psf(self, view, taps, back="flipped", back_taps=None):
+        mvd_set_psf(self.ctx, view, taps, back, back_taps)
+        self.psf_shapes[view] = np.asarray(taps).shape
+
+    def back_taps(self, view):
+        kz, kx = self.psf_shapes[view]
+        return mvd_get_back_taps(self.ctx, view, kz, kx)
+
+    def run(self, obs, *, iters, est=None, update="simultaneous", boundary="zero", init="mean",
+            init_const=1.0, weights=None, layout=None, checkpoints=None, force_2d=False,
+            stream=None):
+        """Deconvolve device observations; returns the estimate ``[Y][Z][X]`` (float32)."""
+        torch = _torch()
+        if len(obs) != self.n_views:
+            raise ValueError("one observation tensor per view")
+        o0 = obs[0]
+        if layout is None:
+            layout = "stack_zyx"
+        if layout == "stack_zyx":
+            n_planes = o0.shape[1]
+        else:
+            n_planes = o0.shape[0]
+        obs_dtype = "u16" if o0.dtype == torch.uint16 else "f32"
+        if est is None:
+            est = torch.empty((n_planes, self.n_z, self.n_x), dtype=torch.float32, device=o0.device)
+        run = make_run(n_planes, iters, update=update, boundary=boundary, init=init,
+                       init_const=init_const, obs_dtype=obs_dtype, layout=layout, weights=weights,
+                       force_2d=force_2d,
+                       checkpoints=checkpoints.data_ptr() if checkpoints is not None else None)
+        nbytes = mvd_workspace_bytes(self.ctx, run)
+        ws = None
+        if nbytes:
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=o0.device)
+            base = ws.data_ptr()
+            run.workspace = (base + 255) // 256 * 256
+            run.workspace_bytes = nbytes
+        mvd_deconvolve_planes(self.ctx, obs, est, run, stream)
+        if ws is not None:
+            s = stream if stream is not None else torch.cuda.current_stream()
+            ws.record_stream(s)
+        return est
+
+
+def deconvolve(obs, psfs, *, iters=10, update="simultaneous", boundary="zero", back="flipped",
+               back_taps=None, weights=None, init="mean", init_const=1.0, est=None,
+               layout="stack_zyx", force_2d=False, stream=None):
+    """One-shot plane-wise MV-RL on device tensors; returns ψ^T ``[Y][Z][X]``."""
+    o0 = obs[0]
+    if layout == "stack_zyx":
+        nz, nx = o0.shape[0], o0.shape[2]
+    else:
+        nz, nx = o0.shape[1], o0.shape[2]
+    dev = o0.device.index if o0.device.index is not None else 0
+    d = Deconvolver(len(obs), nz, nx, dev)
+    try:
+        for v, p in enumerate(psfs):
+            d.set_psf(v, p, back, None if back_taps is None else back_taps[v])
+        out = d.run(obs, iters=iters, est=est, update=update, boundary=boundary, init=init,
+                    init_const=init_const, weights=weights, layout=layout, force_2d=force_2d,
+                    stream=stream)
+        # the context's device taps must outlive the enqueued work
+        (stream if stream is not None else _torch().cuda.current_stream()).synchronize()
+        return out
+    finally:
+        d.close()

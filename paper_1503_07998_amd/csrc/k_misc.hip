@@ -1,0 +1,99 @@
+// Element-wise kernels: reslice / convert of the observations, ψ^0, fill, copy.
+#include "mvd_internal.hpp"
+
+namespace mvd {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ float obs_value(const void *src, int dtype, size_t i) {
+  if (dtype == 1) return (float)static_cast<const uint16_t *>(src)[i];
+  return fmaxf(static_cast<const float *>(src)[i], 0.f);   // NaN → 0
+}
+
+// dst planes [Y][Z][X] ← src stack [Z][Y][X] (layout 1) or planes (layout 2).
+// Each thread moves 4 consecutive elements of one row when X is a multiple of 4.
+__global__ void __launch_bounds__(NT) stage_kernel(const void *__restrict__ src, int dtype, int layout,
+                                                    PlaneGeom g, float *__restrict__ dst, int vec) {
+  const size_t row_elems = (size_t)g.X;
+  const size_t total = (size_t)g.Y * g.Z * g.X;
+  const size_t step = (size_t)gridDim.x * NT * (vec ? 4 : 1);
+  for (size_t e = ((size_t)blockIdx.x * NT + threadIdx.x) * (vec ? 4 : 1); e < total; e += step) {
+    const size_t row = e / row_elems;           // = y·Z + z of the destination
+    const size_t x = e - row * row_elems;
+    const size_t z = row % g.Z, y = row / g.Z;
+    const size_t s = layout == 1 ? (z * g.Y + y) * row_elems + x : e;
+    if (vec) {
+      float4 v;
+      if (dtype == 1) {
+        const ushort4 u = *reinterpret_cast<const ushort4 *>(static_cast<const uint16_t *>(src) + s);
+        v = make_float4((float)u.x, (float)u.y, (float)u.z, (float)u.w);
+      } else {
+        const float4 f = *reinterpret_cast<const float4 *>(static_cast<const float *>(src) + s);
+        v = make_float4(fmaxf(f.x, 0.f), fmaxf(f.y, 0.f), fmaxf(f.z, 0.f), fmaxf(f.w, 0.f));
+      }
+      *reinterpret_cast<float4 *>(dst + e) = v;
+    } else {
+      dst[e] = obs_value(src, dtype, s);
+    }
+  }
+}
+
+struct Ptrs {
+  const float *p[kMaxViews];
+};
+
+__global__ void __launch_bounds__(NT) init_mean_kernel(Ptrs ph, int nv, size_t n, float *__restrict__ dst) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    float s = 0.f;
+    for (int v = 0; v < nv; ++v) s += fmaxf(ph.p[v][i], 0.f);
+    dst[i] = s / (float)nv;
+  }
+}
+
+__global__ void __launch_bounds__(NT) fill_kernel(float *__restrict__ dst, size_t n, float value) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) dst[i] = value;
+}
+
+__global__ void __launch_bounds__(NT) copy_kernel(const float *__restrict__ src, float *__restrict__ dst,
+                                                   size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) dst[i] = src[i];
+}
+
+unsigned grid_for(size_t work) {
+  size_t b = (work + NT - 1) / NT;
+  if (b > 65536) b = 65536;   // grid-stride beyond this
+  if (b == 0) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_stage_obs(const void *src, int dtype, int layout, PlaneGeom g, float *dst,
+                            hipStream_t s) {
+  const size_t total = (size_t)g.Y * g.Z * g.X;
+  if (total == 0) return hipSuccess;
+  const int vec = (g.X % 4 == 0) && ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);
+  hipLaunchKernelGGL(stage_kernel, dim3(grid_for(vec ? total / 4 : total)), dim3(NT), 0, s, src, dtype,
+                     layout, g, dst, vec);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_mean(const float *const *phis, int nv, size_t n, float *dst, hipStream_t s) {
+  Ptrs p{};
+  for (int v = 0; v < nv && v < kMaxViews; ++v) p.p[v] = phis[v];
+  hipLaunchKernelGGL(init_mean_kernel, dim3(grid_for(n)), dim3(NT), 0, s, p, nv, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float *dst, size_t n, float value, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(NT), 0, s, dst, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float *src, float *dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(NT), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace mvd

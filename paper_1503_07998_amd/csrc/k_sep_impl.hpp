@@ -1,0 +1,461 @@
+// Separable (rank-one PSF) forward and backward passes of plane-wise MV-RL.
+//
+// One work-group owns a strip of columns of one plane (normally the whole row)
+// over a segment of rows, and walks down the segment in groups of G rows:
+//
+//   z pass  each thread owns one or two columns and keeps a ring of input rows
+//           in registers; every group it loads G new rows (issued one group
+//           ahead, so the loads overlap the arithmetic of the current group)
+//           and computes G outputs of the K-tap column convolution with
+//           compile-time ring indices.  Results go to LDS, one row per output.
+//   x pass  threads read 8 consecutive row values plus the K−1 halo values with
+//           128-bit LDS reads and compute the K-tap row convolution in
+//           registers, then run the fused epilogue.
+//
+// Forward epilogue:  r_v = φ_v / b_v  (b_v = ψ ⊛ P_v; 1 where b_v ≤ ε).
+// Backward epilogue: ψ' = ψ · Π_v (w_v · q_v + 1 − w_v)  (q_v = r_v ⊛ X_v).
+// (Supplementary Note 1 update; Supplementary Note 2 §1 back-projector.)
+//
+// The update reads ψ only at the output pixel, so ψ' may overwrite ψ.
+// Included by k_sep_<K>.hip with MVD_KB defined: one compilation unit per
+// kernel-size bucket.
+#pragma once
+
+#include <utility>
+
+#include "mvd_internal.hpp"
+
+namespace mvd {
+namespace sepk {
+
+// Kernel arguments are read through the kernarg segment pointer (constant
+// address space): per-view fields are indexed with a runtime view number, and
+// indexing the by-value parameter that way would make the compiler copy the
+// whole argument block to scratch.  Through this pointer the loads are
+// uniform scalar loads.
+typedef __attribute__((address_space(4))) const SepPassArgs KArg;
+typedef __attribute__((address_space(4))) const float KFloat;
+
+__device__ __forceinline__ KArg *kargs() {
+  return (KArg *)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
+constexpr int G = kRowGroup;   // rows per ring step
+constexpr int NX = 8;          // x-pass outputs per work item
+
+template <int KB>
+struct Shape {
+  static constexpr int R = (KB - 1) / 2;
+  // ring slots: the current group's G+K−1 rows plus the next group's G rows
+  static constexpr int M = G * ((2 * G + KB - 1 + G - 1) / G);
+  static constexpr int U = M / G;                  // ring phases
+  static constexpr int NIN4 = (NX + KB - 1 + 3) / 4;
+};
+
+// LDS-only barrier: waits for this wave's LDS traffic, not for its global
+// loads, so the next group's prefetched rows stay in flight across it.
+__device__ __forceinline__ void lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Work-groups are dealt round-robin to the 8 XCDs; remap so that each XCD
+// gets a contiguous run of (plane, segment, strip) tiles and neighbouring
+// segments share its L2.
+__device__ __forceinline__ int logical_block() {
+  const int n = gridDim.x, b = blockIdx.x;
+  if ((n & 7) == 0) return (b & 7) * (n >> 3) + (b >> 3);
+  return b;
+}
+
+struct Geo {
+  int zs, ze, ngroups, xo0, xout;
+  size_t plane_off;
+};
+
+__device__ __forceinline__ Geo tile_geo(KArg *a) {
+  Geo o;
+  int b = logical_block();
+  const int strip = b % a->nstrip;
+  b /= a->nstrip;
+  const int seg = b % a->nseg;
+  const int y = b / a->nseg;
+  o.zs = seg * a->zseg;
+  o.ze = min(o.zs + a->zseg, a->g.Z);
+  o.ngroups = (o.ze - o.zs + G - 1) / G;
+  o.xo0 = strip * a->x_out;
+  o.xout = min(a->x_out, a->g.X - o.xo0);
+  o.plane_off = (size_t)y * a->g.Z * a->g.X;
+  return o;
+}
+
+// Column bookkeeping of the z pass for one thread.
+template <int C, int R>
+struct Cols {
+  int gx[C];     // source column in the plane
+  int lcol[C];   // LDS column
+  bool act[C];   // thread owns a z-pass column
+  bool ok[C];    // column lies in the plane (else its values are 0)
+
+  __device__ __forceinline__ Cols(KArg *a, const Geo &o, int t, int nt) {
+    const bool halo = a->halo != 0;
+    const int ncz = halo ? o.xout + 2 * R : o.xout;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int lc = t + c * nt;
+      act[c] = lc < ncz;
+      int x = halo ? o.xo0 - R + lc : lc;
+      if (a->boundary == 0) {
+        ok[c] = act[c] && x >= 0 && x < a->g.X;
+      } else {
+        ok[c] = act[c];
+        x = wrapi(x, a->g.X);
+      }
+      gx[c] = x;
+      lcol[c] = halo ? lc : lc + R;
+    }
+  }
+};
+
+// Zero the LDS pad columns of a whole-row strip: [0, R) and [R+X, ldsw).
+// Zero boundary keeps them 0; the periodic boundary overwrites the first R of
+// each side with wrapped copies every group.
+template <int R>
+__device__ __forceinline__ void zero_pads(float *lds, int nrows, KArg *a, int t,
+                                          int nt) {
+  const int right = a->ldsw - (R + a->g.X);
+  const int per = R + right;
+  for (int e = t; e < nrows * per; e += nt) {
+    const int row = e / per, p = e - row * per;
+    const int col = p < R ? p : R + a->g.X + (p - R);
+    lds[row * a->ldsw + col] = 0.f;
+  }
+}
+
+// Load input row `rr` (plane coordinates, may lie outside) for this thread's columns.
+template <int C, int R>
+__device__ __forceinline__ void load_row(const float *__restrict__ src, int rr, KArg *a,
+                                         const Cols<C, R> &cl, float *dst /* [C] stride M */,
+                                         int stride) {
+  bool rv;
+  if (a->boundary == 0) {
+    rv = rr >= 0 && rr < a->g.Z;
+  } else {
+    rr = wrapi(rr, a->g.Z);
+    rv = true;
+  }
+  const float *row = src + (size_t)(rv ? rr : 0) * a->g.X;
+#pragma unroll
+  for (int c = 0; c < C; ++c) dst[c * stride] = (rv && cl.ok[c]) ? row[cl.gx[c]] : 0.f;
+}
+
+// Write one z-pass output (row g of the current buffer) and, for a periodic
+// whole-row strip, its wrapped copies in the pad columns.
+template <int C, int R>
+__device__ __forceinline__ void store_mid(float *B, int g, KArg *a, const Cols<C, R> &cl,
+                                          int c, float v) {
+  if (!cl.act[c]) return;
+  float *row = B + g * a->ldsw;
+  row[cl.lcol[c]] = v;
+  if (a->halo == 0 && a->boundary == 1) {
+    const int X = a->g.X, x = cl.gx[c];
+    for (int p = R + x - X; p >= 0; p -= X) row[p] = v;
+    for (int p = R + x + X; p < X + 2 * R; p += X) row[p] = v;
+  }
+}
+
+// K-tap row convolution of 8 consecutive outputs from one LDS row.
+template <int KB>
+__device__ __forceinline__ void xconv(const float *L, KFloat *taps, float (&out)[NX]) {
+  using S = Shape<KB>;
+  float in[S::NIN4 * 4];
+#pragma unroll
+  for (int q = 0; q < S::NIN4; ++q) {
+    const float4 f = *reinterpret_cast<const float4 *>(L + 4 * q);
+    in[4 * q + 0] = f.x;
+    in[4 * q + 1] = f.y;
+    in[4 * q + 2] = f.z;
+    in[4 * q + 3] = f.w;
+  }
+#pragma unroll
+  for (int n = 0; n < NX; ++n) out[n] = 0.f;
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    const float tap = taps[i];
+#pragma unroll
+    for (int n = 0; n < NX; ++n) out[n] = fmaf(tap, in[n + KB - 1 - i], out[n]);
+  }
+}
+
+__device__ __forceinline__ void load8(const float *__restrict__ p, int nvalid, bool vec, float (&v)[NX]) {
+  if (vec && nvalid == NX) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int n = 0; n < NX; ++n) v[n] = n < nvalid ? p[n] : 0.f;
+  }
+}
+
+__device__ __forceinline__ void store8(float *__restrict__ p, int nvalid, bool vec, const float (&v)[NX]) {
+  if (vec && nvalid == NX) {
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4 *>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  } else {
+#pragma unroll
+    for (int n = 0; n < NX; ++n)
+      if (n < nvalid) p[n] = v[n];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward pass: ψ (one input) → ratio planes of up to kSepFwdViews views.
+// ---------------------------------------------------------------------------
+// Per-work-group constants of a pass.
+struct Loop {
+  int t, nt, nv, bufsz, rbase, nxb, nitems;
+  bool vec;
+};
+
+// One ring phase: group i = i0 + u.  u is a compile-time constant so every
+// ring index below is one too and the ring stays in registers.
+template <int KB, int C, int u>
+__device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
+                                          const float *__restrict__ src, float *lds, const Loop &st,
+                                          float (&ring)[C][Shape<KB>::M], int i0) {
+  constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
+  const int i = i0 + u;
+  if (i >= o.ngroups) return;
+  if (i + 1 < o.ngroups) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
+                     &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
+  }
+  float *buf = lds + (i & 1) * st.bufsz;
+  for (int v = 0; v < st.nv; ++v) {
+    KFloat *tz = a->tz[v];
+    float acc[C][G];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c][g] = 0.f;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const float tap = tz[j];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c][g] = fmaf(tap, ring[c][(u * G + g + KB - 1 - j) % M], acc[c][g]);
+    }
+    float *B = buf + v * G * a->ldsw;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < C; ++c) store_mid<C, R>(B, g, a, cl, c, acc[c][g]);
+  }
+  lds_sync();
+  for (int it = st.t; it < st.nitems; it += st.nt) {
+    const int g = it / st.nxb, xb = it - g * st.nxb;
+    const int z = o.zs + i * G + g;
+    if (z >= o.ze) continue;
+    const int ox = xb * NX;
+    const int nvalid = min(NX, o.xout - ox);
+    const size_t off = o.plane_off + (size_t)z * a->g.X + o.xo0 + ox;
+    for (int v = 0; v < st.nv; ++v) {
+      float b[NX];
+      xconv<KB>(buf + (v * G + g) * a->ldsw + ox, a->tx[v], b);
+      float ph[NX];
+      load8(a->phi[v] + off, nvalid, st.vec, ph);
+      float r[NX];
+#pragma unroll
+      for (int n = 0; n < NX; ++n) {
+        const float p = fmaxf(ph[n], 0.f);
+        r[n] = b[n] > kEps ? p / b[n] : 1.f;
+      }
+      store8(a->out[v] + off, nvalid, st.vec, r);
+    }
+  }
+}
+
+template <int KB, int C, int... us>
+__device__ __forceinline__ void fwd_phases(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
+                                           const float *__restrict__ src, float *lds, const Loop &st,
+                                           float (&ring)[C][Shape<KB>::M], int i0,
+                                           std::integer_sequence<int, us...>) {
+  (fwd_group<KB, C, us>(a, o, cl, src, lds, st, ring, i0), ...);
+}
+
+template <int KB, int C>
+__global__ void __launch_bounds__(kSepMaxThreads) sep_forward_kernel(const SepPassArgs) {
+  KArg *a = kargs();
+  using S = Shape<KB>;
+  constexpr int R = S::R, M = S::M, U = S::U;
+  extern __shared__ __align__(16) float lds[];
+  const int nt = blockDim.x, t = threadIdx.x;
+  const Geo o = tile_geo(a);
+  const Cols<C, R> cl(a, o, t, nt);
+  const int nv = a->nviews;
+  if (a->halo == 0) zero_pads<R>(lds, 2 * nv * G, a, t, nt);
+  const int nxb = (o.xout + NX - 1) / NX;
+  const Loop st{t, nt, nv, nv * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0 && ((a->g.X | o.xo0) & 3) == 0};
+  const float *__restrict__ src = a->in[0] + o.plane_off;
+  float ring[C][M];
+#pragma unroll
+  for (int m = 0; m < G + KB - 1; ++m) load_row<C, R>(src, st.rbase + m, a, cl, &ring[0][m], M);
+  for (int i0 = 0; i0 < o.ngroups; i0 += U)
+    fwd_phases<KB, C>(a, o, cl, src, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
+}
+
+// ---------------------------------------------------------------------------
+// Backward pass: VIN ratio planes → ψ' = ψ · Π_v (w_v q_v + 1 − w_v).
+// ---------------------------------------------------------------------------
+template <int KB, int C, int VIN, int u>
+__device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
+                                          float *lds, const Loop &st, float (&ring)[VIN][C][Shape<KB>::M],
+                                          int i0) {
+  constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
+  const int i = i0 + u;
+  if (i >= o.ngroups) return;
+  if (i + 1 < o.ngroups) {
+#pragma unroll
+    for (int v = 0; v < VIN; ++v) {
+      const float *__restrict__ src = a->in[v] + o.plane_off;
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
+                       &ring[v][0][((u + 1) * G + KB - 1 + g) % M], M);
+    }
+  }
+  float *buf = lds + (i & 1) * st.bufsz;
+#pragma unroll
+  for (int v = 0; v < VIN; ++v) {
+    KFloat *tz = a->tz[v];
+    float acc[C][G];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c][g] = 0.f;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const float tap = tz[j];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          acc[c][g] = fmaf(tap, ring[v][c][(u * G + g + KB - 1 - j) % M], acc[c][g]);
+    }
+    float *B = buf + v * G * a->ldsw;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < C; ++c) store_mid<C, R>(B, g, a, cl, c, acc[c][g]);
+  }
+  lds_sync();
+  for (int it = st.t; it < st.nitems; it += st.nt) {
+    const int g = it / st.nxb, xb = it - g * st.nxb;
+    const int z = o.zs + i * G + g;
+    if (z >= o.ze) continue;
+    const int ox = xb * NX;
+    const int nvalid = min(NX, o.xout - ox);
+    const size_t off = o.plane_off + (size_t)z * a->g.X + o.xo0 + ox;
+    float prod[NX];
+#pragma unroll
+    for (int v = 0; v < VIN; ++v) {
+      float q[NX];
+      xconv<KB>(buf + (v * G + g) * a->ldsw + ox, a->tx[v], q);
+      const float w = a->w[v], w1 = 1.f - w;
+#pragma unroll
+      for (int n = 0; n < NX; ++n) {
+        const float c = fmaf(w, q[n], w1);
+        prod[n] = v == 0 ? c : prod[n] * c;
+      }
+    }
+    float ps[NX];
+    load8(a->psi_in + off, nvalid, st.vec, ps);
+#pragma unroll
+    for (int n = 0; n < NX; ++n) ps[n] *= prod[n];
+    store8(a->psi_out + off, nvalid, st.vec, ps);
+  }
+}
+
+template <int KB, int C, int VIN, int... us>
+__device__ __forceinline__ void bwd_phases(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
+                                           float *lds, const Loop &st, float (&ring)[VIN][C][Shape<KB>::M],
+                                           int i0, std::integer_sequence<int, us...>) {
+  (bwd_group<KB, C, VIN, us>(a, o, cl, lds, st, ring, i0), ...);
+}
+
+template <int KB, int C, int VIN>
+__global__ void __launch_bounds__(kSepMaxThreads) sep_backward_kernel(const SepPassArgs) {
+  KArg *a = kargs();
+  using S = Shape<KB>;
+  constexpr int R = S::R, M = S::M, U = S::U;
+  extern __shared__ __align__(16) float lds[];
+  const int nt = blockDim.x, t = threadIdx.x;
+  const Geo o = tile_geo(a);
+  const Cols<C, R> cl(a, o, t, nt);
+  if (a->halo == 0) zero_pads<R>(lds, 2 * VIN * G, a, t, nt);
+  const int nxb = (o.xout + NX - 1) / NX;
+  const Loop st{t, nt, VIN, VIN * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0 && ((a->g.X | o.xo0) & 3) == 0};
+  float ring[VIN][C][M];
+#pragma unroll
+  for (int v = 0; v < VIN; ++v) {
+    const float *__restrict__ src = a->in[v] + o.plane_off;
+#pragma unroll
+    for (int m = 0; m < G + KB - 1; ++m) load_row<C, R>(src, st.rbase + m, a, cl, &ring[v][0][m], M);
+  }
+  for (int i0 = 0; i0 < o.ngroups; i0 += U)
+    bwd_phases<KB, C, VIN>(a, o, cl, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
+}
+
+inline size_t lds_bytes(const SepPassArgs &a, int nviews) {
+  return sizeof(float) * 2ull * nviews * G * a.ldsw;
+}
+
+template <typename K>
+inline hipError_t launch_with_lds(K kern, const SepPassArgs &a, int threads, size_t lds,
+                                  hipStream_t s) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const unsigned nblocks = (unsigned)a.g.Y * a.nseg * a.nstrip;
+  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int KB>
+hipError_t forward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  const size_t lds = lds_bytes(a, a.nviews);
+  if (p.cols == 2) return launch_with_lds(sep_forward_kernel<KB, 2>, a, p.threads, lds, s);
+  return launch_with_lds(sep_forward_kernel<KB, 1>, a, p.threads, lds, s);
+}
+
+template <int KB>
+hipError_t backward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  const size_t lds = lds_bytes(a, p.vin);
+  if (p.vin == 2) return launch_with_lds(sep_backward_kernel<KB, 1, 2>, a, p.threads, lds, s);
+  if (p.cols == 2) return launch_with_lds(sep_backward_kernel<KB, 2, 1>, a, p.threads, lds, s);
+  return launch_with_lds(sep_backward_kernel<KB, 1, 1>, a, p.threads, lds, s);
+}
+
+}  // namespace sepk
+}  // namespace mvd
+
+#define MVD_SEP_INSTANTIATE(KB)                                                            \
+  namespace mvd {                                                                          \
+  hipError_t sep_forward_kb##KB(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {  \
+    return sepk::forward_bucket<KB>(a, p, s);                                              \
+  }                                                                                        \
+  hipError_t sep_backward_kb##KB(const SepPassArgs &a, const SepPlan &p, hipStream_t s) { \
+    return sepk::backward_bucket<KB>(a, p, s);                                             \
+  }                                                                                        \
+  }

@@ -1,0 +1,756 @@
+// C ABI of the plane-wise MV-RL library: validation, contexts, PSF setup,
+// workspace layout and the pass schedule of one deconvolution run.
+#include "../../include/mvd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mvd_internal.hpp"
+#include "psf.hpp"
+
+namespace mvd {
+hipError_t sep_forward_kb3(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_forward_kb7(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_forward_kb11(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_forward_kb15(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_forward_kb21(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_forward_kb31(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_forward_kb41(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_forward_kb63(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_kb3(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_kb7(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_kb11(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_kb15(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_kb21(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_kb31(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_kb41(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_kb63(const SepPassArgs &, const SepPlan &, hipStream_t);
+
+hipError_t launch_sep_forward(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  switch (p.bucket) {
+    case 3: return sep_forward_kb3(a, p, s);
+    case 7: return sep_forward_kb7(a, p, s);
+    case 11: return sep_forward_kb11(a, p, s);
+    case 15: return sep_forward_kb15(a, p, s);
+    case 21: return sep_forward_kb21(a, p, s);
+    case 31: return sep_forward_kb31(a, p, s);
+    case 41: return sep_forward_kb41(a, p, s);
+    case 63: return sep_forward_kb63(a, p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sep_backward(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  switch (p.bucket) {
+    case 3: return sep_backward_kb3(a, p, s);
+    case 7: return sep_backward_kb7(a, p, s);
+    case 11: return sep_backward_kb11(a, p, s);
+    case 15: return sep_backward_kb15(a, p, s);
+    case 21: return sep_backward_kb21(a, p, s);
+    case 31: return sep_backward_kb31(a, p, s);
+    case 41: return sep_backward_kb41(a, p, s);
+    case 63: return sep_backward_kb63(a, p, s);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace mvd
+
+using namespace mvd;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsLimit = 160 * 1024;
+
+size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+struct ViewPsf {
+  bool set = false;
+  Kernel psf;               // P_v as given (float32 values in double)
+  int back_mode = 0;
+  Kernel explicit_back;
+  // derived
+  Kernel back;              // X_v (float32-rounded values)
+  bool sep_p = false, sep_x = false;
+  std::vector<float> pz, px, xz, xx;  // 1D factors (z, x) of P_v and X_v
+};
+
+thread_local std::string g_noctx_error;
+
+}  // namespace
+
+struct mvd_ctx {
+  int nv = 0, Z = 0, X = 0, device = MVD_DEVICE_NONE;
+  std::vector<ViewPsf> views;
+  bool derived = false;
+  int kzm = 1, kxm = 1, kxpm = 4;  // common K×K size of the general kernels
+  float *d_taps = nullptr;         // [V][2][kzm][kxpm] flipped taps (forward, back)
+  size_t d_taps_cap = 0;
+  std::string err;
+  // launch timing (MVD_FLAG_TIMING)
+  struct Mark {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+mvd_status fail(mvd_ctx *c, mvd_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c)
+    c->err = buf;
+  else
+    g_noctx_error = buf;
+  return s;
+}
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old_) != hipSuccess) old_ = -1;
+    if (dev >= 0 && dev != old_) ok_ = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (old_ >= 0) (void)hipSetDevice(old_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int old_ = -1;
+  bool ok_ = true;
+};
+
+bool valid_taps(const float *t, int n) {
+  bool any = false;
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(t[i]) || t[i] < 0.f) return false;
+    if (t[i] > 0.f) any = true;
+  }
+  return any;
+}
+
+Kernel to_kernel(const float *t, int kz, int kx) {
+  Kernel k{kz, kx, std::vector<double>((size_t)kz * kx)};
+  for (int e = 0; e < kz * kx; ++e) k.t[e] = (double)t[e];
+  return k;
+}
+
+Kernel round_f32(const Kernel &k) {
+  Kernel o = k;
+  for (double &e : o.t) e = (double)(float)e;
+  return o;
+}
+
+std::vector<float> to_f32(const std::vector<double> &v) {
+  std::vector<float> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+  return o;
+}
+
+// Build X_v, the rank-one factors and the device copy of the flipped taps.
+mvd_status derive(mvd_ctx *c) {
+  std::vector<Kernel> psfs;
+  for (auto &v : c->views) psfs.push_back(v.psf);
+  c->kzm = 1;
+  c->kxm = 1;
+  for (int v = 0; v < c->nv; ++v) {
+    ViewPsf &w = c->views[v];
+    if (w.back_mode == MVD_BACK_FLIPPED) {
+      w.back = flip(w.psf);
+    } else if (w.back_mode == MVD_BACK_EXPLICIT) {
+      w.back = w.explicit_back;
+    } else {
+      Kernel x;
+      if (!compound_back(psfs, v, w.back_mode, &x))
+        return fail(c, MVD_ERR_ARG, "view %d: compound back-projector has no positive tap", v);
+      w.back = round_f32(x);
+    }
+    std::vector<double> u, vv;
+    w.sep_p = rank_one(w.psf, &u, &vv);
+    if (w.sep_p) {
+      w.pz = to_f32(u);
+      w.px = to_f32(vv);
+    }
+    w.sep_x = rank_one(w.back, &u, &vv);
+    if (w.sep_x) {
+      w.xz = to_f32(u);
+      w.xx = to_f32(vv);
+    }
+    c->kzm = std::max({c->kzm, w.psf.kz, w.back.kz});
+    c->kxm = std::max({c->kxm, w.psf.kx, w.back.kx});
+  }
+  c->kxpm = (c->kxm + 3) & ~3;
+  if (c->device != MVD_DEVICE_NONE) {
+    const size_t per = (size_t)c->kzm * c->kxpm;
+    std::vector<float> host((size_t)c->nv * 2 * per, 0.f);
+    for (int v = 0; v < c->nv; ++v) {
+      for (int which = 0; which < 2; ++which) {
+        const Kernel &k = which == 0 ? c->views[v].psf : c->views[v].back;
+        float *dst = host.data() + ((size_t)v * 2 + which) * per;
+        const int oz = (c->kzm - k.kz) / 2, ox = (c->kxm - k.kx) / 2;
+        // embedded centred in kzm×kxm, then point-reflected: ft[jj][q] = k[kzm-1-jj][kxm-1-q]
+        for (int j = 0; j < k.kz; ++j)
+          for (int i = 0; i < k.kx; ++i) {
+            const int jj = c->kzm - 1 - (j + oz), q = c->kxm - 1 - (i + ox);
+            dst[(size_t)jj * c->kxpm + q] = (float)k.at(j, i);
+          }
+      }
+    }
+    DeviceGuard dg(c->device);
+    if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
+    const size_t bytes = host.size() * sizeof(float);
+    if (bytes > c->d_taps_cap) {
+      if (c->d_taps) (void)hipFree(c->d_taps);
+      c->d_taps = nullptr;
+      c->d_taps_cap = 0;
+      if (hipMalloc(&c->d_taps, bytes) != hipSuccess)
+        return fail(c, MVD_ERR_ALLOC, "cannot allocate %zu bytes of device taps", bytes);
+      c->d_taps_cap = bytes;
+    }
+    if (hipMemcpy(c->d_taps, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(c, MVD_ERR_LAUNCH, "upload of taps failed");
+  }
+  c->derived = true;
+  return MVD_OK;
+}
+
+bool all_set(const mvd_ctx *c) {
+  for (auto &v : c->views)
+    if (!v.set) return false;
+  return true;
+}
+
+// Workspace layout of one run.
+struct Layout {
+  bool stage = false;   // observations staged into float32 planes
+  size_t plane_set = 0; // bytes of one [Y][Z][X] float32 set
+  size_t phi_off = 0, r_off = 0, total = 0;
+  int n_ratio = 0;
+};
+
+Layout layout_of(const mvd_ctx *c, const mvd_run *r) {
+  Layout L;
+  L.plane_set = align_up((size_t)r->n_planes * c->Z * c->X * sizeof(float));
+  L.stage = !(r->obs_layout == MVD_PLANES_YZX && r->obs_dtype == MVD_F32);
+  L.n_ratio = r->update == MVD_UPDATE_SIMULTANEOUS ? c->nv : 1;
+  size_t off = 0;
+  L.phi_off = off;
+  if (L.stage) off += (size_t)c->nv * L.plane_set;
+  L.r_off = off;
+  off += (size_t)L.n_ratio * L.plane_set;
+  L.total = r->n_iters > 0 ? off : (L.stage ? (size_t)c->nv * L.plane_set : 0);
+  return L;
+}
+
+mvd_status check_run(mvd_ctx *c, const mvd_run *r) {
+  if (!r) return fail(c, MVD_ERR_ARG, "run is NULL");
+  if (r->struct_size != sizeof(mvd_run))
+    return fail(c, MVD_ERR_ARG, "run->struct_size %u != %zu", r->struct_size, sizeof(mvd_run));
+  if (r->n_planes < 1) return fail(c, MVD_ERR_ARG, "n_planes must be >= 1");
+  if (r->n_iters < 0) return fail(c, MVD_ERR_ARG, "n_iters must be >= 0");
+  if (r->update != MVD_UPDATE_SIMULTANEOUS && r->update != MVD_UPDATE_SEQUENTIAL)
+    return fail(c, MVD_ERR_ARG, "unknown update %d", r->update);
+  if (r->boundary != MVD_BOUNDARY_ZERO && r->boundary != MVD_BOUNDARY_PERIODIC)
+    return fail(c, MVD_ERR_ARG, "unknown boundary %d", r->boundary);
+  if (r->init != MVD_INIT_MEAN && r->init != MVD_INIT_GIVEN && r->init != MVD_INIT_CONST)
+    return fail(c, MVD_ERR_ARG, "unknown init %d", r->init);
+  if (r->init == MVD_INIT_CONST && !(std::isfinite(r->init_const) && r->init_const > 0.f))
+    return fail(c, MVD_ERR_ARG, "init_const must be finite and > 0");
+  if (r->obs_dtype != MVD_U16 && r->obs_dtype != MVD_F32)
+    return fail(c, MVD_ERR_ARG, "unknown obs_dtype %d", r->obs_dtype);
+  if (r->obs_layout != MVD_STACK_ZYX && r->obs_layout != MVD_PLANES_YZX)
+    return fail(c, MVD_ERR_ARG, "unknown obs_layout %d", r->obs_layout);
+  if (r->flags & ~(MVD_FLAG_FORCE_2D | MVD_FLAG_TIMING))
+    return fail(c, MVD_ERR_ARG, "unknown flags 0x%x", r->flags);
+  if (r->view_weights)
+    for (int v = 0; v < c->nv; ++v) {
+      const float w = r->view_weights[v];
+      if (!(std::isfinite(w) && w >= 0.f && w <= 1.f))
+        return fail(c, MVD_ERR_ARG, "view weight %d = %g outside [0,1]", v, (double)w);
+    }
+  return MVD_OK;
+}
+
+// ---- pass planning -------------------------------------------------------
+struct SepGeom {
+  SepPlan plan;
+  int zseg, nseg, x_out, nstrip, halo, ncols, ldsw;
+};
+
+int round_up(int n, int m) { return (n + m - 1) / m * m; }
+
+SepGeom plan_sep(const mvd_ctx *c, int Y, int kb) {
+  SepGeom s{};
+  const int R = (kb - 1) / 2;
+  const int X = c->X;
+  s.plan.bucket = kb;
+  const bool wide_ok = kb <= 41;   // two columns per thread keep the ring in registers
+  const int max_cols = (wide_ok ? 2 : 1) * kSepMaxThreads;
+  if (X <= kSepMaxThreads) {
+    s.plan.cols = 1;
+    s.nstrip = 1;
+    s.x_out = X;
+    s.halo = 0;
+    s.ncols = X;
+  } else if (X <= max_cols) {
+    s.plan.cols = 2;
+    s.nstrip = 1;
+    s.x_out = X;
+    s.halo = 0;
+    s.ncols = X;
+  } else {
+    s.plan.cols = wide_ok ? 2 : 1;
+    const int per = s.plan.cols * kSepMaxThreads - 2 * R;
+    s.nstrip = (X + per - 1) / per;
+    s.x_out = round_up((X + s.nstrip - 1) / s.nstrip, 4);
+    s.nstrip = (X + s.x_out - 1) / s.x_out;
+    s.halo = R;
+    s.ncols = s.x_out + 2 * R;
+  }
+  s.plan.threads = std::min(kSepMaxThreads, round_up((s.ncols + s.plan.cols - 1) / s.plan.cols, 64));
+  const int nxb = (s.x_out + 7) / 8;
+  s.ldsw = round_up(nxb * 8 + kb - 1 + 4, 4);
+  // segments: enough work-groups to fill 256 CUs several times, segments ≥ 32 rows
+  const int Z = c->Z;
+  const long tiles = (long)Y * s.nstrip;
+  int nseg = (int)std::max(1L, (2048 + tiles - 1) / tiles);
+  nseg = std::min(nseg, std::max(1, Z / 32));
+  s.zseg = round_up((Z + nseg - 1) / nseg, kRowGroup);
+  s.nseg = (Z + s.zseg - 1) / s.zseg;
+  return s;
+}
+
+void fill_sep_common(SepPassArgs &a, const SepGeom &s, PlaneGeom g, int boundary) {
+  a.g = g;
+  a.boundary = boundary;
+  a.zseg = s.zseg;
+  a.nseg = s.nseg;
+  a.x_out = s.x_out;
+  a.nstrip = s.nstrip;
+  a.halo = s.halo;
+  a.ncols = s.ncols;
+  a.ldsw = s.ldsw;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// centred zero-padding of a 1D factor into kb taps
+void put_factor(float *dst, const std::vector<float> &f, int kb) {
+  for (int i = 0; i < kb; ++i) dst[i] = 0.f;
+  const int off = (kb - (int)f.size()) / 2;
+  for (size_t i = 0; i < f.size(); ++i) dst[off + i] = f[i];
+}
+
+struct RunState {
+  mvd_ctx *c;
+  PlaneGeom g;
+  int boundary;
+  bool force2d;
+  hipStream_t s;
+  const float *w;  // host weights or nullptr
+  bool timing;
+};
+
+hipEvent_t take_event(mvd_ctx *c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` between two events when timing is on.
+template <typename F>
+hipError_t timed(const RunState &st, int kind, F &&launch) {
+  if (!st.timing) return launch();
+  mvd_ctx *c = st.c;
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st.s);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, st.s);
+  c->marks.push_back({kind, a, b});
+  return e;
+}
+
+float weight_of(const RunState &st, int v) { return st.w ? st.w[v] : 1.f; }
+
+const float *dtaps(const mvd_ctx *c, int v, int which) {
+  return c->d_taps + ((size_t)v * 2 + which) * c->kzm * c->kxpm;
+}
+
+// Forward pass over views [v0, v0+n): r[v] = φ_v / (psi ⊛ P_v)
+hipError_t forward_views(const RunState &st, const float *psi, const float *const *phi, float *const *r,
+                         int v0, int n) {
+  mvd_ctx *c = st.c;
+  bool sep = !st.force2d;
+  int kmax = 1;
+  for (int v = v0; v < v0 + n; ++v) {
+    sep = sep && c->views[v].sep_p;
+    kmax = std::max({kmax, c->views[v].psf.kz, c->views[v].psf.kx});
+  }
+  if (sep) {
+    const SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax));
+    const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
+    const int cap = (int)std::max<size_t>(1, std::min<size_t>(kSepFwdViews, kLdsLimit / per_view));
+    for (int b = v0; b < v0 + n; b += cap) {
+      const int nb = std::min(cap, v0 + n - b);
+      SepPassArgs a{};
+      fill_sep_common(a, sg, st.g, st.boundary);
+      a.nviews = nb;
+      a.in[0] = psi;
+      for (int k = 0; k < nb; ++k) {
+        const ViewPsf &w = c->views[b + k];
+        a.phi[k] = phi[b + k];
+        a.out[k] = r[b + k];
+        put_factor(a.tz[k], w.pz, sg.plan.bucket);
+        put_factor(a.tx[k], w.px, sg.plan.bucket);
+      }
+      a.vec = aligned16(psi);
+      for (int k = 0; k < nb; ++k) a.vec = a.vec && aligned16(a.phi[k]) && aligned16(a.out[k]);
+      hipError_t e = timed(st, 0, [&] { return launch_sep_forward(a, sg.plan, st.s); });
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  for (int b = v0; b < v0 + n; b += k2dViews) {
+    const int nb = std::min(k2dViews, v0 + n - b);
+    TwoDPassArgs a{};
+    a.g = st.g;
+    a.boundary = st.boundary;
+    a.nviews = nb;
+    a.kz = c->kzm;
+    a.kx = c->kxm;
+    a.in[0] = psi;
+    for (int k = 0; k < nb; ++k) {
+      a.phi[k] = phi[b + k];
+      a.out[k] = r[b + k];
+      a.taps[k] = dtaps(c, b + k, 0);
+    }
+    hipError_t e = timed(st, 0, [&] { return launch_2d_forward(a, st.s); });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Backward pass over views [v0, v0+n): psi_out = psi_in · Π (w q + 1 − w)
+hipError_t backward_views(const RunState &st, const float *const *r, const float *psi_in, float *psi_out,
+                          int v0, int n) {
+  mvd_ctx *c = st.c;
+  bool sep = !st.force2d;
+  int kmax = 1;
+  for (int v = v0; v < v0 + n; ++v) {
+    sep = sep && c->views[v].sep_x;
+    kmax = std::max({kmax, c->views[v].back.kz, c->views[v].back.kx});
+  }
+  const float *cur = psi_in;
+  if (sep) {
+    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax));
+    const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
+    const bool two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit;
+    sg.plan.vin = two ? 2 : 1;
+    for (int b = v0; b < v0 + n; b += sg.plan.vin) {
+      const int nb = std::min(sg.plan.vin, v0 + n - b);
+      SepPlan plan = sg.plan;
+      plan.vin = nb;
+      SepPassArgs a{};
+      fill_sep_common(a, sg, st.g, st.boundary);
+      a.nviews = nb;
+      for (int k = 0; k < nb; ++k) {
+        const ViewPsf &w = c->views[b + k];
+        a.in[k] = r[b + k];
+        a.w[k] = weight_of(st, b + k);
+        put_factor(a.tz[k], w.xz, plan.bucket);
+        put_factor(a.tx[k], w.xx, plan.bucket);
+      }
+      a.psi_in = cur;
+      a.psi_out = psi_out;
+      a.vec = aligned16(cur) && aligned16(psi_out);
+      for (int k = 0; k < nb; ++k) a.vec = a.vec && aligned16(a.in[k]);
+      hipError_t e = timed(st, 1, [&] { return launch_sep_backward(a, plan, st.s); });
+      if (e != hipSuccess) return e;
+      cur = psi_out;
+    }
+    return hipSuccess;
+  }
+  for (int b = v0; b < v0 + n; b += k2dViews) {
+    const int nb = std::min(k2dViews, v0 + n - b);
+    TwoDPassArgs a{};
+    a.g = st.g;
+    a.boundary = st.boundary;
+    a.nviews = nb;
+    a.kz = c->kzm;
+    a.kx = c->kxm;
+    for (int k = 0; k < nb; ++k) {
+      a.in[k] = r[b + k];
+      a.w[k] = weight_of(st, b + k);
+      a.taps[k] = dtaps(c, b + k, 1);
+    }
+    a.psi_in = cur;
+    a.psi_out = psi_out;
+    hipError_t e = timed(st, 1, [&] { return launch_2d_backward(a, st.s); });
+    if (e != hipSuccess) return e;
+    cur = psi_out;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int mvd_version(void) { return MVD_ABI_VERSION; }
+
+const char *mvd_status_string(mvd_status s) {
+  switch (s) {
+    case MVD_OK: return "ok";
+    case MVD_ERR_ARG: return "invalid argument";
+    case MVD_ERR_STATE: return "invalid state";
+    case MVD_ERR_WORKSPACE: return "workspace too small";
+    case MVD_ERR_DEVICE: return "device unavailable";
+    case MVD_ERR_LAUNCH: return "launch failed";
+    case MVD_ERR_UNSUPPORTED: return "unsupported";
+    case MVD_ERR_ALLOC: return "allocation failed";
+  }
+  return "unknown status";
+}
+
+mvd_status mvd_create(mvd_ctx **out, int n_views, int n_z, int n_x, int device) {
+  if (!out) return fail(nullptr, MVD_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_views < 1 || n_views > MVD_MAX_VIEWS)
+    return fail(nullptr, MVD_ERR_ARG, "n_views %d outside [1, %d]", n_views, MVD_MAX_VIEWS);
+  if (n_z < 1 || n_x < 1) return fail(nullptr, MVD_ERR_ARG, "plane %d x %d is empty", n_z, n_x);
+  if ((long long)n_z * n_x > (1LL << 31))
+    return fail(nullptr, MVD_ERR_ARG, "plane %d x %d too large", n_z, n_x);
+  if (device != MVD_DEVICE_NONE) {
+    int n = 0;
+    if (device < 0 || hipGetDeviceCount(&n) != hipSuccess || device >= n)
+      return fail(nullptr, MVD_ERR_DEVICE, "HIP device %d not available", device);
+  }
+  mvd_ctx *c = new (std::nothrow) mvd_ctx;
+  if (!c) return fail(nullptr, MVD_ERR_ALLOC, "out of host memory");
+  c->nv = n_views;
+  c->Z = n_z;
+  c->X = n_x;
+  c->device = device;
+  c->views.resize(n_views);
+  *out = c;
+  g_noctx_error.clear();
+  return MVD_OK;
+}
+
+void mvd_destroy(mvd_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->device != MVD_DEVICE_NONE) {
+    DeviceGuard dg(ctx->device);
+    for (auto &m : ctx->marks) {
+      (void)hipEventDestroy(m.a);
+      (void)hipEventDestroy(m.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->d_taps) (void)hipFree(ctx->d_taps);
+  }
+  delete ctx;
+}
+
+mvd_status mvd_get_timing(mvd_ctx *c, mvd_timing *out, int reset) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  if (!out || out->struct_size != sizeof(mvd_timing))
+    return fail(c, MVD_ERR_ARG, "out is NULL or has a wrong struct_size");
+  for (int k = 0; k < 3; ++k) {
+    out->count[k] = 0;
+    out->ms[k] = 0.0;
+  }
+  if (c->marks.empty()) return MVD_OK;
+  DeviceGuard dg(c->device);
+  if (hipEventSynchronize(c->marks.back().b) != hipSuccess)
+    return fail(c, MVD_ERR_LAUNCH, "event synchronisation failed");
+  for (auto &m : c->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess)
+      return fail(c, MVD_ERR_LAUNCH, "event timing failed");
+    out->count[m.kind] += 1;
+    out->ms[m.kind] += ms;
+  }
+  if (reset) {
+    for (auto &m : c->marks) {
+      c->pool.push_back(m.a);
+      c->pool.push_back(m.b);
+    }
+    c->marks.clear();
+  }
+  return MVD_OK;
+}
+
+mvd_status mvd_set_psf(mvd_ctx *c, int view, const float *taps, int kz, int kx, int back_mode,
+                       const float *back_taps) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  if (view < 0 || view >= c->nv) return fail(c, MVD_ERR_ARG, "view %d outside [0, %d)", view, c->nv);
+  if (kz < 1 || kx < 1 || kz > MVD_MAX_K || kx > MVD_MAX_K || kz % 2 == 0 || kx % 2 == 0)
+    return fail(c, MVD_ERR_ARG, "PSF %d x %d: sides must be odd and in [1, %d]", kz, kx, MVD_MAX_K);
+  if (!taps) return fail(c, MVD_ERR_ARG, "taps is NULL");
+  if (!valid_taps(taps, kz * kx))
+    return fail(c, MVD_ERR_ARG, "taps must be finite, >= 0 and not all zero");
+  if (back_mode < MVD_BACK_FLIPPED || back_mode > MVD_BACK_EXPLICIT)
+    return fail(c, MVD_ERR_ARG, "unknown back-projector mode %d", back_mode);
+  if (back_mode == MVD_BACK_EXPLICIT) {
+    if (!back_taps) return fail(c, MVD_ERR_ARG, "explicit back-projector needs back_taps");
+    if (!valid_taps(back_taps, kz * kx))
+      return fail(c, MVD_ERR_ARG, "back_taps must be finite, >= 0 and not all zero");
+  }
+  ViewPsf &w = c->views[view];
+  w.psf = to_kernel(taps, kz, kx);
+  w.back_mode = back_mode;
+  w.explicit_back = back_mode == MVD_BACK_EXPLICIT ? to_kernel(back_taps, kz, kx) : Kernel{};
+  w.set = true;
+  c->derived = false;
+  if (all_set(c)) return derive(c);
+  return MVD_OK;
+}
+
+mvd_status mvd_get_back_taps(mvd_ctx *c, int view, float *out) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  if (view < 0 || view >= c->nv) return fail(c, MVD_ERR_ARG, "view %d outside [0, %d)", view, c->nv);
+  if (!out) return fail(c, MVD_ERR_ARG, "out is NULL");
+  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
+  const Kernel &b = c->views[view].back;
+  for (size_t e = 0; e < b.t.size(); ++e) out[e] = (float)b.t[e];
+  return MVD_OK;
+}
+
+mvd_status mvd_psf_info(mvd_ctx *c, int view, int *sp, int *sx) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  if (view < 0 || view >= c->nv) return fail(c, MVD_ERR_ARG, "view %d outside [0, %d)", view, c->nv);
+  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
+  if (sp) *sp = c->views[view].sep_p ? 1 : 0;
+  if (sx) *sx = c->views[view].sep_x ? 1 : 0;
+  return MVD_OK;
+}
+
+mvd_status mvd_workspace_bytes(const mvd_ctx *cc, const mvd_run *r, size_t *bytes) {
+  mvd_ctx *c = const_cast<mvd_ctx *>(cc);
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  if (!bytes) return fail(c, MVD_ERR_ARG, "bytes is NULL");
+  mvd_status st = check_run(c, r);
+  if (st != MVD_OK) return st;
+  *bytes = layout_of(c, r).total;
+  return MVD_OK;
+}
+
+mvd_status mvd_reslice(mvd_ctx *c, const void *stack, int dtype, int n_planes, float *planes,
+                       void *stream) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  if (!stack || !planes) return fail(c, MVD_ERR_ARG, "null buffer");
+  if (dtype != MVD_U16 && dtype != MVD_F32) return fail(c, MVD_ERR_ARG, "unknown dtype %d", dtype);
+  if (n_planes < 1) return fail(c, MVD_ERR_ARG, "n_planes must be >= 1");
+  if (c->device == MVD_DEVICE_NONE) return fail(c, MVD_ERR_DEVICE, "host-only context");
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
+  PlaneGeom g{n_planes, c->Z, c->X};
+  hipError_t e = launch_stage_obs(stack, dtype, MVD_STACK_ZYX, g, planes, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "reslice launch: %s", hipGetErrorString(e));
+  return MVD_OK;
+}
+
+mvd_status mvd_deconvolve_planes(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r,
+                                 void *stream) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  mvd_status st = check_run(c, r);
+  if (st != MVD_OK) return st;
+  if (!obs) return fail(c, MVD_ERR_ARG, "obs is NULL");
+  for (int v = 0; v < c->nv; ++v)
+    if (!obs[v]) return fail(c, MVD_ERR_ARG, "obs[%d] is NULL", v);
+  if (!est) return fail(c, MVD_ERR_ARG, "est is NULL");
+  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
+  const Layout L = layout_of(c, r);
+  if (L.total > 0 && (!r->workspace || r->workspace_bytes < L.total))
+    return fail(c, MVD_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
+                r->workspace ? r->workspace_bytes : (size_t)0);
+  if (r->workspace && ((uintptr_t)r->workspace % kAlign))
+    return fail(c, MVD_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+  if (c->device == MVD_DEVICE_NONE) return fail(c, MVD_ERR_DEVICE, "host-only context");
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
+
+  hipStream_t s = (hipStream_t)stream;
+  const PlaneGeom g{r->n_planes, c->Z, c->X};
+  const size_t n = (size_t)g.Y * g.Z * g.X;
+  char *ws = static_cast<char *>(r->workspace);
+
+  RunState rs{c,          g, r->boundary, (r->flags & MVD_FLAG_FORCE_2D) != 0, s, r->view_weights,
+              (r->flags & MVD_FLAG_TIMING) != 0};
+  std::vector<const float *> phi(c->nv);
+  hipError_t e = hipSuccess;
+  for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
+    if (L.stage) {
+      float *dst = reinterpret_cast<float *>(ws + L.phi_off + (size_t)v * L.plane_set);
+      e = timed(rs, 2, [&] { return launch_stage_obs(obs[v], r->obs_dtype, r->obs_layout, g, dst, s); });
+      phi[v] = dst;
+    } else {
+      phi[v] = static_cast<const float *>(obs[v]);
+    }
+  }
+  const int T = r->n_iters;
+  float *psi0 = (r->checkpoints && T > 0) ? r->checkpoints : est;
+  if (e == hipSuccess) {
+    if (r->init == MVD_INIT_MEAN)
+      e = timed(rs, 2, [&] { return launch_init_mean(phi.data(), c->nv, n, psi0, s); });
+    else if (r->init == MVD_INIT_CONST)
+      e = timed(rs, 2, [&] { return launch_fill(psi0, n, r->init_const, s); });
+    else if (psi0 != est)
+      e = timed(rs, 2, [&] { return launch_copy(est, psi0, n, s); });
+  }
+  std::vector<float *> rat(L.n_ratio);
+  for (int k = 0; k < L.n_ratio; ++k) rat[k] = reinterpret_cast<float *>(ws + L.r_off + (size_t)k * L.plane_set);
+
+  for (int t = 0; t < T && e == hipSuccess; ++t) {
+    float *cur = r->checkpoints ? r->checkpoints + (size_t)t * n : est;
+    float *nxt = r->checkpoints ? (t + 1 < T ? r->checkpoints + (size_t)(t + 1) * n : est) : est;
+    if (r->update == MVD_UPDATE_SIMULTANEOUS) {
+      e = forward_views(rs, cur, phi.data(), rat.data(), 0, c->nv);
+      if (e == hipSuccess) e = backward_views(rs, rat.data(), cur, nxt, 0, c->nv);
+    } else {
+      for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
+        const float *src = v == 0 ? cur : nxt;
+        std::vector<float *> rv(c->nv, rat[0]);
+        e = forward_views(rs, src, phi.data(), rv.data(), v, 1);
+        if (e == hipSuccess) e = backward_views(rs, rv.data(), src, nxt, v, 1);
+      }
+    }
+  }
+  if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "launch failed: %s", hipGetErrorString(e));
+  return MVD_OK;
+}
+
+const char *mvd_last_error(const mvd_ctx *c) {
+  if (!c) return g_noctx_error.c_str();
+  return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal interface between the host runtime (mvd_api.cpp, psf.cpp) and the
+// HIP kernel launchers (k_*.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace mvd {
+
+constexpr int kMaxViews = 8;
+constexpr int kMaxK = 63;
+constexpr float kEps = 1e-6f;   // ratio guard: φ/b where b > kEps, else 1
+
+// Views handled by one separable pass launch.
+constexpr int kSepFwdViews = 4;
+constexpr int kSepBwdViews = 2;
+// Views handled by one general (K×K) pass launch.
+constexpr int k2dViews = 4;
+
+// Kernel-size buckets of the separable kernels: the 1D factors are
+// zero-padded (centred) to the bucket size.  Adding 0·a is exact, so padding
+// does not change results.
+constexpr int kSepBuckets[] = {3, 7, 11, 15, 21, 31, 41, 63};
+constexpr int kNumSepBuckets = sizeof(kSepBuckets) / sizeof(int);
+
+inline int sep_bucket(int k) {
+  for (int b : kSepBuckets)
+    if (k <= b) return b;
+  return -1;
+}
+
+// Geometry of one plane set.
+struct PlaneGeom {
+  int Y, Z, X;
+};
+
+// One forward (blur + ratio) or backward (back-projection + update) pass.
+//
+// Forward:  for each view v of the pass: b = in0 ⊛ P_v; out[v] = guard(φ_v / b).
+// Backward: for each view v of the pass: q = in[v] ⊛ X_v; c = w_v·q + (1 − w_v);
+//           psi_out = psi_in · Π_v c.
+struct SepPassArgs {
+  PlaneGeom g;
+  int boundary;       // 0 zero, 1 periodic
+  int nviews;         // views in this launch
+  int zseg;           // output rows per work-group (multiple of the row group)
+  int nseg;           // z segments per plane
+  int x_out;          // output columns per strip
+  int nstrip;         // strips per plane row
+  int halo;           // 0: strip is the whole row (pads from the boundary rule); R: halo columns computed
+  int ncols;          // z-pass columns per work-group (x_out + 2·halo)
+  int ldsw;           // LDS row pitch in floats
+  int vec;            // every plane pointer of the pass is 16-byte aligned
+  const float *in[kSepFwdViews];      // forward: in[0] = ψ; backward: in[v] = r_v
+  const float *phi[kSepFwdViews];     // forward: observations (float32 planes)
+  float *out[kSepFwdViews];           // forward: ratio planes
+  const float *psi_in;                // backward
+  float *psi_out;                     // backward
+  float w[kSepFwdViews];              // backward: view weights
+  float tz[kSepFwdViews][kMaxK];      // z factor, padded to the bucket
+  float tx[kSepFwdViews][kMaxK];      // x factor, padded to the bucket
+};
+
+// General K×K pass (same semantics as SepPassArgs).
+struct TwoDPassArgs {
+  PlaneGeom g;
+  int boundary;
+  int nviews;
+  int kz, kx;                          // common (padded) kernel size of this pass
+  const float *in[k2dViews];
+  const float *phi[k2dViews];
+  float *out[k2dViews];
+  const float *psi_in;
+  float *psi_out;
+  float w[k2dViews];
+  const float *taps[k2dViews];        // device [kz][kx] per view
+};
+
+// Launch configuration chosen by the host for a separable pass.
+struct SepPlan {
+  int bucket;     // KB
+  int cols;       // columns per thread (1 or 2)
+  int threads;    // work-group size
+  int vin;        // backward: inputs per launch (1 or 2)
+};
+
+// --- launchers (return hipSuccess or the launch error) ---------------------
+hipError_t launch_sep_forward(const SepPassArgs &a, const SepPlan &p, hipStream_t s);
+hipError_t launch_sep_backward(const SepPassArgs &a, const SepPlan &p, hipStream_t s);
+hipError_t launch_2d_forward(const TwoDPassArgs &a, hipStream_t s);
+hipError_t launch_2d_backward(const TwoDPassArgs &a, hipStream_t s);
+
+// Observations → float32 planes.  layout 1 = stack [Z][Y][X], 2 = planes.
+hipError_t launch_stage_obs(const void *src, int dtype, int layout, PlaneGeom g, float *dst,
+                            hipStream_t s);
+// ψ^0 = (1/V) Σ_v φ_v
+hipError_t launch_init_mean(const float *const *phis, int nv, size_t n, float *dst,
+                            hipStream_t s);
+hipError_t launch_fill(float *dst, size_t n, float value, hipStream_t s);
+hipError_t launch_copy(const float *src, float *dst, size_t n, hipStream_t s);
+
+// Work-group / LDS parameters of the separable kernels (shared by launchers
+// and the host planner).
+constexpr int kRowGroup = 8;          // output rows produced per ring step
+constexpr int kSepMaxThreads = 512;
+
+}  // namespace mvd

@@ -20,6 +20,7 @@ planes ``[Y][Z][X]``.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -199,38 +200,78 @@ CONFIGS = {
 }
 
 
+_CHUNK = 16   # planes per generation chunk (noise seeds are per chunk, so results
+              # do not depend on how many worker processes are used)
+
+
+def _render_chunk(args):
+    shape_zyx, blobs, y0, y1, background, sig, noise, dtype, seed_key = args
+    nz, _, nx = shape_zyx
+    sel = (blobs.cy + 4 * np.sqrt(blobs.sigma ** 2) + 1 >= y0) & (blobs.cy - 4 * blobs.sigma - 1 < y1)
+    sub = Blobs(cy=blobs.cy[sel] - y0, cz=blobs.cz[sel], cx=blobs.cx[sel], sigma=blobs.sigma[sel],
+                amp=blobs.amp[sel])
+    lam = render((nz, y1 - y0, nx), sub, background, sig[0], sig[1])
+    if not noise:
+        return lam
+    rng = np.random.default_rng(np.random.SeedSequence(list(seed_key)))
+    counts = rng.poisson(lam)
+    if dtype == "u16":
+        return np.minimum(counts, 65535).astype(np.uint16)
+    return counts.astype(np.float32)
+
+
+def _spawn_safe() -> bool:
+    """Spawned workers re-import ``__main__``; that needs a real file."""
+    import sys
+
+    main = sys.modules.get("__main__")
+    f = getattr(main, "__file__", None)
+    return bool(f) and os.path.exists(f)
+
+
+def _render_volume(shape_zyx, blobs, background, sig, noise, dtype, seed_key, workers):
+    ny = shape_zyx[1]
+    jobs = [(shape_zyx, blobs, y0, min(ny, y0 + _CHUNK), background, sig, noise, dtype,
+             (*seed_key, y0 // _CHUNK)) for y0 in range(0, ny, _CHUNK)]
+    if workers > 1 and len(jobs) > 1 and _spawn_safe():
+        import concurrent.futures as cf
+        import multiprocessing as mp
+
+        with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+            parts = list(ex.map(_render_chunk, jobs))
+    else:
+        parts = [_render_chunk(j) for j in jobs]
+    return np.concatenate(parts, axis=1) if len(parts) > 1 else parts[0]
+
+
 def make_volume(spec: VolumeSpec, seed: int | None = None, noise: bool = True,
-                planes: int | None = None):
+                planes: int | None = None, truth: bool = True, workers: int | None = None):
     """Draw truth and per-view observations for ``spec``.
 
-    Returns ``dict(truth=[Z][Y][X] float32, stacks=[V × [Z][Y][X]], psfs=[V × K×K float32])``.
-    Stacks are uint16 (clipped to 65535) for ``obs_dtype == "u16"``, float32
-    otherwise.  ``noise=False`` returns the noise-free blurred intensities
-    (float32).  ``planes`` overrides the number of planes Y (for reduced
-    test volumes with the same plane shape and density).
+    Returns ``dict(truth=[Z][Y][X] float32 or None, stacks=[V × [Z][Y][X]],
+    psfs=[V × K×K float32])``.  Stacks are uint16 (clipped to 65535) for
+    ``obs_dtype == "u16"``, float32 otherwise.  ``noise=False`` returns the
+    noise-free blurred intensities (float32).  ``planes`` overrides the number
+    of planes Y (reduced volumes with the same plane shape and blob density).
+    Large volumes are rendered by ``workers`` processes in chunks of planes;
+    the result does not depend on the worker count.
     """
     seed = spec.seed if seed is None else seed
     ny = spec.n_planes if planes is None else int(planes)
     shape = (spec.n_z, ny, spec.n_x)
-    ss = np.random.SeedSequence(seed)
-    blob_seq, *view_seqs = ss.spawn(1 + spec.n_views)
-    rng = np.random.default_rng(blob_seq)
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0]))
     n_blobs = spec.n_blobs
     if planes is not None and planes != spec.n_planes:
         n_blobs = max(1, int(round(spec.n_blobs * ny / spec.n_planes)))
     blobs = draw_blobs(rng, shape, n_blobs)
-    truth = render(shape, blobs, spec.background)
+    if workers is None:
+        big = spec.n_z * ny * spec.n_x > (1 << 24)
+        workers = min(8, os.cpu_count() or 1) if big else 1
+    tr = None
+    if truth:
+        tr = _render_volume(shape, blobs, spec.background, (0.0, 0.0), False, "f32", (seed, 0), workers)
     stacks = []
-    for (sx, sz), vs in zip(spec.view_sigmas(), view_seqs):
-        lam = render(shape, blobs, spec.background, sx, sz)
-        if noise:
-            vrng = np.random.default_rng(vs)
-            counts = vrng.poisson(lam)
-            if spec.obs_dtype == "u16":
-                obs = np.minimum(counts, 65535).astype(np.uint16)
-            else:
-                obs = counts.astype(np.float32)
-        else:
-            obs = lam.astype(np.float32)
-        stacks.append(obs)
-    return dict(truth=truth, stacks=stacks, psfs=spec.psfs(), blobs=blobs)
+    for v, sig in enumerate(spec.view_sigmas()):
+        stacks.append(_render_volume(shape, blobs, spec.background, sig, noise, spec.obs_dtype,
+                                     (seed, v + 1), workers))
+    return dict(truth=tr, stacks=stacks, psfs=spec.psfs(), blobs=blobs)

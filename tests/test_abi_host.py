@@ -1,0 +1,227 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every entry point ``include/mvd.h`` declares,
+validate its arguments before touching a device, and build the same
+back-projectors as the oracle (a pin of the host PSF algebra).
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_07998_amd import _native as N
+from paper_1503_07998_amd import api
+from synthetic import gaussian_psf, random_psf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mvd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mvd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = N.lib()
+    names = _declared_symbols()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(N.SIGNATURES), "binding and header disagree"
+
+
+def test_version_and_status_strings():
+    lib = N.lib()
+    assert lib.mvd_version() == 1
+    assert lib.mvd_status_string(0) == b"ok"
+    assert lib.mvd_status_string(-3) == b"workspace too small"
+
+
+def test_run_struct_size_matches_c():
+    ctx = api.mvd_create(1, 4, 4, N.MVD_DEVICE_NONE)
+    try:
+        api.mvd_set_psf(ctx, 0, np.ones((1, 1)))
+        r = api.make_run(2, 1)
+        assert api.mvd_workspace_bytes(ctx, r) > 0
+        r.struct_size = r.struct_size - 8
+        with pytest.raises(N.MvdError) as e:
+            api.mvd_workspace_bytes(ctx, r)
+        assert e.value.status == N.MVD_ERR_ARG
+    finally:
+        api.mvd_destroy(ctx)
+
+
+def _status(fn, *args):
+    try:
+        fn(*args)
+    except N.MvdError as e:
+        return e.status
+    return N.MVD_OK
+
+
+def test_create_validation():
+    lib = N.lib()
+    assert lib.mvd_create(None, 1, 4, 4, -1) == N.MVD_ERR_ARG
+    assert _status(api.mvd_create, 0, 4, 4, -1) == N.MVD_ERR_ARG
+    assert _status(api.mvd_create, 9, 4, 4, -1) == N.MVD_ERR_ARG
+    assert _status(api.mvd_create, 1, 0, 4, -1) == N.MVD_ERR_ARG
+    assert _status(api.mvd_create, 1, 4, 0, -1) == N.MVD_ERR_ARG
+    # no GPU in this process: any real device index is unavailable
+    assert _status(api.mvd_create, 1, 4, 4, 0) == N.MVD_ERR_DEVICE
+    assert "not available" in api.mvd_last_error(None)
+
+
+@pytest.fixture
+def host_ctx():
+    ctx = api.mvd_create(2, 16, 16, N.MVD_DEVICE_NONE)
+    yield ctx
+    api.mvd_destroy(ctx)
+
+
+def test_set_psf_validation(host_ctx):
+    ok = np.ones((3, 3)) / 9
+    assert _status(api.mvd_set_psf, host_ctx, 2, ok) == N.MVD_ERR_ARG          # bad view
+    assert _status(api.mvd_set_psf, host_ctx, -1, ok) == N.MVD_ERR_ARG
+    assert _status(api.mvd_set_psf, host_ctx, 0, np.ones((4, 3))) == N.MVD_ERR_ARG   # even side
+    assert _status(api.mvd_set_psf, host_ctx, 0, np.ones((65, 1))) == N.MVD_ERR_ARG  # > 63
+    bad = ok.copy()
+    bad[0, 0] = -1e-3
+    assert _status(api.mvd_set_psf, host_ctx, 0, bad) == N.MVD_ERR_ARG        # negative
+    bad[0, 0] = np.nan
+    assert _status(api.mvd_set_psf, host_ctx, 0, bad) == N.MVD_ERR_ARG        # NaN
+    bad[0, 0] = np.inf
+    assert _status(api.mvd_set_psf, host_ctx, 0, bad) == N.MVD_ERR_ARG
+    assert _status(api.mvd_set_psf, host_ctx, 0, np.zeros((3, 3))) == N.MVD_ERR_ARG  # all zero
+    assert _status(api.mvd_set_psf, host_ctx, 0, ok, "explicit") == N.MVD_ERR_ARG    # no taps
+    assert _status(api.mvd_set_psf, host_ctx, 0, ok, 7) == N.MVD_ERR_ARG             # bad mode
+    assert _status(api.mvd_set_psf, host_ctx, 0, np.ones((63, 63))) == N.MVD_OK
+
+
+def test_state_errors_before_all_psfs(host_ctx):
+    api.mvd_set_psf(host_ctx, 0, np.ones((3, 3)))
+    assert _status(api.mvd_get_back_taps, host_ctx, 0, 3, 3) == N.MVD_ERR_STATE
+    assert _status(api.mvd_psf_info, host_ctx, 0) == N.MVD_ERR_STATE
+
+
+@pytest.mark.parametrize("mode", ["flipped", "efficient_bayes", "opt1", "opt2"])
+@pytest.mark.parametrize("nv", [1, 2, 3])
+def test_back_projector_matches_oracle(mode, nv):
+    rng = np.random.default_rng(17 + nv)
+    shapes = [(5, 7), (7, 3), (3, 5)][:nv]
+    psfs = [random_psf(rng, kz, kx).astype(np.float32) for kz, kx in shapes]
+    ctx = api.mvd_create(nv, 8, 8, N.MVD_DEVICE_NONE)
+    try:
+        for v, p in enumerate(psfs):
+            api.mvd_set_psf(ctx, v, p, mode)
+        for v, p in enumerate(psfs):
+            got = api.mvd_get_back_taps(ctx, v, *p.shape)
+            ref = oracle.back_projector([q.astype(np.float64) for q in psfs], v, mode)
+            np.testing.assert_allclose(got, ref, rtol=2e-7, atol=1e-9 * ref.max())
+    finally:
+        api.mvd_destroy(ctx)
+
+
+def test_explicit_back_projector_is_kept():
+    rng = np.random.default_rng(3)
+    p = random_psf(rng, 5, 5).astype(np.float32)
+    x = random_psf(rng, 5, 5).astype(np.float32)
+    ctx = api.mvd_create(1, 8, 8, N.MVD_DEVICE_NONE)
+    try:
+        api.mvd_set_psf(ctx, 0, p, "explicit", x)
+        np.testing.assert_array_equal(api.mvd_get_back_taps(ctx, 0, 5, 5), x)
+    finally:
+        api.mvd_destroy(ctx)
+
+
+def test_rank_one_detection():
+    rng = np.random.default_rng(5)
+    ctx = api.mvd_create(3, 8, 8, N.MVD_DEVICE_NONE)
+    try:
+        api.mvd_set_psf(ctx, 0, gaussian_psf(31, 1.5, 6.0).astype(np.float32))
+        api.mvd_set_psf(ctx, 1, random_psf(rng, 7, 9).astype(np.float32))
+        api.mvd_set_psf(ctx, 2, random_psf(rng, 7, 9, separable=True).astype(np.float32))
+        assert api.mvd_psf_info(ctx, 0) == (True, True)
+        assert api.mvd_psf_info(ctx, 1) == (False, False)
+        assert api.mvd_psf_info(ctx, 2) == (True, True)
+    finally:
+        api.mvd_destroy(ctx)
+
+
+def test_gaussian_compound_kernels_stay_rank_one():
+    ctx = api.mvd_create(2, 8, 8, N.MVD_DEVICE_NONE)
+    try:
+        for mode in ("efficient_bayes", "opt1", "opt2"):
+            api.mvd_set_psf(ctx, 0, gaussian_psf(31, 1.5, 6.0).astype(np.float32), mode)
+            api.mvd_set_psf(ctx, 1, gaussian_psf(31, 6.0, 1.5).astype(np.float32), mode)
+            assert api.mvd_psf_info(ctx, 0) == (True, True)
+    finally:
+        api.mvd_destroy(ctx)
+
+
+def test_workspace_bytes_formula():
+    ctx = api.mvd_create(2, 10, 12, N.MVD_DEVICE_NONE)
+    try:
+        for v in range(2):
+            api.mvd_set_psf(ctx, v, np.ones((3, 3)))
+        plane_set = (7 * 10 * 12 * 4 + 255) // 256 * 256
+        r = api.make_run(7, 3, layout="stack_zyx")
+        assert api.mvd_workspace_bytes(ctx, r) == 2 * plane_set + 2 * plane_set
+        r = api.make_run(7, 3, layout="planes_yzx", update="sequential")
+        assert api.mvd_workspace_bytes(ctx, r) == plane_set
+        r = api.make_run(7, 0, layout="planes_yzx")
+        assert api.mvd_workspace_bytes(ctx, r) == 0
+        r = api.make_run(7, 0, layout="planes_yzx", obs_dtype="u16")
+        assert api.mvd_workspace_bytes(ctx, r) == 2 * plane_set
+    finally:
+        api.mvd_destroy(ctx)
+
+
+def test_run_validation_before_device():
+    ctx = api.mvd_create(2, 8, 8, N.MVD_DEVICE_NONE)
+    lib = N.lib()
+    dummy = (ctypes.c_void_p * 2)(16, 32)      # never dereferenced: validation fails first
+    est = ctypes.c_void_p(48)
+
+    def call(run):
+        return lib.mvd_deconvolve_planes(ctx, dummy, est, ctypes.byref(run), None)
+
+    try:
+        r = api.make_run(4, 2)
+        assert call(r) == N.MVD_ERR_STATE          # PSFs not set
+        for v in range(2):
+            api.mvd_set_psf(ctx, v, np.ones((3, 3)))
+        bad = [("n_planes", 0), ("n_iters", -1), ("update", 5), ("boundary", 2), ("init", 9),
+               ("obs_dtype", 3), ("obs_layout", 0), ("flags", 0x10)]
+        for field, value in bad:
+            r = api.make_run(4, 2)
+            setattr(r, field, value)
+            assert call(r) == N.MVD_ERR_ARG, field
+        r = api.make_run(4, 2, init="const", init_const=0.0)
+        assert call(r) == N.MVD_ERR_ARG
+        r = api.make_run(4, 2, weights=[1.0, 1.5])
+        assert call(r) == N.MVD_ERR_ARG
+        r = api.make_run(4, 2, weights=[1.0, float("nan")])
+        assert call(r) == N.MVD_ERR_ARG
+        r = api.make_run(4, 2)                      # workspace missing
+        assert call(r) == N.MVD_ERR_WORKSPACE
+        need = api.mvd_workspace_bytes(ctx, r)
+        r = api.make_run(4, 2, workspace=256, workspace_bytes=need - 1)
+        assert call(r) == N.MVD_ERR_WORKSPACE
+        r = api.make_run(4, 2, workspace=256 + 4, workspace_bytes=need)
+        assert call(r) == N.MVD_ERR_ARG             # misaligned workspace
+        r = api.make_run(4, 2, workspace=256, workspace_bytes=need)
+        assert call(r) == N.MVD_ERR_DEVICE          # host-only context
+        assert lib.mvd_deconvolve_planes(ctx, None, est, ctypes.byref(r), None) == N.MVD_ERR_ARG
+        assert lib.mvd_deconvolve_planes(ctx, dummy, None, ctypes.byref(r), None) == N.MVD_ERR_ARG
+        assert lib.mvd_reslice(ctx, 16, 1, 4, 32, None) == N.MVD_ERR_DEVICE
+        assert lib.mvd_reslice(ctx, 16, 5, 4, 32, None) == N.MVD_ERR_ARG
+    finally:
+        api.mvd_destroy(ctx)
+
+
+def test_destroy_null_is_ignored():
+    N.lib().mvd_destroy(None)
