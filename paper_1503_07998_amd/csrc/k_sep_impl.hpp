@@ -115,7 +115,7 @@ struct Cols {
         ok[c] = act[c];
         x = wrapi(x, a->g.X);
       }
-      gx[c] = x;
+      gx[c] = ok[c] ? x : 0;   // always a valid address; the value is dropped when !ok
       lcol[c] = halo ? lc : lc + R;
     }
   }
@@ -136,21 +136,27 @@ __device__ __forceinline__ void zero_pads(float *lds, int nrows, KArg *a, int t,
   }
 }
 
-// Load input row `rr` (plane coordinates, may lie outside) for this thread's columns.
+// A row of zeros standing in for the rows outside the plane under the zero
+// boundary (zero-initialised device memory, never written).
+__device__ float kZeroRow[kMaxPlaneX];
+
+// Load input row `rr` (plane coordinates, may lie outside) for this thread's
+// columns.  The row pointer is chosen per row (uniform): the plane row, its
+// wrapped copy, or the zero row.  Every lane loads from a valid address and the
+// loaded value is used as is, so the loads stay unconditional and the compiler
+// waits for them only where the ring slot is consumed, a group later.  Columns
+// outside the plane are zeroed when the column-pass result is stored.
 template <int C, int R>
 __device__ __forceinline__ void load_row(const float *__restrict__ src, int rr, KArg *a,
                                          const Cols<C, R> &cl, float *dst /* [C] stride M */,
                                          int stride) {
-  bool rv;
-  if (a->boundary == 0) {
-    rv = rr >= 0 && rr < a->g.Z;
-  } else {
-    rr = wrapi(rr, a->g.Z);
-    rv = true;
-  }
-  const float *row = src + (size_t)(rv ? rr : 0) * a->g.X;
+  const int Z = a->g.Z;
+  const bool zero_bc = a->boundary == 0;
+  const bool rv = !zero_bc || (rr >= 0 && rr < Z);
+  const int r2 = zero_bc ? rr : wrapi(rr, Z);
+  const float *row = rv ? src + (size_t)r2 * a->g.X : kZeroRow;
 #pragma unroll
-  for (int c = 0; c < C; ++c) dst[c * stride] = (rv && cl.ok[c]) ? row[cl.gx[c]] : 0.f;
+  for (int c = 0; c < C; ++c) dst[c * stride] = row[cl.gx[c]];
 }
 
 // Write one z-pass output (row g of the current buffer) and, for a periodic
@@ -159,6 +165,7 @@ template <int C, int R>
 __device__ __forceinline__ void store_mid(float *B, int g, KArg *a, const Cols<C, R> &cl,
                                           int c, float v) {
   if (!cl.act[c]) return;
+  v = cl.ok[c] ? v : 0.f;   // column outside the plane (zero boundary)
   float *row = B + g * a->ldsw;
   row[cl.lcol[c]] = v;
   if (a->halo == 0 && a->boundary == 1) {
@@ -169,25 +176,27 @@ __device__ __forceinline__ void store_mid(float *B, int g, KArg *a, const Cols<C
 }
 
 // K-tap row convolution of 8 consecutive outputs from one LDS row.
+// Inputs are streamed 4 at a time (one 128-bit LDS read) and each is used for
+// every output it touches before the next read, so only a handful of inputs
+// are live: out[n] = Σ_i taps[i] · L[n + K − 1 − i].
 template <int KB>
 __device__ __forceinline__ void xconv(const float *L, KFloat *taps, float (&out)[NX]) {
   using S = Shape<KB>;
-  float in[S::NIN4 * 4];
-#pragma unroll
-  for (int q = 0; q < S::NIN4; ++q) {
-    const float4 f = *reinterpret_cast<const float4 *>(L + 4 * q);
-    in[4 * q + 0] = f.x;
-    in[4 * q + 1] = f.y;
-    in[4 * q + 2] = f.z;
-    in[4 * q + 3] = f.w;
-  }
 #pragma unroll
   for (int n = 0; n < NX; ++n) out[n] = 0.f;
 #pragma unroll
-  for (int i = 0; i < KB; ++i) {
-    const float tap = taps[i];
+  for (int q = 0; q < S::NIN4; ++q) {
+    const float4 f = *reinterpret_cast<const float4 *>(L + 4 * q);
+    const float in4[4] = {f.x, f.y, f.z, f.w};
 #pragma unroll
-    for (int n = 0; n < NX; ++n) out[n] = fmaf(tap, in[n + KB - 1 - i], out[n]);
+    for (int e = 0; e < 4; ++e) {
+      const int p = 4 * q + e;
+#pragma unroll
+      for (int n = 0; n < NX; ++n) {
+        const int i = n + KB - 1 - p;
+        if (i >= 0 && i < KB) out[n] = fmaf(taps[i], in4[e], out[n]);
+      }
+    }
   }
 }
 
@@ -232,12 +241,11 @@ __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, S
   constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
   const int i = i0 + u;
   if (i >= o.ngroups) return;
-  if (i + 1 < o.ngroups) {
+  // rows of the next group (past the segment end they are clamped and unused)
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-      load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
-                     &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
-  }
+  for (int g = 0; g < G; ++g)
+    load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
+                   &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
   float *buf = lds + (i & 1) * st.bufsz;
   for (int v = 0; v < st.nv; ++v) {
     KFloat *tz = a->tz[v];
@@ -323,15 +331,13 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
   constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
   const int i = i0 + u;
   if (i >= o.ngroups) return;
-  if (i + 1 < o.ngroups) {
 #pragma unroll
-    for (int v = 0; v < VIN; ++v) {
-      const float *__restrict__ src = a->in[v] + o.plane_off;
+  for (int v = 0; v < VIN; ++v) {
+    const float *__restrict__ src = a->in[v] + o.plane_off;
 #pragma unroll
-      for (int g = 0; g < G; ++g)
-        load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
-                       &ring[v][0][((u + 1) * G + KB - 1 + g) % M], M);
-    }
+    for (int g = 0; g < G; ++g)
+      load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
+                     &ring[v][0][((u + 1) * G + KB - 1 + g) % M], M);
   }
   float *buf = lds + (i & 1) * st.bufsz;
 #pragma unroll

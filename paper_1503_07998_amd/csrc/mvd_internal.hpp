@@ -10,6 +10,7 @@ namespace mvd {
 
 constexpr int kMaxViews = 8;
 constexpr int kMaxK = 63;
+constexpr int kMaxPlaneX = 65536;   // plane width limit (row of zeros of this size)
 constexpr float kEps = 1e-6f;   // ratio guard: φ/b where b > kEps, else 1
 
 // Views handled by one separable pass launch.

@@ -165,7 +165,9 @@ def test_separable_and_general_kernels_agree():
     vol = make_volume(spec, planes=4)
     a = gpu_run(vol["stacks"], vol["psfs"], 10)
     b = gpu_run(vol["stacks"], vol["psfs"], 10, force_2d=True)
-    assert rel_err(a, b) <= 2e-6
+    # two float32 summation orders (two 1D passes vs K² taps), ~1e-7 per
+    # convolution, compounded over 40 convolutions of the multiplicative update
+    assert rel_err(a, b) <= 1e-5
 
 
 @pytest.mark.parametrize("back", ["efficient_bayes", "opt1", "opt2"])
