@@ -7,6 +7,8 @@ back-projection taken as the matrix transpose), and the iteration to its
 invariants (fixed point of a delta PSF, flux, non-negativity, monotone
 I-divergence of EM) and to Gaussian closed forms.
 """
+import zlib
+
 import numpy as np
 import pytest
 import scipy.signal as ss
@@ -48,7 +50,7 @@ PLANE_SHAPES = [(8, 8), (8, 5), (1, 9), (9, 1), (13, 6)]
 @pytest.mark.parametrize("kshape", KERNEL_SHAPES)
 @pytest.mark.parametrize("pshape", PLANE_SHAPES)
 def test_conv_zero_matches_scipy_fill(kshape, pshape):
-    rng = _rng(hash((kshape, pshape)) % 2**32)
+    rng = _rng(zlib.crc32(repr((kshape, pshape)).encode()))
     a = rng.standard_normal(pshape)
     k = rng.standard_normal(kshape)
     ref = ss.convolve2d(a, k, mode="same", boundary="fill", fillvalue=0)
@@ -59,7 +61,7 @@ def test_conv_zero_matches_scipy_fill(kshape, pshape):
 @pytest.mark.parametrize("pshape", PLANE_SHAPES)
 def test_conv_periodic_matches_convolution_theorem(kshape, pshape):
     """Circular convolution via numpy's FFT (kernel centre wrapped to index 0)."""
-    rng = _rng(7 + hash((kshape, pshape)) % 2**31)
+    rng = _rng(7 + zlib.crc32(repr((kshape, pshape)).encode()))
     a = rng.standard_normal(pshape)
     k = rng.standard_normal(kshape)
     nz, nx = pshape
