@@ -159,6 +159,15 @@ __device__ __forceinline__ void load_row(const float *__restrict__ src, int rr, 
   for (int c = 0; c < C; ++c) dst[c * stride] = row[cl.gx[c]];
 }
 
+// LDS row pitch as an opaque per-use value: keeps the compiler from hoisting
+// one precomputed LDS address per row into registers across the whole loop
+// (an add per store is far cheaper than the registers).
+__device__ __forceinline__ int lds_pitch(KArg *a) {
+  int p = a->ldsw;
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 // Write one z-pass output (row g of the current buffer) and, for a periodic
 // whole-row strip, its wrapped copies in the pad columns.
 template <int C, int R>
@@ -166,7 +175,7 @@ __device__ __forceinline__ void store_mid(float *B, int g, KArg *a, const Cols<C
                                           int c, float v) {
   if (!cl.act[c]) return;
   v = cl.ok[c] ? v : 0.f;   // column outside the plane (zero boundary)
-  float *row = B + g * a->ldsw;
+  float *row = B + g * lds_pitch(a);
   row[cl.lcol[c]] = v;
   if (a->halo == 0 && a->boundary == 1) {
     const int X = a->g.X, x = cl.gx[c];
@@ -200,8 +209,37 @@ __device__ __forceinline__ void xconv(const float *L, KFloat *taps, float (&out)
   }
 }
 
+// Per-work-group constants of a pass.
+struct Loop {
+  int t, nt, bufsz, rbase, nxb, nitems;
+  bool vec;   // whole 8-wide items, 16-byte aligned rows: 128-bit loads and stores
+};
+
+// Geometry of one row-pass work item (row g of the group, 8 output columns).
+struct Item {
+  bool valid;
+  int g, ox, nvalid;
+  size_t off;
+};
+
+__device__ __forceinline__ Item item_at(int it, const Loop &st, const Geo &o, int i, KArg *a) {
+  Item r;
+  const int itc = min(it, st.nitems - 1);
+  r.g = itc / st.nxb;
+  const int xb = itc - r.g * st.nxb;
+  const int z = o.zs + i * G + r.g;
+  r.valid = it < st.nitems && z < o.ze;
+  r.ox = xb * NX;
+  r.nvalid = min(NX, o.xout - r.ox);
+  // rows past the segment are clamped to its first row: a valid address whose data is unused
+  r.off = o.plane_off + (size_t)(r.valid ? z : o.zs) * a->g.X + o.xo0 + r.ox;
+  return r;
+}
+
+// 8 values at p.  vec: two 128-bit loads (every item is whole and aligned);
+// otherwise element-wise within the row.
 __device__ __forceinline__ void load8(const float *__restrict__ p, int nvalid, bool vec, float (&v)[NX]) {
-  if (vec && nvalid == NX) {
+  if (vec) {
     const float4 a = *reinterpret_cast<const float4 *>(p);
     const float4 b = *reinterpret_cast<const float4 *>(p + 4);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
@@ -213,7 +251,7 @@ __device__ __forceinline__ void load8(const float *__restrict__ p, int nvalid, b
 }
 
 __device__ __forceinline__ void store8(float *__restrict__ p, int nvalid, bool vec, const float (&v)[NX]) {
-  if (vec && nvalid == NX) {
+  if (vec) {
     *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
     *reinterpret_cast<float4 *>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
   } else {
@@ -223,85 +261,107 @@ __device__ __forceinline__ void store8(float *__restrict__ p, int nvalid, bool v
   }
 }
 
+// Column pass of one group for one input ring: G output rows per column.
+template <int KB, int C, int u>
+__device__ __forceinline__ void zpass(KFloat *tz, const float (&ring)[C][Shape<KB>::M], float (&acc)[C][G]) {
+  constexpr int M = Shape<KB>::M;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c][g] = 0.f;
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    const float tap = tz[j];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c][g] = fmaf(tap, ring[c][(u * G + g + KB - 1 - j) % M], acc[c][g]);
+  }
+}
+
+template <int KB, int C>
+__device__ __forceinline__ void store_group(float *B, KArg *a, const Cols<C, Shape<KB>::R> &cl,
+                                            const float (&acc)[C][G]) {
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int c = 0; c < C; ++c) store_mid<C, Shape<KB>::R>(B, g, a, cl, c, acc[c][g]);
+}
+
 // ---------------------------------------------------------------------------
-// Forward pass: ψ (one input) → ratio planes of up to kSepFwdViews views.
+// Forward pass: ψ (one input) → ratio planes of NV views.
 // ---------------------------------------------------------------------------
-// Per-work-group constants of a pass.
-struct Loop {
-  int t, nt, nv, bufsz, rbase, nxb, nitems;
-  bool vec;
-};
+template <int KB, int NV>
+__device__ __forceinline__ void fwd_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
+                                             const float (&ph)[NV][NX]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    float b[NX];
+    xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, a->tx[v], b);
+    float r[NX];
+#pragma unroll
+    for (int n = 0; n < NX; ++n) {
+      const float p = fmaxf(ph[v][n], 0.f);
+      r[n] = b[n] > kEps ? p / b[n] : 1.f;
+    }
+    store8(a->out[v] + itm.off, itm.nvalid, vec, r);
+  }
+}
 
 // One ring phase: group i = i0 + u.  u is a compile-time constant so every
 // ring index below is one too and the ring stays in registers.
-template <int KB, int C, int u>
+template <int KB, int C, int NV, int u>
 __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                           const float *__restrict__ src, float *lds, const Loop &st,
                                           float (&ring)[C][Shape<KB>::M], int i0) {
   constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
   const int i = i0 + u;
   if (i >= o.ngroups) return;
-  // rows of the next group (past the segment end they are clamped and unused)
+  // 1. loads issued now and consumed later: the next group's rows (past the
+  //    segment end they are clamped and unused) and this thread's first
+  //    row-pass operands.  The column pass below covers their latency.
 #pragma unroll
   for (int g = 0; g < G; ++g)
     load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
                    &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
+  const Item first = item_at(st.t, st, o, i, a);
+  float ph[NV][NX];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) load8(a->phi[v] + first.off, first.nvalid, st.vec, ph[v]);
+  // 2. column pass → LDS
   float *buf = lds + (i & 1) * st.bufsz;
-  for (int v = 0; v < st.nv; ++v) {
-    KFloat *tz = a->tz[v];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
     float acc[C][G];
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c][g] = 0.f;
-#pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      const float tap = tz[j];
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[c][g] = fmaf(tap, ring[c][(u * G + g + KB - 1 - j) % M], acc[c][g]);
-    }
-    float *B = buf + v * G * a->ldsw;
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-      for (int c = 0; c < C; ++c) store_mid<C, R>(B, g, a, cl, c, acc[c][g]);
+    zpass<KB, C, u>(a->tz[v], ring, acc);
+    store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
   }
   lds_sync();
-  for (int it = st.t; it < st.nitems; it += st.nt) {
-    const int g = it / st.nxb, xb = it - g * st.nxb;
-    const int z = o.zs + i * G + g;
-    if (z >= o.ze) continue;
-    const int ox = xb * NX;
-    const int nvalid = min(NX, o.xout - ox);
-    const size_t off = o.plane_off + (size_t)z * a->g.X + o.xo0 + ox;
-    for (int v = 0; v < st.nv; ++v) {
-      float b[NX];
-      xconv<KB>(buf + (v * G + g) * a->ldsw + ox, a->tx[v], b);
-      float ph[NX];
-      load8(a->phi[v] + off, nvalid, st.vec, ph);
-      float r[NX];
+  // 3. row pass + ratio
+  if (first.valid) fwd_epilogue<KB, NV>(a, buf, first, st.vec, ph);
+  for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
+    const Item itm = item_at(it, st, o, i, a);
+    if (!itm.valid) continue;
+    float q[NV][NX];
 #pragma unroll
-      for (int n = 0; n < NX; ++n) {
-        const float p = fmaxf(ph[n], 0.f);
-        r[n] = b[n] > kEps ? p / b[n] : 1.f;
-      }
-      store8(a->out[v] + off, nvalid, st.vec, r);
-    }
+    for (int v = 0; v < NV; ++v) load8(a->phi[v] + itm.off, itm.nvalid, st.vec, q[v]);
+    fwd_epilogue<KB, NV>(a, buf, itm, st.vec, q);
   }
 }
 
-template <int KB, int C, int... us>
+template <int KB, int C, int NV, int... us>
 __device__ __forceinline__ void fwd_phases(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                            const float *__restrict__ src, float *lds, const Loop &st,
                                            float (&ring)[C][Shape<KB>::M], int i0,
                                            std::integer_sequence<int, us...>) {
-  (fwd_group<KB, C, us>(a, o, cl, src, lds, st, ring, i0), ...);
+  (fwd_group<KB, C, NV, us>(a, o, cl, src, lds, st, ring, i0), ...);
 }
 
-template <int KB, int C>
-__global__ void __launch_bounds__(kSepMaxThreads) sep_forward_kernel(const SepPassArgs) {
+
+// OCC: minimum waves per SIMD the register budget must allow (second
+// launch-bounds argument): 4 caps a thread at 128 VGPRs, 2 at 256.
+template <int KB, int C, int NV, int OCC>
+__global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_forward_kernel(const SepPassArgs) {
   KArg *a = kargs();
   using S = Shape<KB>;
   constexpr int R = S::R, M = S::M, U = S::U;
@@ -309,21 +369,40 @@ __global__ void __launch_bounds__(kSepMaxThreads) sep_forward_kernel(const SepPa
   const int nt = blockDim.x, t = threadIdx.x;
   const Geo o = tile_geo(a);
   const Cols<C, R> cl(a, o, t, nt);
-  const int nv = a->nviews;
-  if (a->halo == 0) zero_pads<R>(lds, 2 * nv * G, a, t, nt);
+  if (a->halo == 0) zero_pads<R>(lds, 2 * NV * G, a, t, nt);
   const int nxb = (o.xout + NX - 1) / NX;
-  const Loop st{t, nt, nv, nv * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0 && ((a->g.X | o.xo0) & 3) == 0};
+  const Loop st{t, nt, NV * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0};
   const float *__restrict__ src = a->in[0] + o.plane_off;
   float ring[C][M];
 #pragma unroll
   for (int m = 0; m < G + KB - 1; ++m) load_row<C, R>(src, st.rbase + m, a, cl, &ring[0][m], M);
   for (int i0 = 0; i0 < o.ngroups; i0 += U)
-    fwd_phases<KB, C>(a, o, cl, src, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
+    fwd_phases<KB, C, NV>(a, o, cl, src, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
 }
 
 // ---------------------------------------------------------------------------
 // Backward pass: VIN ratio planes → ψ' = ψ · Π_v (w_v q_v + 1 − w_v).
 // ---------------------------------------------------------------------------
+template <int KB, int VIN>
+__device__ __forceinline__ void bwd_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
+                                             float (&ps)[NX]) {
+  float prod[NX];
+#pragma unroll
+  for (int v = 0; v < VIN; ++v) {
+    float q[NX];
+    xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, a->tx[v], q);
+    const float w = a->w[v], w1 = 1.f - w;
+#pragma unroll
+    for (int n = 0; n < NX; ++n) {
+      const float c = fmaf(w, q[n], w1);
+      prod[n] = v == 0 ? c : prod[n] * c;
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NX; ++n) ps[n] *= prod[n];
+  store8(a->psi_out + itm.off, itm.nvalid, vec, ps);
+}
+
 template <int KB, int C, int VIN, int u>
 __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                           float *lds, const Loop &st, float (&ring)[VIN][C][Shape<KB>::M],
@@ -339,55 +418,24 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
       load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
                      &ring[v][0][((u + 1) * G + KB - 1 + g) % M], M);
   }
+  const Item first = item_at(st.t, st, o, i, a);
+  float ps[NX];
+  load8(a->psi_in + first.off, first.nvalid, st.vec, ps);
   float *buf = lds + (i & 1) * st.bufsz;
 #pragma unroll
   for (int v = 0; v < VIN; ++v) {
-    KFloat *tz = a->tz[v];
     float acc[C][G];
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c][g] = 0.f;
-#pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      const float tap = tz[j];
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-          acc[c][g] = fmaf(tap, ring[v][c][(u * G + g + KB - 1 - j) % M], acc[c][g]);
-    }
-    float *B = buf + v * G * a->ldsw;
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-      for (int c = 0; c < C; ++c) store_mid<C, R>(B, g, a, cl, c, acc[c][g]);
+    zpass<KB, C, u>(a->tz[v], ring[v], acc);
+    store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
   }
   lds_sync();
-  for (int it = st.t; it < st.nitems; it += st.nt) {
-    const int g = it / st.nxb, xb = it - g * st.nxb;
-    const int z = o.zs + i * G + g;
-    if (z >= o.ze) continue;
-    const int ox = xb * NX;
-    const int nvalid = min(NX, o.xout - ox);
-    const size_t off = o.plane_off + (size_t)z * a->g.X + o.xo0 + ox;
-    float prod[NX];
-#pragma unroll
-    for (int v = 0; v < VIN; ++v) {
-      float q[NX];
-      xconv<KB>(buf + (v * G + g) * a->ldsw + ox, a->tx[v], q);
-      const float w = a->w[v], w1 = 1.f - w;
-#pragma unroll
-      for (int n = 0; n < NX; ++n) {
-        const float c = fmaf(w, q[n], w1);
-        prod[n] = v == 0 ? c : prod[n] * c;
-      }
-    }
-    float ps[NX];
-    load8(a->psi_in + off, nvalid, st.vec, ps);
-#pragma unroll
-    for (int n = 0; n < NX; ++n) ps[n] *= prod[n];
-    store8(a->psi_out + off, nvalid, st.vec, ps);
+  if (first.valid) bwd_epilogue<KB, VIN>(a, buf, first, st.vec, ps);
+  for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
+    const Item itm = item_at(it, st, o, i, a);
+    if (!itm.valid) continue;
+    float q[NX];
+    load8(a->psi_in + itm.off, itm.nvalid, st.vec, q);
+    bwd_epilogue<KB, VIN>(a, buf, itm, st.vec, q);
   }
 }
 
@@ -398,8 +446,8 @@ __device__ __forceinline__ void bwd_phases(KArg *a, const Geo &o, const Cols<C, 
   (bwd_group<KB, C, VIN, us>(a, o, cl, lds, st, ring, i0), ...);
 }
 
-template <int KB, int C, int VIN>
-__global__ void __launch_bounds__(kSepMaxThreads) sep_backward_kernel(const SepPassArgs) {
+template <int KB, int C, int VIN, int OCC>
+__global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_backward_kernel(const SepPassArgs) {
   KArg *a = kargs();
   using S = Shape<KB>;
   constexpr int R = S::R, M = S::M, U = S::U;
@@ -409,7 +457,7 @@ __global__ void __launch_bounds__(kSepMaxThreads) sep_backward_kernel(const SepP
   const Cols<C, R> cl(a, o, t, nt);
   if (a->halo == 0) zero_pads<R>(lds, 2 * VIN * G, a, t, nt);
   const int nxb = (o.xout + NX - 1) / NX;
-  const Loop st{t, nt, VIN, VIN * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0 && ((a->g.X | o.xo0) & 3) == 0};
+  const Loop st{t, nt, VIN * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0};
   float ring[VIN][C][M];
 #pragma unroll
   for (int v = 0; v < VIN; ++v) {
@@ -441,16 +489,34 @@ inline hipError_t launch_with_lds(K kern, const SepPassArgs &a, int threads, siz
 template <int KB>
 hipError_t forward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes(a, a.nviews);
-  if (p.cols == 2) return launch_with_lds(sep_forward_kernel<KB, 2>, a, p.threads, lds, s);
-  return launch_with_lds(sep_forward_kernel<KB, 1>, a, p.threads, lds, s);
+  const bool hi = p.occ >= 4;
+  if constexpr (KB <= 41) {
+    // two columns per thread only where the ring still fits (the planner never asks otherwise)
+    if (p.cols == 2) {
+      if (a.nviews == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 2, 2>, a, p.threads, lds, s);
+      return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2>, a, p.threads, lds, s);
+    }
+  }
+  if (p.cols != 1) return hipErrorInvalidValue;
+  if (a.nviews == 2) {
+    if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 2, 4>, a, p.threads, lds, s);
+    return launch_with_lds(sep_forward_kernel<KB, 1, 2, 2>, a, p.threads, lds, s);
+  }
+  if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4>, a, p.threads, lds, s);
+  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2>, a, p.threads, lds, s);
 }
 
 template <int KB>
 hipError_t backward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes(a, p.vin);
-  if (p.vin == 2) return launch_with_lds(sep_backward_kernel<KB, 1, 2>, a, p.threads, lds, s);
-  if (p.cols == 2) return launch_with_lds(sep_backward_kernel<KB, 2, 1>, a, p.threads, lds, s);
-  return launch_with_lds(sep_backward_kernel<KB, 1, 1>, a, p.threads, lds, s);
+  const bool hi = p.occ >= 4;
+  if constexpr (KB <= 41) {
+    if (p.vin == 2) return launch_with_lds(sep_backward_kernel<KB, 1, 2, 2>, a, p.threads, lds, s);
+    if (p.cols == 2) return launch_with_lds(sep_backward_kernel<KB, 2, 1, 2>, a, p.threads, lds, s);
+  }
+  if (p.cols != 1 || p.vin != 1) return hipErrorInvalidValue;
+  if (hi) return launch_with_lds(sep_backward_kernel<KB, 1, 1, 4>, a, p.threads, lds, s);
+  return launch_with_lds(sep_backward_kernel<KB, 1, 1, 2>, a, p.threads, lds, s);
 }
 
 }  // namespace sepk

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -293,6 +294,39 @@ struct SepGeom {
 
 int round_up(int n, int m) { return (n + m - 1) / m * m; }
 
+// Launch-shape overrides for tuning experiments, read once from the
+// environment: MVD_TUNE="fwd_occ=4,bwd_occ=2,bwd_vin=1,zseg=64" (0 = automatic).
+struct Tune {
+  int fwd_occ = 0, bwd_occ = 0, bwd_vin = 0, zseg = 0;
+};
+
+const Tune &tune() {
+  static const Tune t = [] {
+    Tune r;
+    const char *e = std::getenv("MVD_TUNE");
+    if (!e) return r;
+    std::string s(e);
+    size_t pos = 0;
+    while (pos < s.size()) {
+      size_t comma = s.find(',', pos);
+      if (comma == std::string::npos) comma = s.size();
+      const std::string kv = s.substr(pos, comma - pos);
+      const size_t eq = kv.find('=');
+      if (eq != std::string::npos) {
+        const std::string k = kv.substr(0, eq);
+        const int v = std::atoi(kv.c_str() + eq + 1);
+        if (k == "fwd_occ") r.fwd_occ = v;
+        if (k == "bwd_occ") r.bwd_occ = v;
+        if (k == "bwd_vin") r.bwd_vin = v;
+        if (k == "zseg") r.zseg = v;
+      }
+      pos = comma + 1;
+    }
+    return r;
+  }();
+  return t;
+}
+
 SepGeom plan_sep(const mvd_ctx *c, int Y, int kb) {
   SepGeom s{};
   const int R = (kb - 1) / 2;
@@ -330,7 +364,11 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb) {
   int nseg = (int)std::max(1L, (2048 + tiles - 1) / tiles);
   nseg = std::min(nseg, std::max(1, Z / 32));
   s.zseg = round_up((Z + nseg - 1) / nseg, kRowGroup);
+  if (tune().zseg > 0) s.zseg = round_up(tune().zseg, kRowGroup);
   s.nseg = (Z + s.zseg - 1) / s.zseg;
+  // one column per thread keeps a K ≤ 31 ring within 128 VGPRs: 4 waves/SIMD
+  s.plan.occ = (s.plan.cols == 1 && kb <= 31) ? 4 : 2;
+  s.plan.vin = 1;
   return s;
 }
 
@@ -407,7 +445,8 @@ hipError_t forward_views(const RunState &st, const float *psi, const float *cons
     kmax = std::max({kmax, c->views[v].psf.kz, c->views[v].psf.kx});
   }
   if (sep) {
-    const SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax));
+    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax));
+    if (tune().fwd_occ) sg.plan.occ = tune().fwd_occ;
     const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
     const int cap = (int)std::max<size_t>(1, std::min<size_t>(kSepFwdViews, kLdsLimit / per_view));
     for (int b = v0; b < v0 + n; b += cap) {
@@ -464,8 +503,11 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
   if (sep) {
     SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax));
     const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
-    const bool two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit;
+    bool two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit;
+    if (tune().bwd_vin == 1) two = false;
     sg.plan.vin = two ? 2 : 1;
+    if (two) sg.plan.occ = 2;   // two rings: 256-VGPR budget
+    if (tune().bwd_occ) sg.plan.occ = tune().bwd_occ;
     for (int b = v0; b < v0 + n; b += sg.plan.vin) {
       const int nb = std::min(sg.plan.vin, v0 + n - b);
       SepPlan plan = sg.plan;

@@ -14,7 +14,7 @@ constexpr int kMaxPlaneX = 65536;   // plane width limit (row of zeros of this s
 constexpr float kEps = 1e-6f;   // ratio guard: φ/b where b > kEps, else 1
 
 // Views handled by one separable pass launch.
-constexpr int kSepFwdViews = 4;
+constexpr int kSepFwdViews = 2;
 constexpr int kSepBwdViews = 2;
 // Views handled by one general (K×K) pass launch.
 constexpr int k2dViews = 4;
@@ -84,6 +84,7 @@ struct SepPlan {
   int cols;       // columns per thread (1 or 2)
   int threads;    // work-group size
   int vin;        // backward: inputs per launch (1 or 2)
+  int occ;        // register budget: 4 waves/SIMD (128 VGPRs) or 2 (256)
 };
 
 // --- launchers (return hipSuccess or the launch error) ---------------------
