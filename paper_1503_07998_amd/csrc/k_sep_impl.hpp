@@ -481,6 +481,8 @@ inline hipError_t launch_with_lds(K kern, const SepPassArgs &a, int threads, siz
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  // 128-bit row-pass accesses need whole 8-column items (checked on the host too)
+  if (a.vec && (a.g.X % 8 != 0 || a.x_out % 8 != 0)) return hipErrorInvalidValue;
   const unsigned nblocks = (unsigned)a.g.Y * a.nseg * a.nstrip;
   hipLaunchKernelGGL(kern, dim3(nblocks), dim3(threads), lds, s, a);
   return hipGetLastError();

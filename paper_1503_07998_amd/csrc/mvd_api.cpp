@@ -350,7 +350,7 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb) {
     s.plan.cols = wide_ok ? 2 : 1;
     const int per = s.plan.cols * kSepMaxThreads - 2 * R;
     s.nstrip = (X + per - 1) / per;
-    s.x_out = round_up((X + s.nstrip - 1) / s.nstrip, 4);
+    s.x_out = round_up((X + s.nstrip - 1) / s.nstrip, 8);
     s.nstrip = (X + s.x_out - 1) / s.x_out;
     s.halo = R;
     s.ncols = s.x_out + 2 * R;
@@ -385,6 +385,10 @@ void fill_sep_common(SepPassArgs &a, const SepGeom &s, PlaneGeom g, int boundary
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// The row pass moves 8 outputs per item with 128-bit loads and stores only when
+// every item is whole: rows and strips are multiples of 8 columns.
+bool whole_items(const SepGeom &sg, PlaneGeom g) { return g.X % 8 == 0 && sg.x_out % 8 == 0; }
 
 // centred zero-padding of a 1D factor into kb taps
 void put_factor(float *dst, const std::vector<float> &f, int kb) {
@@ -462,7 +466,7 @@ hipError_t forward_views(const RunState &st, const float *psi, const float *cons
         put_factor(a.tz[k], w.pz, sg.plan.bucket);
         put_factor(a.tx[k], w.px, sg.plan.bucket);
       }
-      a.vec = aligned16(psi);
+      a.vec = whole_items(sg, st.g) && aligned16(psi);
       for (int k = 0; k < nb; ++k) a.vec = a.vec && aligned16(a.phi[k]) && aligned16(a.out[k]);
       hipError_t e = timed(st, 0, [&] { return launch_sep_forward(a, sg.plan, st.s); });
       if (e != hipSuccess) return e;
@@ -524,7 +528,7 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
       }
       a.psi_in = cur;
       a.psi_out = psi_out;
-      a.vec = aligned16(cur) && aligned16(psi_out);
+      a.vec = whole_items(sg, st.g) && aligned16(cur) && aligned16(psi_out);
       for (int k = 0; k < nb; ++k) a.vec = a.vec && aligned16(a.in[k]);
       hipError_t e = timed(st, 1, [&] { return launch_sep_backward(a, plan, st.s); });
       if (e != hipSuccess) return e;
@@ -787,6 +791,30 @@ mvd_status mvd_deconvolve_planes(mvd_ctx *c, const void *const *obs, float *est,
     }
   }
   if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "launch failed: %s", hipGetErrorString(e));
+  return MVD_OK;
+}
+
+// Internal (not in the public header): the launch geometry the planner picks for
+// a separable pass over `n_planes` planes with kernel size k, so host-side tests
+// can check every access of the kernels' index arithmetic against its buffer.
+// out[16]: bucket, cols, threads, occ, zseg, nseg, x_out, nstrip, halo, ncols,
+// ldsw, vec (for 16-byte aligned buffers), lds bytes per view.
+int mvd_internal_sep_plan(const mvd_ctx *c, int n_planes, int k, int *out) {
+  if (!c || !out || n_planes < 1 || k < 1 || k > MVD_MAX_K) return MVD_ERR_ARG;
+  const SepGeom sg = plan_sep(c, n_planes, sep_bucket(k));
+  out[0] = sg.plan.bucket;
+  out[1] = sg.plan.cols;
+  out[2] = sg.plan.threads;
+  out[3] = sg.plan.occ;
+  out[4] = sg.zseg;
+  out[5] = sg.nseg;
+  out[6] = sg.x_out;
+  out[7] = sg.nstrip;
+  out[8] = sg.halo;
+  out[9] = sg.ncols;
+  out[10] = sg.ldsw;
+  out[11] = whole_items(sg, PlaneGeom{n_planes, c->Z, c->X}) ? 1 : 0;
+  out[12] = (int)(sizeof(float) * 2ull * kRowGroup * sg.ldsw);
   return MVD_OK;
 }
 

@@ -1,0 +1,126 @@
+"""Host-side model of the separable kernels' index arithmetic.
+
+For launch geometries the planner actually picks (read back through an
+internal export of the library), every global-memory and LDS access the
+kernels make is recomputed here and checked against its buffer.  This runs on
+the CPU so that a planner or indexing mistake shows up before any kernel runs.
+The formulas mirror the kernel source (ring rows, work items, 8-wide row-pass
+accesses, LDS rows and pads).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1503_07998_amd import _native as N
+from paper_1503_07998_amd import api
+
+G = 8      # rows per ring step
+NX = 8     # row-pass outputs per item
+LDS_LIMIT = 160 * 1024
+
+
+def plan(ctx, Y, k):
+    out = (ctypes.c_int * 16)()
+    lib = N.lib()
+    lib.mvd_internal_sep_plan.restype = ctypes.c_int
+    lib.mvd_internal_sep_plan.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    assert lib.mvd_internal_sep_plan(ctx, Y, k, out) == 0
+    keys = ["bucket", "cols", "threads", "occ", "zseg", "nseg", "x_out", "nstrip", "halo", "ncols",
+            "ldsw", "vec", "lds_per_view"]
+    return dict(zip(keys, list(out)[:len(keys)]))
+
+
+def check_geometry(Y, Z, X, k, boundary, views):
+    ctx = api.mvd_create(1, Z, X, N.MVD_DEVICE_NONE)
+    try:
+        p = plan(ctx, Y, k)
+    finally:
+        api.mvd_destroy(ctx)
+    KB = p["bucket"]
+    R = (KB - 1) // 2
+    M = G * ((2 * G + KB - 1 + G - 1) // G)
+    nt, C = p["threads"], p["cols"]
+    assert nt % 64 == 0 and 64 <= nt <= 512
+    assert views * p["lds_per_view"] <= LDS_LIMIT
+    assert p["zseg"] % G == 0 and p["nseg"] * p["zseg"] >= Z and (p["nseg"] - 1) * p["zseg"] < Z
+    assert p["nstrip"] * p["x_out"] >= X and (p["nstrip"] - 1) * p["x_out"] < X
+    if p["vec"]:
+        assert X % 8 == 0 and p["x_out"] % 8 == 0
+    halo = p["halo"] != 0
+    ldsw = p["ldsw"]
+    assert ldsw % 4 == 0
+    plane = Z * X
+    NIN4 = (NX + KB - 1 + 3) // 4
+    for strip in range(p["nstrip"]):
+        xo0 = strip * p["x_out"]
+        xout = min(p["x_out"], X - xo0)
+        assert xout >= 1
+        ncz = xout + 2 * R if halo else xout
+        assert ncz <= nt * C, "z-pass columns exceed the threads' columns"
+        # z-pass columns: LDS column and source column (valid address always)
+        for lc in range(ncz):
+            x = xo0 - R + lc if halo else lc
+            if boundary == "zero":
+                ok = 0 <= x < X
+            else:
+                ok, x = True, x % X
+            gx = x if ok else 0
+            assert 0 <= gx < X
+            lcol = lc if halo else lc + R
+            assert 0 <= lcol < ldsw
+            if not halo and boundary == "periodic":
+                q = R + x - X
+                while q >= 0:
+                    assert q < ldsw
+                    q -= X
+                q = R + x + X
+                while q < X + 2 * R:
+                    assert q < ldsw
+                    q += X
+        if not halo:
+            assert R + X <= ldsw
+        # row-pass items: LDS reads and global accesses
+        nxb = (xout + NX - 1) // NX
+        for xb in range(nxb):
+            ox = xb * NX
+            assert ox + 4 * NIN4 <= ldsw, "row-pass LDS read past the row"
+            nvalid = min(NX, xout - ox)
+            width = NX if p["vec"] else nvalid
+            assert ox + width <= xout or (p["vec"] and xo0 + ox + NX <= X)
+            assert xo0 + ox + width <= X, "row-pass access past the row end"
+    for seg in range(p["nseg"]):
+        zs = seg * p["zseg"]
+        ze = min(zs + p["zseg"], Z)
+        ngroups = (ze - zs + G - 1) // G
+        # ring rows: every row index (incl. the prefetch of the group after the last) is clamped
+        for m in range(0, (ngroups + 1) * G + KB - 1):
+            rr = zs - R + m
+            if boundary == "zero":
+                if 0 <= rr < Z:
+                    assert 0 <= rr * X < plane
+            else:
+                assert 0 <= (rr % Z) < Z
+        # clamped item rows
+        for i in range(ngroups):
+            for g in range(G):
+                z = zs + i * G + g
+                zc = z if z < ze else zs
+                assert 0 <= zc < Z
+
+
+SHAPES = [
+    (2, 1, 37), (2, 41, 1), (3, 8, 8), (4, 37, 53), (2, 70, 100), (2, 13, 200), (2, 24, 700),
+    (2, 16, 1100), (1, 12, 600), (2, 9, 66), (32, 128, 128), (512, 512, 512), (200, 256, 384),
+    (300, 512, 768), (150, 1000, 1000), (256, 256, 256), (4, 1024, 1024), (2, 5, 2100),
+    (1, 3, 513), (1, 7, 1023), (1, 7, 1025), (3, 33, 511),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{y}x{z}x{x}" for y, z, x in SHAPES])
+@pytest.mark.parametrize("k", [1, 5, 9, 15, 21, 31, 41, 63])
+def test_separable_launch_geometry_in_bounds(shape, k):
+    Y, Z, X = shape
+    for boundary in ("zero", "periodic"):
+        for views in (1, 2):
+            check_geometry(Y, Z, X, k, boundary, views)
