@@ -17,6 +17,15 @@ constexpr int TX = 64;
 constexpr int NT = 256;
 constexpr int N4 = 4;   // outputs per thread
 
+// φ / b for b > ε, else 1: reciprocal refined by one Newton-Raphson correction
+// of the quotient (Markstein); within 1 ulp of IEEE, exactly 1 when φ = b.
+__device__ __forceinline__ float guarded_ratio(float phi, float b) {
+  const float y = __builtin_amdgcn_rcpf(b);
+  const float q0 = phi * y;
+  const float q = fmaf(fmaf(-b, q0, phi), y, q0);
+  return b > kEps ? q : 1.f;
+}
+
 __device__ __forceinline__ int wrap2(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;
@@ -113,7 +122,7 @@ __global__ void __launch_bounds__(NT) twod_forward_kernel(const TwoDPassArgs a) 
       for (int n = 0; n < N4; ++n) {
         if (t.x0 + ox + n < a.g.X) {
           const float p = fmaxf(a.phi[v][off + n], 0.f);
-          a.out[v][off + n] = b[n] > kEps ? p / b[n] : 1.f;
+          a.out[v][off + n] = guarded_ratio(p, b[n]);
         }
       }
     }

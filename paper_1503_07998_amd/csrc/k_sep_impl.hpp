@@ -288,6 +288,19 @@ __device__ __forceinline__ void store_group(float *B, KArg *a, const Cols<C, Sha
     for (int c = 0; c < C; ++c) store_mid<C, Shape<KB>::R>(B, g, a, cl, c, acc[c][g]);
 }
 
+// Guarded ratio φ / b for b > ε (else 1).  The quotient is the reciprocal
+// approximation refined by one Newton-Raphson correction of the quotient
+// (Markstein's method): q0 = φ·y, e = φ − b·q0 (exact with FMA), q = q0 + e·y.
+// Within 1 ulp of the IEEE quotient for b > ε and finite φ, and exactly 1 when
+// φ = b (the residual then carries the whole error of q0).
+__device__ __forceinline__ float guarded_ratio(float phi, float b) {
+  const float y = __builtin_amdgcn_rcpf(b);
+  const float q0 = phi * y;
+  const float e = fmaf(-b, q0, phi);
+  const float q = fmaf(e, y, q0);
+  return b > kEps ? q : 1.f;
+}
+
 // ---------------------------------------------------------------------------
 // Forward pass: ψ (one input) → ratio planes of NV views.
 // ---------------------------------------------------------------------------
@@ -300,10 +313,7 @@ __device__ __forceinline__ void fwd_epilogue(KArg *a, const float *buf, const It
     xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, a->tx[v], b);
     float r[NX];
 #pragma unroll
-    for (int n = 0; n < NX; ++n) {
-      const float p = fmaxf(ph[v][n], 0.f);
-      r[n] = b[n] > kEps ? p / b[n] : 1.f;
-    }
+    for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(fmaxf(ph[v][n], 0.f), b[n]);
     store8(a->out[v] + itm.off, itm.nvalid, vec, r);
   }
 }

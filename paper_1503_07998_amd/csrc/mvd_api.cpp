@@ -297,7 +297,7 @@ int round_up(int n, int m) { return (n + m - 1) / m * m; }
 // Launch-shape overrides for tuning experiments, read once from the
 // environment: MVD_TUNE="fwd_occ=4,bwd_occ=2,bwd_vin=1,zseg=64" (0 = automatic).
 struct Tune {
-  int fwd_occ = 0, bwd_occ = 0, bwd_vin = 0, zseg = 0;
+  int fwd_occ = 0, bwd_occ = 0, bwd_vin = 0, zseg = 0, fwd_views = 0;
 };
 
 const Tune &tune() {
@@ -319,6 +319,7 @@ const Tune &tune() {
         if (k == "bwd_occ") r.bwd_occ = v;
         if (k == "bwd_vin") r.bwd_vin = v;
         if (k == "zseg") r.zseg = v;
+        if (k == "fwd_views") r.fwd_views = v;
       }
       pos = comma + 1;
     }
@@ -361,8 +362,8 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb) {
   // segments: enough work-groups to fill 256 CUs several times, segments ≥ 32 rows
   const int Z = c->Z;
   const long tiles = (long)Y * s.nstrip;
-  int nseg = (int)std::max(1L, (2048 + tiles - 1) / tiles);
-  nseg = std::min(nseg, std::max(1, Z / 32));
+  int nseg = (int)std::max(1L, (1024 + tiles - 1) / tiles);
+  nseg = std::min(nseg, std::max(1, Z / 64));
   s.zseg = round_up((Z + nseg - 1) / nseg, kRowGroup);
   if (tune().zseg > 0) s.zseg = round_up(tune().zseg, kRowGroup);
   s.nseg = (Z + s.zseg - 1) / s.zseg;
@@ -452,7 +453,8 @@ hipError_t forward_views(const RunState &st, const float *psi, const float *cons
     SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax));
     if (tune().fwd_occ) sg.plan.occ = tune().fwd_occ;
     const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
-    const int cap = (int)std::max<size_t>(1, std::min<size_t>(kSepFwdViews, kLdsLimit / per_view));
+    int cap = (int)std::max<size_t>(1, std::min<size_t>(kSepFwdViews, kLdsLimit / per_view));
+    if (tune().fwd_views > 0) cap = std::min(cap, tune().fwd_views);
     for (int b = v0; b < v0 + n; b += cap) {
       const int nb = std::min(cap, v0 + n - b);
       SepPassArgs a{};
@@ -507,8 +509,13 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
   if (sep) {
     SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax));
     const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
-    bool two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit;
+    // Two ratio planes per launch save one read and write of ψ but need two
+    // rings (256-VGPR budget); one per launch runs at 4 waves/SIMD and is
+    // faster wherever that variant exists (K ≤ 31, one column per thread).
+    bool two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit &&
+               sg.plan.occ < 4;
     if (tune().bwd_vin == 1) two = false;
+    if (tune().bwd_vin == 2) two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41;
     sg.plan.vin = two ? 2 : 1;
     if (two) sg.plan.occ = 2;   // two rings: 256-VGPR budget
     if (tune().bwd_occ) sg.plan.occ = tune().bwd_occ;
