@@ -362,8 +362,8 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb) {
   // segments: enough work-groups to fill 256 CUs several times, segments ≥ 32 rows
   const int Z = c->Z;
   const long tiles = (long)Y * s.nstrip;
-  int nseg = (int)std::max(1L, (1024 + tiles - 1) / tiles);
-  nseg = std::min(nseg, std::max(1, Z / 64));
+  int nseg = (int)std::max(1L, (2048 + tiles - 1) / tiles);
+  nseg = std::min(nseg, std::max(1, Z / 32));
   s.zseg = round_up((Z + nseg - 1) / nseg, kRowGroup);
   if (tune().zseg > 0) s.zseg = round_up(tune().zseg, kRowGroup);
   s.nseg = (Z + s.zseg - 1) / s.zseg;
