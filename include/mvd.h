@@ -181,15 +181,45 @@ mvd_status mvd_deconvolve_planes(mvd_ctx *ctx, const void *const *obs, float *es
 /* Launch timings of runs made with MVD_FLAG_TIMING since the last reset:
  * summed HIP-event durations (ms) and launch counts per kind.  Kinds: 0 forward
  * pass (blur + ratio), 1 backward pass (back-projection + update), 2 the rest
- * (reslice/convert, ψ^0).  Events are recorded on the run's stream around each
- * launch; this call waits for the last of them.  reset ≠ 0 clears the record.
+ * (reslice/convert, ψ^0), 3 reverse-sweep passes (mvd_backward), 4 tap-gradient
+ * correlations.  Events are recorded on the run's stream around each launch;
+ * this call waits for the last of them.  reset ≠ 0 clears the record.
  * Errors: MVD_ERR_ARG, MVD_ERR_LAUNCH. */
+#define MVD_TIMING_KINDS 5
 typedef struct {
   uint32_t struct_size;
-  int32_t count[3];
-  double ms[3];
+  int32_t count[MVD_TIMING_KINDS];
+  double ms[MVD_TIMING_KINDS];
 } mvd_timing;
 mvd_status mvd_get_timing(mvd_ctx *ctx, mvd_timing *out, int reset);
+
+/* Device workspace needed by mvd_backward() for `run`, in bytes.
+ * Errors: MVD_ERR_ARG, MVD_ERR_STATE. */
+mvd_status mvd_backward_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, size_t *bytes);
+
+/* Reverse sweep (adjoint) of mvd_deconvolve_planes: gradients of a loss L
+ * with respect to the taps of every view's PSF P_v and back-projector X_v,
+ * the view weights and ψ^0, given ∂L/∂ψ^T.  The chain rule of the update
+ * (Supplementary Note 1 / Note 2 §1) is applied backwards through every
+ * iteration, recomputing each iteration's intermediates from its checkpoint.
+ *   obs, run: exactly as in the forward call (same n_iters, update, boundary,
+ *        weights, observations); run->checkpoints must hold ψ^0 … ψ^{T−1} as
+ *        written by that call; run->workspace of mvd_backward_workspace_bytes().
+ *   grad_est: device [Y][Z][X], ∂L/∂ψ^T (read only).
+ *   grad_psf, grad_back: host arrays of V device pointers to float32 [kz][kx]
+ *        of each view's PSF size, receiving ∂L/∂P_v and ∂L/∂X_v (X_v taken as
+ *        an independent kernel; for X_v = P_v^* add the flipped grad_back to
+ *        grad_psf).  Either array may be NULL (not computed).
+ *   grad_weights: device [V] or NULL.  grad_init: device [Y][Z][X], ∂L/∂ψ^0,
+ *        or NULL.  Outputs are overwritten, in float32 from float64 sums in a
+ *        fixed order (bitwise reproducible).
+ * Every view's PSF and back-projector must be rank one (MVD_ERR_UNSUPPORTED
+ * otherwise, and with MVD_FLAG_FORCE_2D).
+ * Errors: MVD_ERR_ARG, MVD_ERR_STATE, MVD_ERR_WORKSPACE, MVD_ERR_UNSUPPORTED,
+ * MVD_ERR_DEVICE, MVD_ERR_LAUNCH. */
+mvd_status mvd_backward(mvd_ctx *ctx, const void *const *obs, const float *grad_est,
+                        const mvd_run *run, float *const *grad_psf, float *const *grad_back,
+                        float *grad_weights, float *grad_init, void *stream);
 
 /* Per-context message of the last failing call (empty if none); valid until
  * the next call on the context.  ctx NULL gives the last message of a call

@@ -38,54 +38,56 @@ def tap_gradient(gbar, a, kshape, boundary=ZERO) -> np.ndarray:
     return out
 
 
-def _factors(psi, phis, psfs, backs, ws, boundary):
+def _factors(psi, phis, psfs, backs, ws, boundary, method="direct"):
     """b, mask, r, q, c of every view from the same ψ."""
     out = []
     for phi, p, x, w in zip(phis, psfs, backs, ws):
-        b = conv2d(psi, p, boundary)
+        b = conv2d(psi, p, boundary, method)
         m = b > EPS
         r = ratio(phi, b)
-        q = conv2d(r, x, boundary)
+        q = conv2d(r, x, boundary, method)
         c = w * q + (1.0 - w)
         out.append((b, m, r, q, c))
     return out
 
 
-def _view_adjoint(cbar, psi, phi_parts, p, x, w, boundary, gp, gx):
+def _view_adjoint(cbar, psi, phi_parts, p, x, w, boundary, gp, gx, method="direct"):
     """Back-propagate c̄ of one view into ψ̄ (returned) and the tap/weight gradients."""
     b, m, r, q, _ = phi_parts
     gw = float(np.sum(cbar * (q - 1.0)))
     qbar = w * cbar
-    rbar = conv2d(qbar, flip(x), boundary)
+    rbar = conv2d(qbar, flip(x), boundary, method)
     gx += tap_gradient(qbar, r, x.shape, boundary)
     safe = np.where(m, b, 1.0)
     bbar = np.where(m, -rbar * r / safe, 0.0)
-    psibar = conv2d(bbar, flip(p), boundary)
+    psibar = conv2d(bbar, flip(p), boundary, method)
     gp += tap_gradient(bbar, psi, p.shape, boundary)
     return psibar, gw
 
 
-def forward_history(phis, psfs, backs, weights, iters, update=SIMULTANEOUS, boundary=ZERO, psi0=None):
+def forward_history(phis, psfs, backs, weights, iters, update=SIMULTANEOUS, boundary=ZERO, psi0=None,
+                    method="direct"):
     """[ψ^0, …, ψ^T] with ψ^0 the mean of the observations unless given."""
     from .mvrl import init_estimate, rl_iteration
 
     psi = init_estimate(phis) if psi0 is None else np.asarray(psi0, dtype=np.float64)
     hist = [psi]
     for _ in range(iters):
-        psi = rl_iteration(psi, phis, psfs, backs, weights, update, boundary)
+        psi = rl_iteration(psi, phis, psfs, backs, weights, update, boundary, method)
         hist.append(psi)
     return hist
 
 
 def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, boundary=ZERO,
-            psi0=None, history=None):
+            psi0=None, history=None, method="direct"):
     """Reverse sweep.  Returns dict(grad_psf=[V×K×K], grad_back=[V×K×K],
     grad_weights=[V], grad_psi0=array)."""
     nv = len(phis)
     ps = [np.asarray(p, dtype=np.float64) for p in psfs]
     xs = [np.asarray(x, dtype=np.float64) for x in backs]
     ws = [1.0] * nv if weights is None else [float(w) for w in weights]
-    hist = history if history is not None else forward_history(phis, ps, xs, ws, iters, update, boundary, psi0)
+    hist = history if history is not None else forward_history(phis, ps, xs, ws, iters, update, boundary, psi0,
+                                                               method)
     gp = [np.zeros_like(p) for p in ps]
     gx = [np.zeros_like(x) for x in xs]
     gw = [0.0] * nv
@@ -93,7 +95,7 @@ def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, bo
     for t in range(iters - 1, -1, -1):
         psi = hist[t]
         if update == SIMULTANEOUS:
-            parts = _factors(psi, phis, ps, xs, ws, boundary)
+            parts = _factors(psi, phis, ps, xs, ws, boundary, method)
             cs = [pt[4] for pt in parts]
             prod = np.ones_like(psi)
             for c in cs:
@@ -105,7 +107,7 @@ def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, bo
                     if u != v:
                         others = others * cs[u]
                 cbar = gbar * psi * others
-                pb, g = _view_adjoint(cbar, psi, parts[v], ps[v], xs[v], ws[v], boundary, gp[v], gx[v])
+                pb, g = _view_adjoint(cbar, psi, parts[v], ps[v], xs[v], ws[v], boundary, gp[v], gx[v], method)
                 new = new + pb
                 gw[v] += g
             gbar = new
@@ -113,13 +115,13 @@ def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, bo
             sub = [psi]
             parts = []
             for v in range(nv):
-                pt = _factors(sub[-1], [phis[v]], [ps[v]], [xs[v]], [ws[v]], boundary)[0]
+                pt = _factors(sub[-1], [phis[v]], [ps[v]], [xs[v]], [ws[v]], boundary, method)[0]
                 parts.append(pt)
                 sub.append(sub[-1] * pt[4])
             for v in range(nv - 1, -1, -1):
                 cur = sub[v]
                 cbar = gbar * cur
-                pb, g = _view_adjoint(cbar, cur, parts[v], ps[v], xs[v], ws[v], boundary, gp[v], gx[v])
+                pb, g = _view_adjoint(cbar, cur, parts[v], ps[v], xs[v], ws[v], boundary, gp[v], gx[v], method)
                 gbar = gbar * parts[v][4] + pb
                 gw[v] += g
         else:

@@ -58,7 +58,7 @@ class MvdRun(ctypes.Structure):
 class MvdTiming(ctypes.Structure):
     """Mirror of ``mvd_timing``."""
 
-    _fields_ = [("struct_size", c_uint32), ("count", c_int32 * 3), ("ms", ctypes.c_double * 3)]
+    _fields_ = [("struct_size", c_uint32), ("count", c_int32 * 5), ("ms", ctypes.c_double * 5)]
 
 
 class MvdError(RuntimeError):
@@ -80,6 +80,9 @@ SIGNATURES = {
     "mvd_reslice": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "mvd_deconvolve_planes": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), c_void_p]),
     "mvd_get_timing": (c_int, [c_void_p, POINTER(MvdTiming), c_int]),
+    "mvd_backward_workspace_bytes": (c_int, [c_void_p, POINTER(MvdRun), POINTER(c_size_t)]),
+    "mvd_backward": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), POINTER(c_void_p),
+                             POINTER(c_void_p), c_void_p, c_void_p, c_void_p]),
     "mvd_last_error": (ctypes.c_char_p, [c_void_p]),
 }
 

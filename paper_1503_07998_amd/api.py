@@ -17,6 +17,7 @@ __all__ = [
     "mvd_version", "mvd_create", "mvd_destroy", "mvd_set_psf", "mvd_get_back_taps",
     "mvd_psf_info", "mvd_workspace_bytes", "mvd_reslice", "mvd_deconvolve_planes",
     "mvd_get_timing", "mvd_last_error", "make_run", "Deconvolver", "deconvolve",
+    "mvd_backward_workspace_bytes", "mvd_backward",
 ]
 
 
@@ -137,7 +138,7 @@ def mvd_get_timing(ctx, reset: bool = True) -> dict:
     t = N.MvdTiming()
     t.struct_size = ctypes.sizeof(N.MvdTiming)
     N.check(N.lib().mvd_get_timing(ctx, ctypes.byref(t), 1 if reset else 0), ctx)
-    names = ("forward", "backward", "other")
+    names = ("forward", "backward", "other", "adjoint", "correlation")
     return {n: (int(t.count[i]), float(t.ms[i])) for i, n in enumerate(names)}
 
 
@@ -145,6 +146,31 @@ def mvd_deconvolve_planes(ctx, obs, est, run, stream=None) -> None:
     ptrs = (c_void_p * len(obs))(*[_dev_ptr(o).value for o in obs])
     N.check(N.lib().mvd_deconvolve_planes(ctx, ptrs, _dev_ptr(est), ctypes.byref(run),
                                           _stream_handle(stream)), ctx)
+
+
+def mvd_backward_workspace_bytes(ctx, run) -> int:
+    n = c_size_t()
+    N.check(N.lib().mvd_backward_workspace_bytes(ctx, ctypes.byref(run), ctypes.byref(n)), ctx)
+    return n.value
+
+
+def _ptr_array(tensors):
+    if tensors is None:
+        return None
+    return (c_void_p * len(tensors))(*[(_dev_ptr(t).value if t is not None else None) for t in tensors])
+
+
+def mvd_backward(ctx, obs, grad_est, run, grad_psf=None, grad_back=None, grad_weights=None,
+                 grad_init=None, stream=None) -> None:
+    ptrs = (c_void_p * len(obs))(*[_dev_ptr(o).value for o in obs])
+    gp = _ptr_array(grad_psf)
+    gb = _ptr_array(grad_back)
+    N.check(N.lib().mvd_backward(ctx, ptrs, _dev_ptr(grad_est), ctypes.byref(run),
+                                 ctypes.cast(gp, POINTER(c_void_p)) if gp is not None else None,
+                                 ctypes.cast(gb, POINTER(c_void_p)) if gb is not None else None,
+                                 _dev_ptr(grad_weights) if grad_weights is not None else None,
+                                 _dev_ptr(grad_init) if grad_init is not None else None,
+                                 _stream_handle(stream)), ctx)
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,132 @@
+"""Differentiable plane-wise MV-RL: ψ^T as a function of per-view Gaussian PSF
+widths (σx, σz) and view weights, behind ``torch.autograd.Function``.
+
+Forward: the HIP library runs the unrolled RL iterations and stores ψ^t of
+every iteration (checkpoints).  Backward: the library's reverse sweep
+(``mvd_backward``) returns ∂L/∂P_v and ∂L/∂X_v on the K×K taps and ∂L/∂w_v;
+with X_v = P_v^* the tap gradient of P_v is ∂L/∂P_v + flip(∂L/∂X_v), chained to
+(σx, σz) by torch through the small Gaussian builder (K×K values, float64).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import api
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def gaussian_taps(k: int, sigma_x, sigma_z):
+    """Normalised point-sampled Gaussian [K][K] (rows Z, columns X), float64, differentiable."""
+    torch = _torch()
+    d = torch.arange(k, dtype=torch.float64, device=sigma_x.device) - (k - 1) / 2.0
+    gx = torch.exp(-d * d / (2 * sigma_x * sigma_x))
+    gz = torch.exp(-d * d / (2 * sigma_z * sigma_z))
+    p = gz[:, None] * gx[None, :]
+    return p / p.sum()
+
+
+class PlanewiseRL:
+    """Observations and run settings of one differentiable deconvolution."""
+
+    def __init__(self, obs, k: int, iters: int, *, update="simultaneous", boundary="zero",
+                 layout="stack_zyx", device: int = 0):
+        torch = _torch()
+        self.obs = list(obs)
+        self.k, self.iters, self.update, self.boundary, self.layout = k, iters, update, boundary, layout
+        o0 = self.obs[0]
+        if layout == "stack_zyx":
+            self.nz, self.ny, self.nx = o0.shape[0], o0.shape[1], o0.shape[2]
+        else:
+            self.ny, self.nz, self.nx = o0.shape
+        self.obs_dtype = "u16" if o0.dtype == torch.uint16 else "f32"
+        self.dec = api.Deconvolver(len(self.obs), self.nz, self.nx, device)
+        self.dev = o0.device
+
+    def _run(self, weights, checkpoints=None, ws_bytes=0):
+        return api.make_run(self.ny, self.iters, update=self.update, boundary=self.boundary,
+                            obs_dtype=self.obs_dtype, layout=self.layout, weights=weights,
+                            checkpoints=checkpoints)
+
+    def set_sigmas(self, sigma):
+        s = sigma.detach().to("cpu", dtype=_torch().float64)
+        for v in range(len(self.obs)):
+            taps = gaussian_taps(self.k, s[v, 0], s[v, 1]).numpy().astype(np.float32)
+            self.dec.set_psf(v, taps, "flipped")
+
+    def __call__(self, sigma, weights):
+        return mv_deconvolve(sigma, weights, self)
+
+
+def _make_function():
+    torch = _torch()
+
+    class MVDeconvFunction(torch.autograd.Function):
+        """ψ^T(σ, w): forward and reverse sweep in the HIP library."""
+
+        @staticmethod
+        def forward(ctx, sigma, weights, prob: PlanewiseRL):
+            prob.set_sigmas(sigma)
+            w = [float(x) for x in weights.detach().cpu().tolist()]
+            T = prob.iters
+            ck = torch.empty((T, prob.ny, prob.nz, prob.nx), dtype=torch.float32, device=prob.dev)
+            est = torch.empty((prob.ny, prob.nz, prob.nx), dtype=torch.float32, device=prob.dev)
+            run = prob._run(w, checkpoints=ck.data_ptr())
+            nbytes = api.mvd_workspace_bytes(prob.dec.ctx, run)
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=prob.dev)
+            run.workspace = (ws.data_ptr() + 255) // 256 * 256
+            run.workspace_bytes = nbytes
+            api.mvd_deconvolve_planes(prob.dec.ctx, prob.obs, est, run)
+            ctx.prob = prob
+            ctx.w = w
+            ctx.save_for_backward(sigma, weights, ck)
+            return est
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            sigma, weights, ck = ctx.saved_tensors
+            prob = ctx.prob
+            V, K = len(prob.obs), prob.k
+            run = prob._run(ctx.w, checkpoints=ck.data_ptr())
+            nbytes = api.mvd_backward_workspace_bytes(prob.dec.ctx, run)
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=prob.dev)
+            run.workspace = (ws.data_ptr() + 255) // 256 * 256
+            run.workspace_bytes = nbytes
+            gp = [torch.empty((K, K), dtype=torch.float32, device=prob.dev) for _ in range(V)]
+            gb = [torch.empty((K, K), dtype=torch.float32, device=prob.dev) for _ in range(V)]
+            gw = torch.empty(V, dtype=torch.float32, device=prob.dev)
+            api.mvd_backward(prob.dec.ctx, prob.obs, grad_out.contiguous().float(), run, gp, gb, gw)
+            torch.cuda.current_stream().synchronize()
+            grad_sigma = None
+            if ctx.needs_input_grad[0]:
+                with torch.enable_grad():
+                    s = sigma.detach().to("cpu", dtype=torch.float64).requires_grad_(True)
+                    total = 0.0
+                    for v in range(V):
+                        tap_grad = gp[v].double().cpu() + torch.flip(gb[v].double().cpu(), (0, 1))
+                        total = total + (gaussian_taps(K, s[v, 0], s[v, 1]) * tap_grad).sum()
+                    (g,) = torch.autograd.grad(total, s)
+                grad_sigma = g.to(device=sigma.device, dtype=sigma.dtype)
+            grad_w = gw.to(device=weights.device, dtype=weights.dtype) if ctx.needs_input_grad[1] else None
+            return grad_sigma, grad_w, None
+
+    return MVDeconvFunction
+
+
+_FUNCTION = None
+
+
+def function_class():
+    """The ``torch.autograd.Function`` subclass (created on first use)."""
+    global _FUNCTION
+    if _FUNCTION is None:
+        _FUNCTION = _make_function()
+    return _FUNCTION
+
+
+def mv_deconvolve(sigma, weights, prob: PlanewiseRL):
+    """ψ^T(σ, w) with autograd support (σ: [V][2] as (σx, σz); w: [V])."""
+    return function_class().apply(sigma, weights, prob)

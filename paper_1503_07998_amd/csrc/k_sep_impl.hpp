@@ -288,39 +288,89 @@ __device__ __forceinline__ void store_group(float *B, KArg *a, const Cols<C, Sha
     for (int c = 0; c < C; ++c) store_mid<C, Shape<KB>::R>(B, g, a, cl, c, acc[c][g]);
 }
 
-// Guarded ratio φ / b for b > ε (else 1).  The quotient is the reciprocal
-// approximation refined by one Newton-Raphson correction of the quotient
-// (Markstein's method): q0 = φ·y, e = φ − b·q0 (exact with FMA), q = q0 + e·y.
-// Within 1 ulp of the IEEE quotient for b > ε and finite φ, and exactly 1 when
-// φ = b (the residual then carries the whole error of q0).
+// ---------------------------------------------------------------------------
+// Single-input passes: one input plane set convolved with NV views' kernels,
+// each view's result finished by the epilogue EP:
+//   kRatio  out = φ / conv (guarded)                 forward pass of the update
+//   kStore  out = conv                               (adjoint: q = r ⊛ X)
+//   kBR     out = conv (b), out2 = φ / conv (r)      (adjoint: recompute b and r)
+//   kBbar   out = −conv · r / b where b > ε, else 0 (adjoint: b̄ from r̄)
+//   kAccum  out = aux0 + conv                        (adjoint: ψ̄ += b̄ ⊛ P^*)
+// ---------------------------------------------------------------------------
+template <int EP>
+struct Epi {
+  static constexpr int nops = (EP == kEpBbar) ? 2 : (EP == kEpStore ? 0 : 1);
+  static constexpr int nbuf = nops > 0 ? nops : 1;
+};
+
+template <int EP>
+__device__ __forceinline__ const float *op_ptr(KArg *a, int v, int k) {
+  if (EP == kEpRatio || EP == kEpBR) return a->phi[v];
+  return k == 0 ? a->aux0[v] : a->aux1[v];
+}
+
+// Quotient n / d by the reciprocal refined with one Newton-Raphson correction
+// of the quotient (Markstein's method): within 1 ulp of the IEEE quotient for
+// d > ε and finite n, and exactly 1 when n = d (the exact FMA residual then
+// carries the whole error of the first quotient).
+__device__ __forceinline__ float nr_quotient(float n, float d) {
+  const float y = __builtin_amdgcn_rcpf(d);
+  const float q0 = n * y;
+  return fmaf(fmaf(-d, q0, n), y, q0);
+}
+
+// Guarded ratio φ / b for b > ε, else 1.
 __device__ __forceinline__ float guarded_ratio(float phi, float b) {
-  const float y = __builtin_amdgcn_rcpf(b);
-  const float q0 = phi * y;
-  const float e = fmaf(-b, q0, phi);
-  const float q = fmaf(e, y, q0);
+  const float q = nr_quotient(phi, b);
   return b > kEps ? q : 1.f;
 }
 
-// ---------------------------------------------------------------------------
-// Forward pass: ψ (one input) → ratio planes of NV views.
-// ---------------------------------------------------------------------------
-template <int KB, int NV>
-__device__ __forceinline__ void fwd_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
-                                             const float (&ph)[NV][NX]) {
+template <int KB, int NV, int EP>
+__device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
+                                                const float (&ops)[NV][Epi<EP>::nbuf][NX]) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     float b[NX];
     xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, a->tx[v], b);
     float r[NX];
+    if constexpr (EP == kEpRatio) {
 #pragma unroll
-    for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(fmaxf(ph[v][n], 0.f), b[n]);
-    store8(a->out[v] + itm.off, itm.nvalid, vec, r);
+      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(fmaxf(ops[v][0][n], 0.f), b[n]);
+      store8(a->out[v] + itm.off, itm.nvalid, vec, r);
+    } else if constexpr (EP == kEpStore) {
+      store8(a->out[v] + itm.off, itm.nvalid, vec, b);
+    } else if constexpr (EP == kEpBR) {
+#pragma unroll
+      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(fmaxf(ops[v][0][n], 0.f), b[n]);
+      store8(a->out[v] + itm.off, itm.nvalid, vec, b);
+      store8(a->out2[v] + itm.off, itm.nvalid, vec, r);
+    } else if constexpr (EP == kEpBbar) {
+#pragma unroll
+      for (int n = 0; n < NX; ++n) {
+        const float bb = ops[v][1][n];
+        const float q = nr_quotient(b[n] * ops[v][0][n], bb);
+        r[n] = bb > kEps ? -q : 0.f;
+      }
+      store8(a->out[v] + itm.off, itm.nvalid, vec, r);
+    } else {
+#pragma unroll
+      for (int n = 0; n < NX; ++n) r[n] = ops[v][0][n] + b[n];
+      store8(a->out[v] + itm.off, itm.nvalid, vec, r);
+    }
   }
+}
+
+template <int NV, int EP>
+__device__ __forceinline__ void load_ops(KArg *a, const Item &itm, bool vec, float (&ops)[NV][Epi<EP>::nbuf][NX]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int k = 0; k < Epi<EP>::nops; ++k) load8(op_ptr<EP>(a, v, k) + itm.off, itm.nvalid, vec, ops[v][k]);
 }
 
 // One ring phase: group i = i0 + u.  u is a compile-time constant so every
 // ring index below is one too and the ring stays in registers.
-template <int KB, int C, int NV, int u>
+template <int KB, int C, int NV, int EP, int u>
 __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                           const float *__restrict__ src, float *lds, const Loop &st,
                                           float (&ring)[C][Shape<KB>::M], int i0) {
@@ -335,9 +385,8 @@ __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, S
     load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
                    &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
   const Item first = item_at(st.t, st, o, i, a);
-  float ph[NV][NX];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) load8(a->phi[v] + first.off, first.nvalid, st.vec, ph[v]);
+  float ops[NV][Epi<EP>::nbuf][NX];
+  load_ops<NV, EP>(a, first, st.vec, ops);
   // 2. column pass → LDS
   float *buf = lds + (i & 1) * st.bufsz;
 #pragma unroll
@@ -347,30 +396,28 @@ __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, S
     store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
   }
   lds_sync();
-  // 3. row pass + ratio
-  if (first.valid) fwd_epilogue<KB, NV>(a, buf, first, st.vec, ph);
+  // 3. row pass + epilogue
+  if (first.valid) single_epilogue<KB, NV, EP>(a, buf, first, st.vec, ops);
   for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
     const Item itm = item_at(it, st, o, i, a);
     if (!itm.valid) continue;
-    float q[NV][NX];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) load8(a->phi[v] + itm.off, itm.nvalid, st.vec, q[v]);
-    fwd_epilogue<KB, NV>(a, buf, itm, st.vec, q);
+    float q[NV][Epi<EP>::nbuf][NX];
+    load_ops<NV, EP>(a, itm, st.vec, q);
+    single_epilogue<KB, NV, EP>(a, buf, itm, st.vec, q);
   }
 }
 
-template <int KB, int C, int NV, int... us>
+template <int KB, int C, int NV, int EP, int... us>
 __device__ __forceinline__ void fwd_phases(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                            const float *__restrict__ src, float *lds, const Loop &st,
                                            float (&ring)[C][Shape<KB>::M], int i0,
                                            std::integer_sequence<int, us...>) {
-  (fwd_group<KB, C, NV, us>(a, o, cl, src, lds, st, ring, i0), ...);
+  (fwd_group<KB, C, NV, EP, us>(a, o, cl, src, lds, st, ring, i0), ...);
 }
-
 
 // OCC: minimum waves per SIMD the register budget must allow (second
 // launch-bounds argument): 4 caps a thread at 128 VGPRs, 2 at 256.
-template <int KB, int C, int NV, int OCC>
+template <int KB, int C, int NV, int OCC, int EP>
 __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_forward_kernel(const SepPassArgs) {
   KArg *a = kargs();
   using S = Shape<KB>;
@@ -387,7 +434,7 @@ __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_forward_kernel(const 
 #pragma unroll
   for (int m = 0; m < G + KB - 1; ++m) load_row<C, R>(src, st.rbase + m, a, cl, &ring[0][m], M);
   for (int i0 = 0; i0 < o.ngroups; i0 += U)
-    fwd_phases<KB, C, NV>(a, o, cl, src, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
+    fwd_phases<KB, C, NV, EP>(a, o, cl, src, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
 }
 
 // ---------------------------------------------------------------------------
@@ -505,17 +552,41 @@ hipError_t forward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s)
   if constexpr (KB <= 41) {
     // two columns per thread only where the ring still fits (the planner never asks otherwise)
     if (p.cols == 2) {
-      if (a.nviews == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 2, 2>, a, p.threads, lds, s);
-      return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2>, a, p.threads, lds, s);
+      if (a.nviews == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 2, 2, kEpRatio>, a, p.threads, lds, s);
+      return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, kEpRatio>, a, p.threads, lds, s);
     }
   }
   if (p.cols != 1) return hipErrorInvalidValue;
   if (a.nviews == 2) {
-    if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 2, 4>, a, p.threads, lds, s);
-    return launch_with_lds(sep_forward_kernel<KB, 1, 2, 2>, a, p.threads, lds, s);
+    if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 2, 4, kEpRatio>, a, p.threads, lds, s);
+    return launch_with_lds(sep_forward_kernel<KB, 1, 2, 2, kEpRatio>, a, p.threads, lds, s);
   }
-  if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4>, a, p.threads, lds, s);
-  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2>, a, p.threads, lds, s);
+  if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, kEpRatio>, a, p.threads, lds, s);
+  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, kEpRatio>, a, p.threads, lds, s);
+}
+
+// One-view single-input pass with an adjoint epilogue (kStore, kBR, kBbar, kAccum).
+template <int KB, int EP>
+hipError_t single_ep(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  const size_t lds = lds_bytes(a, 1);
+  if constexpr (KB <= 41) {
+    if (p.cols == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, EP>, a, p.threads, lds, s);
+  }
+  if (p.cols != 1) return hipErrorInvalidValue;
+  if constexpr (KB <= 31) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, EP>, a, p.threads, lds, s);
+  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, EP>, a, p.threads, lds, s);
+}
+
+template <int KB>
+hipError_t single_bucket(const SepPassArgs &a, const SepPlan &p, int ep, hipStream_t s) {
+  if (a.nviews != 1) return hipErrorInvalidValue;
+  switch (ep) {
+    case kEpStore: return single_ep<KB, kEpStore>(a, p, s);
+    case kEpBR: return single_ep<KB, kEpBR>(a, p, s);
+    case kEpBbar: return single_ep<KB, kEpBbar>(a, p, s);
+    case kEpAccum: return single_ep<KB, kEpAccum>(a, p, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int KB>
@@ -541,5 +612,8 @@ hipError_t backward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s
   }                                                                                        \
   hipError_t sep_backward_kb##KB(const SepPassArgs &a, const SepPlan &p, hipStream_t s) { \
     return sepk::backward_bucket<KB>(a, p, s);                                             \
+  }                                                                                        \
+  hipError_t sep_single_kb##KB(const SepPassArgs &a, const SepPlan &p, int ep, hipStream_t s) { \
+    return sepk::single_bucket<KB>(a, p, ep, s);                                           \
   }                                                                                        \
   }

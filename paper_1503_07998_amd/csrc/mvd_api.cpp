@@ -34,6 +34,29 @@ hipError_t sep_backward_kb31(const SepPassArgs &, const SepPlan &, hipStream_t);
 hipError_t sep_backward_kb41(const SepPassArgs &, const SepPlan &, hipStream_t);
 hipError_t sep_backward_kb63(const SepPassArgs &, const SepPlan &, hipStream_t);
 
+hipError_t sep_single_kb3(const SepPassArgs &, const SepPlan &, int, hipStream_t);
+hipError_t sep_single_kb7(const SepPassArgs &, const SepPlan &, int, hipStream_t);
+hipError_t sep_single_kb11(const SepPassArgs &, const SepPlan &, int, hipStream_t);
+hipError_t sep_single_kb15(const SepPassArgs &, const SepPlan &, int, hipStream_t);
+hipError_t sep_single_kb21(const SepPassArgs &, const SepPlan &, int, hipStream_t);
+hipError_t sep_single_kb31(const SepPassArgs &, const SepPlan &, int, hipStream_t);
+hipError_t sep_single_kb41(const SepPassArgs &, const SepPlan &, int, hipStream_t);
+hipError_t sep_single_kb63(const SepPassArgs &, const SepPlan &, int, hipStream_t);
+
+hipError_t launch_sep_single_dispatch(const SepPassArgs &a, const SepPlan &p, int ep, hipStream_t s) {
+  switch (p.bucket) {
+    case 3: return sep_single_kb3(a, p, ep, s);
+    case 7: return sep_single_kb7(a, p, ep, s);
+    case 11: return sep_single_kb11(a, p, ep, s);
+    case 15: return sep_single_kb15(a, p, ep, s);
+    case 21: return sep_single_kb21(a, p, ep, s);
+    case 31: return sep_single_kb31(a, p, ep, s);
+    case 41: return sep_single_kb41(a, p, ep, s);
+    case 63: return sep_single_kb63(a, p, ep, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_sep_forward(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   switch (p.bucket) {
     case 3: return sep_forward_kb3(a, p, s);
@@ -565,6 +588,139 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
   return hipSuccess;
 }
 
+
+// ---- reverse sweep (adjoint) ----------------------------------------------
+constexpr int kPointBlocks = 1024;
+constexpr int kCorrBlocks = 1024;
+
+struct BwdLayout {
+  bool stage = false;
+  size_t plane_set = 0;
+  size_t phi_off = 0, b_off = 0, r_off = 0, q_off = 0, g_off = 0, sub_off = 0, rat_off = 0;
+  size_t wpart_off = 0, cpart_off = 0, acc_off = 0, total = 0;
+  int nsets = 0, nsub = 0, kzp = 4, kxp = 8;
+};
+
+// accumulators: per view [psf kz·kx][back kz·kx], then V weights (doubles)
+size_t acc_psf(const mvd_ctx *c, int v) { return (size_t)v * 2 * kMaxK * kMaxK; }
+size_t acc_back(const mvd_ctx *c, int v) { return acc_psf(c, v) + kMaxK * kMaxK; }
+size_t acc_w(const mvd_ctx *c) { return (size_t)c->nv * 2 * kMaxK * kMaxK; }
+
+BwdLayout bwd_layout_of(const mvd_ctx *c, const mvd_run *r) {
+  BwdLayout L;
+  const int V = c->nv;
+  const bool sim = r->update == MVD_UPDATE_SIMULTANEOUS;
+  L.plane_set = align_up((size_t)r->n_planes * c->Z * c->X * sizeof(float));
+  L.stage = !(r->obs_layout == MVD_PLANES_YZX && r->obs_dtype == MVD_F32);
+  L.nsets = sim ? V : 1;
+  L.nsub = sim ? 0 : V - 1;
+  size_t off = 0;
+  L.phi_off = off;
+  if (L.stage) off += (size_t)V * L.plane_set;
+  L.b_off = off;
+  off += (size_t)L.nsets * L.plane_set;
+  L.r_off = off;
+  off += (size_t)L.nsets * L.plane_set;
+  L.q_off = off;
+  off += (size_t)L.nsets * L.plane_set;
+  L.g_off = off;
+  off += 2 * L.plane_set;
+  L.sub_off = off;
+  off += (size_t)L.nsub * L.plane_set;
+  L.rat_off = off;
+  if (!sim) off += L.plane_set;
+  for (auto &w : c->views) {
+    L.kzp = std::max({L.kzp, corr_pad(w.psf.kz, 4), corr_pad(w.back.kz, 4)});
+    L.kxp = std::max({L.kxp, corr_pad(w.psf.kx, 8), corr_pad(w.back.kx, 8)});
+  }
+  L.wpart_off = off;
+  off += align_up(sizeof(double) * kPointBlocks * V);
+  L.cpart_off = off;
+  off += align_up(sizeof(float) * (size_t)kCorrBlocks * L.kzp * L.kxp);
+  L.acc_off = off;
+  off += align_up(sizeof(double) * (acc_w(c) + V));
+  L.total = off;
+  return L;
+}
+
+std::vector<float> reversed(const std::vector<float> &f) { return std::vector<float>(f.rbegin(), f.rend()); }
+
+// One view's single-input separable pass with epilogue `ep`.
+hipError_t single_pass(const RunState &st, int ep, const float *in, const std::vector<float> &fz,
+                       const std::vector<float> &fx, float *out, float *out2, const float *aux0,
+                       const float *aux1, const float *phi) {
+  const int k = std::max((int)fz.size(), (int)fx.size());
+  SepGeom sg = plan_sep(st.c, st.g.Y, sep_bucket(k));
+  sg.plan.occ = (sg.plan.cols == 1 && sg.plan.bucket <= 31) ? 4 : 2;
+  SepPassArgs a{};
+  fill_sep_common(a, sg, st.g, st.boundary);
+  a.nviews = 1;
+  a.in[0] = in;
+  a.out[0] = out;
+  a.out2[0] = out2;
+  a.aux0[0] = aux0;
+  a.aux1[0] = aux1;
+  a.phi[0] = phi;
+  put_factor(a.tz[0], fz, sg.plan.bucket);
+  put_factor(a.tx[0], fx, sg.plan.bucket);
+  a.vec = whole_items(sg, st.g) && aligned16(in) && aligned16(out);
+  for (const void *p : {(const void *)out2, (const void *)aux0, (const void *)aux1, (const void *)phi})
+    if (p) a.vec = a.vec && aligned16(p);
+  return timed(st, 3, [&] { return launch_sep_single_dispatch(a, sg.plan, ep, st.s); });
+}
+
+hipError_t tap_corr(const RunState &st, const BwdLayout &L, char *ws, const float *gbar, const float *src,
+                    int kz, int kx, double *acc) {
+  CorrArgs a{};
+  a.g = st.g;
+  a.boundary = st.boundary;
+  a.rz = (kz - 1) / 2;
+  a.rx = (kx - 1) / 2;
+  a.kzp = corr_pad(kz, 4);
+  a.kxp = corr_pad(kx, 8);
+  a.gbar = gbar;
+  a.src = src;
+  a.part = reinterpret_cast<float *>(ws + L.cpart_off);
+  const long ntiles = (long)st.g.Y * ((st.g.Z + 7) / 8) * ((st.g.X + 63) / 64);
+  const int nb = (int)std::min<long>(kCorrBlocks, ntiles);
+  hipError_t e = timed(st, 4, [&] { return launch_corr(a, nb, st.s); });
+  if (e == hipSuccess)
+    e = timed(st, 4, [&] { return launch_corr_finalize(a.part, nb, a.kzp, a.kxp, kz, kx, acc, st.s); });
+  return e;
+}
+
+// Reverse sweep through view v at estimate psi (b, r, q buffers given):
+// gbar_in = ∂L/∂(ψ after the view's factor), gbar_out += the convolution term.
+// The pointwise step is done by the caller (it differs between update orders).
+struct ViewBufs {
+  float *b, *r, *q;
+};
+
+hipError_t view_recompute(const RunState &st, int v, const float *psi, const float *phi, const ViewBufs &vb) {
+  const ViewPsf &w = st.c->views[v];
+  hipError_t e = single_pass(st, kEpBR, psi, w.pz, w.px, vb.b, vb.r, nullptr, nullptr, phi);
+  if (e == hipSuccess) e = single_pass(st, kEpStore, vb.r, w.xz, w.xx, vb.q, nullptr, nullptr, nullptr, nullptr);
+  return e;
+}
+
+hipError_t view_backprop(const RunState &st, const BwdLayout &L, char *ws, int v, const float *psi,
+                         const ViewBufs &vb, float *gbar_out, bool want_psf, bool want_back) {
+  mvd_ctx *c = st.c;
+  const ViewPsf &w = c->views[v];
+  double *acc = reinterpret_cast<double *>(ws + L.acc_off);
+  hipError_t e = hipSuccess;
+  if (want_back) e = tap_corr(st, L, ws, vb.q, vb.r, w.back.kz, w.back.kx, acc + acc_back(c, v));
+  // b̄ = −(q̄ ⊛ X^*) · r / b  (written over b)
+  if (e == hipSuccess)
+    e = single_pass(st, kEpBbar, vb.q, reversed(w.xz), reversed(w.xx), vb.b, nullptr, vb.r, vb.b, nullptr);
+  if (e == hipSuccess && want_psf) e = tap_corr(st, L, ws, vb.b, psi, w.psf.kz, w.psf.kx, acc + acc_psf(c, v));
+  // ψ̄ += b̄ ⊛ P^*
+  if (e == hipSuccess)
+    e = single_pass(st, kEpAccum, vb.b, reversed(w.pz), reversed(w.px), gbar_out, nullptr, gbar_out, nullptr,
+                    nullptr);
+  return e;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -630,7 +786,7 @@ mvd_status mvd_get_timing(mvd_ctx *c, mvd_timing *out, int reset) {
   c->err.clear();
   if (!out || out->struct_size != sizeof(mvd_timing))
     return fail(c, MVD_ERR_ARG, "out is NULL or has a wrong struct_size");
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < MVD_TIMING_KINDS; ++k) {
     out->count[k] = 0;
     out->ms[k] = 0.0;
   }
@@ -822,6 +978,140 @@ int mvd_internal_sep_plan(const mvd_ctx *c, int n_planes, int k, int *out) {
   out[10] = sg.ldsw;
   out[11] = whole_items(sg, PlaneGeom{n_planes, c->Z, c->X}) ? 1 : 0;
   out[12] = (int)(sizeof(float) * 2ull * kRowGroup * sg.ldsw);
+  return MVD_OK;
+}
+
+
+mvd_status mvd_backward_workspace_bytes(const mvd_ctx *cc, const mvd_run *r, size_t *bytes) {
+  mvd_ctx *c = const_cast<mvd_ctx *>(cc);
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  if (!bytes) return fail(c, MVD_ERR_ARG, "bytes is NULL");
+  mvd_status st = check_run(c, r);
+  if (st != MVD_OK) return st;
+  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
+  *bytes = bwd_layout_of(c, r).total;
+  return MVD_OK;
+}
+
+mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_est, const mvd_run *r,
+                        float *const *grad_psf, float *const *grad_back, float *grad_weights,
+                        float *grad_init, void *stream) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  mvd_status st = check_run(c, r);
+  if (st != MVD_OK) return st;
+  if (!obs || !grad_est) return fail(c, MVD_ERR_ARG, "obs or grad_est is NULL");
+  for (int v = 0; v < c->nv; ++v)
+    if (!obs[v]) return fail(c, MVD_ERR_ARG, "obs[%d] is NULL", v);
+  if (r->n_iters < 1) return fail(c, MVD_ERR_ARG, "n_iters must be >= 1 for the reverse sweep");
+  if (!r->checkpoints) return fail(c, MVD_ERR_ARG, "run->checkpoints must hold psi^0..psi^{T-1}");
+  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
+  if (r->flags & MVD_FLAG_FORCE_2D)
+    return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep runs rank-one kernels only");
+  for (int v = 0; v < c->nv; ++v)
+    if (!c->views[v].sep_p || !c->views[v].sep_x)
+      return fail(c, MVD_ERR_UNSUPPORTED, "view %d: PSF or back-projector is not rank one", v);
+  const BwdLayout L = bwd_layout_of(c, r);
+  if (!r->workspace || r->workspace_bytes < L.total)
+    return fail(c, MVD_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
+                r->workspace ? r->workspace_bytes : (size_t)0);
+  if ((uintptr_t)r->workspace % kAlign) return fail(c, MVD_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+  if (c->device == MVD_DEVICE_NONE) return fail(c, MVD_ERR_DEVICE, "host-only context");
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
+
+  hipStream_t s = (hipStream_t)stream;
+  const PlaneGeom g{r->n_planes, c->Z, c->X};
+  const size_t n = (size_t)g.Y * g.Z * g.X;
+  char *ws = static_cast<char *>(r->workspace);
+  RunState rs{c, g, r->boundary, false, s, r->view_weights, (r->flags & MVD_FLAG_TIMING) != 0};
+  const int V = c->nv;
+  const bool sim = r->update == MVD_UPDATE_SIMULTANEOUS;
+  auto plane = [&](size_t off, int k) { return reinterpret_cast<float *>(ws + off + (size_t)k * L.plane_set); };
+  double *acc = reinterpret_cast<double *>(ws + L.acc_off);
+  double *wpart = reinterpret_cast<double *>(ws + L.wpart_off);
+  const bool want_psf = grad_psf != nullptr, want_back = grad_back != nullptr;
+
+  std::vector<const float *> phi(V);
+  hipError_t e = launch_zero_f64(acc, (int)(acc_w(c) + V), s);
+  for (int v = 0; v < V && e == hipSuccess; ++v) {
+    if (L.stage) {
+      e = launch_stage_obs(obs[v], r->obs_dtype, r->obs_layout, g, plane(L.phi_off, v), s);
+      phi[v] = plane(L.phi_off, v);
+    } else {
+      phi[v] = static_cast<const float *>(obs[v]);
+    }
+  }
+  int cur = 0;
+  if (e == hipSuccess) e = launch_copy(grad_est, plane(L.g_off, 0), n, s);
+  const int T = r->n_iters;
+  for (int t = T - 1; t >= 0 && e == hipSuccess; --t) {
+    const float *psi = r->checkpoints + (size_t)t * n;
+    if (sim) {
+      std::vector<ViewBufs> vb(V);
+      for (int v = 0; v < V && e == hipSuccess; ++v) {
+        vb[v] = ViewBufs{plane(L.b_off, v), plane(L.r_off, v), plane(L.q_off, v)};
+        e = view_recompute(rs, v, psi, phi[v], vb[v]);
+      }
+      if (e != hipSuccess) break;
+      AdjPointArgs pa{};
+      pa.n = n;
+      pa.nv = V;
+      pa.psi = psi;
+      pa.gbar_in = plane(L.g_off, cur);
+      pa.gbar_out = plane(L.g_off, 1 - cur);
+      for (int v = 0; v < V; ++v) {
+        pa.q[v] = vb[v].q;
+        pa.w[v] = weight_of(rs, v);
+      }
+      pa.wpart = wpart;
+      e = timed(rs, 3, [&] { return launch_pointwise_sim(pa, kPointBlocks, s); });
+      if (e == hipSuccess) e = launch_sum_partials(wpart, kPointBlocks, V, acc + acc_w(c), s);
+      for (int v = 0; v < V && e == hipSuccess; ++v)
+        e = view_backprop(rs, L, ws, v, psi, vb[v], plane(L.g_off, 1 - cur), want_psf, want_back);
+      cur = 1 - cur;
+    } else {
+      // sub-states ψ_v of the sequential sweep: ψ_0 = ψ^t, ψ_{v+1} = ψ_v · c_v(ψ_v)
+      std::vector<const float *> sub(V);
+      sub[0] = psi;
+      float *rat = plane(L.rat_off, 0);
+      for (int v = 0; v + 1 < V && e == hipSuccess; ++v) {
+        float *dst = plane(L.sub_off, v);
+        std::vector<float *> rv(V, rat);
+        e = forward_views(rs, sub[v], phi.data(), rv.data(), v, 1);
+        if (e == hipSuccess) e = backward_views(rs, rv.data(), sub[v], dst, v, 1);
+        sub[v + 1] = dst;
+      }
+      const ViewBufs vb{plane(L.b_off, 0), plane(L.r_off, 0), plane(L.q_off, 0)};
+      for (int v = V - 1; v >= 0 && e == hipSuccess; --v) {
+        e = view_recompute(rs, v, sub[v], phi[v], vb);
+        if (e != hipSuccess) break;
+        AdjPointArgs pa{};
+        pa.n = n;
+        pa.nv = 1;
+        pa.psi = sub[v];
+        pa.gbar_in = plane(L.g_off, cur);
+        pa.gbar_out = plane(L.g_off, 1 - cur);
+        pa.q[0] = vb.q;
+        pa.w[0] = weight_of(rs, v);
+        pa.wpart = wpart;
+        e = timed(rs, 3, [&] { return launch_pointwise_seq(pa, kPointBlocks, s); });
+        if (e == hipSuccess) e = launch_sum_partials(wpart, kPointBlocks, 1, acc + acc_w(c) + v, s);
+        if (e == hipSuccess) e = view_backprop(rs, L, ws, v, sub[v], vb, plane(L.g_off, 1 - cur), want_psf, want_back);
+        cur = 1 - cur;
+      }
+    }
+  }
+  for (int v = 0; v < V && e == hipSuccess; ++v) {
+    const ViewPsf &w = c->views[v];
+    if (want_psf && grad_psf[v]) e = launch_to_f32(acc + acc_psf(c, v), grad_psf[v], w.psf.kz * w.psf.kx, s);
+    if (e == hipSuccess && want_back && grad_back[v])
+      e = launch_to_f32(acc + acc_back(c, v), grad_back[v], w.back.kz * w.back.kx, s);
+  }
+  if (e == hipSuccess && grad_weights) e = launch_to_f32(acc + acc_w(c), grad_weights, V, s);
+  if (e == hipSuccess && grad_init) e = launch_copy(plane(L.g_off, cur), grad_init, n, s);
+  if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "launch failed: %s", hipGetErrorString(e));
   return MVD_OK;
 }
 

@@ -56,6 +56,9 @@ struct SepPassArgs {
   const float *in[kSepFwdViews];      // forward: in[0] = ψ; backward: in[v] = r_v
   const float *phi[kSepFwdViews];     // forward: observations (float32 planes)
   float *out[kSepFwdViews];           // forward: ratio planes
+  float *out2[kSepFwdViews];          // second output (adjoint recompute: ratio planes)
+  const float *aux0[kSepFwdViews];    // epilogue operands (adjoint passes)
+  const float *aux1[kSepFwdViews];
   const float *psi_in;                // backward
   float *psi_out;                     // backward
   float w[kSepFwdViews];              // backward: view weights
@@ -78,6 +81,13 @@ struct TwoDPassArgs {
   const float *taps[k2dViews];        // device [kz][kx] per view
 };
 
+// Epilogues of the single-input separable pass.
+constexpr int kEpRatio = 0;   // out = φ / conv (guarded)
+constexpr int kEpStore = 1;   // out = conv
+constexpr int kEpBR = 2;      // out = conv, out2 = φ / conv
+constexpr int kEpBbar = 3;    // out = −conv · aux0 / aux1 where aux1 > ε, else 0
+constexpr int kEpAccum = 4;   // out = aux0 + conv
+
 // Launch configuration chosen by the host for a separable pass.
 struct SepPlan {
   int bucket;     // KB
@@ -92,6 +102,44 @@ hipError_t launch_sep_forward(const SepPassArgs &a, const SepPlan &p, hipStream_
 hipError_t launch_sep_backward(const SepPassArgs &a, const SepPlan &p, hipStream_t s);
 hipError_t launch_2d_forward(const TwoDPassArgs &a, hipStream_t s);
 hipError_t launch_2d_backward(const TwoDPassArgs &a, hipStream_t s);
+
+// Reverse sweep: pointwise step of the update (simultaneous: all views;
+// sequential: one view, nv = 1).
+struct AdjPointArgs {
+  size_t n;
+  int nv;
+  const float *psi;
+  const float *gbar_in;
+  float *gbar_out;
+  float *q[kMaxViews];   // in: q_v, out: q̄_v
+  float w[kMaxViews];
+  double *wpart;         // [blocks][nv]
+};
+
+// Tap-gradient correlation over all planes: part[block][j][i] partial sums of
+// Σ gbar[z][x] · s̃rc[z+rz−j][x+rx−i] for lags padded to kzp × kxp.
+struct CorrArgs {
+  PlaneGeom g;
+  int boundary;
+  int rz, rx;
+  int kzp, kxp;
+  const float *gbar;
+  const float *src;
+  float *part;
+};
+
+hipError_t launch_sep_single_dispatch(const SepPassArgs &a, const SepPlan &p, int ep, hipStream_t s);
+hipError_t launch_pointwise_sim(const AdjPointArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_pointwise_seq(const AdjPointArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_sum_partials(const double *part, int nblocks, int nv, double *acc, hipStream_t s);
+hipError_t launch_corr(const CorrArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_corr_finalize(const float *part, int nblocks, int kzp, int kxp, int kz, int kx, double *acc,
+                                hipStream_t s);
+hipError_t launch_to_f32(const double *src, float *dst, int n, hipStream_t s);
+hipError_t launch_zero_f64(double *dst, int n, hipStream_t s);
+int corr_pad(int k, int unit);   // smallest unit·2^n ≥ k
+size_t corr_lds_bytes(int kzp, int kxp);
+int corr_threads(int kzp, int kxp);
 
 // Observations → float32 planes.  layout 1 = stack [Z][Y][X], 2 = planes.
 hipError_t launch_stage_obs(const void *src, int dtype, int layout, PlaneGeom g, float *dst,

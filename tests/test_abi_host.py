@@ -225,3 +225,35 @@ def test_run_validation_before_device():
 
 def test_destroy_null_is_ignored():
     N.lib().mvd_destroy(None)
+
+
+def test_backward_validation_before_device():
+    ctx = api.mvd_create(2, 8, 8, N.MVD_DEVICE_NONE)
+    lib = N.lib()
+    dummy = (ctypes.c_void_p * 2)(16, 32)
+    g = ctypes.c_void_p(48)
+
+    def call(run):
+        return lib.mvd_backward(ctx, dummy, g, ctypes.byref(run), None, None, None, None, None)
+
+    try:
+        for v in range(2):
+            api.mvd_set_psf(ctx, v, np.ones((3, 3)) / 9)
+        r = api.make_run(4, 2)
+        assert call(r) == N.MVD_ERR_ARG                        # no checkpoints
+        r = api.make_run(4, 0, checkpoints=64)
+        assert call(r) == N.MVD_ERR_ARG                        # zero iterations
+        r = api.make_run(4, 2, checkpoints=64)
+        assert call(r) == N.MVD_ERR_WORKSPACE
+        need = api.mvd_backward_workspace_bytes(ctx, r)
+        assert need > api.mvd_workspace_bytes(ctx, r)
+        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need)
+        assert call(r) == N.MVD_ERR_DEVICE
+        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, force_2d=True)
+        assert call(r) == N.MVD_ERR_UNSUPPORTED
+        rng = np.random.default_rng(0)
+        api.mvd_set_psf(ctx, 1, random_psf(rng, 5, 5).astype(np.float32))   # not rank one
+        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need)
+        assert call(r) == N.MVD_ERR_UNSUPPORTED
+    finally:
+        api.mvd_destroy(ctx)

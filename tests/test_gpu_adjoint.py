@@ -1,0 +1,173 @@
+"""GPU reverse sweep (mvd_backward) against the FP64 oracle's adjoint.
+
+Bar: each gradient array within 1e-3 of the oracle's, relative to that array's
+largest magnitude (float32 recomputation and float64 fixed-order reductions
+against the float64 oracle); bitwise equal between two runs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import adjoint as OA
+from synthetic import CONFIGS, make_volume, random_psf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def gpu_forward_backward(stacks, psfs, T, gout, update="simultaneous", boundary="zero", weights=None,
+                         layout="stack_zyx"):
+    from paper_1503_07998_amd import api
+
+    torch = _torch()
+    dev = "cuda:0"
+    obs = [torch.from_numpy(np.ascontiguousarray(s)).to(dev) for s in stacks]
+    if layout == "stack_zyx":
+        Z, Y, X = stacks[0].shape
+    else:
+        Y, Z, X = stacks[0].shape
+    V = len(stacks)
+    d = api.Deconvolver(V, Z, X, 0)
+    for v, p in enumerate(psfs):
+        d.set_psf(v, p, "flipped")
+    obs_dtype = "u16" if stacks[0].dtype == np.uint16 else "f32"
+    ck = torch.empty((T, Y, Z, X), dtype=torch.float32, device=dev)
+    est = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
+    run = api.make_run(Y, T, update=update, boundary=boundary, weights=weights, checkpoints=ck.data_ptr(),
+                       obs_dtype=obs_dtype, layout=layout)
+    nb = api.mvd_workspace_bytes(d.ctx, run)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+    run.workspace = (ws.data_ptr() + 255) // 256 * 256
+    run.workspace_bytes = nb
+    api.mvd_deconvolve_planes(d.ctx, obs, est, run)
+    nb2 = api.mvd_backward_workspace_bytes(d.ctx, run)
+    ws2 = torch.empty(nb2 + 256, dtype=torch.uint8, device=dev)
+    run.workspace = (ws2.data_ptr() + 255) // 256 * 256
+    run.workspace_bytes = nb2
+    g = torch.from_numpy(np.ascontiguousarray(gout.astype(np.float32))).to(dev)
+    gp = [torch.empty(p.shape, dtype=torch.float32, device=dev) for p in psfs]
+    gb = [torch.empty(p.shape, dtype=torch.float32, device=dev) for p in psfs]
+    gw = torch.empty(V, dtype=torch.float32, device=dev)
+    gi = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
+    api.mvd_backward(d.ctx, obs, g, run, gp, gb, gw, gi)
+    torch.cuda.synchronize()
+    out = dict(est=est.cpu().numpy(), grad_psf=[x.cpu().numpy() for x in gp],
+               grad_back=[x.cpu().numpy() for x in gb], grad_weights=gw.cpu().numpy(), grad_init=gi.cpu().numpy())
+    d.close()
+    return out
+
+
+def oracle_adjoint(stacks, psfs, T, gout, update="simultaneous", boundary="zero", weights=None, method="direct"):
+    phis = [oracle.reslice(s) for s in stacks]
+    ps = [p.astype(np.float64) for p in psfs]
+    xs = [oracle.flip(p) for p in ps]
+    return OA.adjoint(phis, ps, xs, weights, T, gout, update, boundary, method=method)
+
+
+def close(got, ref, name, tol=TOL):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max() / scale if scale > 0 else np.abs(got).max()
+    assert err <= tol, f"{name}: max|d|/max = {err:.3e}"
+    return err
+
+
+CASES = [
+    # (Y, Z, X, kernel shapes, T, update, boundary, weights)
+    (3, 40, 48, [(9, 7), (7, 9)], 3, "simultaneous", "zero", [0.9, 0.7]),
+    (2, 33, 30, [(5, 9), (9, 5)], 3, "simultaneous", "periodic", None),
+    (2, 24, 40, [(7, 5), (5, 7), (3, 3)], 2, "sequential", "zero", [1.0, 0.6, 0.8]),
+    (2, 17, 64, [(15, 15), (11, 11)], 2, "sequential", "periodic", None),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"a{i}" for i in range(len(CASES))])
+def test_backward_matches_oracle_adjoint(case):
+    Y, Z, X, shapes, T, update, boundary, weights = case
+    _say(f"backward Y={Y} Z={Z} X={X} k={shapes} T={T} {update} {boundary} w={weights}")
+    rng = np.random.default_rng(Y * 1000 + Z * 10 + X)
+    psfs = [random_psf(rng, kz, kx, separable=True).astype(np.float32) for kz, kx in shapes]
+    stacks = [rng.uniform(20.0, 300.0, (Z, Y, X)).astype(np.float32) for _ in shapes]
+    gout = rng.standard_normal((Y, Z, X))
+    got = gpu_forward_backward(stacks, psfs, T, gout, update, boundary, weights)
+    ref = oracle_adjoint(stacks, psfs, T, gout, update, boundary, weights)
+    for v in range(len(shapes)):
+        close(got["grad_psf"][v], ref["grad_psf"][v], f"grad_psf[{v}]")
+        close(got["grad_back"][v], ref["grad_back"][v], f"grad_back[{v}]")
+    close(got["grad_weights"], ref["grad_weights"], "grad_weights")
+    close(got["grad_init"], ref["grad_psi0"], "grad_init")
+
+
+def test_backward_is_deterministic():
+    _say("backward determinism")
+    rng = np.random.default_rng(77)
+    psfs = [random_psf(rng, 9, 9, separable=True).astype(np.float32) for _ in range(2)]
+    stacks = [rng.uniform(20.0, 300.0, (64, 4, 64)).astype(np.float32) for _ in range(2)]
+    gout = rng.standard_normal((4, 64, 64))
+    a = gpu_forward_backward(stacks, psfs, 3, gout)
+    b = gpu_forward_backward(stacks, psfs, 3, gout)
+    for k in ("grad_weights", "grad_init"):
+        np.testing.assert_array_equal(a[k], b[k])
+    for v in range(2):
+        np.testing.assert_array_equal(a["grad_psf"][v], b["grad_psf"][v])
+        np.testing.assert_array_equal(a["grad_back"][v], b["grad_back"][v])
+
+
+def test_grad256_planes_match_oracle():
+    """The differentiation workload (2 views, 256×256 planes, 31×31 PSFs,
+    5 iterations, MSE to the truth) on 2 planes at full plane size."""
+    _say("grad256 workload, 2 planes")
+    spec = CONFIGS["grad256"]
+    vol = make_volume(spec, planes=2)
+    truth = np.ascontiguousarray(np.transpose(vol["truth"], (1, 0, 2))).astype(np.float64)
+    # forward on the GPU to get ψ^T, then ∂L/∂ψ^T of the MSE
+    from paper_1503_07998_amd import deconvolve
+    torch = _torch()
+    est = deconvolve([torch.from_numpy(s).to("cuda:0") for s in vol["stacks"]], vol["psfs"],
+                     iters=spec.iters).cpu().numpy().astype(np.float64)
+    _, gout = OA.mse_loss_and_grad(est, truth)
+    got = gpu_forward_backward(vol["stacks"], vol["psfs"], spec.iters, gout, weights=[0.9, 0.8])
+    ref = oracle_adjoint(vol["stacks"], vol["psfs"], spec.iters, gout, weights=[0.9, 0.8], method="fft")
+    for v in range(2):
+        close(got["grad_psf"][v], ref["grad_psf"][v], f"grad_psf[{v}]")
+        close(got["grad_back"][v], ref["grad_back"][v], f"grad_back[{v}]")
+    close(got["grad_weights"], ref["grad_weights"], "grad_weights")
+
+
+def test_autograd_sigma_gradients():
+    """σ and weight gradients through torch.autograd vs the oracle's chain."""
+    from paper_1503_07998_amd.autograd import PlanewiseRL
+
+    torch = _torch()
+    _say("autograd sigma gradients")
+    rng = np.random.default_rng(9)
+    Y, Z, X, k, T = 2, 40, 36, 11, 3
+    truth = 100.0 + 600.0 * (rng.random((Y, Z, X)) > 0.95)
+    data_sig = [(1.5, 3.0), (3.0, 1.5)]
+    phis = [oracle.conv2d(truth, OA.gaussian_taps(k, *s)[0]) + rng.uniform(0, 2, truth.shape) for s in data_sig]
+    stacks = [np.ascontiguousarray(np.transpose(p, (1, 0, 2))).astype(np.float32) for p in phis]
+    sig = [(1.7, 3.3), (3.2, 1.6)]
+    ws = [0.9, 0.8]
+    prob = PlanewiseRL([torch.from_numpy(s).to("cuda:0") for s in stacks], k, T)
+    sigma = torch.tensor(sig, dtype=torch.float64, requires_grad=True)
+    w = torch.tensor(ws, dtype=torch.float64, requires_grad=True)
+    psi = prob(sigma, w)
+    loss = ((psi.double() - torch.from_numpy(truth).to("cuda:0")) ** 2).mean()
+    loss.backward()
+    phis32 = [oracle.reslice(s) for s in stacks]
+    ref_loss, ref_gs, ref_gw = OA.sigma_gradients(phis32, sig, ws, T, truth, k)
+    assert abs(loss.item() - ref_loss) <= 1e-4 * ref_loss
+    close(sigma.grad.numpy(), ref_gs, "dL/dsigma")
+    close(w.grad.numpy(), ref_gw, "dL/dw")
+    prob.dec.close()
