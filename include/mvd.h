@@ -98,6 +98,9 @@ typedef enum { MVD_INIT_MEAN = 0, MVD_INIT_GIVEN = 1, MVD_INIT_CONST = 2 } mvd_i
 /* mvd_run.flags */
 #define MVD_FLAG_FORCE_2D 0x1u /* use the general K×K kernels even for rank-1 PSFs */
 #define MVD_FLAG_TIMING 0x2u   /* record HIP events around every launch (see mvd_get_timing) */
+#define MVD_FLAG_GRAPH 0x4u    /* capture the whole run into a HIP graph on first use and replay it
+                                  (per context, keyed by every pointer and parameter of the run;
+                                  not with MVD_FLAG_TIMING) */
 
 /* Parameters of one deconvolution run.  struct_size must be sizeof(mvd_run). */
 typedef struct {
@@ -220,6 +223,47 @@ mvd_status mvd_backward_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, 
 mvd_status mvd_backward(mvd_ctx *ctx, const void *const *obs, const float *grad_est,
                         const mvd_run *run, float *const *grad_psf, float *const *grad_back,
                         float *grad_weights, float *grad_init, void *stream);
+
+/* ---- batched form --------------------------------------------------------
+ * Several deconvolutions (volumes of different plane sizes, view counts and
+ * PSF sizes, each with its own context, observations, estimate and run
+ * parameters) captured into one HIP graph: every volume's whole iteration
+ * loop is one branch of the graph, so a single launch runs all of them
+ * concurrently.  Items are copied; their device buffers must stay valid and
+ * unchanged in address while the batch exists. */
+typedef struct {
+  mvd_ctx *ctx;
+  const void *const *obs;   /* host array of the context's V device pointers */
+  float *est;
+  const mvd_run *run;       /* flags must not include MVD_FLAG_TIMING or MVD_FLAG_GRAPH */
+} mvd_item;
+
+typedef struct mvd_batch mvd_batch;
+
+#define MVD_BATCH_TUNE 0x1u /* time launch-shape candidates per item before capture (runs
+                               one iteration of each item on `stream`, synchronously; items
+                               with MVD_INIT_GIVEN keep the default shapes).  The choice is
+                               cached per workload shape for the process. */
+
+/* Validate every item, optionally autotune, and capture the batch graph.
+ * All items must be on one device.  Errors: MVD_ERR_ARG (item index in
+ * mvd_last_error(NULL)), MVD_ERR_WORKSPACE, MVD_ERR_STATE, MVD_ERR_DEVICE,
+ * MVD_ERR_LAUNCH, MVD_ERR_ALLOC. */
+mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items, uint32_t flags,
+                            void *stream);
+
+/* Launch the captured batch on `stream` (asynchronous). */
+mvd_status mvd_batch_launch(mvd_batch *b, void *stream);
+
+/* Launch shapes chosen for item `item`: out[4] = forward occupancy, forward
+ * views per launch, backward inputs per launch, segment scale (0 = default). */
+mvd_status mvd_batch_tuning(const mvd_batch *b, int item, int *out);
+
+/* Release a batch (the caller has synchronised its launches). */
+void mvd_batch_destroy(mvd_batch *b);
+
+/* One-shot: create (no tuning), launch, wait for completion, destroy. */
+mvd_status mvd_batch_run(const mvd_item *items, int n_items, void *stream);
 
 /* Per-context message of the last failing call (empty if none); valid until
  * the next call on the context.  ctx NULL gives the last message of a call

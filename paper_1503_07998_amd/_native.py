@@ -29,6 +29,7 @@ BOUNDARY = {"zero": 0, "periodic": 1}
 INIT = {"mean": 0, "given": 1, "const": 2}
 MVD_FLAG_FORCE_2D = 0x1
 MVD_FLAG_TIMING = 0x2
+MVD_FLAG_GRAPH = 0x4
 MVD_DEVICE_NONE = -1
 MVD_MAX_VIEWS = 8
 MVD_MAX_K = 63
@@ -61,6 +62,15 @@ class MvdTiming(ctypes.Structure):
     _fields_ = [("struct_size", c_uint32), ("count", c_int32 * 5), ("ms", ctypes.c_double * 5)]
 
 
+class MvdItem(ctypes.Structure):
+    """Mirror of ``mvd_item``."""
+
+    _fields_ = [("ctx", c_void_p), ("obs", POINTER(c_void_p)), ("est", c_void_p), ("run", POINTER(MvdRun))]
+
+
+MVD_BATCH_TUNE = 0x1
+
+
 class MvdError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"mvd status {status}: {message}")
@@ -83,6 +93,11 @@ SIGNATURES = {
     "mvd_backward_workspace_bytes": (c_int, [c_void_p, POINTER(MvdRun), POINTER(c_size_t)]),
     "mvd_backward": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), POINTER(c_void_p),
                              POINTER(c_void_p), c_void_p, c_void_p, c_void_p]),
+    "mvd_batch_create": (c_int, [POINTER(c_void_p), POINTER(MvdItem), c_int, c_uint32, c_void_p]),
+    "mvd_batch_launch": (c_int, [c_void_p, c_void_p]),
+    "mvd_batch_tuning": (c_int, [c_void_p, c_int, POINTER(c_int)]),
+    "mvd_batch_destroy": (None, [c_void_p]),
+    "mvd_batch_run": (c_int, [POINTER(MvdItem), c_int, c_void_p]),
     "mvd_last_error": (ctypes.c_char_p, [c_void_p]),
 }
 

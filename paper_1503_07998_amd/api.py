@@ -17,7 +17,8 @@ __all__ = [
     "mvd_version", "mvd_create", "mvd_destroy", "mvd_set_psf", "mvd_get_back_taps",
     "mvd_psf_info", "mvd_workspace_bytes", "mvd_reslice", "mvd_deconvolve_planes",
     "mvd_get_timing", "mvd_last_error", "make_run", "Deconvolver", "deconvolve",
-    "mvd_backward_workspace_bytes", "mvd_backward",
+    "mvd_backward_workspace_bytes", "mvd_backward", "mvd_batch_create", "mvd_batch_launch",
+    "mvd_batch_tuning", "mvd_batch_destroy", "mvd_batch_run", "Batch",
 ]
 
 
@@ -97,11 +98,13 @@ def mvd_psf_info(ctx, view: int):
 
 def make_run(n_planes, n_iters, *, update="simultaneous", boundary="zero", init="mean",
              init_const=1.0, obs_dtype="f32", layout="stack_zyx", weights=None,
-             checkpoints=None, workspace=None, workspace_bytes=0, force_2d=False, timing=False):
+             checkpoints=None, workspace=None, workspace_bytes=0, force_2d=False, timing=False,
+             graph=False):
     """Build an ``mvd_run``; keeps host weight storage alive on the object."""
     r = N.MvdRun()
     r.struct_size = ctypes.sizeof(N.MvdRun)
-    r.flags = (N.MVD_FLAG_FORCE_2D if force_2d else 0) | (N.MVD_FLAG_TIMING if timing else 0)
+    r.flags = ((N.MVD_FLAG_FORCE_2D if force_2d else 0) | (N.MVD_FLAG_TIMING if timing else 0)
+               | (N.MVD_FLAG_GRAPH if graph else 0))
     r.n_planes = int(n_planes)
     r.n_iters = int(n_iters)
     r.update = N.UPDATE[update]
@@ -171,6 +174,73 @@ def mvd_backward(ctx, obs, grad_est, run, grad_psf=None, grad_back=None, grad_we
                                  _dev_ptr(grad_weights) if grad_weights is not None else None,
                                  _dev_ptr(grad_init) if grad_init is not None else None,
                                  _stream_handle(stream)), ctx)
+
+
+def _items(entries):
+    """entries: [(ctx, obs tensors, est tensor, run)] → ctypes array + keep-alive list."""
+    arr = (N.MvdItem * len(entries))()
+    keep = []
+    for i, (ctx, obs, est, run) in enumerate(entries):
+        ptrs = (c_void_p * len(obs))(*[_dev_ptr(o).value for o in obs])
+        keep.append(ptrs)
+        arr[i].ctx = ctx
+        arr[i].obs = ctypes.cast(ptrs, POINTER(c_void_p))
+        arr[i].est = _dev_ptr(est)
+        arr[i].run = ctypes.pointer(run)
+        keep.append(run)
+    return arr, keep
+
+
+def mvd_batch_create(entries, tune=False, stream=None):
+    arr, keep = _items(entries)
+    b = c_void_p()
+    N.check(N.lib().mvd_batch_create(ctypes.byref(b), arr, len(entries), N.MVD_BATCH_TUNE if tune else 0,
+                                     _stream_handle(stream)))
+    return b
+
+
+def mvd_batch_launch(b, stream=None) -> None:
+    N.check(N.lib().mvd_batch_launch(b, _stream_handle(stream)))
+
+
+def mvd_batch_tuning(b, item: int):
+    out = (c_int * 4)()
+    N.check(N.lib().mvd_batch_tuning(b, int(item), out))
+    return dict(fwd_occ=out[0], fwd_views=out[1], bwd_vin=out[2], zseg_scale=out[3])
+
+
+def mvd_batch_destroy(b) -> None:
+    N.lib().mvd_batch_destroy(b)
+
+
+def mvd_batch_run(entries, stream=None) -> None:
+    arr, keep = _items(entries)
+    N.check(N.lib().mvd_batch_run(arr, len(entries), _stream_handle(stream)))
+
+
+class Batch:
+    """Several deconvolutions in one HIP graph (one branch per volume)."""
+
+    def __init__(self, entries, tune=False, stream=None):
+        self.entries = entries          # keeps tensors and runs alive
+        self.handle = mvd_batch_create(entries, tune, stream)
+
+    def launch(self, stream=None):
+        mvd_batch_launch(self.handle, stream)
+
+    def tuning(self, item):
+        return mvd_batch_tuning(self.handle, item)
+
+    def close(self):
+        if self.handle is not None:
+            mvd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -125,6 +127,14 @@ struct mvd_ctx {
   };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
+  // captured runs (MVD_FLAG_GRAPH)
+  struct Graph {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Graph> graphs;
+  uint64_t psf_generation = 0;   // bumped by every mvd_set_psf (captured taps change)
 };
 
 namespace {
@@ -298,7 +308,7 @@ mvd_status check_run(mvd_ctx *c, const mvd_run *r) {
     return fail(c, MVD_ERR_ARG, "unknown obs_dtype %d", r->obs_dtype);
   if (r->obs_layout != MVD_STACK_ZYX && r->obs_layout != MVD_PLANES_YZX)
     return fail(c, MVD_ERR_ARG, "unknown obs_layout %d", r->obs_layout);
-  if (r->flags & ~(MVD_FLAG_FORCE_2D | MVD_FLAG_TIMING))
+  if (r->flags & ~(MVD_FLAG_FORCE_2D | MVD_FLAG_TIMING | MVD_FLAG_GRAPH))
     return fail(c, MVD_ERR_ARG, "unknown flags 0x%x", r->flags);
   if (r->view_weights)
     for (int v = 0; v < c->nv; ++v) {
@@ -321,6 +331,7 @@ int round_up(int n, int m) { return (n + m - 1) / m * m; }
 // environment: MVD_TUNE="fwd_occ=4,bwd_occ=2,bwd_vin=1,zseg=64" (0 = automatic).
 struct Tune {
   int fwd_occ = 0, bwd_occ = 0, bwd_vin = 0, zseg = 0, fwd_views = 0;
+  int zseg_scale = 0;   // > 0: segment length × 2^(zseg_scale − 2) of the automatic one (2 = as is)
 };
 
 const Tune &tune() {
@@ -351,7 +362,7 @@ const Tune &tune() {
   return t;
 }
 
-SepGeom plan_sep(const mvd_ctx *c, int Y, int kb) {
+SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, const Tune &tn = tune()) {
   SepGeom s{};
   const int R = (kb - 1) / 2;
   const int X = c->X;
@@ -388,7 +399,9 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb) {
   int nseg = (int)std::max(1L, (2048 + tiles - 1) / tiles);
   nseg = std::min(nseg, std::max(1, Z / 32));
   s.zseg = round_up((Z + nseg - 1) / nseg, kRowGroup);
-  if (tune().zseg > 0) s.zseg = round_up(tune().zseg, kRowGroup);
+  if (tn.zseg_scale == 1) s.zseg = round_up(std::max(kRowGroup, s.zseg / 2), kRowGroup);
+  if (tn.zseg_scale == 3) s.zseg = round_up(std::min(Z, 2 * s.zseg), kRowGroup);
+  if (tn.zseg > 0) s.zseg = round_up(tn.zseg, kRowGroup);
   s.nseg = (Z + s.zseg - 1) / s.zseg;
   // one column per thread keeps a K ≤ 31 ring within 128 VGPRs: 4 waves/SIMD
   s.plan.occ = (s.plan.cols == 1 && kb <= 31) ? 4 : 2;
@@ -429,6 +442,7 @@ struct RunState {
   hipStream_t s;
   const float *w;  // host weights or nullptr
   bool timing;
+  const Tune *tn = &tune();   // launch-shape choices (environment or autotuner)
 };
 
 hipEvent_t take_event(mvd_ctx *c) {
@@ -473,11 +487,11 @@ hipError_t forward_views(const RunState &st, const float *psi, const float *cons
     kmax = std::max({kmax, c->views[v].psf.kz, c->views[v].psf.kx});
   }
   if (sep) {
-    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax));
-    if (tune().fwd_occ) sg.plan.occ = tune().fwd_occ;
+    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), *st.tn);
+    if (st.tn->fwd_occ) sg.plan.occ = st.tn->fwd_occ;
     const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
     int cap = (int)std::max<size_t>(1, std::min<size_t>(kSepFwdViews, kLdsLimit / per_view));
-    if (tune().fwd_views > 0) cap = std::min(cap, tune().fwd_views);
+    if (st.tn->fwd_views > 0) cap = std::min(cap, st.tn->fwd_views);
     for (int b = v0; b < v0 + n; b += cap) {
       const int nb = std::min(cap, v0 + n - b);
       SepPassArgs a{};
@@ -530,18 +544,18 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
   }
   const float *cur = psi_in;
   if (sep) {
-    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax));
+    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), *st.tn);
     const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
     // Two ratio planes per launch save one read and write of ψ but need two
     // rings (256-VGPR budget); one per launch runs at 4 waves/SIMD and is
     // faster wherever that variant exists (K ≤ 31, one column per thread).
     bool two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit &&
                sg.plan.occ < 4;
-    if (tune().bwd_vin == 1) two = false;
-    if (tune().bwd_vin == 2) two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41;
+    if (st.tn->bwd_vin == 1) two = false;
+    if (st.tn->bwd_vin == 2) two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit;
     sg.plan.vin = two ? 2 : 1;
     if (two) sg.plan.occ = 2;   // two rings: 256-VGPR budget
-    if (tune().bwd_occ) sg.plan.occ = tune().bwd_occ;
+    if (st.tn->bwd_occ) sg.plan.occ = st.tn->bwd_occ;
     for (int b = v0; b < v0 + n; b += sg.plan.vin) {
       const int nb = std::min(sg.plan.vin, v0 + n - b);
       SepPlan plan = sg.plan;
@@ -650,7 +664,7 @@ hipError_t single_pass(const RunState &st, int ep, const float *in, const std::v
                        const std::vector<float> &fx, float *out, float *out2, const float *aux0,
                        const float *aux1, const float *phi) {
   const int k = std::max((int)fz.size(), (int)fx.size());
-  SepGeom sg = plan_sep(st.c, st.g.Y, sep_bucket(k));
+  SepGeom sg = plan_sep(st.c, st.g.Y, sep_bucket(k), *st.tn);
   sg.plan.occ = (sg.plan.cols == 1 && sg.plan.bucket <= 31) ? 4 : 2;
   SepPassArgs a{};
   fill_sep_common(a, sg, st.g, st.boundary);
@@ -721,7 +735,246 @@ hipError_t view_backprop(const RunState &st, const BwdLayout &L, char *ws, int v
   return e;
 }
 
+
+// ---- one run: validation and enqueue ----------------------------------------
+mvd_status validate_run(mvd_ctx *c, const void *const *obs, const float *est, const mvd_run *r) {
+  mvd_status st = check_run(c, r);
+  if (st != MVD_OK) return st;
+  if (!obs) return fail(c, MVD_ERR_ARG, "obs is NULL");
+  for (int v = 0; v < c->nv; ++v)
+    if (!obs[v]) return fail(c, MVD_ERR_ARG, "obs[%d] is NULL", v);
+  if (!est) return fail(c, MVD_ERR_ARG, "est is NULL");
+  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
+  if ((r->flags & MVD_FLAG_GRAPH) && (r->flags & MVD_FLAG_TIMING))
+    return fail(c, MVD_ERR_ARG, "MVD_FLAG_GRAPH and MVD_FLAG_TIMING exclude each other");
+  const Layout L = layout_of(c, r);
+  if (L.total > 0 && (!r->workspace || r->workspace_bytes < L.total))
+    return fail(c, MVD_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
+                r->workspace ? r->workspace_bytes : (size_t)0);
+  if (r->workspace && ((uintptr_t)r->workspace % kAlign))
+    return fail(c, MVD_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+  if (c->device == MVD_DEVICE_NONE) return fail(c, MVD_ERR_DEVICE, "host-only context");
+  return MVD_OK;
+}
+
+// Enqueue reslice/convert, ψ^0 and every iteration of a validated run on `s`.
+hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, hipStream_t s,
+                       const Tune &tn, bool timing_override = false) {
+  const Layout L = layout_of(c, r);
+  const PlaneGeom g{r->n_planes, c->Z, c->X};
+  const size_t n = (size_t)g.Y * g.Z * g.X;
+  char *ws = static_cast<char *>(r->workspace);
+  RunState rs{c,  g, r->boundary, (r->flags & MVD_FLAG_FORCE_2D) != 0, s, r->view_weights,
+              timing_override || (r->flags & MVD_FLAG_TIMING) != 0, &tn};
+  std::vector<const float *> phi(c->nv);
+  hipError_t e = hipSuccess;
+  for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
+    if (L.stage) {
+      float *dst = reinterpret_cast<float *>(ws + L.phi_off + (size_t)v * L.plane_set);
+      e = timed(rs, 2, [&] { return launch_stage_obs(obs[v], r->obs_dtype, r->obs_layout, g, dst, s); });
+      phi[v] = dst;
+    } else {
+      phi[v] = static_cast<const float *>(obs[v]);
+    }
+  }
+  const int T = r->n_iters;
+  float *psi0 = (r->checkpoints && T > 0) ? r->checkpoints : est;
+  if (e == hipSuccess) {
+    if (r->init == MVD_INIT_MEAN)
+      e = timed(rs, 2, [&] { return launch_init_mean(phi.data(), c->nv, n, psi0, s); });
+    else if (r->init == MVD_INIT_CONST)
+      e = timed(rs, 2, [&] { return launch_fill(psi0, n, r->init_const, s); });
+    else if (psi0 != est)
+      e = timed(rs, 2, [&] { return launch_copy(est, psi0, n, s); });
+  }
+  std::vector<float *> rat(L.n_ratio);
+  for (int k = 0; k < L.n_ratio; ++k) rat[k] = reinterpret_cast<float *>(ws + L.r_off + (size_t)k * L.plane_set);
+  for (int t = 0; t < T && e == hipSuccess; ++t) {
+    float *cur = r->checkpoints ? r->checkpoints + (size_t)t * n : est;
+    float *nxt = r->checkpoints ? (t + 1 < T ? r->checkpoints + (size_t)(t + 1) * n : est) : est;
+    if (r->update == MVD_UPDATE_SIMULTANEOUS) {
+      e = forward_views(rs, cur, phi.data(), rat.data(), 0, c->nv);
+      if (e == hipSuccess) e = backward_views(rs, rat.data(), cur, nxt, 0, c->nv);
+    } else {
+      for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
+        const float *src = v == 0 ? cur : nxt;
+        std::vector<float *> rv(c->nv, rat[0]);
+        e = forward_views(rs, src, phi.data(), rv.data(), v, 1);
+        if (e == hipSuccess) e = backward_views(rs, rv.data(), src, nxt, v, 1);
+      }
+    }
+  }
+  return e;
+}
+
+// ---- graph capture ----------------------------------------------------------
+// A captured run is reused when every pointer and parameter is the same.
+std::vector<uint64_t> run_key(const mvd_ctx *c, const void *const *obs, const float *est, const mvd_run *r) {
+  std::vector<uint64_t> k;
+  for (int v = 0; v < c->nv; ++v) k.push_back((uint64_t)(uintptr_t)obs[v]);
+  k.push_back((uint64_t)(uintptr_t)est);
+  k.push_back((uint64_t)(uintptr_t)r->checkpoints);
+  k.push_back((uint64_t)(uintptr_t)r->workspace);
+  k.push_back(r->workspace_bytes);
+  const int32_t fields[] = {(int32_t)r->flags, r->n_planes, r->n_iters, r->update, r->boundary, r->init,
+                            r->obs_dtype, r->obs_layout};
+  for (int32_t f : fields) k.push_back((uint64_t)(uint32_t)f);
+  uint32_t ic;
+  std::memcpy(&ic, &r->init_const, 4);
+  k.push_back(ic);
+  for (int v = 0; v < c->nv; ++v) {
+    uint32_t w = 0x3f800000u;
+    if (r->view_weights) std::memcpy(&w, &r->view_weights[v], 4);
+    k.push_back(w);
+  }
+  k.push_back(c->psf_generation);
+  return k;
+}
+
+// Capture `launch(stream)` into an executable graph.
+template <typename F>
+hipError_t capture(F &&launch, hipGraph_t *graph, hipGraphExec_t *exec) {
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = launch(cs);
+    hipGraph_t gph = nullptr;
+    e = hipStreamEndCapture(cs, &gph);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, gph, nullptr, nullptr, 0);
+    if (e == hipSuccess) {
+      *graph = gph;
+    } else if (gph) {
+      (void)hipGraphDestroy(gph);
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  return e;
+}
+
+hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, hipGraphExec_t *out) {
+  const std::vector<uint64_t> key = run_key(c, obs, est, r);
+  for (auto &g : c->graphs)
+    if (g.key == key) {
+      *out = g.exec;
+      return hipSuccess;
+    }
+  mvd_ctx::Graph g;
+  g.key = key;
+  hipError_t e = capture([&](hipStream_t cs) { return enqueue_run(c, obs, est, r, cs, tune()); }, &g.graph,
+                         &g.exec);
+  if (e != hipSuccess) return e;
+  if (c->graphs.size() >= 8) {   // keep the cache small: drop the oldest
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    (void)hipGraphDestroy(c->graphs.front().graph);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back(g);
+  *out = g.exec;
+  return hipSuccess;
+}
+
+
+// ---- autotuner ----------------------------------------------------------------
+// Launch-shape candidates timed per workload (kernel sizes, plane shape, planes,
+// views, update order, boundary); the fastest is cached for the process.
+std::vector<Tune> tune_candidates() {
+  std::vector<Tune> c(6);
+  c[1].fwd_occ = 2;
+  c[2].fwd_views = 1;
+  c[3].bwd_vin = 2;
+  c[4].zseg_scale = 1;
+  c[5].zseg_scale = 3;
+  return c;
+}
+
+std::string tune_key(const mvd_ctx *c, const mvd_run *r) {
+  std::string k = "Z" + std::to_string(c->Z) + "X" + std::to_string(c->X) + "Y" + std::to_string(r->n_planes) +
+                  "V" + std::to_string(c->nv) + "u" + std::to_string(r->update) + "b" + std::to_string(r->boundary) +
+                  "f" + std::to_string(r->flags & MVD_FLAG_FORCE_2D) + "K";
+  for (auto &w : c->views)
+    k += std::to_string(w.psf.kz) + "x" + std::to_string(w.psf.kx) + (w.sep_p ? "s" : "g") +
+         std::to_string(w.back.kz) + "x" + std::to_string(w.back.kx) + (w.sep_x ? "s" : "g") + ",";
+  return k;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, Tune> g_tune_cache;
+
+// Forward + backward launch time (ms) of the marks recorded since the last drain.
+double drain_marks(mvd_ctx *c) {
+  double ms = 0.0;
+  for (auto &m : c->marks) {
+    float t = 0.f;
+    if ((m.kind == 0 || m.kind == 1) && hipEventElapsedTime(&t, m.a, m.b) == hipSuccess) ms += t;
+    c->pool.push_back(m.a);
+    c->pool.push_back(m.b);
+  }
+  c->marks.clear();
+  return ms;
+}
+
+// Time every candidate on one iteration of the item's own run (the item's
+// estimate is overwritten, so items that start from a given estimate are not
+// tuned) and return the fastest.
+hipError_t autotune(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, hipStream_t s, Tune *out) {
+  const std::string key = tune_key(c, r);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *out = it->second;
+      return hipSuccess;
+    }
+  }
+  mvd_run probe = *r;
+  probe.n_iters = 1;
+  probe.checkpoints = nullptr;
+  probe.flags &= ~(MVD_FLAG_GRAPH | MVD_FLAG_TIMING);
+  (void)drain_marks(c);
+  hipError_t e = enqueue_run(c, obs, est, &probe, s, Tune{});   // warm-up
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const std::vector<Tune> cand = tune_candidates();
+  double best = 1e30;
+  Tune pick{};
+  for (const Tune &t : cand) {
+    if (e != hipSuccess) break;
+    double ms = 0.0;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+      e = enqueue_run(c, obs, est, &probe, s, t, true);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess) ms += drain_marks(c);
+    }
+    if (e == hipSuccess && ms < best) {
+      best = ms;
+      pick = t;
+    }
+  }
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = pick;
+  *out = pick;
+  return hipSuccess;
+}
+
 }  // namespace
+
+struct mvd_batch {
+  int device = -1;
+  struct Item {
+    mvd_ctx *ctx;
+    std::vector<const void *> obs;
+    float *est;
+    mvd_run run;
+    std::vector<float> weights;
+    Tune tn;
+  };
+  std::vector<Item> items;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 // ===========================================================================
 extern "C" {
@@ -776,6 +1029,10 @@ void mvd_destroy(mvd_ctx *ctx) {
       (void)hipEventDestroy(m.b);
     }
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    for (auto &g : ctx->graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
     if (ctx->d_taps) (void)hipFree(ctx->d_taps);
   }
   delete ctx;
@@ -834,6 +1091,7 @@ mvd_status mvd_set_psf(mvd_ctx *c, int view, const float *taps, int kz, int kx, 
   w.explicit_back = back_mode == MVD_BACK_EXPLICIT ? to_kernel(back_taps, kz, kx) : Kernel{};
   w.set = true;
   c->derived = false;
+  c->psf_generation += 1;
   if (all_set(c)) return derive(c);
   return MVD_OK;
 }
@@ -890,68 +1148,17 @@ mvd_status mvd_deconvolve_planes(mvd_ctx *c, const void *const *obs, float *est,
                                  void *stream) {
   if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
   c->err.clear();
-  mvd_status st = check_run(c, r);
+  mvd_status st = validate_run(c, obs, est, r);
   if (st != MVD_OK) return st;
-  if (!obs) return fail(c, MVD_ERR_ARG, "obs is NULL");
-  for (int v = 0; v < c->nv; ++v)
-    if (!obs[v]) return fail(c, MVD_ERR_ARG, "obs[%d] is NULL", v);
-  if (!est) return fail(c, MVD_ERR_ARG, "est is NULL");
-  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
-  const Layout L = layout_of(c, r);
-  if (L.total > 0 && (!r->workspace || r->workspace_bytes < L.total))
-    return fail(c, MVD_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
-                r->workspace ? r->workspace_bytes : (size_t)0);
-  if (r->workspace && ((uintptr_t)r->workspace % kAlign))
-    return fail(c, MVD_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
-  if (c->device == MVD_DEVICE_NONE) return fail(c, MVD_ERR_DEVICE, "host-only context");
   DeviceGuard dg(c->device);
   if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
-
-  hipStream_t s = (hipStream_t)stream;
-  const PlaneGeom g{r->n_planes, c->Z, c->X};
-  const size_t n = (size_t)g.Y * g.Z * g.X;
-  char *ws = static_cast<char *>(r->workspace);
-
-  RunState rs{c,          g, r->boundary, (r->flags & MVD_FLAG_FORCE_2D) != 0, s, r->view_weights,
-              (r->flags & MVD_FLAG_TIMING) != 0};
-  std::vector<const float *> phi(c->nv);
-  hipError_t e = hipSuccess;
-  for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
-    if (L.stage) {
-      float *dst = reinterpret_cast<float *>(ws + L.phi_off + (size_t)v * L.plane_set);
-      e = timed(rs, 2, [&] { return launch_stage_obs(obs[v], r->obs_dtype, r->obs_layout, g, dst, s); });
-      phi[v] = dst;
-    } else {
-      phi[v] = static_cast<const float *>(obs[v]);
-    }
-  }
-  const int T = r->n_iters;
-  float *psi0 = (r->checkpoints && T > 0) ? r->checkpoints : est;
-  if (e == hipSuccess) {
-    if (r->init == MVD_INIT_MEAN)
-      e = timed(rs, 2, [&] { return launch_init_mean(phi.data(), c->nv, n, psi0, s); });
-    else if (r->init == MVD_INIT_CONST)
-      e = timed(rs, 2, [&] { return launch_fill(psi0, n, r->init_const, s); });
-    else if (psi0 != est)
-      e = timed(rs, 2, [&] { return launch_copy(est, psi0, n, s); });
-  }
-  std::vector<float *> rat(L.n_ratio);
-  for (int k = 0; k < L.n_ratio; ++k) rat[k] = reinterpret_cast<float *>(ws + L.r_off + (size_t)k * L.plane_set);
-
-  for (int t = 0; t < T && e == hipSuccess; ++t) {
-    float *cur = r->checkpoints ? r->checkpoints + (size_t)t * n : est;
-    float *nxt = r->checkpoints ? (t + 1 < T ? r->checkpoints + (size_t)(t + 1) * n : est) : est;
-    if (r->update == MVD_UPDATE_SIMULTANEOUS) {
-      e = forward_views(rs, cur, phi.data(), rat.data(), 0, c->nv);
-      if (e == hipSuccess) e = backward_views(rs, rat.data(), cur, nxt, 0, c->nv);
-    } else {
-      for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
-        const float *src = v == 0 ? cur : nxt;
-        std::vector<float *> rv(c->nv, rat[0]);
-        e = forward_views(rs, src, phi.data(), rv.data(), v, 1);
-        if (e == hipSuccess) e = backward_views(rs, rv.data(), src, nxt, v, 1);
-      }
-    }
+  hipError_t e;
+  if (r->flags & MVD_FLAG_GRAPH) {
+    hipGraphExec_t exec = nullptr;
+    e = cached_graph(c, obs, est, r, &exec);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, (hipStream_t)stream);
+  } else {
+    e = enqueue_run(c, obs, est, r, (hipStream_t)stream, tune());
   }
   if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "launch failed: %s", hipGetErrorString(e));
   return MVD_OK;
@@ -1113,6 +1320,124 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
   if (e == hipSuccess && grad_init) e = launch_copy(plane(L.g_off, cur), grad_init, n, s);
   if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "launch failed: %s", hipGetErrorString(e));
   return MVD_OK;
+}
+
+
+mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items, uint32_t flags, void *stream) {
+  if (!out) return fail(nullptr, MVD_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!items || n_items < 1 || n_items > 64) return fail(nullptr, MVD_ERR_ARG, "need 1..64 items");
+  if (flags & ~MVD_BATCH_TUNE) return fail(nullptr, MVD_ERR_ARG, "unknown batch flags 0x%x", flags);
+  const int dev = items[0].ctx ? items[0].ctx->device : -1;
+  for (int i = 0; i < n_items; ++i) {
+    mvd_ctx *c = items[i].ctx;
+    if (!c) return fail(nullptr, MVD_ERR_ARG, "item %d: ctx is NULL", i);
+    c->err.clear();
+    mvd_status st = validate_run(c, items[i].obs, items[i].est, items[i].run);
+    if (st != MVD_OK) return fail(nullptr, st, "item %d: %s", i, c->err.c_str());
+    if (items[i].run->flags & (MVD_FLAG_TIMING | MVD_FLAG_GRAPH))
+      return fail(nullptr, MVD_ERR_ARG, "item %d: timing and graph flags are not batch item flags", i);
+    if (c->device != dev) return fail(nullptr, MVD_ERR_ARG, "item %d: all items must share one device", i);
+  }
+  DeviceGuard dg(dev);
+  if (!dg.ok()) return fail(nullptr, MVD_ERR_DEVICE, "cannot select device %d", dev);
+  mvd_batch *b = new (std::nothrow) mvd_batch;
+  if (!b) return fail(nullptr, MVD_ERR_ALLOC, "out of host memory");
+  b->device = dev;
+  for (int i = 0; i < n_items; ++i) {
+    mvd_batch::Item it;
+    it.ctx = items[i].ctx;
+    it.obs.assign(items[i].obs, items[i].obs + it.ctx->nv);
+    it.est = items[i].est;
+    it.run = *items[i].run;
+    if (it.run.view_weights) {
+      it.weights.assign(it.run.view_weights, it.run.view_weights + it.ctx->nv);
+      it.run.view_weights = it.weights.data();
+    }
+    b->items.push_back(std::move(it));
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (flags & MVD_BATCH_TUNE) {
+    for (auto &it : b->items) {
+      if (e != hipSuccess) break;
+      if (it.run.init == MVD_INIT_GIVEN) continue;   // tuning would overwrite the given estimate
+      e = autotune(it.ctx, it.obs.data(), it.est, &it.run, s, &it.tn);
+    }
+  }
+  // one graph, one branch per item: fork from the capture stream, join back
+  std::vector<hipStream_t> br(b->items.size(), nullptr);
+  std::vector<hipEvent_t> join(b->items.size(), nullptr);
+  hipEvent_t fork = nullptr;
+  for (size_t i = 0; i < br.size() && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    e = capture(
+        [&](hipStream_t cs) {
+          hipError_t ce = hipEventRecord(fork, cs);
+          for (size_t i = 0; i < b->items.size() && ce == hipSuccess; ++i) {
+            auto &it = b->items[i];
+            ce = hipStreamWaitEvent(br[i], fork, 0);
+            if (ce == hipSuccess) ce = enqueue_run(it.ctx, it.obs.data(), it.est, &it.run, br[i], it.tn);
+            if (ce == hipSuccess) ce = hipEventRecord(join[i], br[i]);
+            if (ce == hipSuccess) ce = hipStreamWaitEvent(cs, join[i], 0);
+          }
+          return ce;
+        },
+        &b->graph, &b->exec);
+  }
+  for (size_t i = 0; i < br.size(); ++i) {
+    if (br[i]) (void)hipStreamDestroy(br[i]);
+    if (join[i]) (void)hipEventDestroy(join[i]);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  if (e != hipSuccess) {
+    mvd_batch_destroy(b);
+    return fail(nullptr, MVD_ERR_LAUNCH, "batch setup failed: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return MVD_OK;
+}
+
+mvd_status mvd_batch_launch(mvd_batch *b, void *stream) {
+  if (!b || !b->exec) return fail(nullptr, MVD_ERR_ARG, "batch is NULL");
+  DeviceGuard dg(b->device);
+  hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(nullptr, MVD_ERR_LAUNCH, "graph launch failed: %s", hipGetErrorString(e));
+  return MVD_OK;
+}
+
+mvd_status mvd_batch_tuning(const mvd_batch *b, int item, int *out) {
+  if (!b || !out || item < 0 || item >= (int)b->items.size()) return fail(nullptr, MVD_ERR_ARG, "bad batch item");
+  const Tune &t = b->items[item].tn;
+  out[0] = t.fwd_occ;
+  out[1] = t.fwd_views;
+  out[2] = t.bwd_vin;
+  out[3] = t.zseg_scale;
+  return MVD_OK;
+}
+
+void mvd_batch_destroy(mvd_batch *b) {
+  if (!b) return;
+  DeviceGuard dg(b->device);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+}
+
+mvd_status mvd_batch_run(const mvd_item *items, int n_items, void *stream) {
+  mvd_batch *b = nullptr;
+  mvd_status st = mvd_batch_create(&b, items, n_items, 0, stream);
+  if (st != MVD_OK) return st;
+  st = mvd_batch_launch(b, stream);
+  DeviceGuard dg(b->device);
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && st == MVD_OK)
+    st = fail(nullptr, MVD_ERR_LAUNCH, "batch execution failed");
+  mvd_batch_destroy(b);
+  return st;
 }
 
 const char *mvd_last_error(const mvd_ctx *c) {
