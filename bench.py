@@ -28,23 +28,46 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def pass_work(spec, kind, Y, Z, X):
-    """Algorithmic bytes and flops of one forward / backward launch over all planes.
+def step_work(spec, kind, Y, Z, X, launches_per_iter):
+    """Algorithmic bytes and flops of one forward / backward launch.
 
-    forward (all V views from one ψ): read ψ, read φ_v, write r_v:
-        bytes = 4 + 8V per voxel;  flops = V · 2 · (kz + kx) (two 1D passes of FMAs)
-    backward: read r_v, read ψ, write ψ:  bytes = 4V + 8;  same flops.
+    Per voxel and view, a forward pass reads φ_v, writes r_v and (once per
+    launch) reads ψ; a backward pass reads r_v and (once per launch) reads and
+    writes ψ.  Each view's two 1D passes cost 2 · (kz + kx) flops (FMA = 2).
+    The library may split the V views of an iteration over several launches,
+    so the work of one iteration is divided by its launches.
     """
     V = spec.n_views
     vox = Y * Z * X
     k = spec.psf_k
-    if spec.update == "simultaneous":
-        b = (4 + 8 * V) if kind == "forward" else (4 * V + 8)
-        f = V * 2 * (k + k)
+    n = launches_per_iter
+    if kind == "forward":
+        b = 8 * V + 4 * n
     else:
-        b = 12 if kind == "forward" else 12
-        f = 2 * (k + k)
-    return vox * b, vox * f
+        b = 4 * V + 8 * n
+    f = V * 2 * (k + k)
+    return vox * b / n, vox * f / n
+
+
+def measured_traffic(name, kind):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (scaled by the factors a copy of known size
+    gives), or None when the kernel source changed since they were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"sep_passes_{name}_traffic.json")
+    src = os.path.join(ROOT, "paper_1503_07998_amd", "csrc", "k_sep_impl.hpp")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != h:
+        return None
+    for k, v in rec["kernels"].items():
+        if f"sep_{kind}_kernel" in k:
+            return v["traffic_bytes"]
+    return None
 
 
 def cpu_baseline(spec, vol, iters):
@@ -237,9 +260,10 @@ def main():
     for kind in ("forward", "backward"):
         n, ms = tim[kind]
         if n:
-            b, f = pass_work(spec, kind, Y, Z, X)
+            per_iter = n / (args.steps * spec.iters)
+            b, f = step_work(spec, kind, Y, Z, X, per_iter)
             avg = ms / n / 1e3
-            kinds[kind] = dict(launches=n, avg_ms=avg * 1e3, bytes=b, flops=f,
+            kinds[kind] = dict(launches=n, launches_per_iteration=per_iter, avg_ms=avg * 1e3, bytes=b, flops=f,
                                gbs=b / avg / 1e9, tflops=f / avg / 1e12)
     dom = max(kinds, key=lambda k: kinds[k]["avg_ms"] * kinds[k]["launches"])
     kd = kinds[dom]
@@ -252,7 +276,7 @@ def main():
         roof = {"bound": "hbm", "achieved": kd["bytes"] / (kd["avg_ms"] / 1e3) / 1e9,
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(spec.name, dom)
     roof["kernel"] = f"{dom} pass (sep_{dom}_kernel, K={spec.psf_k})"
     roof["hbm_frac_algorithmic"] = kd["bytes"] / (kd["avg_ms"] / 1e3) / HBM_PEAK
 
