@@ -5,6 +5,9 @@ uint16 observations, ψ^0, then every RL iteration) with the inputs already
 resident in device memory.  Prints one JSON line (see the keys below).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config vol512]
+
+--config mix times the batched form against plain per-volume calls;
+--config vol1024x4 times the streamed form (host stacks, batches of planes).
 """
 from __future__ import annotations
 
@@ -28,17 +31,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def step_work(spec, kind, Y, Z, X, launches_per_iter):
-    """Algorithmic bytes and flops of one forward / backward launch.
+def step_work(spec, kind, vox, launches_per_iter):
+    """Algorithmic bytes and flops of one forward / backward launch over
+    ``vox`` voxels (a whole volume, or one batch of planes).
 
     Per voxel and view, a forward pass reads φ_v, writes r_v and (once per
     launch) reads ψ; a backward pass reads r_v and (once per launch) reads and
     writes ψ.  Each view's two 1D passes cost 2 · (kz + kx) flops (FMA = 2).
     The library may split the V views of an iteration over several launches,
-    so the work of one iteration is divided by its launches.
+    so the work of one iteration on those voxels is divided by its launches.
     """
     V = spec.n_views
-    vox = Y * Z * X
     k = spec.psf_k
     n = launches_per_iter
     if kind == "forward":
@@ -68,6 +71,39 @@ def measured_traffic(name, kind):
         if f"sep_{kind}_kernel" in k:
             return v["traffic_bytes"]
     return None
+
+
+def roofline(spec, kinds):
+    """Roofline entry of the kernel with the largest share of the step."""
+    dom = max(kinds, key=lambda k: kinds[k]["avg_ms"] * kinds[k]["launches"])
+    kd = kinds[dom]
+    t_hbm = kd["bytes"] / HBM_PEAK
+    t_alu = kd["flops"] / ALU_PEAK
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": kd["flops"] / (kd["avg_ms"] / 1e3) / 1e12,
+                "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": kd["bytes"] / (kd["avg_ms"] / 1e3) / 1e9,
+                "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(spec.name, dom)
+    roof["kernel"] = f"{dom} pass (sep_{dom}_kernel, K={spec.psf_k})"
+    roof["hbm_frac_algorithmic"] = kd["bytes"] / (kd["avg_ms"] / 1e3) / HBM_PEAK
+    return roof
+
+
+def launch_kinds(spec, tim, steps, vox, batches=1):
+    """Per-kind launch statistics of ``steps`` timed runs (HIP events)."""
+    kinds = {}
+    for kind in ("forward", "backward"):
+        n, ms = tim[kind]
+        if n:
+            per_iter = n / (steps * spec.iters * batches)
+            b, f = step_work(spec, kind, vox / batches, per_iter)
+            avg = ms / n / 1e3
+            kinds[kind] = dict(launches=n, launches_per_iteration=per_iter, avg_ms=avg * 1e3, bytes=b, flops=f,
+                               gbs=b / avg / 1e9, tflops=f / avg / 1e12)
+    return kinds
 
 
 def cpu_baseline(spec, vol, iters):
@@ -170,6 +206,144 @@ def bench_mix(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_stream(args, spec):
+    """Observations in page-locked host memory, streamed to the device in
+    batches of planes that overlap with the iterations of other batches.
+    One step = the whole deconvolution, host stacks to device estimate."""
+    import numpy as np
+
+    from synthetic import make_volume
+
+    Y, Z, X, V = spec.n_planes, spec.n_z, spec.n_x, spec.n_views
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    log(f"generating {spec.name}: {V} views, {Y} planes of {Z}x{X}, K={spec.psf_k} ({workers} workers)")
+    t0 = time.perf_counter()
+    vol = make_volume(spec, truth=False, workers=workers)
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    import torch
+
+    from paper_1503_07998_amd import api
+
+    host = []
+    for v in range(V):
+        t = torch.empty((Z, Y, X), dtype=torch.uint16, pin_memory=True)
+        t.numpy()[...] = vol["stacks"][v]
+        host.append(t)
+    y_cpu = Y // 2
+    cpu_sample = [np.ascontiguousarray(s[: Z // 2, y_cpu:y_cpu + 1, :]) for s in vol["stacks"]]
+    del vol["stacks"]
+    dev = torch.device("cuda:0")
+    d = api.Deconvolver(V, Z, X, 0)
+    for v, p in enumerate(vol["psfs"]):
+        d.set_psf(v, p)
+    est = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
+    batch = args.batch
+    nb = (Y + batch - 1) // batch
+
+    def make(timing, ws_bytes, ptr):
+        r = api.make_run(Y, spec.iters, update=spec.update, boundary=spec.boundary, obs_dtype=spec.obs_dtype,
+                         timing=timing)
+        r.workspace, r.workspace_bytes = ptr, ws_bytes
+        return r
+
+    nbytes = api.mvd_stream_workspace_bytes(d.ctx, make(False, 0, None), batch, False)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    wptr = (ws.data_ptr() + 255) // 256 * 256
+    runs = {t: make(t, nbytes, wptr) for t in (False, True)}
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    log(f"streamed: batches of {batch} planes, warmup {args.warmup}")
+    for _ in range(args.warmup):
+        api.mvd_deconvolve_stream(d.ctx, host, est, runs[False], batch, stream)
+    api.mvd_get_timing(d.ctx, reset=True)
+    log(f"streamed: timing {args.steps} steps")
+    ms_step = timed(lambda: api.mvd_deconvolve_stream(d.ctx, host, est, runs[True], batch, stream), args.steps)
+    tim = api.mvd_get_timing(d.ctx, reset=True)
+    ms_plain = timed(lambda: api.mvd_deconvolve_stream(d.ctx, host, est, runs[False], batch, stream), args.steps)
+    vox_it = spec.voxels * spec.iters
+    kinds = launch_kinds(spec, tim, args.steps, spec.voxels, nb)
+    it_ms = sum(kinds[k]["avg_ms"] * kinds[k]["launches"] for k in kinds) / args.steps
+    del ws
+
+    # the same run with the estimate copied back to page-locked host memory
+    log("streamed with host estimate")
+    est_h = torch.empty((Y, Z, X), dtype=torch.float32, pin_memory=True)
+    nbh = api.mvd_stream_workspace_bytes(d.ctx, runs[False], batch, True)
+    wsh = torch.empty(nbh + 256, dtype=torch.uint8, device=dev)
+    rh = make(False, nbh, (wsh.data_ptr() + 255) // 256 * 256)
+    api.mvd_deconvolve_stream(d.ctx, host, est_h, rh, batch, stream)
+    ms_host_out = timed(lambda: api.mvd_deconvolve_stream(d.ctx, host, est_h, rh, batch, stream), args.steps)
+    same = bool(torch.equal(est_h, est.cpu()))
+    del wsh, est_h
+
+    # copies alone, and the device-resident run, for context
+    log("host-to-device copy alone")
+    obs = [torch.empty((Z, Y, X), dtype=torch.uint16, device=dev) for _ in range(V)]
+
+    def copy_in():
+        for o, h in zip(obs, host):
+            o.copy_(h, non_blocking=True)
+
+    copy_in()
+    ms_copy = timed(copy_in, 2)
+    log("device-resident run")
+    rr = api.make_run(Y, spec.iters, update=spec.update, boundary=spec.boundary, obs_dtype=spec.obs_dtype)
+    nr = api.mvd_workspace_bytes(d.ctx, rr)
+    wsr = torch.empty(nr + 256, dtype=torch.uint8, device=dev)
+    rr.workspace, rr.workspace_bytes = (wsr.data_ptr() + 255) // 256 * 256, nr
+    api.mvd_deconvolve_planes(d.ctx, obs, est, rr, stream)
+    ms_res = timed(lambda: api.mvd_deconvolve_planes(d.ctx, obs, est, rr, stream), max(1, args.steps // 2))
+    del wsr, obs
+
+    out = {
+        "metric": "voxel-iterations/s",
+        "value": vox_it / (ms_step / 1e3),
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": (f"{spec.name}: {V} views (0/90/180/270 deg), {Y} planes of {Z}x{X}, "
+                         f"{spec.psf_k}x{spec.psf_k} Gaussian PSFs (sx={spec.psf_sigma[0]}, sz={spec.psf_sigma[1]}), "
+                         f"uint16 Poisson observations of blob nuclei in page-locked host memory streamed in "
+                         f"batches of {batch} planes, {spec.iters} iterations, {spec.update}, "
+                         f"{spec.boundary} boundary, estimate on the device"),
+            "voxels": spec.voxels, "iterations": spec.iters, "views": V, "psf": spec.psf_k,
+            "update": spec.update, "batch_planes": batch, "parallelism": "single GPU",
+        },
+        "ms_per_step_without_events": ms_plain,
+        "iterations_only_value": vox_it / (it_ms / 1e3),
+        "host_estimate_value": vox_it / (ms_host_out / 1e3),
+        "host_estimate_equal": same,
+        "h2d_copy_ms": ms_copy,
+        "h2d_copy_gbs": V * spec.voxels * 2 / (ms_copy / 1e3) / 1e9,
+        "device_resident_value": vox_it / (ms_res / 1e3),
+        "device_resident_ms": ms_res,
+        "kernels": kinds,
+        "roofline": roofline(spec, kinds),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        t0 = time.perf_counter()
+        import oracle
+
+        oracle.deconvolve(cpu_sample, [p.astype(np.float64) for p in vol["psfs"]], 1, update=spec.update)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": (Z // 2) * X / dt, "unit": "voxel-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"rows 0..{Z // 2 - 1} of plane {y_cpu}, 1 of {spec.iters} iterations, {V} views, "
+                      f"direct FP64 convolution, {dt:.1f} s"}
+    d.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +352,7 @@ def main():
     ap.add_argument("--config", default="vol512")
     ap.add_argument("--update", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=64, help="planes per streamed batch (vol1024x4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -193,6 +368,9 @@ def main():
     spec = CONFIGS[args.config]
     if args.update:
         spec.update = args.update
+    if spec.name == "vol1024x4":
+        bench_stream(args, spec)
+        return
     log(f"generating {spec.name}: {spec.n_views} views, {spec.n_planes} planes of {spec.n_z}x{spec.n_x}")
     t0 = time.perf_counter()
     vol = make_volume(spec, truth=False)
@@ -256,29 +434,8 @@ def main():
     torch.cuda.synchronize()
     ms_plain = (time.perf_counter() - t1) * 1e3 / args.steps
 
-    kinds = {}
-    for kind in ("forward", "backward"):
-        n, ms = tim[kind]
-        if n:
-            per_iter = n / (args.steps * spec.iters)
-            b, f = step_work(spec, kind, Y, Z, X, per_iter)
-            avg = ms / n / 1e3
-            kinds[kind] = dict(launches=n, launches_per_iteration=per_iter, avg_ms=avg * 1e3, bytes=b, flops=f,
-                               gbs=b / avg / 1e9, tflops=f / avg / 1e12)
-    dom = max(kinds, key=lambda k: kinds[k]["avg_ms"] * kinds[k]["launches"])
-    kd = kinds[dom]
-    t_hbm = kd["bytes"] / HBM_PEAK
-    t_alu = kd["flops"] / ALU_PEAK
-    if t_alu >= t_hbm:
-        roof = {"bound": "alu", "achieved": kd["flops"] / (kd["avg_ms"] / 1e3) / 1e12,
-                "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": kd["bytes"] / (kd["avg_ms"] / 1e3) / 1e9,
-                "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(spec.name, dom)
-    roof["kernel"] = f"{dom} pass (sep_{dom}_kernel, K={spec.psf_k})"
-    roof["hbm_frac_algorithmic"] = kd["bytes"] / (kd["avg_ms"] / 1e3) / HBM_PEAK
+    kinds = launch_kinds(spec, tim, args.steps, Y * Z * X)
+    roof = roofline(spec, kinds)
 
     it_ms = sum(kinds[k]["avg_ms"] * kinds[k]["launches"] for k in kinds) / args.steps
     out = {

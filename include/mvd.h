@@ -141,8 +141,9 @@ void mvd_destroy(mvd_ctx *ctx);
 
 /* Set view `view`'s PSF P_v (host float32 [kz][kx], copied) and its
  * back-projector mode (mvd_back).  back_taps: host float32 [kz][kx] for
- * MVD_BACK_EXPLICIT, else ignored (may be NULL).  Compound back-projectors are
- * (re)built when a run starts, once every view's PSF is set.  Rank-one taps
+ * MVD_BACK_EXPLICIT, else ignored (may be NULL).  Back-projectors, compound
+ * ones included, are (re)built by the call that completes the set of PSFs and
+ * by every later call.  Rank-one taps
  * (to 1e-6 relative) are run as two 1D passes; others as K×K passes.
  * Errors: MVD_ERR_ARG (bad view, sides even or outside [1, MVD_MAX_K], taps
  * negative/non-finite/all zero, missing explicit taps), MVD_ERR_ALLOC. */
@@ -180,6 +181,45 @@ mvd_status mvd_reslice(mvd_ctx *ctx, const void *stack, int dtype, int n_planes,
  * MVD_ERR_DEVICE, MVD_ERR_LAUNCH. */
 mvd_status mvd_deconvolve_planes(mvd_ctx *ctx, const void *const *obs, float *est,
                                  const mvd_run *run, void *stream);
+
+/* ---- streamed form ---------------------------------------------------------
+ * The whole run of mvd_deconvolve_planes on camera-ordered stacks that stay in
+ * host memory: planes are independent, so the volume is processed in batches
+ * of `batch_planes` consecutive planes, each copied to the device, resliced,
+ * deconvolved for all T iterations and (for a host estimate) copied back,
+ * with the copies of one batch overlapping the iterations of another
+ * (Supplementary Note 2 §3, which interleaves per-plane transfers and RL steps
+ * on several streams; here copies in, compute and copies out run on three
+ * streams, two batches in flight).  Results equal those of
+ * mvd_deconvolve_planes on the whole volume bitwise.
+ *
+ * mvd_stream_workspace_bytes: device workspace for mvd_deconvolve_stream
+ * with this run, batch size and estimate placement (est_on_host ≠ 0 when est
+ * will be host memory): two staging slots of V observation batches (+ one
+ * estimate batch for a host estimate) and one batch run's workspace.
+ * Errors: MVD_ERR_ARG. */
+mvd_status mvd_stream_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, int batch_planes,
+                                      int est_on_host, size_t *bytes);
+
+/* Streamed run.
+ *   obs: host array of V pointers to camera-ordered stacks [Z][Y][X] of
+ *        run->obs_dtype (Y = run->n_planes), in page-locked host memory
+ *        (hipHostMalloc) or device memory.  Read only.  run->obs_layout must
+ *        be MVD_STACK_ZYX.
+ *   est: float32 [Y][Z][X], device or page-locked host memory; ψ^0 on entry
+ *        for MVD_INIT_GIVEN, ψ^T on exit.
+ *   run: as for mvd_deconvolve_planes except checkpoints (must be NULL) and
+ *        MVD_FLAG_GRAPH (not allowed); run->workspace of
+ *        mvd_stream_workspace_bytes() bytes.
+ *   batch_planes: planes per batch, ≥ 1 (the last batch may be shorter).
+ * Compute runs on `stream`; the copies run on two streams the context owns,
+ * ordered after the work already on `stream`, and `stream` waits for them
+ * before it completes, so synchronising `stream` covers the whole call.
+ * Pageable host memory is rejected (MVD_ERR_ARG).
+ * Errors: MVD_ERR_ARG, MVD_ERR_STATE, MVD_ERR_WORKSPACE, MVD_ERR_DEVICE,
+ * MVD_ERR_LAUNCH, MVD_ERR_ALLOC (streams or events). */
+mvd_status mvd_deconvolve_stream(mvd_ctx *ctx, const void *const *obs, float *est,
+                                 const mvd_run *run, int batch_planes, void *stream);
 
 /* Launch timings of runs made with MVD_FLAG_TIMING since the last reset:
  * summed HIP-event durations (ms) and launch counts per kind.  Kinds: 0 forward

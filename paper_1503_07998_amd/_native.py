@@ -98,6 +98,8 @@ SIGNATURES = {
     "mvd_batch_tuning": (c_int, [c_void_p, c_int, POINTER(c_int)]),
     "mvd_batch_destroy": (None, [c_void_p]),
     "mvd_batch_run": (c_int, [POINTER(MvdItem), c_int, c_void_p]),
+    "mvd_stream_workspace_bytes": (c_int, [c_void_p, POINTER(MvdRun), c_int, c_int, POINTER(c_size_t)]),
+    "mvd_deconvolve_stream": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), c_int, c_void_p]),
     "mvd_last_error": (ctypes.c_char_p, [c_void_p]),
 }
 

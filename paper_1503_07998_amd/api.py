@@ -19,6 +19,7 @@ __all__ = [
     "mvd_get_timing", "mvd_last_error", "make_run", "Deconvolver", "deconvolve",
     "mvd_backward_workspace_bytes", "mvd_backward", "mvd_batch_create", "mvd_batch_launch",
     "mvd_batch_tuning", "mvd_batch_destroy", "mvd_batch_run", "Batch",
+    "mvd_stream_workspace_bytes", "mvd_deconvolve_stream",
 ]
 
 
@@ -148,6 +149,31 @@ def mvd_get_timing(ctx, reset: bool = True) -> dict:
 def mvd_deconvolve_planes(ctx, obs, est, run, stream=None) -> None:
     ptrs = (c_void_p * len(obs))(*[_dev_ptr(o).value for o in obs])
     N.check(N.lib().mvd_deconvolve_planes(ctx, ptrs, _dev_ptr(est), ctypes.byref(run),
+                                          _stream_handle(stream)), ctx)
+
+
+def _any_ptr(t):
+    """Pointer of a contiguous device tensor or page-locked host tensor."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_contiguous():
+        raise TypeError("expected a contiguous tensor")
+    if not t.is_cuda and not t.is_pinned():
+        raise ValueError("host tensors must be page-locked (pin_memory=True)")
+    return c_void_p(t.data_ptr())
+
+
+def mvd_stream_workspace_bytes(ctx, run, batch_planes: int, est_on_host: bool) -> int:
+    n = c_size_t()
+    N.check(N.lib().mvd_stream_workspace_bytes(ctx, ctypes.byref(run), int(batch_planes), int(bool(est_on_host)),
+                                               ctypes.byref(n)), ctx)
+    return n.value
+
+
+def mvd_deconvolve_stream(ctx, obs, est, run, batch_planes: int, stream=None) -> None:
+    """Streamed run: ``obs`` are camera-ordered stacks in page-locked host (or
+    device) tensors, ``est`` a device or page-locked host tensor."""
+    ptrs = (c_void_p * len(obs))(*[_any_ptr(o).value for o in obs])
+    N.check(N.lib().mvd_deconvolve_stream(ctx, ptrs, _any_ptr(est), ctypes.byref(run), int(batch_planes),
                                           _stream_handle(stream)), ctx)
 
 

@@ -135,6 +135,9 @@ struct mvd_ctx {
   };
   std::vector<Graph> graphs;
   uint64_t psf_generation = 0;   // bumped by every mvd_set_psf (captured taps change)
+  // streamed runs: copy-in and copy-out streams and their events
+  hipStream_t h2d = nullptr, d2h = nullptr;
+  hipEvent_t sev[7] = {};        // start, in[2], done[2], out[2]
 };
 
 namespace {
@@ -807,6 +810,124 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
   return e;
 }
 
+// ---- streamed runs --------------------------------------------------------------
+// Workspace of a streamed run: `slots` staging slots, each holding V observation
+// batches [Z][ys][X] (and, for a host estimate, one float32 batch [ys][Z][X]),
+// then the workspace of one batch run.
+struct StreamLayout {
+  int ys = 0, slots = 0;
+  size_t obs_bytes = 0, est_bytes = 0, slot = 0, run_off = 0, run_bytes = 0, total = 0;
+};
+
+StreamLayout stream_layout_of(const mvd_ctx *c, const mvd_run *r, int batch, bool est_host) {
+  StreamLayout S;
+  S.ys = std::min(batch, r->n_planes);
+  const size_t s = r->obs_dtype == MVD_U16 ? 2 : 4;
+  const size_t vox = (size_t)S.ys * c->Z * c->X;
+  S.obs_bytes = align_up(vox * s);
+  S.est_bytes = est_host ? align_up(vox * sizeof(float)) : 0;
+  S.slot = (size_t)c->nv * S.obs_bytes + S.est_bytes;
+  S.slots = (r->n_planes + S.ys - 1) / S.ys > 1 ? 2 : 1;
+  S.run_off = (size_t)S.slots * S.slot;
+  mvd_run sub = *r;
+  sub.n_planes = S.ys;
+  S.run_bytes = align_up(layout_of(c, &sub).total);
+  S.total = S.run_off + S.run_bytes;
+  return S;
+}
+
+mvd_status check_stream_run(mvd_ctx *c, const mvd_run *r, int batch) {
+  mvd_status st = check_run(c, r);
+  if (st != MVD_OK) return st;
+  if (batch < 1) return fail(c, MVD_ERR_ARG, "batch_planes must be >= 1");
+  if (r->obs_layout != MVD_STACK_ZYX) return fail(c, MVD_ERR_ARG, "streamed runs take camera-ordered stacks");
+  if (r->checkpoints) return fail(c, MVD_ERR_ARG, "streamed runs keep no checkpoints");
+  if (r->flags & MVD_FLAG_GRAPH) return fail(c, MVD_ERR_ARG, "MVD_FLAG_GRAPH is not available for streamed runs");
+  return MVD_OK;
+}
+
+// 0 pageable/unknown, 1 page-locked host, 2 device (or managed).
+int memory_kind(const void *p) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  if (a.type == hipMemoryTypeHost) return 1;
+  if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) return 2;
+  return 0;
+}
+
+hipError_t stream_resources(mvd_ctx *c) {
+  hipError_t e = hipSuccess;
+  if (!c->h2d) e = hipStreamCreateWithFlags(&c->h2d, hipStreamNonBlocking);
+  if (e == hipSuccess && !c->d2h) e = hipStreamCreateWithFlags(&c->d2h, hipStreamNonBlocking);
+  for (auto &ev : c->sev)
+    if (e == hipSuccess && !ev) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  return e;
+}
+
+// Batches b = 0, 1, … of ys planes alternate between two staging slots.
+//   copy-in (h2d):  wait until slot's previous batch is computed (and copied
+//                   out), copy V observation batches (and ψ^0), record in[k]
+//   compute (s):    wait in[k] (and out[k] for a host estimate), run, record done[k]
+//   copy-out (d2h): wait done[k], copy ψ^T of the batch to the host, record out[k]
+hipError_t enqueue_stream(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, int batch,
+                          bool est_host, hipStream_t s) {
+  const StreamLayout S = stream_layout_of(c, r, batch, est_host);
+  const int Y = r->n_planes, Z = c->Z, X = c->X;
+  const size_t es = r->obs_dtype == MVD_U16 ? 2 : 4;
+  const size_t plane = (size_t)Z * X;
+  char *ws = static_cast<char *>(r->workspace);
+  hipEvent_t start = c->sev[0], *in = c->sev + 1, *done = c->sev + 3, *out = c->sev + 5;
+  hipError_t e = hipEventRecord(start, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->h2d, start, 0);
+  if (e == hipSuccess && est_host) e = hipStreamWaitEvent(c->d2h, start, 0);
+  const int nb = (Y + S.ys - 1) / S.ys;
+  std::vector<const void *> slab(c->nv);
+  for (int b = 0; b < nb && e == hipSuccess; ++b) {
+    const int k = b % S.slots, y0 = b * S.ys, ny = std::min(S.ys, Y - y0);
+    char *slot = ws + (size_t)k * S.slot;
+    float *est_b = est_host ? reinterpret_cast<float *>(slot + (size_t)c->nv * S.obs_bytes) : est + (size_t)y0 * plane;
+    if (b >= S.slots) {
+      e = hipStreamWaitEvent(c->h2d, done[k], 0);
+      if (e == hipSuccess && est_host) e = hipStreamWaitEvent(c->h2d, out[k], 0);
+    }
+    for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
+      char *dst = slot + (size_t)v * S.obs_bytes;
+      const char *src = static_cast<const char *>(obs[v]) + (size_t)y0 * X * es;
+      // rows y0..y0+ny of every slice z: a 2D copy of Z rows of ny·X elements
+      e = hipMemcpy2DAsync(dst, (size_t)ny * X * es, src, (size_t)Y * X * es, (size_t)ny * X * es, Z,
+                           hipMemcpyDefault, c->h2d);
+      slab[v] = dst;
+    }
+    if (e == hipSuccess && est_host && r->init == MVD_INIT_GIVEN)
+      e = hipMemcpyAsync(est_b, est + (size_t)y0 * plane, (size_t)ny * plane * sizeof(float), hipMemcpyDefault,
+                         c->h2d);
+    if (e == hipSuccess) e = hipEventRecord(in[k], c->h2d);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, in[k], 0);
+    if (e == hipSuccess && est_host && b >= S.slots) e = hipStreamWaitEvent(s, out[k], 0);
+    if (e == hipSuccess) {
+      mvd_run sub = *r;
+      sub.n_planes = ny;
+      sub.workspace = ws + S.run_off;
+      sub.workspace_bytes = S.run_bytes;
+      e = enqueue_run(c, slab.data(), est_b, &sub, s, tune());
+    }
+    if (e == hipSuccess) e = hipEventRecord(done[k], s);
+    if (e == hipSuccess && est_host) {
+      e = hipStreamWaitEvent(c->d2h, done[k], 0);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(est + (size_t)y0 * plane, est_b, (size_t)ny * plane * sizeof(float), hipMemcpyDefault,
+                           c->d2h);
+      if (e == hipSuccess) e = hipEventRecord(out[k], c->d2h);
+    }
+  }
+  // `s` completes only after the last copies
+  for (int k = 0; k < S.slots && e == hipSuccess && est_host && nb > 0; ++k) e = hipStreamWaitEvent(s, out[k], 0);
+  return e;
+}
+
 // ---- graph capture ----------------------------------------------------------
 // A captured run is reused when every pointer and parameter is the same.
 std::vector<uint64_t> run_key(const mvd_ctx *c, const void *const *obs, const float *est, const mvd_run *r) {
@@ -1034,6 +1155,10 @@ void mvd_destroy(mvd_ctx *ctx) {
       (void)hipGraphDestroy(g.graph);
     }
     if (ctx->d_taps) (void)hipFree(ctx->d_taps);
+    for (auto e : ctx->sev)
+      if (e) (void)hipEventDestroy(e);
+    if (ctx->h2d) (void)hipStreamDestroy(ctx->h2d);
+    if (ctx->d2h) (void)hipStreamDestroy(ctx->d2h);
   }
   delete ctx;
 }
@@ -1161,6 +1286,50 @@ mvd_status mvd_deconvolve_planes(mvd_ctx *c, const void *const *obs, float *est,
     e = enqueue_run(c, obs, est, r, (hipStream_t)stream, tune());
   }
   if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "launch failed: %s", hipGetErrorString(e));
+  return MVD_OK;
+}
+
+mvd_status mvd_stream_workspace_bytes(const mvd_ctx *cc, const mvd_run *r, int batch_planes, int est_on_host,
+                                      size_t *bytes) {
+  mvd_ctx *c = const_cast<mvd_ctx *>(cc);
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  if (!bytes) return fail(c, MVD_ERR_ARG, "bytes is NULL");
+  mvd_status st = check_stream_run(c, r, batch_planes);
+  if (st != MVD_OK) return st;
+  *bytes = stream_layout_of(c, r, batch_planes, est_on_host != 0).total;
+  return MVD_OK;
+}
+
+mvd_status mvd_deconvolve_stream(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r,
+                                 int batch_planes, void *stream) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  mvd_status st = check_stream_run(c, r, batch_planes);
+  if (st != MVD_OK) return st;
+  if (!obs) return fail(c, MVD_ERR_ARG, "obs is NULL");
+  for (int v = 0; v < c->nv; ++v)
+    if (!obs[v]) return fail(c, MVD_ERR_ARG, "obs[%d] is NULL", v);
+  if (!est) return fail(c, MVD_ERR_ARG, "est is NULL");
+  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
+  if (r->workspace && ((uintptr_t)r->workspace % kAlign))
+    return fail(c, MVD_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+  if (c->device == MVD_DEVICE_NONE) return fail(c, MVD_ERR_DEVICE, "host-only context");
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
+  for (int v = 0; v < c->nv; ++v)
+    if (memory_kind(obs[v]) == 0)
+      return fail(c, MVD_ERR_ARG, "obs[%d] is pageable host memory: use page-locked or device memory", v);
+  const int ek = memory_kind(est);
+  if (ek == 0) return fail(c, MVD_ERR_ARG, "est is pageable host memory: use page-locked or device memory");
+  const bool est_host = ek == 1;
+  const StreamLayout S = stream_layout_of(c, r, batch_planes, est_host);
+  if (!r->workspace || r->workspace_bytes < S.total)
+    return fail(c, MVD_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", S.total,
+                r->workspace ? r->workspace_bytes : (size_t)0);
+  if (stream_resources(c) != hipSuccess) return fail(c, MVD_ERR_ALLOC, "cannot create copy streams or events");
+  hipError_t e = enqueue_stream(c, obs, est, r, batch_planes, est_host, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "streamed run failed: %s", hipGetErrorString(e));
   return MVD_OK;
 }
 

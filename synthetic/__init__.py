@@ -275,3 +275,20 @@ def make_volume(spec: VolumeSpec, seed: int | None = None, noise: bool = True,
         stacks.append(_render_volume(shape, blobs, spec.background, sig, noise, spec.obs_dtype,
                                      (seed, v + 1), workers))
     return dict(truth=tr, stacks=stacks, psfs=spec.psfs(), blobs=blobs)
+
+
+def render_planes(spec: VolumeSpec, planes, seed: int | None = None, noise: bool = True):
+    """Observations of only the listed planes of ``spec``'s full volume (same
+    blob draw as ``make_volume``), for checks at full size that need a few real
+    planes only.  Noise is drawn per plane, so the values differ from the
+    chunked ``make_volume`` draw.  Returns ``[V × [Z][len(planes)][X]]``."""
+    seed = spec.seed if seed is None else seed
+    shape = (spec.n_z, spec.n_planes, spec.n_x)
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0]))
+    blobs = draw_blobs(rng, shape, spec.n_blobs)
+    out = []
+    for v, sig in enumerate(spec.view_sigmas()):
+        parts = [_render_chunk((shape, blobs, int(y), int(y) + 1, spec.background, sig, noise, spec.obs_dtype,
+                                (seed, v + 1, 1 << 20, int(y)))) for y in planes]
+        out.append(np.concatenate(parts, axis=1))
+    return out

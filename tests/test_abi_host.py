@@ -257,3 +257,57 @@ def test_backward_validation_before_device():
         assert call(r) == N.MVD_ERR_UNSUPPORTED
     finally:
         api.mvd_destroy(ctx)
+
+
+def test_stream_workspace_formula():
+    """Two staging slots of V observation batches (+ an estimate batch for a
+    host estimate) and the workspace of one batch run."""
+    ctx = api.mvd_create(3, 10, 12, N.MVD_DEVICE_NONE)
+    try:
+        for v in range(3):
+            api.mvd_set_psf(ctx, v, np.ones((3, 3)))
+
+        def al(n):
+            return (n + 255) // 256 * 256
+
+        vox = 4 * 10 * 12
+        r = api.make_run(11, 2, update="sequential", obs_dtype="u16")
+        run_ws = api.mvd_workspace_bytes(ctx, api.make_run(4, 2, update="sequential", obs_dtype="u16"))
+        assert api.mvd_stream_workspace_bytes(ctx, r, 4, False) == 2 * 3 * al(vox * 2) + run_ws
+        assert api.mvd_stream_workspace_bytes(ctx, r, 4, True) == 2 * (3 * al(vox * 2) + al(vox * 4)) + run_ws
+        # one batch: one slot, batch clipped to the volume
+        r = api.make_run(3, 2, obs_dtype="f32")
+        one = api.mvd_workspace_bytes(ctx, api.make_run(3, 2, obs_dtype="f32"))
+        assert api.mvd_stream_workspace_bytes(ctx, r, 64, False) == 3 * al(3 * 120 * 4) + one
+    finally:
+        api.mvd_destroy(ctx)
+
+
+def test_stream_validation_before_device():
+    ctx = api.mvd_create(2, 8, 8, N.MVD_DEVICE_NONE)
+    lib = N.lib()
+    dummy = (ctypes.c_void_p * 2)(16, 32)
+    est = ctypes.c_void_p(48)
+
+    def call(run, batch=2):
+        return lib.mvd_deconvolve_stream(ctx, dummy, est, ctypes.byref(run), batch, None)
+
+    try:
+        r = api.make_run(4, 2)
+        assert call(r) == N.MVD_ERR_STATE                      # PSFs not set
+        for v in range(2):
+            api.mvd_set_psf(ctx, v, np.ones((3, 3)) / 9)
+        assert call(r, 0) == N.MVD_ERR_ARG                     # empty batch
+        assert call(api.make_run(4, 2, layout="planes_yzx")) == N.MVD_ERR_ARG
+        assert call(api.make_run(4, 2, checkpoints=64)) == N.MVD_ERR_ARG
+        assert call(api.make_run(4, 2, graph=True)) == N.MVD_ERR_ARG
+        r = api.make_run(4, 2, workspace=256 + 8, workspace_bytes=1 << 20)
+        assert call(r) == N.MVD_ERR_ARG                        # misaligned workspace
+        r = api.make_run(4, 2, workspace=256, workspace_bytes=1 << 20)
+        assert call(r) == N.MVD_ERR_DEVICE                     # host-only context
+        assert lib.mvd_deconvolve_stream(ctx, None, est, ctypes.byref(r), 2, None) == N.MVD_ERR_ARG
+        assert lib.mvd_deconvolve_stream(ctx, dummy, None, ctypes.byref(r), 2, None) == N.MVD_ERR_ARG
+        n = ctypes.c_size_t()
+        assert lib.mvd_stream_workspace_bytes(ctx, ctypes.byref(r), 0, 0, ctypes.byref(n)) == N.MVD_ERR_ARG
+    finally:
+        api.mvd_destroy(ctx)
