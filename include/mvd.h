@@ -159,8 +159,11 @@ mvd_status mvd_get_back_taps(mvd_ctx *ctx, int view, float *out);
  * K×K (0) passes.  Either pointer may be NULL. */
 mvd_status mvd_psf_info(mvd_ctx *ctx, int view, int *separable_psf, int *separable_back);
 
-/* Device workspace needed by mvd_deconvolve_planes() for `run`, in bytes
- * (0 is possible).  Errors: MVD_ERR_ARG. */
+/* Device workspace needed by mvd_deconvolve_planes() for `run`, in bytes:
+ * V float32 plane sets for the observations, resliced/converted and clamped
+ * at 0 (whatever their layout and type, so the passes read one form), plus
+ * the ratio planes (V sets for MVD_UPDATE_SIMULTANEOUS, one for sequential;
+ * none when n_iters = 0).  Errors: MVD_ERR_ARG. */
 mvd_status mvd_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, size_t *bytes);
 
 /* Reslice one camera-ordered stack (device [Z][Y][X], u16 or f32) into device
@@ -174,7 +177,7 @@ mvd_status mvd_reslice(mvd_ctx *ctx, const void *stack, int dtype, int n_planes,
  *   obs: host array of V device pointers, one per view, in run->obs_layout
  *        and run->obs_dtype (Y = run->n_planes).  Read only.
  *   est: device float32 [Y][Z][X]; ψ^0 on entry for MVD_INIT_GIVEN, ψ^T on exit.
- * Steps: reslice/convert the observations into the workspace when needed,
+ * Steps: reslice/convert the observations into the workspace,
  * ψ^0, then T iterations (2 passes per iteration for SIMULTANEOUS, 2V for
  * SEQUENTIAL).  ψ stays ≥ 0 for non-negative data.
  * Errors: MVD_ERR_ARG, MVD_ERR_STATE (PSF missing), MVD_ERR_WORKSPACE,
@@ -295,8 +298,9 @@ mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items,
 /* Launch the captured batch on `stream` (asynchronous). */
 mvd_status mvd_batch_launch(mvd_batch *b, void *stream);
 
-/* Launch shapes chosen for item `item`: out[4] = forward occupancy, forward
- * views per launch, backward inputs per launch, segment scale (0 = default). */
+/* Launch shapes chosen for item `item`: out[5] = forward occupancy, forward
+ * views per launch, backward inputs per launch, segment scale, columns per
+ * thread (0 = default in every field). */
 mvd_status mvd_batch_tuning(const mvd_batch *b, int item, int *out);
 
 /* Release a batch (the caller has synchronised its launches). */

@@ -230,9 +230,9 @@ def mvd_batch_launch(b, stream=None) -> None:
 
 
 def mvd_batch_tuning(b, item: int):
-    out = (c_int * 4)()
+    out = (c_int * 5)()
     N.check(N.lib().mvd_batch_tuning(b, int(item), out))
-    return dict(fwd_occ=out[0], fwd_views=out[1], bwd_vin=out[2], zseg_scale=out[3])
+    return dict(fwd_occ=out[0], fwd_views=out[1], bwd_vin=out[2], zseg_scale=out[3], cols=out[4])
 
 
 def mvd_batch_destroy(b) -> None:

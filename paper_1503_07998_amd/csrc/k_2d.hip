@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(NT) twod_forward_kernel(const TwoDPassArgs a) 
 #pragma unroll
       for (int n = 0; n < N4; ++n) {
         if (t.x0 + ox + n < a.g.X) {
-          const float p = fmaxf(a.phi[v][off + n], 0.f);
+          const float p = a.phi[v][off + n];
           a.out[v][off + n] = guarded_ratio(p, b[n]);
         }
       }

@@ -12,7 +12,8 @@
 //           128-bit LDS reads and compute the K-tap row convolution in
 //           registers, then run the fused epilogue.
 //
-// Forward epilogue:  r_v = φ_v / b_v  (b_v = ψ ⊛ P_v; 1 where b_v ≤ ε).
+// Forward epilogue:  r_v = φ_v / b_v  (b_v = ψ ⊛ P_v; 1 where b_v ≤ ε).  φ_v are
+//                    the staged observations, already clamped at 0.
 // Backward epilogue: ψ' = ψ · Π_v (w_v · q_v + 1 − w_v)  (q_v = r_v ⊛ X_v).
 // (Supplementary Note 1 update; Supplementary Note 2 §1 back-projector.)
 //
@@ -122,8 +123,6 @@ struct Cols {
 };
 
 // Zero the LDS pad columns of a whole-row strip: [0, R) and [R+X, ldsw).
-// Zero boundary keeps them 0; the periodic boundary overwrites the first R of
-// each side with wrapped copies every group.
 template <int R>
 __device__ __forceinline__ void zero_pads(float *lds, int nrows, KArg *a, int t,
                                           int nt) {
@@ -168,20 +167,15 @@ __device__ __forceinline__ int lds_pitch(KArg *a) {
   return p;
 }
 
-// Write one z-pass output (row g of the current buffer) and, for a periodic
-// whole-row strip, its wrapped copies in the pad columns.
+// Write one z-pass output (row g of the current buffer).  Whole-row strips
+// (no x halo) are planned for the zero boundary only, so their pad columns
+// stay zero; periodic runs use strips whose halo columns were loaded wrapped.
 template <int C, int R>
 __device__ __forceinline__ void store_mid(float *B, int g, KArg *a, const Cols<C, R> &cl,
                                           int c, float v) {
   if (!cl.act[c]) return;
   v = cl.ok[c] ? v : 0.f;   // column outside the plane (zero boundary)
-  float *row = B + g * lds_pitch(a);
-  row[cl.lcol[c]] = v;
-  if (a->halo == 0 && a->boundary == 1) {
-    const int X = a->g.X, x = cl.gx[c];
-    for (int p = R + x - X; p >= 0; p -= X) row[p] = v;
-    for (int p = R + x + X; p < X + 2 * R; p += X) row[p] = v;
-  }
+  B[g * lds_pitch(a) + cl.lcol[c]] = v;
 }
 
 // K-tap row convolution of 8 consecutive outputs from one LDS row.
@@ -236,10 +230,20 @@ __device__ __forceinline__ Item item_at(int it, const Loop &st, const Geo &o, in
   return r;
 }
 
-// 8 values at p.  vec: two 128-bit loads (every item is whole and aligned);
-// otherwise element-wise within the row.
+// Row-pass access mode: VM = 1 two 128-bit accesses per item (every item is
+// whole and 16-byte aligned), 0 element-wise within the row, 2 chosen at run
+// time from `vec`.  A run-time choice makes both forms join in the same
+// registers, and the copies at the join wait for the loads at once; the fixed
+// forms let the loads stay in flight until their values are used.
+template <int VM>
+__device__ __forceinline__ bool vec_mode(bool vec) {
+  return VM == 2 ? vec : VM == 1;
+}
+
+// 8 values at p (see vec_mode).
+template <int VM>
 __device__ __forceinline__ void load8(const float *__restrict__ p, int nvalid, bool vec, float (&v)[NX]) {
-  if (vec) {
+  if (vec_mode<VM>(vec)) {
     const float4 a = *reinterpret_cast<const float4 *>(p);
     const float4 b = *reinterpret_cast<const float4 *>(p + 4);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
@@ -250,8 +254,9 @@ __device__ __forceinline__ void load8(const float *__restrict__ p, int nvalid, b
   }
 }
 
+template <int VM>
 __device__ __forceinline__ void store8(float *__restrict__ p, int nvalid, bool vec, const float (&v)[NX]) {
-  if (vec) {
+  if (vec_mode<VM>(vec)) {
     *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
     *reinterpret_cast<float4 *>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
   } else {
@@ -325,7 +330,7 @@ __device__ __forceinline__ float guarded_ratio(float phi, float b) {
   return b > kEps ? q : 1.f;
 }
 
-template <int KB, int NV, int EP>
+template <int KB, int NV, int EP, int VM>
 __device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
                                                 const float (&ops)[NV][Epi<EP>::nbuf][NX]) {
 #pragma unroll
@@ -335,15 +340,15 @@ __device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const
     float r[NX];
     if constexpr (EP == kEpRatio) {
 #pragma unroll
-      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(fmaxf(ops[v][0][n], 0.f), b[n]);
-      store8(a->out[v] + itm.off, itm.nvalid, vec, r);
+      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(ops[v][0][n], b[n]);
+      store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, r);
     } else if constexpr (EP == kEpStore) {
-      store8(a->out[v] + itm.off, itm.nvalid, vec, b);
+      store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, b);
     } else if constexpr (EP == kEpBR) {
 #pragma unroll
-      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(fmaxf(ops[v][0][n], 0.f), b[n]);
-      store8(a->out[v] + itm.off, itm.nvalid, vec, b);
-      store8(a->out2[v] + itm.off, itm.nvalid, vec, r);
+      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(ops[v][0][n], b[n]);
+      store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, b);
+      store8<VM>(a->out2[v] + itm.off, itm.nvalid, vec, r);
     } else if constexpr (EP == kEpBbar) {
 #pragma unroll
       for (int n = 0; n < NX; ++n) {
@@ -351,42 +356,44 @@ __device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const
         const float q = nr_quotient(b[n] * ops[v][0][n], bb);
         r[n] = bb > kEps ? -q : 0.f;
       }
-      store8(a->out[v] + itm.off, itm.nvalid, vec, r);
+      store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, r);
     } else {
 #pragma unroll
       for (int n = 0; n < NX; ++n) r[n] = ops[v][0][n] + b[n];
-      store8(a->out[v] + itm.off, itm.nvalid, vec, r);
+      store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, r);
     }
   }
 }
 
-template <int NV, int EP>
+template <int NV, int EP, int VM>
 __device__ __forceinline__ void load_ops(KArg *a, const Item &itm, bool vec, float (&ops)[NV][Epi<EP>::nbuf][NX]) {
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
-    for (int k = 0; k < Epi<EP>::nops; ++k) load8(op_ptr<EP>(a, v, k) + itm.off, itm.nvalid, vec, ops[v][k]);
+    for (int k = 0; k < Epi<EP>::nops; ++k) load8<VM>(op_ptr<EP>(a, v, k) + itm.off, itm.nvalid, vec, ops[v][k]);
 }
 
 // One ring phase: group i = i0 + u.  u is a compile-time constant so every
 // ring index below is one too and the ring stays in registers.
-template <int KB, int C, int NV, int EP, int u>
+template <int KB, int C, int NV, int EP, int VM, int u>
 __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                           const float *__restrict__ src, float *lds, const Loop &st,
                                           float (&ring)[C][Shape<KB>::M], int i0) {
   constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
   const int i = i0 + u;
   if (i >= o.ngroups) return;
-  // 1. loads issued now and consumed later: the next group's rows (past the
-  //    segment end they are clamped and unused) and this thread's first
-  //    row-pass operands.  The column pass below covers their latency.
+  // 1. loads issued now and consumed later: this thread's first row-pass
+  //    operands, then the next group's rows (past the segment end they are
+  //    clamped and unused).  The column pass below covers their latency.
+  //    Memory loads retire in issue order, so the operands go first: the row
+  //    pass can then wait for them while the rows stay in flight.
+  const Item first = item_at(st.t, st, o, i, a);
+  float ops[NV][Epi<EP>::nbuf][NX];
+  load_ops<NV, EP, VM>(a, first, st.vec, ops);
 #pragma unroll
   for (int g = 0; g < G; ++g)
     load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
                    &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
-  const Item first = item_at(st.t, st, o, i, a);
-  float ops[NV][Epi<EP>::nbuf][NX];
-  load_ops<NV, EP>(a, first, st.vec, ops);
   // 2. column pass → LDS
   float *buf = lds + (i & 1) * st.bufsz;
 #pragma unroll
@@ -397,27 +404,27 @@ __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, S
   }
   lds_sync();
   // 3. row pass + epilogue
-  if (first.valid) single_epilogue<KB, NV, EP>(a, buf, first, st.vec, ops);
+  if (first.valid) single_epilogue<KB, NV, EP, VM>(a, buf, first, st.vec, ops);
   for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
     const Item itm = item_at(it, st, o, i, a);
     if (!itm.valid) continue;
     float q[NV][Epi<EP>::nbuf][NX];
-    load_ops<NV, EP>(a, itm, st.vec, q);
-    single_epilogue<KB, NV, EP>(a, buf, itm, st.vec, q);
+    load_ops<NV, EP, VM>(a, itm, st.vec, q);
+    single_epilogue<KB, NV, EP, VM>(a, buf, itm, st.vec, q);
   }
 }
 
-template <int KB, int C, int NV, int EP, int... us>
+template <int KB, int C, int NV, int EP, int VM, int... us>
 __device__ __forceinline__ void fwd_phases(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                            const float *__restrict__ src, float *lds, const Loop &st,
                                            float (&ring)[C][Shape<KB>::M], int i0,
                                            std::integer_sequence<int, us...>) {
-  (fwd_group<KB, C, NV, EP, us>(a, o, cl, src, lds, st, ring, i0), ...);
+  (fwd_group<KB, C, NV, EP, VM, us>(a, o, cl, src, lds, st, ring, i0), ...);
 }
 
 // OCC: minimum waves per SIMD the register budget must allow (second
 // launch-bounds argument): 4 caps a thread at 128 VGPRs, 2 at 256.
-template <int KB, int C, int NV, int OCC, int EP>
+template <int KB, int C, int NV, int OCC, int EP, int VM>
 __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_forward_kernel(const SepPassArgs) {
   KArg *a = kargs();
   using S = Shape<KB>;
@@ -434,13 +441,13 @@ __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_forward_kernel(const 
 #pragma unroll
   for (int m = 0; m < G + KB - 1; ++m) load_row<C, R>(src, st.rbase + m, a, cl, &ring[0][m], M);
   for (int i0 = 0; i0 < o.ngroups; i0 += U)
-    fwd_phases<KB, C, NV, EP>(a, o, cl, src, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
+    fwd_phases<KB, C, NV, EP, VM>(a, o, cl, src, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
 }
 
 // ---------------------------------------------------------------------------
 // Backward pass: VIN ratio planes → ψ' = ψ · Π_v (w_v q_v + 1 − w_v).
 // ---------------------------------------------------------------------------
-template <int KB, int VIN>
+template <int KB, int VIN, int VM>
 __device__ __forceinline__ void bwd_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
                                              float (&ps)[NX]) {
   float prod[NX];
@@ -457,16 +464,20 @@ __device__ __forceinline__ void bwd_epilogue(KArg *a, const float *buf, const It
   }
 #pragma unroll
   for (int n = 0; n < NX; ++n) ps[n] *= prod[n];
-  store8(a->psi_out + itm.off, itm.nvalid, vec, ps);
+  store8<VM>(a->psi_out + itm.off, itm.nvalid, vec, ps);
 }
 
-template <int KB, int C, int VIN, int u>
+template <int KB, int C, int VIN, int VM, int u>
 __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                           float *lds, const Loop &st, float (&ring)[VIN][C][Shape<KB>::M],
                                           int i0) {
   constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
   const int i = i0 + u;
   if (i >= o.ngroups) return;
+  // ψ of the first item, then the next group's rows (see fwd_group)
+  const Item first = item_at(st.t, st, o, i, a);
+  float ps[NX];
+  load8<VM>(a->psi_in + first.off, first.nvalid, st.vec, ps);
 #pragma unroll
   for (int v = 0; v < VIN; ++v) {
     const float *__restrict__ src = a->in[v] + o.plane_off;
@@ -475,9 +486,6 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
       load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
                      &ring[v][0][((u + 1) * G + KB - 1 + g) % M], M);
   }
-  const Item first = item_at(st.t, st, o, i, a);
-  float ps[NX];
-  load8(a->psi_in + first.off, first.nvalid, st.vec, ps);
   float *buf = lds + (i & 1) * st.bufsz;
 #pragma unroll
   for (int v = 0; v < VIN; ++v) {
@@ -486,24 +494,24 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
     store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
   }
   lds_sync();
-  if (first.valid) bwd_epilogue<KB, VIN>(a, buf, first, st.vec, ps);
+  if (first.valid) bwd_epilogue<KB, VIN, VM>(a, buf, first, st.vec, ps);
   for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
     const Item itm = item_at(it, st, o, i, a);
     if (!itm.valid) continue;
     float q[NX];
-    load8(a->psi_in + itm.off, itm.nvalid, st.vec, q);
-    bwd_epilogue<KB, VIN>(a, buf, itm, st.vec, q);
+    load8<VM>(a->psi_in + itm.off, itm.nvalid, st.vec, q);
+    bwd_epilogue<KB, VIN, VM>(a, buf, itm, st.vec, q);
   }
 }
 
-template <int KB, int C, int VIN, int... us>
+template <int KB, int C, int VIN, int VM, int... us>
 __device__ __forceinline__ void bwd_phases(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                            float *lds, const Loop &st, float (&ring)[VIN][C][Shape<KB>::M],
                                            int i0, std::integer_sequence<int, us...>) {
-  (bwd_group<KB, C, VIN, us>(a, o, cl, lds, st, ring, i0), ...);
+  (bwd_group<KB, C, VIN, VM, us>(a, o, cl, lds, st, ring, i0), ...);
 }
 
-template <int KB, int C, int VIN, int OCC>
+template <int KB, int C, int VIN, int OCC, int VM>
 __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_backward_kernel(const SepPassArgs) {
   KArg *a = kargs();
   using S = Shape<KB>;
@@ -523,7 +531,7 @@ __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_backward_kernel(const
     for (int m = 0; m < G + KB - 1; ++m) load_row<C, R>(src, st.rbase + m, a, cl, &ring[v][0][m], M);
   }
   for (int i0 = 0; i0 < o.ngroups; i0 += U)
-    bwd_phases<KB, C, VIN>(a, o, cl, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
+    bwd_phases<KB, C, VIN, VM>(a, o, cl, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
 }
 
 inline size_t lds_bytes(const SepPassArgs &a, int nviews) {
@@ -540,29 +548,37 @@ inline hipError_t launch_with_lds(K kern, const SepPassArgs &a, int threads, siz
   }
   // 128-bit row-pass accesses need whole 8-column items (checked on the host too)
   if (a.vec && (a.g.X % 8 != 0 || a.x_out % 8 != 0)) return hipErrorInvalidValue;
+  // whole-row strips keep zero pad columns: zero boundary only
+  if (a.halo == 0 && a.boundary != 0) return hipErrorInvalidValue;
   const unsigned nblocks = (unsigned)a.g.Y * a.nseg * a.nstrip;
   hipLaunchKernelGGL(kern, dim3(nblocks), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
-template <int KB>
-hipError_t forward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+template <int KB, int VM>
+hipError_t forward_bucket_vm(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes(a, a.nviews);
   const bool hi = p.occ >= 4;
   if constexpr (KB <= 41) {
     // two columns per thread only where the ring still fits (the planner never asks otherwise)
     if (p.cols == 2) {
-      if (a.nviews == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 2, 2, kEpRatio>, a, p.threads, lds, s);
-      return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, kEpRatio>, a, p.threads, lds, s);
+      if (a.nviews == 2)
+        return launch_with_lds(sep_forward_kernel<KB, 2, 2, 2, kEpRatio, VM>, a, p.threads, lds, s);
+      return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, kEpRatio, VM>, a, p.threads, lds, s);
     }
   }
   if (p.cols != 1) return hipErrorInvalidValue;
   if (a.nviews == 2) {
-    if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 2, 4, kEpRatio>, a, p.threads, lds, s);
-    return launch_with_lds(sep_forward_kernel<KB, 1, 2, 2, kEpRatio>, a, p.threads, lds, s);
+    if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 2, 4, kEpRatio, VM>, a, p.threads, lds, s);
+    return launch_with_lds(sep_forward_kernel<KB, 1, 2, 2, kEpRatio, VM>, a, p.threads, lds, s);
   }
-  if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, kEpRatio>, a, p.threads, lds, s);
-  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, kEpRatio>, a, p.threads, lds, s);
+  if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, kEpRatio, VM>, a, p.threads, lds, s);
+  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, kEpRatio, VM>, a, p.threads, lds, s);
+}
+
+template <int KB>
+hipError_t forward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  return a.vec ? forward_bucket_vm<KB, 1>(a, p, s) : forward_bucket_vm<KB, 0>(a, p, s);
 }
 
 // One-view single-input pass with an adjoint epilogue (kStore, kBR, kBbar, kAccum).
@@ -570,11 +586,11 @@ template <int KB, int EP>
 hipError_t single_ep(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes(a, 1);
   if constexpr (KB <= 41) {
-    if (p.cols == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, EP>, a, p.threads, lds, s);
+    if (p.cols == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, EP, 2>, a, p.threads, lds, s);
   }
   if (p.cols != 1) return hipErrorInvalidValue;
-  if constexpr (KB <= 31) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, EP>, a, p.threads, lds, s);
-  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, EP>, a, p.threads, lds, s);
+  if constexpr (KB <= 31) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, EP, 2>, a, p.threads, lds, s);
+  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, EP, 2>, a, p.threads, lds, s);
 }
 
 template <int KB>
@@ -589,17 +605,22 @@ hipError_t single_bucket(const SepPassArgs &a, const SepPlan &p, int ep, hipStre
   return hipErrorInvalidValue;
 }
 
-template <int KB>
-hipError_t backward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+template <int KB, int VM>
+hipError_t backward_bucket_vm(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes(a, p.vin);
   const bool hi = p.occ >= 4;
   if constexpr (KB <= 41) {
-    if (p.vin == 2) return launch_with_lds(sep_backward_kernel<KB, 1, 2, 2>, a, p.threads, lds, s);
-    if (p.cols == 2) return launch_with_lds(sep_backward_kernel<KB, 2, 1, 2>, a, p.threads, lds, s);
+    if (p.vin == 2) return launch_with_lds(sep_backward_kernel<KB, 1, 2, 2, VM>, a, p.threads, lds, s);
+    if (p.cols == 2) return launch_with_lds(sep_backward_kernel<KB, 2, 1, 2, VM>, a, p.threads, lds, s);
   }
   if (p.cols != 1 || p.vin != 1) return hipErrorInvalidValue;
-  if (hi) return launch_with_lds(sep_backward_kernel<KB, 1, 1, 4>, a, p.threads, lds, s);
-  return launch_with_lds(sep_backward_kernel<KB, 1, 1, 2>, a, p.threads, lds, s);
+  if (hi) return launch_with_lds(sep_backward_kernel<KB, 1, 1, 4, VM>, a, p.threads, lds, s);
+  return launch_with_lds(sep_backward_kernel<KB, 1, 1, 2, VM>, a, p.threads, lds, s);
+}
+
+template <int KB>
+hipError_t backward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  return a.vec ? backward_bucket_vm<KB, 1>(a, p, s) : backward_bucket_vm<KB, 0>(a, p, s);
 }
 
 }  // namespace sepk

@@ -273,7 +273,8 @@ bool all_set(const mvd_ctx *c) {
 
 // Workspace layout of one run.
 struct Layout {
-  bool stage = false;   // observations staged into float32 planes
+  bool stage = true;    // observations staged into float32 planes (always: the passes
+                        // then read clamped float32 planes and need no clamp of their own)
   size_t plane_set = 0; // bytes of one [Y][Z][X] float32 set
   size_t phi_off = 0, r_off = 0, total = 0;
   int n_ratio = 0;
@@ -282,7 +283,6 @@ struct Layout {
 Layout layout_of(const mvd_ctx *c, const mvd_run *r) {
   Layout L;
   L.plane_set = align_up((size_t)r->n_planes * c->Z * c->X * sizeof(float));
-  L.stage = !(r->obs_layout == MVD_PLANES_YZX && r->obs_dtype == MVD_F32);
   L.n_ratio = r->update == MVD_UPDATE_SIMULTANEOUS ? c->nv : 1;
   size_t off = 0;
   L.phi_off = off;
@@ -335,6 +335,7 @@ int round_up(int n, int m) { return (n + m - 1) / m * m; }
 struct Tune {
   int fwd_occ = 0, bwd_occ = 0, bwd_vin = 0, zseg = 0, fwd_views = 0;
   int zseg_scale = 0;   // > 0: segment length × 2^(zseg_scale − 2) of the automatic one (2 = as is)
+  int cols = 0;         // 1: one column per thread (strips with halo for rows wider than 512)
 };
 
 const Tune &tune() {
@@ -357,6 +358,8 @@ const Tune &tune() {
         if (k == "bwd_vin") r.bwd_vin = v;
         if (k == "zseg") r.zseg = v;
         if (k == "fwd_views") r.fwd_views = v;
+        if (k == "zseg_scale") r.zseg_scale = v;
+        if (k == "cols") r.cols = v;
       }
       pos = comma + 1;
     }
@@ -365,28 +368,35 @@ const Tune &tune() {
   return t;
 }
 
-SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, const Tune &tn = tune()) {
+// Whole rows (no x halo) under the zero boundary; strips with an x halo of R
+// columns otherwise.  Periodic runs always take strips: their halo columns are
+// read wrapped, so no pass has to copy wrapped values into LDS pad columns.
+SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn = tune()) {
   SepGeom s{};
   const int R = (kb - 1) / 2;
   const int X = c->X;
   s.plan.bucket = kb;
   const bool wide_ok = kb <= 41;   // two columns per thread keep the ring in registers
   const int max_cols = (wide_ok ? 2 : 1) * kSepMaxThreads;
-  if (X <= kSepMaxThreads) {
+  const bool whole = boundary == MVD_BOUNDARY_ZERO;
+  const bool one_col = tn.cols == 1 || !wide_ok;
+  if (whole && X <= kSepMaxThreads) {
     s.plan.cols = 1;
     s.nstrip = 1;
     s.x_out = X;
     s.halo = 0;
     s.ncols = X;
-  } else if (X <= max_cols) {
+  } else if (whole && !one_col && X <= max_cols) {
     s.plan.cols = 2;
     s.nstrip = 1;
     s.x_out = X;
     s.halo = 0;
     s.ncols = X;
   } else {
-    s.plan.cols = wide_ok ? 2 : 1;
-    const int per = s.plan.cols * kSepMaxThreads - 2 * R;
+    s.plan.cols = (X + 2 * R <= kSepMaxThreads || one_col) ? 1 : 2;
+    // outputs per strip: the threads' columns minus the halo, rounded down to
+    // whole 8-column items so that rounding the strip width up cannot exceed it
+    const int per = (s.plan.cols * kSepMaxThreads - 2 * R) / 8 * 8;
     s.nstrip = (X + per - 1) / per;
     s.x_out = round_up((X + s.nstrip - 1) / s.nstrip, 8);
     s.nstrip = (X + s.x_out - 1) / s.x_out;
@@ -406,8 +416,8 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, const Tune &tn = tune()) {
   if (tn.zseg_scale == 3) s.zseg = round_up(std::min(Z, 2 * s.zseg), kRowGroup);
   if (tn.zseg > 0) s.zseg = round_up(tn.zseg, kRowGroup);
   s.nseg = (Z + s.zseg - 1) / s.zseg;
-  // one column per thread keeps a K ≤ 31 ring within 128 VGPRs: 4 waves/SIMD
-  s.plan.occ = (s.plan.cols == 1 && kb <= 31) ? 4 : 2;
+  // one column per thread keeps a K ≤ 41 ring within 128 VGPRs: 4 waves/SIMD
+  s.plan.occ = (s.plan.cols == 1 && kb <= 41) ? 4 : 2;
   s.plan.vin = 1;
   return s;
 }
@@ -490,7 +500,7 @@ hipError_t forward_views(const RunState &st, const float *psi, const float *cons
     kmax = std::max({kmax, c->views[v].psf.kz, c->views[v].psf.kx});
   }
   if (sep) {
-    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), *st.tn);
+    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, *st.tn);
     if (st.tn->fwd_occ) sg.plan.occ = st.tn->fwd_occ;
     const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
     int cap = (int)std::max<size_t>(1, std::min<size_t>(kSepFwdViews, kLdsLimit / per_view));
@@ -547,7 +557,7 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
   }
   const float *cur = psi_in;
   if (sep) {
-    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), *st.tn);
+    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, *st.tn);
     const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
     // Two ratio planes per launch save one read and write of ψ but need two
     // rings (256-VGPR budget); one per launch runs at 4 waves/SIMD and is
@@ -611,7 +621,7 @@ constexpr int kPointBlocks = 1024;
 constexpr int kCorrBlocks = 1024;
 
 struct BwdLayout {
-  bool stage = false;
+  bool stage = true;     // as Layout: observations always staged
   size_t plane_set = 0;
   size_t phi_off = 0, b_off = 0, r_off = 0, q_off = 0, g_off = 0, sub_off = 0, rat_off = 0;
   size_t wpart_off = 0, cpart_off = 0, acc_off = 0, total = 0;
@@ -628,7 +638,6 @@ BwdLayout bwd_layout_of(const mvd_ctx *c, const mvd_run *r) {
   const int V = c->nv;
   const bool sim = r->update == MVD_UPDATE_SIMULTANEOUS;
   L.plane_set = align_up((size_t)r->n_planes * c->Z * c->X * sizeof(float));
-  L.stage = !(r->obs_layout == MVD_PLANES_YZX && r->obs_dtype == MVD_F32);
   L.nsets = sim ? V : 1;
   L.nsub = sim ? 0 : V - 1;
   size_t off = 0;
@@ -667,7 +676,7 @@ hipError_t single_pass(const RunState &st, int ep, const float *in, const std::v
                        const std::vector<float> &fx, float *out, float *out2, const float *aux0,
                        const float *aux1, const float *phi) {
   const int k = std::max((int)fz.size(), (int)fx.size());
-  SepGeom sg = plan_sep(st.c, st.g.Y, sep_bucket(k), *st.tn);
+  SepGeom sg = plan_sep(st.c, st.g.Y, sep_bucket(k), st.boundary, *st.tn);
   sg.plan.occ = (sg.plan.cols == 1 && sg.plan.bucket <= 31) ? 4 : 2;
   SepPassArgs a{};
   fill_sep_common(a, sg, st.g, st.boundary);
@@ -1002,12 +1011,15 @@ hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mv
 // Launch-shape candidates timed per workload (kernel sizes, plane shape, planes,
 // views, update order, boundary); the fastest is cached for the process.
 std::vector<Tune> tune_candidates() {
-  std::vector<Tune> c(6);
+  std::vector<Tune> c(8);
   c[1].fwd_occ = 2;
   c[2].fwd_views = 1;
   c[3].bwd_vin = 2;
   c[4].zseg_scale = 1;
   c[5].zseg_scale = 3;
+  c[6].cols = 1;
+  c[7].cols = 1;
+  c[7].zseg_scale = 3;
   return c;
 }
 
@@ -1338,9 +1350,10 @@ mvd_status mvd_deconvolve_stream(mvd_ctx *c, const void *const *obs, float *est,
 // can check every access of the kernels' index arithmetic against its buffer.
 // out[16]: bucket, cols, threads, occ, zseg, nseg, x_out, nstrip, halo, ncols,
 // ldsw, vec (for 16-byte aligned buffers), lds bytes per view.
-int mvd_internal_sep_plan(const mvd_ctx *c, int n_planes, int k, int *out) {
+int mvd_internal_sep_plan(const mvd_ctx *c, int n_planes, int k, int boundary, int *out) {
   if (!c || !out || n_planes < 1 || k < 1 || k > MVD_MAX_K) return MVD_ERR_ARG;
-  const SepGeom sg = plan_sep(c, n_planes, sep_bucket(k));
+  if (boundary != MVD_BOUNDARY_ZERO && boundary != MVD_BOUNDARY_PERIODIC) return MVD_ERR_ARG;
+  const SepGeom sg = plan_sep(c, n_planes, sep_bucket(k), boundary);
   out[0] = sg.plan.bucket;
   out[1] = sg.plan.cols;
   out[2] = sg.plan.threads;
@@ -1586,6 +1599,7 @@ mvd_status mvd_batch_tuning(const mvd_batch *b, int item, int *out) {
   out[1] = t.fwd_views;
   out[2] = t.bwd_vin;
   out[3] = t.zseg_scale;
+  out[4] = t.cols;
   return MVD_OK;
 }
 

@@ -170,10 +170,11 @@ def test_workspace_bytes_formula():
         plane_set = (7 * 10 * 12 * 4 + 255) // 256 * 256
         r = api.make_run(7, 3, layout="stack_zyx")
         assert api.mvd_workspace_bytes(ctx, r) == 2 * plane_set + 2 * plane_set
+        # observations are staged whatever their layout and type
         r = api.make_run(7, 3, layout="planes_yzx", update="sequential")
-        assert api.mvd_workspace_bytes(ctx, r) == plane_set
+        assert api.mvd_workspace_bytes(ctx, r) == 2 * plane_set + plane_set
         r = api.make_run(7, 0, layout="planes_yzx")
-        assert api.mvd_workspace_bytes(ctx, r) == 0
+        assert api.mvd_workspace_bytes(ctx, r) == 2 * plane_set
         r = api.make_run(7, 0, layout="planes_yzx", obs_dtype="u16")
         assert api.mvd_workspace_bytes(ctx, r) == 2 * plane_set
     finally:

@@ -20,12 +20,13 @@ NX = 8     # row-pass outputs per item
 LDS_LIMIT = 160 * 1024
 
 
-def plan(ctx, Y, k):
+def plan(ctx, Y, k, boundary):
     out = (ctypes.c_int * 16)()
     lib = N.lib()
     lib.mvd_internal_sep_plan.restype = ctypes.c_int
-    lib.mvd_internal_sep_plan.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-    assert lib.mvd_internal_sep_plan(ctx, Y, k, out) == 0
+    lib.mvd_internal_sep_plan.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int)]
+    assert lib.mvd_internal_sep_plan(ctx, Y, k, N.BOUNDARY[boundary], out) == 0
     keys = ["bucket", "cols", "threads", "occ", "zseg", "nseg", "x_out", "nstrip", "halo", "ncols",
             "ldsw", "vec", "lds_per_view"]
     return dict(zip(keys, list(out)[:len(keys)]))
@@ -34,7 +35,7 @@ def plan(ctx, Y, k):
 def check_geometry(Y, Z, X, k, boundary, views):
     ctx = api.mvd_create(1, Z, X, N.MVD_DEVICE_NONE)
     try:
-        p = plan(ctx, Y, k)
+        p = plan(ctx, Y, k, boundary)
     finally:
         api.mvd_destroy(ctx)
     KB = p["bucket"]
@@ -48,6 +49,8 @@ def check_geometry(Y, Z, X, k, boundary, views):
     if p["vec"]:
         assert X % 8 == 0 and p["x_out"] % 8 == 0
     halo = p["halo"] != 0
+    if boundary == "periodic":
+        assert halo, "periodic runs must use strips with wrapped halo columns"
     ldsw = p["ldsw"]
     assert ldsw % 4 == 0
     plane = Z * X
@@ -69,15 +72,6 @@ def check_geometry(Y, Z, X, k, boundary, views):
             assert 0 <= gx < X
             lcol = lc if halo else lc + R
             assert 0 <= lcol < ldsw
-            if not halo and boundary == "periodic":
-                q = R + x - X
-                while q >= 0:
-                    assert q < ldsw
-                    q -= X
-                q = R + x + X
-                while q < X + 2 * R:
-                    assert q < ldsw
-                    q += X
         if not halo:
             assert R + X <= ldsw
         # row-pass items: LDS reads and global accesses
@@ -115,6 +109,21 @@ SHAPES = [
     (300, 512, 768), (150, 1000, 1000), (256, 256, 256), (4, 1024, 1024), (2, 5, 2100),
     (1, 3, 513), (1, 7, 1023), (1, 7, 1025), (3, 33, 511),
 ]
+
+
+def test_strip_width_never_exceeds_thread_columns():
+    """Strips sized against the threads' columns minus the halo, then rounded
+    up to whole items, must still fit (one and two columns per thread)."""
+    for X in (1000, 1001, 1017, 1023, 2047, 2100, 3000):
+        for k in (1, 3, 9, 15, 21, 41, 63):
+            ctx = api.mvd_create(1, 16, X, N.MVD_DEVICE_NONE)
+            try:
+                for b in ("zero", "periodic"):
+                    p = plan(ctx, 2, k, b)
+                    if p["halo"]:
+                        assert p["x_out"] + 2 * p["halo"] <= p["threads"] * p["cols"], (X, k, b, p)
+            finally:
+                api.mvd_destroy(ctx)
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=[f"{y}x{z}x{x}" for y, z, x in SHAPES])
