@@ -101,6 +101,13 @@ typedef enum { MVD_INIT_MEAN = 0, MVD_INIT_GIVEN = 1, MVD_INIT_CONST = 2 } mvd_i
 #define MVD_FLAG_GRAPH 0x4u    /* capture the whole run into a HIP graph on first use and replay it
                                   (per context, keyed by every pointer and parameter of the run;
                                   not with MVD_FLAG_TIMING) */
+#define MVD_FLAG_TUNE 0x8u     /* choose launch shapes (row-segment length, views per launch,
+                                  columns per thread, occupancy) by timing candidates on one
+                                  iteration of this run's own data at the first run of a workload
+                                  shape; the choice is cached for the process.  That first call
+                                  synchronises its stream and overwrites est while it times (so
+                                  runs with MVD_INIT_GIVEN are not tuned).  Results can differ from
+                                  untuned runs by float32 rounding only. */
 
 /* Parameters of one deconvolution run.  struct_size must be sizeof(mvd_run). */
 typedef struct {

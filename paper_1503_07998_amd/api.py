@@ -100,12 +100,12 @@ def mvd_psf_info(ctx, view: int):
 def make_run(n_planes, n_iters, *, update="simultaneous", boundary="zero", init="mean",
              init_const=1.0, obs_dtype="f32", layout="stack_zyx", weights=None,
              checkpoints=None, workspace=None, workspace_bytes=0, force_2d=False, timing=False,
-             graph=False):
+             graph=False, tune=False):
     """Build an ``mvd_run``; keeps host weight storage alive on the object."""
     r = N.MvdRun()
     r.struct_size = ctypes.sizeof(N.MvdRun)
     r.flags = ((N.MVD_FLAG_FORCE_2D if force_2d else 0) | (N.MVD_FLAG_TIMING if timing else 0)
-               | (N.MVD_FLAG_GRAPH if graph else 0))
+               | (N.MVD_FLAG_GRAPH if graph else 0) | (N.MVD_FLAG_TUNE if tune else 0))
     r.n_planes = int(n_planes)
     r.n_iters = int(n_iters)
     r.update = N.UPDATE[update]

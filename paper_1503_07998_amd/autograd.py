@@ -45,11 +45,12 @@ class PlanewiseRL:
         self.obs_dtype = "u16" if o0.dtype == torch.uint16 else "f32"
         self.dec = api.Deconvolver(len(self.obs), self.nz, self.nx, device)
         self.dev = o0.device
+        self.timing = False   # record per-launch HIP events (read with api.mvd_get_timing)
 
     def _run(self, weights, checkpoints=None, ws_bytes=0):
         return api.make_run(self.ny, self.iters, update=self.update, boundary=self.boundary,
                             obs_dtype=self.obs_dtype, layout=self.layout, weights=weights,
-                            checkpoints=checkpoints)
+                            checkpoints=checkpoints, timing=self.timing)
 
     def set_sigmas(self, sigma):
         s = sigma.detach().to("cpu", dtype=_torch().float64)

@@ -311,7 +311,7 @@ mvd_status check_run(mvd_ctx *c, const mvd_run *r) {
     return fail(c, MVD_ERR_ARG, "unknown obs_dtype %d", r->obs_dtype);
   if (r->obs_layout != MVD_STACK_ZYX && r->obs_layout != MVD_PLANES_YZX)
     return fail(c, MVD_ERR_ARG, "unknown obs_layout %d", r->obs_layout);
-  if (r->flags & ~(MVD_FLAG_FORCE_2D | MVD_FLAG_TIMING | MVD_FLAG_GRAPH))
+  if (r->flags & ~(MVD_FLAG_FORCE_2D | MVD_FLAG_TIMING | MVD_FLAG_GRAPH | MVD_FLAG_TUNE))
     return fail(c, MVD_ERR_ARG, "unknown flags 0x%x", r->flags);
   if (r->view_weights)
     for (int v = 0; v < c->nv; ++v) {
@@ -412,8 +412,11 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn =
   int nseg = (int)std::max(1L, (2048 + tiles - 1) / tiles);
   nseg = std::min(nseg, std::max(1, Z / 32));
   s.zseg = round_up((Z + nseg - 1) / nseg, kRowGroup);
-  if (tn.zseg_scale == 1) s.zseg = round_up(std::max(kRowGroup, s.zseg / 2), kRowGroup);
-  if (tn.zseg_scale == 3) s.zseg = round_up(std::min(Z, 2 * s.zseg), kRowGroup);
+  if (tn.zseg_scale > 0 && tn.zseg_scale != 2) {
+    const double f = std::ldexp(1.0, tn.zseg_scale - 2);
+    const int want = (int)std::lround(s.zseg * f);
+    s.zseg = round_up(std::max(kRowGroup, std::min(round_up(Z, kRowGroup), want)), kRowGroup);
+  }
   if (tn.zseg > 0) s.zseg = round_up(tn.zseg, kRowGroup);
   s.nseg = (Z + s.zseg - 1) / s.zseg;
   // one column per thread keeps a K ≤ 41 ring within 128 VGPRs: 4 waves/SIMD
@@ -819,6 +822,8 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
   return e;
 }
 
+hipError_t autotune(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, hipStream_t s, Tune *out);
+
 // ---- streamed runs --------------------------------------------------------------
 // Workspace of a streamed run: `slots` staging slots, each holding V observation
 // batches [Z][ys][X] (and, for a host estimate, one float32 batch [ys][Z][X]),
@@ -894,6 +899,15 @@ hipError_t enqueue_stream(mvd_ctx *c, const void *const *obs, float *est, const 
   if (e == hipSuccess && est_host) e = hipStreamWaitEvent(c->d2h, start, 0);
   const int nb = (Y + S.ys - 1) / S.ys;
   std::vector<const void *> slab(c->nv);
+  Tune tn = tune();
+  auto batch_run = [&](int ny, char *run_ws) {
+    mvd_run sub = *r;
+    sub.n_planes = ny;
+    sub.flags &= ~MVD_FLAG_TUNE;
+    sub.workspace = run_ws;
+    sub.workspace_bytes = S.run_bytes;
+    return sub;
+  };
   for (int b = 0; b < nb && e == hipSuccess; ++b) {
     const int k = b % S.slots, y0 = b * S.ys, ny = std::min(S.ys, Y - y0);
     char *slot = ws + (size_t)k * S.slot;
@@ -916,12 +930,14 @@ hipError_t enqueue_stream(mvd_ctx *c, const void *const *obs, float *est, const 
     if (e == hipSuccess) e = hipEventRecord(in[k], c->h2d);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, in[k], 0);
     if (e == hipSuccess && est_host && b >= S.slots) e = hipStreamWaitEvent(s, out[k], 0);
+    // launch shapes timed on the first batch (full-size batches share its shape)
+    if (e == hipSuccess && b == 0 && (r->flags & MVD_FLAG_TUNE) && r->init != MVD_INIT_GIVEN) {
+      const mvd_run sub = batch_run(ny, ws + S.run_off);
+      e = autotune(c, slab.data(), est_b, &sub, s, &tn);
+    }
     if (e == hipSuccess) {
-      mvd_run sub = *r;
-      sub.n_planes = ny;
-      sub.workspace = ws + S.run_off;
-      sub.workspace_bytes = S.run_bytes;
-      e = enqueue_run(c, slab.data(), est_b, &sub, s, tune());
+      const mvd_run sub = batch_run(ny, ws + S.run_off);
+      e = enqueue_run(c, slab.data(), est_b, &sub, s, tn);
     }
     if (e == hipSuccess) e = hipEventRecord(done[k], s);
     if (e == hipSuccess && est_host) {
@@ -984,7 +1000,8 @@ hipError_t capture(F &&launch, hipGraph_t *graph, hipGraphExec_t *exec) {
   return e;
 }
 
-hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, hipGraphExec_t *out) {
+hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, const Tune &tn,
+                        hipGraphExec_t *out) {
   const std::vector<uint64_t> key = run_key(c, obs, est, r);
   for (auto &g : c->graphs)
     if (g.key == key) {
@@ -993,7 +1010,7 @@ hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mv
     }
   mvd_ctx::Graph g;
   g.key = key;
-  hipError_t e = capture([&](hipStream_t cs) { return enqueue_run(c, obs, est, r, cs, tune()); }, &g.graph,
+  hipError_t e = capture([&](hipStream_t cs) { return enqueue_run(c, obs, est, r, cs, tn); }, &g.graph,
                          &g.exec);
   if (e != hipSuccess) return e;
   if (c->graphs.size() >= 8) {   // keep the cache small: drop the oldest
@@ -1011,15 +1028,15 @@ hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mv
 // Launch-shape candidates timed per workload (kernel sizes, plane shape, planes,
 // views, update order, boundary); the fastest is cached for the process.
 std::vector<Tune> tune_candidates() {
-  std::vector<Tune> c(8);
+  std::vector<Tune> c(9);
   c[1].fwd_occ = 2;
   c[2].fwd_views = 1;
   c[3].bwd_vin = 2;
-  c[4].zseg_scale = 1;
+  c[4].zseg_scale = 1;   // segments × 1/2, × 2, × 4, × 8
   c[5].zseg_scale = 3;
-  c[6].cols = 1;
-  c[7].cols = 1;
-  c[7].zseg_scale = 3;
+  c[6].zseg_scale = 4;
+  c[7].zseg_scale = 5;
+  c[8].cols = 1;
   return c;
 }
 
@@ -1065,8 +1082,18 @@ hipError_t autotune(mvd_ctx *c, const void *const *obs, float *est, const mvd_ru
   mvd_run probe = *r;
   probe.n_iters = 1;
   probe.checkpoints = nullptr;
-  probe.flags &= ~(MVD_FLAG_GRAPH | MVD_FLAG_TIMING);
-  (void)drain_marks(c);
+  probe.flags &= ~(MVD_FLAG_GRAPH | MVD_FLAG_TIMING | MVD_FLAG_TUNE);
+  // the caller's timing records are kept aside while the candidates are timed
+  std::vector<mvd_ctx::Mark> kept;
+  kept.swap(c->marks);
+  struct Restore {
+    mvd_ctx *c;
+    std::vector<mvd_ctx::Mark> &kept;
+    ~Restore() {
+      (void)drain_marks(c);
+      c->marks.swap(kept);
+    }
+  } restore{c, kept};
   hipError_t e = enqueue_run(c, obs, est, &probe, s, Tune{});   // warm-up
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   const std::vector<Tune> cand = tune_candidates();
@@ -1289,13 +1316,17 @@ mvd_status mvd_deconvolve_planes(mvd_ctx *c, const void *const *obs, float *est,
   if (st != MVD_OK) return st;
   DeviceGuard dg(c->device);
   if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
-  hipError_t e;
-  if (r->flags & MVD_FLAG_GRAPH) {
+  hipError_t e = hipSuccess;
+  Tune tn = tune();
+  if ((r->flags & MVD_FLAG_TUNE) && r->init != MVD_INIT_GIVEN)
+    e = autotune(c, obs, est, r, (hipStream_t)stream, &tn);
+  if (e != hipSuccess) {
+  } else if (r->flags & MVD_FLAG_GRAPH) {
     hipGraphExec_t exec = nullptr;
-    e = cached_graph(c, obs, est, r, &exec);
+    e = cached_graph(c, obs, est, r, tn, &exec);
     if (e == hipSuccess) e = hipGraphLaunch(exec, (hipStream_t)stream);
   } else {
-    e = enqueue_run(c, obs, est, r, (hipStream_t)stream, tune());
+    e = enqueue_run(c, obs, est, r, (hipStream_t)stream, tn);
   }
   if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "launch failed: %s", hipGetErrorString(e));
   return MVD_OK;

@@ -115,3 +115,34 @@ def test_batch_run_one_shot_and_validation():
         api.mvd_batch_create([(st["dec"].ctx, st["obs"], st["est"], bad)])
     assert e.value.status == N.MVD_ERR_WORKSPACE
     st["dec"].close()
+
+
+def test_tuned_run_matches_plain():
+    """MVD_FLAG_TUNE times launch-shape candidates on the first call of a shape
+    and caches the choice; results equal the untuned run up to float32
+    rounding (several views' factors may be applied in one launch)."""
+    from paper_1503_07998_amd import api
+
+    torch = _torch()
+    _say("tuned run vs plain (mix_b shape, 3 planes), then cached")
+    st = _setup(CONFIGS["mix_b"], 3)
+    d, obs, est, run = st["dec"], st["obs"], st["est"], st["run"]
+    api.mvd_deconvolve_planes(d.ctx, obs, est, run)
+    torch.cuda.synchronize()
+    plain = est.cpu().numpy().copy()
+    run.flags |= 0x8   # MVD_FLAG_TUNE
+    for rep in range(2):
+        est.fill_(-1.0)
+        api.mvd_deconvolve_planes(d.ctx, obs, est, run)
+        torch.cuda.synchronize()
+        got = est.cpu().numpy()
+        err = np.abs(got - plain).max() / np.abs(plain).max()
+        assert err <= 1e-6, f"tuned vs plain: {err:.3e} (call {rep})"
+    run.flags |= 0x4   # tuned and captured
+    for rep in range(2):
+        est.fill_(-1.0)
+        api.mvd_deconvolve_planes(d.ctx, obs, est, run)
+        torch.cuda.synchronize()
+        err = np.abs(est.cpu().numpy() - plain).max() / np.abs(plain).max()
+        assert err <= 1e-6, f"tuned graph vs plain: {err:.3e}"
+    d.close()

@@ -72,7 +72,7 @@ def _plain(d, spec, stacks, init=None):
     return est.cpu().numpy()
 
 
-def _streamed(d, spec, host_obs, batch, est_host, init=None, Y=None):
+def _streamed(d, spec, host_obs, batch, est_host, init=None, Y=None, tune=False):
     from paper_1503_07998_amd import api
 
     torch = _torch()
@@ -88,7 +88,7 @@ def _streamed(d, spec, host_obs, batch, est_host, init=None, Y=None):
         kw["init"] = "given"
     else:
         est.fill_(-7.0)
-    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype, **kw)
+    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype, tune=tune, **kw)
     nb = api.mvd_stream_workspace_bytes(d.ctx, run, batch, est_host)
     ws, run.workspace = _workspace(nb)
     run.workspace_bytes = nb
@@ -118,6 +118,17 @@ def test_streamed_equals_plain(small_case, batch, est_host):
     _say(f"streamed 37 planes batch={batch} est_host={est_host}")
     got = _streamed(small_case["d"], SMALL, small_case["host"], batch, est_host)
     np.testing.assert_array_equal(got, small_case["plain"])
+
+
+@pytest.mark.parametrize("est_host", [False, True], ids=["est_dev", "est_host"])
+def test_streamed_tuned(small_case, est_host):
+    """Launch shapes timed on the first batch: equal to the plain run up to
+    float32 rounding, twice in a row (the second call uses the cached choice)."""
+    _say(f"streamed with tuning est_host={est_host}")
+    for rep in range(2):
+        got = _streamed(small_case["d"], SMALL, small_case["host"], 8, est_host, tune=True)
+        err = np.abs(got - small_case["plain"]).max() / np.abs(small_case["plain"]).max()
+        assert err <= 1e-6, f"tuned streamed vs plain: {err:.3e} (call {rep})"
 
 
 def test_streamed_small_matches_oracle(small_case):
