@@ -105,6 +105,7 @@ constexpr int CTZ = 8;    // tile rows (one per row group of threads)
 constexpr int CTX = 64;   // tile columns
 constexpr int LJ = 4;     // lags per thread along z
 constexpr int LI = 8;     // lags per thread along x
+constexpr int SU = 8;     // window elements staged per thread per step
 
 struct CorrGeo {
   int kzp, kxp, nbj, nbi, nblk, bw, bh;
@@ -117,7 +118,9 @@ __device__ __forceinline__ CorrGeo corr_geo(const CorrArgs &a) {
   g.nbj = g.kzp / LJ;
   g.nbi = g.kxp / LI;
   g.nblk = g.nbj * g.nbi;
-  g.bw = CTX + g.kxp;          // staged columns (last one unused)
+  // staged columns: CTX + kxp − 1 used, padded so that the row pitch is 4 (mod 8)
+  // floats: tile rows then start 4 banks apart (see the lane mapping below)
+  g.bw = CTX + g.kxp + 4;
   g.bh = CTZ + g.kzp - 1;
   return g;
 }
@@ -128,8 +131,13 @@ __global__ void __launch_bounds__(1024) corr_kernel(CorrArgs a) {
   float *At = sm;                       // [CTZ][CTX]
   float *Bt = sm + CTZ * CTX;           // [bh][bw]
   const int t = threadIdx.x;
-  const int blk = t % G.nblk, rg = t / G.nblk;   // lag block, tile row
-  const int jb = blk / G.nbi, ib = blk % G.nbi;
+  // lane → (x-lag block, tile row, z-lag block), x-lag block fastest: the 8 lanes
+  // that share an LDS cycle read windows 8 columns apart in two rows whose
+  // pitch is 4 (mod 8) floats, so their 16-byte reads fall in distinct banks
+  const int ib = t % G.nbi;
+  const int rg = (t / G.nbi) % CTZ;
+  const int jb = t / (G.nbi * CTZ);
+  const int blk = jb * G.nbi + ib;        // lag block
   const int Z = a.g.Z, X = a.g.X;
   const int ntz = (Z + CTZ - 1) / CTZ, ntx = (X + CTX - 1) / CTX;
   const long ntiles = (long)a.g.Y * ntz * ntx;
@@ -138,6 +146,9 @@ __global__ void __launch_bounds__(1024) corr_kernel(CorrArgs a) {
   for (int jj = 0; jj < LJ; ++jj)
 #pragma unroll
     for (int ii = 0; ii < LI; ++ii) acc[jj][ii] = 0.f;
+  // this thread's staging walk over the window, the same for every tile
+  const int nt = blockDim.x;
+  const int br0 = t / G.bw, bc0 = t % G.bw, dr = nt / G.bw, dc = nt % G.bw;
   for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int txi = (int)(tile % ntx);
     const int tzi = (int)((tile / ntx) % ntz);
@@ -151,16 +162,39 @@ __global__ void __launch_bounds__(1024) corr_kernel(CorrArgs a) {
       const int z = z0 + r, x = x0 + c;
       At[e] = (z < Z && x < X) ? a.gbar[po + (size_t)z * X + x] : 0.f;
     }
-    for (int e = t; e < G.bh * G.bw; e += blockDim.x) {
-      const int r = e / G.bw, c = e % G.bw;
-      int z = z0 + a.rz - G.kzp + 1 + r, x = x0 + a.rx - G.kxp + 1 + c;
-      float v = 0.f;
-      if (a.boundary == 0) {
-        if (z >= 0 && z < Z && x >= 0 && x < X) v = a.src[po + (size_t)z * X + x];
-      } else {
-        v = a.src[po + (size_t)wrapc(z, Z) * X + wrapc(x, X)];
+    // element e = t + k·nt of the [bh][bw] window, walked as (row, column), SU
+    // elements at a time: all SU loads are issued (at clamped, valid addresses)
+    // before any is stored, so their latencies overlap
+    const int zb = z0 + a.rz - G.kzp + 1, xb = x0 + a.rx - G.kxp + 1;
+    for (int r = br0, c = bc0, e = t; r < G.bh;) {
+      float v[SU];
+      int ev[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        int z = zb + r, x = xb + c;
+        bool in = r < G.bh;
+        if (a.boundary == 0) {
+          in = in && z >= 0 && z < Z && x >= 0 && x < X;
+          z = min(max(z, 0), Z - 1);
+          x = min(max(x, 0), X - 1);
+        } else {
+          z = wrapc(z, Z);
+          x = wrapc(x, X);
+        }
+        const float w = a.src[po + (size_t)z * X + x];
+        v[u] = in ? w : 0.f;
+        ev[u] = r < G.bh ? e : -1;
+        e += nt;
+        r += dr;
+        c += dc;
+        if (c >= G.bw) {
+          c -= G.bw;
+          ++r;
+        }
       }
-      Bt[e] = v;
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+        if (ev[u] >= 0) Bt[ev[u]] = v[u];
     }
     __syncthreads();
     if (rg < CTZ) {
@@ -213,16 +247,19 @@ __global__ void __launch_bounds__(1024) corr_kernel(CorrArgs a) {
   }
 }
 
-// acc[j][i] += Σ_b part[b][j][i] over lags inside the true kernel (fixed order).
-__global__ void corr_finalize_kernel(const float *__restrict__ part, int nblocks, int kzp, int kxp, int kz,
-                                     int kx, double *acc) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= kz * kx) return;
+// acc[j][i] += Σ_b part[b][j][i] over lags inside the true kernel: one
+// work-group per lag, strided float64 partial sums and a tree in a fixed
+// order (bitwise reproducible).
+__global__ void __launch_bounds__(NT) corr_finalize_kernel(const float *__restrict__ part, int nblocks, int kzp,
+                                                           int kxp, int kz, int kx, double *acc) {
+  __shared__ double sh[NT];
+  const int l = blockIdx.x;
   const int j = l / kx, i = l % kx;
-  const int pl = j * kxp + i;
+  const size_t pl = (size_t)j * kxp + i, stride = (size_t)kzp * kxp;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * kzp * kxp + pl];
-  acc[l] += s;
+  for (int b = threadIdx.x; b < nblocks; b += NT) s += part[(size_t)b * stride + pl];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) acc[l] += s;
 }
 
 __global__ void to_f32_kernel(const double *__restrict__ src, float *__restrict__ dst, int n) {
@@ -244,7 +281,7 @@ int corr_pad(int k, int unit) {
 }
 
 size_t corr_lds_bytes(int kzp, int kxp) {
-  const size_t tiles = sizeof(float) * ((size_t)CTZ * CTX + (size_t)(CTZ + kzp - 1) * (CTX + kxp));
+  const size_t tiles = sizeof(float) * ((size_t)CTZ * CTX + (size_t)(CTZ + kzp - 1) * (CTX + kxp + 4));
   const size_t red = sizeof(float) * (size_t)CTZ * (kzp / LJ) * (kxp / LI) * LJ * LI;
   return tiles > red ? tiles : red;
 }
@@ -279,9 +316,7 @@ hipError_t launch_corr(const CorrArgs &a, int nblocks, hipStream_t s) {
 
 hipError_t launch_corr_finalize(const float *part, int nblocks, int kzp, int kxp, int kz, int kx, double *acc,
                                 hipStream_t s) {
-  const int n = kz * kx;
-  hipLaunchKernelGGL(corr_finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, part, nblocks, kzp, kxp, kz,
-                     kx, acc);
+  hipLaunchKernelGGL(corr_finalize_kernel, dim3(kz * kx), dim3(NT), 0, s, part, nblocks, kzp, kxp, kz, kx, acc);
   return hipGetLastError();
 }
 

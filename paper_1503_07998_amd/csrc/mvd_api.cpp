@@ -621,7 +621,7 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
 
 // ---- reverse sweep (adjoint) ----------------------------------------------
 constexpr int kPointBlocks = 1024;
-constexpr int kCorrBlocks = 1024;
+constexpr int kCorrBlocks = 4096;
 
 struct BwdLayout {
   bool stage = true;     // as Layout: observations always staged
