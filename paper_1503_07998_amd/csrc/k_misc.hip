@@ -1,4 +1,6 @@
 // Element-wise kernels: reslice / convert of the observations, ψ^0, fill, copy.
+#include <algorithm>
+
 #include "mvd_internal.hpp"
 
 namespace mvd {
@@ -43,6 +45,64 @@ struct Ptrs {
   const float *p[kMaxViews];
 };
 
+struct StageViews {
+  const void *src[kMaxViews];
+  float *dst[kMaxViews];
+  float *mean;   // ψ^0 = (1/V) Σ_v φ_v, or null
+  int nv, dtype, layout, vec;
+  PlaneGeom g;
+};
+
+__device__ __forceinline__ float4 load4(const void *src, int dtype, size_t off) {
+  if (dtype == 1) {
+    const ushort4 u = *reinterpret_cast<const ushort4 *>(static_cast<const uint16_t *>(src) + off);
+    return make_float4((float)u.x, (float)u.y, (float)u.z, (float)u.w);
+  }
+  const float4 f = *reinterpret_cast<const float4 *>(static_cast<const float *>(src) + off);
+  return make_float4(fmaxf(f.x, 0.f), fmaxf(f.y, 0.f), fmaxf(f.z, 0.f), fmaxf(f.w, 0.f));
+}
+
+// Every view's observations → float32 planes, and optionally their mean, in
+// one pass: one wave per destination row (y, z), lanes along x.
+__global__ void __launch_bounds__(NT) stage_views_kernel(StageViews a) {
+  const int lane = threadIdx.x & 63;
+  const size_t nrows = (size_t)a.g.Y * a.g.Z;
+  const size_t X = (size_t)a.g.X;
+  const size_t nwaves = (size_t)gridDim.x * (NT / 64);
+  const float nvf = (float)a.nv;
+  for (size_t rr = (size_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6); rr < nrows; rr += nwaves) {
+    const size_t y = rr / a.g.Z, z = rr - y * a.g.Z;
+    const size_t srow = a.layout == 1 ? (z * a.g.Y + y) * X : rr * X;
+    const size_t drow = rr * X;
+    if (a.vec) {
+      for (size_t x = 4 * (size_t)lane; x < X; x += 256) {
+        float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int v = 0; v < a.nv; ++v) {
+          const float4 f = load4(a.src[v], a.dtype, srow + x);
+          *reinterpret_cast<float4 *>(a.dst[v] + drow + x) = f;
+          sum.x += f.x;
+          sum.y += f.y;
+          sum.z += f.z;
+          sum.w += f.w;
+        }
+        if (a.mean)
+          *reinterpret_cast<float4 *>(a.mean + drow + x) =
+              make_float4(sum.x / nvf, sum.y / nvf, sum.z / nvf, sum.w / nvf);
+      }
+    } else {
+      for (size_t x = lane; x < X; x += 64) {
+        float sum = 0.f;
+        for (int v = 0; v < a.nv; ++v) {
+          const float f = obs_value(a.src[v], a.dtype, srow + x);
+          a.dst[v][drow + x] = f;
+          sum += f;
+        }
+        if (a.mean) a.mean[drow + x] = sum / nvf;
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(NT) init_mean_kernel(Ptrs ph, int nv, size_t n, float *__restrict__ dst) {
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
     float s = 0.f;
@@ -76,6 +136,30 @@ hipError_t launch_stage_obs(const void *src, int dtype, int layout, PlaneGeom g,
   const int vec = (g.X % 4 == 0) && ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);
   hipLaunchKernelGGL(stage_kernel, dim3(grid_for(vec ? total / 4 : total)), dim3(NT), 0, s, src, dtype,
                      layout, g, dst, vec);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_views(const void *const *src, int nv, int dtype, int layout, PlaneGeom g,
+                              float *const *dst, float *mean, hipStream_t s) {
+  const size_t rows = (size_t)g.Y * g.Z;
+  if (rows == 0 || g.X == 0) return hipSuccess;
+  if (nv < 1 || nv > kMaxViews) return hipErrorInvalidValue;
+  StageViews a{};
+  a.nv = nv;
+  a.dtype = dtype;
+  a.layout = layout;
+  a.g = g;
+  a.mean = mean;
+  const uintptr_t sa = dtype == 1 ? 8 : 16;
+  int vec = g.X % 4 == 0 && (!mean || (uintptr_t)mean % 16 == 0);
+  for (int v = 0; v < nv; ++v) {
+    a.src[v] = src[v];
+    a.dst[v] = dst[v];
+    vec = vec && (uintptr_t)src[v] % sa == 0 && (uintptr_t)dst[v] % 16 == 0;
+  }
+  a.vec = vec;
+  const size_t blocks = std::min<size_t>((rows + NT / 64 - 1) / (NT / 64), 65536);
+  hipLaunchKernelGGL(stage_views_kernel, dim3((unsigned)blocks), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 

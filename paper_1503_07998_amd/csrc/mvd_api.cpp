@@ -272,9 +272,9 @@ bool all_set(const mvd_ctx *c) {
 }
 
 // Workspace layout of one run.
+// The observations are always staged into clamped float32 planes, so the
+// passes read one form and need no clamp of their own.
 struct Layout {
-  bool stage = true;    // observations staged into float32 planes (always: the passes
-                        // then read clamped float32 planes and need no clamp of their own)
   size_t plane_set = 0; // bytes of one [Y][Z][X] float32 set
   size_t phi_off = 0, r_off = 0, total = 0;
   int n_ratio = 0;
@@ -286,10 +286,10 @@ Layout layout_of(const mvd_ctx *c, const mvd_run *r) {
   L.n_ratio = r->update == MVD_UPDATE_SIMULTANEOUS ? c->nv : 1;
   size_t off = 0;
   L.phi_off = off;
-  if (L.stage) off += (size_t)c->nv * L.plane_set;
+  off += (size_t)c->nv * L.plane_set;
   L.r_off = off;
   off += (size_t)L.n_ratio * L.plane_set;
-  L.total = r->n_iters > 0 ? off : (L.stage ? (size_t)c->nv * L.plane_set : 0);
+  L.total = r->n_iters > 0 ? off : (size_t)c->nv * L.plane_set;
   return L;
 }
 
@@ -624,7 +624,6 @@ constexpr int kPointBlocks = 1024;
 constexpr int kCorrBlocks = 4096;
 
 struct BwdLayout {
-  bool stage = true;     // as Layout: observations always staged
   size_t plane_set = 0;
   size_t phi_off = 0, b_off = 0, r_off = 0, q_off = 0, g_off = 0, sub_off = 0, rat_off = 0;
   size_t wpart_off = 0, cpart_off = 0, acc_off = 0, total = 0;
@@ -645,7 +644,7 @@ BwdLayout bwd_layout_of(const mvd_ctx *c, const mvd_run *r) {
   L.nsub = sim ? 0 : V - 1;
   size_t off = 0;
   L.phi_off = off;
-  if (L.stage) off += (size_t)V * L.plane_set;
+  off += (size_t)V * L.plane_set;   // staged observations
   L.b_off = off;
   off += (size_t)L.nsets * L.plane_set;
   L.r_off = off;
@@ -782,26 +781,22 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
   RunState rs{c,  g, r->boundary, (r->flags & MVD_FLAG_FORCE_2D) != 0, s, r->view_weights,
               timing_override || (r->flags & MVD_FLAG_TIMING) != 0, &tn};
   std::vector<const float *> phi(c->nv);
-  hipError_t e = hipSuccess;
-  for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
-    if (L.stage) {
-      float *dst = reinterpret_cast<float *>(ws + L.phi_off + (size_t)v * L.plane_set);
-      e = timed(rs, 2, [&] { return launch_stage_obs(obs[v], r->obs_dtype, r->obs_layout, g, dst, s); });
-      phi[v] = dst;
-    } else {
-      phi[v] = static_cast<const float *>(obs[v]);
-    }
+  std::vector<float *> staged(c->nv);
+  for (int v = 0; v < c->nv; ++v) {
+    staged[v] = reinterpret_cast<float *>(ws + L.phi_off + (size_t)v * L.plane_set);
+    phi[v] = staged[v];
   }
   const int T = r->n_iters;
   float *psi0 = (r->checkpoints && T > 0) ? r->checkpoints : est;
-  if (e == hipSuccess) {
-    if (r->init == MVD_INIT_MEAN)
-      e = timed(rs, 2, [&] { return launch_init_mean(phi.data(), c->nv, n, psi0, s); });
-    else if (r->init == MVD_INIT_CONST)
-      e = timed(rs, 2, [&] { return launch_fill(psi0, n, r->init_const, s); });
-    else if (psi0 != est)
-      e = timed(rs, 2, [&] { return launch_copy(est, psi0, n, s); });
-  }
+  // observations of every view staged in one pass, with ψ^0 = their mean when asked
+  float *mean = r->init == MVD_INIT_MEAN ? psi0 : nullptr;
+  hipError_t e = timed(rs, 2, [&] {
+    return launch_stage_views(obs, c->nv, r->obs_dtype, r->obs_layout, g, staged.data(), mean, s);
+  });
+  if (e == hipSuccess && r->init == MVD_INIT_CONST)
+    e = timed(rs, 2, [&] { return launch_fill(psi0, n, r->init_const, s); });
+  else if (e == hipSuccess && r->init == MVD_INIT_GIVEN && psi0 != est)
+    e = timed(rs, 2, [&] { return launch_copy(est, psi0, n, s); });
   std::vector<float *> rat(L.n_ratio);
   for (int k = 0; k < L.n_ratio; ++k) rat[k] = reinterpret_cast<float *>(ws + L.r_off + (size_t)k * L.plane_set);
   for (int t = 0; t < T && e == hipSuccess; ++t) {
@@ -1454,15 +1449,13 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
   const bool want_psf = grad_psf != nullptr, want_back = grad_back != nullptr;
 
   std::vector<const float *> phi(V);
-  hipError_t e = launch_zero_f64(acc, (int)(acc_w(c) + V), s);
-  for (int v = 0; v < V && e == hipSuccess; ++v) {
-    if (L.stage) {
-      e = launch_stage_obs(obs[v], r->obs_dtype, r->obs_layout, g, plane(L.phi_off, v), s);
-      phi[v] = plane(L.phi_off, v);
-    } else {
-      phi[v] = static_cast<const float *>(obs[v]);
-    }
+  std::vector<float *> staged(V);
+  for (int v = 0; v < V; ++v) {
+    staged[v] = plane(L.phi_off, v);
+    phi[v] = staged[v];
   }
+  hipError_t e = launch_zero_f64(acc, (int)(acc_w(c) + V), s);
+  if (e == hipSuccess) e = launch_stage_views(obs, V, r->obs_dtype, r->obs_layout, g, staged.data(), nullptr, s);
   int cur = 0;
   if (e == hipSuccess) e = launch_copy(grad_est, plane(L.g_off, 0), n, s);
   const int T = r->n_iters;

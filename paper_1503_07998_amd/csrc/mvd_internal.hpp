@@ -144,6 +144,10 @@ int corr_threads(int kzp, int kxp);
 // Observations → float32 planes.  layout 1 = stack [Z][Y][X], 2 = planes.
 hipError_t launch_stage_obs(const void *src, int dtype, int layout, PlaneGeom g, float *dst,
                             hipStream_t s);
+// Every view's observations → float32 planes dst[v] in one pass, and
+// ψ^0 = (1/V) Σ_v φ_v into `mean` when it is not null.
+hipError_t launch_stage_views(const void *const *src, int nv, int dtype, int layout, PlaneGeom g,
+                              float *const *dst, float *mean, hipStream_t s);
 // ψ^0 = (1/V) Σ_v φ_v
 hipError_t launch_init_mean(const float *const *phis, int nv, size_t n, float *dst,
                             hipStream_t s);
