@@ -216,11 +216,17 @@ struct Item {
   size_t off;
 };
 
+// Items are dealt to lanes in pairs of rows: lane pairs (2p, 2p+1) take the same
+// 8 columns of rows 2q and 2q+1.  The LDS row pitch is 4 (mod 8) floats, so of
+// the 8 lanes that share an LDS cycle, those on the odd row read 16-byte
+// chunks in the bank groups the even-row lanes leave free.
 __device__ __forceinline__ Item item_at(int it, const Loop &st, const Geo &o, int i, KArg *a) {
   Item r;
   const int itc = min(it, st.nitems - 1);
-  r.g = itc / st.nxb;
-  const int xb = itc - r.g * st.nxb;
+  const int pr = itc >> 1;
+  const int gp = pr / st.nxb;
+  const int xb = pr - gp * st.nxb;
+  r.g = 2 * gp + (itc & 1);
   const int z = o.zs + i * G + r.g;
   r.valid = it < st.nitems && z < o.ze;
   r.ox = xb * NX;

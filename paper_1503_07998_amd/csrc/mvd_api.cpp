@@ -405,7 +405,10 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn =
   }
   s.plan.threads = std::min(kSepMaxThreads, round_up((s.ncols + s.plan.cols - 1) / s.plan.cols, 64));
   const int nxb = (s.x_out + 7) / 8;
+  // row pitch ≡ 4 (mod 8) floats: the row pass reads pairs of rows whose
+  // 16-byte chunks then fall in complementary LDS bank groups
   s.ldsw = round_up(nxb * 8 + kb - 1 + 4, 4);
+  if (s.ldsw % 8 == 0) s.ldsw += 4;
   // segments: enough work-groups to fill 256 CUs several times, segments ≥ 32 rows
   const int Z = c->Z;
   const long tiles = (long)Y * s.nstrip;
