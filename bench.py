@@ -26,19 +26,21 @@ HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 # fp32 vector FMA without packed instructions: 256 CUs × 4 SIMDs × 16 lanes ×
 # 2 flop × 2.4 GHz (the library is built with packed FP32 disabled)
 ALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
+MFMA_F32_PEAK = 157.3e12     # dense FP32 matrix-core peak (the general K×K passes)
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def step_work(spec, kind, vox, launches_per_iter):
+def step_work(spec, kind, vox, launches_per_iter, general=False):
     """Algorithmic bytes and flops of one forward / backward launch over
     ``vox`` voxels (a whole volume, or one batch of planes).
 
     Per voxel and view, a forward pass reads φ_v, writes r_v and (once per
     launch) reads ψ; a backward pass reads r_v and (once per launch) reads and
-    writes ψ.  Each view's two 1D passes cost 2 · (kz + kx) flops (FMA = 2).
+    writes ψ.  Each view's two 1D passes cost 2 · (kz + kx) flops (FMA = 2);
+    a general K×K pass costs 2 · kz · kx.
     The library may split the V views of an iteration over several launches,
     so the work of one iteration on those voxels is divided by its launches.
     """
@@ -49,7 +51,7 @@ def step_work(spec, kind, vox, launches_per_iter):
         b = 8 * V + 4 * n
     else:
         b = 4 * V + 8 * n
-    f = V * 2 * (k + k)
+    f = V * 2 * (k * k if general else k + k)
     return vox * b / n, vox * f / n
 
 
@@ -75,33 +77,38 @@ def measured_traffic(name, kind):
     return max(cands, key=lambda v: v.get("trace_calls", 0))["traffic_bytes"]
 
 
-def roofline(spec, kinds):
+def roofline(spec, kinds, general=False):
     """Roofline entry of the kernel with the largest share of the step."""
     dom = max(kinds, key=lambda k: kinds[k]["avg_ms"] * kinds[k]["launches"])
     kd = kinds[dom]
     t_hbm = kd["bytes"] / HBM_PEAK
-    t_alu = kd["flops"] / ALU_PEAK
-    if t_alu >= t_hbm:
+    t_alu = kd["flops"] / (MFMA_F32_PEAK if general else ALU_PEAK)
+    if general:
+        # useful flops only: the banded Toeplitz operands also multiply zeros
+        roof = {"bound": "mfma", "achieved": kd["flops"] / (kd["avg_ms"] / 1e3) / 1e12,
+                "peak": MFMA_F32_PEAK / 1e12, "unit": "TFLOP/s"}
+    elif t_alu >= t_hbm:
         roof = {"bound": "alu", "achieved": kd["flops"] / (kd["avg_ms"] / 1e3) / 1e12,
                 "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": kd["bytes"] / (kd["avg_ms"] / 1e3) / 1e9,
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(spec.name, dom)
-    roof["kernel"] = f"{dom} pass (sep_{dom}_kernel, K={spec.psf_k})"
+    roof["traffic"] = None if general else measured_traffic(spec.name, dom)
+    roof["kernel"] = (f"{dom} pass (twod_{dom}_kernel, general {spec.psf_k}x{spec.psf_k})" if general
+                      else f"{dom} pass (sep_{dom}_kernel, K={spec.psf_k})")
     roof["hbm_frac_algorithmic"] = kd["bytes"] / (kd["avg_ms"] / 1e3) / HBM_PEAK
     return roof
 
 
-def launch_kinds(spec, tim, steps, vox, batches=1):
+def launch_kinds(spec, tim, steps, vox, batches=1, general=False):
     """Per-kind launch statistics of ``steps`` timed runs (HIP events)."""
     kinds = {}
     for kind in ("forward", "backward"):
         n, ms = tim[kind]
         if n:
             per_iter = n / (steps * spec.iters * batches)
-            b, f = step_work(spec, kind, vox / batches, per_iter)
+            b, f = step_work(spec, kind, vox / batches, per_iter, general)
             avg = ms / n / 1e3
             kinds[kind] = dict(launches=n, launches_per_iteration=per_iter, avg_ms=avg * 1e3, bytes=b, flops=f,
                                gbs=b / avg / 1e9, tflops=f / avg / 1e12)
@@ -446,6 +453,8 @@ def main():
     ap.add_argument("--update", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=64, help="planes per streamed batch (vol1024x4)")
+    ap.add_argument("--force-2d", action="store_true",
+                    help="run the general KxK passes even for rank-one PSFs (default workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -489,7 +498,8 @@ def main():
 
     def make(timing):
         return api.make_run(Y, spec.iters, update=spec.update, boundary=spec.boundary,
-                            obs_dtype=obs_dtype, layout=layout, timing=timing, tune=True)
+                            obs_dtype=obs_dtype, layout=layout, timing=timing, tune=not args.force_2d,
+                            force_2d=args.force_2d)
 
     run = make(False)
     nbytes = api.mvd_workspace_bytes(d.ctx, run)
@@ -530,8 +540,8 @@ def main():
     torch.cuda.synchronize()
     ms_plain = (time.perf_counter() - t1) * 1e3 / args.steps
 
-    kinds = launch_kinds(spec, tim, args.steps, Y * Z * X)
-    roof = roofline(spec, kinds)
+    kinds = launch_kinds(spec, tim, args.steps, Y * Z * X, general=args.force_2d)
+    roof = roofline(spec, kinds, general=args.force_2d)
 
     it_ms = sum(kinds[k]["avg_ms"] * kinds[k]["launches"] for k in kinds) / args.steps
     out = {
@@ -552,7 +562,8 @@ def main():
                          f"{spec.psf_k}x{spec.psf_k} Gaussian PSFs (sx={spec.psf_sigma[0]}, "
                          f"sz={spec.psf_sigma[1]}, view 1 rotated 90 deg), {spec.obs_dtype} Poisson "
                          f"observations of blob nuclei, {spec.iters} iterations, {spec.update}, "
-                         f"{spec.boundary} boundary"),
+                         f"{spec.boundary} boundary"
+                         + (", general KxK passes forced (no rank-one split)" if args.force_2d else "")),
             "voxels": spec.voxels, "iterations": spec.iters, "views": spec.n_views,
             "psf": spec.psf_k, "update": spec.update, "parallelism": "single GPU",
         },

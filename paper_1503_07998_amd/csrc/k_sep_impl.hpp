@@ -169,12 +169,13 @@ __device__ __forceinline__ int lds_pitch(KArg *a) {
 
 // Write one z-pass output (row g of the current buffer).  Whole-row strips
 // (no x halo) are planned for the zero boundary only, so their pad columns
-// stay zero; periodic runs use strips whose halo columns were loaded wrapped.
-template <int C, int R>
+// stay zero and every active column lies in the plane; strips with a halo
+// zero the columns outside the plane (zero boundary) or hold wrapped columns.
+template <int C, int R, bool MASK>
 __device__ __forceinline__ void store_mid(float *B, int g, KArg *a, const Cols<C, R> &cl,
                                           int c, float v) {
   if (!cl.act[c]) return;
-  v = cl.ok[c] ? v : 0.f;   // column outside the plane (zero boundary)
+  if (MASK) v = cl.ok[c] ? v : 0.f;   // column outside the plane (zero boundary)
   B[g * lds_pitch(a) + cl.lcol[c]] = v;
 }
 
@@ -293,10 +294,17 @@ __device__ __forceinline__ void zpass(KFloat *tz, const float (&ring)[C][Shape<K
 template <int KB, int C>
 __device__ __forceinline__ void store_group(float *B, KArg *a, const Cols<C, Shape<KB>::R> &cl,
                                             const float (&acc)[C][G]) {
+  if (a->halo == 0) {   // uniform: whole rows need no mask
 #pragma unroll
-  for (int g = 0; g < G; ++g)
+    for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int c = 0; c < C; ++c) store_mid<C, Shape<KB>::R>(B, g, a, cl, c, acc[c][g]);
+      for (int c = 0; c < C; ++c) store_mid<C, Shape<KB>::R, false>(B, g, a, cl, c, acc[c][g]);
+  } else {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < C; ++c) store_mid<C, Shape<KB>::R, true>(B, g, a, cl, c, acc[c][g]);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -336,6 +336,7 @@ struct Tune {
   int fwd_occ = 0, bwd_occ = 0, bwd_vin = 0, zseg = 0, fwd_views = 0;
   int zseg_scale = 0;   // > 0: segment length × 2^(zseg_scale − 2) of the automatic one (2 = as is)
   int cols = 0;         // 1: one column per thread (strips with halo for rows wider than 512)
+  int valu2d = 0;       // 1: general K×K passes on the vector ALUs instead of the matrix cores
 };
 
 const Tune &tune() {
@@ -360,6 +361,7 @@ const Tune &tune() {
         if (k == "fwd_views") r.fwd_views = v;
         if (k == "zseg_scale") r.zseg_scale = v;
         if (k == "cols") r.cols = v;
+        if (k == "valu2d") r.valu2d = v;
       }
       pos = comma + 1;
     }
@@ -540,6 +542,7 @@ hipError_t forward_views(const RunState &st, const float *psi, const float *cons
     a.kz = c->kzm;
     a.kx = c->kxm;
     a.in[0] = psi;
+    a.mfma = st.tn->valu2d ? 0 : 1;
     for (int k = 0; k < nb; ++k) {
       a.phi[k] = phi[b + k];
       a.out[k] = r[b + k];
@@ -607,6 +610,7 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
     a.nviews = nb;
     a.kz = c->kzm;
     a.kx = c->kxm;
+    a.mfma = st.tn->valu2d ? 0 : 1;
     for (int k = 0; k < nb; ++k) {
       a.in[k] = r[b + k];
       a.w[k] = weight_of(st, b + k);
@@ -1399,6 +1403,17 @@ int mvd_internal_sep_plan(const mvd_ctx *c, int n_planes, int k, int boundary, i
   return MVD_OK;
 }
 
+
+// Internal (not in the public header): the matrix-core general pass's plan for a
+// kz × kx kernel, for the host-side bounds model.  out[3]: column steps, input
+// tile row pitch, LDS bytes.
+int mvd_internal_mfma_plan(int kz, int kx, int *out) {
+  if (!out || kz < 1 || kx < 1 || kz > MVD_MAX_K || kx > MVD_MAX_K) return MVD_ERR_ARG;
+  out[0] = mfma_chunks(kx);
+  out[1] = mfma_tile_width(out[0]);
+  out[2] = (int)mfma_lds_bytes(kz, kx);
+  return MVD_OK;
+}
 
 mvd_status mvd_backward_workspace_bytes(const mvd_ctx *cc, const mvd_run *r, size_t *bytes) {
   mvd_ctx *c = const_cast<mvd_ctx *>(cc);

@@ -79,7 +79,25 @@ struct TwoDPassArgs {
   float *psi_out;
   float w[k2dViews];
   const float *taps[k2dViews];        // device [kz][kx] per view
+  int mfma;                            // 1: matrix-core kernels, 0: vector-ALU kernels
 };
+
+// Matrix-core general passes.  Column steps of 4 covering the 16 + kx − 1 input
+// columns of a 16-column block, rounded up to the compiled sizes (extra steps
+// meet zero taps); -1 beyond them.
+__host__ __device__ constexpr int mfma_chunks(int kx) {
+  return (15 + kx + 3) / 4 <= 6 ? 6
+       : (15 + kx + 3) / 4 <= 8 ? 8
+       : (15 + kx + 3) / 4 <= 12 ? 12
+       : (15 + kx + 3) / 4 <= 16 ? 16
+       : (15 + kx + 3) / 4 <= 20 ? 20 : -1;
+}
+// Input-tile row pitch: covers columns up to 48 + 4·nck − 1 and is ≡ 2 (mod 32).
+__host__ __device__ constexpr int mfma_tile_width(int nck) {
+  return 48 + 4 * nck + ((2 - (48 + 4 * nck) % 32) % 32 + 32) % 32;
+}
+// LDS bytes of one work-group (input tile + one view's tap rows).
+size_t mfma_lds_bytes(int kz, int kx);
 
 // Epilogues of the single-input separable pass.
 constexpr int kEpRatio = 0;   // out = φ / conv (guarded)

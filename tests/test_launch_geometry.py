@@ -133,3 +133,43 @@ def test_separable_launch_geometry_in_bounds(shape, k):
     for boundary in ("zero", "periodic"):
         for views in (1, 2):
             check_geometry(Y, Z, X, k, boundary, views)
+
+
+def mfma_plan(kz, kx):
+    out = (ctypes.c_int * 3)()
+    lib = N.lib()
+    lib.mvd_internal_mfma_plan.restype = ctypes.c_int
+    lib.mvd_internal_mfma_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    assert lib.mvd_internal_mfma_plan(kz, kx, out) == 0
+    return out[0], out[1], out[2]
+
+
+@pytest.mark.parametrize("kz", [1, 3, 9, 15, 31, 41, 63])
+def test_matrix_core_general_pass_in_bounds(kz):
+    """Every LDS access of the matrix-core K×K pass (work-group tile 32 × 64,
+    waves at rows 0/16 and columns 0/32, two 16-column blocks each) lies in the
+    staged input tile or the tap rows, and the work-group fits in LDS."""
+    MZ, MX = 32, 64
+    for kx in range(1, 64, 2):
+        nck, tw, lds = mfma_plan(kz, kx)
+        assert nck > 0 and 4 * nck >= 16 + kx - 1, (kx, nck)      # steps cover the band
+        assert tw % 32 == 2
+        th, fl = MZ + kz - 1, 4 * nck + 16
+        assert lds == 4 * (th * tw + kz * fl) <= LDS_LIMIT
+        lane = np.arange(64)
+        n, kk = lane % 16, lane // 16
+        for m0 in (0, 16):
+            for c0 in (0, 32):
+                for c in (0, nck - 1):
+                    for j in (0, kz - 1):
+                        row = m0 + n + j
+                        assert row.max() < th and row.min() >= 0
+                        for blk in (0, 16):
+                            col = c0 + blk + 4 * c + kk
+                            assert col.max() < tw
+                        fidx = j * fl + 16 + kk - n + 4 * c
+                        assert fidx.min() >= j * fl and fidx.max() < (j + 1) * fl
+        # output rows and columns of the accumulators stay in the work-group tile
+        for i in range(4):
+            assert (16 + 4 * (lane // 16) + i).max() < MZ
+        assert (32 + 16 + lane % 16).max() < MX
