@@ -51,7 +51,25 @@ struct Shape {
   static constexpr int M = G * ((2 * G + KB - 1 + G - 1) / G);
   static constexpr int U = M / G;                  // ring phases
   static constexpr int NIN4 = (NX + KB - 1 + 3) / 4;
+  // column pass on the matrix cores: a block of 4 output rows takes input rows
+  // k = 0 … KB + 2 of its window; per view a [4][NK] tap table in LDS
+  static constexpr int NK = (KB + 3 + 3) / 4 * 4;
 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Tap table of the matrix-core column pass: TT[i][k] = tz[i + KB − 1 − k], the
+// tap that input row k of a 4-row block contributes to its output row i (zero
+// off the kernel).  Filled once per work-group; the caller synchronises.
+template <int KB>
+__device__ __forceinline__ void fill_tap_table(float *TT, KArg *a, int nviews, int t, int nt) {
+  constexpr int NK = Shape<KB>::NK;
+  for (int e = t; e < nviews * 4 * NK; e += nt) {
+    const int v = e / (4 * NK), i = (e / NK) % 4, k = e % NK;
+    const int j = i + KB - 1 - k;
+    TT[e] = (j >= 0 && j < KB) ? a->tz[v][j] : 0.f;
+  }
+}
 
 // LDS-only barrier: waits for this wave's LDS traffic, not for its global
 // loads, so the next group's prefetched rows stay in flight across it.
@@ -207,7 +225,8 @@ __device__ __forceinline__ void xconv(const float *L, KFloat *taps, float (&out)
 // Per-work-group constants of a pass.
 struct Loop {
   int t, nt, bufsz, rbase, nxb, nitems;
-  bool vec;   // whole 8-wide items, 16-byte aligned rows: 128-bit loads and stores
+  bool vec;          // whole 8-wide items, 16-byte aligned rows: 128-bit loads and stores
+  const float *tt;   // tap tables of the column pass, [views][4][NK]
 };
 
 // Geometry of one row-pass work item (row g of the group, 8 output columns).
@@ -273,22 +292,45 @@ __device__ __forceinline__ void store8(float *__restrict__ p, int nvalid, bool v
   }
 }
 
-// Column pass of one group for one input ring: G output rows per column.
+// Column pass of one group for one input ring: G output rows per column, on the
+// matrix cores.  v_mfma_f32_4x4x1f32 treats the wave as 16 blocks of 4 lanes:
+// lane 4b + i supplies A[i] and lane 4b + j supplies B[j] of block b, and
+// register i of lane 4b + j receives D[i][j] += A[i]·B[j].  With B = this
+// lane's ring register of input row k (its own column) and A = TT[lane % 4][k],
+// register i of every lane accumulates output row g0 + i of its own column:
+// Σ_k tz[i + KB − 1 − k] · in[g0 + k].  A 4-row block needs input rows
+// k = 0 … KB + 2 only (all in the current group's window), KB + 3 steps against
+// 4·KB multiply-adds on the vector ALUs, which stay free for the row pass.
 template <int KB, int C, int u>
-__device__ __forceinline__ void zpass(KFloat *tz, const float (&ring)[C][Shape<KB>::M], float (&acc)[C][G]) {
-  constexpr int M = Shape<KB>::M;
+__device__ __forceinline__ void zpass(const float *TT, const float (&ring)[C][Shape<KB>::M], float (&acc)[C][G]) {
+  constexpr int M = Shape<KB>::M, NK = Shape<KB>::NK, NB = G / 4;
+  const float *tl = TT + (threadIdx.x & 3) * NK;
+  f32x4 d[C][NB];
 #pragma unroll
-  for (int g = 0; g < G; ++g)
+  for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c][g] = 0.f;
+    for (int b = 0; b < NB; ++b) d[c][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int j = 0; j < KB; ++j) {
-    const float tap = tz[j];
+  for (int kq = 0; kq < NK / 4; ++kq) {
+    const float4 t4 = *reinterpret_cast<const float4 *>(tl + 4 * kq);
+    const float tv[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * kq + e;
+      if (k > KB + 2) continue;
 #pragma unroll
-      for (int c = 0; c < C; ++c) acc[c][g] = fmaf(tap, ring[c][(u * G + g + KB - 1 - j) % M], acc[c][g]);
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          d[c][b] = __builtin_amdgcn_mfma_f32_4x4x1f32(tv[e], ring[c][(u * G + 4 * b + k) % M], d[c][b], 0, 0, 0);
+    }
   }
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[c][4 * b + i] = d[c][b][i];
 }
 
 template <int KB, int C>
@@ -413,7 +455,7 @@ __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, S
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     float acc[C][G];
-    zpass<KB, C, u>(a->tz[v], ring, acc);
+    zpass<KB, C, u>(st.tt + v * 4 * Shape<KB>::NK, ring, acc);
     store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
   }
   lds_sync();
@@ -449,7 +491,10 @@ __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_forward_kernel(const 
   const Cols<C, R> cl(a, o, t, nt);
   if (a->halo == 0) zero_pads<R>(lds, 2 * NV * G, a, t, nt);
   const int nxb = (o.xout + NX - 1) / NX;
-  const Loop st{t, nt, NV * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0};
+  float *tt = lds + 2 * NV * G * a->ldsw;
+  fill_tap_table<KB>(tt, a, NV, t, nt);
+  lds_sync();
+  const Loop st{t, nt, NV * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0, tt};
   const float *__restrict__ src = a->in[0] + o.plane_off;
   float ring[C][M];
 #pragma unroll
@@ -504,7 +549,7 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
 #pragma unroll
   for (int v = 0; v < VIN; ++v) {
     float acc[C][G];
-    zpass<KB, C, u>(a->tz[v], ring[v], acc);
+    zpass<KB, C, u>(st.tt + v * 4 * Shape<KB>::NK, ring[v], acc);
     store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
   }
   lds_sync();
@@ -536,7 +581,10 @@ __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_backward_kernel(const
   const Cols<C, R> cl(a, o, t, nt);
   if (a->halo == 0) zero_pads<R>(lds, 2 * VIN * G, a, t, nt);
   const int nxb = (o.xout + NX - 1) / NX;
-  const Loop st{t, nt, VIN * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0};
+  float *tt = lds + 2 * VIN * G * a->ldsw;
+  fill_tap_table<KB>(tt, a, VIN, t, nt);
+  lds_sync();
+  const Loop st{t, nt, VIN * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0, tt};
   float ring[VIN][C][M];
 #pragma unroll
   for (int v = 0; v < VIN; ++v) {
@@ -548,8 +596,10 @@ __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_backward_kernel(const
     bwd_phases<KB, C, VIN, VM>(a, o, cl, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
 }
 
+// Double-buffered column-pass rows and the column pass's tap tables.
+template <int KB>
 inline size_t lds_bytes(const SepPassArgs &a, int nviews) {
-  return sizeof(float) * 2ull * nviews * G * a.ldsw;
+  return sizeof(float) * (2ull * nviews * G * a.ldsw + (size_t)nviews * 4 * Shape<KB>::NK);
 }
 
 template <typename K>
@@ -571,7 +621,7 @@ inline hipError_t launch_with_lds(K kern, const SepPassArgs &a, int threads, siz
 
 template <int KB, int VM>
 hipError_t forward_bucket_vm(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
-  const size_t lds = lds_bytes(a, a.nviews);
+  const size_t lds = lds_bytes<KB>(a, a.nviews);
   const bool hi = p.occ >= 4;
   if constexpr (KB <= 41) {
     // two columns per thread only where the ring still fits (the planner never asks otherwise)
@@ -598,7 +648,7 @@ hipError_t forward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s)
 // One-view single-input pass with an adjoint epilogue (kStore, kBR, kBbar, kAccum).
 template <int KB, int EP>
 hipError_t single_ep(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
-  const size_t lds = lds_bytes(a, 1);
+  const size_t lds = lds_bytes<KB>(a, 1);
   if constexpr (KB <= 41) {
     if (p.cols == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, EP, 2>, a, p.threads, lds, s);
   }
@@ -621,7 +671,7 @@ hipError_t single_bucket(const SepPassArgs &a, const SepPlan &p, int ep, hipStre
 
 template <int KB, int VM>
 hipError_t backward_bucket_vm(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
-  const size_t lds = lds_bytes(a, p.vin);
+  const size_t lds = lds_bytes<KB>(a, p.vin);
   const bool hi = p.occ >= 4;
   if constexpr (KB <= 41) {
     if (p.vin == 2) return launch_with_lds(sep_backward_kernel<KB, 1, 2, 2, VM>, a, p.threads, lds, s);

@@ -430,6 +430,12 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn =
   return s;
 }
 
+// LDS of one view in a separable pass: double-buffered column-pass rows and the
+// column pass's [4][NK] tap table (NK = bucket + 3 rounded up to 4).
+size_t sep_lds_per_view(const SepGeom &sg) {
+  return sizeof(float) * (2ull * kRowGroup * sg.ldsw + 4ull * ((sg.plan.bucket + 3 + 3) / 4 * 4));
+}
+
 void fill_sep_common(SepPassArgs &a, const SepGeom &s, PlaneGeom g, int boundary) {
   a.g = g;
   a.boundary = boundary;
@@ -510,7 +516,7 @@ hipError_t forward_views(const RunState &st, const float *psi, const float *cons
   if (sep) {
     SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, *st.tn);
     if (st.tn->fwd_occ) sg.plan.occ = st.tn->fwd_occ;
-    const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
+    const size_t per_view = sep_lds_per_view(sg);
     int cap = (int)std::max<size_t>(1, std::min<size_t>(kSepFwdViews, kLdsLimit / per_view));
     if (st.tn->fwd_views > 0) cap = std::min(cap, st.tn->fwd_views);
     for (int b = v0; b < v0 + n; b += cap) {
@@ -567,7 +573,7 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
   const float *cur = psi_in;
   if (sep) {
     SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, *st.tn);
-    const size_t per_view = sizeof(float) * 2ull * kRowGroup * sg.ldsw;
+    const size_t per_view = sep_lds_per_view(sg);
     // Two ratio planes per launch save one read and write of ψ but need two
     // rings (256-VGPR budget); one per launch runs at 4 waves/SIMD and is
     // faster wherever that variant exists (K ≤ 31, one column per thread).
@@ -1399,7 +1405,7 @@ int mvd_internal_sep_plan(const mvd_ctx *c, int n_planes, int k, int boundary, i
   out[9] = sg.ncols;
   out[10] = sg.ldsw;
   out[11] = whole_items(sg, PlaneGeom{n_planes, c->Z, c->X}) ? 1 : 0;
-  out[12] = (int)(sizeof(float) * 2ull * kRowGroup * sg.ldsw);
+  out[12] = (int)sep_lds_per_view(sg);
   return MVD_OK;
 }
 
