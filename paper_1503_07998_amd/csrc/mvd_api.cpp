@@ -337,6 +337,9 @@ struct Tune {
   int zseg_scale = 0;   // > 0: segment length × 2^(zseg_scale − 2) of the automatic one (2 = as is)
   int cols = 0;         // 1: one column per thread (strips with halo for rows wider than 512)
   int valu2d = 0;       // 1: general K×K passes on the vector ALUs instead of the matrix cores
+  int threads = 0;      // > 0: at most this many threads per work-group (64-multiple ≤ 512;
+                        // rows wider than it are split into strips with halos)
+  int bwd_threads = 0;  // the same for two-view backward launches only
 };
 
 const Tune &tune() {
@@ -362,6 +365,8 @@ const Tune &tune() {
         if (k == "zseg_scale") r.zseg_scale = v;
         if (k == "cols") r.cols = v;
         if (k == "valu2d") r.valu2d = v;
+        if (k == "threads") r.threads = v;
+        if (k == "bwd_threads") r.bwd_threads = v;
       }
       pos = comma + 1;
     }
@@ -379,10 +384,12 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn =
   const int X = c->X;
   s.plan.bucket = kb;
   const bool wide_ok = kb <= 41;   // two columns per thread keep the ring in registers
-  const int max_cols = (wide_ok ? 2 : 1) * kSepMaxThreads;
+  int maxt = (tn.threads >= 64 && tn.threads <= kSepMaxThreads) ? tn.threads / 64 * 64 : kSepMaxThreads;
+  maxt = std::max(maxt, std::min(kSepMaxThreads, round_up(2 * R + 64, 64)));   // a strip keeps ≥ 64 outputs
+  const int max_cols = (wide_ok ? 2 : 1) * maxt;
   const bool whole = boundary == MVD_BOUNDARY_ZERO;
-  const bool one_col = tn.cols == 1 || !wide_ok;
-  if (whole && X <= kSepMaxThreads) {
+  const bool one_col = tn.cols == 1 || !wide_ok || maxt < kSepMaxThreads;
+  if (whole && X <= maxt) {
     s.plan.cols = 1;
     s.nstrip = 1;
     s.x_out = X;
@@ -395,17 +402,17 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn =
     s.halo = 0;
     s.ncols = X;
   } else {
-    s.plan.cols = (X + 2 * R <= kSepMaxThreads || one_col) ? 1 : 2;
+    s.plan.cols = (X + 2 * R <= maxt || one_col) ? 1 : 2;
     // outputs per strip: the threads' columns minus the halo, rounded down to
     // whole 8-column items so that rounding the strip width up cannot exceed it
-    const int per = (s.plan.cols * kSepMaxThreads - 2 * R) / 8 * 8;
+    const int per = (s.plan.cols * maxt - 2 * R) / 8 * 8;
     s.nstrip = (X + per - 1) / per;
     s.x_out = round_up((X + s.nstrip - 1) / s.nstrip, 8);
     s.nstrip = (X + s.x_out - 1) / s.x_out;
     s.halo = R;
     s.ncols = s.x_out + 2 * R;
   }
-  s.plan.threads = std::min(kSepMaxThreads, round_up((s.ncols + s.plan.cols - 1) / s.plan.cols, 64));
+  s.plan.threads = std::min(maxt, round_up((s.ncols + s.plan.cols - 1) / s.plan.cols, 64));
   const int nxb = (s.x_out + 7) / 8;
   // row pitch ≡ 4 (mod 8) floats: the row pass reads pairs of rows whose
   // 16-byte chunks then fall in complementary LDS bank groups
@@ -574,13 +581,19 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
   if (sep) {
     SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, *st.tn);
     const size_t per_view = sep_lds_per_view(sg);
-    // Two ratio planes per launch save one read and write of ψ but need two
-    // rings (256-VGPR budget); one per launch runs at 4 waves/SIMD and is
-    // faster wherever that variant exists (K ≤ 31, one column per thread).
-    bool two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit &&
-               sg.plan.occ < 4;
+    // Two ratio planes per launch save one read and write of ψ (16 instead of
+    // 24 B per voxel for two views) but need two rings (256-VGPR budget, 2
+    // waves/SIMD).  With the column pass on the matrix cores the vector ALUs
+    // only run the row pass, and the saved traffic wins (vol512: 0.653 ms for
+    // both views against 2 × 0.341); the tuner still tries one per launch.
+    const bool can_two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit;
+    bool two = can_two;
     if (st.tn->bwd_vin == 1) two = false;
-    if (st.tn->bwd_vin == 2) two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit;
+    if (two && st.tn->bwd_threads > 0) {   // narrower work-groups: more of them per CU
+      Tune nt = *st.tn;
+      nt.threads = st.tn->bwd_threads;
+      sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, nt);
+    }
     sg.plan.vin = two ? 2 : 1;
     if (two) sg.plan.occ = 2;   // two rings: 256-VGPR budget
     if (st.tn->bwd_occ) sg.plan.occ = st.tn->bwd_occ;
@@ -1039,7 +1052,7 @@ std::vector<Tune> tune_candidates() {
   std::vector<Tune> c(9);
   c[1].fwd_occ = 2;
   c[2].fwd_views = 1;
-  c[3].bwd_vin = 2;
+  c[3].bwd_vin = 1;      // one ratio plane per backward launch
   c[4].zseg_scale = 1;   // segments × 1/2, × 2, × 4, × 8
   c[5].zseg_scale = 3;
   c[6].zseg_scale = 4;
