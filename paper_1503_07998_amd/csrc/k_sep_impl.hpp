@@ -509,20 +509,15 @@ __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_forward_kernel(const 
 template <int KB, int VIN, int VM>
 __device__ __forceinline__ void bwd_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
                                              float (&ps)[NX]) {
-  float prod[NX];
+  // ψ · c_0 · c_1 … applied view by view: the same rounding as one launch per view
 #pragma unroll
   for (int v = 0; v < VIN; ++v) {
     float q[NX];
     xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, a->tx[v], q);
     const float w = a->w[v], w1 = 1.f - w;
 #pragma unroll
-    for (int n = 0; n < NX; ++n) {
-      const float c = fmaf(w, q[n], w1);
-      prod[n] = v == 0 ? c : prod[n] * c;
-    }
+    for (int n = 0; n < NX; ++n) ps[n] *= fmaf(w, q[n], w1);
   }
-#pragma unroll
-  for (int n = 0; n < NX; ++n) ps[n] *= prod[n];
   store8<VM>(a->psi_out + itm.off, itm.nvalid, vec, ps);
 }
 
@@ -533,7 +528,17 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
   constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
   const int i = i0 + u;
   if (i >= o.ngroups) return;
-  // ψ of the first item, then the next group's rows (see fwd_group)
+  // column pass on the matrix cores first, then ψ of the first item, then the
+  // next group's rows: ψ is not live while the rings are busiest, and since
+  // memory loads retire in order the row pass can wait for ψ with the rows
+  // still in flight (the prefetched slots are outside this group's window)
+  float *buf = lds + (i & 1) * st.bufsz;
+#pragma unroll
+  for (int v = 0; v < VIN; ++v) {
+    float acc[C][G];
+    zpass<KB, C, u>(st.tt + v * 4 * Shape<KB>::NK, ring[v], acc);
+    store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
+  }
   const Item first = item_at(st.t, st, o, i, a);
   float ps[NX];
   load8<VM>(a->psi_in + first.off, first.nvalid, st.vec, ps);
@@ -544,13 +549,6 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
     for (int g = 0; g < G; ++g)
       load_row<C, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl,
                      &ring[v][0][((u + 1) * G + KB - 1 + g) % M], M);
-  }
-  float *buf = lds + (i & 1) * st.bufsz;
-#pragma unroll
-  for (int v = 0; v < VIN; ++v) {
-    float acc[C][G];
-    zpass<KB, C, u>(st.tt + v * 4 * Shape<KB>::NK, ring[v], acc);
-    store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
   }
   lds_sync();
   if (first.valid) bwd_epilogue<KB, VIN, VM>(a, buf, first, st.vec, ps);
