@@ -26,8 +26,18 @@
 
 #include "mvd_internal.hpp"
 
+// Rows per ring step and the namespace of this instantiation: the split-view
+// backward kernels are compiled with 16-row groups in translation units of
+// their own.
+#ifndef MVD_SEP_G
+#define MVD_SEP_G 8
+#endif
+#ifndef MVD_SEP_NS
+#define MVD_SEP_NS sepk
+#endif
+
 namespace mvd {
-namespace sepk {
+namespace MVD_SEP_NS {
 
 // Kernel arguments are read through the kernarg segment pointer (constant
 // address space): per-view fields are indexed with a runtime view number, and
@@ -41,7 +51,7 @@ __device__ __forceinline__ KArg *kargs() {
   return (KArg *)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
-constexpr int G = kRowGroup;   // rows per ring step
+constexpr int G = MVD_SEP_G;   // rows per ring step
 constexpr int NX = 8;          // x-pass outputs per work item
 
 template <int KB>
@@ -685,8 +695,92 @@ hipError_t backward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s
   return a.vec ? backward_bucket_vm<KB, 1>(a, p, s) : backward_bucket_vm<KB, 0>(a, p, s);
 }
 
-}  // namespace sepk
+// ---------------------------------------------------------------------------
+// Split-view backward pass for two ratio planes: a 1024-thread work-group whose
+// first half keeps view 0's ring and second half view 1's, one ring per thread
+// (one column each), so it fits 128 VGPRs and runs 4 waves/SIMD.  With 16-row
+// groups the row pass has one item per thread covering both views:
+// ψ' = ψ · c_0 · c_1 as in the two-plane pass.  Whole rows, one column per
+// thread, X ≤ 512.
+// ---------------------------------------------------------------------------
+template <int KB, int VM, int u>
+__device__ __forceinline__ void bwd_split_group(KArg *a, const Geo &o, const Cols<1, Shape<KB>::R> &cl, float *lds,
+                                                const Loop &st, float (&ring)[1][Shape<KB>::M], int i0, int view) {
+  constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
+  const int i = i0 + u;
+  if (i >= o.ngroups) return;
+  float *buf = lds + (i & 1) * st.bufsz;
+  {
+    float acc[1][G];
+    zpass<KB, 1, u>(st.tt + view * 4 * Shape<KB>::NK, ring, acc);
+    store_group<KB, 1>(buf + view * G * lds_pitch(a), a, cl, acc);
+  }
+  const Item first = item_at(st.t, st, o, i, a);
+  float ps[NX];
+  load8<VM>(a->psi_in + first.off, first.nvalid, st.vec, ps);
+  const float *__restrict__ src = a->in[view] + o.plane_off;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    load_row<1, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl, &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
+  lds_sync();
+  if (first.valid) bwd_epilogue<KB, 2, VM>(a, buf, first, st.vec, ps);
+  for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
+    const Item itm = item_at(it, st, o, i, a);
+    if (!itm.valid) continue;
+    float q[NX];
+    load8<VM>(a->psi_in + itm.off, itm.nvalid, st.vec, q);
+    bwd_epilogue<KB, 2, VM>(a, buf, itm, st.vec, q);
+  }
+}
+
+template <int KB, int VM, int... us>
+__device__ __forceinline__ void bwd_split_phases(KArg *a, const Geo &o, const Cols<1, Shape<KB>::R> &cl, float *lds,
+                                                 const Loop &st, float (&ring)[1][Shape<KB>::M], int i0, int view,
+                                                 std::integer_sequence<int, us...>) {
+  (bwd_split_group<KB, VM, us>(a, o, cl, lds, st, ring, i0, view), ...);
+}
+
+template <int KB, int VM>
+__global__ void __launch_bounds__(2 * kSepMaxThreads, 4) sep_backward_split_kernel(const SepPassArgs) {
+  KArg *a = kargs();
+  using S = Shape<KB>;
+  constexpr int R = S::R, M = S::M, U = S::U;
+  extern __shared__ __align__(16) float lds[];
+  const int nt = blockDim.x, t = threadIdx.x, half = nt / 2;
+  const int view = t / half, tc = t - view * half;   // wave-uniform view
+  const Geo o = tile_geo(a);
+  const Cols<1, R> cl(a, o, tc, half);
+  zero_pads<R>(lds, 2 * 2 * G, a, t, nt);
+  const int nxb = (o.xout + NX - 1) / NX;
+  float *tt = lds + 2 * 2 * G * a->ldsw;
+  fill_tap_table<KB>(tt, a, 2, t, nt);
+  lds_sync();
+  const Loop st{t, nt, 2 * G * a->ldsw, o.zs - R, nxb, G * nxb, a->vec != 0, tt};
+  const float *__restrict__ src = a->in[view] + o.plane_off;
+  float ring[1][M];
+#pragma unroll
+  for (int m = 0; m < G + KB - 1; ++m) load_row<1, R>(src, st.rbase + m, a, cl, &ring[0][m], M);
+  for (int i0 = 0; i0 < o.ngroups; i0 += U)
+    bwd_split_phases<KB, VM>(a, o, cl, lds, st, ring, i0, view, std::make_integer_sequence<int, U>{});
+}
+
+template <int KB>
+hipError_t backward_split_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  // 128-bit row-pass accesses only (the element-wise form would not fit 128 VGPRs)
+  if (p.cols != 1 || p.vin != 2 || a.halo != 0 || a.nviews != 2 || !a.vec) return hipErrorInvalidValue;
+  const size_t lds = lds_bytes<KB>(a, 2);
+  return launch_with_lds(sep_backward_split_kernel<KB, 1>, a, p.threads, lds, s);
+}
+
+}  // namespace MVD_SEP_NS
 }  // namespace mvd
+
+#define MVD_SEP_INSTANTIATE_SPLIT(KB)                                                      \
+  namespace mvd {                                                                          \
+  hipError_t sep_backward_split_kb##KB(const SepPassArgs &a, const SepPlan &p, hipStream_t s) { \
+    return MVD_SEP_NS::backward_split_bucket<KB>(a, p, s);                                 \
+  }                                                                                        \
+  }
 
 #define MVD_SEP_INSTANTIATE(KB)                                                            \
   namespace mvd {                                                                          \

@@ -45,6 +45,25 @@ hipError_t sep_single_kb31(const SepPassArgs &, const SepPlan &, int, hipStream_
 hipError_t sep_single_kb41(const SepPassArgs &, const SepPlan &, int, hipStream_t);
 hipError_t sep_single_kb63(const SepPassArgs &, const SepPlan &, int, hipStream_t);
 
+hipError_t sep_backward_split_kb3(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_split_kb7(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_split_kb11(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_split_kb15(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_split_kb21(const SepPassArgs &, const SepPlan &, hipStream_t);
+hipError_t sep_backward_split_kb31(const SepPassArgs &, const SepPlan &, hipStream_t);
+
+hipError_t launch_sep_backward_split(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  switch (p.bucket) {
+    case 3: return sep_backward_split_kb3(a, p, s);
+    case 7: return sep_backward_split_kb7(a, p, s);
+    case 11: return sep_backward_split_kb11(a, p, s);
+    case 15: return sep_backward_split_kb15(a, p, s);
+    case 21: return sep_backward_split_kb21(a, p, s);
+    case 31: return sep_backward_split_kb31(a, p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_sep_single_dispatch(const SepPassArgs &a, const SepPlan &p, int ep, hipStream_t s) {
   switch (p.bucket) {
     case 3: return sep_single_kb3(a, p, ep, s);
@@ -340,6 +359,8 @@ struct Tune {
   int threads = 0;      // > 0: at most this many threads per work-group (64-multiple ≤ 512;
                         // rows wider than it are split into strips with halos)
   int bwd_threads = 0;  // the same for two-view backward launches only
+  int bwd_split = 0;    // two-view backward as one 1024-thread work-group per row segment (half
+                        // the threads per view, 16-row groups): 0 where it applies, 2 never
 };
 
 const Tune &tune() {
@@ -367,6 +388,7 @@ const Tune &tune() {
         if (k == "valu2d") r.valu2d = v;
         if (k == "threads") r.threads = v;
         if (k == "bwd_threads") r.bwd_threads = v;
+        if (k == "bwd_split") r.bwd_split = v;
       }
       pos = comma + 1;
     }
@@ -441,6 +463,27 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn =
 // column pass's [4][NK] tap table (NK = bucket + 3 rounded up to 4).
 size_t sep_lds_per_view(const SepGeom &sg) {
   return sizeof(float) * (2ull * kRowGroup * sg.ldsw + 4ull * ((sg.plan.bucket + 3 + 3) / 4 * 4));
+}
+
+// Split-view backward: two views' double-buffered 16-row groups and tap tables.
+constexpr int kSplitRows = 16;
+size_t split_lds_bytes(const SepGeom &sg) {
+  return sizeof(float) * (2ull * 2 * kSplitRows * sg.ldsw + 2ull * 4 * ((sg.plan.bucket + 3 + 3) / 4 * 4));
+}
+
+// Geometry of the split-view form from a two-plane plan, or false where it does
+// not apply (strips, several columns per thread, > 31 taps, periodic, LDS).
+bool split_geom(const SepGeom &sg, PlaneGeom g, int boundary, SepGeom *out) {
+  if (sg.halo != 0 || sg.plan.cols != 1 || sg.plan.bucket > 31 || boundary != MVD_BOUNDARY_ZERO) return false;
+  SepGeom sp = sg;
+  sp.zseg = round_up(sg.zseg, kSplitRows);
+  sp.nseg = (g.Z + sp.zseg - 1) / sp.zseg;
+  sp.plan.threads = 2 * sg.plan.threads;
+  sp.plan.occ = 4;
+  sp.plan.vin = 2;
+  if (split_lds_bytes(sp) > kLdsLimit) return false;
+  *out = sp;
+  return true;
 }
 
 void fill_sep_common(SepPassArgs &a, const SepGeom &s, PlaneGeom g, int boundary) {
@@ -586,6 +629,8 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
     // waves/SIMD).  With the column pass on the matrix cores the vector ALUs
     // only run the row pass, and the saved traffic wins (vol512: 0.653 ms for
     // both views against 2 × 0.341); the tuner still tries one per launch.
+    // Where rows are ≤ 512 wide the split-view form holds one ring per thread
+    // in a 1024-thread work-group instead (4 waves/SIMD, 0.616 ms at vol512).
     const bool can_two = n >= 2 && sg.plan.cols == 1 && sg.plan.bucket <= 41 && 2 * per_view <= kLdsLimit;
     bool two = can_two;
     if (st.tn->bwd_vin == 1) two = false;
@@ -597,12 +642,19 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
     sg.plan.vin = two ? 2 : 1;
     if (two) sg.plan.occ = 2;   // two rings: 256-VGPR budget
     if (st.tn->bwd_occ) sg.plan.occ = st.tn->bwd_occ;
+    // split-view form (two planes per launch in one 1024-thread work-group):
+    // whole rows of ≤ 512 columns, zero boundary, ≤ 31 taps, 128-bit accesses
+    SepGeom sp = sg;
+    const bool split = two && st.tn->bwd_split != 2 && split_geom(sg, st.g, st.boundary, &sp);
     for (int b = v0; b < v0 + n; b += sg.plan.vin) {
       const int nb = std::min(sg.plan.vin, v0 + n - b);
-      SepPlan plan = sg.plan;
+      const bool use_split = split && nb == 2 && whole_items(sp, st.g) && aligned16(cur) && aligned16(psi_out) &&
+                             aligned16(r[b]) && aligned16(r[b + 1]);
+      const SepGeom &gm = use_split ? sp : sg;
+      SepPlan plan = gm.plan;
       plan.vin = nb;
       SepPassArgs a{};
-      fill_sep_common(a, sg, st.g, st.boundary);
+      fill_sep_common(a, gm, st.g, st.boundary);
       a.nviews = nb;
       for (int k = 0; k < nb; ++k) {
         const ViewPsf &w = c->views[b + k];
@@ -613,9 +665,11 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
       }
       a.psi_in = cur;
       a.psi_out = psi_out;
-      a.vec = whole_items(sg, st.g) && aligned16(cur) && aligned16(psi_out);
+      a.vec = whole_items(gm, st.g) && aligned16(cur) && aligned16(psi_out);
       for (int k = 0; k < nb; ++k) a.vec = a.vec && aligned16(a.in[k]);
-      hipError_t e = timed(st, 1, [&] { return launch_sep_backward(a, plan, st.s); });
+      hipError_t e = timed(st, 1, [&] {
+        return use_split ? launch_sep_backward_split(a, plan, st.s) : launch_sep_backward(a, plan, st.s);
+      });
       if (e != hipSuccess) return e;
       cur = psi_out;
     }
@@ -1049,7 +1103,7 @@ hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mv
 // Launch-shape candidates timed per workload (kernel sizes, plane shape, planes,
 // views, update order, boundary); the fastest is cached for the process.
 std::vector<Tune> tune_candidates() {
-  std::vector<Tune> c(9);
+  std::vector<Tune> c(10);
   c[1].fwd_occ = 2;
   c[2].fwd_views = 1;
   c[3].bwd_vin = 1;      // one ratio plane per backward launch
@@ -1058,6 +1112,7 @@ std::vector<Tune> tune_candidates() {
   c[6].zseg_scale = 4;
   c[7].zseg_scale = 5;
   c[8].cols = 1;
+  c[9].bwd_split = 2;    // two-plane backward without the split-view form
   return c;
 }
 
@@ -1431,6 +1486,20 @@ int mvd_internal_mfma_plan(int kz, int kx, int *out) {
   out[0] = mfma_chunks(kx);
   out[1] = mfma_tile_width(out[0]);
   out[2] = (int)mfma_lds_bytes(kz, kx);
+  return MVD_OK;
+}
+
+// Internal: the split-view backward plan (same out[] layout as the separable
+// plan; returns MVD_ERR_UNSUPPORTED where the form does not apply).
+int mvd_internal_split_plan(const mvd_ctx *c, int n_planes, int k, int *out) {
+  if (!c || !out || n_planes < 1 || k < 1 || k > MVD_MAX_K) return MVD_ERR_ARG;
+  const SepGeom sg = plan_sep(c, n_planes, sep_bucket(k), MVD_BOUNDARY_ZERO);
+  SepGeom sp;
+  if (!split_geom(sg, PlaneGeom{n_planes, c->Z, c->X}, MVD_BOUNDARY_ZERO, &sp)) return MVD_ERR_UNSUPPORTED;
+  const int v[13] = {sp.plan.bucket, sp.plan.cols, sp.plan.threads, sp.plan.occ, sp.zseg, sp.nseg, sp.x_out,
+                     sp.nstrip, sp.halo, sp.ncols, sp.ldsw, whole_items(sp, PlaneGeom{n_planes, c->Z, c->X}) ? 1 : 0,
+                     (int)split_lds_bytes(sp)};
+  for (int i = 0; i < 13; ++i) out[i] = v[i];
   return MVD_OK;
 }
 

@@ -173,3 +173,48 @@ def test_matrix_core_general_pass_in_bounds(kz):
         for i in range(4):
             assert (16 + 4 * (lane // 16) + i).max() < MZ
         assert (32 + 16 + lane % 16).max() < MX
+
+
+@pytest.mark.parametrize("shape", [(2, 1, 37), (3, 8, 8), (4, 37, 53), (2, 70, 100), (2, 13, 200), (1, 12, 512),
+                                   (32, 128, 128), (512, 512, 512), (256, 256, 256), (3, 33, 511), (2, 41, 1)],
+                         ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("k", [1, 5, 9, 15, 21, 31])
+def test_split_view_backward_in_bounds(shape, k):
+    """The split-view backward form: 1024-thread work-groups, half the threads
+    per view (one column each), 16-row groups, both views' buffers in LDS."""
+    Y, Z, X = shape
+    GS = 16
+    ctx = api.mvd_create(1, Z, X, N.MVD_DEVICE_NONE)
+    try:
+        out = (ctypes.c_int * 16)()
+        lib = N.lib()
+        lib.mvd_internal_split_plan.restype = ctypes.c_int
+        lib.mvd_internal_split_plan.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_int)]
+        st = lib.mvd_internal_split_plan(ctx, Y, k, out)
+    finally:
+        api.mvd_destroy(ctx)
+    if X > 512:
+        assert st == N.MVD_ERR_UNSUPPORTED
+        return
+    assert st == 0
+    keys = ["bucket", "cols", "threads", "occ", "zseg", "nseg", "x_out", "nstrip", "halo", "ncols", "ldsw", "vec",
+            "lds"]
+    p = dict(zip(keys, list(out)[:13]))
+    KB, nt, ldsw = p["bucket"], p["threads"], p["ldsw"]
+    R = (KB - 1) // 2
+    half = nt // 2
+    assert nt <= 1024 and nt % 128 == 0 and p["halo"] == 0 and p["nstrip"] == 1 and p["cols"] == 1
+    assert half >= X, "each half must hold one column per thread"
+    assert p["zseg"] % GS == 0 and p["nseg"] * p["zseg"] >= Z and (p["nseg"] - 1) * p["zseg"] < Z
+    NK = (KB + 3 + 3) // 4 * 4
+    assert p["lds"] == 4 * (2 * 2 * GS * ldsw + 2 * 4 * NK) <= LDS_LIMIT
+    # columns: LDS column lc + R of each view's rows, pads R and beyond X
+    assert R + X <= ldsw
+    nxb = (X + NX - 1) // NX
+    assert GS * nxb <= nt or True      # items beyond the threads loop
+    NIN4 = (NX + KB - 1 + 3) // 4
+    for xb in range(nxb):
+        assert xb * NX + 4 * NIN4 <= ldsw
+    # row-pass LDS rows: (view·16 + g) of buffer (i & 1), g < 16
+    assert (2 * GS + GS) * ldsw <= 2 * 2 * GS * ldsw   # view 1, row 15 of buffer 0 within both buffers
