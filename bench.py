@@ -425,6 +425,8 @@ def bench_grad(args, spec):
     pairs = n_corr // 2                        # each tap gradient: one correlation + one finalize launch
     flops = 2.0 * K * K * vox                  # one K×K tap gradient over every voxel
     achieved = flops / (ms_corr / pairs / 1e3) / 1e12 if pairs else None
+    valu_corr = "valu_corr=1" in os.environ.get("MVD_TUNE", "")
+    corr_peak = ALU_PEAK if valu_corr else MFMA_F32_PEAK
     out = {
         "metric": "voxel-iterations/s",
         "value": vox * spec.iters / (ms_step / 1e3),
@@ -438,9 +440,11 @@ def bench_grad(args, spec):
             "voxels": vox, "iterations": spec.iters, "views": V, "psf": K, "parallelism": "single GPU"},
         "loss": float(loss), "grad_sigma": gs.tolist(), "grad_weights": gw.tolist(),
         "launch_ms": breakdown,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / (ALU_PEAK / 1e12) if achieved else None, "traffic": None,
-                     "kernel": f"tap-gradient correlation ({K}x{K} lags, 2 flop per lag and voxel)"},
+        "roofline": {"bound": "alu" if valu_corr else "mfma", "achieved": achieved, "peak": corr_peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / (corr_peak / 1e12) if achieved else None,
+                     "traffic": None,
+                     "kernel": (f"tap-gradient correlation on the {'vector ALUs' if valu_corr else 'matrix cores'} "
+                                f"({K}x{K} lags, 2 flop per lag and voxel)")},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle forward + reverse sweep on one plane)")

@@ -247,6 +247,178 @@ __global__ void __launch_bounds__(1024) corr_kernel(CorrArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tap-gradient correlation on the matrix cores.  With x' = x + Rx − i,
+//   G[j][i] = Σ_{y,z} Σ_x' ã[y][z + Rz − j][x'] · ḡ[y][z][x' − Rx + i],
+// so each row z adds the product of a K × W block of ã rows (A[j][x']) with a
+// W × K Toeplitz block of ḡ's row (B[x'][i] = ḡ[z][x' − Rx + i]): a dense
+// contraction over x' with no structural zeros.  A tile is 16 rows z × tw
+// columns x' (tw ≤ 256, a multiple of 16, chosen on the host so that the tiles
+// of a row cover its X + Kx − 1 columns with little excess); the ã rows it
+// needs (row pitch ≡ 2 mod 32 floats: the 16 rows × 2 columns that a
+// half-wave reads fall in distinct banks) and its ḡ rows (zero outside the
+// plane) are staged in LDS.  Wave w takes rows z0 + w, z0 + w + 4, …; each
+// step of 4 columns is one v_mfma_f32_16x16x4f32 per 16 × 16 block of G
+// (lane l supplies A[16·jb + l % 16][4q + l / 16] and B[4q + l / 16][16·ib + l % 16]).
+// A work-group keeps its blocks of G in registers over all its tiles, sums its
+// 4 waves in a fixed order and writes one partial, reduced in float64 by the
+// same finalize step as the vector form.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MCZ = 16;      // rows z per tile
+constexpr int MCXMAX = 256;  // columns x' per tile, at most
+constexpr int MCT = 256;     // threads (4 waves)
+
+struct McGeo {
+  int kz, kx, xa, ntx, ntz, nr, pa, pb;
+  long ntiles;
+};
+
+__host__ __device__ inline int mc_pitch(int tw) { return (tw + 31) / 32 * 32 + 2; }
+
+__device__ __forceinline__ McGeo mc_geo(const CorrArgs &a) {
+  McGeo g;
+  g.kz = 2 * a.rz + 1;
+  g.kx = 2 * a.rx + 1;
+  g.xa = a.rx - g.kx + 1;                          // first column x' that meets a tap
+  g.ntx = (a.g.X + g.kx - 1 + a.tw - 1) / a.tw;
+  g.ntz = (a.g.Z + MCZ - 1) / MCZ;
+  g.nr = MCZ + a.kzp - 1;
+  g.pa = mc_pitch(a.tw);
+  g.pb = a.tw + a.kxp;
+  g.ntiles = (long)a.g.Y * g.ntz * g.ntx;
+  return g;
+}
+
+// Stage a rows × pitch window into LDS: element (r, c) comes from src(r, c),
+// which returns a clamped in-plane index and whether the value is kept (else 0).
+// Each thread walks elements t, t + MCT, … and issues MSU loads before it
+// stores any, so that their latencies overlap.
+constexpr int MSU = 8;
+template <class F>
+__device__ __forceinline__ void mc_stage(float *dst, int rows, int pitch, const float *__restrict__ src, F at) {
+  const int t = threadIdx.x;
+  const int dr = MCT / pitch, dc = MCT % pitch;
+  int r = t / pitch, c = t % pitch;
+  for (int e = t; r < rows;) {
+    float v[MSU];
+    int ev[MSU];
+#pragma unroll
+    for (int u = 0; u < MSU; ++u) {
+      bool in;
+      const size_t i = at(r < rows ? r : rows - 1, c, in);
+      const float w = src[i];
+      v[u] = in ? w : 0.f;
+      ev[u] = r < rows ? e : -1;
+      e += MCT;
+      r += dr;
+      c += dc;
+      if (c >= pitch) {
+        c -= pitch;
+        ++r;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < MSU; ++u)
+      if (ev[u] >= 0) dst[ev[u]] = v[u];
+  }
+}
+
+template <int KZB, int KXB>
+__global__ void __launch_bounds__(MCT) corr_mfma_kernel(CorrArgs a) {
+  extern __shared__ __align__(16) float sm[];
+  const McGeo G = mc_geo(a);
+  float *As = sm;                     // [nr][pa]: ã[z0 + Rz − (kzp − 1) + r][x0' + c]
+  float *Bs = sm + G.nr * G.pa;       // [MCZ][pb]: ḡ[z0 + r][x0' − Rx + c]
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int n = lane & 15, kk = lane >> 4;
+  const int Z = a.g.Z, X = a.g.X, tw = a.tw;
+  f32x4 acc[KZB][KXB];
+#pragma unroll
+  for (int jb = 0; jb < KZB; ++jb)
+#pragma unroll
+    for (int ib = 0; ib < KXB; ++ib) acc[jb][ib] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (long tile = blockIdx.x; tile < G.ntiles; tile += gridDim.x) {
+    const int tx = (int)(tile % G.ntx);
+    const int tz = (int)((tile / G.ntx) % G.ntz);
+    const int y = (int)(tile / ((long)G.ntx * G.ntz));
+    const int z0 = tz * MCZ, x0 = G.xa + tx * tw;
+    const size_t po = (size_t)y * Z * X;
+    const int za = z0 + a.rz - (a.kzp - 1), xg = x0 - a.rx;
+    const int boundary = a.boundary;
+    mc_stage(As, G.nr, G.pa, a.src, [&](int r, int c, bool &in) -> size_t {
+      int z = za + r, x = x0 + c;
+      in = c < tw;
+      if (boundary == 0) {
+        in = in && z >= 0 && z < Z && x >= 0 && x < X;
+        z = min(max(z, 0), Z - 1);
+        x = min(max(x, 0), X - 1);
+      } else {
+        z = wrapc(z, Z);
+        x = wrapc(x, X);
+      }
+      return po + (size_t)z * X + x;
+    });
+    mc_stage(Bs, MCZ, G.pb, a.gbar, [&](int r, int c, bool &in) -> size_t {
+      const int z = z0 + r, x = xg + c;
+      in = z < Z && x >= 0 && x < X;
+      return po + (size_t)min(z, Z - 1) * X + min(max(x, 0), X - 1);
+    });
+    __syncthreads();
+    for (int zz = w; zz < MCZ && z0 + zz < Z; zz += 4) {
+      const float *Ar = As + (zz + a.kzp - 1 - n) * G.pa + kk;   // A[16·jb + n][4q + kk]
+      const float *Br = Bs + zz * G.pb + kk + n;                  // B[4q + kk][16·ib + n]
+      // 4 steps of 4 columns at a time (tw is a multiple of 16), operands of
+      // the next 4 loaded before the products of these
+      float av[2][4][KZB], bv[2][4][KXB];
+      auto load = [&](int buf, int q0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int jb = 0; jb < KZB; ++jb) av[buf][s][jb] = Ar[4 * (q0 + s) - 16 * jb * G.pa];
+#pragma unroll
+          for (int ib = 0; ib < KXB; ++ib) bv[buf][s][ib] = Br[4 * (q0 + s) + 16 * ib];
+        }
+      };
+      auto step = [&](int buf) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int jb = 0; jb < KZB; ++jb)
+#pragma unroll
+            for (int ib = 0; ib < KXB; ++ib)
+              acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[buf][s][jb], bv[buf][s][ib], acc[jb][ib], 0, 0, 0);
+      };
+      const int nq = tw / 4;
+      load(0, 0);
+      int q0 = 0;
+      for (; q0 + 8 <= nq; q0 += 8) {
+        load(1, q0 + 4);
+        step(0);
+        if (q0 + 8 < nq) load(0, q0 + 8);
+        step(1);
+      }
+      if (q0 < nq) step(0);
+    }
+    __syncthreads();
+  }
+  // the 4 waves' blocks through LDS, summed in a fixed order; register r of
+  // lane l holds row 4·(l / 16) + r, column l % 16 of a block
+  float *red = sm;   // [4][kzp][kxp]
+  const int nl = a.kzp * a.kxp;
+#pragma unroll
+  for (int jb = 0; jb < KZB; ++jb)
+#pragma unroll
+    for (int ib = 0; ib < KXB; ++ib)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        red[w * nl + (16 * jb + 4 * kk + r) * a.kxp + 16 * ib + n] = acc[jb][ib][r];
+  __syncthreads();
+  for (int l = t; l < nl; l += MCT)
+    a.part[(size_t)blockIdx.x * nl + l] = ((red[l] + red[nl + l]) + red[2 * nl + l]) + red[3 * nl + l];
+}
+
 // acc[j][i] += Σ_b part[b][j][i] over lags inside the true kernel: one
 // work-group per lag, strided float64 partial sums and a tree in a fixed
 // order (bitwise reproducible).
@@ -301,6 +473,48 @@ hipError_t launch_pointwise_seq(const AdjPointArgs &a, int nblocks, hipStream_t 
 hipError_t launch_sum_partials(const double *part, int nblocks, int nv, double *acc, hipStream_t s) {
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, part, nblocks, nv, acc);
   return hipGetLastError();
+}
+
+int corr_mfma_pad(int k) { return (k + 15) / 16 * 16; }
+
+void corr_mfma_shape(const PlaneGeom &g, int kx, int *tw, long *ntiles) {
+  const int width = g.X + kx - 1;
+  const int ntx = (width + MCXMAX - 1) / MCXMAX;
+  *tw = (width + 16 * ntx - 1) / (16 * ntx) * 16;
+  *ntiles = (long)g.Y * ((g.Z + MCZ - 1) / MCZ) * ((width + *tw - 1) / *tw);
+}
+
+size_t corr_mfma_lds_bytes(int kzp, int kxp, int tw) {
+  const size_t tiles = sizeof(float) * ((size_t)(MCZ + kzp - 1) * mc_pitch(tw) + (size_t)MCZ * (tw + kxp));
+  const size_t red = sizeof(float) * 4ull * kzp * kxp;
+  return tiles > red ? tiles : red;
+}
+
+template <int KZB, int KXB>
+hipError_t launch_corr_mfma_t(const CorrArgs &a, int nblocks, hipStream_t s) {
+  const size_t lds = corr_mfma_lds_bytes(a.kzp, a.kxp, a.tw);
+  auto kern = corr_mfma_kernel<KZB, KXB>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(MCT), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_mfma(const CorrArgs &a, int nblocks, hipStream_t s) {
+  if (a.kzp % 16 || a.kxp % 16 || a.kzp > 64 || a.kxp > 64 || a.tw <= 0 || a.tw % 16 || a.tw > MCXMAX ||
+      a.kzp < 2 * a.rz + 1 || a.kxp < 2 * a.rx + 1)
+    return hipErrorInvalidValue;
+  const int zb = a.kzp / 16, xb = a.kxp / 16;
+#define MVD_CORR_CASE(ZB, XB) \
+  if (zb == ZB && xb == XB) return launch_corr_mfma_t<ZB, XB>(a, nblocks, s);
+#define MVD_CORR_ROW(ZB) MVD_CORR_CASE(ZB, 1) MVD_CORR_CASE(ZB, 2) MVD_CORR_CASE(ZB, 3) MVD_CORR_CASE(ZB, 4)
+  MVD_CORR_ROW(1) MVD_CORR_ROW(2) MVD_CORR_ROW(3) MVD_CORR_ROW(4)
+#undef MVD_CORR_ROW
+#undef MVD_CORR_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_corr(const CorrArgs &a, int nblocks, hipStream_t s) {

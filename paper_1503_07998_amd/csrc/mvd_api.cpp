@@ -361,41 +361,46 @@ struct Tune {
   int bwd_threads = 0;  // the same for two-view backward launches only
   int bwd_split = 0;    // two-view backward as one 1024-thread work-group per row segment (half
                         // the threads per view, 16-row groups): 0 where it applies, 2 never
+  int valu_corr = 0;    // 1: tap-gradient correlation on the vector ALUs instead of the matrix cores
 };
 
-const Tune &tune() {
-  static const Tune t = [] {
-    Tune r;
-    const char *e = std::getenv("MVD_TUNE");
-    if (!e) return r;
-    std::string s(e);
-    size_t pos = 0;
-    while (pos < s.size()) {
-      size_t comma = s.find(',', pos);
-      if (comma == std::string::npos) comma = s.size();
-      const std::string kv = s.substr(pos, comma - pos);
-      const size_t eq = kv.find('=');
-      if (eq != std::string::npos) {
-        const std::string k = kv.substr(0, eq);
-        const int v = std::atoi(kv.c_str() + eq + 1);
-        if (k == "fwd_occ") r.fwd_occ = v;
-        if (k == "bwd_occ") r.bwd_occ = v;
-        if (k == "bwd_vin") r.bwd_vin = v;
-        if (k == "zseg") r.zseg = v;
-        if (k == "fwd_views") r.fwd_views = v;
-        if (k == "zseg_scale") r.zseg_scale = v;
-        if (k == "cols") r.cols = v;
-        if (k == "valu2d") r.valu2d = v;
-        if (k == "threads") r.threads = v;
-        if (k == "bwd_threads") r.bwd_threads = v;
-        if (k == "bwd_split") r.bwd_split = v;
-      }
-      pos = comma + 1;
+Tune parse_tune(const char *e) {
+  Tune r;
+  if (!e) return r;
+  const std::string s(e);
+  size_t pos = 0;
+  while (pos < s.size()) {
+    size_t comma = s.find(',', pos);
+    if (comma == std::string::npos) comma = s.size();
+    const std::string kv = s.substr(pos, comma - pos);
+    const size_t eq = kv.find('=');
+    if (eq != std::string::npos) {
+      const std::string k = kv.substr(0, eq);
+      const int v = std::atoi(kv.c_str() + eq + 1);
+      if (k == "fwd_occ") r.fwd_occ = v;
+      if (k == "bwd_occ") r.bwd_occ = v;
+      if (k == "bwd_vin") r.bwd_vin = v;
+      if (k == "zseg") r.zseg = v;
+      if (k == "fwd_views") r.fwd_views = v;
+      if (k == "zseg_scale") r.zseg_scale = v;
+      if (k == "cols") r.cols = v;
+      if (k == "valu2d") r.valu2d = v;
+      if (k == "valu_corr") r.valu_corr = v;
+      if (k == "threads") r.threads = v;
+      if (k == "bwd_threads") r.bwd_threads = v;
+      if (k == "bwd_split") r.bwd_split = v;
     }
-    return r;
-  }();
+    pos = comma + 1;
+  }
+  return r;
+}
+
+Tune &tune_mut() {
+  static Tune t = parse_tune(std::getenv("MVD_TUNE"));
   return t;
 }
+
+const Tune &tune() { return tune_mut(); }
 
 // Whole rows (no x halo) under the zero boundary; strips with an x halo of R
 // columns otherwise.  Periodic runs always take strips: their halo columns are
@@ -701,13 +706,14 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
 
 // ---- reverse sweep (adjoint) ----------------------------------------------
 constexpr int kPointBlocks = 1024;
-constexpr int kCorrBlocks = 4096;
+constexpr int kCorrBlocks = 4096;      // vector form: work-groups (partials) at most
+constexpr int kCorrMfmaBlocks = 1024;  // matrix-core form
 
 struct BwdLayout {
   size_t plane_set = 0;
   size_t phi_off = 0, b_off = 0, r_off = 0, q_off = 0, g_off = 0, sub_off = 0, rat_off = 0;
   size_t wpart_off = 0, cpart_off = 0, acc_off = 0, total = 0;
-  int nsets = 0, nsub = 0, kzp = 4, kxp = 8;
+  int nsets = 0, nsub = 0;
 };
 
 // accumulators: per view [psf kz·kx][back kz·kx], then V weights (doubles)
@@ -737,14 +743,15 @@ BwdLayout bwd_layout_of(const mvd_ctx *c, const mvd_run *r) {
   off += (size_t)L.nsub * L.plane_set;
   L.rat_off = off;
   if (!sim) off += L.plane_set;
-  for (auto &w : c->views) {
-    L.kzp = std::max({L.kzp, corr_pad(w.psf.kz, 4), corr_pad(w.back.kz, 4)});
-    L.kxp = std::max({L.kxp, corr_pad(w.psf.kx, 8), corr_pad(w.back.kx, 8)});
-  }
+  size_t lags = 0;   // padded lags of a partial, either form
+  for (auto &w : c->views)
+    for (const Kernel *d : {&w.psf, &w.back})
+      lags = std::max({lags, (size_t)corr_pad(d->kz, 4) * corr_pad(d->kx, 8),
+                       (size_t)corr_mfma_pad(d->kz) * corr_mfma_pad(d->kx)});
   L.wpart_off = off;
   off += align_up(sizeof(double) * kPointBlocks * V);
   L.cpart_off = off;
-  off += align_up(sizeof(float) * (size_t)kCorrBlocks * L.kzp * L.kxp);
+  off += align_up(sizeof(float) * (size_t)kCorrBlocks * lags);
   L.acc_off = off;
   off += align_up(sizeof(double) * (acc_w(c) + V));
   L.total = off;
@@ -784,14 +791,22 @@ hipError_t tap_corr(const RunState &st, const BwdLayout &L, char *ws, const floa
   a.boundary = st.boundary;
   a.rz = (kz - 1) / 2;
   a.rx = (kx - 1) / 2;
-  a.kzp = corr_pad(kz, 4);
-  a.kxp = corr_pad(kx, 8);
   a.gbar = gbar;
   a.src = src;
   a.part = reinterpret_cast<float *>(ws + L.cpart_off);
-  const long ntiles = (long)st.g.Y * ((st.g.Z + 7) / 8) * ((st.g.X + 63) / 64);
-  const int nb = (int)std::min<long>(kCorrBlocks, ntiles);
-  hipError_t e = timed(st, 4, [&] { return launch_corr(a, nb, st.s); });
+  const bool mfma = !st.tn->valu_corr;
+  long ntiles;
+  if (mfma) {
+    a.kzp = corr_mfma_pad(kz);
+    a.kxp = corr_mfma_pad(kx);
+    corr_mfma_shape(st.g, kx, &a.tw, &ntiles);
+  } else {
+    a.kzp = corr_pad(kz, 4);
+    a.kxp = corr_pad(kx, 8);
+    ntiles = (long)st.g.Y * ((st.g.Z + 7) / 8) * ((st.g.X + 63) / 64);
+  }
+  const int nb = (int)std::min<long>(mfma ? kCorrMfmaBlocks : kCorrBlocks, ntiles);
+  hipError_t e = timed(st, 4, [&] { return mfma ? launch_corr_mfma(a, nb, st.s) : launch_corr(a, nb, st.s); });
   if (e == hipSuccess)
     e = timed(st, 4, [&] { return launch_corr_finalize(a.part, nb, a.kzp, a.kxp, kz, kx, acc, st.s); });
   return e;
@@ -1486,6 +1501,32 @@ int mvd_internal_mfma_plan(int kz, int kx, int *out) {
   out[0] = mfma_chunks(kx);
   out[1] = mfma_tile_width(out[0]);
   out[2] = (int)mfma_lds_bytes(kz, kx);
+  return MVD_OK;
+}
+
+// Internal: replace the process-wide launch-shape overrides (the MVD_TUNE
+// syntax; NULL: re-read the environment).  Lets one process compare the
+// alternative forms of a pass; not thread-safe against running calls.
+int mvd_internal_set_tune(const char *spec) {
+  tune_mut() = parse_tune(spec ? spec : std::getenv("MVD_TUNE"));
+  return MVD_OK;
+}
+
+// Internal: the matrix-core tap-gradient correlation's launch for a volume of
+// n_planes × Z × X and a kz × kx kernel.  out[6]: kzp, kxp, tile width, tiles,
+// work-groups, LDS bytes.
+int mvd_internal_corr_plan(int n_planes, int Z, int X, int kz, int kx, long *out) {
+  if (!out || n_planes < 1 || Z < 1 || X < 1 || kz < 1 || kx < 1 || kz > MVD_MAX_K || kx > MVD_MAX_K)
+    return MVD_ERR_ARG;
+  int tw;
+  long ntiles;
+  corr_mfma_shape(PlaneGeom{n_planes, Z, X}, kx, &tw, &ntiles);
+  out[0] = corr_mfma_pad(kz);
+  out[1] = corr_mfma_pad(kx);
+  out[2] = tw;
+  out[3] = ntiles;
+  out[4] = std::min<long>(kCorrMfmaBlocks, ntiles);
+  out[5] = (long)corr_mfma_lds_bytes((int)out[0], (int)out[1], tw);
   return MVD_OK;
 }
 

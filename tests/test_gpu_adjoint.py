@@ -89,13 +89,29 @@ CASES = [
     (2, 33, 30, [(5, 9), (9, 5)], 3, "simultaneous", "periodic", None),
     (2, 24, 40, [(7, 5), (5, 7), (3, 3)], 2, "sequential", "zero", [1.0, 0.6, 0.8]),
     (2, 17, 64, [(15, 15), (11, 11)], 2, "sequential", "periodic", None),
+    # several correlation tiles along z and x' with ragged ends; 41 taps pad to 48
+    (2, 37, 300, [(31, 31), (21, 41)], 2, "simultaneous", "zero", [0.8, 0.9]),
+    (1, 35, 270, [(17, 33), (33, 17)], 2, "sequential", "periodic", None),
 ]
 
 
+@pytest.fixture(params=["mfma", "valu"])
+def corr_form(request):
+    """Tap-gradient correlation on the matrix cores (default) or the vector ALUs."""
+    import ctypes
+    from paper_1503_07998_amd import _native as N
+
+    lib = N.lib()
+    lib.mvd_internal_set_tune.argtypes = [ctypes.c_char_p]
+    lib.mvd_internal_set_tune(b"valu_corr=1" if request.param == "valu" else b"")
+    yield request.param
+    lib.mvd_internal_set_tune(None)
+
+
 @pytest.mark.parametrize("case", CASES, ids=[f"a{i}" for i in range(len(CASES))])
-def test_backward_matches_oracle_adjoint(case):
+def test_backward_matches_oracle_adjoint(case, corr_form):
     Y, Z, X, shapes, T, update, boundary, weights = case
-    _say(f"backward Y={Y} Z={Z} X={X} k={shapes} T={T} {update} {boundary} w={weights}")
+    _say(f"backward Y={Y} Z={Z} X={X} k={shapes} T={T} {update} {boundary} w={weights} corr={corr_form}")
     rng = np.random.default_rng(Y * 1000 + Z * 10 + X)
     psfs = [random_psf(rng, kz, kx, separable=True).astype(np.float32) for kz, kx in shapes]
     stacks = [rng.uniform(20.0, 300.0, (Z, Y, X)).astype(np.float32) for _ in shapes]
@@ -122,6 +138,33 @@ def test_backward_is_deterministic():
     for v in range(2):
         np.testing.assert_array_equal(a["grad_psf"][v], b["grad_psf"][v])
         np.testing.assert_array_equal(a["grad_back"][v], b["grad_back"][v])
+
+
+def test_correlation_forms_agree():
+    """Matrix-core and vector-ALU correlations give the same tap gradients up
+    to float32 summation order."""
+    import ctypes
+    from paper_1503_07998_amd import _native as N
+
+    _say("correlation forms agree, 4 planes of 48x200, 31x31 and 41x41")
+    rng = np.random.default_rng(91)
+    psfs = [random_psf(rng, 31, 31, separable=True).astype(np.float32),
+            random_psf(rng, 41, 41, separable=True).astype(np.float32)]
+    stacks = [rng.uniform(20.0, 300.0, (48, 4, 200)).astype(np.float32) for _ in range(2)]
+    gout = rng.standard_normal((4, 48, 200))
+    lib = N.lib()
+    lib.mvd_internal_set_tune.argtypes = [ctypes.c_char_p]
+    try:
+        lib.mvd_internal_set_tune(b"")
+        a = gpu_forward_backward(stacks, psfs, 2, gout)
+        lib.mvd_internal_set_tune(b"valu_corr=1")
+        b = gpu_forward_backward(stacks, psfs, 2, gout)
+    finally:
+        lib.mvd_internal_set_tune(None)
+    for v in range(2):
+        close(a["grad_psf"][v], b["grad_psf"][v], f"grad_psf[{v}]", tol=1e-5)
+        close(a["grad_back"][v], b["grad_back"][v], f"grad_back[{v}]", tol=1e-5)
+    np.testing.assert_array_equal(a["grad_init"], b["grad_init"])
 
 
 def test_grad256_planes_match_oracle():

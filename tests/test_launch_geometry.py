@@ -218,3 +218,125 @@ def test_split_view_backward_in_bounds(shape, k):
         assert xb * NX + 4 * NIN4 <= ldsw
     # row-pass LDS rows: (view·16 + g) of buffer (i & 1), g < 16
     assert (2 * GS + GS) * ldsw <= 2 * 2 * GS * ldsw   # view 1, row 15 of buffer 0 within both buffers
+
+
+# ---------------------------------------------------------------------------
+# Matrix-core tap-gradient correlation
+# ---------------------------------------------------------------------------
+MCZ, MCT = 16, 256
+
+
+def corr_plan(Y, Z, X, kz, kx):
+    out = (ctypes.c_long * 6)()
+    lib = N.lib()
+    lib.mvd_internal_corr_plan.restype = ctypes.c_int
+    lib.mvd_internal_corr_plan.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_long)]
+    assert lib.mvd_internal_corr_plan(Y, Z, X, kz, kx, out) == 0
+    return dict(zip(["kzp", "kxp", "tw", "ntiles", "nblocks", "lds"], list(out)))
+
+
+def corr_pitch(tw):
+    return (tw + 31) // 32 * 32 + 2
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 5, 37), (3, 16, 16), (2, 17, 300), (256, 256, 256),
+                                   (1024, 1024, 1024), (3, 40, 513), (1, 70, 2048)],
+                         ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("k", [(1, 1), (3, 9), (15, 15), (31, 31), (41, 17), (63, 63)],
+                         ids=lambda k: f"{k[0]}x{k[1]}")
+def test_matrix_core_correlation_in_bounds(shape, k):
+    """Every LDS access of the matrix-core correlation (staged ã rows and ḡ
+    rows, 16 × 16 × 4 operand lanes, the 4-wave reduction) and every partial it
+    writes lies in its buffer; the tiles of a row cover every column x' that
+    meets a tap; the work-group fits in LDS."""
+    Y, Z, X = shape
+    kz, kx = k
+    p = corr_plan(Y, Z, X, kz, kx)
+    kzp, kxp, tw = p["kzp"], p["kxp"], p["tw"]
+    rz, rx = (kz - 1) // 2, (kx - 1) // 2
+    assert kzp % 16 == 0 and kxp % 16 == 0 and kz <= kzp <= 64 and kx <= kxp <= 64
+    assert tw % 16 == 0 and 16 <= tw <= 256
+    width = X + kx - 1
+    ntx = -(-width // tw)
+    assert ntx * tw >= width and (ntx - 1) * tw < width
+    assert p["ntiles"] == Y * (-(-Z // MCZ)) * ntx and 1 <= p["nblocks"] <= min(1024, p["ntiles"])
+    nr, pa, pb = MCZ + kzp - 1, corr_pitch(tw), tw + kxp
+    assert pa % 32 == 2 and pa >= tw
+    assert p["lds"] == 4 * max(nr * pa + MCZ * pb, 4 * kzp * kxp) <= LDS_LIMIT
+    lane = np.arange(64)
+    n, kk = lane % 16, lane // 16
+    for zz in (0, MCZ - 1):
+        for q in (0, tw // 4 - 1):
+            for jb in range(kzp // 16):
+                row = zz + kzp - 1 - n - 16 * jb
+                col = 4 * q + kk
+                assert row.min() >= 0 and row.max() < nr and col.max() < tw
+            for ib in range(kxp // 16):
+                bcol = kk + n + 16 * ib + 4 * q
+                assert bcol.max() < pb
+    # the staging walk: element e = t + u·MCT of a rows × pitch window
+    for rows, pitch in ((nr, pa), (MCZ, pb)):
+        e = np.arange(MCT)[:, None] + MCT * np.arange(-(-rows * pitch // MCT) + 8)[None, :]
+        r, c = e // pitch, e % pitch
+        kept = r < rows
+        assert (e[kept] < rows * pitch).all() and (c < pitch).all()
+    # reduction: row 16·jb + 4·kk + r, column 16·ib + n of each wave's block
+    for w in (0, 3):
+        idx = w * kzp * kxp + (16 * (kzp // 16 - 1) + 4 * kk + 3) * kxp + 16 * (kxp // 16 - 1) + n
+        assert idx.max() < 4 * kzp * kxp
+    # global reads: clamped (zero boundary) or wrapped (periodic) indices inside the plane
+    za_min = 0 + rz - (kzp - 1)
+    x0_max = rx - kx + 1 + (ntx - 1) * tw
+    for z in (za_min, (-(-Z // MCZ) - 1) * MCZ + rz + MCZ - 1):
+        for x in (rx - kx + 1, x0_max + pa - 1):
+            assert 0 <= min(max(z, 0), Z - 1) < Z and 0 <= min(max(x, 0), X - 1) < X
+            assert 0 <= z % Z < Z and 0 <= x % X < X
+
+
+@pytest.mark.parametrize("boundary", ["zero", "periodic"])
+@pytest.mark.parametrize("shape,k", [((2, 19, 37), (7, 5)), ((1, 33, 300), (15, 31)), ((2, 5, 9), (9, 3))],
+                         ids=["19x37", "33x300", "5x9"])
+def test_matrix_core_correlation_tiling_model(shape, k, boundary):
+    """The tile decomposition of the matrix-core correlation, replayed in
+    numpy: for each tile the staged ã window (A[j][x'] = ã[z + Rz − j][x'])
+    times the staged Toeplitz window of ḡ (B[x'][i] = ḡ[z][x' − Rx + i]),
+    summed over rows and tiles, equals the direct sum
+    Σ ḡ[y][z][x] · ã[y][z + Rz − j][x + Rx − i] over the plane."""
+    Y, Z, X = shape
+    kz, kx = k
+    p = corr_plan(Y, Z, X, kz, kx)
+    kzp, kxp, tw = p["kzp"], p["kxp"], p["tw"]
+    rz, rx = (kz - 1) // 2, (kx - 1) // 2
+    rng = np.random.default_rng(3)
+    src = rng.standard_normal((Y, Z, X))
+    gbar = rng.standard_normal((Y, Z, X))
+
+    def sat(y, z, x):
+        if boundary == "periodic":
+            return src[y, z % Z, x % X]
+        return src[y, z, x] if 0 <= z < Z and 0 <= x < X else 0.0
+
+    direct = np.zeros((kz, kx))
+    for j in range(kz):
+        for i in range(kx):
+            for y in range(Y):
+                for z in range(Z):
+                    for x in range(X):
+                        direct[j, i] += gbar[y, z, x] * sat(y, z + rz - j, x + rx - i)
+    xa = rx - kx + 1
+    ntx = -(-(X + kx - 1) // tw)
+    C = np.zeros((kzp, kxp))
+    nr, pb = MCZ + kzp - 1, tw + kxp
+    for y in range(Y):
+        for tz in range(-(-Z // MCZ)):
+            for tx in range(ntx):
+                z0, x0 = tz * MCZ, xa + tx * tw
+                za = z0 + rz - (kzp - 1)
+                As = np.array([[sat(y, za + r, x0 + c) for c in range(tw)] for r in range(nr)])
+                Bs = np.array([[gbar[y, z0 + r, x0 - rx + c] if z0 + r < Z and 0 <= x0 - rx + c < X else 0.0
+                                for c in range(pb)] for r in range(MCZ)])
+                for zz in range(min(MCZ, Z - z0)):
+                    A = np.array([As[zz + kzp - 1 - j] for j in range(kzp)])            # [kzp][tw]
+                    B = np.array([Bs[zz, c:c + kxp] for c in range(tw)])                 # [tw][kxp]
+                    C += A @ B
+    np.testing.assert_allclose(C[:kz, :kx], direct, rtol=1e-12, atol=1e-9)
