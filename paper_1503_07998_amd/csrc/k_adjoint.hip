@@ -13,6 +13,7 @@
 //  * reductions in a fixed order (deterministic) into float64 accumulators.
 // (Chain rule of the update of Supplementary Note 1 / Note 2 §1.)
 #include "mvd_internal.hpp"
+#include <algorithm>
 
 namespace mvd {
 namespace {
@@ -38,64 +39,114 @@ __device__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// VW consecutive floats at p + i (one 16-byte access when VW = 4).
+template <int VW>
+__device__ __forceinline__ void ldv(const float *p, size_t i, float (&o)[VW]) {
+  if constexpr (VW == 4) {
+    const float4 v = *reinterpret_cast<const float4 *>(p + i);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  } else {
+    o[0] = p[i];
+  }
+}
+
+template <int VW>
+__device__ __forceinline__ void stv(float *p, size_t i, const float (&o)[VW]) {
+  if constexpr (VW == 4)
+    *reinterpret_cast<float4 *>(p + i) = make_float4(o[0], o[1], o[2], o[3]);
+  else
+    p[i] = o[0];
+}
+
+// NV views, VW elements per thread and step (4: every array 16-byte aligned and
+// n a multiple of 4).  Π_{u≠v} c_u is formed as (c_0 ⋯ c_{v−1}) · (c_{v+1} ⋯ c_{NV−1}).
+template <int NV, int VW>
 __global__ void __launch_bounds__(NT) pointwise_sim_kernel(AdjPointArgs a) {
   __shared__ double sh[NT];
-  double wsum[kMaxViews];
-  for (int v = 0; v < kMaxViews; ++v) wsum[v] = 0.0;
-  const int nv = a.nv;
-  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < a.n; i += (size_t)gridDim.x * NT) {
-    const float gin = a.gbar_in[i];
-    const float psi = a.psi[i];
-    float q[kMaxViews], c[kMaxViews];
-    float prod = 1.f;
-    for (int v = 0; v < nv; ++v) {
-      q[v] = a.q[v][i];
-      c[v] = fmaf(a.w[v], q[v], 1.f - a.w[v]);
-      prod *= c[v];
-    }
-    a.gbar_out[i] = gin * prod;
-    const float gp = gin * psi;
-    for (int v = 0; v < nv; ++v) {
-      float others = 1.f;
-      for (int u = 0; u < nv; ++u)
-        if (u != v) others *= c[u];
-      const float cbar = gp * others;
-      wsum[v] += (double)cbar * (double)(q[v] - 1.f);
-      a.q[v][i] = a.w[v] * cbar;
-    }
+  double wsum[NV];
+  float w[NV], w1[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    wsum[v] = 0.0;
+    w[v] = a.w[v];
+    w1[v] = 1.f - w[v];
   }
-  for (int v = 0; v < nv; ++v) {
+  for (size_t i = ((size_t)blockIdx.x * NT + threadIdx.x) * VW; i < a.n; i += (size_t)gridDim.x * NT * VW) {
+    float gin[VW], psi[VW], q[NV][VW], gout[VW];
+    ldv<VW>(a.gbar_in, i, gin);
+    ldv<VW>(a.psi, i, psi);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ldv<VW>(a.q[v], i, q[v]);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      float c[NV], pre[NV + 1];
+      pre[0] = 1.f;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        c[v] = fmaf(w[v], q[v][e], w1[v]);
+        pre[v + 1] = pre[v] * c[v];
+      }
+      gout[e] = gin[e] * pre[NV];
+      const float gp = gin[e] * psi[e];
+      float suf = 1.f;
+#pragma unroll
+      for (int v = NV - 1; v >= 0; --v) {
+        const float cbar = gp * (pre[v] * suf);
+        suf *= c[v];
+        wsum[v] += (double)cbar * (double)(q[v][e] - 1.f);
+        q[v][e] = w[v] * cbar;
+      }
+    }
+    stv<VW>(a.gbar_out, i, gout);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) stv<VW>(a.q[v], i, q[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
     const double s = block_sum(wsum[v], sh);
-    if (threadIdx.x == 0) a.wpart[(size_t)blockIdx.x * nv + v] = s;
+    if (threadIdx.x == 0) a.wpart[(size_t)blockIdx.x * NV + v] = s;
   }
 }
 
 // Sequential update, view v: ψ_{v+1} = ψ_v · c_v.  gbar holds ∂L/∂ψ_{v+1} on
 // entry and the direct term ∂L/∂ψ_v = gbar · c_v on exit; q becomes q̄.
+template <int VW>
 __global__ void __launch_bounds__(NT) pointwise_seq_kernel(AdjPointArgs a) {
   __shared__ double sh[NT];
   double wsum = 0.0;
   const float w = a.w[0], w1 = 1.f - w;
-  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < a.n; i += (size_t)gridDim.x * NT) {
-    const float g = a.gbar_in[i];
-    const float q = a.q[0][i];
-    const float c = fmaf(w, q, w1);
-    const float cbar = g * a.psi[i];
-    a.gbar_out[i] = g * c;
-    wsum += (double)cbar * (double)(q - 1.f);
-    a.q[0][i] = w * cbar;
+  for (size_t i = ((size_t)blockIdx.x * NT + threadIdx.x) * VW; i < a.n; i += (size_t)gridDim.x * NT * VW) {
+    float g[VW], q[VW], psi[VW], go[VW];
+    ldv<VW>(a.gbar_in, i, g);
+    ldv<VW>(a.q[0], i, q);
+    ldv<VW>(a.psi, i, psi);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const float c = fmaf(w, q[e], w1);
+      const float cbar = g[e] * psi[e];
+      go[e] = g[e] * c;
+      wsum += (double)cbar * (double)(q[e] - 1.f);
+      q[e] = w * cbar;
+    }
+    stv<VW>(a.gbar_out, i, go);
+    stv<VW>(a.q[0], i, q);
   }
   const double s = block_sum(wsum, sh);
   if (threadIdx.x == 0) a.wpart[blockIdx.x] = s;
 }
 
-// acc[v] += Σ_b part[b][v] (fixed order), one thread per view.
-__global__ void sum_partials_kernel(const double *__restrict__ part, int nblocks, int nv, double *acc) {
-  const int v = threadIdx.x;
-  if (v >= nv) return;
+// acc[v] += Σ_b part[b][v]: one work-group per view, fixed order.
+__global__ void __launch_bounds__(NT) sum_partials_kernel(const double *__restrict__ part, int nblocks, int nv,
+                                                          double *acc) {
+  __shared__ double sh[NT];
+  const int v = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * nv + v];
-  acc[v] += s;
+  for (int b = threadIdx.x; b < nblocks; b += NT) s += part[(size_t)b * nv + v];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) acc[v] += s;
 }
 
 // ---------------------------------------------------------------------------
@@ -255,7 +306,7 @@ __global__ void __launch_bounds__(1024) corr_kernel(CorrArgs a) {
 // contraction over x' with no structural zeros.  A tile is 16 rows z × tw
 // columns x' (tw ≤ 256, a multiple of 16, chosen on the host so that the tiles
 // of a row cover its X + Kx − 1 columns with little excess); the ã rows it
-// needs (row pitch ≡ 2 mod 32 floats: the 16 rows × 2 columns that a
+// needs (row pitch ≡ 2 mod 4 floats: the 16 rows × 2 columns that a
 // half-wave reads fall in distinct banks) and its ḡ rows (zero outside the
 // plane) are staged in LDS.  Wave w takes rows z0 + w, z0 + w + 4, …; each
 // step of 4 columns is one v_mfma_f32_16x16x4f32 per 16 × 16 block of G
@@ -275,7 +326,7 @@ struct McGeo {
   long ntiles;
 };
 
-__host__ __device__ inline int mc_pitch(int tw) { return (tw + 31) / 32 * 32 + 2; }
+__host__ __device__ inline int mc_pitch(int tw) { return tw + 2; }
 
 __device__ __forceinline__ McGeo mc_geo(const CorrArgs &a) {
   McGeo g;
@@ -460,18 +511,47 @@ size_t corr_lds_bytes(int kzp, int kxp) {
 
 int corr_threads(int kzp, int kxp) { return CTZ * (kzp / LJ) * (kxp / LI); }
 
-hipError_t launch_pointwise_sim(const AdjPointArgs &a, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(pointwise_sim_kernel, dim3(nblocks), dim3(NT), 0, s, a);
+bool point_vec(const AdjPointArgs &a, int nv) {
+  bool ok = a.n % 4 == 0;
+  for (const void *p : {(const void *)a.psi, (const void *)a.gbar_in, (const void *)a.gbar_out})
+    ok = ok && (uintptr_t)p % 16 == 0;
+  for (int v = 0; v < nv; ++v) ok = ok && (uintptr_t)a.q[v] % 16 == 0;
+  return ok;
+}
+
+template <int NV>
+hipError_t launch_sim_nv(const AdjPointArgs &a, int nblocks, hipStream_t s) {
+  if (point_vec(a, NV))
+    hipLaunchKernelGGL((pointwise_sim_kernel<NV, 4>), dim3(nblocks), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((pointwise_sim_kernel<NV, 1>), dim3(nblocks), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
+hipError_t launch_pointwise_sim(const AdjPointArgs &a, int nblocks, hipStream_t s) {
+  switch (a.nv) {
+    case 1: return launch_sim_nv<1>(a, nblocks, s);
+    case 2: return launch_sim_nv<2>(a, nblocks, s);
+    case 3: return launch_sim_nv<3>(a, nblocks, s);
+    case 4: return launch_sim_nv<4>(a, nblocks, s);
+    case 5: return launch_sim_nv<5>(a, nblocks, s);
+    case 6: return launch_sim_nv<6>(a, nblocks, s);
+    case 7: return launch_sim_nv<7>(a, nblocks, s);
+    case 8: return launch_sim_nv<8>(a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_pointwise_seq(const AdjPointArgs &a, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(pointwise_seq_kernel, dim3(nblocks), dim3(NT), 0, s, a);
+  if (point_vec(a, 1))
+    hipLaunchKernelGGL(pointwise_seq_kernel<4>, dim3(nblocks), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL(pointwise_seq_kernel<1>, dim3(nblocks), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_sum_partials(const double *part, int nblocks, int nv, double *acc, hipStream_t s) {
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, part, nblocks, nv, acc);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(nv), dim3(NT), 0, s, part, nblocks, nv, acc);
   return hipGetLastError();
 }
 
@@ -488,6 +568,12 @@ size_t corr_mfma_lds_bytes(int kzp, int kxp, int tw) {
   const size_t tiles = sizeof(float) * ((size_t)(MCZ + kzp - 1) * mc_pitch(tw) + (size_t)MCZ * (tw + kxp));
   const size_t red = sizeof(float) * 4ull * kzp * kxp;
   return tiles > red ? tiles : red;
+}
+
+int corr_mfma_blocks(int kzp, int kxp, int tw, long ntiles, int max_blocks) {
+  // work-groups resident per CU (LDS-bound; registers allow 4), times the CUs
+  const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, 160 * 1024 / corr_mfma_lds_bytes(kzp, kxp, tw)));
+  return (int)std::min<long>({ntiles, (long)max_blocks, 256L * per_cu});
 }
 
 template <int KZB, int KXB>

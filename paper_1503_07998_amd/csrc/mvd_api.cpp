@@ -805,7 +805,8 @@ hipError_t tap_corr(const RunState &st, const BwdLayout &L, char *ws, const floa
     a.kxp = corr_pad(kx, 8);
     ntiles = (long)st.g.Y * ((st.g.Z + 7) / 8) * ((st.g.X + 63) / 64);
   }
-  const int nb = (int)std::min<long>(mfma ? kCorrMfmaBlocks : kCorrBlocks, ntiles);
+  const int nb = mfma ? corr_mfma_blocks(a.kzp, a.kxp, a.tw, ntiles, kCorrMfmaBlocks)
+                      : (int)std::min<long>(kCorrBlocks, ntiles);
   hipError_t e = timed(st, 4, [&] { return mfma ? launch_corr_mfma(a, nb, st.s) : launch_corr(a, nb, st.s); });
   if (e == hipSuccess)
     e = timed(st, 4, [&] { return launch_corr_finalize(a.part, nb, a.kzp, a.kxp, kz, kx, acc, st.s); });
@@ -1525,7 +1526,7 @@ int mvd_internal_corr_plan(int n_planes, int Z, int X, int kz, int kx, long *out
   out[1] = corr_mfma_pad(kx);
   out[2] = tw;
   out[3] = ntiles;
-  out[4] = std::min<long>(kCorrMfmaBlocks, ntiles);
+  out[4] = corr_mfma_blocks((int)out[0], (int)out[1], tw, ntiles, kCorrMfmaBlocks);
   out[5] = (long)corr_mfma_lds_bytes((int)out[0], (int)out[1], tw);
   return MVD_OK;
 }

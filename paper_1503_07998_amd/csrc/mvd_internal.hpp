@@ -158,6 +158,7 @@ hipError_t launch_corr_mfma(const CorrArgs &a, int nblocks, hipStream_t s);
 int corr_mfma_pad(int k);
 void corr_mfma_shape(const PlaneGeom &g, int kx, int *tw, long *ntiles);
 size_t corr_mfma_lds_bytes(int kzp, int kxp, int tw);
+int corr_mfma_blocks(int kzp, int kxp, int tw, long ntiles, int max_blocks);   // one resident wave of work-groups
 hipError_t launch_corr_finalize(const float *part, int nblocks, int kzp, int kxp, int kz, int kx, double *acc,
                                 hipStream_t s);
 hipError_t launch_to_f32(const double *src, float *dst, int n, hipStream_t s);
