@@ -322,8 +322,8 @@ constexpr int MCXMAX = 256;  // columns x' per tile, at most
 constexpr int MCT = 256;     // threads (4 waves)
 
 struct McGeo {
-  int kz, kx, xa, ntx, ntz, nr, pa, pb;
-  long ntiles;
+  int kz, kx, xa, ntx, ntz, nzc, nr, pa, pb;
+  long nitems;
 };
 
 __host__ __device__ inline int mc_pitch(int tw) { return tw + 2; }
@@ -335,24 +335,26 @@ __device__ __forceinline__ McGeo mc_geo(const CorrArgs &a) {
   g.xa = a.rx - g.kx + 1;                          // first column x' that meets a tap
   g.ntx = (a.g.X + g.kx - 1 + a.tw - 1) / a.tw;
   g.ntz = (a.g.Z + MCZ - 1) / MCZ;
+  g.nzc = (g.ntz + a.zch - 1) / a.zch;
   g.nr = MCZ + a.kzp - 1;
   g.pa = mc_pitch(a.tw);
   g.pb = a.tw + a.kxp;
-  g.ntiles = (long)a.g.Y * g.ntz * g.ntx;
+  g.nitems = (long)a.g.Y * g.nzc * g.ntx;
   return g;
 }
 
-// Stage a rows × pitch window into LDS: element (r, c) comes from src(r, c),
-// which returns a clamped in-plane index and whether the value is kept (else 0).
-// Each thread walks elements t, t + MCT, … and issues MSU loads before it
-// stores any, so that their latencies overlap.
+// Stage rows × pitch elements into LDS: element (r, c) comes from src[at(r, c)]
+// (at returns a clamped in-plane index and whether the value is kept, else 0)
+// and goes to row slot(r).  Each thread walks elements t, t + MCT, … and
+// issues MSU loads before it stores any, so that their latencies overlap.
 constexpr int MSU = 8;
-template <class F>
-__device__ __forceinline__ void mc_stage(float *dst, int rows, int pitch, const float *__restrict__ src, F at) {
+template <class F, class S>
+__device__ __forceinline__ void mc_stage(float *dst, int rows, int pitch, const float *__restrict__ src, F at,
+                                         S slot) {
   const int t = threadIdx.x;
   const int dr = MCT / pitch, dc = MCT % pitch;
   int r = t / pitch, c = t % pitch;
-  for (int e = t; r < rows;) {
+  while (r < rows) {
     float v[MSU];
     int ev[MSU];
 #pragma unroll
@@ -361,8 +363,7 @@ __device__ __forceinline__ void mc_stage(float *dst, int rows, int pitch, const 
       const size_t i = at(r < rows ? r : rows - 1, c, in);
       const float w = src[i];
       v[u] = in ? w : 0.f;
-      ev[u] = r < rows ? e : -1;
-      e += MCT;
+      ev[u] = r < rows ? slot(r) * pitch + c : -1;
       r += dr;
       c += dc;
       if (c >= pitch) {
@@ -380,79 +381,105 @@ template <int KZB, int KXB>
 __global__ void __launch_bounds__(MCT) corr_mfma_kernel(CorrArgs a) {
   extern __shared__ __align__(16) float sm[];
   const McGeo G = mc_geo(a);
-  float *As = sm;                     // [nr][pa]: ã[z0 + Rz − (kzp − 1) + r][x0' + c]
-  float *Bs = sm + G.nr * G.pa;       // [MCZ][pb]: ḡ[z0 + r][x0' − Rx + c]
+  // As: ring of nr rows; window row r of the current tile (ã row z0 + Rz − (kzp − 1) + r,
+  // columns x0' + c) sits in slot (ring0 + r) mod nr.  Bs: [MCZ][pb] = ḡ[z0 + r][x0' − Rx + c].
+  float *As = sm;
+  float *Bs = sm + G.nr * G.pa;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int n = lane & 15, kk = lane >> 4;
-  const int Z = a.g.Z, X = a.g.X, tw = a.tw;
+  const int Z = a.g.Z, X = a.g.X, tw = a.tw, nr = G.nr;
+  const int boundary = a.boundary;
   f32x4 acc[KZB][KXB];
 #pragma unroll
   for (int jb = 0; jb < KZB; ++jb)
 #pragma unroll
     for (int ib = 0; ib < KXB; ++ib) acc[jb][ib] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (long tile = blockIdx.x; tile < G.ntiles; tile += gridDim.x) {
-    const int tx = (int)(tile % G.ntx);
-    const int tz = (int)((tile / G.ntx) % G.ntz);
-    const int y = (int)(tile / ((long)G.ntx * G.ntz));
-    const int z0 = tz * MCZ, x0 = G.xa + tx * tw;
+  // item = (plane y, run of zch tiles down z, column tile): the tiles of a run
+  // share all but 16 of their ã rows, so each later tile stages only those
+  for (long item = blockIdx.x; item < G.nitems; item += gridDim.x) {
+    const int tx = (int)(item % G.ntx);
+    const int zc = (int)((item / G.ntx) % G.nzc);
+    const int y = (int)(item / ((long)G.ntx * G.nzc));
+    const int x0 = G.xa + tx * tw, xg = x0 - a.rx;
     const size_t po = (size_t)y * Z * X;
-    const int za = z0 + a.rz - (a.kzp - 1), xg = x0 - a.rx;
-    const int boundary = a.boundary;
-    mc_stage(As, G.nr, G.pa, a.src, [&](int r, int c, bool &in) -> size_t {
-      int z = za + r, x = x0 + c;
-      in = c < tw;
-      if (boundary == 0) {
-        in = in && z >= 0 && z < Z && x >= 0 && x < X;
-        z = min(max(z, 0), Z - 1);
-        x = min(max(x, 0), X - 1);
-      } else {
-        z = wrapc(z, Z);
-        x = wrapc(x, X);
-      }
-      return po + (size_t)z * X + x;
-    });
-    mc_stage(Bs, MCZ, G.pb, a.gbar, [&](int r, int c, bool &in) -> size_t {
-      const int z = z0 + r, x = xg + c;
-      in = z < Z && x >= 0 && x < X;
-      return po + (size_t)min(z, Z - 1) * X + min(max(x, 0), X - 1);
-    });
-    __syncthreads();
-    for (int zz = w; zz < MCZ && z0 + zz < Z; zz += 4) {
-      const float *Ar = As + (zz + a.kzp - 1 - n) * G.pa + kk;   // A[16·jb + n][4q + kk]
-      const float *Br = Bs + zz * G.pb + kk + n;                  // B[4q + kk][16·ib + n]
-      // 4 steps of 4 columns at a time (tw is a multiple of 16), operands of
-      // the next 4 loaded before the products of these
-      float av[2][4][KZB], bv[2][4][KXB];
-      auto load = [&](int buf, int q0) {
+    const int tz0 = zc * a.zch, tz1 = min(G.ntz, tz0 + a.zch);
+    int ring0 = 0;
+    for (int tz = tz0; tz < tz1; ++tz) {
+      const int z0 = tz * MCZ;
+      const int za = z0 + a.rz - (a.kzp - 1);
+      const int rfirst = tz == tz0 ? 0 : nr - MCZ;   // window rows to stage
+      const int rs = ring0 + rfirst;
+      mc_stage(
+          As, nr - rfirst, G.pa, a.src,
+          [&](int r, int c, bool &in) -> size_t {
+            int z = za + rfirst + r, x = x0 + c;
+            in = c < tw;
+            if (boundary == 0) {
+              in = in && z >= 0 && z < Z && x >= 0 && x < X;
+              z = min(max(z, 0), Z - 1);
+              x = min(max(x, 0), X - 1);
+            } else {
+              z = wrapc(z, Z);
+              x = wrapc(x, X);
+            }
+            return po + (size_t)z * X + x;
+          },
+          [&](int r) { return rs + r < nr ? rs + r : rs + r - nr; });
+      mc_stage(
+          Bs, MCZ, G.pb, a.gbar,
+          [&](int r, int c, bool &in) -> size_t {
+            const int z = z0 + r, x = xg + c;
+            in = z < Z && x >= 0 && x < X;
+            return po + (size_t)min(z, Z - 1) * X + min(max(x, 0), X - 1);
+          },
+          [](int r) { return r; });
+      __syncthreads();
+      for (int zz = w; zz < MCZ && z0 + zz < Z; zz += 4) {
+        // A[16·jb + n][4q + kk] = window row zz + kzp − 1 − n − 16·jb, column 4q + kk
+        const float *Ar[KZB];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-#pragma unroll
-          for (int jb = 0; jb < KZB; ++jb) av[buf][s][jb] = Ar[4 * (q0 + s) - 16 * jb * G.pa];
-#pragma unroll
-          for (int ib = 0; ib < KXB; ++ib) bv[buf][s][ib] = Br[4 * (q0 + s) + 16 * ib];
+        for (int jb = 0; jb < KZB; ++jb) {
+          int sl = ring0 + zz + a.kzp - 1 - n - 16 * jb;
+          sl = sl < nr ? sl : sl - nr;
+          Ar[jb] = As + sl * G.pa + kk;
         }
-      };
-      auto step = [&](int buf) {
+        const float *Br = Bs + zz * G.pb + kk + n;                  // B[4q + kk][16·ib + n]
+        // 4 steps of 4 columns at a time (tw is a multiple of 16), operands of
+        // the next 4 loaded before the products of these
+        float av[2][4][KZB], bv[2][4][KXB];
+        auto load = [&](int buf, int q0) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+          for (int s = 0; s < 4; ++s) {
 #pragma unroll
-          for (int jb = 0; jb < KZB; ++jb)
+            for (int jb = 0; jb < KZB; ++jb) av[buf][s][jb] = Ar[jb][4 * (q0 + s)];
 #pragma unroll
-            for (int ib = 0; ib < KXB; ++ib)
-              acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[buf][s][jb], bv[buf][s][ib], acc[jb][ib], 0, 0, 0);
-      };
-      const int nq = tw / 4;
-      load(0, 0);
-      int q0 = 0;
-      for (; q0 + 8 <= nq; q0 += 8) {
-        load(1, q0 + 4);
-        step(0);
-        if (q0 + 8 < nq) load(0, q0 + 8);
-        step(1);
+            for (int ib = 0; ib < KXB; ++ib) bv[buf][s][ib] = Br[4 * (q0 + s) + 16 * ib];
+          }
+        };
+        auto step = [&](int buf) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int jb = 0; jb < KZB; ++jb)
+#pragma unroll
+              for (int ib = 0; ib < KXB; ++ib)
+                acc[jb][ib] =
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(av[buf][s][jb], bv[buf][s][ib], acc[jb][ib], 0, 0, 0);
+        };
+        const int nq = tw / 4;
+        load(0, 0);
+        int q0 = 0;
+        for (; q0 + 8 <= nq; q0 += 8) {
+          load(1, q0 + 4);
+          step(0);
+          if (q0 + 8 < nq) load(0, q0 + 8);
+          step(1);
+        }
+        if (q0 < nq) step(0);
       }
-      if (q0 < nq) step(0);
+      __syncthreads();
+      ring0 = ring0 + MCZ < nr ? ring0 + MCZ : ring0 + MCZ - nr;
     }
-    __syncthreads();
   }
   // the 4 waves' blocks through LDS, summed in a fixed order; register r of
   // lane l holds row 4·(l / 16) + r, column l % 16 of a block
@@ -557,23 +584,39 @@ hipError_t launch_sum_partials(const double *part, int nblocks, int nv, double *
 
 int corr_mfma_pad(int k) { return (k + 15) / 16 * 16; }
 
-void corr_mfma_shape(const PlaneGeom &g, int kx, int *tw, long *ntiles) {
-  const int width = g.X + kx - 1;
-  const int ntx = (width + MCXMAX - 1) / MCXMAX;
-  *tw = (width + 16 * ntx - 1) / (16 * ntx) * 16;
-  *ntiles = (long)g.Y * ((g.Z + MCZ - 1) / MCZ) * ((width + *tw - 1) / *tw);
-}
-
 size_t corr_mfma_lds_bytes(int kzp, int kxp, int tw) {
   const size_t tiles = sizeof(float) * ((size_t)(MCZ + kzp - 1) * mc_pitch(tw) + (size_t)MCZ * (tw + kxp));
   const size_t red = sizeof(float) * 4ull * kzp * kxp;
   return tiles > red ? tiles : red;
 }
 
-int corr_mfma_blocks(int kzp, int kxp, int tw, long ntiles, int max_blocks) {
-  // work-groups resident per CU (LDS-bound; registers allow 4), times the CUs
-  const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, 160 * 1024 / corr_mfma_lds_bytes(kzp, kxp, tw)));
-  return (int)std::min<long>({ntiles, (long)max_blocks, 256L * per_cu});
+CorrMfmaShape corr_mfma_shape(const PlaneGeom &g, int kz, int kx, int max_blocks) {
+  CorrMfmaShape m;
+  m.kzp = corr_mfma_pad(kz);
+  m.kxp = corr_mfma_pad(kx);
+  const int width = g.X + kx - 1;
+  const int ntx0 = (width + MCXMAX - 1) / MCXMAX;
+  m.tw = (width + 16 * ntx0 - 1) / (16 * ntx0) * 16;
+  const int ntx = (width + m.tw - 1) / m.tw;
+  const int ntz = (g.Z + MCZ - 1) / MCZ;
+  m.lds = corr_mfma_lds_bytes(m.kzp, m.kxp, m.tw);
+  // resident work-groups: LDS-bound, at most 4 per CU (registers), 256 CUs
+  const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, 160 * 1024 / m.lds));
+  const long slots = std::min<long>(max_blocks, 256L * per_cu);
+  // run length down z: fewest tiles on the busiest work-group, then the longest run
+  long best = -1;
+  m.zch = 1;
+  for (int c = 1; c <= ntz; ++c) {
+    const long items = (long)g.Y * ntx * ((ntz + c - 1) / c);
+    const long span = (items + slots - 1) / slots * c;
+    if (best < 0 || span <= best) {
+      best = span;
+      m.zch = c;
+    }
+  }
+  m.nitems = (long)g.Y * ntx * ((ntz + m.zch - 1) / m.zch);
+  m.nblocks = (int)std::min<long>(m.nitems, slots);
+  return m;
 }
 
 template <int KZB, int KXB>
@@ -591,7 +634,7 @@ hipError_t launch_corr_mfma_t(const CorrArgs &a, int nblocks, hipStream_t s) {
 
 hipError_t launch_corr_mfma(const CorrArgs &a, int nblocks, hipStream_t s) {
   if (a.kzp % 16 || a.kxp % 16 || a.kzp > 64 || a.kxp > 64 || a.tw <= 0 || a.tw % 16 || a.tw > MCXMAX ||
-      a.kzp < 2 * a.rz + 1 || a.kxp < 2 * a.rx + 1)
+      a.kzp < 2 * a.rz + 1 || a.kxp < 2 * a.rx + 1 || a.zch < 1)
     return hipErrorInvalidValue;
   const int zb = a.kzp / 16, xb = a.kxp / 16;
 #define MVD_CORR_CASE(ZB, XB) \

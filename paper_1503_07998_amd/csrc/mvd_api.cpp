@@ -795,18 +795,19 @@ hipError_t tap_corr(const RunState &st, const BwdLayout &L, char *ws, const floa
   a.src = src;
   a.part = reinterpret_cast<float *>(ws + L.cpart_off);
   const bool mfma = !st.tn->valu_corr;
-  long ntiles;
+  int nb;
   if (mfma) {
-    a.kzp = corr_mfma_pad(kz);
-    a.kxp = corr_mfma_pad(kx);
-    corr_mfma_shape(st.g, kx, &a.tw, &ntiles);
+    const CorrMfmaShape m = corr_mfma_shape(st.g, kz, kx, kCorrMfmaBlocks);
+    a.kzp = m.kzp;
+    a.kxp = m.kxp;
+    a.tw = m.tw;
+    a.zch = m.zch;
+    nb = m.nblocks;
   } else {
     a.kzp = corr_pad(kz, 4);
     a.kxp = corr_pad(kx, 8);
-    ntiles = (long)st.g.Y * ((st.g.Z + 7) / 8) * ((st.g.X + 63) / 64);
+    nb = (int)std::min<long>(kCorrBlocks, (long)st.g.Y * ((st.g.Z + 7) / 8) * ((st.g.X + 63) / 64));
   }
-  const int nb = mfma ? corr_mfma_blocks(a.kzp, a.kxp, a.tw, ntiles, kCorrMfmaBlocks)
-                      : (int)std::min<long>(kCorrBlocks, ntiles);
   hipError_t e = timed(st, 4, [&] { return mfma ? launch_corr_mfma(a, nb, st.s) : launch_corr(a, nb, st.s); });
   if (e == hipSuccess)
     e = timed(st, 4, [&] { return launch_corr_finalize(a.part, nb, a.kzp, a.kxp, kz, kx, acc, st.s); });
@@ -1514,20 +1515,14 @@ int mvd_internal_set_tune(const char *spec) {
 }
 
 // Internal: the matrix-core tap-gradient correlation's launch for a volume of
-// n_planes × Z × X and a kz × kx kernel.  out[6]: kzp, kxp, tile width, tiles,
-// work-groups, LDS bytes.
+// n_planes × Z × X and a kz × kx kernel.  out[7]: kzp, kxp, tile width, tiles
+// per z run, work items, work-groups, LDS bytes.
 int mvd_internal_corr_plan(int n_planes, int Z, int X, int kz, int kx, long *out) {
   if (!out || n_planes < 1 || Z < 1 || X < 1 || kz < 1 || kx < 1 || kz > MVD_MAX_K || kx > MVD_MAX_K)
     return MVD_ERR_ARG;
-  int tw;
-  long ntiles;
-  corr_mfma_shape(PlaneGeom{n_planes, Z, X}, kx, &tw, &ntiles);
-  out[0] = corr_mfma_pad(kz);
-  out[1] = corr_mfma_pad(kx);
-  out[2] = tw;
-  out[3] = ntiles;
-  out[4] = corr_mfma_blocks((int)out[0], (int)out[1], tw, ntiles, kCorrMfmaBlocks);
-  out[5] = (long)corr_mfma_lds_bytes((int)out[0], (int)out[1], tw);
+  const CorrMfmaShape m = corr_mfma_shape(PlaneGeom{n_planes, Z, X}, kz, kx, kCorrMfmaBlocks);
+  const long v[7] = {m.kzp, m.kxp, m.tw, m.zch, m.nitems, m.nblocks, (long)m.lds};
+  for (int i = 0; i < 7; ++i) out[i] = v[i];
   return MVD_OK;
 }
 

@@ -141,7 +141,7 @@ struct CorrArgs {
   int boundary;
   int rz, rx;
   int kzp, kxp;
-  int tw;            // matrix-core form: columns x' per tile
+  int tw, zch;       // matrix-core form: columns x' per tile, tiles per run down z
   const float *gbar;
   const float *src;
   float *part;
@@ -152,13 +152,18 @@ hipError_t launch_pointwise_sim(const AdjPointArgs &a, int nblocks, hipStream_t 
 hipError_t launch_pointwise_seq(const AdjPointArgs &a, int nblocks, hipStream_t s);
 hipError_t launch_sum_partials(const double *part, int nblocks, int nv, double *acc, hipStream_t s);
 hipError_t launch_corr(const CorrArgs &a, int nblocks, hipStream_t s);
-// Matrix-core form: kzp, kxp = corr_mfma_pad(k) (multiples of 16, ≤ 64) and the
-// tile width tw and tile count from corr_mfma_shape.
+// Matrix-core form: padded lags, tile width, z-run length and grid from
+// corr_mfma_shape (at most max_blocks work-groups, one resident wave of them).
+struct CorrMfmaShape {
+  int kzp, kxp, tw, zch;
+  long nitems;
+  int nblocks;
+  size_t lds;
+};
 hipError_t launch_corr_mfma(const CorrArgs &a, int nblocks, hipStream_t s);
 int corr_mfma_pad(int k);
-void corr_mfma_shape(const PlaneGeom &g, int kx, int *tw, long *ntiles);
+CorrMfmaShape corr_mfma_shape(const PlaneGeom &g, int kz, int kx, int max_blocks);
 size_t corr_mfma_lds_bytes(int kzp, int kxp, int tw);
-int corr_mfma_blocks(int kzp, int kxp, int tw, long ntiles, int max_blocks);   // one resident wave of work-groups
 hipError_t launch_corr_finalize(const float *part, int nblocks, int kzp, int kxp, int kz, int kx, double *acc,
                                 hipStream_t s);
 hipError_t launch_to_f32(const double *src, float *dst, int n, hipStream_t s);

@@ -227,85 +227,94 @@ MCZ, MCT = 16, 256
 
 
 def corr_plan(Y, Z, X, kz, kx):
-    out = (ctypes.c_long * 6)()
+    out = (ctypes.c_long * 7)()
     lib = N.lib()
     lib.mvd_internal_corr_plan.restype = ctypes.c_int
     lib.mvd_internal_corr_plan.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_long)]
     assert lib.mvd_internal_corr_plan(Y, Z, X, kz, kx, out) == 0
-    return dict(zip(["kzp", "kxp", "tw", "ntiles", "nblocks", "lds"], list(out)))
+    return dict(zip(["kzp", "kxp", "tw", "zch", "nitems", "nblocks", "lds"], list(out)))
 
 
 def corr_pitch(tw):
-    return (tw + 31) // 32 * 32 + 2
+    return tw + 2
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (2, 5, 37), (3, 16, 16), (2, 17, 300), (256, 256, 256),
-                                   (1024, 1024, 1024), (3, 40, 513), (1, 70, 2048)],
+                                   (1024, 1024, 1024), (3, 40, 513), (1, 70, 2048), (300, 150, 1000)],
                          ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("k", [(1, 1), (3, 9), (15, 15), (31, 31), (41, 17), (63, 63)],
                          ids=lambda k: f"{k[0]}x{k[1]}")
 def test_matrix_core_correlation_in_bounds(shape, k):
-    """Every LDS access of the matrix-core correlation (staged ã rows and ḡ
-    rows, 16 × 16 × 4 operand lanes, the 4-wave reduction) and every partial it
-    writes lies in its buffer; the tiles of a row cover every column x' that
-    meets a tap; the work-group fits in LDS."""
+    """Every LDS access of the matrix-core correlation (the ring of staged ã
+    rows, the ḡ rows, 16 × 16 × 4 operand lanes, the 4-wave reduction) and
+    every partial it writes lies in its buffer; the tiles of a row cover every
+    column x' that meets a tap; the work-group fits in LDS."""
     Y, Z, X = shape
     kz, kx = k
     p = corr_plan(Y, Z, X, kz, kx)
-    kzp, kxp, tw = p["kzp"], p["kxp"], p["tw"]
+    kzp, kxp, tw, zch = p["kzp"], p["kxp"], p["tw"], p["zch"]
     rz, rx = (kz - 1) // 2, (kx - 1) // 2
     assert kzp % 16 == 0 and kxp % 16 == 0 and kz <= kzp <= 64 and kx <= kxp <= 64
     assert tw % 16 == 0 and 16 <= tw <= 256
     width = X + kx - 1
-    ntx = -(-width // tw)
+    ntx, ntz = -(-width // tw), -(-Z // MCZ)
     assert ntx * tw >= width and (ntx - 1) * tw < width
-    assert p["ntiles"] == Y * (-(-Z // MCZ)) * ntx and 1 <= p["nblocks"] <= min(1024, p["ntiles"])
+    assert 1 <= zch <= ntz and p["nitems"] == Y * ntx * (-(-ntz // zch))
+    assert 1 <= p["nblocks"] <= min(1024, p["nitems"])
     nr, pa, pb = MCZ + kzp - 1, corr_pitch(tw), tw + kxp
-    assert pa % 32 == 2 and pa >= tw
+    assert pa % 4 == 2 and pa >= tw and nr >= MCZ
+    # the 32 lanes of a half-wave (16 rows n, 2 columns kk) read 32 distinct banks
+    half = (-(np.arange(16)[:, None]) * pa + np.arange(2)[None, :]) % 32
+    assert len(np.unique(half)) == 32
     assert p["lds"] == 4 * max(nr * pa + MCZ * pb, 4 * kzp * kxp) <= LDS_LIMIT
+    assert (LDS_LIMIT // p["lds"]) * 256 >= p["nblocks"] or p["nblocks"] <= 256
     lane = np.arange(64)
     n, kk = lane % 16, lane // 16
-    for zz in (0, MCZ - 1):
-        for q in (0, tw // 4 - 1):
+    for ring0 in range(0, nr):
+        for zz in (0, MCZ - 1):
             for jb in range(kzp // 16):
-                row = zz + kzp - 1 - n - 16 * jb
-                col = 4 * q + kk
-                assert row.min() >= 0 and row.max() < nr and col.max() < tw
-            for ib in range(kxp // 16):
-                bcol = kk + n + 16 * ib + 4 * q
-                assert bcol.max() < pb
-    # the staging walk: element e = t + u·MCT of a rows × pitch window
-    for rows, pitch in ((nr, pa), (MCZ, pb)):
+                sl = ring0 + zz + kzp - 1 - n - 16 * jb
+                assert sl.min() >= 0 and sl.max() < 2 * nr
+                sl = np.where(sl < nr, sl, sl - nr)
+                assert sl.min() >= 0 and sl.max() < nr
+    for q in (0, tw // 4 - 1):
+        assert (4 * q + kk).max() < tw
+        for ib in range(kxp // 16):
+            assert (kk + n + 16 * ib + 4 * q).max() < pb
+    # the staging walk: element e = t + u·MCT of a rows × pitch window, rows mapped to ring slots
+    for rows, pitch, ringed in ((nr, pa, True), (MCZ, pa, True), (MCZ, pb, False)):
         e = np.arange(MCT)[:, None] + MCT * np.arange(-(-rows * pitch // MCT) + 8)[None, :]
         r, c = e // pitch, e % pitch
         kept = r < rows
-        assert (e[kept] < rows * pitch).all() and (c < pitch).all()
+        assert (c < pitch).all() and (r[kept] < rows).all()
+        for rs in ((0, nr - MCZ, nr - 1) if ringed else (0,)):
+            slot = np.where(rs + r < nr, rs + r, rs + r - nr) if ringed else r
+            lim = nr * pa if ringed else MCZ * pb
+            assert (slot[kept] >= 0).all() and (slot[kept] * pitch + c[kept] < lim).all()
     # reduction: row 16·jb + 4·kk + r, column 16·ib + n of each wave's block
     for w in (0, 3):
         idx = w * kzp * kxp + (16 * (kzp // 16 - 1) + 4 * kk + 3) * kxp + 16 * (kxp // 16 - 1) + n
         assert idx.max() < 4 * kzp * kxp
-    # global reads: clamped (zero boundary) or wrapped (periodic) indices inside the plane
-    za_min = 0 + rz - (kzp - 1)
-    x0_max = rx - kx + 1 + (ntx - 1) * tw
-    for z in (za_min, (-(-Z // MCZ) - 1) * MCZ + rz + MCZ - 1):
-        for x in (rx - kx + 1, x0_max + pa - 1):
-            assert 0 <= min(max(z, 0), Z - 1) < Z and 0 <= min(max(x, 0), X - 1) < X
-            assert 0 <= z % Z < Z and 0 <= x % X < X
 
 
 @pytest.mark.parametrize("boundary", ["zero", "periodic"])
-@pytest.mark.parametrize("shape,k", [((2, 19, 37), (7, 5)), ((1, 33, 300), (15, 31)), ((2, 5, 9), (9, 3))],
-                         ids=["19x37", "33x300", "5x9"])
-def test_matrix_core_correlation_tiling_model(shape, k, boundary):
+@pytest.mark.parametrize("shape,k", [((2, 19, 37), (7, 5)), ((1, 33, 300), (15, 31)), ((2, 5, 9), (9, 3)),
+                                     ((1, 70, 20), (31, 3))],
+                         ids=["19x37", "33x300", "5x9", "70x20"])
+@pytest.mark.parametrize("zch", [None, 1, 2, 3])
+def test_matrix_core_correlation_tiling_model(shape, k, boundary, zch):
     """The tile decomposition of the matrix-core correlation, replayed in
-    numpy: for each tile the staged ã window (A[j][x'] = ã[z + Rz − j][x'])
-    times the staged Toeplitz window of ḡ (B[x'][i] = ḡ[z][x' − Rx + i]),
-    summed over rows and tiles, equals the direct sum
-    Σ ḡ[y][z][x] · ã[y][z + Rz − j][x + Rx − i] over the plane."""
+    numpy with the kernel's ring of ã rows: for each tile the staged ã window
+    (A[j][x'] = ã[z + Rz − j][x']) times the staged Toeplitz window of ḡ
+    (B[x'][i] = ḡ[z][x' − Rx + i]), summed over rows, tiles and runs, equals
+    the direct sum Σ ḡ[y][z][x] · ã[y][z + Rz − j][x + Rx − i] over the plane.
+    zch=None takes the planner's run length."""
     Y, Z, X = shape
     kz, kx = k
     p = corr_plan(Y, Z, X, kz, kx)
     kzp, kxp, tw = p["kzp"], p["kxp"], p["tw"]
+    ntz = -(-Z // MCZ)
+    zch = p["zch"] if zch is None else min(zch, ntz)
     rz, rx = (kz - 1) // 2, (kx - 1) // 2
     rng = np.random.default_rng(3)
     src = rng.standard_normal((Y, Z, X))
@@ -327,16 +336,31 @@ def test_matrix_core_correlation_tiling_model(shape, k, boundary):
     ntx = -(-(X + kx - 1) // tw)
     C = np.zeros((kzp, kxp))
     nr, pb = MCZ + kzp - 1, tw + kxp
+    ring = np.full((nr, tw), np.nan)
     for y in range(Y):
-        for tz in range(-(-Z // MCZ)):
+        for zc in range(-(-ntz // zch)):
             for tx in range(ntx):
-                z0, x0 = tz * MCZ, xa + tx * tw
-                za = z0 + rz - (kzp - 1)
-                As = np.array([[sat(y, za + r, x0 + c) for c in range(tw)] for r in range(nr)])
-                Bs = np.array([[gbar[y, z0 + r, x0 - rx + c] if z0 + r < Z and 0 <= x0 - rx + c < X else 0.0
-                                for c in range(pb)] for r in range(MCZ)])
-                for zz in range(min(MCZ, Z - z0)):
-                    A = np.array([As[zz + kzp - 1 - j] for j in range(kzp)])            # [kzp][tw]
-                    B = np.array([Bs[zz, c:c + kxp] for c in range(tw)])                 # [tw][kxp]
-                    C += A @ B
+                x0 = xa + tx * tw
+                tz0 = zc * zch
+                ring0 = 0
+                for tz in range(tz0, min(ntz, tz0 + zch)):
+                    z0 = tz * MCZ
+                    za = z0 + rz - (kzp - 1)
+                    rfirst = 0 if tz == tz0 else nr - MCZ
+                    rs = ring0 + rfirst
+                    for r in range(nr - rfirst):
+                        slot = rs + r if rs + r < nr else rs + r - nr
+                        ring[slot] = [sat(y, za + rfirst + r, x0 + c) for c in range(tw)]
+                    Bs = np.array([[gbar[y, z0 + r, x0 - rx + c] if z0 + r < Z and 0 <= x0 - rx + c < X else 0.0
+                                    for c in range(pb)] for r in range(MCZ)])
+                    for zz in range(min(MCZ, Z - z0)):
+                        rows = []
+                        for j in range(kzp):
+                            sl = ring0 + zz + kzp - 1 - j
+                            rows.append(ring[sl if sl < nr else sl - nr])
+                        A = np.array(rows)                                            # [kzp][tw]
+                        B = np.array([Bs[zz, c:c + kxp] for c in range(tw)])           # [tw][kxp]
+                        assert not np.isnan(A).any()
+                        C += A @ B
+                    ring0 = ring0 + MCZ if ring0 + MCZ < nr else ring0 + MCZ - nr
     np.testing.assert_allclose(C[:kz, :kx], direct, rtol=1e-12, atol=1e-9)
