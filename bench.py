@@ -43,10 +43,11 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
     """Algorithmic bytes and flops of one forward / backward launch over
     ``vox`` voxels (a whole volume, or one batch of planes).
 
-    Per voxel and view, a forward pass reads φ_v, writes r_v and (once per
-    launch) reads ψ; a backward pass reads r_v and (once per launch) reads and
-    writes ψ.  Each view's two 1D passes cost 2 · (kz + kx) flops (FMA = 2);
-    a general K×K pass costs 2 · kz · kx.
+    Per voxel and view, a forward pass reads φ_v (as given: 2 bytes for
+    uint16 observations; the general K×K passes read float32 staged copies),
+    writes r_v and (once per launch) reads ψ; a backward pass reads r_v and
+    (once per launch) reads and writes ψ.  Each view's two 1D passes cost
+    2 · (kz + kx) flops (FMA = 2); a general K×K pass costs 2 · kz · kx.
     The library may split the V views of an iteration over several launches,
     so the work of one iteration on those voxels is divided by its launches.
     """
@@ -54,7 +55,8 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
     k = spec.psf_k
     n = launches_per_iter
     if kind == "forward":
-        b = 8 * V + 4 * n
+        phi = 2 if (spec.obs_dtype == "u16" and not general) else 4
+        b = (phi + 4) * V + 4 * n
     else:
         b = 4 * V + 8 * n
     f = V * 2 * (k * k if general else k + k)

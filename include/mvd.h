@@ -168,9 +168,10 @@ mvd_status mvd_psf_info(mvd_ctx *ctx, int view, int *separable_psf, int *separab
 
 /* Device workspace needed by mvd_deconvolve_planes() for `run`, in bytes:
  * V float32 plane sets for the observations, resliced/converted and clamped
- * at 0 (whatever their layout and type, so the passes read one form), plus
- * the ratio planes (V sets for MVD_UPDATE_SIMULTANEOUS, one for sequential;
- * none when n_iters = 0).  Errors: MVD_ERR_ARG. */
+ * at 0 (filled only when some view's forward pass is a K×K pass; the rank-one
+ * passes read the observations as given, through their layout's strides),
+ * plus the ratio planes (V sets for MVD_UPDATE_SIMULTANEOUS, one for
+ * sequential; none when n_iters = 0).  Errors: MVD_ERR_ARG. */
 mvd_status mvd_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, size_t *bytes);
 
 /* Reslice one camera-ordered stack (device [Z][Y][X], u16 or f32) into device
@@ -184,9 +185,12 @@ mvd_status mvd_reslice(mvd_ctx *ctx, const void *stack, int dtype, int n_planes,
  *   obs: host array of V device pointers, one per view, in run->obs_layout
  *        and run->obs_dtype (Y = run->n_planes).  Read only.
  *   est: device float32 [Y][Z][X]; ψ^0 on entry for MVD_INIT_GIVEN, ψ^T on exit.
- * Steps: reslice/convert the observations into the workspace,
- * ψ^0, then T iterations (2 passes per iteration for SIMULTANEOUS, 2V for
- * SEQUENTIAL).  ψ stays ≥ 0 for non-negative data.
+ * Steps: ψ^0 (and, for K×K forward passes, the observations resliced and
+ * converted into the workspace), then T iterations (2 passes per iteration
+ * for SIMULTANEOUS, 2V for SEQUENTIAL) that read the observations in place:
+ * they must stay unchanged until the stream has finished the run.  uint16
+ * values convert exactly, float values are clamped below at 0 (NaN → 0).
+ * ψ stays ≥ 0 for non-negative data.
  * Errors: MVD_ERR_ARG, MVD_ERR_STATE (PSF missing), MVD_ERR_WORKSPACE,
  * MVD_ERR_DEVICE, MVD_ERR_LAUNCH. */
 mvd_status mvd_deconvolve_planes(mvd_ctx *ctx, const void *const *obs, float *est,

@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(NT) stage_views_kernel(StageViews a) {
         float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
         for (int v = 0; v < a.nv; ++v) {
           const float4 f = load4(a.src[v], a.dtype, srow + x);
-          *reinterpret_cast<float4 *>(a.dst[v] + drow + x) = f;
+          if (a.dst[v]) *reinterpret_cast<float4 *>(a.dst[v] + drow + x) = f;
           sum.x += f.x;
           sum.y += f.y;
           sum.z += f.z;
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(NT) stage_views_kernel(StageViews a) {
         float sum = 0.f;
         for (int v = 0; v < a.nv; ++v) {
           const float f = obs_value(a.src[v], a.dtype, srow + x);
-          a.dst[v][drow + x] = f;
+          if (a.dst[v]) a.dst[v][drow + x] = f;
           sum += f;
         }
         if (a.mean) a.mean[drow + x] = sum / nvf;
@@ -154,8 +154,8 @@ hipError_t launch_stage_views(const void *const *src, int nv, int dtype, int lay
   int vec = g.X % 4 == 0 && (!mean || (uintptr_t)mean % 16 == 0);
   for (int v = 0; v < nv; ++v) {
     a.src[v] = src[v];
-    a.dst[v] = dst[v];
-    vec = vec && (uintptr_t)src[v] % sa == 0 && (uintptr_t)dst[v] % 16 == 0;
+    a.dst[v] = dst ? dst[v] : nullptr;
+    vec = vec && (uintptr_t)src[v] % sa == 0 && (uintptr_t)a.dst[v] % 16 == 0;
   }
   a.vec = vec;
   const size_t blocks = std::min<size_t>((rows + NT / 64 - 1) / (NT / 64), 65536);

@@ -102,7 +102,7 @@ __device__ __forceinline__ int logical_block() {
 }
 
 struct Geo {
-  int zs, ze, ngroups, xo0, xout;
+  int y, zs, ze, ngroups, xo0, xout;
   size_t plane_off;
 };
 
@@ -118,6 +118,7 @@ __device__ __forceinline__ Geo tile_geo(KArg *a) {
   o.ngroups = (o.ze - o.zs + G - 1) / G;
   o.xo0 = strip * a->x_out;
   o.xout = min(a->x_out, a->g.X - o.xo0);
+  o.y = y;
   o.plane_off = (size_t)y * a->g.Z * a->g.X;
   return o;
 }
@@ -243,7 +244,8 @@ struct Loop {
 struct Item {
   bool valid;
   int g, ox, nvalid;
-  size_t off;
+  size_t off;    // in the plane set
+  size_t soff;   // in the forward pass's observations
 };
 
 // Items are dealt to lanes in pairs of rows: lane pairs (2p, 2p+1) take the same
@@ -262,7 +264,9 @@ __device__ __forceinline__ Item item_at(int it, const Loop &st, const Geo &o, in
   r.ox = xb * NX;
   r.nvalid = min(NX, o.xout - r.ox);
   // rows past the segment are clamped to its first row: a valid address whose data is unused
-  r.off = o.plane_off + (size_t)(r.valid ? z : o.zs) * a->g.X + o.xo0 + r.ox;
+  const int zc = r.valid ? z : o.zs;
+  r.off = o.plane_off + (size_t)zc * a->g.X + o.xo0 + r.ox;
+  r.soff = (size_t)o.y * a->obs_sy + (size_t)zc * a->obs_sz + o.xo0 + r.ox;
   return r;
 }
 
@@ -374,10 +378,33 @@ struct Epi {
   static constexpr int nbuf = nops > 0 ? nops : 1;
 };
 
+// Epilogue operands of one item: float32 values, or for uint16 observations
+// the raw 16-bit pairs (converted where they are used, so the loads can stay
+// in flight through the column pass).
+template <int EP, int NV>
+struct Ops {
+  float f[NV][Epi<EP>::nbuf][NX];
+};
+template <int NV>
+struct Ops<kEpRatioU16, NV> {
+  uint32_t u[NV][NX / 2];
+};
+
 template <int EP>
 __device__ __forceinline__ const float *op_ptr(KArg *a, int v, int k) {
-  if (EP == kEpRatio || EP == kEpBR) return a->phi[v];
+  if (EP == kEpBR) return a->phi[v];
   return k == 0 ? a->aux0[v] : a->aux1[v];
+}
+
+// φ of element n of an item for the ratio epilogues.
+template <int EP, int NV>
+__device__ __forceinline__ float obs_at(const Ops<EP, NV> &ops, int v, int n) {
+  if constexpr (EP == kEpRatioU16)
+    return (float)((ops.u[v][n >> 1] >> (16 * (n & 1))) & 0xffffu);
+  else if constexpr (EP == kEpRatio)
+    return fmaxf(ops.f[v][0][n], 0.f);
+  else
+    return ops.f[v][0][n];
 }
 
 // Quotient n / d by the reciprocal refined with one Newton-Raphson correction
@@ -398,45 +425,67 @@ __device__ __forceinline__ float guarded_ratio(float phi, float b) {
 
 template <int KB, int NV, int EP, int VM>
 __device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
-                                                const float (&ops)[NV][Epi<EP>::nbuf][NX]) {
+                                                const Ops<EP, NV> &ops) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     float b[NX];
     xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, a->tx[v], b);
     float r[NX];
-    if constexpr (EP == kEpRatio) {
+    if constexpr (EP == kEpRatio || EP == kEpRatioU16) {
 #pragma unroll
-      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(ops[v][0][n], b[n]);
+      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(obs_at(ops, v, n), b[n]);
       store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, r);
     } else if constexpr (EP == kEpStore) {
       store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, b);
     } else if constexpr (EP == kEpBR) {
 #pragma unroll
-      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(ops[v][0][n], b[n]);
+      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(obs_at(ops, v, n), b[n]);
       store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, b);
       store8<VM>(a->out2[v] + itm.off, itm.nvalid, vec, r);
     } else if constexpr (EP == kEpBbar) {
 #pragma unroll
       for (int n = 0; n < NX; ++n) {
-        const float bb = ops[v][1][n];
-        const float q = nr_quotient(b[n] * ops[v][0][n], bb);
+        const float bb = ops.f[v][1][n];
+        const float q = nr_quotient(b[n] * ops.f[v][0][n], bb);
         r[n] = bb > kEps ? -q : 0.f;
       }
       store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, r);
     } else {
 #pragma unroll
-      for (int n = 0; n < NX; ++n) r[n] = ops[v][0][n] + b[n];
+      for (int n = 0; n < NX; ++n) r[n] = ops.f[v][0][n] + b[n];
       store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, r);
     }
   }
 }
 
 template <int NV, int EP, int VM>
-__device__ __forceinline__ void load_ops(KArg *a, const Item &itm, bool vec, float (&ops)[NV][Epi<EP>::nbuf][NX]) {
+__device__ __forceinline__ void load_ops(KArg *a, const Item &itm, bool vec, Ops<EP, NV> &ops) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
+  for (int v = 0; v < NV; ++v) {
+    if constexpr (EP == kEpRatioU16) {
+      const uint16_t *p = static_cast<const uint16_t *>(a->obs[v]) + itm.soff;
+      if (vec_mode<VM>(vec)) {
+        const uint4 w = *reinterpret_cast<const uint4 *>(p);
+        ops.u[v][0] = w.x;
+        ops.u[v][1] = w.y;
+        ops.u[v][2] = w.z;
+        ops.u[v][3] = w.w;
+      } else {
 #pragma unroll
-    for (int k = 0; k < Epi<EP>::nops; ++k) load8<VM>(op_ptr<EP>(a, v, k) + itm.off, itm.nvalid, vec, ops[v][k]);
+        for (int h = 0; h < NX / 2; ++h) {
+          const uint32_t lo = 2 * h < itm.nvalid ? p[2 * h] : 0u;
+          const uint32_t hi = 2 * h + 1 < itm.nvalid ? p[2 * h + 1] : 0u;
+          ops.u[v][h] = lo | (hi << 16);
+        }
+      }
+    } else if constexpr (EP == kEpRatio) {
+      load8<VM>(static_cast<const float *>(a->obs[v]) + itm.soff, itm.nvalid, vec, ops.f[v][0]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < Epi<EP>::nops; ++k)
+        load8<VM>(op_ptr<EP>(a, v, k) + itm.off, itm.nvalid, vec, ops.f[v][k]);
+    }
+  }
 }
 
 // One ring phase: group i = i0 + u.  u is a compile-time constant so every
@@ -454,7 +503,7 @@ __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, S
   //    Memory loads retire in issue order, so the operands go first: the row
   //    pass can then wait for them while the rows stay in flight.
   const Item first = item_at(st.t, st, o, i, a);
-  float ops[NV][Epi<EP>::nbuf][NX];
+  Ops<EP, NV> ops;
   load_ops<NV, EP, VM>(a, first, st.vec, ops);
 #pragma unroll
   for (int g = 0; g < G; ++g)
@@ -474,7 +523,7 @@ __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, S
   for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
     const Item itm = item_at(it, st, o, i, a);
     if (!itm.valid) continue;
-    float q[NV][Epi<EP>::nbuf][NX];
+    Ops<EP, NV> q;
     load_ops<NV, EP, VM>(a, itm, st.vec, q);
     single_epilogue<KB, NV, EP, VM>(a, buf, itm, st.vec, q);
   }
@@ -627,30 +676,40 @@ inline hipError_t launch_with_lds(K kern, const SepPassArgs &a, int threads, siz
   return hipGetLastError();
 }
 
-template <int KB, int VM>
+template <int KB, int EP, int VM>
 hipError_t forward_bucket_vm(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes<KB>(a, a.nviews);
   const bool hi = p.occ >= 4;
   if constexpr (KB <= 41) {
     // two columns per thread only where the ring still fits (the planner never asks otherwise)
     if (p.cols == 2) {
-      if (a.nviews == 2)
-        return launch_with_lds(sep_forward_kernel<KB, 2, 2, 2, kEpRatio, VM>, a, p.threads, lds, s);
-      return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, kEpRatio, VM>, a, p.threads, lds, s);
+      if (a.nviews == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 2, 2, EP, VM>, a, p.threads, lds, s);
+      return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, EP, VM>, a, p.threads, lds, s);
     }
   }
   if (p.cols != 1) return hipErrorInvalidValue;
   if (a.nviews == 2) {
-    if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 2, 4, kEpRatio, VM>, a, p.threads, lds, s);
-    return launch_with_lds(sep_forward_kernel<KB, 1, 2, 2, kEpRatio, VM>, a, p.threads, lds, s);
+    if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 2, 4, EP, VM>, a, p.threads, lds, s);
+    return launch_with_lds(sep_forward_kernel<KB, 1, 2, 2, EP, VM>, a, p.threads, lds, s);
   }
-  if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, kEpRatio, VM>, a, p.threads, lds, s);
-  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, kEpRatio, VM>, a, p.threads, lds, s);
+  if (hi) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, EP, VM>, a, p.threads, lds, s);
+  return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, EP, VM>, a, p.threads, lds, s);
+}
+
+// 128-bit accesses also need the observations' rows in whole 16-byte units.
+inline bool obs_vec_ok(const SepPassArgs &a) {
+  const long unit = a.obs_u16 ? 8 : 4;
+  bool ok = a.obs_sy % unit == 0 && a.obs_sz % unit == 0;
+  for (int v = 0; v < a.nviews; ++v) ok = ok && (uintptr_t)a.obs[v] % 16 == 0;
+  return ok;
 }
 
 template <int KB>
 hipError_t forward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
-  return a.vec ? forward_bucket_vm<KB, 1>(a, p, s) : forward_bucket_vm<KB, 0>(a, p, s);
+  if (a.vec && !obs_vec_ok(a)) return hipErrorInvalidValue;
+  if (a.obs_u16)
+    return a.vec ? forward_bucket_vm<KB, kEpRatioU16, 1>(a, p, s) : forward_bucket_vm<KB, kEpRatioU16, 0>(a, p, s);
+  return a.vec ? forward_bucket_vm<KB, kEpRatio, 1>(a, p, s) : forward_bucket_vm<KB, kEpRatio, 0>(a, p, s);
 }
 
 // One-view single-input pass with an adjoint epilogue (kStore, kBR, kBbar, kAccum).

@@ -559,8 +559,42 @@ const float *dtaps(const mvd_ctx *c, int v, int which) {
 }
 
 // Forward pass over views [v0, v0+n): r[v] = φ_v / (psi ⊛ P_v)
-hipError_t forward_views(const RunState &st, const float *psi, const float *const *phi, float *const *r,
-                         int v0, int n) {
+// Observations as the forward pass reads them: the arrays as given (float32 or
+// uint16, plane or stack layout, read through strides) for the separable
+// passes; float32 planes staged in the workspace for the general passes
+// (null where no view needs them).
+struct ObsRef {
+  const void *const *p;
+  bool u16;
+  long sy, sz;
+  const float *const *staged;
+};
+
+ObsRef obs_given(const void *const *obs, int dtype, int layout, const PlaneGeom &g, const float *const *staged) {
+  ObsRef o{obs, dtype == MVD_U16, 0, 0, staged};
+  if (layout == MVD_STACK_ZYX) {
+    o.sy = g.X;
+    o.sz = (long)g.Y * g.X;
+  } else {
+    o.sy = (long)g.Z * g.X;
+    o.sz = g.X;
+  }
+  return o;
+}
+
+ObsRef obs_staged(const float *const *staged, const PlaneGeom &g) {
+  return ObsRef{reinterpret_cast<const void *const *>(staged), false, (long)g.Z * g.X, g.X, staged};
+}
+
+// The forward passes of a run take the general K×K form for some view.
+bool run_needs_2d(const RunState &st) {
+  if (st.force2d) return true;
+  for (int v = 0; v < st.c->nv; ++v)
+    if (!st.c->views[v].sep_p) return true;
+  return false;
+}
+
+hipError_t forward_views(const RunState &st, const float *psi, const ObsRef &ob, float *const *r, int v0, int n) {
   mvd_ctx *c = st.c;
   bool sep = !st.force2d;
   int kmax = 1;
@@ -580,15 +614,19 @@ hipError_t forward_views(const RunState &st, const float *psi, const float *cons
       fill_sep_common(a, sg, st.g, st.boundary);
       a.nviews = nb;
       a.in[0] = psi;
+      a.obs_u16 = ob.u16 ? 1 : 0;
+      a.obs_sy = ob.sy;
+      a.obs_sz = ob.sz;
       for (int k = 0; k < nb; ++k) {
         const ViewPsf &w = c->views[b + k];
-        a.phi[k] = phi[b + k];
+        a.obs[k] = ob.p[b + k];
         a.out[k] = r[b + k];
         put_factor(a.tz[k], w.pz, sg.plan.bucket);
         put_factor(a.tx[k], w.px, sg.plan.bucket);
       }
-      a.vec = whole_items(sg, st.g) && aligned16(psi);
-      for (int k = 0; k < nb; ++k) a.vec = a.vec && aligned16(a.phi[k]) && aligned16(a.out[k]);
+      const long unit = ob.u16 ? 8 : 4;   // elements per 16 bytes
+      a.vec = whole_items(sg, st.g) && aligned16(psi) && ob.sy % unit == 0 && ob.sz % unit == 0;
+      for (int k = 0; k < nb; ++k) a.vec = a.vec && aligned16(a.obs[k]) && aligned16(a.out[k]);
       hipError_t e = timed(st, 0, [&] { return launch_sep_forward(a, sg.plan, st.s); });
       if (e != hipSuccess) return e;
     }
@@ -604,8 +642,9 @@ hipError_t forward_views(const RunState &st, const float *psi, const float *cons
     a.kx = c->kxm;
     a.in[0] = psi;
     a.mfma = st.tn->valu2d ? 0 : 1;
+    if (!ob.staged) return hipErrorInvalidValue;
     for (int k = 0; k < nb; ++k) {
-      a.phi[k] = phi[b + k];
+      a.phi[k] = ob.staged[b + k];
       a.out[k] = r[b + k];
       a.taps[k] = dtaps(c, b + k, 0);
     }
@@ -877,19 +916,22 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
   char *ws = static_cast<char *>(r->workspace);
   RunState rs{c,  g, r->boundary, (r->flags & MVD_FLAG_FORCE_2D) != 0, s, r->view_weights,
               timing_override || (r->flags & MVD_FLAG_TIMING) != 0, &tn};
-  std::vector<const float *> phi(c->nv);
+  // the separable forward passes read the observations as given; only the
+  // general K×K passes need them staged as float32 planes
+  const bool need_staged = run_needs_2d(rs);
   std::vector<float *> staged(c->nv);
-  for (int v = 0; v < c->nv; ++v) {
-    staged[v] = reinterpret_cast<float *>(ws + L.phi_off + (size_t)v * L.plane_set);
-    phi[v] = staged[v];
-  }
+  for (int v = 0; v < c->nv; ++v) staged[v] = reinterpret_cast<float *>(ws + L.phi_off + (size_t)v * L.plane_set);
+  const ObsRef ob = obs_given(obs, r->obs_dtype, r->obs_layout, g, need_staged ? staged.data() : nullptr);
   const int T = r->n_iters;
   float *psi0 = (r->checkpoints && T > 0) ? r->checkpoints : est;
-  // observations of every view staged in one pass, with ψ^0 = their mean when asked
+  // one pass over the observations: the staged planes where needed, and ψ^0 = their mean when asked
   float *mean = r->init == MVD_INIT_MEAN ? psi0 : nullptr;
-  hipError_t e = timed(rs, 2, [&] {
-    return launch_stage_views(obs, c->nv, r->obs_dtype, r->obs_layout, g, staged.data(), mean, s);
-  });
+  hipError_t e = hipSuccess;
+  if (need_staged || mean)
+    e = timed(rs, 2, [&] {
+      return launch_stage_views(obs, c->nv, r->obs_dtype, r->obs_layout, g, need_staged ? staged.data() : nullptr,
+                                mean, s);
+    });
   if (e == hipSuccess && r->init == MVD_INIT_CONST)
     e = timed(rs, 2, [&] { return launch_fill(psi0, n, r->init_const, s); });
   else if (e == hipSuccess && r->init == MVD_INIT_GIVEN && psi0 != est)
@@ -900,13 +942,13 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
     float *cur = r->checkpoints ? r->checkpoints + (size_t)t * n : est;
     float *nxt = r->checkpoints ? (t + 1 < T ? r->checkpoints + (size_t)(t + 1) * n : est) : est;
     if (r->update == MVD_UPDATE_SIMULTANEOUS) {
-      e = forward_views(rs, cur, phi.data(), rat.data(), 0, c->nv);
+      e = forward_views(rs, cur, ob, rat.data(), 0, c->nv);
       if (e == hipSuccess) e = backward_views(rs, rat.data(), cur, nxt, 0, c->nv);
     } else {
       for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
         const float *src = v == 0 ? cur : nxt;
         std::vector<float *> rv(c->nv, rat[0]);
-        e = forward_views(rs, src, phi.data(), rv.data(), v, 1);
+        e = forward_views(rs, src, ob, rv.data(), v, 1);
         if (e == hipSuccess) e = backward_views(rs, rv.data(), src, nxt, v, 1);
       }
     }
@@ -1635,7 +1677,7 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
       for (int v = 0; v + 1 < V && e == hipSuccess; ++v) {
         float *dst = plane(L.sub_off, v);
         std::vector<float *> rv(V, rat);
-        e = forward_views(rs, sub[v], phi.data(), rv.data(), v, 1);
+        e = forward_views(rs, sub[v], obs_staged(staged.data(), g), rv.data(), v, 1);
         if (e == hipSuccess) e = backward_views(rs, rv.data(), sub[v], dst, v, 1);
         sub[v + 1] = dst;
       }

@@ -54,7 +54,10 @@ struct SepPassArgs {
   int ldsw;           // LDS row pitch in floats
   int vec;            // every plane pointer of the pass is 16-byte aligned
   const float *in[kSepFwdViews];      // forward: in[0] = ψ; backward: in[v] = r_v
-  const float *phi[kSepFwdViews];     // forward: observations (float32 planes)
+  const float *phi[kSepFwdViews];     // adjoint recompute: staged observations (float32 planes)
+  const void *obs[kSepFwdViews];      // forward: observations as given, float32 or uint16 (obs_u16)
+  long obs_sy, obs_sz;                // element (y, z, x) of obs[v] at y·obs_sy + z·obs_sz + x
+  int obs_u16;
   float *out[kSepFwdViews];           // forward: ratio planes
   float *out2[kSepFwdViews];          // second output (adjoint recompute: ratio planes)
   const float *aux0[kSepFwdViews];    // epilogue operands (adjoint passes)
@@ -100,7 +103,8 @@ __host__ __device__ constexpr int mfma_tile_width(int nck) {
 size_t mfma_lds_bytes(int kz, int kx);
 
 // Epilogues of the single-input separable pass.
-constexpr int kEpRatio = 0;   // out = φ / conv (guarded)
+constexpr int kEpRatio = 0;   // out = φ / conv (guarded); φ float32 at obs (clamped at 0 when read)
+constexpr int kEpRatioU16 = 5;  // the same with φ uint16 at obs
 constexpr int kEpStore = 1;   // out = conv
 constexpr int kEpBR = 2;      // out = conv, out2 = φ / conv
 constexpr int kEpBbar = 3;    // out = −conv · aux0 / aux1 where aux1 > ε, else 0
@@ -177,6 +181,7 @@ hipError_t launch_stage_obs(const void *src, int dtype, int layout, PlaneGeom g,
                             hipStream_t s);
 // Every view's observations → float32 planes dst[v] in one pass, and
 // ψ^0 = (1/V) Σ_v φ_v into `mean` when it is not null.
+// Observations → float32 planes dst[v] (dst null: none written) and their mean (mean null: none).
 hipError_t launch_stage_views(const void *const *src, int nv, int dtype, int layout, PlaneGeom g,
                               float *const *dst, float *mean, hipStream_t s);
 // ψ^0 = (1/V) Σ_v φ_v

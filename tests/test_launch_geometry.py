@@ -95,12 +95,15 @@ def check_geometry(Y, Z, X, k, boundary, views):
                     assert 0 <= rr * X < plane
             else:
                 assert 0 <= (rr % Z) < Z
-        # clamped item rows
+        # clamped item rows; the forward pass reads the observations at
+        # y·sy + z·sz + x in the layout they were given in (stack or planes)
         for i in range(ngroups):
             for g in range(G):
                 z = zs + i * G + g
                 zc = z if z < ze else zs
                 assert 0 <= zc < Z
+                for sy, sz in ((X, Y * X), (Z * X, X)):
+                    assert (Y - 1) * sy + zc * sz + X <= Y * Z * X
 
 
 SHAPES = [
