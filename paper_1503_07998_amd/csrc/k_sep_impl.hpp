@@ -74,11 +74,19 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int KB>
 __device__ __forceinline__ void fill_tap_table(float *TT, KArg *a, int nviews, int t, int nt) {
   constexpr int NK = Shape<KB>::NK;
-  for (int e = t; e < nviews * 4 * NK; e += nt) {
-    const int v = e / (4 * NK), i = (e / NK) % 4, k = e % NK;
+  for (int e = t; e < nviews * 8 * NK; e += nt) {
+    const int v = e / (8 * NK), x = (e / (4 * NK)) & 1, i = (e / NK) % 4, k = e % NK;
     const int j = i + KB - 1 - k;
-    TT[e] = (j >= 0 && j < KB) ? a->tz[v][j] : 0.f;
+    TT[e] = (j >= 0 && j < KB) ? (x ? a->tx[v][j] : a->tz[v][j]) : 0.f;
   }
+}
+
+// Tap tables of view v: [4][NK] for the column pass, then [4][NK] for the row pass.
+template <int KB>
+__device__ __forceinline__ const float *ztab(const float *tt, int v) { return tt + v * 8 * Shape<KB>::NK; }
+template <int KB>
+__device__ __forceinline__ const float *xtab(const float *tt, int v) {
+  return tt + v * 8 * Shape<KB>::NK + 4 * Shape<KB>::NK;
 }
 
 // LDS-only barrier: waits for this wave's LDS traffic, not for its global
@@ -213,7 +221,7 @@ __device__ __forceinline__ void store_mid(float *B, int g, KArg *a, const Cols<C
 // every output it touches before the next read, so only a handful of inputs
 // are live: out[n] = Σ_i taps[i] · L[n + K − 1 − i].
 template <int KB>
-__device__ __forceinline__ void xconv(const float *L, KFloat *taps, float (&out)[NX]) {
+__device__ __forceinline__ void xconv_valu(const float *L, KFloat *taps, float (&out)[NX]) {
   using S = Shape<KB>;
 #pragma unroll
   for (int n = 0; n < NX; ++n) out[n] = 0.f;
@@ -231,6 +239,61 @@ __device__ __forceinline__ void xconv(const float *L, KFloat *taps, float (&out)
       }
     }
   }
+}
+
+// The same 8 outputs on the matrix cores, in two blocks of 4 (outputs 4b + i):
+// out[4b + i] = Σ_k TX[i][k] · L[4b + k], TX[i][k] = taps[i + K − 1 − k], the
+// row-pass form of the column pass's v_mfma_f32_4x4x1f32 scheme (B = this
+// lane's own input, A = TX[lane % 4][k]); K + 3 steps per block against 4K
+// vector multiply-adds.  Inputs are read 4 at a time; block 0 takes step k of
+// chunk k / 4, block 1 the step that input fed block 0 four steps earlier.
+// Every lane of the wave must take part (the caller keeps the loop uniform).
+template <int KB>
+__device__ __forceinline__ void xconv_mfma(const float *L, const float *TX, float (&out)[NX]) {
+  using S = Shape<KB>;
+  constexpr int NK = S::NK, KS = KB + 3;   // steps per block
+  const float *tl = TX + (threadIdx.x & 3) * NK;
+  f32x4 d0 = f32x4{0.f, 0.f, 0.f, 0.f}, d1 = f32x4{0.f, 0.f, 0.f, 0.f};
+  float tp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < S::NIN4; ++q) {
+    const float4 f = *reinterpret_cast<const float4 *>(L + 4 * q);
+    const float in4[4] = {f.x, f.y, f.z, f.w};
+    float tc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (4 * q < KS) {
+      const float4 t4 = *reinterpret_cast<const float4 *>(tl + 4 * q);
+      tc[0] = t4.x;
+      tc[1] = t4.y;
+      tc[2] = t4.z;
+      tc[3] = t4.w;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (4 * q + e < KS) d0 = __builtin_amdgcn_mfma_f32_4x4x1f32(tc[e], in4[e], d0, 0, 0, 0);
+      if (q >= 1 && 4 * (q - 1) + e < KS) d1 = __builtin_amdgcn_mfma_f32_4x4x1f32(tp[e], in4[e], d1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) tp[e] = tc[e];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    out[i] = d0[i];
+    out[4 + i] = d1[i];
+  }
+}
+
+#ifndef MVD_ROW_MFMA
+#define MVD_ROW_MFMA 1
+#endif
+
+// Row pass of one item from LDS row L: matrix cores (default) or vector ALUs.
+template <int KB>
+__device__ __forceinline__ void xconv(const float *L, const float *TX, KFloat *taps, float (&out)[NX]) {
+#if MVD_ROW_MFMA
+  xconv_mfma<KB>(L, TX, out);
+#else
+  xconv_valu<KB>(L, taps, out);
+#endif
 }
 
 // Per-work-group constants of a pass.
@@ -423,13 +486,16 @@ __device__ __forceinline__ float guarded_ratio(float phi, float b) {
   return b > kEps ? q : 1.f;
 }
 
+// Row pass and epilogue of one item for every view; the row pass runs on every
+// lane (invalid items at clamped addresses), only valid items store.
 template <int KB, int NV, int EP, int VM>
-__device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
-                                                const Ops<EP, NV> &ops) {
+__device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const float *tt, const Item &itm,
+                                                bool vec, const Ops<EP, NV> &ops) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     float b[NX];
-    xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, a->tx[v], b);
+    xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, xtab<KB>(tt, v), a->tx[v], b);
+    if (!itm.valid) continue;
     float r[NX];
     if constexpr (EP == kEpRatio || EP == kEpRatioU16) {
 #pragma unroll
@@ -514,18 +580,17 @@ __device__ __forceinline__ void fwd_group(KArg *a, const Geo &o, const Cols<C, S
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     float acc[C][G];
-    zpass<KB, C, u>(st.tt + v * 4 * Shape<KB>::NK, ring, acc);
+    zpass<KB, C, u>(ztab<KB>(st.tt, v), ring, acc);
     store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
   }
   lds_sync();
-  // 3. row pass + epilogue
-  if (first.valid) single_epilogue<KB, NV, EP, VM>(a, buf, first, st.vec, ops);
-  for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
-    const Item itm = item_at(it, st, o, i, a);
-    if (!itm.valid) continue;
+  // 3. row pass + epilogue, in wave-uniform steps over the items
+  single_epilogue<KB, NV, EP, VM>(a, buf, st.tt, first, st.vec, ops);
+  for (int base = st.nt; base < st.nitems; base += st.nt) {
+    const Item itm = item_at(base + st.t, st, o, i, a);
     Ops<EP, NV> q;
     load_ops<NV, EP, VM>(a, itm, st.vec, q);
-    single_epilogue<KB, NV, EP, VM>(a, buf, itm, st.vec, q);
+    single_epilogue<KB, NV, EP, VM>(a, buf, st.tt, itm, st.vec, q);
   }
 }
 
@@ -566,18 +631,18 @@ __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_forward_kernel(const 
 // Backward pass: VIN ratio planes → ψ' = ψ · Π_v (w_v q_v + 1 − w_v).
 // ---------------------------------------------------------------------------
 template <int KB, int VIN, int VM>
-__device__ __forceinline__ void bwd_epilogue(KArg *a, const float *buf, const Item &itm, bool vec,
+__device__ __forceinline__ void bwd_epilogue(KArg *a, const float *buf, const float *tt, const Item &itm, bool vec,
                                              float (&ps)[NX]) {
   // ψ · c_0 · c_1 … applied view by view: the same rounding as one launch per view
 #pragma unroll
   for (int v = 0; v < VIN; ++v) {
     float q[NX];
-    xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, a->tx[v], q);
+    xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, xtab<KB>(tt, v), a->tx[v], q);
     const float w = a->w[v], w1 = 1.f - w;
 #pragma unroll
     for (int n = 0; n < NX; ++n) ps[n] *= fmaf(w, q[n], w1);
   }
-  store8<VM>(a->psi_out + itm.off, itm.nvalid, vec, ps);
+  if (itm.valid) store8<VM>(a->psi_out + itm.off, itm.nvalid, vec, ps);
 }
 
 template <int KB, int C, int VIN, int VM, int u>
@@ -595,7 +660,7 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
 #pragma unroll
   for (int v = 0; v < VIN; ++v) {
     float acc[C][G];
-    zpass<KB, C, u>(st.tt + v * 4 * Shape<KB>::NK, ring[v], acc);
+    zpass<KB, C, u>(ztab<KB>(st.tt, v), ring[v], acc);
     store_group<KB, C>(buf + v * G * lds_pitch(a), a, cl, acc);
   }
   const Item first = item_at(st.t, st, o, i, a);
@@ -610,13 +675,12 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
                      &ring[v][0][((u + 1) * G + KB - 1 + g) % M], M);
   }
   lds_sync();
-  if (first.valid) bwd_epilogue<KB, VIN, VM>(a, buf, first, st.vec, ps);
-  for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
-    const Item itm = item_at(it, st, o, i, a);
-    if (!itm.valid) continue;
+  bwd_epilogue<KB, VIN, VM>(a, buf, st.tt, first, st.vec, ps);
+  for (int base = st.nt; base < st.nitems; base += st.nt) {
+    const Item itm = item_at(base + st.t, st, o, i, a);
     float q[NX];
     load8<VM>(a->psi_in + itm.off, itm.nvalid, st.vec, q);
-    bwd_epilogue<KB, VIN, VM>(a, buf, itm, st.vec, q);
+    bwd_epilogue<KB, VIN, VM>(a, buf, st.tt, itm, st.vec, q);
   }
 }
 
@@ -653,10 +717,10 @@ __global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_backward_kernel(const
     bwd_phases<KB, C, VIN, VM>(a, o, cl, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
 }
 
-// Double-buffered column-pass rows and the column pass's tap tables.
+// Double-buffered column-pass rows and the tap tables of both passes.
 template <int KB>
 inline size_t lds_bytes(const SepPassArgs &a, int nviews) {
-  return sizeof(float) * (2ull * nviews * G * a.ldsw + (size_t)nviews * 4 * Shape<KB>::NK);
+  return sizeof(float) * (2ull * nviews * G * a.ldsw + (size_t)nviews * 8 * Shape<KB>::NK);
 }
 
 template <typename K>
@@ -771,7 +835,7 @@ __device__ __forceinline__ void bwd_split_group(KArg *a, const Geo &o, const Col
   float *buf = lds + (i & 1) * st.bufsz;
   {
     float acc[1][G];
-    zpass<KB, 1, u>(st.tt + view * 4 * Shape<KB>::NK, ring, acc);
+    zpass<KB, 1, u>(ztab<KB>(st.tt, view), ring, acc);
     store_group<KB, 1>(buf + view * G * lds_pitch(a), a, cl, acc);
   }
   const Item first = item_at(st.t, st, o, i, a);
@@ -782,13 +846,12 @@ __device__ __forceinline__ void bwd_split_group(KArg *a, const Geo &o, const Col
   for (int g = 0; g < G; ++g)
     load_row<1, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl, &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
   lds_sync();
-  if (first.valid) bwd_epilogue<KB, 2, VM>(a, buf, first, st.vec, ps);
-  for (int it = st.t + st.nt; it < st.nitems; it += st.nt) {
-    const Item itm = item_at(it, st, o, i, a);
-    if (!itm.valid) continue;
+  bwd_epilogue<KB, 2, VM>(a, buf, st.tt, first, st.vec, ps);
+  for (int base = st.nt; base < st.nitems; base += st.nt) {
+    const Item itm = item_at(base + st.t, st, o, i, a);
     float q[NX];
     load8<VM>(a->psi_in + itm.off, itm.nvalid, st.vec, q);
-    bwd_epilogue<KB, 2, VM>(a, buf, itm, st.vec, q);
+    bwd_epilogue<KB, 2, VM>(a, buf, st.tt, itm, st.vec, q);
   }
 }
 

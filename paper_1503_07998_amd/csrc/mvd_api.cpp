@@ -465,15 +465,15 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn =
 }
 
 // LDS of one view in a separable pass: double-buffered column-pass rows and the
-// column pass's [4][NK] tap table (NK = bucket + 3 rounded up to 4).
+// two passes' [4][NK] tap tables (NK = bucket + 3 rounded up to 4).
 size_t sep_lds_per_view(const SepGeom &sg) {
-  return sizeof(float) * (2ull * kRowGroup * sg.ldsw + 4ull * ((sg.plan.bucket + 3 + 3) / 4 * 4));
+  return sizeof(float) * (2ull * kRowGroup * sg.ldsw + 8ull * ((sg.plan.bucket + 3 + 3) / 4 * 4));
 }
 
 // Split-view backward: two views' double-buffered 16-row groups and tap tables.
 constexpr int kSplitRows = 16;
 size_t split_lds_bytes(const SepGeom &sg) {
-  return sizeof(float) * (2ull * 2 * kSplitRows * sg.ldsw + 2ull * 4 * ((sg.plan.bucket + 3 + 3) / 4 * 4));
+  return sizeof(float) * (2ull * 2 * kSplitRows * sg.ldsw + 2ull * 8 * ((sg.plan.bucket + 3 + 3) / 4 * 4));
 }
 
 // Geometry of the split-view form from a two-plane plan, or false where it does

@@ -211,7 +211,7 @@ def test_split_view_backward_in_bounds(shape, k):
     assert half >= X, "each half must hold one column per thread"
     assert p["zseg"] % GS == 0 and p["nseg"] * p["zseg"] >= Z and (p["nseg"] - 1) * p["zseg"] < Z
     NK = (KB + 3 + 3) // 4 * 4
-    assert p["lds"] == 4 * (2 * 2 * GS * ldsw + 2 * 4 * NK) <= LDS_LIMIT
+    assert p["lds"] == 4 * (2 * 2 * GS * ldsw + 2 * 8 * NK) <= LDS_LIMIT
     # columns: LDS column lc + R of each view's rows, pads R and beyond X
     assert R + X <= ldsw
     nxb = (X + NX - 1) // NX
