@@ -251,6 +251,25 @@ def test_dtypes_and_layouts(dtype, layout):
     check(got, ref)
 
 
+@pytest.mark.parametrize("shape", [(24, 5, 40), (13, 3, 37), (9, 4, 66), (40, 2, 8)],
+                         ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("update", ["simultaneous", "sequential"])
+def test_observation_forms_bitwise(shape, update):
+    """The forward passes read the observations in place (uint16 or float32,
+    stack or plane layout, 16-byte or element-wise accesses): the same values
+    in any of the four forms give bitwise the same estimate."""
+    _say(f"observation forms {shape} {update}")
+    rng = np.random.default_rng(31)
+    psfs = [gaussian_psf(7, 1.2, 2.5).astype(np.float32), gaussian_psf(7, 2.5, 1.2).astype(np.float32)]
+    stacks = [rng.integers(0, 3000, size=shape, dtype=np.uint16) for _ in range(2)]
+    planes = [np.ascontiguousarray(np.transpose(s, (1, 0, 2))) for s in stacks]
+    ref = gpu_run(stacks, psfs, 3, update=update)
+    for obs, layout in (([s.astype(np.float32) for s in stacks], "stack_zyx"), (planes, "planes_yzx"),
+                        ([p.astype(np.float32) for p in planes], "planes_yzx")):
+        got = gpu_run(obs, psfs, 3, layout=layout, update=update)
+        np.testing.assert_array_equal(got, ref)
+
+
 def test_division_guard():
     _say("division guard")
     rng = np.random.default_rng(13)
