@@ -50,6 +50,7 @@ struct StageViews {
   float *dst[kMaxViews];
   float *mean;   // ψ^0 = (1/V) Σ_v φ_v, or null
   int nv, dtype, layout, vec;
+  int ysrc;   // planes of the source stack (its y stride is X, its z stride ysrc·X)
   PlaneGeom g;
 };
 
@@ -72,7 +73,7 @@ __global__ void __launch_bounds__(NT) stage_views_kernel(StageViews a) {
   const float nvf = (float)a.nv;
   for (size_t rr = (size_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6); rr < nrows; rr += nwaves) {
     const size_t y = rr / a.g.Z, z = rr - y * a.g.Z;
-    const size_t srow = a.layout == 1 ? (z * a.g.Y + y) * X : rr * X;
+    const size_t srow = a.layout == 1 ? (z * a.ysrc + y) * X : rr * X;
     const size_t drow = rr * X;
     if (a.vec) {
       for (size_t x = 4 * (size_t)lane; x < X; x += 256) {
@@ -140,7 +141,7 @@ hipError_t launch_stage_obs(const void *src, int dtype, int layout, PlaneGeom g,
 }
 
 hipError_t launch_stage_views(const void *const *src, int nv, int dtype, int layout, PlaneGeom g,
-                              float *const *dst, float *mean, hipStream_t s) {
+                              float *const *dst, float *mean, hipStream_t s, int ysrc) {
   const size_t rows = (size_t)g.Y * g.Z;
   if (rows == 0 || g.X == 0) return hipSuccess;
   if (nv < 1 || nv > kMaxViews) return hipErrorInvalidValue;
@@ -148,6 +149,7 @@ hipError_t launch_stage_views(const void *const *src, int nv, int dtype, int lay
   a.nv = nv;
   a.dtype = dtype;
   a.layout = layout;
+  a.ysrc = ysrc > 0 ? ysrc : g.Y;
   a.g = g;
   a.mean = mean;
   const uintptr_t sa = dtype == 1 ? 8 : 16;

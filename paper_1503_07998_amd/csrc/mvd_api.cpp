@@ -362,6 +362,7 @@ struct Tune {
   int bwd_split = 0;    // two-view backward as one 1024-thread work-group per row segment (half
                         // the threads per view, 16-row groups): 0 where it applies, 2 never
   int valu_corr = 0;    // 1: tap-gradient correlation on the vector ALUs instead of the matrix cores
+  int plane_batch = 0;  // > 0: run this many planes through all iterations at a time
 };
 
 Tune parse_tune(const char *e) {
@@ -389,6 +390,7 @@ Tune parse_tune(const char *e) {
       if (k == "threads") r.threads = v;
       if (k == "bwd_threads") r.bwd_threads = v;
       if (k == "bwd_split") r.bwd_split = v;
+      if (k == "plane_batch") r.plane_batch = v;
     }
     pos = comma + 1;
   }
@@ -907,7 +909,16 @@ mvd_status validate_run(mvd_ctx *c, const void *const *obs, const float *est, co
   return MVD_OK;
 }
 
-// Enqueue reslice/convert, ψ^0 and every iteration of a validated run on `s`.
+// Planes per batch of the plane-blocked schedule (the whole volume: iteration-major).
+int plane_batch(const mvd_run *r, const Tune &tn) {
+  if (tn.plane_batch > 0) return std::min(tn.plane_batch, r->n_planes);
+  return r->n_planes;
+}
+
+// Enqueue ψ^0 and every iteration of a validated run on `s`.  Planes are
+// independent, so the run may go batch by batch of planes, each batch through
+// all T iterations (a batch that fits the last-level cache keeps its working
+// set there); the results do not depend on the batch size.
 hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, hipStream_t s,
                        const Tune &tn, bool timing_override = false) {
   const Layout L = layout_of(c, r);
@@ -921,35 +932,50 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
   const bool need_staged = run_needs_2d(rs);
   std::vector<float *> staged(c->nv);
   for (int v = 0; v < c->nv; ++v) staged[v] = reinterpret_cast<float *>(ws + L.phi_off + (size_t)v * L.plane_set);
-  const ObsRef ob = obs_given(obs, r->obs_dtype, r->obs_layout, g, need_staged ? staged.data() : nullptr);
-  const int T = r->n_iters;
-  float *psi0 = (r->checkpoints && T > 0) ? r->checkpoints : est;
-  // one pass over the observations: the staged planes where needed, and ψ^0 = their mean when asked
-  float *mean = r->init == MVD_INIT_MEAN ? psi0 : nullptr;
-  hipError_t e = hipSuccess;
-  if (need_staged || mean)
-    e = timed(rs, 2, [&] {
-      return launch_stage_views(obs, c->nv, r->obs_dtype, r->obs_layout, g, need_staged ? staged.data() : nullptr,
-                                mean, s);
-    });
-  if (e == hipSuccess && r->init == MVD_INIT_CONST)
-    e = timed(rs, 2, [&] { return launch_fill(psi0, n, r->init_const, s); });
-  else if (e == hipSuccess && r->init == MVD_INIT_GIVEN && psi0 != est)
-    e = timed(rs, 2, [&] { return launch_copy(est, psi0, n, s); });
   std::vector<float *> rat(L.n_ratio);
   for (int k = 0; k < L.n_ratio; ++k) rat[k] = reinterpret_cast<float *>(ws + L.r_off + (size_t)k * L.plane_set);
-  for (int t = 0; t < T && e == hipSuccess; ++t) {
-    float *cur = r->checkpoints ? r->checkpoints + (size_t)t * n : est;
-    float *nxt = r->checkpoints ? (t + 1 < T ? r->checkpoints + (size_t)(t + 1) * n : est) : est;
-    if (r->update == MVD_UPDATE_SIMULTANEOUS) {
-      e = forward_views(rs, cur, ob, rat.data(), 0, c->nv);
-      if (e == hipSuccess) e = backward_views(rs, rat.data(), cur, nxt, 0, c->nv);
-    } else {
-      for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
-        const float *src = v == 0 ? cur : nxt;
-        std::vector<float *> rv(c->nv, rat[0]);
-        e = forward_views(rs, src, ob, rv.data(), v, 1);
-        if (e == hipSuccess) e = backward_views(rs, rv.data(), src, nxt, v, 1);
+  const ObsRef whole = obs_given(obs, r->obs_dtype, r->obs_layout, g, nullptr);
+  const size_t esz = r->obs_dtype == MVD_U16 ? 2 : 4;
+  const int T = r->n_iters;
+  const int B = plane_batch(r, tn);
+  hipError_t e = hipSuccess;
+  for (int y0 = 0; y0 < g.Y && e == hipSuccess; y0 += B) {
+    const PlaneGeom gb{std::min(B, g.Y - y0), g.Z, g.X};
+    const size_t nb = (size_t)gb.Y * g.Z * g.X, off = (size_t)y0 * g.Z * g.X;
+    RunState rb = rs;
+    rb.g = gb;
+    // this batch's observations: the same strides, starting at plane y0 (the
+    // staged planes and ratio planes of a batch are the first planes of their sets)
+    std::vector<const void *> ob_p(c->nv);
+    for (int v = 0; v < c->nv; ++v) ob_p[v] = static_cast<const char *>(obs[v]) + (size_t)y0 * whole.sy * esz;
+    const ObsRef ob{ob_p.data(), whole.u16, whole.sy, whole.sz, need_staged ? staged.data() : nullptr};
+    float *est_b = est + off;
+    auto slot = [&](int t) { return r->checkpoints + (size_t)t * n + off; };
+    float *psi0 = (r->checkpoints && T > 0) ? slot(0) : est_b;
+    // one pass over the observations: the staged planes where needed, and ψ^0 = their mean when asked
+    float *mean = r->init == MVD_INIT_MEAN ? psi0 : nullptr;
+    if (need_staged || mean)
+      e = timed(rb, 2, [&] {
+        return launch_stage_views(ob_p.data(), c->nv, r->obs_dtype, r->obs_layout, gb,
+                                  need_staged ? staged.data() : nullptr, mean, s, g.Y);
+      });
+    if (e == hipSuccess && r->init == MVD_INIT_CONST)
+      e = timed(rb, 2, [&] { return launch_fill(psi0, nb, r->init_const, s); });
+    else if (e == hipSuccess && r->init == MVD_INIT_GIVEN && psi0 != est_b)
+      e = timed(rb, 2, [&] { return launch_copy(est_b, psi0, nb, s); });
+    for (int t = 0; t < T && e == hipSuccess; ++t) {
+      float *cur = r->checkpoints ? slot(t) : est_b;
+      float *nxt = r->checkpoints ? (t + 1 < T ? slot(t + 1) : est_b) : est_b;
+      if (r->update == MVD_UPDATE_SIMULTANEOUS) {
+        e = forward_views(rb, cur, ob, rat.data(), 0, c->nv);
+        if (e == hipSuccess) e = backward_views(rb, rat.data(), cur, nxt, 0, c->nv);
+      } else {
+        for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
+          const float *src = v == 0 ? cur : nxt;
+          std::vector<float *> rv(c->nv, rat[0]);
+          e = forward_views(rb, src, ob, rv.data(), v, 1);
+          if (e == hipSuccess) e = backward_views(rb, rv.data(), src, nxt, v, 1);
+        }
       }
     }
   }
@@ -1160,9 +1186,10 @@ hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mv
 
 // ---- autotuner ----------------------------------------------------------------
 // Launch-shape candidates timed per workload (kernel sizes, plane shape, planes,
-// views, update order, boundary); the fastest is cached for the process.
+// views, update order, boundary); the fastest is cached for the process.  Each
+// candidate starts from the process-wide overrides.
 std::vector<Tune> tune_candidates() {
-  std::vector<Tune> c(10);
+  std::vector<Tune> c(10, tune());
   c[1].fwd_occ = 2;
   c[2].fwd_views = 1;
   c[3].bwd_vin = 1;      // one ratio plane per backward launch

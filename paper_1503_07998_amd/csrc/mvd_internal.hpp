@@ -182,8 +182,9 @@ hipError_t launch_stage_obs(const void *src, int dtype, int layout, PlaneGeom g,
 // Every view's observations → float32 planes dst[v] in one pass, and
 // ψ^0 = (1/V) Σ_v φ_v into `mean` when it is not null.
 // Observations → float32 planes dst[v] (dst null: none written) and their mean (mean null: none).
+// A camera stack source may hold more planes than g.Y (ysrc; 0: g.Y), src pointing at plane y0.
 hipError_t launch_stage_views(const void *const *src, int nv, int dtype, int layout, PlaneGeom g,
-                              float *const *dst, float *mean, hipStream_t s);
+                              float *const *dst, float *mean, hipStream_t s, int ysrc = 0);
 // ψ^0 = (1/V) Σ_v φ_v
 hipError_t launch_init_mean(const float *const *phis, int nv, size_t n, float *dst,
                             hipStream_t s);

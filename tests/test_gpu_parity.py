@@ -270,6 +270,52 @@ def test_observation_forms_bitwise(shape, update):
         np.testing.assert_array_equal(got, ref)
 
 
+@pytest.mark.parametrize("batch", [1, 3, 7])
+@pytest.mark.parametrize("update,layout,dtype", [("simultaneous", "stack_zyx", "u16"),
+                                                  ("sequential", "planes_yzx", "f32"),
+                                                  ("simultaneous", "planes_yzx", "u16")])
+def test_plane_batches_bitwise(batch, update, layout, dtype):
+    """Planes are independent: running the volume batch by batch of planes
+    (each batch through every iteration) gives bitwise the whole-volume
+    result, with checkpoints at the same slots."""
+    import ctypes
+    from paper_1503_07998_amd import _native as N
+
+    torch = _torch()
+    _say(f"plane batches of {batch}: {update} {layout} {dtype}")
+    rng = np.random.default_rng(41)
+    psfs = [gaussian_psf(9, 1.5, 3.0).astype(np.float32), gaussian_psf(9, 3.0, 1.5).astype(np.float32)]
+    shape = (20, 9, 32) if layout == "stack_zyx" else (9, 20, 32)
+    if dtype == "u16":
+        obs = [rng.integers(0, 2000, size=shape, dtype=np.uint16) for _ in range(2)]
+    else:
+        obs = [rng.uniform(0.0, 500.0, size=shape).astype(np.float32) for _ in range(2)]
+    lib = N.lib()
+    lib.mvd_internal_set_tune.argtypes = [ctypes.c_char_p]
+
+    def run():
+        from paper_1503_07998_amd import Deconvolver
+
+        d = Deconvolver(2, 20, 32, 0)
+        for v, p in enumerate(psfs):
+            d.set_psf(v, p)
+        ck = torch.empty((4, 9, 20, 32), dtype=torch.float32, device="cuda:0")
+        a = d.run([_dev(o) for o in obs], iters=4, update=update, layout=layout).cpu().numpy()
+        b = d.run([_dev(o) for o in obs], iters=4, update=update, layout=layout, checkpoints=ck).cpu().numpy()
+        d.close()
+        return a, b, ck.cpu().numpy()
+
+    try:
+        lib.mvd_internal_set_tune(b"")
+        ref = run()
+        lib.mvd_internal_set_tune(f"plane_batch={batch}".encode())
+        got = run()
+    finally:
+        lib.mvd_internal_set_tune(None)
+    for x, y in zip(got, ref):
+        np.testing.assert_array_equal(x, y)
+
+
 def test_division_guard():
     _say("division guard")
     rng = np.random.default_rng(13)
