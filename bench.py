@@ -83,11 +83,14 @@ def measured_traffic(name, kind):
         return None
     if rec.get("kernel_source_sha256") != h:
         return None
-    # the instance of the pass that ran most often in the profiled bench run
-    cands = [v for k, v in rec["kernels"].items() if f"sep_{kind}_kernel" in k]
+    # the instance of the pass (plain or split-view form) that ran most often in
+    # the profiled bench run
+    cands = [(k, v) for k, v in rec["kernels"].items()
+             if f"sep_{kind}_kernel" in k or f"sep_{kind}_split_kernel" in k]
     if not cands:
         return None
-    return max(cands, key=lambda v: v.get("trace_calls", 0))["traffic_bytes"]
+    k, v = max(cands, key=lambda kv: kv[1].get("trace_calls", 0))
+    return {"bytes": v["traffic_bytes"], "instance": k}
 
 
 def roofline(spec, kinds, general=False):
@@ -113,9 +116,14 @@ def roofline(spec, kinds, general=False):
         roof = {"bound": "mfma", "achieved": kd["flops_mfma"] / sec / 1e12, "peak": MFMA_F32_PEAK / 1e12,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None if general else measured_traffic(spec.name, dom)
-    roof["kernel"] = (f"{dom} pass (twod_{dom}_kernel, general {spec.psf_k}x{spec.psf_k})" if general
-                      else f"{dom} pass (sep_{dom}_kernel, K={spec.psf_k})")
+    meas = None if general else measured_traffic(spec.name, dom)
+    roof["traffic"] = meas["bytes"] if meas else None
+    if general:
+        roof["kernel"] = f"{dom} pass (twod_{dom}_kernel, general {spec.psf_k}x{spec.psf_k})"
+    elif meas:
+        roof["kernel"] = f"{dom} pass ({meas['instance']})"
+    else:
+        roof["kernel"] = f"{dom} pass (sep_{dom} kernels, K={spec.psf_k})"
     roof["floor_ms"] = {k: v * 1e3 for k, v in times.items()}
     roof["hbm_frac_algorithmic"] = kd["bytes"] / sec / HBM_PEAK
     return roof
