@@ -776,7 +776,9 @@ hipError_t forward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s)
   return a.vec ? forward_bucket_vm<KB, kEpRatio, 1>(a, p, s) : forward_bucket_vm<KB, kEpRatio, 0>(a, p, s);
 }
 
-// One-view single-input pass with an adjoint epilogue (kStore, kBR, kBbar, kAccum).
+// One-view single-input pass with an adjoint epilogue (kStore, kBR, kBbar, kAccum):
+// two columns per thread element-wise or 128-bit (VM 2: chosen at run time),
+// one column per thread with the access form fixed at compile time.
 template <int KB, int EP>
 hipError_t single_ep(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes<KB>(a, 1);
@@ -784,7 +786,10 @@ hipError_t single_ep(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
     if (p.cols == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, EP, 2>, a, p.threads, lds, s);
   }
   if (p.cols != 1) return hipErrorInvalidValue;
-  if constexpr (KB <= 31) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, EP, 2>, a, p.threads, lds, s);
+  if constexpr (KB <= 31) {
+    if (a.vec) return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, EP, 1>, a, p.threads, lds, s);
+    return launch_with_lds(sep_forward_kernel<KB, 1, 1, 4, EP, 0>, a, p.threads, lds, s);
+  }
   return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, EP, 2>, a, p.threads, lds, s);
 }
 
