@@ -271,7 +271,8 @@ mvd_status mvd_backward_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, 
  *        or NULL.  Outputs are overwritten, in float32 from float64 sums in a
  *        fixed order (bitwise reproducible).
  * Every view's PSF and back-projector must be rank one (MVD_ERR_UNSUPPORTED
- * otherwise, and with MVD_FLAG_FORCE_2D).
+ * otherwise, and with MVD_FLAG_FORCE_2D).  Where a run of the same workload
+ * was tuned (MVD_FLAG_TUNE) in this process, the passes take its launch shapes.
  * Errors: MVD_ERR_ARG, MVD_ERR_STATE, MVD_ERR_WORKSPACE, MVD_ERR_UNSUPPORTED,
  * MVD_ERR_DEVICE, MVD_ERR_LAUNCH. */
 mvd_status mvd_backward(mvd_ctx *ctx, const void *const *obs, const float *grad_est,

@@ -47,10 +47,10 @@ class PlanewiseRL:
         self.dev = o0.device
         self.timing = False   # record per-launch HIP events (read with api.mvd_get_timing)
 
-    def _run(self, weights, checkpoints=None, ws_bytes=0):
+    def _run(self, weights, checkpoints=None, ws_bytes=0, tune=False):
         return api.make_run(self.ny, self.iters, update=self.update, boundary=self.boundary,
                             obs_dtype=self.obs_dtype, layout=self.layout, weights=weights,
-                            checkpoints=checkpoints, timing=self.timing)
+                            checkpoints=checkpoints, timing=self.timing, tune=tune)
 
     def set_sigmas(self, sigma):
         s = sigma.detach().to("cpu", dtype=_torch().float64)
@@ -75,7 +75,9 @@ def _make_function():
             T = prob.iters
             ck = torch.empty((T, prob.ny, prob.nz, prob.nx), dtype=torch.float32, device=prob.dev)
             est = torch.empty((prob.ny, prob.nz, prob.nx), dtype=torch.float32, device=prob.dev)
-            run = prob._run(w, checkpoints=ck.data_ptr())
+            # launch shapes timed on the first call for this workload (cached by the
+            # library, which reuses them for the reverse sweep)
+            run = prob._run(w, checkpoints=ck.data_ptr(), tune=not prob.timing)
             nbytes = api.mvd_workspace_bytes(prob.dec.ctx, run)
             ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=prob.dev)
             run.workspace = (ws.data_ptr() + 255) // 256 * 256

@@ -1652,7 +1652,15 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
   const PlaneGeom g{r->n_planes, c->Z, c->X};
   const size_t n = (size_t)g.Y * g.Z * g.X;
   char *ws = static_cast<char *>(r->workspace);
-  RunState rs{c, g, r->boundary, false, s, r->view_weights, (r->flags & MVD_FLAG_TIMING) != 0};
+  // launch shapes: those the autotuner chose for the forward run of the same
+  // workload, if it ran (the reverse sweep's passes have the same shapes)
+  Tune tn = tune();
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(c, r));
+    if (it != g_tune_cache.end()) tn = it->second;
+  }
+  RunState rs{c, g, r->boundary, false, s, r->view_weights, (r->flags & MVD_FLAG_TIMING) != 0, &tn};
   const int V = c->nv;
   const bool sim = r->update == MVD_UPDATE_SIMULTANEOUS;
   auto plane = [&](size_t off, int k) { return reinterpret_cast<float *>(ws + off + (size_t)k * L.plane_set); };
