@@ -9,11 +9,12 @@
 //           and computes G outputs of the K-tap column convolution with
 //           compile-time ring indices.  Results go to LDS, one row per output.
 //   x pass  threads read 8 consecutive row values plus the K−1 halo values with
-//           128-bit LDS reads and compute the K-tap row convolution in
-//           registers, then run the fused epilogue.
+//           128-bit LDS reads and compute the K-tap row convolution on the
+//           matrix cores (two 4-output blocks), then run the fused epilogue.
 //
 // Forward epilogue:  r_v = φ_v / b_v  (b_v = ψ ⊛ P_v; 1 where b_v ≤ ε).  φ_v are
-//                    the staged observations, already clamped at 0.
+//                    read where the caller left them (uint16, or float32
+//                    clamped at 0), through the layout's strides.
 // Backward epilogue: ψ' = ψ · Π_v (w_v · q_v + 1 − w_v)  (q_v = r_v ⊛ X_v).
 // (Supplementary Note 1 update; Supplementary Note 2 §1 back-projector.)
 //

@@ -290,9 +290,8 @@ bool all_set(const mvd_ctx *c) {
   return true;
 }
 
-// Workspace layout of one run.
-// The observations are always staged into clamped float32 planes, so the
-// passes read one form and need no clamp of their own.
+// Workspace layout of one run: float32 copies of the observations (filled
+// only where a K×K forward pass needs them) and the ratio planes.
 struct Layout {
   size_t plane_set = 0; // bytes of one [Y][Z][X] float32 set
   size_t phi_off = 0, r_off = 0, total = 0;

@@ -277,7 +277,8 @@ def test_observation_forms_bitwise(shape, update):
 def test_plane_batches_bitwise(batch, update, layout, dtype):
     """Planes are independent: running the volume batch by batch of planes
     (each batch through every iteration) gives bitwise the whole-volume
-    result, with checkpoints at the same slots."""
+    result, with checkpoints at the same slots, for the mean, given and
+    constant initial estimates."""
     import ctypes
     from paper_1503_07998_amd import _native as N
 
@@ -293,6 +294,8 @@ def test_plane_batches_bitwise(batch, update, layout, dtype):
     lib = N.lib()
     lib.mvd_internal_set_tune.argtypes = [ctypes.c_char_p]
 
+    given = rng.uniform(10.0, 100.0, (9, 20, 32)).astype(np.float32)
+
     def run():
         from paper_1503_07998_amd import Deconvolver
 
@@ -302,8 +305,12 @@ def test_plane_batches_bitwise(batch, update, layout, dtype):
         ck = torch.empty((4, 9, 20, 32), dtype=torch.float32, device="cuda:0")
         a = d.run([_dev(o) for o in obs], iters=4, update=update, layout=layout).cpu().numpy()
         b = d.run([_dev(o) for o in obs], iters=4, update=update, layout=layout, checkpoints=ck).cpu().numpy()
+        g = d.run([_dev(o) for o in obs], iters=3, update=update, layout=layout, init="given",
+                  est=_dev(given)).cpu().numpy()
+        c = d.run([_dev(o) for o in obs], iters=2, update=update, layout=layout, init="const",
+                  init_const=7.0).cpu().numpy()
         d.close()
-        return a, b, ck.cpu().numpy()
+        return a, b, ck.cpu().numpy(), g, c
 
     try:
         lib.mvd_internal_set_tune(b"")
