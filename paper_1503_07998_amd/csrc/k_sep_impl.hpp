@@ -605,8 +605,11 @@ __device__ __forceinline__ void fwd_phases(KArg *a, const Geo &o, const Cols<C, 
 
 // OCC: minimum waves per SIMD the register budget must allow (second
 // launch-bounds argument): 4 caps a thread at 128 VGPRs, 2 at 256.
+// Work-groups of up to 2·kSepMaxThreads threads in the 4-waves/SIMD form (rows
+// up to 1024 columns, one column per thread), kSepMaxThreads otherwise.
 template <int KB, int C, int NV, int OCC, int EP, int VM>
-__global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_forward_kernel(const SepPassArgs) {
+__global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads, OCC)
+    sep_forward_kernel(const SepPassArgs) {
   KArg *a = kargs();
   using S = Shape<KB>;
   constexpr int R = S::R, M = S::M, U = S::U;
@@ -693,7 +696,8 @@ __device__ __forceinline__ void bwd_phases(KArg *a, const Geo &o, const Cols<C, 
 }
 
 template <int KB, int C, int VIN, int OCC, int VM>
-__global__ void __launch_bounds__(kSepMaxThreads, OCC) sep_backward_kernel(const SepPassArgs) {
+__global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads, OCC)
+    sep_backward_kernel(const SepPassArgs) {
   KArg *a = kargs();
   using S = Shape<KB>;
   constexpr int R = S::R, M = S::M, U = S::U;
@@ -745,6 +749,8 @@ template <int KB, int EP, int VM>
 hipError_t forward_bucket_vm(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes<KB>(a, a.nviews);
   const bool hi = p.occ >= 4;
+  // more than kSepMaxThreads threads: the one-column 4-waves/SIMD kernels only
+  if (p.threads > kSepMaxThreads && !(hi && p.cols == 1)) return hipErrorInvalidValue;
   if constexpr (KB <= 41) {
     // two columns per thread only where the ring still fits (the planner never asks otherwise)
     if (p.cols == 2) {
@@ -783,6 +789,7 @@ hipError_t forward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s)
 template <int KB, int EP>
 hipError_t single_ep(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes<KB>(a, 1);
+  if (p.threads > kSepMaxThreads) return hipErrorInvalidValue;
   if constexpr (KB <= 41) {
     if (p.cols == 2) return launch_with_lds(sep_forward_kernel<KB, 2, 1, 2, EP, 2>, a, p.threads, lds, s);
   }
@@ -810,6 +817,7 @@ template <int KB, int VM>
 hipError_t backward_bucket_vm(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes<KB>(a, p.vin);
   const bool hi = p.occ >= 4;
+  if (p.threads > kSepMaxThreads && !(hi && p.cols == 1 && p.vin == 1)) return hipErrorInvalidValue;
   if constexpr (KB <= 41) {
     if (p.vin == 2) return launch_with_lds(sep_backward_kernel<KB, 1, 2, 2, VM>, a, p.threads, lds, s);
     if (p.cols == 2) return launch_with_lds(sep_backward_kernel<KB, 2, 1, 2, VM>, a, p.threads, lds, s);

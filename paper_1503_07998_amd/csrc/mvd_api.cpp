@@ -362,6 +362,8 @@ struct Tune {
                         // the threads per view, 16-row groups): 0 where it applies, 2 never
   int valu_corr = 0;    // 1: tap-gradient correlation on the vector ALUs instead of the matrix cores
   int plane_batch = 0;  // > 0: run this many planes through all iterations at a time
+  int wide = 0;         // rows of 513–1024 columns as one column per thread in up to
+                        // 1024-thread work-groups (one-ring passes): 0 where it applies, 2 never
 };
 
 Tune parse_tune(const char *e) {
@@ -390,6 +392,7 @@ Tune parse_tune(const char *e) {
       if (k == "bwd_threads") r.bwd_threads = v;
       if (k == "bwd_split") r.bwd_split = v;
       if (k == "plane_batch") r.plane_batch = v;
+      if (k == "wide") r.wide = v;
     }
     pos = comma + 1;
   }
@@ -406,7 +409,7 @@ const Tune &tune() { return tune_mut(); }
 // Whole rows (no x halo) under the zero boundary; strips with an x halo of R
 // columns otherwise.  Periodic runs always take strips: their halo columns are
 // read wrapped, so no pass has to copy wrapped values into LDS pad columns.
-SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn = tune()) {
+SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn = tune(), bool one_ring = false) {
   SepGeom s{};
   const int R = (kb - 1) / 2;
   const int X = c->X;
@@ -417,6 +420,11 @@ SepGeom plan_sep(const mvd_ctx *c, int Y, int kb, int boundary, const Tune &tn =
   const int max_cols = (wide_ok ? 2 : 1) * maxt;
   const bool whole = boundary == MVD_BOUNDARY_ZERO;
   const bool one_col = tn.cols == 1 || !wide_ok || maxt < kSepMaxThreads;
+  // whole rows of up to 2·kSepMaxThreads columns, one column per thread: only
+  // the one-ring kernels with the 128-VGPR budget accept such work-groups
+  const bool wide_rows = one_ring && tn.wide != 2 && whole && wide_ok && tn.threads == 0 && tn.cols == 0 &&
+                         X > maxt && X <= 2 * kSepMaxThreads;
+  if (wide_rows) maxt = round_up(X, 64);
   if (whole && X <= maxt) {
     s.plan.cols = 1;
     s.nstrip = 1;
@@ -480,7 +488,9 @@ size_t split_lds_bytes(const SepGeom &sg) {
 // Geometry of the split-view form from a two-plane plan, or false where it does
 // not apply (strips, several columns per thread, > 31 taps, periodic, LDS).
 bool split_geom(const SepGeom &sg, PlaneGeom g, int boundary, SepGeom *out) {
-  if (sg.halo != 0 || sg.plan.cols != 1 || sg.plan.bucket > 31 || boundary != MVD_BOUNDARY_ZERO) return false;
+  if (sg.halo != 0 || sg.plan.cols != 1 || sg.plan.bucket > 31 || boundary != MVD_BOUNDARY_ZERO ||
+      sg.plan.threads > kSepMaxThreads)
+    return false;
   SepGeom sp = sg;
   sp.zseg = round_up(sg.zseg, kSplitRows);
   sp.nseg = (g.Z + sp.zseg - 1) / sp.zseg;
@@ -604,8 +614,9 @@ hipError_t forward_views(const RunState &st, const float *psi, const ObsRef &ob,
     kmax = std::max({kmax, c->views[v].psf.kz, c->views[v].psf.kx});
   }
   if (sep) {
-    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, *st.tn);
-    if (st.tn->fwd_occ) sg.plan.occ = st.tn->fwd_occ;
+    SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, *st.tn, true);
+    // (work-groups beyond kSepMaxThreads exist only in the 128-VGPR form)
+    if (st.tn->fwd_occ && sg.plan.threads <= kSepMaxThreads) sg.plan.occ = st.tn->fwd_occ;
     const size_t per_view = sep_lds_per_view(sg);
     int cap = (int)std::max<size_t>(1, std::min<size_t>(kSepFwdViews, kLdsLimit / per_view));
     if (st.tn->fwd_views > 0) cap = std::min(cap, st.tn->fwd_views);
@@ -684,9 +695,13 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
       nt.threads = st.tn->bwd_threads;
       sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, nt);
     }
+    if (!two) {   // one ring per thread: rows up to 1024 wide may take 1024-thread work-groups
+      const SepGeom w = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, *st.tn, true);
+      if (w.plan.threads > kSepMaxThreads) sg = w;
+    }
     sg.plan.vin = two ? 2 : 1;
     if (two) sg.plan.occ = 2;   // two rings: 256-VGPR budget
-    if (st.tn->bwd_occ) sg.plan.occ = st.tn->bwd_occ;
+    if (st.tn->bwd_occ && sg.plan.threads <= kSepMaxThreads) sg.plan.occ = st.tn->bwd_occ;
     // split-view form (two planes per launch in one 1024-thread work-group):
     // whole rows of ≤ 512 columns, zero boundary, ≤ 31 taps, 128-bit accesses
     SepGeom sp = sg;
@@ -1188,7 +1203,7 @@ hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mv
 // views, update order, boundary); the fastest is cached for the process.  Each
 // candidate starts from the process-wide overrides.
 std::vector<Tune> tune_candidates() {
-  std::vector<Tune> c(10, tune());
+  std::vector<Tune> c(11, tune());
   c[1].fwd_occ = 2;
   c[2].fwd_views = 1;
   c[3].bwd_vin = 1;      // one ratio plane per backward launch
@@ -1198,6 +1213,7 @@ std::vector<Tune> tune_candidates() {
   c[7].zseg_scale = 5;
   c[8].cols = 1;
   c[9].bwd_split = 2;    // two-plane backward without the split-view form
+  c[10].wide = 2;        // rows wider than 512 as two columns per thread
   return c;
 }
 
@@ -1542,10 +1558,14 @@ mvd_status mvd_deconvolve_stream(mvd_ctx *c, const void *const *obs, float *est,
 // can check every access of the kernels' index arithmetic against its buffer.
 // out[16]: bucket, cols, threads, occ, zseg, nseg, x_out, nstrip, halo, ncols,
 // ldsw, vec (for 16-byte aligned buffers), lds bytes per view.
+// k < 0: the plan of a one-ring pass for kernel size −k (the forward pass and
+// the one-plane backward, which may take rows up to 1024 wide in one work-group).
 int mvd_internal_sep_plan(const mvd_ctx *c, int n_planes, int k, int boundary, int *out) {
+  const bool one_ring = k < 0;
+  k = one_ring ? -k : k;
   if (!c || !out || n_planes < 1 || k < 1 || k > MVD_MAX_K) return MVD_ERR_ARG;
   if (boundary != MVD_BOUNDARY_ZERO && boundary != MVD_BOUNDARY_PERIODIC) return MVD_ERR_ARG;
-  const SepGeom sg = plan_sep(c, n_planes, sep_bucket(k), boundary);
+  const SepGeom sg = plan_sep(c, n_planes, sep_bucket(k), boundary, tune(), one_ring);
   out[0] = sg.plan.bucket;
   out[1] = sg.plan.cols;
   out[2] = sg.plan.threads;

@@ -323,6 +323,29 @@ def test_plane_batches_bitwise(batch, update, layout, dtype):
         np.testing.assert_array_equal(x, y)
 
 
+@pytest.mark.parametrize("x,k,update", [(600, 41, "sequential"), (1000, 31, "simultaneous"), (1024, 41, "simultaneous")])
+def test_wide_rows_bitwise(x, k, update):
+    """Rows of 513–1024 columns as one column per thread in up to 1024-thread
+    work-groups give bitwise the results of the two-columns-per-thread form."""
+    import ctypes
+    from paper_1503_07998_amd import _native as N
+
+    _say(f"wide rows X={x} K={k} {update}")
+    rng = np.random.default_rng(x + k)
+    psfs = [gaussian_psf(k, 1.5, k / 5.0).astype(np.float32), gaussian_psf(k, k / 5.0, 1.5).astype(np.float32)]
+    obs = [rng.integers(0, 3000, size=(24, 3, x), dtype=np.uint16) for _ in range(2)]
+    lib = N.lib()
+    lib.mvd_internal_set_tune.argtypes = [ctypes.c_char_p]
+    try:
+        lib.mvd_internal_set_tune(b"wide=2")
+        ref = gpu_run(obs, psfs, 3, update=update)
+        lib.mvd_internal_set_tune(b"")
+        got = gpu_run(obs, psfs, 3, update=update)
+    finally:
+        lib.mvd_internal_set_tune(None)
+    np.testing.assert_array_equal(got, ref)
+
+
 def test_division_guard():
     _say("division guard")
     rng = np.random.default_rng(13)

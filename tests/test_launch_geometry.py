@@ -20,29 +20,31 @@ NX = 8     # row-pass outputs per item
 LDS_LIMIT = 160 * 1024
 
 
-def plan(ctx, Y, k, boundary):
+def plan(ctx, Y, k, boundary, one_ring=False):
     out = (ctypes.c_int * 16)()
     lib = N.lib()
     lib.mvd_internal_sep_plan.restype = ctypes.c_int
     lib.mvd_internal_sep_plan.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int)]
-    assert lib.mvd_internal_sep_plan(ctx, Y, k, N.BOUNDARY[boundary], out) == 0
+    assert lib.mvd_internal_sep_plan(ctx, Y, -k if one_ring else k, N.BOUNDARY[boundary], out) == 0
     keys = ["bucket", "cols", "threads", "occ", "zseg", "nseg", "x_out", "nstrip", "halo", "ncols",
             "ldsw", "vec", "lds_per_view"]
     return dict(zip(keys, list(out)[:len(keys)]))
 
 
-def check_geometry(Y, Z, X, k, boundary, views):
+def check_geometry(Y, Z, X, k, boundary, views, one_ring=False):
     ctx = api.mvd_create(1, Z, X, N.MVD_DEVICE_NONE)
     try:
-        p = plan(ctx, Y, k, boundary)
+        p = plan(ctx, Y, k, boundary, one_ring)
     finally:
         api.mvd_destroy(ctx)
     KB = p["bucket"]
     R = (KB - 1) // 2
     M = G * ((2 * G + KB - 1 + G - 1) // G)
     nt, C = p["threads"], p["cols"]
-    assert nt % 64 == 0 and 64 <= nt <= 512
+    assert nt % 64 == 0 and 64 <= nt <= 1024
+    if nt > 512:   # only the one-column 4-waves/SIMD kernels take such work-groups
+        assert one_ring and C == 1 and p["occ"] == 4 and p["halo"] == 0 and X <= nt
     assert views * p["lds_per_view"] <= LDS_LIMIT
     assert p["zseg"] % G == 0 and p["nseg"] * p["zseg"] >= Z and (p["nseg"] - 1) * p["zseg"] < Z
     assert p["nstrip"] * p["x_out"] >= X and (p["nstrip"] - 1) * p["x_out"] < X
@@ -367,3 +369,24 @@ def test_matrix_core_correlation_tiling_model(shape, k, boundary, zch):
                         C += A @ B
                     ring0 = ring0 + MCZ if ring0 + MCZ < nr else ring0 + MCZ - nr
     np.testing.assert_allclose(C[:kz, :kx], direct, rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("shape", [(2, 24, 600), (1, 12, 1000), (3, 40, 1024), (2, 9, 513), (150, 1000, 1000),
+                                   (64, 1024, 1024)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("k", [3, 15, 31, 41, 63])
+def test_wide_rows_geometry_in_bounds(shape, k):
+    """One-ring passes over rows of 513–1024 columns plan one column per thread
+    in up to 1024-thread work-groups; every access stays in its buffer (the
+    same model as the other plans)."""
+    import ctypes
+
+    lib = N.lib()
+    lib.mvd_internal_set_tune.argtypes = [ctypes.c_char_p]
+    try:
+        lib.mvd_internal_set_tune(b"")
+        Y, Z, X = shape
+        for boundary in ("zero", "periodic"):
+            check_geometry(Y, Z, X, k, boundary, 1, one_ring=True)
+            check_geometry(Y, Z, X, k, boundary, 2, one_ring=True)
+    finally:
+        lib.mvd_internal_set_tune(None)
