@@ -247,34 +247,50 @@ def ratio(phi, b):
     return np.where(b > EPS, phi / safe, 1.0)
 
 
-def view_factor(psi, phi, p, x, w, boundary, method="direct"):
-    """c_v = w · [(φ_v / (ψ ⊛ P_v)) ⊛ X_v] + (1 − w) for one view."""
+def sensitivity(shape, x, boundary, method="direct"):
+    """s = 1 ⊛ X: the back-projection of a plane of ones, i.e. Aᵀ1 when X = Aᵀ.
+    Under the zero boundary it falls below the tap sum within R of the edges."""
+    return conv2d(np.ones(shape), x, boundary, method)
+
+
+def view_factor(psi, phi, p, x, w, boundary, method="direct", normalize=False):
+    """c_v = w · [(φ_v / (ψ ⊛ P_v)) ⊛ X_v] + (1 − w) for one view.
+
+    normalize: the back-projection is divided by s = 1 ⊛ X_v where s > EPS
+    (the EM form ψ · Aᵀ(φ/Aψ) / Aᵀ1 of the update for a zero-extended
+    convolution, whose columns do not all sum to one near the edges; the
+    paper's update assumes they do, Supplementary Note 1).
+    """
     b = conv2d(psi, p, boundary, method)
     r = ratio(phi, b)
     q = conv2d(r, x, boundary, method)
+    if normalize:
+        s = sensitivity(psi.shape[-2:], x, boundary, method)
+        q = np.where(s > EPS, q / np.where(s > EPS, s, 1.0), q)
     return w * q + (1.0 - w)
 
 
 def rl_iteration(psi, phis, psfs, backs, weights=None, update=SIMULTANEOUS,
-                 boundary=ZERO, method="direct") -> np.ndarray:
+                 boundary=ZERO, method="direct", normalize=False) -> np.ndarray:
     """ψ^{t+1} from ψ^t.
 
     simultaneous: every view's factor from the same ψ^t, then ψ^t · Π_v c_v
     (the printed update).  sequential: for v in order, ψ ← ψ · c_v(ψ), each
     view's correction multiplied into the estimate before the next view.
-    Weights w_v (default 1) temper each factor as w·q + (1 − w).
+    Weights w_v (default 1) temper each factor as w·q + (1 − w).  normalize:
+    see view_factor.
     """
     nv = len(phis)
     ws = [1.0] * nv if weights is None else [float(w) for w in weights]
     if update == SIMULTANEOUS:
         prod = np.ones_like(psi)
         for v in range(nv):
-            prod = prod * view_factor(psi, phis[v], psfs[v], backs[v], ws[v], boundary, method)
+            prod = prod * view_factor(psi, phis[v], psfs[v], backs[v], ws[v], boundary, method, normalize)
         return psi * prod
     if update == SEQUENTIAL:
         cur = psi
         for v in range(nv):
-            cur = cur * view_factor(cur, phis[v], psfs[v], backs[v], ws[v], boundary, method)
+            cur = cur * view_factor(cur, phis[v], psfs[v], backs[v], ws[v], boundary, method, normalize)
         return cur
     raise ValueError(update)
 
@@ -282,7 +298,7 @@ def rl_iteration(psi, phis, psfs, backs, weights=None, update=SIMULTANEOUS,
 def deconvolve(obs, psfs, iters: int, *, update=SIMULTANEOUS, boundary=ZERO,
                back="flipped", back_taps=None, weights=None, init="mean",
                init_const=1.0, init_given=None, layout="stack_zyx",
-               method="direct", return_history=False):
+               method="direct", return_history=False, normalize=False):
     """Plane-wise MV-RL: reslice, ψ^0, then ``iters`` iterations; returns ψ^T ``[Y][Z][X]``.
 
     ``obs``: per-view stacks ``[Z][Y][X]`` (layout "stack_zyx") or planes
@@ -302,7 +318,7 @@ def deconvolve(obs, psfs, iters: int, *, update=SIMULTANEOUS, boundary=ZERO,
     psi = init_estimate(phis, init, init_const, init_given)
     hist = [psi]
     for _ in range(int(iters)):
-        psi = rl_iteration(psi, phis, ps, backs, weights, update, boundary, method)
+        psi = rl_iteration(psi, phis, ps, backs, weights, update, boundary, method, normalize)
         if return_history:
             hist.append(psi)
     if return_history:

@@ -138,11 +138,14 @@ def _matrix(k, shape, boundary):
     return m
 
 
-def _dense_step(psi, phis, mats, backs, ws, update):
+def _dense_step(psi, phis, mats, backs, ws, update, normalize=False):
     def factor(cur, phi, a, b, w):
         d = a @ cur
         r = np.where(d > oracle.EPS, phi / np.where(d > oracle.EPS, d, 1.0), 1.0)
-        return w * (b @ r) + (1.0 - w)
+        q = b @ r
+        if normalize:                       # EM form: divide by the column sums b·1
+            q = q / (b @ np.ones_like(r))
+        return w * q + (1.0 - w)
 
     if update == "simultaneous":
         prod = np.ones_like(psi)
@@ -393,3 +396,83 @@ def test_compound_kernel_uses_flip_of_own_view():
     x = oracle.back_projector([p0, p1], 0, "efficient_bayes")
     f = p0[::-1, ::-1]
     np.testing.assert_allclose(x, f * f / (f * f).sum(), rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# EM-normalised back-projection (divide by X ⊛ 1 = Aᵀ1)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("update", ["simultaneous", "sequential"])
+@pytest.mark.parametrize("boundary", ["zero", "periodic"])
+@pytest.mark.parametrize("nv", [1, 2, 3])
+def test_normalized_step_matches_dense_matrix_form(update, boundary, nv):
+    """ψ · Π_v [w · Aᵀ(φ/Aψ) / Aᵀ1 + 1 − w] with A built column by column."""
+    rng = _rng(400 + nv)
+    shape = (9, 7)
+    psfs = [random_psf(rng, kz, kx) for kz, kx in [(5, 3), (3, 7), (9, 9)][:nv]]
+    phis = [rng.uniform(0.0, 50.0, shape) for _ in range(nv)]
+    psi0 = rng.uniform(1.0, 10.0, shape)
+    ws = [1.0, 0.6, 0.3][:nv]
+    mats = [_matrix(p, shape, boundary) for p in psfs]
+    ref = _dense_step(psi0.ravel(), [p.ravel() for p in phis], mats, [m.T for m in mats], ws, update,
+                      normalize=True)
+    backs = [oracle.back_projector(psfs, v) for v in range(nv)]
+    got = oracle.rl_iteration(psi0, phis, psfs, backs, ws, update, boundary, normalize=True)
+    np.testing.assert_allclose(got.ravel(), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_sensitivity_is_column_sums():
+    """1 ⊛ X is Aᵀ1 for X = flip(P): the column sums of the zero-boundary operator,
+    below the tap sum only within R of the edges."""
+    rng = _rng(410)
+    psf = random_psf(rng, 7, 5)
+    shape = (11, 13)
+    m = _matrix(psf, shape, "zero")
+    s = oracle.sensitivity(shape, oracle.flip(psf), "zero")
+    np.testing.assert_allclose(s.ravel(), m.sum(axis=0), rtol=1e-13, atol=1e-15)
+    inner = s[3:-3, 2:-2]
+    np.testing.assert_allclose(inner, psf.sum(), rtol=1e-13)
+    assert s[0, 0] < psf.sum()
+
+
+def test_normalized_flux_identity_zero_boundary():
+    """V = 1, w = 1: Σ (Aᵀ1)·ψ' = Σ φ for the normalised update (where Aψ > ε),
+    while the unnormalised update misses it under the zero boundary."""
+    rng = _rng(411)
+    psf = gaussian_psf(9, 1.4, 2.6)
+    phi = rng.uniform(20.0, 300.0, (1, 24, 20))
+    psi = rng.uniform(50.0, 150.0, (1, 24, 20))
+    back = oracle.flip(psf)
+    s = oracle.sensitivity((24, 20), back, "zero")
+    nxt = oracle.rl_iteration(psi, [phi], [psf], [back], boundary="zero", normalize=True)
+    assert abs(float(np.sum(s * nxt)) - float(np.sum(phi))) <= 1e-10 * float(np.sum(phi))
+    plain = oracle.rl_iteration(psi, [phi], [psf], [back], boundary="zero")
+    assert abs(float(np.sum(s * plain)) - float(np.sum(phi))) > 1e-6 * float(np.sum(phi))
+
+
+def test_normalized_i_divergence_monotone_zero_boundary():
+    """The normalised single-view update is EM for Poisson data under the zero
+    boundary too, so its I-divergence never rises (plain RL's does rise there)."""
+    rng = _rng(412)
+    phi = rng.poisson(rng.uniform(20.0, 200.0, (1, 32, 28))).astype(np.float64)
+    psf = gaussian_psf(9, 1.3, 2.5)
+    back = oracle.flip(psf)
+    psi = oracle.init_estimate([phi])
+    prev = oracle.i_divergence(psi, [phi], [psf], "zero")
+    for _ in range(12):
+        psi = oracle.rl_iteration(psi, [phi], [psf], [back], boundary="zero", normalize=True)
+        cur = oracle.i_divergence(psi, [phi], [psf], "zero")
+        assert cur <= prev * (1 + 1e-12)
+        prev = cur
+
+
+def test_normalized_periodic_is_plain_for_unit_sum_kernels():
+    """Under the periodic boundary 1 ⊛ X is the tap sum everywhere: for a
+    unit-sum back-projector the normalised update is the plain one."""
+    rng = _rng(413)
+    psfs = [gaussian_psf(7, 1.2, 2.0), gaussian_psf(7, 2.0, 1.2)]
+    phis = [rng.uniform(10.0, 90.0, (2, 12, 10)) for _ in range(2)]
+    psi = rng.uniform(10.0, 90.0, (2, 12, 10))
+    backs = [oracle.flip(p) for p in psfs]
+    a = oracle.rl_iteration(psi, phis, psfs, backs, boundary="periodic", normalize=True)
+    b = oracle.rl_iteration(psi, phis, psfs, backs, boundary="periodic")
+    np.testing.assert_allclose(a, b, rtol=1e-13)
