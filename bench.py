@@ -143,7 +143,7 @@ def launch_kinds(spec, tim, steps, vox, batches=1, general=False):
     return kinds
 
 
-def cpu_baseline(spec, vol, iters):
+def cpu_baseline(spec, vol, iters, normalize=False):
     import numpy as np
 
     import oracle
@@ -151,7 +151,8 @@ def cpu_baseline(spec, vol, iters):
     y = spec.n_planes // 2
     sub = [np.ascontiguousarray(s[:, y:y + 1, :]) for s in vol["stacks"]]
     t0 = time.perf_counter()
-    oracle.deconvolve(sub, [p.astype(np.float64) for p in vol["psfs"]], iters, update=spec.update)
+    oracle.deconvolve(sub, [p.astype(np.float64) for p in vol["psfs"]], iters, update=spec.update,
+                      normalize=normalize)
     dt = time.perf_counter() - t0
     vox_it = spec.n_z * spec.n_x * iters
     return {"value": vox_it / dt, "unit": "voxel-iterations/s", "cores": 1, "kind": "oracle",
@@ -487,6 +488,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="planes per streamed batch (vol1024x4)")
     ap.add_argument("--force-2d", action="store_true",
                     help="run the general KxK passes even for rank-one PSFs (default workload)")
+    ap.add_argument("--normalize", action="store_true",
+                    help="EM-normalised back-projection (divide by X (*) 1; default workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -531,7 +534,7 @@ def main():
     def make(timing):
         return api.make_run(Y, spec.iters, update=spec.update, boundary=spec.boundary,
                             obs_dtype=obs_dtype, layout=layout, timing=timing, tune=not args.force_2d,
-                            force_2d=args.force_2d)
+                            force_2d=args.force_2d, normalize=args.normalize)
 
     run = make(False)
     nbytes = api.mvd_workspace_bytes(d.ctx, run)
@@ -595,7 +598,8 @@ def main():
                          f"sz={spec.psf_sigma[1]}, view 1 rotated 90 deg), {spec.obs_dtype} Poisson "
                          f"observations of blob nuclei, {spec.iters} iterations, {spec.update}, "
                          f"{spec.boundary} boundary"
-                         + (", general KxK passes forced (no rank-one split)" if args.force_2d else "")),
+                         + (", general KxK passes forced (no rank-one split)" if args.force_2d else "")
+                         + (", EM-normalised back-projection" if args.normalize else "")),
             "voxels": spec.voxels, "iterations": spec.iters, "views": spec.n_views,
             "psf": spec.psf_k, "update": spec.update, "parallelism": "single GPU",
         },
@@ -608,7 +612,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(spec, vol, spec.iters)
+        out["cpu_baseline"] = cpu_baseline(spec, vol, spec.iters, normalize=args.normalize)
     d.close()
     print(json.dumps(out), flush=True)
 

@@ -101,6 +101,13 @@ typedef enum { MVD_INIT_MEAN = 0, MVD_INIT_GIVEN = 1, MVD_INIT_CONST = 2 } mvd_i
 #define MVD_FLAG_GRAPH 0x4u    /* capture the whole run into a HIP graph on first use and replay it
                                   (per context, keyed by every pointer and parameter of the run;
                                   not with MVD_FLAG_TIMING) */
+#define MVD_FLAG_NORMALIZE 0x10u /* divide each view's back-projection by X_v ⊛ 1 (the
+                                    sensitivity Aᵀ1; below the tap sum within R of the edges
+                                    under the zero boundary): the EM form of the update for a
+                                    zero-extended convolution.  Rank-one back-projectors only
+                                    (MVD_ERR_UNSUPPORTED otherwise, with MVD_FLAG_FORCE_2D, and
+                                    in mvd_backward).  Supplementary Note 1 (the update assumes
+                                    unit column sums) */
 #define MVD_FLAG_TUNE 0x8u     /* choose launch shapes (row-segment length, views per launch,
                                   columns per thread, occupancy) by timing candidates on one
                                   iteration of this run's own data at the first run of a workload

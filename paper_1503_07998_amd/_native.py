@@ -31,6 +31,7 @@ MVD_FLAG_FORCE_2D = 0x1
 MVD_FLAG_TIMING = 0x2
 MVD_FLAG_GRAPH = 0x4
 MVD_FLAG_TUNE = 0x8
+MVD_FLAG_NORMALIZE = 0x10
 MVD_DEVICE_NONE = -1
 MVD_MAX_VIEWS = 8
 MVD_MAX_K = 63

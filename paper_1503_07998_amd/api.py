@@ -100,12 +100,13 @@ def mvd_psf_info(ctx, view: int):
 def make_run(n_planes, n_iters, *, update="simultaneous", boundary="zero", init="mean",
              init_const=1.0, obs_dtype="f32", layout="stack_zyx", weights=None,
              checkpoints=None, workspace=None, workspace_bytes=0, force_2d=False, timing=False,
-             graph=False, tune=False):
+             graph=False, tune=False, normalize=False):
     """Build an ``mvd_run``; keeps host weight storage alive on the object."""
     r = N.MvdRun()
     r.struct_size = ctypes.sizeof(N.MvdRun)
     r.flags = ((N.MVD_FLAG_FORCE_2D if force_2d else 0) | (N.MVD_FLAG_TIMING if timing else 0)
-               | (N.MVD_FLAG_GRAPH if graph else 0) | (N.MVD_FLAG_TUNE if tune else 0))
+               | (N.MVD_FLAG_GRAPH if graph else 0) | (N.MVD_FLAG_TUNE if tune else 0)
+               | (N.MVD_FLAG_NORMALIZE if normalize else 0))
     r.n_planes = int(n_planes)
     r.n_iters = int(n_iters)
     r.update = N.UPDATE[update]
@@ -301,7 +302,7 @@ class Deconvolver:
 
     def run(self, obs, *, iters, est=None, update="simultaneous", boundary="zero", init="mean",
             init_const=1.0, weights=None, layout=None, checkpoints=None, force_2d=False,
-            stream=None):
+            stream=None, normalize=False):
         """Deconvolve device observations; returns the estimate ``[Y][Z][X]`` (float32)."""
         torch = _torch()
         if len(obs) != self.n_views:
@@ -318,7 +319,7 @@ class Deconvolver:
             est = torch.empty((n_planes, self.n_z, self.n_x), dtype=torch.float32, device=o0.device)
         run = make_run(n_planes, iters, update=update, boundary=boundary, init=init,
                        init_const=init_const, obs_dtype=obs_dtype, layout=layout, weights=weights,
-                       force_2d=force_2d,
+                       force_2d=force_2d, normalize=normalize,
                        checkpoints=checkpoints.data_ptr() if checkpoints is not None else None)
         nbytes = mvd_workspace_bytes(self.ctx, run)
         ws = None
@@ -336,7 +337,7 @@ class Deconvolver:
 
 def deconvolve(obs, psfs, *, iters=10, update="simultaneous", boundary="zero", back="flipped",
                back_taps=None, weights=None, init="mean", init_const=1.0, est=None,
-               layout="stack_zyx", force_2d=False, stream=None):
+               layout="stack_zyx", force_2d=False, stream=None, normalize=False):
     """One-shot plane-wise MV-RL on device tensors; returns ψ^T ``[Y][Z][X]``."""
     o0 = obs[0]
     if layout == "stack_zyx":
@@ -350,7 +351,7 @@ def deconvolve(obs, psfs, *, iters=10, update="simultaneous", boundary="zero", b
             d.set_psf(v, p, back, None if back_taps is None else back_taps[v])
         out = d.run(obs, iters=iters, est=est, update=update, boundary=boundary, init=init,
                     init_const=init_const, weights=weights, layout=layout, force_2d=force_2d,
-                    stream=stream)
+                    stream=stream, normalize=normalize)
         # the context's device taps must outlive the enqueued work
         (stream if stream is not None else _torch().cuda.current_stream()).synchronize()
         return out

@@ -136,7 +136,8 @@ struct mvd_ctx {
   std::vector<ViewPsf> views;
   bool derived = false;
   int kzm = 1, kxm = 1, kxpm = 4;  // common K×K size of the general kernels
-  float *d_taps = nullptr;         // [V][2][kzm][kxpm] flipped taps (forward, back)
+  float *d_taps = nullptr;         // [V][2][kzm][kxpm] flipped taps (forward, back), then the
+                                   // sensitivity factors [V][2 boundaries][Z + X] (+ pad)
   size_t d_taps_cap = 0;
   std::string err;
   // launch timing (MVD_FLAG_TIMING)
@@ -218,6 +219,13 @@ std::vector<float> to_f32(const std::vector<double> &v) {
 }
 
 // Build X_v, the rank-one factors and the device copy of the flipped taps.
+// Floats of the sensitivity factors (padded so that an 8-wide read past a row end
+// stays inside the allocation).
+// Each [Z] and [X] vector starts on a 16-byte boundary (the passes read 8 at a time).
+size_t norm_stride(const mvd_ctx *c) { return (size_t)((c->Z + 3) / 4 * 4) + (size_t)((c->X + 3) / 4 * 4); }
+size_t norm_zlen(const mvd_ctx *c) { return (size_t)((c->Z + 3) / 4 * 4); }
+size_t norm_floats(const mvd_ctx *c) { return (size_t)c->nv * 2 * norm_stride(c) + 16; }
+
 mvd_status derive(mvd_ctx *c) {
   std::vector<Kernel> psfs;
   for (auto &v : c->views) psfs.push_back(v.psf);
@@ -252,7 +260,31 @@ mvd_status derive(mvd_ctx *c) {
   c->kxpm = (c->kxm + 3) & ~3;
   if (c->device != MVD_DEVICE_NONE) {
     const size_t per = (size_t)c->kzm * c->kxpm;
-    std::vector<float> host((size_t)c->nv * 2 * per, 0.f);
+    const size_t ntaps = (size_t)c->nv * 2 * per;
+    std::vector<float> host(ntaps + norm_floats(c), 0.f);
+    // 1 ⊛ X_v for a rank-one X_v = xz ⊗ xx: (Σ_j xz[j] over rows z + Rz − j inside
+    // the plane) · (the same along x); periodic: the full sums
+    for (int v = 0; v < c->nv; ++v) {
+      const ViewPsf &w = c->views[v];
+      if (!w.sep_x) continue;
+      for (int bd = 0; bd < 2; ++bd) {
+        float *nz = host.data() + ntaps + ((size_t)v * 2 + bd) * norm_stride(c);
+        float *nx = nz + norm_zlen(c);
+        const int kz = (int)w.xz.size(), kx = (int)w.xx.size(), rz = (kz - 1) / 2, rx = (kx - 1) / 2;
+        for (int z = 0; z < c->Z; ++z) {
+          double acc = 0.0;
+          for (int j = 0; j < kz; ++j)
+            if (bd == 1 || (z + rz - j >= 0 && z + rz - j < c->Z)) acc += w.xz[j];
+          nz[z] = (float)acc;
+        }
+        for (int x = 0; x < c->X; ++x) {
+          double acc = 0.0;
+          for (int i = 0; i < kx; ++i)
+            if (bd == 1 || (x + rx - i >= 0 && x + rx - i < c->X)) acc += w.xx[i];
+          nx[x] = (float)acc;
+        }
+      }
+    }
     for (int v = 0; v < c->nv; ++v) {
       for (int which = 0; which < 2; ++which) {
         const Kernel &k = which == 0 ? c->views[v].psf : c->views[v].back;
@@ -282,6 +314,13 @@ mvd_status derive(mvd_ctx *c) {
   }
   c->derived = true;
   return MVD_OK;
+}
+
+// Device sensitivity factors of view v under `boundary`: [Z] along z, then (at
+// norm_zlen) [X].
+const float *norm_factors(const mvd_ctx *c, int v, int boundary) {
+  const size_t ntaps = (size_t)c->nv * 2 * c->kzm * c->kxpm;
+  return c->d_taps + ntaps + ((size_t)v * 2 + (boundary == MVD_BOUNDARY_PERIODIC ? 1 : 0)) * norm_stride(c);
 }
 
 bool all_set(const mvd_ctx *c) {
@@ -329,8 +368,16 @@ mvd_status check_run(mvd_ctx *c, const mvd_run *r) {
     return fail(c, MVD_ERR_ARG, "unknown obs_dtype %d", r->obs_dtype);
   if (r->obs_layout != MVD_STACK_ZYX && r->obs_layout != MVD_PLANES_YZX)
     return fail(c, MVD_ERR_ARG, "unknown obs_layout %d", r->obs_layout);
-  if (r->flags & ~(MVD_FLAG_FORCE_2D | MVD_FLAG_TIMING | MVD_FLAG_GRAPH | MVD_FLAG_TUNE))
+  if (r->flags & ~(MVD_FLAG_FORCE_2D | MVD_FLAG_TIMING | MVD_FLAG_GRAPH | MVD_FLAG_TUNE | MVD_FLAG_NORMALIZE))
     return fail(c, MVD_ERR_ARG, "unknown flags 0x%x", r->flags);
+  if (r->flags & MVD_FLAG_NORMALIZE) {
+    if (r->flags & MVD_FLAG_FORCE_2D)
+      return fail(c, MVD_ERR_UNSUPPORTED, "MVD_FLAG_NORMALIZE needs the rank-one passes");
+    if (c->derived)
+      for (int v = 0; v < c->nv; ++v)
+        if (!c->views[v].sep_x)
+          return fail(c, MVD_ERR_UNSUPPORTED, "MVD_FLAG_NORMALIZE: view %d's back-projector is not rank one", v);
+  }
   if (r->view_weights)
     for (int v = 0; v < c->nv; ++v) {
       const float w = r->view_weights[v];
@@ -536,6 +583,7 @@ struct RunState {
   const float *w;  // host weights or nullptr
   bool timing;
   const Tune *tn = &tune();   // launch-shape choices (environment or autotuner)
+  bool normalize = false;     // divide back-projections by 1 ⊛ X_v (MVD_FLAG_NORMALIZE)
 };
 
 hipEvent_t take_event(mvd_ctx *c) {
@@ -705,7 +753,8 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
     // split-view form (two planes per launch in one 1024-thread work-group):
     // whole rows of ≤ 512 columns, zero boundary, ≤ 31 taps, 128-bit accesses
     SepGeom sp = sg;
-    const bool split = two && st.tn->bwd_split != 2 && split_geom(sg, st.g, st.boundary, &sp);
+    // (not with the EM normalisation: the split form has no registers left for it)
+    const bool split = two && !st.normalize && st.tn->bwd_split != 2 && split_geom(sg, st.g, st.boundary, &sp);
     for (int b = v0; b < v0 + n; b += sg.plan.vin) {
       const int nb = std::min(sg.plan.vin, v0 + n - b);
       const bool use_split = split && nb == 2 && whole_items(sp, st.g) && aligned16(cur) && aligned16(psi_out) &&
@@ -722,6 +771,10 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
         a.w[k] = weight_of(st, b + k);
         put_factor(a.tz[k], w.xz, plan.bucket);
         put_factor(a.tx[k], w.xx, plan.bucket);
+        if (st.normalize) {
+          a.nsz[k] = norm_factors(c, b + k, st.boundary);
+          a.nsx[k] = a.nsz[k] + norm_zlen(c);
+        }
       }
       a.psi_in = cur;
       a.psi_out = psi_out;
@@ -941,6 +994,7 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
   char *ws = static_cast<char *>(r->workspace);
   RunState rs{c,  g, r->boundary, (r->flags & MVD_FLAG_FORCE_2D) != 0, s, r->view_weights,
               timing_override || (r->flags & MVD_FLAG_TIMING) != 0, &tn};
+  rs.normalize = (r->flags & MVD_FLAG_NORMALIZE) != 0;
   // the separable forward passes read the observations as given; only the
   // general K×K passes need them staged as float32 planes
   const bool need_staged = run_needs_2d(rs);
@@ -1220,7 +1274,7 @@ std::vector<Tune> tune_candidates() {
 std::string tune_key(const mvd_ctx *c, const mvd_run *r) {
   std::string k = "Z" + std::to_string(c->Z) + "X" + std::to_string(c->X) + "Y" + std::to_string(r->n_planes) +
                   "V" + std::to_string(c->nv) + "u" + std::to_string(r->update) + "b" + std::to_string(r->boundary) +
-                  "f" + std::to_string(r->flags & MVD_FLAG_FORCE_2D) + "K";
+                  "f" + std::to_string(r->flags & (MVD_FLAG_FORCE_2D | MVD_FLAG_NORMALIZE)) + "K";
   for (auto &w : c->views)
     k += std::to_string(w.psf.kz) + "x" + std::to_string(w.psf.kx) + (w.sep_p ? "s" : "g") +
          std::to_string(w.back.kz) + "x" + std::to_string(w.back.kx) + (w.sep_x ? "s" : "g") + ",";
@@ -1655,6 +1709,8 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
   if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
   if (r->flags & MVD_FLAG_FORCE_2D)
     return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep runs rank-one kernels only");
+  if (r->flags & MVD_FLAG_NORMALIZE)
+    return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep has no normalised form");
   for (int v = 0; v < c->nv; ++v)
     if (!c->views[v].sep_p || !c->views[v].sep_x)
       return fail(c, MVD_ERR_UNSUPPORTED, "view %d: PSF or back-projector is not rank one", v);

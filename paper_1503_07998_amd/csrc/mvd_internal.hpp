@@ -65,6 +65,8 @@ struct SepPassArgs {
   const float *psi_in;                // backward
   float *psi_out;                     // backward
   float w[kSepFwdViews];              // backward: view weights
+  const float *nsz[kSepFwdViews];     // backward with normalisation: 1 ⊛ X_v = nsz[z]·nsx[x]
+  const float *nsx[kSepFwdViews];     //   (separable; null: no normalisation)
   float tz[kSepFwdViews][kMaxK];      // z factor, padded to the bucket
   float tx[kSepFwdViews][kMaxK];      // x factor, padded to the bucket
 };

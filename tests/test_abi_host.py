@@ -196,13 +196,18 @@ def test_run_validation_before_device():
         for v in range(2):
             api.mvd_set_psf(ctx, v, np.ones((3, 3)))
         bad = [("n_planes", 0), ("n_iters", -1), ("update", 5), ("boundary", 2), ("init", 9),
-               ("obs_dtype", 3), ("obs_layout", 0), ("flags", 0x10)]
+               ("obs_dtype", 3), ("obs_layout", 0), ("flags", 0x20)]
         for field, value in bad:
             r = api.make_run(4, 2)
             setattr(r, field, value)
             assert call(r) == N.MVD_ERR_ARG, field
         r = api.make_run(4, 2, init="const", init_const=0.0)
         assert call(r) == N.MVD_ERR_ARG
+        # the EM normalisation runs on the rank-one passes only
+        r = api.make_run(4, 2, normalize=True, force_2d=True)
+        assert call(r) == N.MVD_ERR_UNSUPPORTED
+        r = api.make_run(4, 2, normalize=True)
+        assert call(r) == N.MVD_ERR_WORKSPACE       # valid so far: the workspace check comes next
         r = api.make_run(4, 2, weights=[1.0, 1.5])
         assert call(r) == N.MVD_ERR_ARG
         r = api.make_run(4, 2, weights=[1.0, float("nan")])
@@ -253,6 +258,8 @@ def test_backward_validation_before_device():
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, force_2d=True)
         assert call(r) == N.MVD_ERR_UNSUPPORTED
         rng = np.random.default_rng(0)
+        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, normalize=True)
+        assert call(r) == N.MVD_ERR_UNSUPPORTED
         api.mvd_set_psf(ctx, 1, random_psf(rng, 5, 5).astype(np.float32))   # not rank one
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need)
         assert call(r) == N.MVD_ERR_UNSUPPORTED

@@ -346,6 +346,34 @@ def test_wide_rows_bitwise(x, k, update):
     np.testing.assert_array_equal(got, ref)
 
 
+NORM_CASES = [
+    # (Z, Y, X, kernel shapes, update, boundary, weights)
+    (37, 3, 45, [(9, 7), (7, 9)], "simultaneous", "zero", None),           # ragged, element-wise
+    (40, 4, 64, [(15, 15), (11, 11)], "simultaneous", "zero", [0.8, 0.6]),  # split-view backward
+    (33, 2, 48, [(9, 5), (5, 9), (3, 3)], "sequential", "zero", [1.0, 0.5, 0.9]),
+    (24, 2, 40, [(7, 7), (9, 9)], "simultaneous", "periodic", None),
+    (20, 2, 600, [(31, 31), (21, 21)], "sequential", "zero", None),        # rows wider than 512
+    (16, 3, 32, [(31, 31)], "simultaneous", "zero", None),                 # kernel taller than the plane
+]
+
+
+@pytest.mark.parametrize("case", NORM_CASES, ids=[f"n{i}" for i in range(len(NORM_CASES))])
+def test_normalized_matches_oracle(case):
+    """EM-normalised back-projection (MVD_FLAG_NORMALIZE) against the oracle's
+    normalised update."""
+    Z, Y, X, shapes, update, boundary, weights = case
+    _say(f"normalised Z={Z} Y={Y} X={X} k={shapes} {update} {boundary} w={weights}")
+    rng = np.random.default_rng(Z * 100 + X)
+    psfs = [random_psf(rng, kz, kx, separable=True).astype(np.float32) for kz, kx in shapes]
+    stacks = [rng.integers(0, 3000, size=(Z, Y, X), dtype=np.uint16) for _ in shapes]
+    got = gpu_run(stacks, psfs, 4, update=update, boundary=boundary, weights=weights, normalize=True)
+    ref = oracle_run(stacks, psfs, 4, update=update, boundary=boundary, weights=weights, normalize=True)
+    check(got, ref)
+    if boundary == "zero":   # the normalisation changes the result near the edges
+        plain = oracle_run(stacks, psfs, 4, update=update, boundary=boundary, weights=weights)
+        assert np.abs(plain - ref).max() > 1e-3 * np.abs(ref).max()
+
+
 def test_division_guard():
     _say("division guard")
     rng = np.random.default_rng(13)
@@ -414,16 +442,18 @@ def test_batched_mix_volumes_sampled(name):
     check(got, ref)
 
 
-def test_full_size_vol512_sampled_planes():
+@pytest.mark.parametrize("normalize", [False, True], ids=["plain", "normalised"])
+def test_full_size_vol512_sampled_planes(normalize):
     """The 512³, 2-view, 31×31 workload at full size in the bench's launch
-    configuration; 8 seeded planes recomputed by the oracle (planes are
-    independent, so a sample is exact)."""
-    _say("vol512 full size, sampled planes")
+    configuration (also with the EM-normalised back-projection); 8 seeded
+    planes recomputed by the oracle (planes are independent, so a sample is
+    exact)."""
+    _say(f"vol512 full size, sampled planes, normalize={normalize}")
     spec = CONFIGS["vol512"]
     vol = make_volume(spec, truth=False)
-    got = gpu_run(vol["stacks"], vol["psfs"], spec.iters)
+    got = gpu_run(vol["stacks"], vol["psfs"], spec.iters, normalize=normalize)
     rng = np.random.default_rng(512)
     ys = sorted(set([0, spec.n_planes - 1] + list(rng.choice(spec.n_planes, 6, replace=False))))
     sub = [np.ascontiguousarray(s[:, ys, :]) for s in vol["stacks"]]
-    ref = oracle_run(sub, vol["psfs"], spec.iters, method="fft")
+    ref = oracle_run(sub, vol["psfs"], spec.iters, method="fft", normalize=normalize)
     check(got[ys], ref)
