@@ -277,11 +277,14 @@ def rl_iteration(psi, phis, psfs, backs, weights=None, update=SIMULTANEOUS,
     simultaneous: every view's factor from the same ψ^t, then ψ^t · Π_v c_v
     (the printed update).  sequential: for v in order, ψ ← ψ · c_v(ψ), each
     view's correction multiplied into the estimate before the next view.
-    Weights w_v (default 1) temper each factor as w·q + (1 − w).  normalize:
-    see view_factor.
+    Weights w_v (default 1) temper each factor as w·q + (1 − w); a weight may
+    be a per-pixel array (the per-pixel, per-view weights of the memory table,
+    whose formula the paper leaves open: read here as the same tempering
+    pixel by pixel).  normalize: see view_factor.
     """
     nv = len(phis)
-    ws = [1.0] * nv if weights is None else [float(w) for w in weights]
+    # a weight is a scalar or, per pixel, an array of the planes' shape
+    ws = [1.0] * nv if weights is None else [w if np.ndim(w) else float(w) for w in weights]
     if update == SIMULTANEOUS:
         prod = np.ones_like(psi)
         for v in range(nv):

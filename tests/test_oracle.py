@@ -476,3 +476,65 @@ def test_normalized_periodic_is_plain_for_unit_sum_kernels():
     a = oracle.rl_iteration(psi, phis, psfs, backs, boundary="periodic", normalize=True)
     b = oracle.rl_iteration(psi, phis, psfs, backs, boundary="periodic")
     np.testing.assert_allclose(a, b, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Per-pixel view weights
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("update", ["simultaneous", "sequential"])
+@pytest.mark.parametrize("normalize", [False, True])
+def test_pixel_weights_match_dense_matrix_form(update, normalize):
+    """ψ · Π_v [ω_v ⊙ q_v + 1 − ω_v] with per-pixel ω_v, against the dense form
+    with the weights applied element by element."""
+    rng = _rng(420)
+    shape = (8, 9)
+    psfs = [random_psf(rng, 5, 3), random_psf(rng, 3, 7)]
+    phis = [rng.uniform(0.0, 50.0, shape) for _ in range(2)]
+    psi0 = rng.uniform(1.0, 10.0, shape)
+    om = [rng.uniform(0.0, 1.0, shape) for _ in range(2)]
+    mats = [_matrix(p, shape, "zero") for p in psfs]
+
+    def factor(cur, phi, a, w):
+        d = a @ cur
+        r = np.where(d > oracle.EPS, phi / np.where(d > oracle.EPS, d, 1.0), 1.0)
+        q = a.T @ r
+        if normalize:
+            q = q / (a.T @ np.ones_like(r))
+        return w * q + (1.0 - w)
+
+    cur = psi0.ravel()
+    if update == "simultaneous":
+        cur = cur * factor(cur, phis[0].ravel(), mats[0], om[0].ravel()) * \
+            factor(cur, phis[1].ravel(), mats[1], om[1].ravel())
+    else:
+        for v in range(2):
+            cur = cur * factor(cur, phis[v].ravel(), mats[v], om[v].ravel())
+    backs = [oracle.back_projector(psfs, v) for v in range(2)]
+    got = oracle.rl_iteration(psi0, phis, psfs, backs, om, update, "zero", normalize=normalize)
+    np.testing.assert_allclose(got.ravel(), cur, rtol=1e-12, atol=1e-12)
+
+
+def test_constant_pixel_weights_equal_scalar_weights():
+    rng = _rng(421)
+    psfs = [gaussian_psf(7, 1.2, 2.0), gaussian_psf(7, 2.0, 1.2)]
+    phis = [rng.uniform(10.0, 90.0, (2, 12, 10)) for _ in range(2)]
+    psi = rng.uniform(10.0, 90.0, (2, 12, 10))
+    backs = [oracle.flip(p) for p in psfs]
+    a = oracle.rl_iteration(psi, phis, psfs, backs, [0.7, 0.3], "sequential", "zero")
+    b = oracle.rl_iteration(psi, phis, psfs, backs, [np.full((2, 12, 10), 0.7), np.full((2, 12, 10), 0.3)],
+                            "sequential", "zero")
+    np.testing.assert_array_equal(a, b)
+
+
+def test_zero_pixel_weights_freeze_the_estimate_there():
+    """Where every view's ω is 0 the estimate does not move."""
+    rng = _rng(422)
+    psfs = [gaussian_psf(7, 1.2, 2.0), gaussian_psf(7, 2.0, 1.2)]
+    phis = [rng.uniform(10.0, 90.0, (1, 16, 12)) for _ in range(2)]
+    psi = rng.uniform(10.0, 90.0, (1, 16, 12))
+    om = np.ones((1, 16, 12))
+    om[:, 4:9, 3:7] = 0.0
+    backs = [oracle.flip(p) for p in psfs]
+    nxt = oracle.rl_iteration(psi, phis, psfs, backs, [om, om], "simultaneous", "zero")
+    np.testing.assert_array_equal(nxt[:, 4:9, 3:7], psi[:, 4:9, 3:7])
+    assert np.abs(nxt - psi).max() > 1e-3
