@@ -33,6 +33,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# per-pixel view weights (--pixel-weights): the backward pass also reads them
+WEIGHT_PLANES = False
+
+
 def step_work(spec, kind, vox, launches_per_iter, general=False):
     """(bytes, flops) of one launch; see step_work_split for the flop split."""
     b, f, _, _ = step_work_split(spec, kind, vox, launches_per_iter, general)
@@ -58,7 +62,7 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
         phi = 2 if (spec.obs_dtype == "u16" and not general) else 4
         b = (phi + 4) * V + 4 * n
     else:
-        b = 4 * V + 8 * n
+        b = (8 if WEIGHT_PLANES else 4) * V + 8 * n
     f = V * 2 * (k * k if general else k + k)
     # where the flops run: separable passes do the column (z) convolution on the
     # matrix cores and the row (x) convolution on the vector ALUs; the general
@@ -490,7 +494,11 @@ def main():
                     help="run the general KxK passes even for rank-one PSFs (default workload)")
     ap.add_argument("--normalize", action="store_true",
                     help="EM-normalised back-projection (divide by X (*) 1; default workload)")
+    ap.add_argument("--pixel-weights", action="store_true",
+                    help="per-pixel view weights (seeded uniform [0.5, 1] planes; default workload)")
     args = ap.parse_args()
+    global WEIGHT_PLANES
+    WEIGHT_PLANES = args.pixel_weights
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -531,10 +539,15 @@ def main():
     est = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
     obs_dtype = "u16" if spec.obs_dtype == "u16" else "f32"
 
+    wplanes = None
+    if args.pixel_weights:
+        g = torch.Generator(device=dev).manual_seed(7)
+        wplanes = [0.5 + 0.5 * torch.rand((Y, Z, X), generator=g, device=dev) for _ in range(spec.n_views)]
+
     def make(timing):
         return api.make_run(Y, spec.iters, update=spec.update, boundary=spec.boundary,
                             obs_dtype=obs_dtype, layout=layout, timing=timing, tune=not args.force_2d,
-                            force_2d=args.force_2d, normalize=args.normalize)
+                            force_2d=args.force_2d, normalize=args.normalize, weight_planes=wplanes)
 
     run = make(False)
     nbytes = api.mvd_workspace_bytes(d.ctx, run)
@@ -599,7 +612,8 @@ def main():
                          f"observations of blob nuclei, {spec.iters} iterations, {spec.update}, "
                          f"{spec.boundary} boundary"
                          + (", general KxK passes forced (no rank-one split)" if args.force_2d else "")
-                         + (", EM-normalised back-projection" if args.normalize else "")),
+                         + (", EM-normalised back-projection" if args.normalize else "")
+                         + (", per-pixel view weights" if args.pixel_weights else "")),
             "voxels": spec.voxels, "iterations": spec.iters, "views": spec.n_views,
             "psf": spec.psf_k, "update": spec.update, "parallelism": "single GPU",
         },

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define MVD_ABI_VERSION 1
+#define MVD_ABI_VERSION 2
 #define MVD_MAX_VIEWS 8
 #define MVD_MAX_K 63
 #define MVD_DEVICE_NONE (-1) /* host-only context: PSF setup and validation only */
@@ -134,6 +134,15 @@ typedef struct {
                                  or NULL.  Needed later by mvd_backward. */
   void *workspace;            /* device scratch of mvd_workspace_bytes() bytes */
   size_t workspace_bytes;
+  const float *const *weight_planes; /* host array of V device pointers to float32
+                                 [Y][Z][X] per-pixel weights ω_v in [0,1], or NULL.  Each
+                                 pixel's correction is tempered as ω·c + (1 − ω) with
+                                 ω = view_weights[v] · ω_v(pixel) (the memory table's
+                                 per-pixel, per-view weights, Supplementary Note 2; their
+                                 formula is not given).  Rank-one back-projectors and
+                                 device-resident runs only: MVD_ERR_UNSUPPORTED with
+                                 K×K passes and in mvd_backward, MVD_ERR_ARG for streamed
+                                 runs.  Read only, kept alive until the stream is done. */
 } mvd_run;
 
 /* Library version (MVD_ABI_VERSION). */

@@ -55,6 +55,7 @@ class MvdRun(ctypes.Structure):
         ("checkpoints", c_void_p),
         ("workspace", c_void_p),
         ("workspace_bytes", c_size_t),
+        ("weight_planes", c_void_p),
     ]
 
 

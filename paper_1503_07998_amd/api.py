@@ -100,8 +100,9 @@ def mvd_psf_info(ctx, view: int):
 def make_run(n_planes, n_iters, *, update="simultaneous", boundary="zero", init="mean",
              init_const=1.0, obs_dtype="f32", layout="stack_zyx", weights=None,
              checkpoints=None, workspace=None, workspace_bytes=0, force_2d=False, timing=False,
-             graph=False, tune=False, normalize=False):
-    """Build an ``mvd_run``; keeps host weight storage alive on the object."""
+             graph=False, tune=False, normalize=False, weight_planes=None):
+    """Build an ``mvd_run``; keeps host weight storage alive on the object.
+    ``weight_planes``: per-view device pointers (or tensors) of per-pixel weights."""
     r = N.MvdRun()
     r.struct_size = ctypes.sizeof(N.MvdRun)
     r.flags = ((N.MVD_FLAG_FORCE_2D if force_2d else 0) | (N.MVD_FLAG_TIMING if timing else 0)
@@ -122,6 +123,11 @@ def make_run(n_planes, n_iters, *, update="simultaneous", boundary="zero", init=
     r.checkpoints = checkpoints
     r.workspace = workspace
     r.workspace_bytes = int(workspace_bytes)
+    if weight_planes is not None:
+        ptrs = [p.data_ptr() if hasattr(p, "data_ptr") else int(p) for p in weight_planes]
+        arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+        r._planes_keepalive = (arr, list(weight_planes))
+        r.weight_planes = ctypes.cast(arr, ctypes.c_void_p)
     return r
 
 
@@ -302,7 +308,7 @@ class Deconvolver:
 
     def run(self, obs, *, iters, est=None, update="simultaneous", boundary="zero", init="mean",
             init_const=1.0, weights=None, layout=None, checkpoints=None, force_2d=False,
-            stream=None, normalize=False):
+            stream=None, normalize=False, weight_planes=None):
         """Deconvolve device observations; returns the estimate ``[Y][Z][X]`` (float32)."""
         torch = _torch()
         if len(obs) != self.n_views:
@@ -319,7 +325,7 @@ class Deconvolver:
             est = torch.empty((n_planes, self.n_z, self.n_x), dtype=torch.float32, device=o0.device)
         run = make_run(n_planes, iters, update=update, boundary=boundary, init=init,
                        init_const=init_const, obs_dtype=obs_dtype, layout=layout, weights=weights,
-                       force_2d=force_2d, normalize=normalize,
+                       force_2d=force_2d, normalize=normalize, weight_planes=weight_planes,
                        checkpoints=checkpoints.data_ptr() if checkpoints is not None else None)
         nbytes = mvd_workspace_bytes(self.ctx, run)
         ws = None
@@ -337,7 +343,7 @@ class Deconvolver:
 
 def deconvolve(obs, psfs, *, iters=10, update="simultaneous", boundary="zero", back="flipped",
                back_taps=None, weights=None, init="mean", init_const=1.0, est=None,
-               layout="stack_zyx", force_2d=False, stream=None, normalize=False):
+               layout="stack_zyx", force_2d=False, stream=None, normalize=False, weight_planes=None):
     """One-shot plane-wise MV-RL on device tensors; returns ψ^T ``[Y][Z][X]``."""
     o0 = obs[0]
     if layout == "stack_zyx":
@@ -351,7 +357,7 @@ def deconvolve(obs, psfs, *, iters=10, update="simultaneous", boundary="zero", b
             d.set_psf(v, p, back, None if back_taps is None else back_taps[v])
         out = d.run(obs, iters=iters, est=est, update=update, boundary=boundary, init=init,
                     init_const=init_const, weights=weights, layout=layout, force_2d=force_2d,
-                    stream=stream, normalize=normalize)
+                    stream=stream, normalize=normalize, weight_planes=weight_planes)
         # the context's device taps must outlive the enqueued work
         (stream if stream is not None else _torch().cuda.current_stream()).synchronize()
         return out

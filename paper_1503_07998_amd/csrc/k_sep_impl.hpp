@@ -637,7 +637,7 @@ __global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads
 // ---------------------------------------------------------------------------
 // Backward pass: VIN ratio planes → ψ' = ψ · Π_v (w_v q_v + 1 − w_v).
 // ---------------------------------------------------------------------------
-template <int KB, int VIN, int VM, bool NRM>
+template <int KB, int VIN, int VM, int EB>
 __device__ __forceinline__ void bwd_epilogue(KArg *a, const float *buf, const float *tt, const Item &itm, bool vec,
                                              float (&ps)[NX]) {
   // ψ · c_0 · c_1 … applied view by view: the same rounding as one launch per view
@@ -645,7 +645,7 @@ __device__ __forceinline__ void bwd_epilogue(KArg *a, const float *buf, const fl
   for (int v = 0; v < VIN; ++v) {
     float q[NX];
     xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, xtab<KB>(tt, v), a->tx[v], q);
-    if constexpr (NRM) {   // EM normalisation: q / (1 ⊛ X_v) where that exceeds ε
+    if constexpr (EB & 1) {   // EM normalisation: q / (1 ⊛ X_v) where that exceeds ε
       const float sz = a->nsz[v][itm.z];
       float sx[NX];
       load8<VM>(a->nsx[v] + itm.x, itm.nvalid, vec, sx);
@@ -656,13 +656,23 @@ __device__ __forceinline__ void bwd_epilogue(KArg *a, const float *buf, const fl
       }
     }
     const float w = a->w[v], w1 = 1.f - w;
+    if constexpr (EB & 2) {   // per-pixel weights: ω = w · ω_v(pixel)
+      float om[NX];
+      load8<VM>(a->wpl[v] + itm.off, itm.nvalid, vec, om);
 #pragma unroll
-    for (int n = 0; n < NX; ++n) ps[n] *= fmaf(w, q[n], w1);
+      for (int n = 0; n < NX; ++n) {
+        const float o = w * om[n];
+        ps[n] *= fmaf(o, q[n], 1.f - o);
+      }
+    } else {
+#pragma unroll
+      for (int n = 0; n < NX; ++n) ps[n] *= fmaf(w, q[n], w1);
+    }
   }
   if (itm.valid) store8<VM>(a->psi_out + itm.off, itm.nvalid, vec, ps);
 }
 
-template <int KB, int C, int VIN, int VM, bool NRM, int u>
+template <int KB, int C, int VIN, int VM, int EB, int u>
 __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                           float *lds, const Loop &st, float (&ring)[VIN][C][Shape<KB>::M],
                                           int i0) {
@@ -692,23 +702,23 @@ __device__ __forceinline__ void bwd_group(KArg *a, const Geo &o, const Cols<C, S
                      &ring[v][0][((u + 1) * G + KB - 1 + g) % M], M);
   }
   lds_sync();
-  bwd_epilogue<KB, VIN, VM, NRM>(a, buf, st.tt, first, st.vec, ps);
+  bwd_epilogue<KB, VIN, VM, EB>(a, buf, st.tt, first, st.vec, ps);
   for (int base = st.nt; base < st.nitems; base += st.nt) {
     const Item itm = item_at(base + st.t, st, o, i, a);
     float q[NX];
     load8<VM>(a->psi_in + itm.off, itm.nvalid, st.vec, q);
-    bwd_epilogue<KB, VIN, VM, NRM>(a, buf, st.tt, itm, st.vec, q);
+    bwd_epilogue<KB, VIN, VM, EB>(a, buf, st.tt, itm, st.vec, q);
   }
 }
 
-template <int KB, int C, int VIN, int VM, bool NRM, int... us>
+template <int KB, int C, int VIN, int VM, int EB, int... us>
 __device__ __forceinline__ void bwd_phases(KArg *a, const Geo &o, const Cols<C, Shape<KB>::R> &cl,
                                            float *lds, const Loop &st, float (&ring)[VIN][C][Shape<KB>::M],
                                            int i0, std::integer_sequence<int, us...>) {
-  (bwd_group<KB, C, VIN, VM, NRM, us>(a, o, cl, lds, st, ring, i0), ...);
+  (bwd_group<KB, C, VIN, VM, EB, us>(a, o, cl, lds, st, ring, i0), ...);
 }
 
-template <int KB, int C, int VIN, int OCC, int VM, bool NRM>
+template <int KB, int C, int VIN, int OCC, int VM, int EB>
 __global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads, OCC)
     sep_backward_kernel(const SepPassArgs) {
   KArg *a = kargs();
@@ -732,7 +742,7 @@ __global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads
     for (int m = 0; m < G + KB - 1; ++m) load_row<C, R>(src, st.rbase + m, a, cl, &ring[v][0][m], M);
   }
   for (int i0 = 0; i0 < o.ngroups; i0 += U)
-    bwd_phases<KB, C, VIN, VM, NRM>(a, o, cl, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
+    bwd_phases<KB, C, VIN, VM, EB>(a, o, cl, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
 }
 
 // Double-buffered column-pass rows and the tap tables of both passes.
@@ -826,27 +836,35 @@ hipError_t single_bucket(const SepPassArgs &a, const SepPlan &p, int ep, hipStre
   return hipErrorInvalidValue;
 }
 
-// NRM: the EM-normalised form (a.nsz set), a separate instance so that the
-// plain passes keep their registers.
-template <int KB, int VM, bool NRM>
+template <int KB, int VM, int EB>
 hipError_t backward_bucket_vm(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   const size_t lds = lds_bytes<KB>(a, p.vin);
   const bool hi = p.occ >= 4;
   if (p.threads > kSepMaxThreads && !(hi && p.cols == 1 && p.vin == 1)) return hipErrorInvalidValue;
   if constexpr (KB <= 41) {
-    if (p.vin == 2) return launch_with_lds(sep_backward_kernel<KB, 1, 2, 2, VM, NRM>, a, p.threads, lds, s);
-    if (p.cols == 2) return launch_with_lds(sep_backward_kernel<KB, 2, 1, 2, VM, NRM>, a, p.threads, lds, s);
+    if (p.vin == 2) return launch_with_lds(sep_backward_kernel<KB, 1, 2, 2, VM, EB>, a, p.threads, lds, s);
+    if (p.cols == 2) return launch_with_lds(sep_backward_kernel<KB, 2, 1, 2, VM, EB>, a, p.threads, lds, s);
   }
   if (p.cols != 1 || p.vin != 1) return hipErrorInvalidValue;
-  if (hi) return launch_with_lds(sep_backward_kernel<KB, 1, 1, 4, VM, NRM>, a, p.threads, lds, s);
-  return launch_with_lds(sep_backward_kernel<KB, 1, 1, 2, VM, NRM>, a, p.threads, lds, s);
+  if (hi) return launch_with_lds(sep_backward_kernel<KB, 1, 1, 4, VM, EB>, a, p.threads, lds, s);
+  return launch_with_lds(sep_backward_kernel<KB, 1, 1, 2, VM, EB>, a, p.threads, lds, s);
 }
 
+template <int KB, int EB>
+hipError_t backward_bucket_eb(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  return a.vec ? backward_bucket_vm<KB, 1, EB>(a, p, s) : backward_bucket_vm<KB, 0, EB>(a, p, s);
+}
+
+// EB: bit 0 the EM normalisation (a.nsz set), bit 1 per-pixel weights (a.wpl
+// set); separate instances so that the plain passes keep their registers.
 template <int KB>
 hipError_t backward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
-  if (a.nsz[0])
-    return a.vec ? backward_bucket_vm<KB, 1, true>(a, p, s) : backward_bucket_vm<KB, 0, true>(a, p, s);
-  return a.vec ? backward_bucket_vm<KB, 1, false>(a, p, s) : backward_bucket_vm<KB, 0, false>(a, p, s);
+  switch ((a.nsz[0] ? 1 : 0) | (a.wpl[0] ? 2 : 0)) {
+    case 0: return backward_bucket_eb<KB, 0>(a, p, s);
+    case 1: return backward_bucket_eb<KB, 1>(a, p, s);
+    case 2: return backward_bucket_eb<KB, 2>(a, p, s);
+    default: return backward_bucket_eb<KB, 3>(a, p, s);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -857,7 +875,7 @@ hipError_t backward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s
 // ψ' = ψ · c_0 · c_1 as in the two-plane pass.  Whole rows, one column per
 // thread, X ≤ 512.
 // ---------------------------------------------------------------------------
-template <int KB, int VM, bool NRM, int u>
+template <int KB, int VM, int EB, int u>
 __device__ __forceinline__ void bwd_split_group(KArg *a, const Geo &o, const Cols<1, Shape<KB>::R> &cl, float *lds,
                                                 const Loop &st, float (&ring)[1][Shape<KB>::M], int i0, int view) {
   constexpr int M = Shape<KB>::M, R = Shape<KB>::R;
@@ -877,23 +895,23 @@ __device__ __forceinline__ void bwd_split_group(KArg *a, const Geo &o, const Col
   for (int g = 0; g < G; ++g)
     load_row<1, R>(src, st.rbase + (i + 1) * G + KB - 1 + g, a, cl, &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
   lds_sync();
-  bwd_epilogue<KB, 2, VM, NRM>(a, buf, st.tt, first, st.vec, ps);
+  bwd_epilogue<KB, 2, VM, EB>(a, buf, st.tt, first, st.vec, ps);
   for (int base = st.nt; base < st.nitems; base += st.nt) {
     const Item itm = item_at(base + st.t, st, o, i, a);
     float q[NX];
     load8<VM>(a->psi_in + itm.off, itm.nvalid, st.vec, q);
-    bwd_epilogue<KB, 2, VM, NRM>(a, buf, st.tt, itm, st.vec, q);
+    bwd_epilogue<KB, 2, VM, EB>(a, buf, st.tt, itm, st.vec, q);
   }
 }
 
-template <int KB, int VM, bool NRM, int... us>
+template <int KB, int VM, int EB, int... us>
 __device__ __forceinline__ void bwd_split_phases(KArg *a, const Geo &o, const Cols<1, Shape<KB>::R> &cl, float *lds,
                                                  const Loop &st, float (&ring)[1][Shape<KB>::M], int i0, int view,
                                                  std::integer_sequence<int, us...>) {
-  (bwd_split_group<KB, VM, NRM, us>(a, o, cl, lds, st, ring, i0, view), ...);
+  (bwd_split_group<KB, VM, EB, us>(a, o, cl, lds, st, ring, i0, view), ...);
 }
 
-template <int KB, int VM, bool NRM>
+template <int KB, int VM, int EB>
 __global__ void __launch_bounds__(2 * kSepMaxThreads, 4) sep_backward_split_kernel(const SepPassArgs) {
   KArg *a = kargs();
   using S = Shape<KB>;
@@ -914,7 +932,7 @@ __global__ void __launch_bounds__(2 * kSepMaxThreads, 4) sep_backward_split_kern
 #pragma unroll
   for (int m = 0; m < G + KB - 1; ++m) load_row<1, R>(src, st.rbase + m, a, cl, &ring[0][m], M);
   for (int i0 = 0; i0 < o.ngroups; i0 += U)
-    bwd_split_phases<KB, VM, NRM>(a, o, cl, lds, st, ring, i0, view, std::make_integer_sequence<int, U>{});
+    bwd_split_phases<KB, VM, EB>(a, o, cl, lds, st, ring, i0, view, std::make_integer_sequence<int, U>{});
 }
 
 template <int KB>
@@ -922,8 +940,9 @@ hipError_t backward_split_bucket(const SepPassArgs &a, const SepPlan &p, hipStre
   // 128-bit row-pass accesses only (the element-wise form would not fit 128 VGPRs)
   if (p.cols != 1 || p.vin != 2 || a.halo != 0 || a.nviews != 2 || !a.vec) return hipErrorInvalidValue;
   const size_t lds = lds_bytes<KB>(a, 2);
-  if (a.nsz[0]) return launch_with_lds(sep_backward_split_kernel<KB, 1, true>, a, p.threads, lds, s);
-  return launch_with_lds(sep_backward_split_kernel<KB, 1, false>, a, p.threads, lds, s);
+  // (the plain update only: no registers are left for the epilogue variants)
+  if (a.nsz[0] || a.wpl[0]) return hipErrorInvalidValue;
+  return launch_with_lds(sep_backward_split_kernel<KB, 1, 0>, a, p.threads, lds, s);
 }
 
 }  // namespace MVD_SEP_NS

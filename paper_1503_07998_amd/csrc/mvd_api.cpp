@@ -378,6 +378,15 @@ mvd_status check_run(mvd_ctx *c, const mvd_run *r) {
         if (!c->views[v].sep_x)
           return fail(c, MVD_ERR_UNSUPPORTED, "MVD_FLAG_NORMALIZE: view %d's back-projector is not rank one", v);
   }
+  if (r->weight_planes) {
+    for (int v = 0; v < c->nv; ++v)
+      if (!r->weight_planes[v]) return fail(c, MVD_ERR_ARG, "weight_planes[%d] is NULL", v);
+    if (r->flags & MVD_FLAG_FORCE_2D) return fail(c, MVD_ERR_UNSUPPORTED, "weight planes need the rank-one passes");
+    if (c->derived)
+      for (int v = 0; v < c->nv; ++v)
+        if (!c->views[v].sep_x)
+          return fail(c, MVD_ERR_UNSUPPORTED, "weight planes: view %d's back-projector is not rank one", v);
+  }
   if (r->view_weights)
     for (int v = 0; v < c->nv; ++v) {
       const float w = r->view_weights[v];
@@ -584,6 +593,8 @@ struct RunState {
   bool timing;
   const Tune *tn = &tune();   // launch-shape choices (environment or autotuner)
   bool normalize = false;     // divide back-projections by 1 ⊛ X_v (MVD_FLAG_NORMALIZE)
+  const float *const *wpl = nullptr;   // per-pixel weight planes of the whole volume, or null
+  size_t wpl_off = 0;                  // elements from their start to this launch's first plane
 };
 
 hipEvent_t take_event(mvd_ctx *c) {
@@ -754,7 +765,8 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
     // whole rows of ≤ 512 columns, zero boundary, ≤ 31 taps, 128-bit accesses
     SepGeom sp = sg;
     // (not with the EM normalisation: the split form has no registers left for it)
-    const bool split = two && !st.normalize && st.tn->bwd_split != 2 && split_geom(sg, st.g, st.boundary, &sp);
+    const bool split =
+        two && !st.normalize && !st.wpl && st.tn->bwd_split != 2 && split_geom(sg, st.g, st.boundary, &sp);
     for (int b = v0; b < v0 + n; b += sg.plan.vin) {
       const int nb = std::min(sg.plan.vin, v0 + n - b);
       const bool use_split = split && nb == 2 && whole_items(sp, st.g) && aligned16(cur) && aligned16(psi_out) &&
@@ -775,11 +787,12 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
           a.nsz[k] = norm_factors(c, b + k, st.boundary);
           a.nsx[k] = a.nsz[k] + norm_zlen(c);
         }
+        if (st.wpl) a.wpl[k] = st.wpl[b + k] + st.wpl_off;
       }
       a.psi_in = cur;
       a.psi_out = psi_out;
       a.vec = whole_items(gm, st.g) && aligned16(cur) && aligned16(psi_out);
-      for (int k = 0; k < nb; ++k) a.vec = a.vec && aligned16(a.in[k]);
+      for (int k = 0; k < nb; ++k) a.vec = a.vec && aligned16(a.in[k]) && (!a.wpl[k] || aligned16(a.wpl[k]));
       hipError_t e = timed(st, 1, [&] {
         return use_split ? launch_sep_backward_split(a, plan, st.s) : launch_sep_backward(a, plan, st.s);
       });
@@ -995,6 +1008,7 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
   RunState rs{c,  g, r->boundary, (r->flags & MVD_FLAG_FORCE_2D) != 0, s, r->view_weights,
               timing_override || (r->flags & MVD_FLAG_TIMING) != 0, &tn};
   rs.normalize = (r->flags & MVD_FLAG_NORMALIZE) != 0;
+  rs.wpl = r->weight_planes;
   // the separable forward passes read the observations as given; only the
   // general K×K passes need them staged as float32 planes
   const bool need_staged = run_needs_2d(rs);
@@ -1012,6 +1026,7 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
     const size_t nb = (size_t)gb.Y * g.Z * g.X, off = (size_t)y0 * g.Z * g.X;
     RunState rb = rs;
     rb.g = gb;
+    rb.wpl_off = off;
     // this batch's observations: the same strides, starting at plane y0 (the
     // staged planes and ratio planes of a batch are the first planes of their sets)
     std::vector<const void *> ob_p(c->nv);
@@ -1085,6 +1100,7 @@ mvd_status check_stream_run(mvd_ctx *c, const mvd_run *r, int batch) {
   if (r->obs_layout != MVD_STACK_ZYX) return fail(c, MVD_ERR_ARG, "streamed runs take camera-ordered stacks");
   if (r->checkpoints) return fail(c, MVD_ERR_ARG, "streamed runs keep no checkpoints");
   if (r->flags & MVD_FLAG_GRAPH) return fail(c, MVD_ERR_ARG, "MVD_FLAG_GRAPH is not available for streamed runs");
+  if (r->weight_planes) return fail(c, MVD_ERR_ARG, "streamed runs take no weight planes");
   return MVD_OK;
 }
 
@@ -1274,7 +1290,8 @@ std::vector<Tune> tune_candidates() {
 std::string tune_key(const mvd_ctx *c, const mvd_run *r) {
   std::string k = "Z" + std::to_string(c->Z) + "X" + std::to_string(c->X) + "Y" + std::to_string(r->n_planes) +
                   "V" + std::to_string(c->nv) + "u" + std::to_string(r->update) + "b" + std::to_string(r->boundary) +
-                  "f" + std::to_string(r->flags & (MVD_FLAG_FORCE_2D | MVD_FLAG_NORMALIZE)) + "K";
+                  "f" + std::to_string(r->flags & (MVD_FLAG_FORCE_2D | MVD_FLAG_NORMALIZE)) +
+                  (r->weight_planes ? "w" : "") + "K";
   for (auto &w : c->views)
     k += std::to_string(w.psf.kz) + "x" + std::to_string(w.psf.kx) + (w.sep_p ? "s" : "g") +
          std::to_string(w.back.kz) + "x" + std::to_string(w.back.kx) + (w.sep_x ? "s" : "g") + ",";
@@ -1360,6 +1377,7 @@ struct mvd_batch {
     float *est;
     mvd_run run;
     std::vector<float> weights;
+    std::vector<const float *> wplanes;
     Tune tn;
   };
   std::vector<Item> items;
@@ -1711,6 +1729,7 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
     return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep runs rank-one kernels only");
   if (r->flags & MVD_FLAG_NORMALIZE)
     return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep has no normalised form");
+  if (r->weight_planes) return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep takes scalar view weights only");
   for (int v = 0; v < c->nv; ++v)
     if (!c->views[v].sep_p || !c->views[v].sep_x)
       return fail(c, MVD_ERR_UNSUPPORTED, "view %d: PSF or back-projector is not rank one", v);
@@ -1854,6 +1873,10 @@ mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items,
     if (it.run.view_weights) {
       it.weights.assign(it.run.view_weights, it.run.view_weights + it.ctx->nv);
       it.run.view_weights = it.weights.data();
+    }
+    if (it.run.weight_planes) {
+      it.wplanes.assign(it.run.weight_planes, it.run.weight_planes + it.ctx->nv);
+      it.run.weight_planes = it.wplanes.data();
     }
     b->items.push_back(std::move(it));
   }

@@ -67,6 +67,7 @@ struct SepPassArgs {
   float w[kSepFwdViews];              // backward: view weights
   const float *nsz[kSepFwdViews];     // backward with normalisation: 1 ⊛ X_v = nsz[z]·nsx[x]
   const float *nsx[kSepFwdViews];     //   (separable; null: no normalisation)
+  const float *wpl[kSepFwdViews];     // backward: per-pixel weights (plane sets), or null
   float tz[kSepFwdViews][kMaxK];      // z factor, padded to the bucket
   float tx[kSepFwdViews][kMaxK];      // x factor, padded to the bucket
 };

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_status_strings():
     lib = N.lib()
-    assert lib.mvd_version() == 1
+    assert lib.mvd_version() == 2
     assert lib.mvd_status_string(0) == b"ok"
     assert lib.mvd_status_string(-3) == b"workspace too small"
 
@@ -206,6 +206,13 @@ def test_run_validation_before_device():
         # the EM normalisation runs on the rank-one passes only
         r = api.make_run(4, 2, normalize=True, force_2d=True)
         assert call(r) == N.MVD_ERR_UNSUPPORTED
+        # per-pixel weights: every view's plane, rank-one passes only
+        r = api.make_run(4, 2, weight_planes=[64, 0])
+        assert call(r) == N.MVD_ERR_ARG
+        r = api.make_run(4, 2, weight_planes=[64, 128], force_2d=True)
+        assert call(r) == N.MVD_ERR_UNSUPPORTED
+        r = api.make_run(4, 2, weight_planes=[64, 128])
+        assert call(r) == N.MVD_ERR_WORKSPACE
         r = api.make_run(4, 2, normalize=True)
         assert call(r) == N.MVD_ERR_WORKSPACE       # valid so far: the workspace check comes next
         r = api.make_run(4, 2, weights=[1.0, 1.5])
@@ -260,6 +267,8 @@ def test_backward_validation_before_device():
         rng = np.random.default_rng(0)
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, normalize=True)
         assert call(r) == N.MVD_ERR_UNSUPPORTED
+        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, weight_planes=[64, 128])
+        assert call(r) == N.MVD_ERR_UNSUPPORTED
         api.mvd_set_psf(ctx, 1, random_psf(rng, 5, 5).astype(np.float32))   # not rank one
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need)
         assert call(r) == N.MVD_ERR_UNSUPPORTED
@@ -309,6 +318,7 @@ def test_stream_validation_before_device():
         assert call(api.make_run(4, 2, layout="planes_yzx")) == N.MVD_ERR_ARG
         assert call(api.make_run(4, 2, checkpoints=64)) == N.MVD_ERR_ARG
         assert call(api.make_run(4, 2, graph=True)) == N.MVD_ERR_ARG
+        assert call(api.make_run(4, 2, weight_planes=[64, 128])) == N.MVD_ERR_ARG
         r = api.make_run(4, 2, workspace=256 + 8, workspace_bytes=1 << 20)
         assert call(r) == N.MVD_ERR_ARG                        # misaligned workspace
         r = api.make_run(4, 2, workspace=256, workspace_bytes=1 << 20)

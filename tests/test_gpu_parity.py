@@ -374,6 +374,69 @@ def test_normalized_matches_oracle(case):
         assert np.abs(plain - ref).max() > 1e-3 * np.abs(ref).max()
 
 
+WPL_CASES = [
+    # (Z, Y, X, kernel shapes, update, scalar weights, normalize)
+    (40, 3, 64, [(15, 15), (11, 11)], "simultaneous", None, False),
+    (37, 2, 45, [(9, 7), (7, 9), (5, 5)], "sequential", [0.9, 0.7, 1.0], False),
+    (24, 2, 600, [(21, 21), (9, 9)], "simultaneous", [0.8, 1.0], True),
+]
+
+
+@pytest.mark.parametrize("case", WPL_CASES, ids=[f"w{i}" for i in range(len(WPL_CASES))])
+def test_weight_planes_match_oracle(case):
+    """Per-pixel view weights ω_v (times the scalar weights) against the
+    oracle's per-pixel tempering."""
+    torch = _torch()
+    Z, Y, X, shapes, update, weights, normalize = case
+    _say(f"weight planes Z={Z} Y={Y} X={X} k={shapes} {update} w={weights} normalize={normalize}")
+    rng = np.random.default_rng(Z * 10 + X)
+    psfs = [random_psf(rng, kz, kx, separable=True).astype(np.float32) for kz, kx in shapes]
+    stacks = [rng.integers(0, 3000, size=(Z, Y, X), dtype=np.uint16) for _ in shapes]
+    om = [rng.uniform(0.0, 1.0, (Y, Z, X)).astype(np.float32) for _ in shapes]
+    planes = [torch.from_numpy(o).to("cuda:0") for o in om]
+    got = gpu_run(stacks, psfs, 3, update=update, weights=weights, normalize=normalize, weight_planes=planes)
+    ws = [1.0] * len(shapes) if weights is None else weights
+    eff = [np.float32(w) * o.astype(np.float64) for w, o in zip(ws, om)]
+    ref = oracle_run(stacks, psfs, 3, update=update, weights=eff, normalize=normalize)
+    check(got, ref)
+
+
+def test_unit_weight_planes_are_scalar_weights_bitwise():
+    """Planes of ones leave the scalar weights: bitwise the scalar-weighted run
+    (which takes the split-view backward; the weighted one the two-plane form)."""
+    torch = _torch()
+    _say("unit weight planes vs scalar weights")
+    rng = np.random.default_rng(97)
+    psfs = [gaussian_psf(15, 1.5, 3.0).astype(np.float32), gaussian_psf(15, 3.0, 1.5).astype(np.float32)]
+    stacks = [rng.integers(0, 3000, size=(48, 3, 64), dtype=np.uint16) for _ in range(2)]
+    ones = [torch.ones((3, 48, 64), dtype=torch.float32, device="cuda:0") for _ in range(2)]
+    a = gpu_run(stacks, psfs, 4, weights=[0.8, 0.6])
+    b = gpu_run(stacks, psfs, 4, weights=[0.8, 0.6], weight_planes=ones)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_weight_planes_in_plane_batches_bitwise():
+    import ctypes
+    from paper_1503_07998_amd import _native as N
+
+    torch = _torch()
+    _say("weight planes with plane batches")
+    rng = np.random.default_rng(98)
+    psfs = [gaussian_psf(9, 1.5, 3.0).astype(np.float32), gaussian_psf(9, 3.0, 1.5).astype(np.float32)]
+    stacks = [rng.integers(0, 3000, size=(20, 7, 32), dtype=np.uint16) for _ in range(2)]
+    planes = [torch.from_numpy(rng.uniform(0.0, 1.0, (7, 20, 32)).astype(np.float32)).to("cuda:0") for _ in range(2)]
+    lib = N.lib()
+    lib.mvd_internal_set_tune.argtypes = [ctypes.c_char_p]
+    try:
+        lib.mvd_internal_set_tune(b"")
+        a = gpu_run(stacks, psfs, 3, weight_planes=planes)
+        lib.mvd_internal_set_tune(b"plane_batch=3")
+        b = gpu_run(stacks, psfs, 3, weight_planes=planes)
+    finally:
+        lib.mvd_internal_set_tune(None)
+    np.testing.assert_array_equal(a, b)
+
+
 def test_division_guard():
     _say("division guard")
     rng = np.random.default_rng(13)
