@@ -1216,6 +1216,7 @@ std::vector<uint64_t> run_key(const mvd_ctx *c, const void *const *obs, const fl
     uint32_t w = 0x3f800000u;
     if (r->view_weights) std::memcpy(&w, &r->view_weights[v], 4);
     k.push_back(w);
+    k.push_back(r->weight_planes ? (uint64_t)(uintptr_t)r->weight_planes[v] : 0);
   }
   k.push_back(c->psf_generation);
   return k;

@@ -415,6 +415,41 @@ def test_unit_weight_planes_are_scalar_weights_bitwise():
     np.testing.assert_array_equal(a, b)
 
 
+def test_weight_planes_graph_replays():
+    """A captured run is keyed by its weight planes too: replays with other
+    planes equal the eager runs with them."""
+    from paper_1503_07998_amd import api
+
+    torch = _torch()
+    _say("weight planes under graph replay")
+    rng = np.random.default_rng(99)
+    Z, Y, X = 24, 3, 40
+    d = api.Deconvolver(2, Z, X, 0)
+    for v in range(2):
+        d.set_psf(v, gaussian_psf(9, 1.5 + v, 3.0 - v).astype(np.float32))
+    obs = [torch.from_numpy(rng.integers(0, 3000, size=(Z, Y, X), dtype=np.uint16)).to("cuda:0") for _ in range(2)]
+    sets = [[torch.from_numpy(rng.uniform(0.2, 1.0, (Y, Z, X)).astype(np.float32)).to("cuda:0") for _ in range(2)]
+            for _ in range(2)]
+    est = torch.empty((Y, Z, X), dtype=torch.float32, device="cuda:0")
+    outs = {}
+    for graph in (False, True):
+        for i, planes in enumerate(sets):
+            run = api.make_run(Y, 3, obs_dtype="u16", graph=graph, weight_planes=planes)
+            nb = api.mvd_workspace_bytes(d.ctx, run)
+            ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda:0")
+            run.workspace = (ws.data_ptr() + 255) // 256 * 256
+            run.workspace_bytes = nb
+            for _ in range(2 if graph else 1):
+                api.mvd_deconvolve_planes(d.ctx, obs, est, run)
+                torch.cuda.synchronize()
+            outs[(graph, i)] = est.cpu().numpy().copy()
+            del ws
+    d.close()
+    for i in range(2):
+        np.testing.assert_array_equal(outs[(True, i)], outs[(False, i)])
+    assert np.abs(outs[(False, 0)] - outs[(False, 1)]).max() > 0
+
+
 def test_weight_planes_in_plane_batches_bitwise():
     import ctypes
     from paper_1503_07998_amd import _native as N
