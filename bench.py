@@ -97,8 +97,12 @@ def measured_traffic(name, kind):
     return {"bytes": v["traffic_bytes"], "instance": k}
 
 
-def roofline(spec, kinds, general=False):
+def roofline(spec, kinds, general=False, variant=False):
     """Roofline entry of the kernel with the largest share of the step.
+
+    ``variant`` marks a run whose passes are other kernel instances than the
+    profiled default run (normalised or per-pixel-weighted back-projection):
+    its HBM traffic has not been counted, so none is reported.
 
     The binding ceiling is the largest of the HBM time (algorithmic bytes at
     8 TB/s), the vector-ALU time (row-pass flops at 78.6 TFLOP/s) and the
@@ -120,7 +124,7 @@ def roofline(spec, kinds, general=False):
         roof = {"bound": "mfma", "achieved": kd["flops_mfma"] / sec / 1e12, "peak": MFMA_F32_PEAK / 1e12,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    meas = None if general else measured_traffic(spec.name, dom)
+    meas = None if general or variant else measured_traffic(spec.name, dom)
     roof["traffic"] = meas["bytes"] if meas else None
     if general:
         roof["kernel"] = f"{dom} pass (twod_{dom}_kernel, general {spec.psf_k}x{spec.psf_k})"
@@ -589,7 +593,7 @@ def main():
     ms_plain = (time.perf_counter() - t1) * 1e3 / args.steps
 
     kinds = launch_kinds(spec, tim, args.steps, Y * Z * X, general=args.force_2d)
-    roof = roofline(spec, kinds, general=args.force_2d)
+    roof = roofline(spec, kinds, general=args.force_2d, variant=args.normalize or args.pixel_weights)
 
     it_ms = sum(kinds[k]["avg_ms"] * kinds[k]["launches"] for k in kinds) / args.steps
     out = {
