@@ -64,11 +64,10 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
     else:
         b = (8 if WEIGHT_PLANES else 4) * V + 8 * n
     f = V * 2 * (k * k if general else k + k)
-    # where the flops run: separable passes do the column (z) convolution on the
-    # matrix cores and the row (x) convolution on the vector ALUs; the general
-    # K×K passes run entirely on the matrix cores
-    f_mfma = V * 2 * (k * k if general else k)
-    f_valu = 0 if general else V * 2 * k
+    # where the flops run: the separable passes do both the column (z) and the
+    # row (x) convolution on the matrix cores, and so do the general K×K passes
+    f_mfma = f
+    f_valu = 0
     return vox * b / n, vox * f / n, vox * f_valu / n, vox * f_mfma / n
 
 
