@@ -187,6 +187,10 @@ CONFIGS = {
     # 4 views 0/90/180/270, 1024³, 41×41 PSFs σx=1.5/σz=8, uint16, sequential.
     "vol1024x4": VolumeSpec("vol1024x4", 1024, 1024, 1024, 41, (1.5, 8.0), (0, 90, 180, 270),
                             (1024 ** 3) // (16 ** 3), "u16", 10, "sequential", seed=3),
+    # Planes of the 2048³ size class: 2 views, 64 planes of 2048×2048 (planes
+    # are independent, so a slab times the per-plane rate of the full volume).
+    "planes2048": VolumeSpec("planes2048", 64, 2048, 2048, 31, (1.5, 6.0), (0, 90),
+                             (64 * 2048 * 2048) // (16 ** 3), "u16", 10, "simultaneous", seed=6),
     # Batched mix: three uneven volumes.
     "mix_a": VolumeSpec("mix_a", 200, 256, 384, 21, (1.5, 4.0), (0, 90), 4800, "f32", 10,
                         "sequential", seed=41),
