@@ -555,3 +555,15 @@ def test_full_size_vol512_sampled_planes(normalize):
     sub = [np.ascontiguousarray(s[:, ys, :]) for s in vol["stacks"]]
     ref = oracle_run(sub, vol["psfs"], spec.iters, method="fft", normalize=normalize)
     check(got[ys], ref)
+
+
+def test_planes2048_one_plane():
+    """A plane of the 2048³ size class (2 views, 2048×2048, 31×31, uint16):
+    rows wider than any work-group run in three strips with a 15-column halo
+    under the zero boundary."""
+    _say("planes2048: 1 plane of 2048x2048, 31x31, simultaneous")
+    spec = CONFIGS["planes2048"]
+    vol = make_volume(spec, planes=1, truth=False)
+    got = gpu_run(vol["stacks"], vol["psfs"], spec.iters)
+    ref = oracle_run(vol["stacks"], vol["psfs"], spec.iters, method="fft")
+    check(got, ref)
