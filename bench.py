@@ -82,20 +82,30 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
     return vox * b / n, vox * f / n, vox * f_valu / n, vox * f_mfma / n
 
 
+def kernel_code_hash(path):
+    """sha256 of a C++ source with its comments removed and its whitespace
+    collapsed: edits to comments keep it, any change to the code does not."""
+    import hashlib
+    import re
+
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
+
+
 def measured_traffic(name, kind):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (scaled by the factors a copy of known size
-    gives), or None when the kernel source changed since they were taken."""
-    import hashlib
-
+    gives), or None when the kernel code changed since they were taken."""
     path = os.path.join(ROOT, "profiles", f"sep_passes_{name}_traffic.json")
     src = os.path.join(ROOT, "paper_1503_07998_amd", "csrc", "k_sep_impl.hpp")
     try:
         rec = json.load(open(path))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = kernel_code_hash(src)
     except OSError:
         return None
-    if rec.get("kernel_source_sha256") != h:
+    if rec.get("kernel_code_sha256") != h:
         return None
     # the instance of the pass (plain or split-view form) that ran most often in
     # the profiled bench run

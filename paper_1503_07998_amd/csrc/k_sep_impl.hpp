@@ -381,7 +381,7 @@ __device__ __forceinline__ void store8(float *__restrict__ p, int nvalid, bool v
 // register i of every lane accumulates output row g0 + i of its own column:
 // Σ_k tz[i + KB − 1 − k] · in[g0 + k].  A 4-row block needs input rows
 // k = 0 … KB + 2 only (all in the current group's window), KB + 3 steps against
-// 4·KB multiply-adds on the vector ALUs, which stay free for the row pass.
+// 4·KB multiply-adds on the vector ALUs.
 template <int KB, int C, int u>
 __device__ __forceinline__ void zpass(const float *TT, const float (&ring)[C][Shape<KB>::M], float (&acc)[C][G]) {
   constexpr int M = Shape<KB>::M, NK = Shape<KB>::NK, NB = G / 4;

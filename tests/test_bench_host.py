@@ -49,17 +49,27 @@ def test_roofline_bound_and_fraction():
 
 
 def test_traffic_record_guard():
-    """The committed counter record is used only while its kernel-source hash
+    """The committed counter record is used only while its kernel-code hash
     matches; a record for another workload name does not exist."""
     rec = json.load(open(os.path.join(ROOT, "profiles", "sep_passes_vol512_traffic.json")))
     got = bench.measured_traffic("vol512", "backward")
-    import hashlib
     src = os.path.join(ROOT, "paper_1503_07998_amd", "csrc", "k_sep_impl.hpp")
-    same = rec["kernel_source_sha256"] == hashlib.sha256(open(src, "rb").read()).hexdigest()
+    same = rec["kernel_code_sha256"] == bench.kernel_code_hash(src)
     assert (got is not None) == same
     if got is not None:
         assert got["bytes"] > 0 and "backward" in got["instance"]
     assert bench.measured_traffic("no_such_workload", "backward") is None
+
+
+def test_kernel_code_hash_ignores_comments(tmp_path):
+    a = tmp_path / "a.hpp"
+    b = tmp_path / "b.hpp"
+    c = tmp_path / "c.hpp"
+    a.write_text("int f(int x) {  // doubles\n  return 2 * x; /* note */\n}\n")
+    b.write_text("// another remark\nint f(int x) {\n  return 2 * x;\n}\n")
+    c.write_text("int f(int x) {\n  return 3 * x;\n}\n")
+    assert bench.kernel_code_hash(a) == bench.kernel_code_hash(b)
+    assert bench.kernel_code_hash(a) != bench.kernel_code_hash(c)
 
 
 def test_more_than_one_gpu_is_refused():
