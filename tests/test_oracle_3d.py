@@ -26,6 +26,21 @@ def test_conv3d_matches_scipy():
     np.testing.assert_allclose(F.conv3d(a, k), ss.convolve(a, k, mode="same"), rtol=1e-12, atol=1e-12)
 
 
+def test_gaussian_psf3_marginal_is_the_plane_psf():
+    """Summed along the rotation axis, the 3D Gaussian is the 2D Gaussian of
+    the same (σx, σz) that the plane-wise runs use; the y profile is a
+    normalised 1D Gaussian (closed form at the centre: 1 / Σ_l exp(−l²/2σ²))."""
+    from synthetic import gaussian_psf
+
+    p3 = F.gaussian_psf3(11, 1.7, 1.3, 3.1, ky=9)
+    assert p3.shape == (9, 11, 11) and abs(p3.sum() - 1.0) < 1e-14
+    np.testing.assert_allclose(p3.sum(axis=0), gaussian_psf(11, 1.3, 3.1), rtol=1e-12, atol=1e-15)
+    prof = p3.sum(axis=(1, 2))
+    lags = np.arange(9) - 4
+    assert abs(prof[4] - 1.0 / np.exp(-lags ** 2 / (2 * 1.7 ** 2)).sum()) < 1e-14
+    np.testing.assert_allclose(prof, prof[::-1], rtol=1e-14)
+
+
 def test_conv3d_fft_matches_direct():
     rng = _rng(4)
     a = rng.random((7, 12, 10))
