@@ -77,3 +77,23 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode != 0
     assert "one GPU" in p.stdout + p.stderr
+
+
+def test_cpu_baseline_is_bounded():
+    """The oracle leg times one plane; planes larger than 512×512 get fewer
+    iterations so that the leg stays a few seconds."""
+    import numpy as np
+
+    from synthetic import VolumeSpec
+
+    spec = VolumeSpec("tiny", 3, 24, 20, 5, (1.0, 2.0), (0, 90), 4, "u16", 3, "simultaneous", seed=9)
+    rng = np.random.default_rng(0)
+    vol = {"stacks": [rng.integers(90, 200, (24, 3, 20)).astype(np.uint16) for _ in range(2)],
+           "psfs": [np.full((5, 5), 1 / 25, dtype=np.float32)] * 2}
+    out = bench.cpu_baseline(spec, vol, spec.iters)
+    assert out["kind"] == "oracle" and out["value"] > 0 and "all 3 iterations" in out["sample"]
+    wide = VolumeSpec("wide", 1, 1024, 1024, 3, (1.0, 2.0), (0, 90), 4, "u16", 10, "simultaneous", seed=9)
+    vol = {"stacks": [rng.integers(90, 200, (1024, 1, 1024)).astype(np.uint16) for _ in range(2)],
+           "psfs": [np.full((3, 3), 1 / 9, dtype=np.float32)] * 2}
+    out = bench.cpu_baseline(wide, vol, wide.iters)
+    assert "2 of 10 iterations" in out["sample"]
