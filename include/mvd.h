@@ -48,6 +48,7 @@ extern "C" {
 #define MVD_MAX_VIEWS 8
 #define MVD_MAX_K 63
 #define MVD_DEVICE_NONE (-1) /* host-only context: PSF setup and validation only */
+#define MVD_MAX_PLANE_X 65536 /* widest plane row (X) a context accepts */
 
 typedef struct mvd_ctx mvd_ctx;
 
@@ -154,8 +155,8 @@ const char *mvd_status_string(mvd_status s);
 /* Create a context for V views of Z×X planes on HIP device `device`
  * (or MVD_DEVICE_NONE for a host-only context).  *out receives the context,
  * owned by the caller and released with mvd_destroy().
- * Errors: MVD_ERR_ARG (null out, V outside [1, MVD_MAX_VIEWS], Z or X < 1),
- * MVD_ERR_DEVICE (device does not exist). */
+ * Errors: MVD_ERR_ARG (null out, V outside [1, MVD_MAX_VIEWS], Z or X < 1,
+ * X > MVD_MAX_PLANE_X, Z·X > 2^31), MVD_ERR_DEVICE (device does not exist). */
 mvd_status mvd_create(mvd_ctx **out, int n_views, int n_z, int n_x, int device);
 
 /* Release a context (NULL is ignored).  Waits for nothing: the caller must
@@ -323,7 +324,9 @@ typedef struct mvd_batch mvd_batch;
 mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items, uint32_t flags,
                             void *stream);
 
-/* Launch the captured batch on `stream` (asynchronous). */
+/* Launch the captured batch on `stream` (asynchronous).  The batch holds each
+ * item's taps as they were at creation: after mvd_set_psf or mvd_destroy on an
+ * item's context the batch must be recreated (MVD_ERR_STATE, nothing launched). */
 mvd_status mvd_batch_launch(mvd_batch *b, void *stream);
 
 /* Launch shapes chosen for item `item`: out[5] = forward occupancy, forward

@@ -1,0 +1,65 @@
+/*
+ * mvd_testing.h — test and tuning hooks of libmvd (not part of the stable
+ * ABI in mvd.h).
+ *
+ * These entry points expose the host planner's launch geometry so that CPU
+ * tests can check every index the kernels compute against its buffer, and let
+ * one process switch the launch-shape overrides that the MVD_TUNE environment
+ * variable otherwise sets once.  They may change with MVD_TESTING_VERSION;
+ * callers check mvd_internal_version() first.  None of them touches a device.
+ * Return values are mvd_status codes (0 ok, MVD_ERR_ARG on a bad argument,
+ * MVD_ERR_UNSUPPORTED where the asked-for form does not apply).
+ */
+#ifndef MVD_TESTING_H
+#define MVD_TESTING_H
+
+#include <stddef.h>
+
+#include "mvd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MVD_TESTING_VERSION 1
+
+/* MVD_TESTING_VERSION of the library. */
+int mvd_internal_version(void);
+
+/* Launch plan of a separable pass over n_planes planes of ctx's size with a
+ * k-tap kernel under `boundary` (k < 0: the one-ring form for −k taps, which
+ * the forward pass and the one-plane backward use).  out[13]: bucket, columns
+ * per thread, threads, occupancy, row-segment length, segments, outputs per
+ * strip, strips, halo, z-pass columns, LDS row pitch, 16-byte row-pass access
+ * (for 16-byte aligned buffers), LDS bytes per view. */
+int mvd_internal_sep_plan(const mvd_ctx *ctx, int n_planes, int k, int boundary, int *out);
+
+/* The split-view two-plane backward's plan (same out[] layout), or
+ * MVD_ERR_UNSUPPORTED where the form does not apply. */
+int mvd_internal_split_plan(const mvd_ctx *ctx, int n_planes, int k, int *out);
+
+/* The matrix-core K×K pass for a kz × kx kernel.  out[3]: column steps, input
+ * tile row pitch, LDS bytes. */
+int mvd_internal_mfma_plan(int kz, int kx, int *out);
+
+/* The matrix-core tap-gradient correlation for a volume of n_planes × Z × X
+ * and a kz × kx kernel.  out[7]: padded lags (z, x), tile width, tiles per
+ * z run, work items, work-groups, LDS bytes. */
+int mvd_internal_corr_plan(int n_planes, int Z, int X, int kz, int kx, long *out);
+
+/* Replace the process-wide launch-shape overrides (MVD_TUNE syntax,
+ * "key=value,..."; NULL re-reads the environment).  Affects every context of
+ * the process from the next enqueued run on; not thread-safe against calls
+ * running in other threads. */
+int mvd_internal_set_tune(const char *spec);
+
+/* Workspace bytes that the launch-shape tuner's probe (one iteration of the
+ * run, made for MVD_FLAG_TUNE) would use, or 0 when the run makes no probe
+ * (n_iters = 0).  Never more than mvd_workspace_bytes() of the same run. */
+int mvd_internal_tune_probe_bytes(const mvd_ctx *ctx, const mvd_run *run, size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MVD_TESTING_H */

@@ -298,6 +298,55 @@ class Deconvolver:
         except Exception:
             pass
 
+    def check_tensors(self, obs, layout, *, iters, est=None, checkpoints=None, weight_planes=None):
+        """Check the tensors of a run against this context before any pointer
+        reaches the library: one observation per view, all uint16 or all
+        float32 of the layout's shape (camera stack [Z][Y][X] or planes
+        [Y][Z][X]) on one device; est float32 [Y][Z][X]; checkpoints float32
+        with T·Y·Z·X elements; weight planes float32 [Y][Z][X].  Returns
+        (Y, obs dtype name); raises ValueError / TypeError."""
+        torch = _torch()
+        if len(obs) != self.n_views:
+            raise ValueError(f"one observation tensor per view ({self.n_views}), got {len(obs)}")
+        if layout not in ("stack_zyx", "planes_yzx"):
+            raise ValueError(f"unknown layout {layout!r}")
+        o0 = obs[0]
+        if not isinstance(o0, torch.Tensor) or o0.dim() != 3:
+            raise ValueError("observations must be 3D tensors")
+        if o0.dtype not in (torch.uint16, torch.float32):
+            raise TypeError(f"observations must be uint16 or float32, got {o0.dtype}")
+        n_planes = o0.shape[1] if layout == "stack_zyx" else o0.shape[0]
+        want = (self.n_z, n_planes, self.n_x) if layout == "stack_zyx" else (n_planes, self.n_z, self.n_x)
+        for v, o in enumerate(obs):
+            if not isinstance(o, torch.Tensor) or o.dtype != o0.dtype:
+                raise TypeError(f"view {v}: every view must have the dtype of view 0 ({o0.dtype})")
+            if tuple(o.shape) != want:
+                raise ValueError(f"view {v}: shape {tuple(o.shape)} != {want} for layout {layout}")
+            if o.device != o0.device:
+                raise ValueError(f"view {v}: all views must be on one device")
+        plane_shape = (n_planes, self.n_z, self.n_x)
+
+        def f32_of(t, name, shape=None, numel=None):
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float32:
+                raise TypeError(f"{name} must be a float32 tensor")
+            if shape is not None and tuple(t.shape) != shape:
+                raise ValueError(f"{name}: shape {tuple(t.shape)} != {shape}")
+            if numel is not None and t.numel() != numel:
+                raise ValueError(f"{name}: {t.numel()} elements, need {numel}")
+            if t.device != o0.device:
+                raise ValueError(f"{name} must be on the observations' device")
+
+        if est is not None:
+            f32_of(est, "est", shape=plane_shape)
+        if checkpoints is not None:
+            f32_of(checkpoints, "checkpoints", numel=int(iters) * n_planes * self.n_z * self.n_x)
+        if weight_planes is not None:
+            if len(weight_planes) != self.n_views:
+                raise ValueError("one weight plane set per view")
+            for v, w in enumerate(weight_planes):
+                f32_of(w, f"weight_planes[{v}]", shape=plane_shape)
+        return n_planes, ("u16" if o0.dtype == torch.uint16 else "f32")
+
     def set_psf(self, view, taps, back="flipped", back_taps=None):
         mvd_set_psf(self.ctx, view, taps, back, back_taps)
         self.psf_shapes[view] = np.asarray(taps).shape
@@ -311,16 +360,11 @@ class Deconvolver:
             stream=None, normalize=False, weight_planes=None):
         """Deconvolve device observations; returns the estimate ``[Y][Z][X]`` (float32)."""
         torch = _torch()
-        if len(obs) != self.n_views:
-            raise ValueError("one observation tensor per view")
-        o0 = obs[0]
         if layout is None:
             layout = "stack_zyx"
-        if layout == "stack_zyx":
-            n_planes = o0.shape[1]
-        else:
-            n_planes = o0.shape[0]
-        obs_dtype = "u16" if o0.dtype == torch.uint16 else "f32"
+        n_planes, obs_dtype = self.check_tensors(obs, layout, iters=iters, est=est, checkpoints=checkpoints,
+                                                 weight_planes=weight_planes)
+        o0 = obs[0]
         if est is None:
             est = torch.empty((n_planes, self.n_z, self.n_x), dtype=torch.float32, device=o0.device)
         run = make_run(n_planes, iters, update=update, boundary=boundary, init=init,

@@ -46,6 +46,7 @@ class PlanewiseRL:
         self.dec = api.Deconvolver(len(self.obs), self.nz, self.nx, device)
         self.dev = o0.device
         self.timing = False   # record per-launch HIP events (read with api.mvd_get_timing)
+        self._sigma_set = None   # the (σx, σz) values whose taps the context holds
 
     def _run(self, weights, checkpoints=None, ws_bytes=0, tune=False):
         return api.make_run(self.ny, self.iters, update=self.update, boundary=self.boundary,
@@ -53,10 +54,16 @@ class PlanewiseRL:
                             checkpoints=checkpoints, timing=self.timing, tune=tune)
 
     def set_sigmas(self, sigma):
+        """Give the context the taps of these widths (no-op if it holds them already)."""
         s = sigma.detach().to("cpu", dtype=_torch().float64)
+        key = tuple(s.flatten().tolist())
+        if key == self._sigma_set:
+            return
+        self._sigma_set = None
         for v in range(len(self.obs)):
             taps = gaussian_taps(self.k, s[v, 0], s[v, 1]).numpy().astype(np.float32)
             self.dec.set_psf(v, taps, "flipped")
+        self._sigma_set = key
 
     def __call__(self, sigma, weights):
         return mv_deconvolve(sigma, weights, self)
@@ -92,6 +99,9 @@ def _make_function():
         def backward(ctx, grad_out):
             sigma, weights, ck = ctx.saved_tensors
             prob = ctx.prob
+            # the reverse sweep recomputes every iteration with the context's taps: give it
+            # this forward's (another forward may have run in between, as gradcheck does)
+            prob.set_sigmas(sigma)
             V, K = len(prob.obs), prob.k
             run = prob._run(ctx.w, checkpoints=ck.data_ptr())
             nbytes = api.mvd_backward_workspace_bytes(prob.dec.ctx, run)

@@ -1,6 +1,7 @@
 // C ABI of the plane-wise MV-RL library: validation, contexts, PSF setup,
 // workspace layout and the pass schedule of one deconvolution run.
 #include "../../include/mvd.h"
+#include "../../include/mvd_testing.h"
 
 #include <hip/hip_runtime.h>
 
@@ -19,6 +20,7 @@
 #include "psf.hpp"
 
 namespace mvd {
+static_assert(kMaxPlaneX == MVD_MAX_PLANE_X, "the zero row must cover the widest accepted plane");
 hipError_t sep_forward_kb3(const SepPassArgs &, const SepPlan &, hipStream_t);
 hipError_t sep_forward_kb7(const SepPassArgs &, const SepPlan &, hipStream_t);
 hipError_t sep_forward_kb11(const SepPassArgs &, const SepPlan &, hipStream_t);
@@ -129,6 +131,12 @@ struct ViewPsf {
 
 thread_local std::string g_noctx_error;
 
+// Live contexts (pointer → serial), so that a batch can tell a context it
+// captured from one destroyed since (or a new one at the same address).
+std::mutex g_live_mu;
+std::map<const mvd_ctx *, uint64_t> g_live;
+uint64_t g_next_serial = 1;
+
 }  // namespace
 
 struct mvd_ctx {
@@ -155,6 +163,7 @@ struct mvd_ctx {
   };
   std::vector<Graph> graphs;
   uint64_t psf_generation = 0;   // bumped by every mvd_set_psf (captured taps change)
+  uint64_t serial = 0;           // unique per context of the process (live-context registry)
   // streamed runs: copy-in and copy-out streams and their events
   hipStream_t h2d = nullptr, d2h = nullptr;
   hipEvent_t sev[7] = {};        // start, in[2], done[2], out[2]
@@ -1318,7 +1327,23 @@ double drain_marks(mvd_ctx *c) {
 // Time every candidate on one iteration of the item's own run (the item's
 // estimate is overwritten, so items that start from a given estimate are not
 // tuned) and return the fastest.
+// A probe runs one iteration, so it needs the workspace of a run with
+// n_iters ≥ 1; a run without iterations has no passes to tune and makes none.
+bool tune_probe(const mvd_run *r, mvd_run *probe) {
+  if (r->n_iters < 1) return false;
+  *probe = *r;
+  probe->n_iters = 1;
+  probe->checkpoints = nullptr;
+  probe->flags &= ~(MVD_FLAG_GRAPH | MVD_FLAG_TIMING | MVD_FLAG_TUNE);
+  return true;
+}
+
 hipError_t autotune(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, hipStream_t s, Tune *out) {
+  mvd_run probe;
+  if (!tune_probe(r, &probe)) {
+    *out = Tune{};
+    return hipSuccess;
+  }
   const std::string key = tune_key(c, r);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1328,10 +1353,6 @@ hipError_t autotune(mvd_ctx *c, const void *const *obs, float *est, const mvd_ru
       return hipSuccess;
     }
   }
-  mvd_run probe = *r;
-  probe.n_iters = 1;
-  probe.checkpoints = nullptr;
-  probe.flags &= ~(MVD_FLAG_GRAPH | MVD_FLAG_TIMING | MVD_FLAG_TUNE);
   // the caller's timing records are kept aside while the candidates are timed
   std::vector<mvd_ctx::Mark> kept;
   kept.swap(c->marks);
@@ -1374,6 +1395,7 @@ struct mvd_batch {
   int device = -1;
   struct Item {
     mvd_ctx *ctx;
+    uint64_t serial, psf_generation;   // the context's identity and taps at capture
     std::vector<const void *> obs;
     float *est;
     mvd_run run;
@@ -1413,6 +1435,9 @@ mvd_status mvd_create(mvd_ctx **out, int n_views, int n_z, int n_x, int device) 
   if (n_z < 1 || n_x < 1) return fail(nullptr, MVD_ERR_ARG, "plane %d x %d is empty", n_z, n_x);
   if ((long long)n_z * n_x > (1LL << 31))
     return fail(nullptr, MVD_ERR_ARG, "plane %d x %d too large", n_z, n_x);
+  // rows outside the plane are read from a static row of kMaxPlaneX zeros
+  if (n_x > MVD_MAX_PLANE_X)
+    return fail(nullptr, MVD_ERR_ARG, "plane width %d above MVD_MAX_PLANE_X = %d", n_x, MVD_MAX_PLANE_X);
   if (device != MVD_DEVICE_NONE) {
     int n = 0;
     if (device < 0 || hipGetDeviceCount(&n) != hipSuccess || device >= n)
@@ -1425,6 +1450,11 @@ mvd_status mvd_create(mvd_ctx **out, int n_views, int n_z, int n_x, int device) 
   c->X = n_x;
   c->device = device;
   c->views.resize(n_views);
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    c->serial = g_next_serial++;
+    g_live[c] = c->serial;
+  }
   *out = c;
   g_noctx_error.clear();
   return MVD_OK;
@@ -1432,6 +1462,10 @@ mvd_status mvd_create(mvd_ctx **out, int n_views, int n_z, int n_x, int device) 
 
 void mvd_destroy(mvd_ctx *ctx) {
   if (!ctx) return;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.erase(ctx);
+  }
   if (ctx->device != MVD_DEVICE_NONE) {
     DeviceGuard dg(ctx->device);
     for (auto &m : ctx->marks) {
@@ -1626,7 +1660,7 @@ mvd_status mvd_deconvolve_stream(mvd_ctx *c, const void *const *obs, float *est,
   return MVD_OK;
 }
 
-// Internal (not in the public header): the launch geometry the planner picks for
+// Test hook (mvd_testing.h): the launch geometry the planner picks for
 // a separable pass over `n_planes` planes with kernel size k, so host-side tests
 // can check every access of the kernels' index arithmetic against its buffer.
 // out[16]: bucket, cols, threads, occ, zseg, nseg, x_out, nstrip, halo, ncols,
@@ -1656,7 +1690,7 @@ int mvd_internal_sep_plan(const mvd_ctx *c, int n_planes, int k, int boundary, i
 }
 
 
-// Internal (not in the public header): the matrix-core general pass's plan for a
+// Test hook (mvd_testing.h): the matrix-core general pass's plan for a
 // kz × kx kernel, for the host-side bounds model.  out[3]: column steps, input
 // tile row pitch, LDS bytes.
 int mvd_internal_mfma_plan(int kz, int kx, int *out) {
@@ -1667,7 +1701,17 @@ int mvd_internal_mfma_plan(int kz, int kx, int *out) {
   return MVD_OK;
 }
 
-// Internal: replace the process-wide launch-shape overrides (the MVD_TUNE
+int mvd_internal_version(void) { return MVD_TESTING_VERSION; }
+
+int mvd_internal_tune_probe_bytes(const mvd_ctx *c, const mvd_run *r, size_t *bytes) {
+  if (!c || !r || !bytes || r->struct_size != sizeof(mvd_run) || r->n_planes < 1 || r->n_iters < 0)
+    return MVD_ERR_ARG;
+  mvd_run probe;
+  *bytes = tune_probe(r, &probe) ? layout_of(c, &probe).total : 0;
+  return MVD_OK;
+}
+
+// Test hook (mvd_testing.h): replace the process-wide launch-shape overrides (the MVD_TUNE
 // syntax; NULL: re-read the environment).  Lets one process compare the
 // alternative forms of a pass; not thread-safe against running calls.
 int mvd_internal_set_tune(const char *spec) {
@@ -1675,7 +1719,7 @@ int mvd_internal_set_tune(const char *spec) {
   return MVD_OK;
 }
 
-// Internal: the matrix-core tap-gradient correlation's launch for a volume of
+// Test hook (mvd_testing.h): the matrix-core tap-gradient correlation's launch for a volume of
 // n_planes × Z × X and a kz × kx kernel.  out[7]: kzp, kxp, tile width, tiles
 // per z run, work items, work-groups, LDS bytes.
 int mvd_internal_corr_plan(int n_planes, int Z, int X, int kz, int kx, long *out) {
@@ -1687,7 +1731,7 @@ int mvd_internal_corr_plan(int n_planes, int Z, int X, int kz, int kx, long *out
   return MVD_OK;
 }
 
-// Internal: the split-view backward plan (same out[] layout as the separable
+// Test hook (mvd_testing.h): the split-view backward plan (same out[] layout as the separable
 // plan; returns MVD_ERR_UNSUPPORTED where the form does not apply).
 int mvd_internal_split_plan(const mvd_ctx *c, int n_planes, int k, int *out) {
   if (!c || !out || n_planes < 1 || k < 1 || k > MVD_MAX_K) return MVD_ERR_ARG;
@@ -1868,6 +1912,8 @@ mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items,
   for (int i = 0; i < n_items; ++i) {
     mvd_batch::Item it;
     it.ctx = items[i].ctx;
+    it.serial = it.ctx->serial;
+    it.psf_generation = it.ctx->psf_generation;
     it.obs.assign(items[i].obs, items[i].obs + it.ctx->nv);
     it.est = items[i].est;
     it.run = *items[i].run;
@@ -1929,6 +1975,19 @@ mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items,
 
 mvd_status mvd_batch_launch(mvd_batch *b, void *stream) {
   if (!b || !b->exec) return fail(nullptr, MVD_ERR_ARG, "batch is NULL");
+  {
+    // the captured launches hold the items' taps and tap buffers: a context
+    // destroyed or given new PSFs since capture invalidates the batch
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    for (size_t i = 0; i < b->items.size(); ++i) {
+      const auto &it = b->items[i];
+      auto f = g_live.find(it.ctx);
+      if (f == g_live.end() || f->second != it.serial)
+        return fail(nullptr, MVD_ERR_STATE, "item %zu: its context was destroyed after the batch was created", i);
+      if (it.ctx->psf_generation != it.psf_generation)
+        return fail(nullptr, MVD_ERR_STATE, "item %zu: mvd_set_psf was called after the batch was created", i);
+    }
+  }
   DeviceGuard dg(b->device);
   hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
   if (e != hipSuccess) return fail(nullptr, MVD_ERR_LAUNCH, "graph launch failed: %s", hipGetErrorString(e));

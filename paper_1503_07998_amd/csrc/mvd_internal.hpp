@@ -10,7 +10,7 @@ namespace mvd {
 
 constexpr int kMaxViews = 8;
 constexpr int kMaxK = 63;
-constexpr int kMaxPlaneX = 65536;   // plane width limit (row of zeros of this size)
+constexpr int kMaxPlaneX = 65536;   // plane width limit (row of zeros of this size; mvd_create enforces it)
 constexpr float kEps = 1e-6f;   // ratio guard: φ/b where b > kEps, else 1
 
 // Views handled by one separable pass launch.

@@ -70,6 +70,10 @@ def test_create_validation():
     assert _status(api.mvd_create, 9, 4, 4, -1) == N.MVD_ERR_ARG
     assert _status(api.mvd_create, 1, 0, 4, -1) == N.MVD_ERR_ARG
     assert _status(api.mvd_create, 1, 4, 0, -1) == N.MVD_ERR_ARG
+    # rows outside the plane are read from a static zero row of MVD_MAX_PLANE_X floats
+    assert _status(api.mvd_create, 1, 4, 65537, -1) == N.MVD_ERR_ARG
+    assert "MVD_MAX_PLANE_X" in api.mvd_last_error(None)
+    api.mvd_destroy(api.mvd_create(1, 4, 65536, -1))
     # no GPU in this process: any real device index is unavailable
     assert _status(api.mvd_create, 1, 4, 4, 0) == N.MVD_ERR_DEVICE
     assert "not available" in api.mvd_last_error(None)
@@ -327,5 +331,81 @@ def test_stream_validation_before_device():
         assert lib.mvd_deconvolve_stream(ctx, dummy, None, ctypes.byref(r), 2, None) == N.MVD_ERR_ARG
         n = ctypes.c_size_t()
         assert lib.mvd_stream_workspace_bytes(ctx, ctypes.byref(r), 0, 0, ctypes.byref(n)) == N.MVD_ERR_ARG
+    finally:
+        api.mvd_destroy(ctx)
+
+
+def test_deconvolver_rejects_mismatched_tensors():
+    """Deconvolver.run checks every tensor against the context before any pointer
+    reaches the library (CPU tensors here: the checks come first)."""
+    import torch
+
+    d = api.Deconvolver(2, 6, 8, N.MVD_DEVICE_NONE)
+    try:
+        ok = [torch.zeros((6, 3, 8), dtype=torch.uint16) for _ in range(2)]   # stack [Z][Y][X]
+        assert d.check_tensors(ok, "stack_zyx", iters=2) == (3, "u16")
+        planes = [torch.zeros((3, 6, 8), dtype=torch.float32) for _ in range(2)]
+        assert d.check_tensors(planes, "planes_yzx", iters=2) == (3, "f32")
+        with pytest.raises(ValueError):
+            d.check_tensors(ok[:1], "stack_zyx", iters=2)                     # one view short
+        with pytest.raises(ValueError):
+            d.check_tensors([ok[0], torch.zeros((6, 3, 9), dtype=torch.uint16)], "stack_zyx", iters=2)
+        with pytest.raises(ValueError):
+            d.check_tensors(ok, "planes_yzx", iters=2)                        # wrong layout for the shape
+        with pytest.raises(TypeError):
+            d.check_tensors([t.to(torch.float64) for t in planes], "planes_yzx", iters=2)
+        with pytest.raises(TypeError):
+            d.check_tensors([planes[0], planes[1].to(torch.int32)], "planes_yzx", iters=2)
+        with pytest.raises(ValueError):
+            d.check_tensors(planes, "planes_yzx", iters=2, est=torch.zeros((3, 6, 7)))
+        with pytest.raises(TypeError):
+            d.check_tensors(planes, "planes_yzx", iters=2, est=torch.zeros((3, 6, 8), dtype=torch.float64))
+        with pytest.raises(ValueError):
+            d.check_tensors(planes, "planes_yzx", iters=2, checkpoints=torch.zeros((1, 3, 6, 8)))
+        d.check_tensors(planes, "planes_yzx", iters=2, checkpoints=torch.zeros((2, 3, 6, 8)))
+        with pytest.raises(ValueError):
+            d.check_tensors(planes, "planes_yzx", iters=2, weight_planes=[torch.zeros((3, 6, 8))])
+        with pytest.raises(ValueError):
+            d.run([torch.zeros((6, 3, 9), dtype=torch.uint16)] * 2, iters=1)
+    finally:
+        d.close()
+
+
+def _testing_symbols():
+    text = open(os.path.join(ROOT, "include", "mvd_testing.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mvd_internal_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_testing_hook():
+    """The test and tuning hooks are declared in include/mvd_testing.h, versioned."""
+    lib = N.lib()
+    names = _testing_symbols()
+    assert len(names) >= 6
+    for name in names:
+        assert hasattr(lib, name), name
+    text = open(os.path.join(ROOT, "include", "mvd_testing.h")).read()
+    want = int(re.search(r"#define MVD_TESTING_VERSION (\d+)", text).group(1))
+    assert lib.mvd_internal_version() == want
+
+
+def test_tune_probe_fits_the_reported_workspace():
+    """The tuner's one-iteration probe never needs more workspace than the run
+    reports (a run without iterations makes no probe at all)."""
+    lib = N.lib()
+    lib.mvd_internal_tune_probe_bytes.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
+    ctx = api.mvd_create(3, 24, 40, N.MVD_DEVICE_NONE)
+    try:
+        for v in range(3):
+            api.mvd_set_psf(ctx, v, gaussian_psf(9, 1.5, 3.0))
+        for update in ("simultaneous", "sequential"):
+            for iters in (0, 1, 4):
+                r = api.make_run(5, iters, update=update, tune=True)
+                need = api.mvd_workspace_bytes(ctx, r)
+                probe = ctypes.c_size_t()
+                assert lib.mvd_internal_tune_probe_bytes(ctx, ctypes.byref(r), ctypes.byref(probe)) == 0
+                assert probe.value <= need, (update, iters, probe.value, need)
+                if iters == 0:
+                    assert probe.value == 0
     finally:
         api.mvd_destroy(ctx)

@@ -214,3 +214,34 @@ def test_autograd_sigma_gradients():
     close(sigma.grad.numpy(), ref_gs, "dL/dsigma")
     close(w.grad.numpy(), ref_gw, "dL/dw")
     prob.dec.close()
+
+
+def test_autograd_backward_uses_its_own_forward_sigma():
+    """forward(σ1), forward(σ2), then backward of the first: the reverse sweep
+    must recompute with σ1's taps (the context holds σ2's after the second call)."""
+    from paper_1503_07998_amd.autograd import PlanewiseRL
+
+    torch = _torch()
+    _say("autograd: backward after an interleaved forward")
+    rng = np.random.default_rng(19)
+    Y, Z, X, k, T = 2, 32, 40, 11, 3
+    truth = 100.0 + 600.0 * (rng.random((Y, Z, X)) > 0.95)
+    data_sig = [(1.5, 3.0), (3.0, 1.5)]
+    phis = [oracle.conv2d(truth, OA.gaussian_taps(k, *s)[0]) + rng.uniform(0, 2, truth.shape) for s in data_sig]
+    stacks = [np.ascontiguousarray(np.transpose(p, (1, 0, 2))).astype(np.float32) for p in phis]
+    sig1, sig2 = [(1.7, 3.3), (3.2, 1.6)], [(2.4, 2.1), (1.9, 2.8)]
+    ws = [0.9, 0.8]
+    prob = PlanewiseRL([torch.from_numpy(s).to("cuda:0") for s in stacks], k, T)
+    s1 = torch.tensor(sig1, dtype=torch.float64, requires_grad=True)
+    w1 = torch.tensor(ws, dtype=torch.float64, requires_grad=True)
+    psi1 = prob(s1, w1)
+    s2 = torch.tensor(sig2, dtype=torch.float64, requires_grad=True)
+    _ = prob(s2, torch.tensor(ws, dtype=torch.float64))
+    loss = ((psi1.double() - torch.from_numpy(truth).to("cuda:0")) ** 2).mean()
+    loss.backward()
+    phis32 = [oracle.reslice(s) for s in stacks]
+    ref_loss, ref_gs, ref_gw = OA.sigma_gradients(phis32, sig1, ws, T, truth, k)
+    assert abs(loss.item() - ref_loss) <= 1e-4 * ref_loss
+    close(s1.grad.numpy(), ref_gs, "dL/dsigma (first forward)")
+    close(w1.grad.numpy(), ref_gw, "dL/dw (first forward)")
+    prob.dec.close()

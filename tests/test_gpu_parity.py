@@ -567,3 +567,38 @@ def test_planes2048_one_plane():
     got = gpu_run(vol["stacks"], vol["psfs"], spec.iters)
     ref = oracle_run(vol["stacks"], vol["psfs"], spec.iters, method="fft")
     check(got, ref)
+
+
+def test_tuned_run_without_iterations_is_the_mean():
+    """MVD_FLAG_TUNE with T = 0: no probe is made (there are no passes), so the
+    run stays inside its reported workspace and returns ψ^0, the views' mean."""
+    from paper_1503_07998_amd import api
+
+    torch = _torch()
+    _say("tuned run, 0 iterations")
+    rng = np.random.default_rng(77)
+    stacks = [rng.integers(0, 4000, (40, 6, 64)).astype(np.uint16) for _ in range(2)]
+    psfs = [gaussian_psf(15, 1.5, 4.0), gaussian_psf(15, 4.0, 1.5)]
+    ctx = api.mvd_create(2, 40, 64, 0)
+    try:
+        for v in range(2):
+            api.mvd_set_psf(ctx, v, psfs[v])
+        obs = [_dev(s) for s in stacks]
+        est = torch.empty((6, 40, 64), dtype=torch.float32, device="cuda:0")
+        run = api.make_run(6, 0, obs_dtype="u16", tune=True)
+        nbytes = api.mvd_workspace_bytes(ctx, run)
+        # the workspace sits at the end of its allocation: a write past it would land
+        # in the guard bytes after it, which must stay untouched
+        guard = 1 << 20
+        buf = torch.full((nbytes + guard + 256,), 0xAB, dtype=torch.uint8, device="cuda:0")
+        base = (buf.data_ptr() + 255) // 256 * 256
+        run.workspace = base if nbytes else None
+        run.workspace_bytes = nbytes
+        api.mvd_deconvolve_planes(ctx, obs, est, run)
+        torch.cuda.synchronize()
+        off = base - buf.data_ptr() + nbytes
+        assert bool((buf[off:off + guard] == 0xAB).all()), "the run wrote past its workspace"
+        ref = oracle.deconvolve(stacks, [p.astype(np.float64) for p in psfs], 0)
+        np.testing.assert_allclose(est.cpu().numpy(), ref, rtol=1e-6, atol=0)
+    finally:
+        api.mvd_destroy(ctx)

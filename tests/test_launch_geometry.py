@@ -18,6 +18,7 @@ from paper_1503_07998_amd import api
 G = 8      # rows per ring step
 NX = 8     # row-pass outputs per item
 LDS_LIMIT = 160 * 1024
+MAX_PLANE_X = 65536   # length of the kernels' static zero row (rows outside the plane)
 
 
 def plan(ctx, Y, k, boundary, one_ring=False):
@@ -89,12 +90,17 @@ def check_geometry(Y, Z, X, k, boundary, views, one_ring=False):
         zs = seg * p["zseg"]
         ze = min(zs + p["zseg"], Z)
         ngroups = (ze - zs + G - 1) // G
-        # ring rows: every row index (incl. the prefetch of the group after the last) is clamped
+        # ring rows: every row index (incl. the prefetch of the group after the last) is clamped;
+        # a row outside the plane under the zero boundary reads the static zero row at the
+        # threads' source columns, which must lie inside it
+        max_gx = X - 1
         for m in range(0, (ngroups + 1) * G + KB - 1):
             rr = zs - R + m
             if boundary == "zero":
                 if 0 <= rr < Z:
                     assert 0 <= rr * X < plane
+                else:
+                    assert max_gx < MAX_PLANE_X, "zero-row read past its end"
             else:
                 assert 0 <= (rr % Z) < Z
         # clamped item rows; the forward pass reads the observations at
@@ -390,3 +396,11 @@ def test_wide_rows_geometry_in_bounds(shape, k):
             check_geometry(Y, Z, X, k, boundary, 2, one_ring=True)
     finally:
         lib.mvd_internal_set_tune(None)
+
+
+@pytest.mark.parametrize("k", [3, 31, 63])
+def test_widest_accepted_plane_geometry_in_bounds(k):
+    """The widest plane a context accepts (MVD_MAX_PLANE_X columns): strips with
+    halos, and every zero-row read inside the static row."""
+    for boundary in ("zero", "periodic"):
+        check_geometry(1, 3, MAX_PLANE_X, k, boundary, 1)
