@@ -213,6 +213,26 @@ mvd_status mvd_reslice(mvd_ctx *ctx, const void *stack, int dtype, int n_planes,
 mvd_status mvd_deconvolve_planes(mvd_ctx *ctx, const void *const *obs, float *est,
                                  const mvd_run *run, void *stream);
 
+/* Allocation-free form of mvd_deconvolve_planes, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments and results (bitwise)
+ * except that run->workspace must be NULL and run->workspace_bytes 0: the
+ * workspace is a static device array of MVD_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends.  Planes are
+ * independent, so the volume goes through all T iterations in batches of as
+ * many planes as fit the scratch (mvd_workspace_bytes of a batch ≤
+ * MVD_SCRATCH_BYTES).  The call makes no device allocation: no hipMalloc,
+ * events or graphs (MVD_FLAG_TIMING, MVD_FLAG_GRAPH and MVD_FLAG_TUNE are
+ * rejected).  Every call on a GPU shares that GPU's scratch, which keeps the
+ * last call's contents (every value a run reads from it, it has written
+ * first): calls that overlap on one GPU (several streams or threads) race.
+ * Errors: as mvd_deconvolve_planes; MVD_ERR_WORKSPACE when one plane's
+ * workspace exceeds MVD_SCRATCH_BYTES, MVD_ERR_ARG with a workspace or one of
+ * those flags. */
+#define MVD_SCRATCH_BYTES (64u << 20)
+mvd_status mvd_deconvolve_planes_static(mvd_ctx *ctx, const void *const *obs, float *est,
+                                        const mvd_run *run, void *stream);
+
 /* ---- streamed form ---------------------------------------------------------
  * The whole run of mvd_deconvolve_planes on camera-ordered stacks that stay in
  * host memory: planes are independent, so the volume is processed in batches

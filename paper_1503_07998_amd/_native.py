@@ -35,6 +35,7 @@ MVD_FLAG_NORMALIZE = 0x10
 MVD_DEVICE_NONE = -1
 MVD_MAX_VIEWS = 8
 MVD_MAX_K = 63
+MVD_SCRATCH_BYTES = 64 << 20   # static scratch of mvd_deconvolve_planes_static (per GPU)
 
 
 class MvdRun(ctypes.Structure):
@@ -92,6 +93,7 @@ SIGNATURES = {
     "mvd_workspace_bytes": (c_int, [c_void_p, POINTER(MvdRun), POINTER(c_size_t)]),
     "mvd_reslice": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "mvd_deconvolve_planes": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), c_void_p]),
+    "mvd_deconvolve_planes_static": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), c_void_p]),
     "mvd_get_timing": (c_int, [c_void_p, POINTER(MvdTiming), c_int]),
     "mvd_backward_workspace_bytes": (c_int, [c_void_p, POINTER(MvdRun), POINTER(c_size_t)]),
     "mvd_backward": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), POINTER(c_void_p),

@@ -19,7 +19,7 @@ __all__ = [
     "mvd_get_timing", "mvd_last_error", "make_run", "Deconvolver", "deconvolve",
     "mvd_backward_workspace_bytes", "mvd_backward", "mvd_batch_create", "mvd_batch_launch",
     "mvd_batch_tuning", "mvd_batch_destroy", "mvd_batch_run", "Batch",
-    "mvd_stream_workspace_bytes", "mvd_deconvolve_stream",
+    "mvd_stream_workspace_bytes", "mvd_deconvolve_stream", "mvd_deconvolve_planes_static",
 ]
 
 
@@ -157,6 +157,14 @@ def mvd_deconvolve_planes(ctx, obs, est, run, stream=None) -> None:
     ptrs = (c_void_p * len(obs))(*[_dev_ptr(o).value for o in obs])
     N.check(N.lib().mvd_deconvolve_planes(ctx, ptrs, _dev_ptr(est), ctypes.byref(run),
                                           _stream_handle(stream)), ctx)
+
+
+def mvd_deconvolve_planes_static(ctx, obs, est, run, stream=None) -> None:
+    """The allocation-free form: ``run`` carries no workspace (the library's
+    static per-device scratch is used instead)."""
+    ptrs = (c_void_p * len(obs))(*[_dev_ptr(o).value for o in obs])
+    N.check(N.lib().mvd_deconvolve_planes_static(ctx, ptrs, _dev_ptr(est), ctypes.byref(run),
+                                                 _stream_handle(stream)), ctx)
 
 
 def _any_ptr(t):

@@ -137,6 +137,32 @@ std::mutex g_live_mu;
 std::map<const mvd_ctx *, uint64_t> g_live;
 uint64_t g_next_serial = 1;
 
+// Device scratch of mvd_deconvolve_planes_static: one array per GPU, held
+// until the process ends.  Host code never uses the array's name as an
+// address (in host code it is only a stand-in for the symbol): each device's
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is passed to kernels.
+constexpr size_t kScratchBytes = (size_t)MVD_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;
+
+// With `dev` current: this device's scratch address, taken on first use.
+hipError_t scratch_setup(int dev, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = p;
+  *out = p;
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct mvd_ctx {
@@ -1010,7 +1036,11 @@ int plane_batch(const mvd_run *r, const Tune &tn) {
 // set there); the results do not depend on the batch size.
 hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, hipStream_t s,
                        const Tune &tn, bool timing_override = false) {
-  const Layout L = layout_of(c, r);
+  // a batch of B planes uses the first B planes of every workspace set
+  const int B = plane_batch(r, tn);
+  mvd_run rl = *r;
+  rl.n_planes = B;
+  const Layout L = layout_of(c, &rl);
   const PlaneGeom g{r->n_planes, c->Z, c->X};
   const size_t n = (size_t)g.Y * g.Z * g.X;
   char *ws = static_cast<char *>(r->workspace);
@@ -1028,7 +1058,6 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
   const ObsRef whole = obs_given(obs, r->obs_dtype, r->obs_layout, g, nullptr);
   const size_t esz = r->obs_dtype == MVD_U16 ? 2 : 4;
   const int T = r->n_iters;
-  const int B = plane_batch(r, tn);
   hipError_t e = hipSuccess;
   for (int y0 = 0; y0 < g.Y && e == hipSuccess; y0 += B) {
     const PlaneGeom gb{std::min(B, g.Y - y0), g.Z, g.X};
@@ -1443,6 +1472,15 @@ mvd_status mvd_create(mvd_ctx **out, int n_views, int n_z, int n_x, int device) 
     if (device < 0 || hipGetDeviceCount(&n) != hipSuccess || device >= n)
       return fail(nullptr, MVD_ERR_DEVICE, "HIP device %d not available", device);
   }
+  if (device != MVD_DEVICE_NONE) {
+    // the static entry point's scratch address on this device (once per device)
+    DeviceGuard dg(device);
+    void *p = nullptr;
+    if (!dg.ok()) return fail(nullptr, MVD_ERR_DEVICE, "cannot select device %d", device);
+    const hipError_t e = scratch_setup(device, &p);
+    if (e != hipSuccess)
+      return fail(nullptr, MVD_ERR_DEVICE, "device %d: scratch address unavailable: %s", device, hipGetErrorString(e));
+  }
   mvd_ctx *c = new (std::nothrow) mvd_ctx;
   if (!c) return fail(nullptr, MVD_ERR_ALLOC, "out of host memory");
   c->nv = n_views;
@@ -1612,6 +1650,49 @@ mvd_status mvd_deconvolve_planes(mvd_ctx *c, const void *const *obs, float *est,
   } else {
     e = enqueue_run(c, obs, est, r, (hipStream_t)stream, tn);
   }
+  if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "launch failed: %s", hipGetErrorString(e));
+  return MVD_OK;
+}
+
+mvd_status mvd_deconvolve_planes_static(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r,
+                                        void *stream) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  mvd_status st = check_run(c, r);
+  if (st != MVD_OK) return st;
+  if (r->flags & (MVD_FLAG_TIMING | MVD_FLAG_GRAPH | MVD_FLAG_TUNE))
+    return fail(c, MVD_ERR_ARG, "timing, graph and tuning flags create events or graphs: not in the static form");
+  if (r->workspace || r->workspace_bytes)
+    return fail(c, MVD_ERR_ARG, "the static form uses the library's scratch: pass no workspace");
+  if (!obs) return fail(c, MVD_ERR_ARG, "obs is NULL");
+  for (int v = 0; v < c->nv; ++v)
+    if (!obs[v]) return fail(c, MVD_ERR_ARG, "obs[%d] is NULL", v);
+  if (!est) return fail(c, MVD_ERR_ARG, "est is NULL");
+  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
+  if (c->device == MVD_DEVICE_NONE) return fail(c, MVD_ERR_DEVICE, "host-only context");
+  // the largest batch of planes whose workspace fits the scratch; each batch
+  // goes through all iterations (planes are independent)
+  auto need = [&](int planes) {
+    mvd_run one = *r;
+    one.n_planes = planes;
+    return layout_of(c, &one).total;
+  };
+  if (need(1) > kScratchBytes)
+    return fail(c, MVD_ERR_WORKSPACE, "one plane needs %zu bytes of workspace; the static scratch holds %zu",
+                need(1), kScratchBytes);
+  int B = (int)std::min<size_t>((size_t)r->n_planes, std::max<size_t>(1, kScratchBytes / need(1)));
+  while (B > 1 && need(B) > kScratchBytes) --B;
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
+  void *ptr = nullptr;
+  hipError_t e = scratch_setup(c->device, &ptr);
+  if (e != hipSuccess) return fail(c, MVD_ERR_DEVICE, "scratch address unavailable: %s", hipGetErrorString(e));
+  mvd_run rr = *r;
+  rr.workspace = ptr;
+  rr.workspace_bytes = kScratchBytes;
+  Tune tn = tune();
+  tn.plane_batch = tn.plane_batch > 0 ? std::min(tn.plane_batch, B) : B;
+  e = enqueue_run(c, obs, est, &rr, (hipStream_t)stream, tn);
   if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "launch failed: %s", hipGetErrorString(e));
   return MVD_OK;
 }

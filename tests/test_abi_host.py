@@ -409,3 +409,38 @@ def test_tune_probe_fits_the_reported_workspace():
                     assert probe.value == 0
     finally:
         api.mvd_destroy(ctx)
+
+
+def test_static_entry_point_validation_before_device():
+    """The allocation-free form checks its arguments before any device work: no
+    workspace may be given, event/graph flags are refused, host-only contexts
+    have no device scratch."""
+    lib = N.lib()
+    ctx = api.mvd_create(1, 8, 8, N.MVD_DEVICE_NONE)
+    try:
+        api.mvd_set_psf(ctx, 0, np.ones((3, 3)) / 9)
+        ptrs = (ctypes.c_void_p * 1)(ctypes.c_void_p(4096))
+        est = ctypes.c_void_p(8192)
+        r = api.make_run(2, 1)
+        assert lib.mvd_deconvolve_planes_static(ctx, ptrs, est, ctypes.byref(r), None) == N.MVD_ERR_DEVICE
+        r.workspace = 4096
+        r.workspace_bytes = 1 << 20
+        assert lib.mvd_deconvolve_planes_static(ctx, ptrs, est, ctypes.byref(r), None) == N.MVD_ERR_ARG
+        for kw in ({"timing": True}, {"graph": True}, {"tune": True}):
+            r = api.make_run(2, 1, **kw)
+            assert lib.mvd_deconvolve_planes_static(ctx, ptrs, est, ctypes.byref(r), None) == N.MVD_ERR_ARG
+        r = api.make_run(2, 1)
+        assert lib.mvd_deconvolve_planes_static(ctx, None, est, ctypes.byref(r), None) == N.MVD_ERR_ARG
+        assert lib.mvd_deconvolve_planes_static(ctx, ptrs, None, ctypes.byref(r), None) == N.MVD_ERR_ARG
+    finally:
+        api.mvd_destroy(ctx)
+    # a plane whose own workspace exceeds the scratch (2 views of 4096x2048 float32:
+    # 64 MiB of ratio planes alone) is refused up front
+    big = api.mvd_create(2, 4096, 2048, N.MVD_DEVICE_NONE)
+    try:
+        for v in range(2):
+            api.mvd_set_psf(big, v, np.ones((3, 3)) / 9)
+        one = api.make_run(1, 1)
+        assert api.mvd_workspace_bytes(big, one) > N.MVD_SCRATCH_BYTES
+    finally:
+        api.mvd_destroy(big)
