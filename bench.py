@@ -171,39 +171,77 @@ def launch_kinds(spec, tim, steps, vox, batches=1, general=False):
     return kinds
 
 
-def cpu_baseline(spec, vol, iters, normalize=False):
+def host_cores():
+    """Host threads this process may use (capped at 16, the machine's CPU share)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _oracle_job(job):
+    """One worker's share of the CPU baseline: the oracle on its planes."""
     import numpy as np
 
     import oracle
 
-    y = spec.n_planes // 2
-    sub = [np.ascontiguousarray(s[:, y:y + 1, :]) for s in vol["stacks"]]
-    # about as much work as 10 iterations of a 512×512 plane (a few seconds):
-    # every iteration of a larger plane costs the same, so fewer are timed
+    stacks, psfs, iters, update, normalize = job
+    oracle.deconvolve(stacks, [np.asarray(p, dtype=np.float64) for p in psfs], iters, update=update,
+                      normalize=normalize, method="fft")
+    return True
+
+
+def oracle_pool(jobs):
+    """Run oracle jobs over worker processes (one job each, at most host_cores()
+    at a time); returns (wall seconds of the timed map, workers used)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    workers = min(host_cores(), len(jobs))
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_oracle_job, [jobs[0]] * workers))   # start and warm every worker
+        t0 = time.perf_counter()
+        list(ex.map(_oracle_job, jobs))
+        return time.perf_counter() - t0, workers
+
+
+def cpu_baseline(spec, vol, iters, normalize=False):
+    """The float64 oracle on the host's cores: one plane per worker process, a
+    seeded sample of the workload's planes, the oracle's FFT convolution mode
+    (pinned to its direct sum)."""
+    cores = host_cores()
+    y0 = max(0, spec.n_planes // 2 - cores // 2)
+    ys = list(range(y0, min(spec.n_planes, y0 + cores)))
+    # about 10 iterations of a 512×512 plane per worker: larger planes time fewer iterations
     n_it = max(1, min(iters, (10 * 512 * 512) // (spec.n_z * spec.n_x)))
-    t0 = time.perf_counter()
-    oracle.deconvolve(sub, [p.astype(np.float64) for p in vol["psfs"]], n_it, update=spec.update,
-                      normalize=normalize)
-    dt = time.perf_counter() - t0
-    vox_it = spec.n_z * spec.n_x * n_it
+    jobs = [([s[:, y:y + 1, :].copy() for s in vol["stacks"]], vol["psfs"], n_it, spec.update, normalize)
+            for y in ys]
+    dt, workers = oracle_pool(jobs)
+    vox_it = len(ys) * spec.n_z * spec.n_x * n_it
     which = f"all {iters}" if n_it == iters else f"{n_it} of {iters}"
-    return {"value": vox_it / dt, "unit": "voxel-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 of {spec.n_planes} planes (plane {y}), {which} iterations, "
-                      f"{spec.n_views} views, direct FP64 convolution, {dt:.1f} s"}
+    return {"value": vox_it / dt, "unit": "voxel-iterations/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(ys)} of {spec.n_planes} planes ({ys[0]}..{ys[-1]}), one per worker process, "
+                      f"{which} iterations, {spec.n_views} views, FP64 FFT convolution, {dt:.1f} s"}
 
 
-def bench_mix(args):
-    """Three uneven volumes: plain per-volume calls vs one batched graph launch."""
+def mix_record(args, cpu=True):
+    """Three uneven volumes: plain per-volume calls vs one batched launch.
+    Returns a dict: batched and plain rates, their ratio, the largest relative
+    difference between the two estimates, the roofline of the mix's dominant
+    kernel (from HIP-event timings of the plain calls) and the CPU baseline."""
     import numpy as np
 
     from synthetic import CONFIGS, make_volume
 
     specs = [CONFIGS["mix_a"], CONFIGS["mix_b"], CONFIGS["mix_c"]]
     vols = []
+    workers = host_cores()
     for spec in specs:   # all inputs drawn before the GPU is touched
         log(f"generating {spec.name}: {spec.n_views} views, {spec.n_planes} planes of {spec.n_z}x{spec.n_x}, "
             f"K={spec.psf_k}")
-        vols.append(make_volume(spec, truth=False))
+        vols.append(make_volume(spec, truth=False, workers=workers))
+    cpu_jobs = []
+    for spec, vol in zip(specs, vols):   # one plane of each volume for the CPU baseline
+        y = spec.n_planes // 2
+        cpu_jobs.append(([np.ascontiguousarray(s[:, y:y + 1, :]) for s in vol["stacks"]], vol["psfs"], 1,
+                         spec.update, False))
     import torch
 
     from paper_1503_07998_amd import api
@@ -217,19 +255,23 @@ def bench_mix(args):
         for v, p in enumerate(vol["psfs"]):
             d.set_psf(v, p)
         est = torch.empty((spec.n_planes, spec.n_z, spec.n_x), dtype=torch.float32, device=dev)
-        run = api.make_run(spec.n_planes, spec.iters, update=spec.update, boundary=spec.boundary,
-                           obs_dtype=spec.obs_dtype, layout="stack_zyx", tune=True)
-        nb = api.mvd_workspace_bytes(d.ctx, run)
+        runs = {}
+        for timing in (False, True):
+            runs[timing] = api.make_run(spec.n_planes, spec.iters, update=spec.update, boundary=spec.boundary,
+                                        obs_dtype=spec.obs_dtype, layout="stack_zyx", tune=True, timing=timing)
+        nb = api.mvd_workspace_bytes(d.ctx, runs[False])
         ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
-        run.workspace = (ws.data_ptr() + 255) // 256 * 256
-        run.workspace_bytes = nb
-        setups.append(dict(spec=spec, obs=obs, dec=d, est=est, run=run, ws=ws))
+        for r in runs.values():
+            r.workspace = (ws.data_ptr() + 255) // 256 * 256
+            r.workspace_bytes = nb
+        setups.append(dict(spec=spec, obs=obs, dec=d, est=est, runs=runs, ws=ws))
     vox_it = sum(sp.voxels * sp.iters for sp in specs)
 
-    def plain_step():   # tuned launch shapes too (first call), so only the single launch differs
+    def plain_step(timing=False):   # tuned launch shapes too (first call), so only the single launch differs
         for st in setups:
-            api.mvd_deconvolve_planes(st["dec"].ctx, st["obs"], st["est"], st["run"])
+            api.mvd_deconvolve_planes(st["dec"].ctx, st["obs"], st["est"], st["runs"][timing])
 
+    log("mix: plain per-volume calls")
     for _ in range(args.warmup):
         plain_step()
     torch.cuda.synchronize()
@@ -239,9 +281,19 @@ def bench_mix(args):
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     plain_out = [st["est"].cpu().numpy().copy() for st in setups]
+    # launch durations of one plain step, per volume
+    for st in setups:
+        api.mvd_get_timing(st["dec"].ctx, reset=True)
+    plain_step(timing=True)
+    torch.cuda.synchronize()
+    per_vol = []
+    for st in setups:
+        tim = api.mvd_get_timing(st["dec"].ctx, reset=True)
+        kinds = launch_kinds(st["spec"], tim, 1, st["spec"].voxels)
+        per_vol.append((st["spec"], kinds))
 
-    log("batch: autotune + capture")
-    entries = [(st["dec"].ctx, st["obs"], st["est"], st["run"]) for st in setups]
+    log("mix: batch: autotune + capture")
+    entries = [(st["dec"].ctx, st["obs"], st["est"], st["runs"][False]) for st in setups]
     b = api.Batch(entries, tune=True)
     for _ in range(args.warmup):
         b.launch()
@@ -255,25 +307,80 @@ def bench_mix(args):
                for st, ref in zip(setups, plain_out))
     tuning = [b.tuning(i) for i in range(len(setups))]
     b.close()
+    # the dominant kernel of the mix: the (volume, pass) with the largest total launch time
+    spec_d, kinds_d = max(per_vol, key=lambda sk: max(k["avg_ms"] * k["launches"] for k in sk[1].values()))
+    roof = roofline(spec_d, kinds_d, variant=True)
+    roof["kernel"] = f"{spec_d.name}: " + roof["kernel"]
     out = {
-        "metric": "voxel-iterations/s",
-        "value": vox_it / (batch_ms / 1e3),
-        "unit": "voxel-iterations/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": batch_ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batched mix: 200 planes 256x384 (2 views, 21x21), 300 planes 512x768 "
-                               "(3 views, 31x31), 150 planes 1000x1000 (4 views, 41x41), f32 Poisson "
-                               "observations, 10 sequential iterations, zero boundary",
-                   "voxels": sum(sp.voxels for sp in specs), "parallelism": "single GPU"},
-        "plain_value": vox_it / (plain_ms / 1e3),
-        "plain_ms_per_step": plain_ms,
-        "batched_over_plain": plain_ms / batch_ms,
-        "max_rel_diff_batched_vs_plain": diff,
-        "tuning": tuning,
+        "value": vox_it / (batch_ms / 1e3), "unit": "voxel-iterations/s", "ms_per_step": batch_ms,
+        "plain_value": vox_it / (plain_ms / 1e3), "plain_ms_per_step": plain_ms,
+        "batched_over_plain": plain_ms / batch_ms, "max_rel_diff_batched_vs_plain": diff,
+        "workload": "batched mix: 200 planes 256x384 (2 views, 21x21), 300 planes 512x768 (3 views, 31x31), "
+                    "150 planes 1000x1000 (4 views, 41x41), f32 Poisson observations, 10 sequential iterations, "
+                    "zero boundary",
+        "voxels": sum(sp.voxels for sp in specs), "tuning": tuning,
+        "kernels": {sp.name: k for sp, k in per_vol},
+        "roofline": roof,
     }
     for st in setups:
         st["dec"].close()
+    del setups
+    if cpu:
+        log("mix: cpu baseline (oracle)")
+        dt, w = oracle_pool(cpu_jobs)
+        vi = sum(sp.n_z * sp.n_x for sp in specs)
+        out["cpu_baseline"] = {
+            "value": vi / dt, "unit": "voxel-iterations/s", "cores": w, "kind": "oracle",
+            "sample": "the middle plane of each of the 3 volumes, one per worker process, 1 of 10 iterations, "
+                      f"FP64 FFT convolution, {dt:.1f} s"}
+    return out
+
+
+def bench_mix(args):
+    """--config mix: the batched-vs-plain record as its own JSON line."""
+    rec = mix_record(args, cpu=not args.no_cpu_baseline)
+    out = {
+        "metric": "voxel-iterations/s", "value": rec["value"], "unit": "voxel-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": rec["workload"], "voxels": rec["voxels"], "parallelism": "single GPU"},
+    }
+    out.update({k: v for k, v in rec.items() if k not in ("value", "unit", "ms_per_step", "workload", "voxels")})
     print(json.dumps(out), flush=True)
+
+
+def bench_calibrate(args):
+    """A kernel of known traffic for calibrating the HBM byte counters: the
+    reslice of a float32 camera stack of 1 GiB into float32 planes (every
+    element read once and written once)."""
+    import torch
+
+    from paper_1503_07998_amd import api
+
+    Z, Y, X = 1024, 256, 1024    # 2^28 float32 values = 1 GiB
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(3)
+    stack = torch.rand((Z, Y, X), generator=g, device=dev)
+    planes = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
+    ctx = api.mvd_create(1, Z, X, 0)
+    try:
+        for _ in range(args.warmup):
+            api.mvd_reslice(ctx, stack, Y, planes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            api.mvd_reslice(ctx, stack, Y, planes)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    finally:
+        api.mvd_destroy(ctx)
+    nbytes = Z * Y * X * 4
+    print(json.dumps({"metric": "GB/s", "value": 2 * nbytes / (ms / 1e3) / 1e9, "unit": "GB/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "reslice of a 1 GiB float32 stack (1024 slices of 256x1024) into "
+                                             "planes: counter calibration, 1 GiB read + 1 GiB written per launch"},
+                      "bytes_read": nbytes, "bytes_written": nbytes}), flush=True)
 
 
 def bench_stream(args, spec):
@@ -299,8 +406,9 @@ def bench_stream(args, spec):
         t = torch.empty((Z, Y, X), dtype=torch.uint16, pin_memory=True)
         t.numpy()[...] = vol["stacks"][v]
         host.append(t)
-    y_cpu = Y // 2
-    cpu_sample = [np.ascontiguousarray(s[: Z // 2, y_cpu:y_cpu + 1, :]) for s in vol["stacks"]]
+    y_cpu = max(0, Y // 2 - host_cores() // 2)
+    cpu_jobs = [([np.ascontiguousarray(s[:, y:y + 1, :]) for s in vol["stacks"]], vol["psfs"], 1, spec.update,
+                 False) for y in range(y_cpu, min(Y, y_cpu + host_cores()))]
     del vol["stacks"]
     dev = torch.device("cuda:0")
     d = api.Deconvolver(V, Z, X, 0)
@@ -402,15 +510,11 @@ def bench_stream(args, spec):
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        t0 = time.perf_counter()
-        import oracle
-
-        oracle.deconvolve(cpu_sample, [p.astype(np.float64) for p in vol["psfs"]], 1, update=spec.update)
-        dt = time.perf_counter() - t0
+        dt, w = oracle_pool(cpu_jobs)
         out["cpu_baseline"] = {
-            "value": (Z // 2) * X / dt, "unit": "voxel-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"rows 0..{Z // 2 - 1} of plane {y_cpu}, 1 of {spec.iters} iterations, {V} views, "
-                      f"direct FP64 convolution, {dt:.1f} s"}
+            "value": len(cpu_jobs) * Z * X / dt, "unit": "voxel-iterations/s", "cores": w, "kind": "oracle",
+            "sample": f"{len(cpu_jobs)} of {Y} planes, one per worker process, 1 of {spec.iters} iterations, "
+                      f"{V} views, FP64 FFT convolution, {dt:.1f} s"}
     d.close()
     print(json.dumps(out), flush=True)
 
@@ -524,6 +628,8 @@ def main():
                     help="EM-normalised back-projection (divide by X (*) 1; default workload)")
     ap.add_argument("--pixel-weights", action="store_true",
                     help="per-pixel view weights (seeded uniform [0.5, 1] planes; default workload)")
+    ap.add_argument("--no-mix", action="store_true",
+                    help="leave out the batched-vs-plain mix record of the default run")
     args = ap.parse_args()
     global WEIGHT_PLANES
     WEIGHT_PLANES = args.pixel_weights
@@ -534,6 +640,9 @@ def main():
 
     if args.config == "mix":
         bench_mix(args)
+        return
+    if args.config == "calibrate":
+        bench_calibrate(args)
         return
 
     from synthetic import CONFIGS, make_volume
@@ -655,6 +764,11 @@ def main():
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(spec, vol, spec.iters, normalize=args.normalize)
     d.close()
+    del obs, est, ws, runs, wplanes
+    torch.cuda.empty_cache()
+    plain = not (args.force_2d or args.normalize or args.pixel_weights or args.update)
+    if spec.name == "vol512" and plain and not args.no_mix:
+        out["mix"] = mix_record(args, cpu=not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)
 
 

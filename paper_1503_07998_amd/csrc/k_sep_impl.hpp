@@ -188,10 +188,16 @@ __device__ __forceinline__ void load_row(const float *__restrict__ src, int rr, 
                                          const Cols<C, R> &cl, float *dst /* [C] stride M */,
                                          int stride) {
   const int Z = a->g.Z;
-  const bool zero_bc = a->boundary == 0;
-  const bool rv = !zero_bc || (rr >= 0 && rr < Z);
-  const int r2 = zero_bc ? rr : wrapi(rr, Z);
-  const float *row = rv ? src + (size_t)r2 * a->g.X : kZeroRow;
+  const float *row;
+  if (a->boundary == 0) {
+    // a plane holds at most 2^31 elements (checked when a context is made),
+    // so the row offset fits 32 unsigned bits
+    row = (unsigned)rr < (unsigned)Z ? src + (unsigned)rr * (unsigned)a->g.X : kZeroRow;
+  } else {
+    // a real branch: the modulo of the periodic rule is not evaluated for
+    // zero-boundary rows (a select would compute it for every row)
+    row = src + (size_t)wrapi(rr, Z) * a->g.X;
+  }
 #pragma unroll
   for (int c = 0; c < C; ++c) dst[c * stride] = row[cl.gx[c]];
 }

@@ -80,7 +80,8 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_cpu_baseline_is_bounded():
-    """The oracle leg times one plane; planes larger than 512×512 get fewer
+    """The oracle leg times one plane per worker process (as many workers as
+    the host gives, at most 16); planes larger than 512×512 get fewer
     iterations so that the leg stays a few seconds."""
     import numpy as np
 
@@ -92,6 +93,7 @@ def test_cpu_baseline_is_bounded():
            "psfs": [np.full((5, 5), 1 / 25, dtype=np.float32)] * 2}
     out = bench.cpu_baseline(spec, vol, spec.iters)
     assert out["kind"] == "oracle" and out["value"] > 0 and "all 3 iterations" in out["sample"]
+    assert out["cores"] == min(3, bench.host_cores())   # 3 planes: at most 3 workers
     wide = VolumeSpec("wide", 1, 1024, 1024, 3, (1.0, 2.0), (0, 90), 4, "u16", 10, "simultaneous", seed=9)
     vol = {"stacks": [rng.integers(90, 200, (1024, 1, 1024)).astype(np.uint16) for _ in range(2)],
            "psfs": [np.full((3, 3), 1 / 9, dtype=np.float32)] * 2}
