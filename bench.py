@@ -222,7 +222,8 @@ def cpu_baseline(spec, vol, iters, normalize=False):
 
 
 def mix_record(args, cpu=True):
-    """Three uneven volumes: plain per-volume calls vs one batched launch.
+    """Three uneven volumes: plain per-volume calls vs one batched launch (the
+    persistent work-queue kernel; the graph form is timed beside it).
     Returns a dict: batched and plain rates, their ratio, the largest relative
     difference between the two estimates, the roofline of the mix's dominant
     kernel (from HIP-event timings of the plain calls) and the CPU baseline."""
@@ -292,20 +293,30 @@ def mix_record(args, cpu=True):
         kinds = launch_kinds(st["spec"], tim, 1, st["spec"].voxels)
         per_vol.append((st["spec"], kinds))
 
-    log("mix: batch: autotune + capture")
     entries = [(st["dec"].ctx, st["obs"], st["est"], st["runs"][False]) for st in setups]
-    b = api.Batch(entries, tune=True)
-    for _ in range(args.warmup):
-        b.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b.launch()
-    torch.cuda.synchronize()
-    batch_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    diff = max(float(np.abs(st["est"].cpu().numpy() - ref).max() / np.abs(ref).max())
-               for st, ref in zip(setups, plain_out))
-    tuning = [b.tuning(i) for i in range(len(setups))]
+
+    def time_batch(b):
+        for _ in range(args.warmup):
+            b.launch()
+        b.wait()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.launch()
+        b.wait()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        d = max(float(np.abs(st["est"].cpu().numpy() - ref).max() / np.abs(ref).max())
+                for st, ref in zip(setups, plain_out))
+        return ms, d
+
+    log("mix: graph form (autotune + capture)")
+    bg = api.Batch(entries, tune=True, graph=True)
+    graph_ms, graph_diff = time_batch(bg)
+    tuning = [bg.tuning(i) for i in range(len(setups))]
+    bg.close()
+    log("mix: persistent form")
+    b = api.Batch(entries)
+    info = b.info()
+    batch_ms, diff = time_batch(b)
     b.close()
     # the dominant kernel of the mix: the (volume, pass) with the largest total launch time
     spec_d, kinds_d = max(per_vol, key=lambda sk: max(k["avg_ms"] * k["launches"] for k in sk[1].values()))
@@ -315,6 +326,9 @@ def mix_record(args, cpu=True):
         "value": vox_it / (batch_ms / 1e3), "unit": "voxel-iterations/s", "ms_per_step": batch_ms,
         "plain_value": vox_it / (plain_ms / 1e3), "plain_ms_per_step": plain_ms,
         "batched_over_plain": plain_ms / batch_ms, "max_rel_diff_batched_vs_plain": diff,
+        "batch_form": info,
+        "graph_form_value": vox_it / (graph_ms / 1e3), "graph_form_ms_per_step": graph_ms,
+        "graph_form_max_rel_diff": graph_diff,
         "workload": "batched mix: 200 planes 256x384 (2 views, 21x21), 300 planes 512x768 (3 views, 31x31), "
                     "150 planes 1000x1000 (4 views, 41x41), f32 Poisson observations, 10 sequential iterations, "
                     "zero boundary",

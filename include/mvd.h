@@ -319,10 +319,21 @@ mvd_status mvd_backward(mvd_ctx *ctx, const void *const *obs, const float *grad_
 /* ---- batched form --------------------------------------------------------
  * Several deconvolutions (volumes of different plane sizes, view counts and
  * PSF sizes, each with its own context, observations, estimate and run
- * parameters) captured into one HIP graph: every volume's whole iteration
- * loop is one branch of the graph, so a single launch runs all of them
- * concurrently.  Items are copied; their device buffers must stay valid and
- * unchanged in address while the batch exists. */
+ * parameters) in one launch.  Planes are independent (Results, second
+ * paragraph), so the batch is a queue of work items, one per (volume, phase,
+ * plane, tile): ψ^0, then every forward and backward pass of every iteration
+ * in the volume's update order, each pass cut into row-segment × column-strip
+ * tiles.  One persistent kernel takes items from an atomic queue head; an
+ * item waits until every tile of its plane's previous phase is complete
+ * (per-plane counters), and the table lists items in that dependency order,
+ * so a work-group only waits for items already taken by running ones.  The
+ * volumes advance together (their item lists are merged in proportion).
+ * Items that the persistent kernel does not take (K×K or > 41-tap passes,
+ * normalised or per-pixel-weighted updates, checkpoints, rows that are not
+ * whole 16-byte units) make the batch a HIP graph instead: every volume's
+ * whole iteration loop as one branch.  Results equal mvd_deconvolve_planes
+ * bitwise in both forms.  Items are copied; their device buffers must stay
+ * valid and unchanged in address while the batch exists. */
 typedef struct {
   mvd_ctx *ctx;
   const void *const *obs;   /* host array of the context's V device pointers */
@@ -332,10 +343,11 @@ typedef struct {
 
 typedef struct mvd_batch mvd_batch;
 
-#define MVD_BATCH_TUNE 0x1u /* time launch-shape candidates per item before capture (runs
-                               one iteration of each item on `stream`, synchronously; items
-                               with MVD_INIT_GIVEN keep the default shapes).  The choice is
+#define MVD_BATCH_TUNE 0x1u /* graph form: time launch-shape candidates per item before capture
+                               (runs one iteration of each item on `stream`, synchronously;
+                               items with MVD_INIT_GIVEN keep the default shapes).  The choice is
                                cached per workload shape for the process. */
+#define MVD_BATCH_GRAPH 0x2u /* use the graph form even where the persistent form applies */
 
 /* Validate every item, optionally autotune, and capture the batch graph.
  * All items must be on one device.  Errors: MVD_ERR_ARG (item index in
@@ -344,10 +356,21 @@ typedef struct mvd_batch mvd_batch;
 mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items, uint32_t flags,
                             void *stream);
 
-/* Launch the captured batch on `stream` (asynchronous).  The batch holds each
+/* Launch the batch on `stream` (asynchronous; one kernel launch in the
+ * persistent form).  Calls that overlap on one batch race (they share its
+ * queue).  The batch holds each
  * item's taps as they were at creation: after mvd_set_psf or mvd_destroy on an
  * item's context the batch must be recreated (MVD_ERR_STATE, nothing launched). */
 mvd_status mvd_batch_launch(mvd_batch *b, void *stream);
+
+/* Wait for the batch's work on `stream` and report its status: MVD_ERR_LAUNCH
+ * when a persistent launch's wait for a dependency gave up (the flag is then
+ * cleared) or the stream failed.  Errors: MVD_ERR_ARG, MVD_ERR_LAUNCH. */
+mvd_status mvd_batch_wait(mvd_batch *b, void *stream);
+
+/* Form of the batch: out[4] = persistent (1) or graph (0), work items,
+ * work-groups of the persistent launch, its LDS bytes per work-group. */
+mvd_status mvd_batch_info(const mvd_batch *b, int *out);
 
 /* Launch shapes chosen for item `item`: out[5] = forward occupancy, forward
  * views per launch, backward inputs per launch, segment scale, columns per

@@ -53,6 +53,27 @@ int mvd_internal_corr_plan(int n_planes, int Z, int X, int kz, int kx, long *out
  * running in other threads. */
 int mvd_internal_set_tune(const char *spec);
 
+/* Polls a persistent batch's work-group makes before it gives up waiting for
+ * a dependency (0: the default, about 2^24).  Lets a test make the wait give
+ * up at once, so the failure report is exercised with every kernel ending
+ * normally. */
+int mvd_internal_set_pq_spin(unsigned polls);
+
+/* Raise a persistent batch's give-up flag from the host, as a wait that gave
+ * up would: the next launch's work-groups skip every item and end, and
+ * mvd_batch_wait reports MVD_ERR_LAUNCH.  MVD_ERR_ARG for a graph batch. */
+int mvd_internal_batch_raise_giveup(mvd_batch *b);
+
+/* The persistent form's item order for jobs of n_planes[k] planes cut into
+ * nseg[k] row segments × nstrip[k] column strips (tile = (plane·nseg + seg)·
+ * nstrip + strip), two tiles per item where pair[k] ≠ 0, per_iter[k] phases
+ * per iteration over iters[k] iterations (plus the ψ^0 phase), windows of
+ * `window` planes (0: whole volumes): up to `cap` items (job, phase, tile,
+ * second tile or −1) into out[4·cap].  Returns the number of items (or a
+ * negative mvd_status). */
+long mvd_internal_pq_order(int n_jobs, const int *n_planes, const int *nseg, const int *nstrip, const int *pair,
+                           const int *per_iter, const int *iters, int window, int *out, long cap);
+
 /* Workspace bytes that the launch-shape tuner's probe (one iteration of the
  * run, made for MVD_FLAG_TUNE) would use, or 0 when the run makes no probe
  * (n_iters = 0).  Never more than mvd_workspace_bytes() of the same run. */

@@ -73,6 +73,7 @@ class MvdItem(ctypes.Structure):
 
 
 MVD_BATCH_TUNE = 0x1
+MVD_BATCH_GRAPH = 0x2
 
 
 class MvdError(RuntimeError):
@@ -100,6 +101,8 @@ SIGNATURES = {
                              POINTER(c_void_p), c_void_p, c_void_p, c_void_p]),
     "mvd_batch_create": (c_int, [POINTER(c_void_p), POINTER(MvdItem), c_int, c_uint32, c_void_p]),
     "mvd_batch_launch": (c_int, [c_void_p, c_void_p]),
+    "mvd_batch_wait": (c_int, [c_void_p, c_void_p]),
+    "mvd_batch_info": (c_int, [c_void_p, POINTER(c_int)]),
     "mvd_batch_tuning": (c_int, [c_void_p, c_int, POINTER(c_int)]),
     "mvd_batch_destroy": (None, [c_void_p]),
     "mvd_batch_run": (c_int, [POINTER(MvdItem), c_int, c_void_p]),

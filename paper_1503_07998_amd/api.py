@@ -20,6 +20,7 @@ __all__ = [
     "mvd_backward_workspace_bytes", "mvd_backward", "mvd_batch_create", "mvd_batch_launch",
     "mvd_batch_tuning", "mvd_batch_destroy", "mvd_batch_run", "Batch",
     "mvd_stream_workspace_bytes", "mvd_deconvolve_stream", "mvd_deconvolve_planes_static",
+    "mvd_batch_wait", "mvd_batch_info",
 ]
 
 
@@ -232,16 +233,26 @@ def _items(entries):
     return arr, keep
 
 
-def mvd_batch_create(entries, tune=False, stream=None):
+def mvd_batch_create(entries, tune=False, stream=None, graph=False):
     arr, keep = _items(entries)
     b = c_void_p()
-    N.check(N.lib().mvd_batch_create(ctypes.byref(b), arr, len(entries), N.MVD_BATCH_TUNE if tune else 0,
-                                     _stream_handle(stream)))
+    flags = (N.MVD_BATCH_TUNE if tune else 0) | (N.MVD_BATCH_GRAPH if graph else 0)
+    N.check(N.lib().mvd_batch_create(ctypes.byref(b), arr, len(entries), flags, _stream_handle(stream)))
     return b
 
 
 def mvd_batch_launch(b, stream=None) -> None:
     N.check(N.lib().mvd_batch_launch(b, _stream_handle(stream)))
+
+
+def mvd_batch_wait(b, stream=None) -> None:
+    N.check(N.lib().mvd_batch_wait(b, _stream_handle(stream)))
+
+
+def mvd_batch_info(b):
+    out = (c_int * 4)()
+    N.check(N.lib().mvd_batch_info(b, out))
+    return dict(persistent=bool(out[0]), items=out[1], work_groups=out[2], lds_bytes=out[3])
 
 
 def mvd_batch_tuning(b, item: int):
@@ -260,14 +271,21 @@ def mvd_batch_run(entries, stream=None) -> None:
 
 
 class Batch:
-    """Several deconvolutions in one HIP graph (one branch per volume)."""
+    """Several deconvolutions in one launch: the persistent work-queue kernel,
+    or a HIP graph with one branch per volume where items need it."""
 
-    def __init__(self, entries, tune=False, stream=None):
+    def __init__(self, entries, tune=False, stream=None, graph=False):
         self.entries = entries          # keeps tensors and runs alive
-        self.handle = mvd_batch_create(entries, tune, stream)
+        self.handle = mvd_batch_create(entries, tune, stream, graph)
 
     def launch(self, stream=None):
         mvd_batch_launch(self.handle, stream)
+
+    def wait(self, stream=None):
+        mvd_batch_wait(self.handle, stream)
+
+    def info(self):
+        return mvd_batch_info(self.handle)
 
     def tuning(self, item):
         return mvd_batch_tuning(self.handle, item)

@@ -115,9 +115,9 @@ struct Geo {
   size_t plane_off;
 };
 
-__device__ __forceinline__ Geo tile_geo(KArg *a) {
+// Geometry of tile b of a pass: (plane, segment, strip), strip fastest.
+__device__ __forceinline__ Geo tile_geo(KArg *a, int b) {
   Geo o;
-  int b = logical_block();
   const int strip = b % a->nstrip;
   b /= a->nstrip;
   const int seg = b % a->nseg;
@@ -131,6 +131,9 @@ __device__ __forceinline__ Geo tile_geo(KArg *a) {
   o.plane_off = (size_t)y * a->g.Z * a->g.X;
   return o;
 }
+
+// Barriers a tile executes: one after its set-up, one per row group.
+__device__ __forceinline__ int tile_barriers(KArg *a, int b) { return 1 + tile_geo(a, b).ngroups; }
 
 // Column bookkeeping of the z pass for one thread.
 template <int C, int R>
@@ -612,19 +615,15 @@ __device__ __forceinline__ void fwd_phases(KArg *a, const Geo &o, const Cols<C, 
   (fwd_group<KB, C, NV, EP, VM, us>(a, o, cl, src, lds, st, ring, i0), ...);
 }
 
-// OCC: minimum waves per SIMD the register budget must allow (second
-// launch-bounds argument): 4 caps a thread at 128 VGPRs, 2 at 256.
-// Work-groups of up to 2·kSepMaxThreads threads in the 4-waves/SIMD form (rows
-// up to 1024 columns, one column per thread), kSepMaxThreads otherwise.
-template <int KB, int C, int NV, int OCC, int EP, int VM>
-__global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads, OCC)
-    sep_forward_kernel(const SepPassArgs) {
-  KArg *a = kargs();
+// One tile of a single-input pass (the forward pass and the adjoint's
+// single-view passes) by threads t = 0 … nt−1 (whole waves) with LDS at `lds`.
+// Every wave of the work-group must execute the same barriers: 1 + the tile's
+// row groups (tile_barriers).
+template <int KB, int C, int NV, int EP, int VM>
+__device__ __forceinline__ void fwd_tile(KArg *a, int b, int t, int nt, float *lds) {
   using S = Shape<KB>;
   constexpr int R = S::R, M = S::M, U = S::U;
-  extern __shared__ __align__(16) float lds[];
-  const int nt = blockDim.x, t = threadIdx.x;
-  const Geo o = tile_geo(a);
+  const Geo o = tile_geo(a, b);
   const Cols<C, R> cl(a, o, t, nt);
   if (a->halo == 0) zero_pads<R>(lds, 2 * NV * G, a, t, nt);
   const int nxb = (o.xout + NX - 1) / NX;
@@ -638,6 +637,17 @@ __global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads
   for (int m = 0; m < G + KB - 1; ++m) load_row<C, R>(src, st.rbase + m, a, cl, &ring[0][m], M);
   for (int i0 = 0; i0 < o.ngroups; i0 += U)
     fwd_phases<KB, C, NV, EP, VM>(a, o, cl, src, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
+}
+
+// OCC: minimum waves per SIMD the register budget must allow (second
+// launch-bounds argument): 4 caps a thread at 128 VGPRs, 2 at 256.
+// Work-groups of up to 2·kSepMaxThreads threads in the 4-waves/SIMD form (rows
+// up to 1024 columns, one column per thread), kSepMaxThreads otherwise.
+template <int KB, int C, int NV, int OCC, int EP, int VM>
+__global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads, OCC)
+    sep_forward_kernel(const SepPassArgs) {
+  extern __shared__ __align__(16) float lds[];
+  fwd_tile<KB, C, NV, EP, VM>(kargs(), logical_block(), threadIdx.x, blockDim.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -724,15 +734,13 @@ __device__ __forceinline__ void bwd_phases(KArg *a, const Geo &o, const Cols<C, 
   (bwd_group<KB, C, VIN, VM, EB, us>(a, o, cl, lds, st, ring, i0), ...);
 }
 
-template <int KB, int C, int VIN, int OCC, int VM, int EB>
-__global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads, OCC)
-    sep_backward_kernel(const SepPassArgs) {
-  KArg *a = kargs();
+// One tile of the backward pass by threads t = 0 … nt−1 with LDS at `lds`
+// (barriers as fwd_tile).
+template <int KB, int C, int VIN, int VM, int EB>
+__device__ __forceinline__ void bwd_tile(KArg *a, int b, int t, int nt, float *lds) {
   using S = Shape<KB>;
   constexpr int R = S::R, M = S::M, U = S::U;
-  extern __shared__ __align__(16) float lds[];
-  const int nt = blockDim.x, t = threadIdx.x;
-  const Geo o = tile_geo(a);
+  const Geo o = tile_geo(a, b);
   const Cols<C, R> cl(a, o, t, nt);
   if (a->halo == 0) zero_pads<R>(lds, 2 * VIN * G, a, t, nt);
   const int nxb = (o.xout + NX - 1) / NX;
@@ -749,6 +757,13 @@ __global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads
   }
   for (int i0 = 0; i0 < o.ngroups; i0 += U)
     bwd_phases<KB, C, VIN, VM, EB>(a, o, cl, lds, st, ring, i0, std::make_integer_sequence<int, U>{});
+}
+
+template <int KB, int C, int VIN, int OCC, int VM, int EB>
+__global__ void __launch_bounds__(OCC >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads, OCC)
+    sep_backward_kernel(const SepPassArgs) {
+  extern __shared__ __align__(16) float lds[];
+  bwd_tile<KB, C, VIN, VM, EB>(kargs(), logical_block(), threadIdx.x, blockDim.x, lds);
 }
 
 // Double-buffered column-pass rows and the tap tables of both passes.
@@ -925,7 +940,7 @@ __global__ void __launch_bounds__(2 * kSepMaxThreads, 4) sep_backward_split_kern
   extern __shared__ __align__(16) float lds[];
   const int nt = blockDim.x, t = threadIdx.x, half = nt / 2;
   const int view = t / half, tc = t - view * half;   // wave-uniform view
-  const Geo o = tile_geo(a);
+  const Geo o = tile_geo(a, logical_block());
   const Cols<1, R> cl(a, o, tc, half);
   zero_pads<R>(lds, 2 * 2 * G, a, t, nt);
   const int nxb = (o.xout + NX - 1) / NX;

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -460,6 +461,8 @@ struct Tune {
                         // the threads per view, 16-row groups): 0 where it applies, 2 never
   int valu_corr = 0;    // 1: tap-gradient correlation on the vector ALUs instead of the matrix cores
   int plane_batch = 0;  // > 0: run this many planes through all iterations at a time
+  int pq_window = 0;    // persistent batches: planes per window of a volume's items (0: all)
+  int pq_zseg_scale = 0;  // persistent batches: segment length × 2^(v − 2) of the planner's (0: × 2)
   int wide = 0;         // rows of 513–1024 columns as one column per thread in up to
                         // 1024-thread work-groups (one-ring passes): 0 where it applies, 2 never
 };
@@ -491,6 +494,8 @@ Tune parse_tune(const char *e) {
       if (k == "bwd_split") r.bwd_split = v;
       if (k == "plane_batch") r.plane_batch = v;
       if (k == "wide") r.wide = v;
+      if (k == "pq_window") r.pq_window = v;
+      if (k == "pq_zseg_scale") r.pq_zseg_scale = v;
     }
     pos = comma + 1;
   }
@@ -1429,6 +1434,194 @@ hipError_t autotune(mvd_ctx *c, const void *const *obs, float *est, const mvd_ru
 
 }  // namespace
 
+// ---- persistent batched form ----------------------------------------------
+// Whether a run can go through the persistent queue kernel: rank-one passes
+// of at most 41 taps, the plain update (no normalisation, no per-pixel
+// weights), no checkpoints, and whole 16-byte row items.
+bool pq_eligible(const mvd_ctx *c, const void *const *obs, const float *est, const mvd_run *r, std::string *why) {
+  auto no = [&](const char *m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (r->flags & (MVD_FLAG_FORCE_2D | MVD_FLAG_NORMALIZE)) return no("K×K or normalised passes");
+  if (r->weight_planes) return no("per-pixel weights");
+  if (r->checkpoints) return no("checkpoints");
+  int kmax = 1;
+  for (int v = 0; v < c->nv; ++v) {
+    const ViewPsf &w = c->views[v];
+    if (!w.sep_p || !w.sep_x) return no("a PSF or back-projector that is not rank one");
+    kmax = std::max({kmax, w.psf.kz, w.psf.kx, w.back.kz, w.back.kx});
+  }
+  if (sep_bucket(kmax) > 41) return no("more than 41 taps");
+  if (c->X % 8) return no("rows not a multiple of 8 columns");
+  const ObsRef ob = obs_given(obs, r->obs_dtype, r->obs_layout, PlaneGeom{r->n_planes, c->Z, c->X}, nullptr);
+  const long unit = ob.u16 ? 8 : 4;
+  if (ob.sy % unit || ob.sz % unit) return no("observation rows not in whole 16-byte units");
+  for (int v = 0; v < c->nv; ++v)
+    if (!aligned16(obs[v])) return no("observations not 16-byte aligned");
+  if (!aligned16(est)) return no("estimate not 16-byte aligned");
+  return true;
+}
+
+// The launch shapes of the persistent form: one column per thread, at most
+// kSepMaxThreads columns per tile (wider rows in strips with halos).
+Tune pq_tune() {
+  Tune t;
+  t.threads = kSepMaxThreads;
+  t.cols = 1;
+  return t;
+}
+
+// The job of one volume: its tiling and the arguments of every pass.
+bool pq_job(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, unsigned *done, PqJob *out) {
+  const PlaneGeom g{r->n_planes, c->Z, c->X};
+  int kmax = 1;
+  for (int v = 0; v < c->nv; ++v)
+    kmax = std::max({kmax, c->views[v].psf.kz, c->views[v].psf.kx, c->views[v].back.kz, c->views[v].back.kx});
+  // rows of 513–1024 columns: one whole-row tile per work-group (every thread
+  // a column); otherwise tiles of at most kSepMaxThreads columns, two per item
+  // segments twice the planner's length: fewer items, each with a fixed cost
+  // (dequeue, dependency check, ring fill); measured on the three-volume mix:
+  // 64.9 ms per step against 70.1 ms with the planner's segments
+  Tune tw{}, tp = pq_tune();
+  tw.zseg_scale = tp.zseg_scale = tune().pq_zseg_scale > 0 ? tune().pq_zseg_scale : 3;
+  const SepGeom wide = plan_sep(c, g.Y, sep_bucket(kmax), r->boundary, tw, true);
+  const bool one = wide.plan.threads > kSepMaxThreads && wide.plan.threads <= kPqThreads && wide.halo == 0 &&
+                   wide.plan.cols == 1;
+  const SepGeom sg = one ? wide : plan_sep(c, g.Y, sep_bucket(kmax), r->boundary, tp);
+  if (sg.plan.cols != 1 || !whole_items(sg, g)) return false;
+  if (!one && sg.plan.threads > kPqThreads / 2) return false;
+  PqJob j{};
+  j.g = g;
+  j.kb = sg.plan.bucket;
+  j.pair = one ? 0 : 1;
+  j.nseg = sg.nseg;
+  j.nstrip = sg.nstrip;
+  j.zseg = sg.zseg;
+  j.x_out = sg.x_out;
+  j.ntiles = sg.nseg * sg.nstrip;
+  j.sim = r->update == MVD_UPDATE_SIMULTANEOUS;
+  const int V = c->nv;
+  j.nf = j.sim ? (V + 1) / 2 : V;
+  j.per_iter = j.sim ? j.nf + V : 2 * V;
+  j.init = r->init == MVD_INIT_MEAN ? 0 : (r->init == MVD_INIT_GIVEN ? 1 : 2);
+  j.init_const = r->init_const;
+  j.nv = V;
+  const ObsRef ob = obs_given(obs, r->obs_dtype, r->obs_layout, g, nullptr);
+  j.obs_u16 = ob.u16 ? 1 : 0;
+  j.obs_sy = ob.sy;
+  j.obs_sz = ob.sz;
+  for (int v = 0; v < V; ++v) j.obs[v] = obs[v];
+  j.est = est;
+  j.done = done;
+  const Layout L = layout_of(c, r);
+  char *ws = static_cast<char *>(r->workspace);
+  auto ratio = [&](int v) { return reinterpret_cast<float *>(ws + L.r_off + (size_t)(j.sim ? v : 0) * L.plane_set); };
+  for (int s = 0; s < j.nf; ++s) {
+    SepPassArgs &a = j.f[s];
+    fill_sep_common(a, sg, g, r->boundary);
+    const int v0 = j.sim ? 2 * s : s;
+    a.nviews = j.sim ? std::min(2, V - v0) : 1;
+    a.in[0] = est;
+    a.obs_u16 = j.obs_u16;
+    a.obs_sy = ob.sy;
+    a.obs_sz = ob.sz;
+    for (int k = 0; k < a.nviews; ++k) {
+      const ViewPsf &w = c->views[v0 + k];
+      a.obs[k] = obs[v0 + k];
+      a.out[k] = ratio(v0 + k);
+      put_factor(a.tz[k], w.pz, j.kb);
+      put_factor(a.tx[k], w.px, j.kb);
+      if (!aligned16(a.out[k])) return false;
+    }
+    a.vec = 1;
+    j.fkind[s] = (ob.u16 ? 2 : 0) + (a.nviews == 2 ? 1 : 0);
+  }
+  for (int v = 0; v < V; ++v) {
+    SepPassArgs &a = j.b[v];
+    fill_sep_common(a, sg, g, r->boundary);
+    a.nviews = 1;
+    a.in[0] = ratio(v);
+    a.w[0] = r->view_weights ? r->view_weights[v] : 1.f;
+    put_factor(a.tz[0], c->views[v].xz, j.kb);
+    put_factor(a.tx[0], c->views[v].xx, j.kb);
+    a.psi_in = est;
+    a.psi_out = est;
+    a.vec = 1;
+  }
+  j.lds_floats = (int)(pq_lds_bytes(j) / sizeof(float));
+  *out = j;
+  return true;
+}
+
+// Items of all jobs in dependency order.  Each job's tiles go window by
+// window (`win` planes), a window's tiles by (phase, plane, tile); a job with
+// paired tiles takes them two at a time (consecutive tiles of one phase and
+// row segment: the same barriers).  Then the jobs' lists are merged so that
+// every job advances in proportion to its length (all finish together).  A
+// phase of a plane needs only the plane's earlier phases, and each job's own
+// order is kept, so those come earlier.
+std::vector<int4> pq_items(const std::vector<PqJob> &jobs, const std::vector<int> &win,
+                           const std::vector<int> &iters) {
+  std::vector<std::vector<int4>> per(jobs.size());
+  for (size_t k = 0; k < jobs.size(); ++k) {
+    const PqJob &j = jobs[k];
+    const int nphase = 1 + iters[k] * j.per_iter;
+    for (int y0 = 0; y0 < j.g.Y; y0 += win[k]) {
+      const int y1 = std::min(j.g.Y, y0 + win[k]);
+      for (int p = 0; p < nphase; ++p) {
+        if (!j.pair) {
+          for (int b = y0 * j.ntiles; b < y1 * j.ntiles; ++b) per[k].push_back(make_int4((int)k, p, b, -1));
+          continue;
+        }
+        // pair tiles of the same row segment: within a segment, consecutive (plane, strip)
+        for (int seg = 0; seg < j.nseg; ++seg) {
+          int pend = -1;
+          for (int y = y0; y < y1; ++y)
+            for (int st = 0; st < j.nstrip; ++st) {
+              const int b = (y * j.nseg + seg) * j.nstrip + st;
+              if (pend < 0) {
+                pend = b;
+              } else {
+                per[k].push_back(make_int4((int)k, p, pend, b));
+                pend = -1;
+              }
+            }
+          if (pend >= 0) per[k].push_back(make_int4((int)k, p, pend, -1));
+        }
+      }
+    }
+  }
+  std::vector<int4> out;
+  std::vector<size_t> pos(jobs.size(), 0);
+  for (;;) {   // next: the job whose next item sits earliest in its own list, relatively
+    int best = -1;
+    double key = 2.0;
+    for (size_t k = 0; k < per.size(); ++k) {
+      if (pos[k] >= per[k].size()) continue;
+      const double f = (pos[k] + 0.5) / per[k].size();
+      if (f < key) {
+        key = f;
+        best = (int)k;
+      }
+    }
+    if (best < 0) break;
+    out.push_back(per[best][pos[best]++]);
+  }
+  return out;
+}
+
+// Polls before a wait gives up (test hook; 0 = the default).
+std::atomic<unsigned> g_pq_spin{0};
+constexpr unsigned kPqSpinDefault = 1u << 24;
+
+struct PqState {
+  void *dmem = nullptr;         // jobs, items, counters
+  PqQueue q{};
+  int nblocks = 0;
+  size_t lds = 0;
+};
+
 struct mvd_batch {
   int device = -1;
   struct Item {
@@ -1444,7 +1637,70 @@ struct mvd_batch {
   std::vector<Item> items;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool persistent = false;   // one persistent queue launch instead of the graph
+  PqState pq;
+  std::string why_graph;      // why the graph form was taken
 };
+
+namespace {
+
+// Build the persistent form of a batch: job table, item table and counters in
+// one device allocation made here (at creation; launches allocate nothing).
+hipError_t pq_setup(mvd_batch *b, int window) {
+  std::vector<PqJob> jobs(b->items.size());
+  std::vector<int> win(b->items.size());
+  std::vector<size_t> done_off(b->items.size());
+  std::vector<int> iters(b->items.size());
+  size_t ndone = 0;
+  for (size_t k = 0; k < b->items.size(); ++k) {
+    const auto &it = b->items[k];
+    iters[k] = it.run.n_iters;
+    done_off[k] = ndone;
+    ndone += (size_t)it.run.n_planes;
+  }
+  // jobs, then items, then counters (per plane, then head / exited / give-up)
+  const size_t jobs_bytes = align_up(jobs.size() * sizeof(PqJob));
+  for (size_t k = 0; k < b->items.size(); ++k) {
+    auto &it = b->items[k];
+    if (!pq_job(it.ctx, it.obs.data(), it.est, &it.run, nullptr, &jobs[k])) return hipErrorInvalidValue;
+    // planes per window (0: the whole volume, iteration-major as the plain path)
+    win[k] = window > 0 ? std::min(window, jobs[k].g.Y) : jobs[k].g.Y;
+  }
+  const std::vector<int4> items = pq_items(jobs, win, iters);
+  const size_t items_bytes = align_up(items.size() * sizeof(int4));
+  const size_t done_bytes = align_up((ndone + 3) * sizeof(unsigned));
+  hipError_t e = hipMalloc(&b->pq.dmem, jobs_bytes + items_bytes + done_bytes);
+  if (e != hipSuccess) return e;
+  char *base = static_cast<char *>(b->pq.dmem);
+  unsigned *done = reinterpret_cast<unsigned *>(base + jobs_bytes + items_bytes);
+  for (size_t k = 0; k < jobs.size(); ++k) jobs[k].done = done + done_off[k];
+  e = hipMemcpy(base, jobs.data(), jobs.size() * sizeof(PqJob), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(base + jobs_bytes, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(done, 0, (ndone + 3) * sizeof(unsigned));
+  if (e != hipSuccess) return e;
+  PqQueue &q = b->pq.q;
+  q.items = reinterpret_cast<const int4 *>(base + jobs_bytes);
+  q.n_items = (int)items.size();
+  q.n_jobs = (int)jobs.size();
+  q.jobs = reinterpret_cast<const PqJob *>(base);
+  q.head = done + ndone;
+  q.exited = done + ndone + 1;
+  q.giveup = done + ndone + 2;
+  size_t lds = 0;
+  for (const PqJob &j : jobs) lds = std::max(lds, (j.pair ? 2 : 1) * (size_t)j.lds_floats * sizeof(float));
+  if (lds > kLdsLimit) return hipErrorInvalidValue;
+  b->pq.lds = lds;
+  int per_cu = 0, cus = 0;
+  e = pq_occupancy(lds, &per_cu);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  b->pq.nblocks = per_cu * cus;
+  return hipSuccess;
+}
+
+}  // namespace
 
 // ===========================================================================
 extern "C" {
@@ -1793,6 +2049,43 @@ int mvd_internal_mfma_plan(int kz, int kx, int *out) {
 
 int mvd_internal_version(void) { return MVD_TESTING_VERSION; }
 
+int mvd_internal_set_pq_spin(unsigned polls) {
+  g_pq_spin.store(polls);
+  return MVD_OK;
+}
+
+int mvd_internal_batch_raise_giveup(mvd_batch *b) {
+  if (!b || !b->persistent) return MVD_ERR_ARG;
+  DeviceGuard dg(b->device);
+  return hipMemset(b->pq.q.giveup, 1, sizeof(unsigned)) == hipSuccess ? MVD_OK : MVD_ERR_LAUNCH;
+}
+
+long mvd_internal_pq_order(int n_jobs, const int *n_planes, const int *nseg, const int *nstrip, const int *pair,
+                           const int *per_iter, const int *iters, int window, int *out, long cap) {
+  if (n_jobs < 1 || !n_planes || !nseg || !nstrip || !pair || !per_iter || !iters) return MVD_ERR_ARG;
+  std::vector<PqJob> jobs(n_jobs);
+  std::vector<int> win(n_jobs), it(iters, iters + n_jobs);
+  for (int k = 0; k < n_jobs; ++k) {
+    if (n_planes[k] < 1 || nseg[k] < 1 || nstrip[k] < 1 || per_iter[k] < 1 || iters[k] < 0) return MVD_ERR_ARG;
+    jobs[k].g = PlaneGeom{n_planes[k], 1, 1};
+    jobs[k].nseg = nseg[k];
+    jobs[k].nstrip = nstrip[k];
+    jobs[k].ntiles = nseg[k] * nstrip[k];
+    jobs[k].pair = pair[k] ? 1 : 0;
+    jobs[k].per_iter = per_iter[k];
+    win[k] = window > 0 ? std::min(window, n_planes[k]) : n_planes[k];
+  }
+  const std::vector<int4> items = pq_items(jobs, win, it);
+  if (out)
+    for (long i = 0; i < (long)items.size() && i < cap; ++i) {
+      out[4 * i] = items[i].x;
+      out[4 * i + 1] = items[i].y;
+      out[4 * i + 2] = items[i].z;
+      out[4 * i + 3] = items[i].w;
+    }
+  return (long)items.size();
+}
+
 int mvd_internal_tune_probe_bytes(const mvd_ctx *c, const mvd_run *r, size_t *bytes) {
   if (!c || !r || !bytes || r->struct_size != sizeof(mvd_run) || r->n_planes < 1 || r->n_iters < 0)
     return MVD_ERR_ARG;
@@ -1982,7 +2275,7 @@ mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items,
   if (!out) return fail(nullptr, MVD_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!items || n_items < 1 || n_items > 64) return fail(nullptr, MVD_ERR_ARG, "need 1..64 items");
-  if (flags & ~MVD_BATCH_TUNE) return fail(nullptr, MVD_ERR_ARG, "unknown batch flags 0x%x", flags);
+  if (flags & ~(MVD_BATCH_TUNE | MVD_BATCH_GRAPH)) return fail(nullptr, MVD_ERR_ARG, "unknown batch flags 0x%x", flags);
   const int dev = items[0].ctx ? items[0].ctx->device : -1;
   for (int i = 0; i < n_items; ++i) {
     mvd_ctx *c = items[i].ctx;
@@ -2019,6 +2312,30 @@ mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items,
   }
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
+  // the persistent queue form where every item allows it, else the graph form
+  bool pq = !(flags & MVD_BATCH_GRAPH);
+  for (size_t i = 0; i < b->items.size() && pq; ++i) {
+    const auto &it = b->items[i];
+    std::string why;
+    if (!pq_eligible(it.ctx, it.obs.data(), it.est, &it.run, &why)) {
+      pq = false;
+      b->why_graph = "item " + std::to_string(i) + ": " + why;
+    }
+  }
+  if (pq) {
+    e = pq_setup(b, tune().pq_window);
+    if (e == hipSuccess) {
+      b->persistent = true;
+      *out = b;
+      return MVD_OK;
+    }
+    // a batch the persistent form cannot take runs as a graph
+    b->why_graph = std::string("persistent setup: ") + hipGetErrorString(e);
+    if (b->pq.dmem) (void)hipFree(b->pq.dmem);
+    b->pq = PqState{};
+    (void)hipGetLastError();
+    e = hipSuccess;
+  }
   if (flags & MVD_BATCH_TUNE) {
     for (auto &it : b->items) {
       if (e != hipSuccess) break;
@@ -2064,7 +2381,7 @@ mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items,
 }
 
 mvd_status mvd_batch_launch(mvd_batch *b, void *stream) {
-  if (!b || !b->exec) return fail(nullptr, MVD_ERR_ARG, "batch is NULL");
+  if (!b || (!b->exec && !b->persistent)) return fail(nullptr, MVD_ERR_ARG, "batch is NULL");
   {
     // the captured launches hold the items' taps and tap buffers: a context
     // destroyed or given new PSFs since capture invalidates the batch
@@ -2079,8 +2396,40 @@ mvd_status mvd_batch_launch(mvd_batch *b, void *stream) {
     }
   }
   DeviceGuard dg(b->device);
+  if (b->persistent) {
+    PqQueue q = b->pq.q;
+    const unsigned lim = g_pq_spin.load();
+    q.spin_limit = lim ? lim : kPqSpinDefault;
+    hipError_t e = launch_pq(q, b->pq.nblocks, b->pq.lds, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, MVD_ERR_LAUNCH, "persistent launch failed: %s", hipGetErrorString(e));
+    return MVD_OK;
+  }
   hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
   if (e != hipSuccess) return fail(nullptr, MVD_ERR_LAUNCH, "graph launch failed: %s", hipGetErrorString(e));
+  return MVD_OK;
+}
+
+mvd_status mvd_batch_wait(mvd_batch *b, void *stream) {
+  if (!b) return fail(nullptr, MVD_ERR_ARG, "batch is NULL");
+  DeviceGuard dg(b->device);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return fail(nullptr, MVD_ERR_LAUNCH, "batch execution failed: %s", hipGetErrorString(e));
+  if (b->persistent) {
+    unsigned flag = 0;
+    e = hipMemcpy(&flag, b->pq.q.giveup, sizeof(flag), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && flag) e = hipMemset(b->pq.q.giveup, 0, sizeof(unsigned));
+    if (e != hipSuccess) return fail(nullptr, MVD_ERR_LAUNCH, "batch status read failed: %s", hipGetErrorString(e));
+    if (flag) return fail(nullptr, MVD_ERR_LAUNCH, "persistent batch: a work-group gave up waiting for a dependency");
+  }
+  return MVD_OK;
+}
+
+mvd_status mvd_batch_info(const mvd_batch *b, int *out) {
+  if (!b || !out) return fail(nullptr, MVD_ERR_ARG, "batch or out is NULL");
+  out[0] = b->persistent ? 1 : 0;
+  out[1] = b->persistent ? b->pq.q.n_items : 0;
+  out[2] = b->persistent ? b->pq.nblocks : 0;
+  out[3] = b->persistent ? (int)b->pq.lds : 0;
   return MVD_OK;
 }
 
@@ -2100,6 +2449,7 @@ void mvd_batch_destroy(mvd_batch *b) {
   DeviceGuard dg(b->device);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->pq.dmem) (void)hipFree(b->pq.dmem);
   delete b;
 }
 
@@ -2108,9 +2458,8 @@ mvd_status mvd_batch_run(const mvd_item *items, int n_items, void *stream) {
   mvd_status st = mvd_batch_create(&b, items, n_items, 0, stream);
   if (st != MVD_OK) return st;
   st = mvd_batch_launch(b, stream);
-  DeviceGuard dg(b->device);
-  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && st == MVD_OK)
-    st = fail(nullptr, MVD_ERR_LAUNCH, "batch execution failed");
+  const mvd_status w = mvd_batch_wait(b, stream);
+  if (st == MVD_OK) st = w;
   mvd_batch_destroy(b);
   return st;
 }

@@ -199,4 +199,45 @@ hipError_t launch_copy(const float *src, float *dst, size_t n, hipStream_t s);
 constexpr int kRowGroup = 8;          // output rows produced per ring step
 constexpr int kSepMaxThreads = 512;
 
+// ---- persistent batched form (k_pq.hip) ------------------------------------
+// One volume of a persistent batch.  Every pass of the volume uses one tiling
+// of its planes (row segments × column strips, one column per thread): tile b
+// of a pass is (plane, segment, strip) as in SepPassArgs.  Phase 0 is ψ^0; then per iteration `per_iter` phases: for the
+// simultaneous update the nf forward passes (views in pairs) and then one
+// backward pass per view, for the sequential update F_0, B_0, F_1, B_1, ….
+constexpr int kPqThreads = 1024;   // persistent work-groups: one wide tile or two tiles of ≤ 512 threads
+
+struct PqJob {
+  PlaneGeom g;
+  int kb;                      // kernel-size bucket of every pass
+  int pair;                    // 1: tiles of ≤ kPqThreads/2 threads, two per item; 0: one tile per item
+  int lds_floats;              // LDS of one tile (floats; the second tile of a pair starts there)
+  int nseg, nstrip, zseg, x_out, ntiles;   // tiling (ntiles = nseg · nstrip per plane)
+  int sim, nf, per_iter;
+  int fkind[kMaxViews];        // forward pass variant: 0/1 float32 obs with 1/2 views, 2/3 uint16
+  // ψ^0
+  int init;                    // 0 mean of the views, 1 given (nothing to do), 2 constant
+  float init_const;
+  int nv, obs_u16;
+  long obs_sy, obs_sz;
+  const void *obs[kMaxViews];
+  float *est;
+  unsigned *done;              // [Y] tiles completed per plane (zero between launches)
+  SepPassArgs f[kMaxViews];    // forward passes of an iteration
+  SepPassArgs b[kMaxViews];    // backward passes (one ratio plane each)
+};
+
+struct PqQueue {
+  const int4 *items;           // (job, phase, tile, second tile or −1) in dependency order; tile = plane·ntiles + t
+  int n_items, n_jobs;
+  const PqJob *jobs;
+  unsigned *head, *exited;     // queue head; work-groups that have left (zero between launches)
+  unsigned *giveup;            // raised when a wait exceeds spin_limit polls
+  unsigned spin_limit;
+};
+
+size_t pq_lds_bytes(const PqJob &j);
+hipError_t launch_pq(const PqQueue &q, int nblocks, size_t lds, hipStream_t s);
+hipError_t pq_occupancy(size_t lds, int *blocks_per_cu);
+
 }  // namespace mvd

@@ -27,6 +27,7 @@ import numpy as np
 
 __all__ = [
     "gaussian_psf",
+    "nucleus",
     "Blobs",
     "draw_blobs",
     "render",
@@ -279,6 +280,29 @@ def make_volume(spec: VolumeSpec, seed: int | None = None, noise: bool = True,
         stacks.append(_render_volume(shape, blobs, spec.background, sig, noise, spec.obs_dtype,
                                      (seed, v + 1), workers))
     return dict(truth=tr, stacks=stacks, psfs=spec.psfs(), blobs=blobs)
+
+
+def nucleus(shape_yzx, seed: int, radii=(12.0, 14.0, 16.0), n_spots: int = 120, background: float = 10.0,
+            amplitude: float = 300.0) -> np.ndarray:
+    """One simulated nucleus in planes order ``[Y][Z][X]`` (float64): a
+    soft-edged ellipsoid (semi-axes ``radii`` along y, z, x, centred) whose
+    interior carries chromatin-like texture, a sum of ``n_spots`` Gaussian
+    spots (σ ~ U[1, 2] px, weight ~ U[0.5, 1]) at uniform positions inside
+    80% of the semi-axes; intensity background + amplitude · body ·
+    (0.4 + texture / max texture)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 7]))
+    ny, nz, nx = shape_yzx
+    c = np.array([ny / 2, nz / 2, nx / 2])
+    rad = np.asarray(radii, dtype=np.float64)
+    yy, zz, xx = np.meshgrid(np.arange(ny), np.arange(nz), np.arange(nx), indexing="ij")
+    d = np.sqrt(((yy - c[0]) / rad[0]) ** 2 + ((zz - c[1]) / rad[1]) ** 2 + ((xx - c[2]) / rad[2]) ** 2)
+    body = 1.0 / (1.0 + np.exp((d - 1.0) * 12.0))
+    tex = np.zeros(shape_yzx)
+    for _ in range(n_spots):
+        p = c + (rng.random(3) * 2 - 1) * rad * 0.8
+        sd = rng.uniform(1.0, 2.0)
+        tex += rng.uniform(0.5, 1.0) * np.exp(-((yy - p[0]) ** 2 + (zz - p[1]) ** 2 + (xx - p[2]) ** 2) / (2 * sd * sd))
+    return background + amplitude * body * (0.4 + tex / tex.max())
 
 
 def render_planes(spec: VolumeSpec, planes, seed: int | None = None, noise: bool = True):

@@ -146,3 +146,192 @@ def test_tuned_run_matches_plain():
         err = np.abs(est.cpu().numpy() - plain).max() / np.abs(plain).max()
         assert err <= 1e-6, f"tuned graph vs plain: {err:.3e}"
     d.close()
+
+
+def _planes_case(nz, nx, ny, views, k, iters, update, seed, *, dtype="f32", layout="stack_zyx", boundary="zero",
+                 init="mean", weights=None, periodic_ok=True):
+    """A seeded volume with its own context, workspace and run (not from CONFIGS)."""
+    from paper_1503_07998_amd import api
+    from synthetic import gaussian_psf, random_psf
+
+    torch = _torch()
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx) if layout == "stack_zyx" else (ny, nz, nx)
+    if dtype == "u16":
+        stacks = [rng.integers(50, 3000, shape).astype(np.uint16) for _ in range(views)]
+    else:
+        stacks = [rng.uniform(50.0, 3000.0, shape).astype(np.float32) for _ in range(views)]
+    psfs = [random_psf(rng, k, k, separable=True) if v % 2 else gaussian_psf(k, 1.2 + 0.3 * v, 2.5) for v in range(views)]
+    d = api.Deconvolver(views, nz, nx, 0)
+    for v, p in enumerate(psfs):
+        d.set_psf(v, p)
+    obs = [torch.from_numpy(s).to("cuda:0") for s in stacks]
+    est = torch.empty((ny, nz, nx), dtype=torch.float32, device="cuda:0")
+    run = api.make_run(ny, iters, update=update, boundary=boundary, init=init, init_const=150.0,
+                       obs_dtype=dtype, layout=layout, weights=weights)
+    nb = api.mvd_workspace_bytes(d.ctx, run)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda:0")
+    run.workspace = (ws.data_ptr() + 255) // 256 * 256
+    run.workspace_bytes = nb
+    given = torch.from_numpy(rng.uniform(80.0, 200.0, (ny, nz, nx)).astype(np.float32)).to("cuda:0")
+    return dict(obs=obs, dec=d, est=est, run=run, ws=ws, init=init, given=given,
+                stacks=stacks, psfs=psfs, update=update, iters=iters)
+
+
+def _reset(st):
+    if st["init"] == "given":
+        st["est"].copy_(st["given"])
+    else:
+        st["est"].fill_(-1.0)
+
+
+def _plain(st):
+    from paper_1503_07998_amd import api
+
+    torch = _torch()
+    _reset(st)
+    api.mvd_deconvolve_planes(st["dec"].ctx, st["obs"], st["est"], st["run"])
+    torch.cuda.synchronize()
+    return st["est"].cpu().numpy().copy()
+
+
+def _persistent_cases():
+    return [
+        # the three mix shapes, fewer planes
+        dict(nz=256, nx=384, ny=3, views=2, k=21, iters=3, update="sequential", seed=1),
+        dict(nz=128, nx=768, ny=2, views=3, k=31, iters=2, update="sequential", seed=2),
+        dict(nz=100, nx=1000, ny=2, views=4, k=41, iters=2, update="sequential", seed=3),
+        # simultaneous, two views in one forward pass, uint16 stacks
+        dict(nz=64, nx=96, ny=5, views=2, k=31, iters=3, update="simultaneous", seed=4, dtype="u16"),
+        # simultaneous, three views (views in pairs: (0, 1), (2)), planes layout, weights
+        dict(nz=40, nx=64, ny=4, views=3, k=15, iters=3, update="simultaneous", seed=5, layout="planes_yzx",
+             weights=[1.0, 0.7, 0.5]),
+        # periodic boundary (column strips with wrapped halos), small kernels, constant ψ^0
+        dict(nz=24, nx=48, ny=3, views=1, k=3, iters=4, update="sequential", seed=6, boundary="periodic",
+             init="const"),
+        dict(nz=33, nx=40, ny=3, views=2, k=7, iters=2, update="simultaneous", seed=7, init="given"),
+    ]
+
+
+def test_persistent_batch_equals_plain_bitwise():
+    """Every volume of one persistent launch equals its plain run bitwise, on
+    three launches in a row (the queue and the per-plane counters reset
+    themselves at the end of each launch)."""
+    from paper_1503_07998_amd import api
+
+    torch = _torch()
+    _say("persistent batch of 7 volumes vs plain runs, 3 launches")
+    setups = [_planes_case(**c) for c in _persistent_cases()]
+    plain = [_plain(st) for st in setups]
+    entries = [(st["dec"].ctx, st["obs"], st["est"], st["run"]) for st in setups]
+    b = api.Batch(entries)
+    info = b.info()
+    assert info["persistent"], info
+    assert info["work_groups"] >= 256
+    for rep in range(3):
+        for st in setups:
+            _reset(st)
+        b.launch()
+        b.wait()
+        for i, (st, ref) in enumerate(zip(setups, plain)):
+            np.testing.assert_array_equal(st["est"].cpu().numpy(), ref, err_msg=f"volume {i}, launch {rep}")
+    b.close()
+    # the plain path itself against the oracle (one simultaneous and one sequential volume)
+    for i in (3, 0):
+        st = setups[i]
+        ref = oracle.deconvolve(st["stacks"], [np.asarray(p, dtype=np.float64) for p in st["psfs"]], st["iters"],
+                                update=st["update"], method="fft")
+        assert np.abs(plain[i] - ref).max() / np.abs(ref).max() <= 1e-4
+    for st in setups:
+        st["dec"].close()
+
+
+def test_persistent_batch_windows_and_graph_fallback():
+    """Windows of planes change only the order of the work, not the results;
+    an item the persistent kernel does not take (rows not a multiple of 8
+    columns) makes the batch a graph, with the same results."""
+    from paper_1503_07998_amd import _native as N
+    from paper_1503_07998_amd import api
+    import ctypes
+
+    torch = _torch()
+    _say("persistent batch with 2-plane windows; graph fallback")
+    cases = _persistent_cases()[:4]
+    setups = [_planes_case(**c) for c in cases]
+    plain = [_plain(st) for st in setups]
+    lib = N.lib()
+    lib.mvd_internal_set_tune.argtypes = [ctypes.c_char_p]
+    try:
+        lib.mvd_internal_set_tune(b"pq_window=2")
+        b = api.Batch([(st["dec"].ctx, st["obs"], st["est"], st["run"]) for st in setups])
+    finally:
+        lib.mvd_internal_set_tune(None)
+    assert b.info()["persistent"]
+    for st in setups:
+        _reset(st)
+    b.launch()
+    b.wait()
+    for st, ref in zip(setups, plain):
+        np.testing.assert_array_equal(st["est"].cpu().numpy(), ref)
+    b.close()
+    odd = _planes_case(nz=20, nx=37, ny=3, views=2, k=5, iters=2, update="simultaneous", seed=9)
+    ref = _plain(odd)
+    b = api.Batch([(odd["dec"].ctx, odd["obs"], odd["est"], odd["run"]),
+                   (setups[0]["dec"].ctx, setups[0]["obs"], setups[0]["est"], setups[0]["run"])])
+    assert not b.info()["persistent"]
+    _reset(odd)
+    _reset(setups[0])
+    b.launch()
+    b.wait()
+    np.testing.assert_array_equal(odd["est"].cpu().numpy(), ref)
+    np.testing.assert_array_equal(setups[0]["est"].cpu().numpy(), plain[0])
+    b.close()
+    for st in setups + [odd]:
+        st["dec"].close()
+
+
+def test_persistent_give_up_is_reported():
+    """A raised give-up flag (as a wait that exceeded its spin limit would
+    raise it) makes every work-group skip the rest and end; the host gets
+    MVD_ERR_LAUNCH, and the next launch runs normally.  A spin limit of one
+    poll either gives up (reported) or, where no wait was needed, leaves the
+    result exact: never a silent wrong result."""
+    from paper_1503_07998_amd import _native as N
+    from paper_1503_07998_amd import api
+    import ctypes
+
+    torch = _torch()
+    _say("persistent batch: give-up flag reported, then a normal launch")
+    st = _planes_case(nz=512, nx=512, ny=2, views=2, k=31, iters=2, update="simultaneous", seed=11)
+    ref = _plain(st)
+    b = api.Batch([(st["dec"].ctx, st["obs"], st["est"], st["run"])])
+    lib = N.lib()
+    lib.mvd_internal_batch_raise_giveup.argtypes = [ctypes.c_void_p]
+    assert lib.mvd_internal_batch_raise_giveup(b.handle) == 0
+    _reset(st)
+    b.launch()
+    with pytest.raises(N.MvdError) as e:
+        b.wait()
+    assert e.value.status == N.MVD_ERR_LAUNCH
+    _reset(st)
+    b.launch()
+    b.wait()
+    np.testing.assert_array_equal(st["est"].cpu().numpy(), ref)
+    lib.mvd_internal_set_pq_spin.argtypes = [ctypes.c_uint]
+    try:
+        lib.mvd_internal_set_pq_spin(1)
+        _reset(st)
+        b.launch()
+        try:
+            b.wait()
+            np.testing.assert_array_equal(st["est"].cpu().numpy(), ref)
+        except N.MvdError as err:
+            assert err.status == N.MVD_ERR_LAUNCH
+    finally:
+        lib.mvd_internal_set_pq_spin(0)
+    _reset(st)
+    b.launch()
+    b.wait()
+    np.testing.assert_array_equal(st["est"].cpu().numpy(), ref)
+    b.close()
+    st["dec"].close()
