@@ -167,8 +167,10 @@ void mvd_destroy(mvd_ctx *ctx);
  * back-projector mode (mvd_back).  back_taps: host float32 [kz][kx] for
  * MVD_BACK_EXPLICIT, else ignored (may be NULL).  Back-projectors, compound
  * ones included, are (re)built by the call that completes the set of PSFs and
- * by every later call.  Rank-one taps
- * (to 1e-6 relative) are run as two 1D passes; others as K×K passes.
+ * by every later call.  Rank-one taps (to 1e-6 relative) are run as two 1D
+ * passes; taps whose SVD gives at most 6 rank-one terms reproducing them to
+ * 1e-6 of the largest as that many pairs of 1D passes; others
+ * as K×K passes (mvd_psf_info).
  * Errors: MVD_ERR_ARG (bad view, sides even or outside [1, MVD_MAX_K], taps
  * negative/non-finite/all zero, missing explicit taps), MVD_ERR_ALLOC. */
 mvd_status mvd_set_psf(mvd_ctx *ctx, int view, const float *taps, int kz, int kx,
@@ -179,16 +181,20 @@ mvd_status mvd_set_psf(mvd_ctx *ctx, int view, const float *taps, int kz, int kx
  * Errors: MVD_ERR_ARG, MVD_ERR_STATE (some view has no PSF). */
 mvd_status mvd_get_back_taps(mvd_ctx *ctx, int view, float *out);
 
-/* Whether view v's forward PSF and back-projector run as rank-one (1) or
- * K×K (0) passes.  Either pointer may be NULL. */
+/* How view v's forward PSF and back-projector run: 1 = rank one (two 1D
+ * passes); r ≥ 2 = a sum of r rank-one terms from the kernel's SVD (at most
+ * 6 terms, every tap reproduced to 1e-6 of the largest; r pairs of 1D passes
+ * accumulated before the ratio or the update, Supplementary Note 2 §4 convolves
+ * with measured PSFs); 0 = K×K passes.  Either pointer may be NULL. */
 mvd_status mvd_psf_info(mvd_ctx *ctx, int view, int *separable_psf, int *separable_back);
 
 /* Device workspace needed by mvd_deconvolve_planes() for `run`, in bytes:
  * V float32 plane sets for the observations, resliced/converted and clamped
- * at 0 (filled only when some view's forward pass is a K×K pass; the rank-one
+ * at 0 (filled only when some view's PSF is not rank one; the rank-one
  * passes read the observations as given, through their layout's strides),
  * plus the ratio planes (V sets for MVD_UPDATE_SIMULTANEOUS, one for
- * sequential; none when n_iters = 0).  Errors: MVD_ERR_ARG. */
+ * sequential; none when n_iters = 0), plus one set for partial sums where a
+ * kernel runs as a sum of rank-one terms.  Errors: MVD_ERR_ARG. */
 mvd_status mvd_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, size_t *bytes);
 
 /* Reslice one camera-ordered stack (device [Z][Y][X], u16 or f32) into device

@@ -53,6 +53,13 @@ int mvd_internal_corr_plan(int n_planes, int Z, int X, int kz, int kx, long *out
  * running in other threads. */
 int mvd_internal_set_tune(const char *spec);
 
+/* The 1D factors view `view`'s PSF (which = 0) or back-projector (1) runs
+ * with: R terms, each kz z-taps then kx x-taps (float32), into out[R·(kz+kx)]
+ * (at most `cap` terms written).  Returns R: 1 for a rank-one kernel, the
+ * number of terms for a sum of rank-one terms, 0 for the K×K passes; or a
+ * negative mvd_status. */
+int mvd_internal_psf_terms(mvd_ctx *ctx, int view, int which, float *out, int cap);
+
 /* Polls a persistent batch's work-group makes before it gives up waiting for
  * a dependency (0: the default, about 2^24).  Lets a test make the wait give
  * up at once, so the failure report is exercised with every kernel ending

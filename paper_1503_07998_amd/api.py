@@ -93,9 +93,11 @@ def mvd_get_back_taps(ctx, view: int, kz: int, kx: int) -> np.ndarray:
 
 
 def mvd_psf_info(ctx, view: int):
+    """(PSF, back-projector) pass forms: 1 rank one, r ≥ 2 a sum of r rank-one
+    terms, 0 K×K."""
     sp, sx = c_int(), c_int()
     N.check(N.lib().mvd_psf_info(ctx, int(view), ctypes.byref(sp), ctypes.byref(sx)), ctx)
-    return bool(sp.value), bool(sx.value)
+    return sp.value, sx.value
 
 
 def make_run(n_planes, n_iters, *, update="simultaneous", boundary="zero", init="mean",

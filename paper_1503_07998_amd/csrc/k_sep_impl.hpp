@@ -446,11 +446,16 @@ __device__ __forceinline__ void store_group(float *B, KArg *a, const Cols<C, Sha
 //   kStore  out = conv                               (adjoint: q = r ⊛ X)
 //   kBR     out = conv (b), out2 = φ / conv (r)      (adjoint: recompute b and r)
 //   kBbar   out = −conv · r / b where b > ε, else 0 (adjoint: b̄ from r̄)
-//   kAccum  out = aux0 + conv                        (adjoint: ψ̄ += b̄ ⊛ P^*)
+//   kAccum  out = aux0 + conv                        (adjoint: ψ̄ += b̄ ⊛ P^*; the
+//                                                    middle terms of a low-rank kernel)
+//   kAccumRatio   out = φ / (aux0 + conv), φ at aux1 (last term of a low-rank P_v)
+//   kAccumUpdate  out = ψ · (w (aux0 + conv) + 1 − w), ψ at aux1 (last term of a
+//                 low-rank X_v; out may be ψ itself: read and written at one pixel)
 // ---------------------------------------------------------------------------
 template <int EP>
 struct Epi {
-  static constexpr int nops = (EP == kEpBbar) ? 2 : (EP == kEpStore ? 0 : 1);
+  static constexpr int nops = (EP == kEpBbar || EP == kEpAccumRatio || EP == kEpAccumUpdate) ? 2
+                              : (EP == kEpStore ? 0 : 1);
   static constexpr int nbuf = nops > 0 ? nops : 1;
 };
 
@@ -528,6 +533,15 @@ __device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const
         const float q = nr_quotient(b[n] * ops.f[v][0][n], bb);
         r[n] = bb > kEps ? -q : 0.f;
       }
+      store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, r);
+    } else if constexpr (EP == kEpAccumRatio) {
+#pragma unroll
+      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(ops.f[v][1][n], ops.f[v][0][n] + b[n]);
+      store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, r);
+    } else if constexpr (EP == kEpAccumUpdate) {
+      const float w = a->w[v], w1 = 1.f - w;
+#pragma unroll
+      for (int n = 0; n < NX; ++n) r[n] = ops.f[v][1][n] * fmaf(w, ops.f[v][0][n] + b[n], w1);
       store8<VM>(a->out[v] + itm.off, itm.nvalid, vec, r);
     } else {
 #pragma unroll
@@ -853,6 +867,8 @@ hipError_t single_bucket(const SepPassArgs &a, const SepPlan &p, int ep, hipStre
     case kEpBR: return single_ep<KB, kEpBR>(a, p, s);
     case kEpBbar: return single_ep<KB, kEpBbar>(a, p, s);
     case kEpAccum: return single_ep<KB, kEpAccum>(a, p, s);
+    case kEpAccumRatio: return single_ep<KB, kEpAccumRatio>(a, p, s);
+    case kEpAccumUpdate: return single_ep<KB, kEpAccumUpdate>(a, p, s);
   }
   return hipErrorInvalidValue;
 }

@@ -117,6 +117,12 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsLimit = 160 * 1024;
 
+// Kernels that are not rank one run as sums of rank-one terms when their SVD
+// needs at most kLowRankMax terms to reproduce every tap to kLowRankTol of the
+// largest (the rank-one test's tolerance); each term costs one 1D pass pair.
+constexpr int kLowRankMax = 6;
+constexpr double kLowRankTol = 1e-6;
+
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 struct ViewPsf {
@@ -128,6 +134,9 @@ struct ViewPsf {
   Kernel back;              // X_v (float32-rounded values)
   bool sep_p = false, sep_x = false;
   std::vector<float> pz, px, xz, xx;  // 1D factors (z, x) of P_v and X_v
+  // kernels that are not rank one but a sum of a few rank-one terms (from
+  // their SVD): each term's factors; empty where the K×K passes are taken
+  std::vector<std::vector<float>> lpz, lpx, lxz, lxx;
 };
 
 thread_local std::string g_noctx_error;
@@ -290,6 +299,23 @@ mvd_status derive(mvd_ctx *c) {
       w.xz = to_f32(u);
       w.xx = to_f32(vv);
     }
+    // not rank one: a sum of at most kLowRankMax rank-one terms reproducing
+    // every tap to kLowRankTol of the largest runs as that many 1D pass pairs
+    w.lpz.clear();
+    w.lpx.clear();
+    w.lxz.clear();
+    w.lxx.clear();
+    std::vector<std::vector<double>> us, vs;
+    if (!w.sep_p && low_rank(w.psf, kLowRankMax, kLowRankTol, &us, &vs))
+      for (size_t t = 0; t < us.size(); ++t) {
+        w.lpz.push_back(to_f32(us[t]));
+        w.lpx.push_back(to_f32(vs[t]));
+      }
+    if (!w.sep_x && low_rank(w.back, kLowRankMax, kLowRankTol, &us, &vs))
+      for (size_t t = 0; t < us.size(); ++t) {
+        w.lxz.push_back(to_f32(us[t]));
+        w.lxx.push_back(to_f32(vs[t]));
+      }
     c->kzm = std::max({c->kzm, w.psf.kz, w.back.kz});
     c->kxm = std::max({c->kxm, w.psf.kx, w.back.kx});
   }
@@ -369,9 +395,19 @@ bool all_set(const mvd_ctx *c) {
 // only where a K×K forward pass needs them) and the ratio planes.
 struct Layout {
   size_t plane_set = 0; // bytes of one [Y][Z][X] float32 set
-  size_t phi_off = 0, r_off = 0, total = 0;
+  size_t phi_off = 0, r_off = 0, acc_off = 0, total = 0;
   int n_ratio = 0;
+  bool acc = false;     // a plane set for the partial sums of kernels run as sums of rank-one terms
 };
+
+// Some pass of the run sums several rank-one terms (a PSF or back-projector
+// that is not rank one but of low rank, and K×K passes not forced).
+bool uses_low_rank(const mvd_ctx *c, const mvd_run *r) {
+  if (!c->derived || (r->flags & MVD_FLAG_FORCE_2D)) return false;
+  for (const ViewPsf &w : c->views)
+    if ((!w.sep_p && !w.lpz.empty()) || (!w.sep_x && !w.lxz.empty())) return true;
+  return false;
+}
 
 Layout layout_of(const mvd_ctx *c, const mvd_run *r) {
   Layout L;
@@ -382,6 +418,9 @@ Layout layout_of(const mvd_ctx *c, const mvd_run *r) {
   off += (size_t)c->nv * L.plane_set;
   L.r_off = off;
   off += (size_t)L.n_ratio * L.plane_set;
+  L.acc = uses_low_rank(c, r);
+  L.acc_off = off;
+  if (L.acc) off += L.plane_set;
   L.total = r->n_iters > 0 ? off : (size_t)c->nv * L.plane_set;
   return L;
 }
@@ -644,6 +683,7 @@ struct RunState {
   bool normalize = false;     // divide back-projections by 1 ⊛ X_v (MVD_FLAG_NORMALIZE)
   const float *const *wpl = nullptr;   // per-pixel weight planes of the whole volume, or null
   size_t wpl_off = 0;                  // elements from their start to this launch's first plane
+  float *acc = nullptr;                // partial sums of low-rank kernels' terms (a plane set), or null
 };
 
 hipEvent_t take_event(mvd_ctx *c) {
@@ -713,6 +753,9 @@ bool run_needs_2d(const RunState &st) {
   return false;
 }
 
+hipError_t lowrank_forward(const RunState &st, const float *psi, const float *phi, float *rv, int v);
+hipError_t lowrank_backward(const RunState &st, const float *rv, const float *psi_in, float *psi_out, int v);
+
 hipError_t forward_views(const RunState &st, const float *psi, const ObsRef &ob, float *const *r, int v0, int n) {
   mvd_ctx *c = st.c;
   bool sep = !st.force2d;
@@ -720,6 +763,20 @@ hipError_t forward_views(const RunState &st, const float *psi, const ObsRef &ob,
   for (int v = v0; v < v0 + n; ++v) {
     sep = sep && c->views[v].sep_p;
     kmax = std::max({kmax, c->views[v].psf.kz, c->views[v].psf.kx});
+  }
+  // PSFs of low rank: view by view, each as a sum of rank-one terms (the
+  // others of the range in their own launches)
+  if (!sep && !st.force2d && st.acc) {
+    bool lr = false;
+    for (int v = v0; v < v0 + n; ++v) lr = lr || (!c->views[v].sep_p && !c->views[v].lpz.empty());
+    if (lr) {
+      if (n == 1) return lowrank_forward(st, psi, ob.staged ? ob.staged[v0] : nullptr, r[v0], v0);
+      for (int v = v0; v < v0 + n; ++v) {
+        hipError_t e = forward_views(st, psi, ob, r, v, 1);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }
   }
   if (sep) {
     SepGeom sg = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, *st.tn, true);
@@ -783,6 +840,21 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
   for (int v = v0; v < v0 + n; ++v) {
     sep = sep && c->views[v].sep_x;
     kmax = std::max({kmax, c->views[v].back.kz, c->views[v].back.kx});
+  }
+  // back-projectors of low rank: view by view in view order (ψ · c_0 · c_1 …)
+  if (!sep && !st.force2d && st.acc) {
+    bool lr = false;
+    for (int v = v0; v < v0 + n; ++v) lr = lr || (!c->views[v].sep_x && !c->views[v].lxz.empty());
+    if (lr) {
+      if (n == 1) return lowrank_backward(st, r[v0], psi_in, psi_out, v0);
+      const float *in = psi_in;
+      for (int v = v0; v < v0 + n; ++v) {
+        hipError_t e = backward_views(st, r, in, psi_out, v, 1);
+        if (e != hipSuccess) return e;
+        in = psi_out;
+      }
+      return hipSuccess;
+    }
   }
   const float *cur = psi_in;
   if (sep) {
@@ -933,7 +1005,7 @@ std::vector<float> reversed(const std::vector<float> &f) { return std::vector<fl
 // One view's single-input separable pass with epilogue `ep`.
 hipError_t single_pass(const RunState &st, int ep, const float *in, const std::vector<float> &fz,
                        const std::vector<float> &fx, float *out, float *out2, const float *aux0,
-                       const float *aux1, const float *phi) {
+                       const float *aux1, const float *phi, float w = 1.f, int kind = 3) {
   const int k = std::max((int)fz.size(), (int)fx.size());
   SepGeom sg = plan_sep(st.c, st.g.Y, sep_bucket(k), st.boundary, *st.tn);
   sg.plan.occ = (sg.plan.cols == 1 && sg.plan.bucket <= 31) ? 4 : 2;
@@ -946,12 +1018,46 @@ hipError_t single_pass(const RunState &st, int ep, const float *in, const std::v
   a.aux0[0] = aux0;
   a.aux1[0] = aux1;
   a.phi[0] = phi;
+  a.w[0] = w;
   put_factor(a.tz[0], fz, sg.plan.bucket);
   put_factor(a.tx[0], fx, sg.plan.bucket);
   a.vec = whole_items(sg, st.g) && aligned16(in) && aligned16(out);
   for (const void *p : {(const void *)out2, (const void *)aux0, (const void *)aux1, (const void *)phi})
     if (p) a.vec = a.vec && aligned16(p);
-  return timed(st, 3, [&] { return launch_sep_single_dispatch(a, sg.plan, ep, st.s); });
+  return timed(st, kind, [&] { return launch_sep_single_dispatch(a, sg.plan, ep, st.s); });
+}
+
+// A forward pass of view v whose PSF is a sum of rank-one terms: b = Σ_t ψ ⊛
+// (pz_t ⊗ px_t), term by term into the partial-sum planes, the last term
+// finishing r_v = φ_v / b (φ_v from the staged float32 planes).
+hipError_t lowrank_forward(const RunState &st, const float *psi, const float *phi, float *rv, int v) {
+  const ViewPsf &w = st.c->views[v];
+  const int R = (int)w.lpz.size();
+  if (R < 2 || !st.acc || !phi) return hipErrorInvalidValue;
+  for (int t = 0; t < R; ++t) {
+    const bool last = t == R - 1;
+    const int ep = t == 0 ? kEpStore : (last ? kEpAccumRatio : kEpAccum);
+    hipError_t e = single_pass(st, ep, psi, w.lpz[t], w.lpx[t], last ? rv : st.acc, nullptr, t > 0 ? st.acc : nullptr,
+                               last ? phi : nullptr, nullptr, 1.f, 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// A backward pass of view v whose back-projector is a sum of rank-one terms:
+// q = Σ_t r_v ⊛ (xz_t ⊗ xx_t), the last term finishing ψ_out = ψ_in · (w q + 1 − w).
+hipError_t lowrank_backward(const RunState &st, const float *rv, const float *psi_in, float *psi_out, int v) {
+  const ViewPsf &w = st.c->views[v];
+  const int R = (int)w.lxz.size();
+  if (R < 2 || !st.acc) return hipErrorInvalidValue;
+  for (int t = 0; t < R; ++t) {
+    const bool last = t == R - 1;
+    const int ep = t == 0 ? kEpStore : (last ? kEpAccumUpdate : kEpAccum);
+    hipError_t e = single_pass(st, ep, rv, w.lxz[t], w.lxx[t], last ? psi_out : st.acc, nullptr,
+                               t > 0 ? st.acc : nullptr, last ? psi_in : nullptr, nullptr, weight_of(st, v), 1);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t tap_corr(const RunState &st, const BwdLayout &L, char *ws, const float *gbar, const float *src,
@@ -1062,6 +1168,7 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
               timing_override || (r->flags & MVD_FLAG_TIMING) != 0, &tn};
   rs.normalize = (r->flags & MVD_FLAG_NORMALIZE) != 0;
   rs.wpl = r->weight_planes;
+  if (L.acc) rs.acc = reinterpret_cast<float *>(ws + L.acc_off);
   // the separable forward passes read the observations as given; only the
   // general K×K passes need them staged as float32 planes
   const bool need_staged = run_needs_2d(rs);
@@ -1863,8 +1970,9 @@ mvd_status mvd_psf_info(mvd_ctx *c, int view, int *sp, int *sx) {
   c->err.clear();
   if (view < 0 || view >= c->nv) return fail(c, MVD_ERR_ARG, "view %d outside [0, %d)", view, c->nv);
   if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
-  if (sp) *sp = c->views[view].sep_p ? 1 : 0;
-  if (sx) *sx = c->views[view].sep_x ? 1 : 0;
+  const ViewPsf &w = c->views[view];
+  if (sp) *sp = w.sep_p ? 1 : (int)w.lpz.size();
+  if (sx) *sx = w.sep_x ? 1 : (int)w.lxz.size();
   return MVD_OK;
 }
 
@@ -2048,6 +2156,26 @@ int mvd_internal_mfma_plan(int kz, int kx, int *out) {
 }
 
 int mvd_internal_version(void) { return MVD_TESTING_VERSION; }
+
+int mvd_internal_psf_terms(mvd_ctx *c, int view, int which, float *out, int cap) {
+  if (!c || view < 0 || view >= c->nv || !c->derived || (which != 0 && which != 1)) return MVD_ERR_ARG;
+  const ViewPsf &w = c->views[view];
+  const bool one = which == 0 ? w.sep_p : w.sep_x;
+  const auto &zs = which == 0 ? w.lpz : w.lxz;
+  const auto &xs = which == 0 ? w.lpx : w.lxx;
+  const int R = one ? 1 : (int)zs.size();
+  if (out) {
+    const Kernel &k = which == 0 ? w.psf : w.back;
+    long o = 0;
+    for (int t = 0; t < R && t < cap; ++t) {
+      const std::vector<float> &fz = one ? (which == 0 ? w.pz : w.xz) : zs[t];
+      const std::vector<float> &fx = one ? (which == 0 ? w.px : w.xx) : xs[t];
+      for (int j = 0; j < k.kz; ++j) out[o++] = fz[j];
+      for (int i = 0; i < k.kx; ++i) out[o++] = fx[i];
+    }
+  }
+  return R;
+}
 
 int mvd_internal_set_pq_spin(unsigned polls) {
   g_pq_spin.store(polls);

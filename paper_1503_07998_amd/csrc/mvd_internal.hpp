@@ -112,6 +112,10 @@ constexpr int kEpStore = 1;   // out = conv
 constexpr int kEpBR = 2;      // out = conv, out2 = φ / conv
 constexpr int kEpBbar = 3;    // out = −conv · aux0 / aux1 where aux1 > ε, else 0
 constexpr int kEpAccum = 4;   // out = aux0 + conv
+// Last term of a kernel that runs as a sum of rank-one terms (aux0: the sum of
+// the earlier terms):
+constexpr int kEpAccumRatio = 6;   // b = aux0 + conv; out = φ / b (guarded), φ float32 at aux1
+constexpr int kEpAccumUpdate = 7;  // q = aux0 + conv; out = ψ · (w q + 1 − w), ψ at aux1 (may be out)
 
 // Launch configuration chosen by the host for a separable pass.
 struct SepPlan {

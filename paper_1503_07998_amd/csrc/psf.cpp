@@ -105,4 +105,99 @@ bool rank_one(const Kernel &k, std::vector<double> *u, std::vector<double> *v) {
   return true;
 }
 
+// Singular value decomposition of k (kz × kx) by one-sided Jacobi rotations
+// (Hestenes): columns of A = k are rotated pairwise until orthogonal; then
+// σ_i = |a_i|, v_i = the accumulated rotations' column i, u_i = a_i / σ_i.
+// Small matrices (at most 63 × 63), float64, converged to 1e-15.
+static void jacobi_svd(const Kernel &k, std::vector<double> *sv, std::vector<std::vector<double>> *U,
+                       std::vector<std::vector<double>> *V) {
+  const int m = k.kz, n = k.kx;
+  std::vector<std::vector<double>> a(n, std::vector<double>(m)), v(n, std::vector<double>(n, 0.0));
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < m; ++j) a[i][j] = k.at(j, i);
+    v[i][i] = 1.0;
+  }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double alpha = 0.0, beta = 0.0, gamma = 0.0;
+        for (int j = 0; j < m; ++j) {
+          alpha += a[p][j] * a[p][j];
+          beta += a[q][j] * a[q][j];
+          gamma += a[p][j] * a[q][j];
+        }
+        if (gamma == 0.0 || std::fabs(gamma) <= 1e-15 * std::sqrt(alpha * beta)) continue;
+        off = std::max(off, std::fabs(gamma) / std::sqrt(alpha * beta));
+        const double zeta = (beta - alpha) / (2.0 * gamma);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+        for (int j = 0; j < m; ++j) {
+          const double x = a[p][j], y = a[q][j];
+          a[p][j] = c * x - s * y;
+          a[q][j] = s * x + c * y;
+        }
+        for (int j = 0; j < n; ++j) {
+          const double x = v[p][j], y = v[q][j];
+          v[p][j] = c * x - s * y;
+          v[q][j] = s * x + c * y;
+        }
+      }
+    if (off <= 1e-15) break;
+  }
+  std::vector<int> order(n);
+  std::vector<double> norm(n);
+  for (int i = 0; i < n; ++i) {
+    double s2 = 0.0;
+    for (int j = 0; j < m; ++j) s2 += a[i][j] * a[i][j];
+    norm[i] = std::sqrt(s2);
+    order[i] = i;
+  }
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return norm[x] > norm[y]; });
+  sv->clear();
+  U->clear();
+  V->clear();
+  for (int i : order) {
+    sv->push_back(norm[i]);
+    std::vector<double> u(m, 0.0);
+    if (norm[i] > 0.0)
+      for (int j = 0; j < m; ++j) u[j] = a[i][j] / norm[i];
+    U->push_back(u);
+    V->push_back(v[i]);
+  }
+}
+
+// The fewest rank-one terms Σ_t u_t ⊗ v_t (from the SVD, each term's factors
+// scaled by √σ_t) that reproduce every tap to tol · max|k|, at most rmax of
+// them; false if more are needed.
+bool low_rank(const Kernel &k, int rmax, double tol, std::vector<std::vector<double>> *us,
+              std::vector<std::vector<double>> *vs) {
+  double amax = 0.0;
+  for (double e : k.t) amax = std::max(amax, std::fabs(e));
+  if (!(amax > 0.0)) return false;
+  std::vector<double> sv;
+  std::vector<std::vector<double>> U, V;
+  jacobi_svd(k, &sv, &U, &V);
+  std::vector<double> approx(k.t.size(), 0.0);
+  us->clear();
+  vs->clear();
+  for (int r = 0; r < rmax && r < (int)sv.size(); ++r) {
+    const double sq = std::sqrt(sv[r]);
+    std::vector<double> u(U[r]), v(V[r]);
+    for (double &e : u) e *= sq;
+    for (double &e : v) e *= sq;
+    us->push_back(u);
+    vs->push_back(v);
+    double err = 0.0;
+    for (int j = 0; j < k.kz; ++j)
+      for (int i = 0; i < k.kx; ++i) {
+        double &ap = approx[(size_t)j * k.kx + i];
+        ap += u[j] * v[i];
+        err = std::max(err, std::fabs(ap - k.at(j, i)));
+      }
+    if (err <= tol * amax) return true;
+  }
+  return false;
+}
+
 }  // namespace mvd

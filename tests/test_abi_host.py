@@ -444,3 +444,83 @@ def test_static_entry_point_validation_before_device():
         assert api.mvd_workspace_bytes(big, one) > N.MVD_SCRATCH_BYTES
     finally:
         api.mvd_destroy(big)
+
+
+def _terms(ctx, view, which, kz, kx):
+    lib = N.lib()
+    lib.mvd_internal_psf_terms.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    r = lib.mvd_internal_psf_terms(ctx, view, which, None, 0)
+    if r <= 0:
+        return r, None
+    buf = (ctypes.c_float * (r * (kz + kx)))()
+    assert lib.mvd_internal_psf_terms(ctx, view, which, buf, r) == r
+    a = np.frombuffer(buf, dtype=np.float32).astype(np.float64).reshape(r, kz + kx)
+    return r, sum(np.outer(t[:kz], t[kz:]) for t in a)
+
+
+def _low_rank_psf(rng, k, r):
+    """Sum of r random positive asymmetric outer products (rank r), unit sum."""
+    p = sum(np.outer(rng.uniform(0.05, 1.0, k), rng.uniform(0.05, 1.0, k)) for _ in range(r))
+    return p / p.sum()
+
+
+def _rotated_gaussian(k, sx, sz, deg):
+    d = np.arange(k) - (k - 1) / 2
+    zz, xx = np.meshgrid(d, d, indexing="ij")
+    a = np.deg2rad(deg)
+    xr, zr = np.cos(a) * xx + np.sin(a) * zz, -np.sin(a) * xx + np.cos(a) * zz
+    p = np.exp(-xr ** 2 / (2 * sx * sx) - zr ** 2 / (2 * sz * sz))
+    return p / p.sum()
+
+
+@pytest.mark.parametrize("k", [15, 31, 41, 51])
+def test_low_rank_kernels_run_as_sums_of_terms(k):
+    """A PSF that is a sum of r ≤ 6 outer products runs as r rank-one terms from
+    its float64 SVD (Jacobi), and their factors reproduce the float32 taps to
+    1e-6 of the largest tap; the flipped back-projector has the same rank."""
+    rng = np.random.default_rng(k)
+    for r in (2, 3, 4, 6):
+        p = _low_rank_psf(rng, k, r).astype(np.float32)
+        ctx = api.mvd_create(1, 40, 40, N.MVD_DEVICE_NONE)
+        try:
+            api.mvd_set_psf(ctx, 0, p)
+            sp, sx = api.mvd_psf_info(ctx, 0)
+            assert (sp, sx) == (r, r)
+            for which, ref in ((0, p.astype(np.float64)), (1, p.astype(np.float64)[::-1, ::-1])):
+                got_r, approx = _terms(ctx, 0, which, k, k)
+                assert got_r == r
+                assert np.abs(approx - ref).max() <= 1e-6 * np.abs(ref).max()
+        finally:
+            api.mvd_destroy(ctx)
+
+
+def test_kernels_of_higher_rank_keep_the_kxk_passes():
+    """Rank 7 (above the 6-term limit), a Gaussian rotated by 20° (its SVD needs
+    many more terms for 1e-6) and iid random taps run as K×K passes; a rank-one
+    kernel reports 1."""
+    rng = np.random.default_rng(3)
+    cases = [(_low_rank_psf(rng, 31, 7), 0), (_rotated_gaussian(31, 1.5, 6.0, 20.0), 0),
+             (random_psf(rng, 21, 21), 0), (gaussian_psf(21, 1.5, 4.0), 1)]
+    for p, want in cases:
+        ctx = api.mvd_create(1, 40, 40, N.MVD_DEVICE_NONE)
+        try:
+            api.mvd_set_psf(ctx, 0, p.astype(np.float32))
+            assert api.mvd_psf_info(ctx, 0)[0] == want
+        finally:
+            api.mvd_destroy(ctx)
+
+
+def test_low_rank_runs_need_a_partial_sum_plane_set():
+    rng = np.random.default_rng(5)
+    ctx = api.mvd_create(2, 16, 24, N.MVD_DEVICE_NONE)
+    try:
+        api.mvd_set_psf(ctx, 0, gaussian_psf(7, 1.0, 2.0))
+        api.mvd_set_psf(ctx, 1, gaussian_psf(7, 2.0, 1.0))
+        r = api.make_run(3, 2)
+        base = api.mvd_workspace_bytes(ctx, r)
+        api.mvd_set_psf(ctx, 1, _low_rank_psf(rng, 7, 2).astype(np.float32))
+        assert api.mvd_workspace_bytes(ctx, r) == base + 3 * 16 * 24 * 4 + (256 - (3 * 16 * 24 * 4) % 256) % 256
+        assert api.mvd_workspace_bytes(ctx, api.make_run(3, 2, force_2d=True)) == base
+    finally:
+        api.mvd_destroy(ctx)
