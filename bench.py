@@ -42,6 +42,8 @@ PAPER_CONTEXT = {
               "(3.36e8 voxel-iterations/s), Supplementary Table 1",
     "planes2048": "GTX TITAN Black, 2048^3 padded, 2 views, 10 iterations: 152.3 s "
                   "(5.64e8 voxel-iterations/s), Supplementary Table 1",
+    "vol2048": "GTX TITAN Black, 2048^3 padded, 2 views, 10 iterations, disk to disk: 152.3 s "
+               "(5.64e8 voxel-iterations/s), Supplementary Table 1",
 }
 
 # per-pixel view weights (--pixel-weights): the backward pass also reads them
@@ -54,6 +56,10 @@ def step_work(spec, kind, vox, launches_per_iter, general=False):
     return b, f
 
 
+# PSF terms per view (--psf lowrank: a sum of this many rank-one terms)
+PSF_TERMS = 1
+
+
 def step_work_split(spec, kind, vox, launches_per_iter, general=False):
     """Algorithmic bytes and flops of one forward / backward launch over
     ``vox`` voxels (a whole volume, or one batch of planes).
@@ -62,19 +68,27 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
     uint16 observations; the general K×K passes read float32 staged copies),
     writes r_v and (once per launch) reads ψ; a backward pass reads r_v and
     (once per launch) reads and writes ψ.  Each view's two 1D passes cost
-    2 · (kz + kx) flops (FMA = 2); a general K×K pass costs 2 · kz · kx.
+    2 · (kz + kx) flops (FMA = 2); a general K×K pass costs 2 · kz · kx; a PSF
+    of R rank-one terms runs R pairs of 1D passes through a partial-sum plane.
     The library may split the V views of an iteration over several launches,
     so the work of one iteration on those voxels is divided by its launches.
     """
     V = spec.n_views
     k = spec.psf_k
     n = launches_per_iter
-    if kind == "forward":
+    R = PSF_TERMS
+    if R > 1 and not general:
+        # one launch per view and term: every term reads its input (ψ forward,
+        # r_v backward), terms after the first read and all but the last write
+        # the partial sum; the last adds φ_v (float32) and r_v forward, ψ in and
+        # ψ out backward: 4R + 8(R − 1) + 8 = 12R bytes per voxel and view
+        b = 12 * R * V
+    elif kind == "forward":
         phi = 2 if (spec.obs_dtype == "u16" and not general) else 4
         b = (phi + 4) * V + 4 * n
     else:
         b = (8 if WEIGHT_PLANES else 4) * V + 8 * n
-    f = V * 2 * (k * k if general else k + k)
+    f = V * 2 * (k * k if general else PSF_TERMS * (k + k))
     # where the flops run: the separable passes do both the column (z) and the
     # row (x) convolution on the matrix cores, and so do the general K×K passes
     f_mfma = f
@@ -169,6 +183,22 @@ def launch_kinds(spec, tim, steps, vox, batches=1, general=False):
             kinds[kind] = dict(launches=n, launches_per_iteration=per_iter, avg_ms=avg * 1e3, bytes=b, flops=f,
                                flops_valu=fv, flops_mfma=fm, gbs=b / avg / 1e9, tflops=f / avg / 1e12)
     return kinds
+
+
+def lowrank_psfs(spec):
+    """Non-separable rank-two PSFs for every view: the view's Gaussian plus 0.3 ×
+    a Gaussian of twice its x width and half its z width, offset by 3 rows and
+    −2 columns (a weaker side lobe), normalised; float32 [K][K]."""
+    import numpy as np
+
+    from synthetic import gaussian_psf
+
+    out = []
+    for sx, sz in spec.view_sigmas():
+        side = np.roll(np.roll(gaussian_psf(spec.psf_k, 2.0 * sx, 0.5 * sz), 3, axis=0), -2, axis=1)
+        p = gaussian_psf(spec.psf_k, sx, sz) + 0.3 * side
+        out.append((p / p.sum()).astype(np.float32))
+    return out
 
 
 def host_cores():
@@ -627,6 +657,166 @@ def bench_grad(args, spec):
     print(json.dumps(out), flush=True)
 
 
+def write_stack(path, t, chunk=64):
+    """Writes a device tensor [Z][Y][X] to a raw file, chunk slices at a time,
+    then flushes it and drops it from the page cache (so it is read from disk)."""
+    fd = os.open(path, os.O_WRONLY | os.O_CREAT | os.O_TRUNC, 0o644)
+    try:
+        for z0 in range(0, t.shape[0], chunk):
+            buf = t[z0:z0 + chunk].cpu().numpy().tobytes()
+            view = memoryview(buf)
+            while view:
+                n = os.write(fd, view)
+                view = view[n:]
+        os.fsync(fd)
+        os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
+    finally:
+        os.close(fd)
+
+
+def bench_vol2048(args, spec):
+    """The whole 2048³ volume (2 views, 10 iterations): device-resident, then,
+    with --disk DIR, the same run disk to disk (stacks read from raw files in
+    DIR, ψ^T written to a raw file there, page cache dropped behind every read
+    and write).  The observations are a slab of --distinct rendered planes
+    repeated along the plane axis on the device (planes are deconvolved
+    independently, so the per-plane work is that of a fully rendered volume)."""
+    import shutil
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    from paper_1503_07998_amd import api
+    from synthetic import make_volume
+
+    Y, Z, X = spec.n_planes, spec.n_z, spec.n_x
+    nd = args.distinct
+    if nd < 1 or Y % nd:
+        raise SystemExit(f"--distinct must divide {Y}")
+    log(f"generating a {nd}-plane slab of {spec.name}")
+    t0 = time.perf_counter()
+    vol = make_volume(spec, planes=nd, truth=False, workers=host_cores())
+    log(f"generated in {time.perf_counter() - t0:.1f} s; repeating it {Y // nd}x along the plane axis")
+    dev = torch.device("cuda:0")
+    obs = [torch.from_numpy(s).to(dev).repeat(1, Y // nd, 1) for s in vol["stacks"]]
+    d = api.Deconvolver(spec.n_views, Z, X, 0)
+    for v, p in enumerate(vol["psfs"]):
+        d.set_psf(v, p)
+    est = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
+
+    def make(timing):
+        return api.make_run(Y, spec.iters, update=spec.update, boundary=spec.boundary, obs_dtype="u16",
+                            layout="stack_zyx", timing=timing, tune=True)
+
+    nbytes = api.mvd_workspace_bytes(d.ctx, make(False))
+    log(f"device memory: stacks {2 * sum(o.numel() for o in obs) / 1e9:.1f} GB, estimate "
+        f"{est.numel() * 4 / 1e9:.1f} GB, workspace {nbytes / 1e9:.1f} GB")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    wptr = (ws.data_ptr() + 255) // 256 * 256
+    runs = {}
+    for timing in (False, True):
+        r = make(timing)
+        r.workspace = wptr
+        r.workspace_bytes = nbytes
+        runs[timing] = r
+    stream = torch.cuda.current_stream()
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        api.mvd_deconvolve_planes(d.ctx, obs, est, runs[False], stream)
+    torch.cuda.synchronize()
+    api.mvd_get_timing(d.ctx, reset=True)
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        api.mvd_deconvolve_planes(d.ctx, obs, est, runs[True], stream)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    tim = api.mvd_get_timing(d.ctx, reset=True)
+    vox_it = spec.voxels * spec.iters
+    kinds = launch_kinds(spec, tim, args.steps, Y * Z * X)
+    out = {
+        "metric": "voxel-iterations/s",
+        "value": vox_it / (ms_step / 1e3),
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{spec.name}: {spec.n_views} views, {Y} planes of {Z}x{X}, {spec.psf_k}x{spec.psf_k} "
+                         f"Gaussian PSFs (sx={spec.psf_sigma[0]}, sz={spec.psf_sigma[1]}, view 1 rotated 90 deg), "
+                         f"u16 Poisson observations of blob nuclei ({nd} rendered planes repeated along the plane "
+                         f"axis), {spec.iters} iterations, {spec.update}, {spec.boundary} boundary, "
+                         "device-resident"),
+            "voxels": spec.voxels, "iterations": spec.iters, "views": spec.n_views,
+            "psf": spec.psf_k, "update": spec.update, "parallelism": "single GPU",
+        },
+        "kernels": kinds,
+        "roofline": roofline(spec, kinds),
+        "paper_context": PAPER_CONTEXT.get(spec.name),
+    }
+    del ws, runs
+    torch.cuda.empty_cache()
+    if args.disk:
+        ddir = tempfile.mkdtemp(dir=args.disk, prefix="mvd_vol2048.")
+        try:
+            paths = [os.path.join(ddir, f"view{v}.u16") for v in range(spec.n_views)]
+            log(f"writing the stacks to {ddir}")
+            t0 = time.perf_counter()
+            for p, o in zip(paths, obs):
+                write_stack(p, o)
+            log(f"wrote {2 * sum(o.numel() for o in obs) / 1e9:.1f} GB in {time.perf_counter() - t0:.1f} s")
+            est_path = os.path.join(ddir, "estimate.f32")
+            run = api.make_run(Y, spec.iters, update=spec.update, boundary=spec.boundary, obs_dtype="u16",
+                               layout="stack_zyx", tune=True)
+            nb = api.mvd_stream_workspace_bytes(d.ctx, run, args.batch, True)
+            ws2 = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+            run.workspace = (ws2.data_ptr() + 255) // 256 * 256
+            run.workspace_bytes = nb
+            fds = [os.open(p, os.O_RDONLY) for p in paths]
+            efd = os.open(est_path, os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o644)
+            try:
+                log(f"disk-to-disk run: batches of {args.batch} planes, {args.io_threads} I/O threads")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = api.mvd_deconvolve_files(d.ctx, fds, efd, run, args.batch, io_threads=args.io_threads,
+                                              sync=True, drop_cache=True, stream=stream)
+                wall = time.perf_counter() - t0
+                # a few planes of the file against the device-resident result
+                diff = 0.0
+                for y in (0, Y // 2, Y - 1):
+                    got = np.fromfile(est_path, dtype=np.float32, count=Z * X, offset=y * Z * X * 4)
+                    ref = est[y].cpu().numpy().ravel()
+                    diff = max(diff, float(np.abs(got - ref).max() / np.abs(ref).max()))
+            finally:
+                for fd in fds + [efd]:
+                    os.close(fd)
+            out["disk"] = {
+                "value": vox_it / wall, "unit": "voxel-iterations/s", "seconds": wall,
+                "workload": (f"the same run disk to disk: stacks read from raw uint16 files, estimate written as "
+                             f"raw float32 planes, batches of {args.batch} planes, 3 page-locked batches per "
+                             f"direction, {args.io_threads} I/O threads, page cache dropped behind every read and "
+                             "write, estimate file fdatasync'ed"),
+                "read_s": st["read_s"], "write_s": st["write_s"], "wait_for_reads_s": st["wait_s"],
+                "bytes_read": st["bytes_read"], "bytes_written": st["bytes_written"],
+                "read_gbs": st["bytes_read"] / st["read_s"] / 1e9 if st["read_s"] else None,
+                "write_gbs": st["bytes_written"] / st["write_s"] / 1e9 if st["write_s"] else None,
+                "max_rel_diff_vs_device_resident": diff,
+                "paper_context": PAPER_CONTEXT.get(spec.name),
+            }
+            log(f"disk run: {wall:.1f} s; read {st['read_s']:.1f} s, write {st['write_s']:.1f} s")
+        finally:
+            shutil.rmtree(ddir, ignore_errors=True)
+    d.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -644,9 +834,18 @@ def main():
                     help="per-pixel view weights (seeded uniform [0.5, 1] planes; default workload)")
     ap.add_argument("--no-mix", action="store_true",
                     help="leave out the batched-vs-plain mix record of the default run")
+    ap.add_argument("--disk", default=None, metavar="DIR",
+                    help="vol2048: also run disk to disk with the files in DIR (needs ~70 GB free)")
+    ap.add_argument("--distinct", type=int, default=32,
+                    help="vol2048: rendered planes repeated along the plane axis")
+    ap.add_argument("--io-threads", type=int, default=8, help="vol2048 --disk: threads per read or write")
+    ap.add_argument("--psf", default="gauss", choices=["gauss", "lowrank"],
+                    help="lowrank: deconvolve with non-separable rank-two PSFs (a main lobe and a weaker, "
+                         "wider offset lobe per view; default workload)")
     args = ap.parse_args()
-    global WEIGHT_PLANES
+    global WEIGHT_PLANES, PSF_TERMS
     WEIGHT_PLANES = args.pixel_weights
+    PSF_TERMS = 2 if args.psf == "lowrank" else 1
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -670,6 +869,9 @@ def main():
     if spec.name == "grad256":
         bench_grad(args, spec)
         return
+    if spec.name == "vol2048":
+        bench_vol2048(args, spec)
+        return
     log(f"generating {spec.name}: {spec.n_views} views, {spec.n_planes} planes of {spec.n_z}x{spec.n_x}")
     t0 = time.perf_counter()
     vol = make_volume(spec, truth=False, workers=max(1, min(16, len(os.sched_getaffinity(0)))))
@@ -685,8 +887,12 @@ def main():
     Y, Z, X = spec.n_planes, spec.n_z, spec.n_x
     layout = "stack_zyx"
     d = api.Deconvolver(spec.n_views, Z, X, 0)
-    for v, p in enumerate(vol["psfs"]):
+    psfs = vol["psfs"] if args.psf == "gauss" else lowrank_psfs(spec)
+    for v, p in enumerate(psfs):
         d.set_psf(v, p)
+    if args.psf == "lowrank":
+        forms = [api.mvd_psf_info(d.ctx, v) for v in range(spec.n_views)]
+        log(f"PSF terms per view (PSF, back-projector): {forms}")
     est = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
     obs_dtype = "u16" if spec.obs_dtype == "u16" else "f32"
 
@@ -740,7 +946,8 @@ def main():
     ms_plain = (time.perf_counter() - t1) * 1e3 / args.steps
 
     kinds = launch_kinds(spec, tim, args.steps, Y * Z * X, general=args.force_2d)
-    roof = roofline(spec, kinds, general=args.force_2d, variant=args.normalize or args.pixel_weights)
+    roof = roofline(spec, kinds, general=args.force_2d,
+                    variant=args.normalize or args.pixel_weights or args.psf != "gauss")
 
     it_ms = sum(kinds[k]["avg_ms"] * kinds[k]["launches"] for k in kinds) / args.steps
     out = {
@@ -762,6 +969,8 @@ def main():
                          f"sz={spec.psf_sigma[1]}, view 1 rotated 90 deg), {spec.obs_dtype} Poisson "
                          f"observations of blob nuclei, {spec.iters} iterations, {spec.update}, "
                          f"{spec.boundary} boundary"
+                         + (", deconvolved with non-separable rank-two PSFs (main lobe + 0.3 x wider offset "
+                            "lobe)" if args.psf == "lowrank" else "")
                          + (", general KxK passes forced (no rank-one split)" if args.force_2d else "")
                          + (", EM-normalised back-projection" if args.normalize else "")
                          + (", per-pixel view weights" if args.pixel_weights else "")),
@@ -776,11 +985,11 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(spec, vol, spec.iters, normalize=args.normalize)
+        out["cpu_baseline"] = cpu_baseline(spec, dict(vol, psfs=psfs), spec.iters, normalize=args.normalize)
     d.close()
     del obs, est, ws, runs, wplanes
     torch.cuda.empty_cache()
-    plain = not (args.force_2d or args.normalize or args.pixel_weights or args.update)
+    plain = not (args.force_2d or args.normalize or args.pixel_weights or args.update or args.psf != "gauss")
     if spec.name == "vol512" and plain and not args.no_mix:
         out["mix"] = mix_record(args, cpu=not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)

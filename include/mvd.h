@@ -60,7 +60,8 @@ typedef enum {
   MVD_ERR_DEVICE = -4,      /* no usable GPU / host-only context */
   MVD_ERR_LAUNCH = -5,      /* HIP launch or runtime failure */
   MVD_ERR_UNSUPPORTED = -6, /* valid but not supported combination */
-  MVD_ERR_ALLOC = -7        /* small internal allocation failed */
+  MVD_ERR_ALLOC = -7,       /* small internal allocation failed */
+  MVD_ERR_IO = -8           /* a file read or write failed (disk-to-disk form) */
 } mvd_status;
 
 typedef enum { MVD_U16 = 1, MVD_F32 = 2 } mvd_dtype;
@@ -277,6 +278,59 @@ mvd_status mvd_stream_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, in
  * MVD_ERR_LAUNCH, MVD_ERR_ALLOC (streams or events). */
 mvd_status mvd_deconvolve_stream(mvd_ctx *ctx, const void *const *obs, float *est,
                                  const mvd_run *run, int batch_planes, void *stream);
+
+/* ---- disk-to-disk form ------------------------------------------------------
+ * The streamed run with the stacks read from files and the estimate written to
+ * a file (Supplementary Note 2 §3, Algorithm 1: planes are loaded from disk into
+ * main memory, copied to the GPU, deconvolved and saved back, with the disk
+ * traffic of some planes hidden behind the iterations of others).  Here a
+ * reader thread fills `host_slots` page-locked input batches, the caller's
+ * thread enqueues copies and iterations exactly as mvd_deconvolve_stream does,
+ * and a writer thread drains `host_slots` page-locked output batches to the
+ * estimate file; each read or write is split over `io_threads` threads.
+ * Results equal those of mvd_deconvolve_stream (and of mvd_deconvolve_planes)
+ * bitwise. */
+#define MVD_FILES_SYNC 0x1        /* fdatasync the estimate file before returning */
+#define MVD_FILES_DROP_CACHE 0x2  /* after each read and each (flushed) write, drop the
+                                     file range from the page cache (posix_fadvise), so
+                                     the run is timed against the disk, not the cache */
+typedef struct {
+  uint32_t struct_size;           /* sizeof(mvd_files) */
+  uint32_t flags;                 /* MVD_FILES_* */
+  int32_t obs_fd[MVD_MAX_VIEWS];  /* per view: descriptor of a regular file open for reading */
+  int64_t obs_offset[MVD_MAX_VIEWS]; /* byte offset of view v's stack [Z][Y][X] of run->obs_dtype
+                                        (native byte order, no padding) in its file */
+  int32_t est_fd;                 /* regular file open for writing */
+  int64_t est_offset;             /* byte offset of ψ^T, float32 planes [Y][Z][X] (the file
+                                     grows as needed; other bytes are left alone) */
+  int32_t host_slots;             /* page-locked batches on each side: 0 → 3 (the paper's
+                                     stream count), else 2..8 */
+  int32_t io_threads;             /* threads per batch read or write: 0 → 4, else 1..64 */
+  /* out, filled on MVD_OK: */
+  double seconds[4];              /* reader busy, writer busy (with SYNC: incl. fdatasync),
+                                     caller's thread waiting for reads, wall time of the call */
+  int64_t bytes[2];               /* bytes read, bytes written */
+} mvd_files;
+
+/* Disk-to-disk run.
+ *   io: the files (see mvd_files); the library reads obs with pread and writes
+ *       the estimate with pwrite, and never closes the descriptors.
+ *   run: as for mvd_deconvolve_stream, except run->init: MVD_INIT_MEAN or
+ *        MVD_INIT_CONST (MVD_INIT_GIVEN has no source here: MVD_ERR_ARG);
+ *        run->workspace: device memory of mvd_stream_workspace_bytes(ctx, run,
+ *        batch_planes, 1) bytes.
+ *   batch_planes: planes per batch, ≥ 1.
+ * Synchronous: returns when every plane has been written (and `stream`, on
+ * which the iterations run, has completed).  Page-locked host batches
+ * (host_slots × (V input + 1 output) batches) are allocated on first use and
+ * kept by the context, which frees them in mvd_destroy.
+ * Errors: MVD_ERR_ARG (bad descriptor, not a regular file, a file shorter than
+ * its stack, bad offsets or counts; checked before any device work),
+ * MVD_ERR_STATE, MVD_ERR_DEVICE, MVD_ERR_WORKSPACE, MVD_ERR_ALLOC (host
+ * batches, threads, streams or events), MVD_ERR_IO (a read or write failed or
+ * came up short: the estimate file is then incomplete), MVD_ERR_LAUNCH. */
+mvd_status mvd_deconvolve_files(mvd_ctx *ctx, mvd_files *io, const mvd_run *run, int batch_planes,
+                                void *stream);
 
 /* Launch timings of runs made with MVD_FLAG_TIMING since the last reset:
  * summed HIP-event durations (ms) and launch counts per kind.  Kinds: 0 forward

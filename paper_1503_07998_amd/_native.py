@@ -20,6 +20,7 @@ MVD_ERR_DEVICE = -4
 MVD_ERR_LAUNCH = -5
 MVD_ERR_UNSUPPORTED = -6
 MVD_ERR_ALLOC = -7
+MVD_ERR_IO = -8
 
 MVD_U16, MVD_F32 = 1, 2
 MVD_STACK_ZYX, MVD_PLANES_YZX = 1, 2
@@ -75,6 +76,26 @@ class MvdItem(ctypes.Structure):
 MVD_BATCH_TUNE = 0x1
 MVD_BATCH_GRAPH = 0x2
 
+MVD_FILES_SYNC = 0x1
+MVD_FILES_DROP_CACHE = 0x2
+
+
+class MvdFiles(ctypes.Structure):
+    """Mirror of ``mvd_files``."""
+
+    _fields_ = [
+        ("struct_size", c_uint32),
+        ("flags", c_uint32),
+        ("obs_fd", c_int32 * MVD_MAX_VIEWS),
+        ("obs_offset", ctypes.c_int64 * MVD_MAX_VIEWS),
+        ("est_fd", c_int32),
+        ("est_offset", ctypes.c_int64),
+        ("host_slots", c_int32),
+        ("io_threads", c_int32),
+        ("seconds", ctypes.c_double * 4),
+        ("bytes", ctypes.c_int64 * 2),
+    ]
+
 
 class MvdError(RuntimeError):
     def __init__(self, status: int, message: str):
@@ -108,6 +129,7 @@ SIGNATURES = {
     "mvd_batch_run": (c_int, [POINTER(MvdItem), c_int, c_void_p]),
     "mvd_stream_workspace_bytes": (c_int, [c_void_p, POINTER(MvdRun), c_int, c_int, POINTER(c_size_t)]),
     "mvd_deconvolve_stream": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), c_int, c_void_p]),
+    "mvd_deconvolve_files": (c_int, [c_void_p, POINTER(MvdFiles), POINTER(MvdRun), c_int, c_void_p]),
     "mvd_last_error": (ctypes.c_char_p, [c_void_p]),
 }
 

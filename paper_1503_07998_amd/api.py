@@ -195,6 +195,29 @@ def mvd_deconvolve_stream(ctx, obs, est, run, batch_planes: int, stream=None) ->
                                           _stream_handle(stream)), ctx)
 
 
+def mvd_deconvolve_files(ctx, obs_fds, est_fd, run, batch_planes: int, *, obs_offsets=None, est_offset=0,
+                         host_slots=0, io_threads=0, sync=False, drop_cache=False, stream=None) -> dict:
+    """Disk-to-disk run: camera-ordered stacks read from the open descriptors
+    ``obs_fds`` (at ``obs_offsets``), ψ^T written as float32 planes to ``est_fd``
+    at ``est_offset``; ``run.workspace`` is device memory of
+    ``mvd_stream_workspace_bytes(ctx, run, batch_planes, True)`` bytes.  Returns
+    the call's timings (s) and byte counts."""
+    io = N.MvdFiles()
+    io.struct_size = ctypes.sizeof(N.MvdFiles)
+    io.flags = (N.MVD_FILES_SYNC if sync else 0) | (N.MVD_FILES_DROP_CACHE if drop_cache else 0)
+    for v, fd in enumerate(obs_fds):
+        io.obs_fd[v] = int(fd)
+        io.obs_offset[v] = int(obs_offsets[v]) if obs_offsets is not None else 0
+    io.est_fd = int(est_fd)
+    io.est_offset = int(est_offset)
+    io.host_slots = int(host_slots)
+    io.io_threads = int(io_threads)
+    N.check(N.lib().mvd_deconvolve_files(ctx, ctypes.byref(io), ctypes.byref(run), int(batch_planes),
+                                         _stream_handle(stream)), ctx)
+    return {"read_s": io.seconds[0], "write_s": io.seconds[1], "wait_s": io.seconds[2], "wall_s": io.seconds[3],
+            "bytes_read": int(io.bytes[0]), "bytes_written": int(io.bytes[1])}
+
+
 def mvd_backward_workspace_bytes(ctx, run) -> int:
     n = c_size_t()
     N.check(N.lib().mvd_backward_workspace_bytes(ctx, ctypes.byref(run), ctypes.byref(n)), ctx)

@@ -5,9 +5,16 @@
 
 #include <hip/hip_runtime.h>
 
+#include <fcntl.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <atomic>
+#include <cerrno>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -15,6 +22,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mvd_internal.hpp"
@@ -203,6 +211,9 @@ struct mvd_ctx {
   // streamed runs: copy-in and copy-out streams and their events
   hipStream_t h2d = nullptr, d2h = nullptr;
   hipEvent_t sev[7] = {};        // start, in[2], done[2], out[2]
+  // disk-to-disk runs: page-locked host batches, kept for later calls
+  void *fhost = nullptr;
+  size_t fhost_bytes = 0;
 };
 
 namespace {
@@ -1289,71 +1300,363 @@ hipError_t stream_resources(mvd_ctx *c) {
 //                   out), copy V observation batches (and ψ^0), record in[k]
 //   compute (s):    wait in[k] (and out[k] for a host estimate), run, record done[k]
 //   copy-out (d2h): wait done[k], copy ψ^T of the batch to the host, record out[k]
-hipError_t enqueue_stream(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, int batch,
-                          bool est_host, hipStream_t s) {
-  const StreamLayout S = stream_layout_of(c, r, batch, est_host);
-  const int Y = r->n_planes, Z = c->Z, X = c->X;
-  const size_t es = r->obs_dtype == MVD_U16 ? 2 : 4;
-  const size_t plane = (size_t)Z * X;
-  char *ws = static_cast<char *>(r->workspace);
-  hipEvent_t start = c->sev[0], *in = c->sev + 1, *done = c->sev + 3, *out = c->sev + 5;
-  hipError_t e = hipEventRecord(start, s);
-  if (e == hipSuccess) e = hipStreamWaitEvent(c->h2d, start, 0);
-  if (e == hipSuccess && est_host) e = hipStreamWaitEvent(c->d2h, start, 0);
-  const int nb = (Y + S.ys - 1) / S.ys;
-  std::vector<const void *> slab(c->nv);
-  Tune tn = tune();
-  auto batch_run = [&](int ny, char *run_ws) {
+// The streamed form feeds it batches of the caller's stacks; the disk-to-disk
+// form feeds it page-locked batches read from files.
+struct StreamPipe {
+  mvd_ctx *c;
+  const mvd_run *r;
+  StreamLayout S;
+  bool est_host;
+  hipStream_t s;
+  Tune tn;
+  std::vector<const void *> slab;
+  hipEvent_t start, *in, *done, *out;
+
+  StreamPipe(mvd_ctx *c_, const mvd_run *r_, int batch, bool est_host_, hipStream_t s_)
+      : c(c_), r(r_), S(stream_layout_of(c_, r_, batch, est_host_)), est_host(est_host_), s(s_), tn(tune()),
+        slab(c_->nv), start(c_->sev[0]), in(c_->sev + 1), done(c_->sev + 3), out(c_->sev + 5) {}
+
+  int batches() const { return (r->n_planes + S.ys - 1) / S.ys; }
+
+  hipError_t begin() {
+    hipError_t e = hipEventRecord(start, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->h2d, start, 0);
+    if (e == hipSuccess && est_host) e = hipStreamWaitEvent(c->d2h, start, 0);
+    return e;
+  }
+
+  mvd_run batch_run(int ny) const {
     mvd_run sub = *r;
     sub.n_planes = ny;
     sub.flags &= ~MVD_FLAG_TUNE;
-    sub.workspace = run_ws;
+    sub.workspace = static_cast<char *>(r->workspace) + S.run_off;
     sub.workspace_bytes = S.run_bytes;
     return sub;
-  };
-  for (int b = 0; b < nb && e == hipSuccess; ++b) {
-    const int k = b % S.slots, y0 = b * S.ys, ny = std::min(S.ys, Y - y0);
-    char *slot = ws + (size_t)k * S.slot;
-    float *est_b = est_host ? reinterpret_cast<float *>(slot + (size_t)c->nv * S.obs_bytes) : est + (size_t)y0 * plane;
+  }
+
+  // Batch b: src[v] holds its rows as Z slices of ny·X elements, `pitch` bytes
+  // apart; est_b_io is the batch's ψ (host for a host estimate, else device).
+  hipError_t batch(int b, const void *const *src, size_t pitch, float *est_b_io) {
+    const int Z = c->Z, X = c->X, y0 = b * S.ys, ny = std::min(S.ys, r->n_planes - y0), k = b % S.slots;
+    const size_t es = r->obs_dtype == MVD_U16 ? 2 : 4;
+    const size_t plane = (size_t)Z * X;
+    char *slot = static_cast<char *>(r->workspace) + (size_t)k * S.slot;
+    float *est_b = est_host ? reinterpret_cast<float *>(slot + (size_t)c->nv * S.obs_bytes) : est_b_io;
+    hipError_t e = hipSuccess;
     if (b >= S.slots) {
       e = hipStreamWaitEvent(c->h2d, done[k], 0);
       if (e == hipSuccess && est_host) e = hipStreamWaitEvent(c->h2d, out[k], 0);
     }
     for (int v = 0; v < c->nv && e == hipSuccess; ++v) {
       char *dst = slot + (size_t)v * S.obs_bytes;
-      const char *src = static_cast<const char *>(obs[v]) + (size_t)y0 * X * es;
       // rows y0..y0+ny of every slice z: a 2D copy of Z rows of ny·X elements
-      e = hipMemcpy2DAsync(dst, (size_t)ny * X * es, src, (size_t)Y * X * es, (size_t)ny * X * es, Z,
-                           hipMemcpyDefault, c->h2d);
+      e = hipMemcpy2DAsync(dst, (size_t)ny * X * es, src[v], pitch, (size_t)ny * X * es, Z, hipMemcpyDefault,
+                           c->h2d);
       slab[v] = dst;
     }
     if (e == hipSuccess && est_host && r->init == MVD_INIT_GIVEN)
-      e = hipMemcpyAsync(est_b, est + (size_t)y0 * plane, (size_t)ny * plane * sizeof(float), hipMemcpyDefault,
-                         c->h2d);
+      e = hipMemcpyAsync(est_b, est_b_io, (size_t)ny * plane * sizeof(float), hipMemcpyDefault, c->h2d);
     if (e == hipSuccess) e = hipEventRecord(in[k], c->h2d);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, in[k], 0);
     if (e == hipSuccess && est_host && b >= S.slots) e = hipStreamWaitEvent(s, out[k], 0);
     // launch shapes timed on the first batch (full-size batches share its shape)
     if (e == hipSuccess && b == 0 && (r->flags & MVD_FLAG_TUNE) && r->init != MVD_INIT_GIVEN) {
-      const mvd_run sub = batch_run(ny, ws + S.run_off);
+      const mvd_run sub = batch_run(ny);
       e = autotune(c, slab.data(), est_b, &sub, s, &tn);
     }
     if (e == hipSuccess) {
-      const mvd_run sub = batch_run(ny, ws + S.run_off);
+      const mvd_run sub = batch_run(ny);
       e = enqueue_run(c, slab.data(), est_b, &sub, s, tn);
     }
     if (e == hipSuccess) e = hipEventRecord(done[k], s);
     if (e == hipSuccess && est_host) {
       e = hipStreamWaitEvent(c->d2h, done[k], 0);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(est + (size_t)y0 * plane, est_b, (size_t)ny * plane * sizeof(float), hipMemcpyDefault,
-                           c->d2h);
+        e = hipMemcpyAsync(est_b_io, est_b, (size_t)ny * plane * sizeof(float), hipMemcpyDefault, c->d2h);
       if (e == hipSuccess) e = hipEventRecord(out[k], c->d2h);
     }
+    return e;
   }
+
   // `s` completes only after the last copies
-  for (int k = 0; k < S.slots && e == hipSuccess && est_host && nb > 0; ++k) e = hipStreamWaitEvent(s, out[k], 0);
+  hipError_t end() {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < S.slots && e == hipSuccess && est_host && batches() > 0; ++k)
+      e = hipStreamWaitEvent(s, out[k], 0);
+    return e;
+  }
+};
+
+hipError_t enqueue_stream(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, int batch,
+                          bool est_host, hipStream_t s) {
+  StreamPipe p(c, r, batch, est_host, s);
+  const size_t es = r->obs_dtype == MVD_U16 ? 2 : 4;
+  const size_t plane = (size_t)c->Z * c->X, row = (size_t)c->X * es;
+  std::vector<const void *> src(c->nv);
+  hipError_t e = p.begin();
+  for (int b = 0; b < p.batches() && e == hipSuccess; ++b) {
+    const int y0 = b * p.S.ys;
+    for (int v = 0; v < c->nv; ++v) src[v] = static_cast<const char *>(obs[v]) + (size_t)y0 * row;
+    e = p.batch(b, src.data(), (size_t)r->n_planes * row, est + (size_t)y0 * plane);
+  }
+  if (e == hipSuccess) e = p.end();
   return e;
+}
+
+// ---- disk-to-disk runs ------------------------------------------------------
+// Three actors share a batch counter each: the reader thread (`read`: batches
+// in page-locked input slots), the caller's thread (`issued`: batches whose
+// copies and iterations are enqueued, with an event per host slot recorded
+// after the batch's copy-in and one after its copy-out) and the writer thread
+// (`written`).  Host slot k = b mod H serves batch b; the reader refills an
+// input slot once the copy-in event of the batch before has completed, and the
+// caller reuses an output slot once the writer has written it.
+struct FilePipe {
+  std::mutex mu;
+  std::condition_variable cv;
+  int read = 0, issued = 0, written = 0;
+  bool failed = false;
+  mvd_status st = MVD_OK;
+  std::string msg;
+  double t_read = 0, t_write = 0, t_wait = 0;
+
+  void fail_with(mvd_status s, const std::string &m) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!failed) {
+      failed = true;
+      st = s;
+      msg = m;
+    }
+    cv.notify_all();
+  }
+  // wait until pred() or a failure; false on failure
+  template <class P>
+  bool wait(P pred) {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [&] { return failed || pred(); });
+    return !failed;
+  }
+  void bump(int &counter, int value) {
+    std::lock_guard<std::mutex> lk(mu);
+    counter = value;
+    cv.notify_all();
+  }
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// One piece of a batch read or write.
+struct IoPiece {
+  int fd;
+  int64_t off;
+  char *buf;
+  size_t len;
+};
+
+// Runs the pieces on `threads` threads (pread / pwrite until each piece is
+// done); with `drop`, flushes written ranges and drops every range from the
+// page cache.  Returns an empty string or the first error.
+std::string run_pieces(const std::vector<IoPiece> &pieces, int threads, bool write, bool drop) {
+  std::atomic<size_t> next{0};
+  std::mutex emu;
+  std::string err;
+  auto work = [&] {
+    for (;;) {
+      const size_t i = next.fetch_add(1);
+      if (i >= pieces.size()) return;
+      const IoPiece &p = pieces[i];
+      size_t done = 0;
+      while (done < p.len) {
+        const ssize_t n = write ? pwrite(p.fd, p.buf + done, p.len - done, (off_t)(p.off + done))
+                                : pread(p.fd, p.buf + done, p.len - done, (off_t)(p.off + done));
+        if (n < 0 && errno == EINTR) continue;
+        if (n <= 0) {
+          char m[160];
+          snprintf(m, sizeof m, "%s of %zu bytes at offset %lld: %s", write ? "pwrite" : "pread", p.len - done,
+                   (long long)(p.off + done), n == 0 ? "end of file" : strerror(errno));
+          std::lock_guard<std::mutex> lk(emu);
+          if (err.empty()) err = m;
+          return;
+        }
+        done += (size_t)n;
+      }
+      if (drop) {
+        if (write) (void)sync_file_range(p.fd, p.off, (off_t)p.len,
+                                         SYNC_FILE_RANGE_WAIT_BEFORE | SYNC_FILE_RANGE_WRITE |
+                                             SYNC_FILE_RANGE_WAIT_AFTER);
+        (void)posix_fadvise(p.fd, p.off, (off_t)p.len, POSIX_FADV_DONTNEED);
+      }
+    }
+  };
+  const int T = (int)std::min<size_t>((size_t)threads, pieces.size());
+  std::vector<std::thread> team;
+  try {
+    for (int t = 1; t < T; ++t) team.emplace_back(work);
+  } catch (...) {
+    // fewer threads: the caller's thread still drains the list
+  }
+  work();
+  for (auto &t : team) t.join();
+  return err;
+}
+
+// Cuts [off, off + len) of one file into pieces of about `chunk` bytes.
+void add_pieces(std::vector<IoPiece> &out, int fd, int64_t off, char *buf, size_t len, size_t chunk) {
+  for (size_t o = 0; o < len; o += chunk) out.push_back(IoPiece{fd, off + (int64_t)o, buf + o, std::min(chunk, len - o)});
+}
+
+constexpr size_t kIoChunk = 8u << 20;
+
+mvd_status run_files(mvd_ctx *c, mvd_files *io, const mvd_run *r, int batch, hipStream_t s) {
+  const double t0 = now_s();
+  const int H = io->host_slots ? io->host_slots : 3;
+  const int T = io->io_threads ? io->io_threads : 4;
+  const bool drop = io->flags & MVD_FILES_DROP_CACHE;
+  const int V = c->nv, Z = c->Z, X = c->X, Y = r->n_planes;
+  const size_t es = r->obs_dtype == MVD_U16 ? 2 : 4;
+  const size_t plane = (size_t)Z * X;
+  StreamPipe p(c, r, batch, true, s);
+  const int ys = p.S.ys, nb = p.batches();
+  // page-locked batches: H input slots of V compact [Z][ys][X] stacks, then H
+  // output slots of [ys][Z][X] float32
+  const size_t in_view = align_up((size_t)ys * plane * es), in_slot = (size_t)V * in_view;
+  const size_t out_slot = align_up((size_t)ys * plane * sizeof(float));
+  const size_t need = (size_t)H * (in_slot + out_slot);
+  if (c->fhost_bytes < need) {
+    if (c->fhost) (void)hipHostFree(c->fhost);
+    c->fhost = nullptr;
+    c->fhost_bytes = 0;
+    if (hipHostMalloc(&c->fhost, need, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      c->fhost = nullptr;
+      return fail(c, MVD_ERR_ALLOC, "cannot allocate %zu bytes of page-locked host batches", need);
+    }
+    c->fhost_bytes = need;
+  }
+  char *hin = static_cast<char *>(c->fhost), *hout = hin + (size_t)H * in_slot;
+  std::vector<hipEvent_t> copied(H, nullptr), drained(H, nullptr);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < H && e == hipSuccess; ++k) {
+    e = hipEventCreateWithFlags(&copied[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&drained[k], hipEventDisableTiming);
+  }
+  auto destroy_events = [&] {
+    for (int k = 0; k < H; ++k) {
+      if (copied[k]) (void)hipEventDestroy(copied[k]);
+      if (drained[k]) (void)hipEventDestroy(drained[k]);
+    }
+  };
+  if (e != hipSuccess) {
+    destroy_events();
+    return fail(c, MVD_ERR_ALLOC, "cannot create events: %s", hipGetErrorString(e));
+  }
+  FilePipe fp;
+  int64_t nread = 0, nwritten = 0;
+  auto reader = [&] {
+    for (int b = 0; b < nb; ++b) {
+      const int k = b % H, y0 = b * ys, ny = std::min(ys, Y - y0);
+      if (b >= H) {
+        if (!fp.wait([&] { return fp.issued > b - H; })) return;
+        if (hipEventSynchronize(copied[k]) != hipSuccess) {
+          fp.fail_with(MVD_ERR_LAUNCH, "copy-in event failed");
+          return;
+        }
+      }
+      const double ta = now_s();
+      std::vector<IoPiece> pieces;
+      for (int v = 0; v < V; ++v) {
+        char *dst = hin + (size_t)k * in_slot + (size_t)v * in_view;
+        const size_t run = (size_t)ny * X * es;   // bytes of one slice's rows y0..y0+ny
+        if (ny == Y) {
+          add_pieces(pieces, io->obs_fd[v], io->obs_offset[v], dst, (size_t)Z * run, kIoChunk);
+        } else {
+          for (int z = 0; z < Z; ++z)
+            add_pieces(pieces, io->obs_fd[v], io->obs_offset[v] + (int64_t)(((size_t)z * Y + y0) * X * es),
+                       dst + (size_t)z * run, run, kIoChunk);
+        }
+      }
+      const std::string err = run_pieces(pieces, T, false, drop);
+      if (!err.empty()) {
+        fp.fail_with(MVD_ERR_IO, "reading batch " + std::to_string(b) + ": " + err);
+        return;
+      }
+      for (const auto &q : pieces) nread += (int64_t)q.len;
+      fp.t_read += now_s() - ta;
+      fp.bump(fp.read, b + 1);
+    }
+  };
+  auto writer = [&] {
+    for (int b = 0; b < nb; ++b) {
+      const int k = b % H, y0 = b * ys, ny = std::min(ys, Y - y0);
+      if (!fp.wait([&] { return fp.issued > b; })) return;
+      if (hipEventSynchronize(drained[k]) != hipSuccess) {
+        fp.fail_with(MVD_ERR_LAUNCH, "copy-out event failed");
+        return;
+      }
+      const double ta = now_s();
+      std::vector<IoPiece> pieces;
+      add_pieces(pieces, io->est_fd, io->est_offset + (int64_t)((size_t)y0 * plane * sizeof(float)),
+                 hout + (size_t)k * out_slot, (size_t)ny * plane * sizeof(float), kIoChunk);
+      const std::string err = run_pieces(pieces, T, true, drop);
+      if (!err.empty()) {
+        fp.fail_with(MVD_ERR_IO, "writing batch " + std::to_string(b) + ": " + err);
+        return;
+      }
+      nwritten += (int64_t)((size_t)ny * plane * sizeof(float));
+      fp.t_write += now_s() - ta;
+      fp.bump(fp.written, b + 1);
+    }
+    if ((io->flags & MVD_FILES_SYNC) && nb > 0) {
+      const double ta = now_s();
+      if (fdatasync(io->est_fd) != 0) {
+        fp.fail_with(MVD_ERR_IO, std::string("fdatasync: ") + strerror(errno));
+        return;
+      }
+      fp.t_write += now_s() - ta;
+    }
+  };
+  std::thread tr, tw;
+  try {
+    tr = std::thread(reader);
+    tw = std::thread(writer);
+  } catch (...) {
+    fp.fail_with(MVD_ERR_ALLOC, "cannot start the reader and writer threads");
+  }
+  std::vector<const void *> src(V);
+  e = fp.failed ? hipSuccess : p.begin();
+  for (int b = 0; b < nb && e == hipSuccess; ++b) {
+    const int k = b % H, ny = std::min(ys, Y - b * ys);
+    const double ta = now_s();
+    if (!fp.wait([&] { return fp.read > b && (b < H || fp.written > b - H); })) break;
+    fp.t_wait += now_s() - ta;
+    for (int v = 0; v < V; ++v) src[v] = hin + (size_t)k * in_slot + (size_t)v * in_view;
+    e = p.batch(b, src.data(), (size_t)ny * X * es, reinterpret_cast<float *>(hout + (size_t)k * out_slot));
+    if (e == hipSuccess) e = hipEventRecord(copied[k], c->h2d);
+    if (e == hipSuccess) e = hipEventRecord(drained[k], c->d2h);
+    if (e == hipSuccess) fp.bump(fp.issued, b + 1);
+  }
+  if (e == hipSuccess) e = p.end();
+  if (e != hipSuccess) fp.fail_with(MVD_ERR_LAUNCH, std::string("streamed batch failed: ") + hipGetErrorString(e));
+  fp.wait([&] { return fp.written == nb; });
+  if (tr.joinable()) tr.join();
+  if (tw.joinable()) tw.join();
+  // nothing may still use the host batches or the events when the call returns
+  hipError_t es1 = hipStreamSynchronize(s);
+  hipError_t es2 = hipStreamSynchronize(c->h2d);
+  hipError_t es3 = hipStreamSynchronize(c->d2h);
+  destroy_events();
+  if (fp.failed) return fail(c, fp.st, "%s", fp.msg.c_str());
+  if (es1 != hipSuccess || es2 != hipSuccess || es3 != hipSuccess)
+    return fail(c, MVD_ERR_LAUNCH, "stream synchronisation failed");
+  io->seconds[0] = fp.t_read;
+  io->seconds[1] = fp.t_write;
+  io->seconds[2] = fp.t_wait;
+  io->seconds[3] = now_s() - t0;
+  io->bytes[0] = nread;
+  io->bytes[1] = nwritten;
+  return MVD_OK;
 }
 
 // ---- graph capture ----------------------------------------------------------
@@ -1824,6 +2127,7 @@ const char *mvd_status_string(mvd_status s) {
     case MVD_ERR_LAUNCH: return "launch failed";
     case MVD_ERR_UNSUPPORTED: return "unsupported";
     case MVD_ERR_ALLOC: return "allocation failed";
+    case MVD_ERR_IO: return "file read or write failed";
   }
   return "unknown status";
 }
@@ -1892,6 +2196,7 @@ void mvd_destroy(mvd_ctx *ctx) {
       if (e) (void)hipEventDestroy(e);
     if (ctx->h2d) (void)hipStreamDestroy(ctx->h2d);
     if (ctx->d2h) (void)hipStreamDestroy(ctx->d2h);
+    if (ctx->fhost) (void)hipHostFree(ctx->fhost);
   }
   delete ctx;
 }
@@ -2112,6 +2417,55 @@ mvd_status mvd_deconvolve_stream(mvd_ctx *c, const void *const *obs, float *est,
   hipError_t e = enqueue_stream(c, obs, est, r, batch_planes, est_host, (hipStream_t)stream);
   if (e != hipSuccess) return fail(c, MVD_ERR_LAUNCH, "streamed run failed: %s", hipGetErrorString(e));
   return MVD_OK;
+}
+
+mvd_status mvd_deconvolve_files(mvd_ctx *c, mvd_files *io, const mvd_run *r, int batch_planes, void *stream) {
+  if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
+  c->err.clear();
+  if (!io || io->struct_size != sizeof(mvd_files)) return fail(c, MVD_ERR_ARG, "io is NULL or has a wrong struct_size");
+  mvd_status st = check_stream_run(c, r, batch_planes);
+  if (st != MVD_OK) return st;
+  if (r->init == MVD_INIT_GIVEN) return fail(c, MVD_ERR_ARG, "the disk-to-disk form reads no initial estimate");
+  if (io->flags & ~(uint32_t)(MVD_FILES_SYNC | MVD_FILES_DROP_CACHE))
+    return fail(c, MVD_ERR_ARG, "unknown flags 0x%x", io->flags);
+  if (io->host_slots != 0 && (io->host_slots < 2 || io->host_slots > 8))
+    return fail(c, MVD_ERR_ARG, "host_slots %d outside {0} and [2, 8]", io->host_slots);
+  if (io->io_threads < 0 || io->io_threads > 64) return fail(c, MVD_ERR_ARG, "io_threads %d outside [0, 64]", io->io_threads);
+  const size_t es = r->obs_dtype == MVD_U16 ? 2 : 4;
+  const int64_t stack = (int64_t)((size_t)c->Z * r->n_planes * c->X * es);
+  for (int v = 0; v < c->nv; ++v) {
+    struct stat sb;
+    if (io->obs_fd[v] < 0 || fstat(io->obs_fd[v], &sb) != 0)
+      return fail(c, MVD_ERR_ARG, "obs_fd[%d] = %d is not an open descriptor", v, io->obs_fd[v]);
+    if (!S_ISREG(sb.st_mode)) return fail(c, MVD_ERR_ARG, "obs_fd[%d] is not a regular file", v);
+    if (io->obs_offset[v] < 0) return fail(c, MVD_ERR_ARG, "obs_offset[%d] is negative", v);
+    if ((int64_t)sb.st_size < io->obs_offset[v] + stack)
+      return fail(c, MVD_ERR_ARG, "view %d: file of %lld bytes holds no %lld-byte stack at offset %lld", v,
+                  (long long)sb.st_size, (long long)stack, (long long)io->obs_offset[v]);
+    if (fcntl(io->obs_fd[v], F_GETFL) & O_WRONLY) return fail(c, MVD_ERR_ARG, "obs_fd[%d] is write-only", v);
+  }
+  {
+    struct stat sb;
+    if (io->est_fd < 0 || fstat(io->est_fd, &sb) != 0)
+      return fail(c, MVD_ERR_ARG, "est_fd = %d is not an open descriptor", io->est_fd);
+    if (!S_ISREG(sb.st_mode)) return fail(c, MVD_ERR_ARG, "est_fd is not a regular file");
+    if (io->est_offset < 0) return fail(c, MVD_ERR_ARG, "est_offset is negative");
+    const int fl = fcntl(io->est_fd, F_GETFL);
+    if ((fl & O_ACCMODE) == O_RDONLY) return fail(c, MVD_ERR_ARG, "est_fd is not open for writing");
+    if (fl & O_APPEND) return fail(c, MVD_ERR_ARG, "est_fd is in append mode (positioned writes needed)");
+  }
+  if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
+  if (c->device == MVD_DEVICE_NONE) return fail(c, MVD_ERR_DEVICE, "host-only context");
+  if (r->workspace && ((uintptr_t)r->workspace % kAlign))
+    return fail(c, MVD_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+  const StreamLayout S = stream_layout_of(c, r, batch_planes, true);
+  if (!r->workspace || r->workspace_bytes < S.total)
+    return fail(c, MVD_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", S.total,
+                r->workspace ? r->workspace_bytes : (size_t)0);
+  DeviceGuard dg(c->device);
+  if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
+  if (stream_resources(c) != hipSuccess) return fail(c, MVD_ERR_ALLOC, "cannot create copy streams or events");
+  return run_files(c, io, r, batch_planes, (hipStream_t)stream);
 }
 
 // Test hook (mvd_testing.h): the launch geometry the planner picks for

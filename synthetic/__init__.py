@@ -192,6 +192,11 @@ CONFIGS = {
     # are independent, so a slab times the per-plane rate of the full volume).
     "planes2048": VolumeSpec("planes2048", 64, 2048, 2048, 31, (1.5, 6.0), (0, 90),
                              (64 * 2048 * 2048) // (16 ** 3), "u16", 10, "simultaneous", seed=6),
+    # The whole 2048³ size class: 2 views, 2048 planes of 2048×2048, 31×31, uint16.
+    # (Rendering every plane on the host is slow; the benchmark renders a slab
+    # of distinct planes and repeats it along the plane axis on the device.)
+    "vol2048": VolumeSpec("vol2048", 2048, 2048, 2048, 31, (1.5, 6.0), (0, 90),
+                          (2048 ** 3) // (16 ** 3), "u16", 10, "simultaneous", seed=7),
     # Batched mix: three uneven volumes.
     "mix_a": VolumeSpec("mix_a", 200, 256, 384, 21, (1.5, 4.0), (0, 90), 4800, "f32", 10,
                         "sequential", seed=41),

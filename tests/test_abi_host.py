@@ -335,6 +335,99 @@ def test_stream_validation_before_device():
         api.mvd_destroy(ctx)
 
 
+def _files_io(obs_fds, est_fd, **kw):
+    io = N.MvdFiles()
+    io.struct_size = ctypes.sizeof(N.MvdFiles)
+    for v, fd in enumerate(obs_fds):
+        io.obs_fd[v] = fd
+    io.est_fd = est_fd
+    for k, val in kw.items():
+        if k == "obs_offset":
+            for v, o in enumerate(val):
+                io.obs_offset[v] = o
+        else:
+            setattr(io, k, val)
+    return io
+
+
+def test_files_struct_matches_c_layout():
+    """mvd_files: 2 × u32, 8 descriptors, 8 offsets (8-aligned), est descriptor and
+    offset, two counts, 4 doubles, 2 byte counts."""
+    assert ctypes.sizeof(N.MvdFiles) == 8 + 32 + 64 + 8 + 8 + 8 + 32 + 16
+    assert N.MvdFiles.obs_offset.offset == 40 and N.MvdFiles.est_offset.offset == 112
+    assert N.lib().mvd_status_string(N.MVD_ERR_IO) == b"file read or write failed"
+
+
+def test_files_validation_before_device(tmp_path):
+    """Every argument of the disk-to-disk form, the files included, is checked
+    before the device: a host-only context reaches MVD_ERR_DEVICE only with all
+    of them valid."""
+    Y, Z, X = 5, 8, 8
+    ctx = api.mvd_create(2, Z, X, N.MVD_DEVICE_NONE)
+    lib = N.lib()
+    stack = Z * Y * X * 2
+    paths = [tmp_path / f"v{v}.raw" for v in range(2)]
+    for p in paths:
+        p.write_bytes(b"\0" * (64 + stack))
+    short = tmp_path / "short.raw"
+    short.write_bytes(b"\0" * (stack - 2))
+    fds = [os.open(str(p), os.O_RDONLY) for p in paths]
+    sfd = os.open(str(short), os.O_RDONLY)
+    efd = os.open(str(tmp_path / "est.raw"), os.O_RDWR | os.O_CREAT)
+    rfd = os.open(str(tmp_path / "est.raw"), os.O_RDONLY)
+    afd = os.open(str(tmp_path / "est.raw"), os.O_WRONLY | os.O_APPEND)
+    wfd = os.open(str(paths[0]), os.O_WRONLY)
+    dfd = os.open(str(tmp_path), os.O_RDONLY)
+    r = api.make_run(Y, 2, obs_dtype="u16", workspace=256, workspace_bytes=1 << 24)
+
+    def call(io, run=r, batch=2):
+        return lib.mvd_deconvolve_files(ctx, ctypes.byref(io), ctypes.byref(run), batch, None)
+
+    try:
+        assert call(_files_io(fds, efd)) == N.MVD_ERR_STATE                      # PSFs not set
+        for v in range(2):
+            api.mvd_set_psf(ctx, v, np.ones((3, 3)) / 9)
+        good = _files_io(fds, efd, obs_offset=[64, 0])
+        assert call(good) == N.MVD_ERR_DEVICE                                   # host-only context
+        assert lib.mvd_deconvolve_files(ctx, None, ctypes.byref(r), 2, None) == N.MVD_ERR_ARG
+        bad = _files_io(fds, efd)
+        bad.struct_size -= 8
+        assert call(bad) == N.MVD_ERR_ARG
+        assert call(good, batch=0) == N.MVD_ERR_ARG                             # empty batch
+        assert call(good, run=api.make_run(Y, 2, obs_dtype="u16", init="given")) == N.MVD_ERR_ARG
+        assert call(good, run=api.make_run(Y, 2, obs_dtype="u16", layout="planes_yzx")) == N.MVD_ERR_ARG
+        cases = [
+            _files_io([fds[0], sfd], efd),                          # view 1's file too short
+            _files_io(fds, efd, obs_offset=[65, 0]),                # offset past the stack's end
+            _files_io(fds, efd, obs_offset=[-1, 0]),                # negative offset
+            _files_io([fds[0], -1], efd),                           # no descriptor
+            _files_io([fds[0], 1 << 20], efd),                      # closed descriptor
+            _files_io([fds[0], dfd], efd),                          # a directory
+            _files_io([wfd, fds[1]], efd),                          # write-only input
+            _files_io(fds, rfd),                                    # estimate file read-only
+            _files_io(fds, afd),                                    # estimate file in append mode
+            _files_io(fds, dfd),                                    # estimate "file" a directory
+            _files_io(fds, efd, est_offset=-4),
+            _files_io(fds, efd, flags=0x4),                         # unknown flag
+            _files_io(fds, efd, host_slots=1),                      # too few host batches
+            _files_io(fds, efd, host_slots=9),
+            _files_io(fds, efd, io_threads=-1),
+            _files_io(fds, efd, io_threads=65),
+        ]
+        for i, io in enumerate(cases):
+            assert call(io) == N.MVD_ERR_ARG, (i, api.mvd_last_error(ctx))
+        # the same stack as float32 no longer fits the files
+        assert call(good, run=api.make_run(Y, 2, obs_dtype="f32")) == N.MVD_ERR_ARG
+        ok = _files_io(fds, efd, flags=N.MVD_FILES_SYNC | N.MVD_FILES_DROP_CACHE, host_slots=8, io_threads=64)
+        assert call(ok) == N.MVD_ERR_DEVICE
+        # nothing was written on the way
+        assert os.path.getsize(tmp_path / "est.raw") == 0
+    finally:
+        for fd in fds + [sfd, efd, rfd, afd, wfd, dfd]:
+            os.close(fd)
+        api.mvd_destroy(ctx)
+
+
 def test_deconvolver_rejects_mismatched_tensors():
     """Deconvolver.run checks every tensor against the context before any pointer
     reaches the library (CPU tensors here: the checks come first)."""
