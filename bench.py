@@ -77,6 +77,13 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
     k = spec.psf_k
     n = launches_per_iter
     R = PSF_TERMS
+    if kind == "fused":
+        # one launch per iteration: ψ in, every view's φ_v (as given), ψ' out;
+        # the ratio planes stay on chip.  Both passes' 1D convolutions.
+        phi = 2 if spec.obs_dtype == "u16" else 4
+        b = 8 + phi * V
+        f = V * 2 * 2 * (k + k)
+        return vox * b / n, vox * f / n, 0.0, vox * f / n
     if R > 1 and not general:
         # one launch per view and term: every term reads its input (ψ forward,
         # r_v backward), terms after the first read and all but the last write
@@ -96,16 +103,27 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
     return vox * b / n, vox * f / n, vox * f_valu / n, vox * f_mfma / n
 
 
-def kernel_code_hash(path):
-    """sha256 of a C++ source with its comments removed and its whitespace
+def kernel_code_hash(*paths):
+    """sha256 of C++ sources with their comments removed and their whitespace
     collapsed: edits to comments keep it, any change to the code does not."""
     import hashlib
     import re
 
-    text = open(path, encoding="utf-8").read()
-    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", " ", text)
-    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
+    parts = []
+    for path in paths:
+        text = open(path, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        parts.append(" ".join(text.split()))
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()
+
+
+# the pass kernels whose counters the traffic record holds
+PASS_SOURCES = ("k_sep_impl.hpp", "k_fused.hip")
+
+
+def pass_code_hash():
+    return kernel_code_hash(*[os.path.join(ROOT, "paper_1503_07998_amd", "csrc", f) for f in PASS_SOURCES])
 
 
 def measured_traffic(name, kind):
@@ -113,18 +131,17 @@ def measured_traffic(name, kind):
     FETCH_SIZE / WRITE_SIZE runs (scaled by the factors a copy of known size
     gives), or None when the kernel code changed since they were taken."""
     path = os.path.join(ROOT, "profiles", f"sep_passes_{name}_traffic.json")
-    src = os.path.join(ROOT, "paper_1503_07998_amd", "csrc", "k_sep_impl.hpp")
     try:
         rec = json.load(open(path))
-        h = kernel_code_hash(src)
+        h = pass_code_hash()
     except OSError:
         return None
     if rec.get("kernel_code_sha256") != h:
         return None
-    # the instance of the pass (plain or split-view form) that ran most often in
-    # the profiled bench run
-    cands = [(k, v) for k, v in rec["kernels"].items()
-             if f"sep_{kind}_kernel" in k or f"sep_{kind}_split_kernel" in k]
+    # the instance of the pass (plain, split-view or fused form) that ran most
+    # often in the profiled bench run
+    names = ("fused_kernel",) if kind == "fused" else (f"sep_{kind}_kernel", f"sep_{kind}_split_kernel")
+    cands = [(k, v) for k, v in rec["kernels"].items() if any(n in k for n in names)]
     if not cands:
         return None
     k, v = max(cands, key=lambda kv: kv[1].get("trace_calls", 0))
@@ -164,6 +181,8 @@ def roofline(spec, kinds, general=False, variant=False):
         roof["kernel"] = f"{dom} pass (twod_{dom}_kernel, general {spec.psf_k}x{spec.psf_k})"
     elif meas:
         roof["kernel"] = f"{dom} pass ({meas['instance']})"
+    elif dom == "fused":
+        roof["kernel"] = f"fused iteration (fused_kernel, K={spec.psf_k})"
     else:
         roof["kernel"] = f"{dom} pass (sep_{dom} kernels, K={spec.psf_k})"
     roof["floor_ms"] = {k: v * 1e3 for k, v in times.items()}
@@ -174,8 +193,8 @@ def roofline(spec, kinds, general=False, variant=False):
 def launch_kinds(spec, tim, steps, vox, batches=1, general=False):
     """Per-kind launch statistics of ``steps`` timed runs (HIP events)."""
     kinds = {}
-    for kind in ("forward", "backward"):
-        n, ms = tim[kind]
+    for kind in ("forward", "backward", "fused"):
+        n, ms = tim.get(kind, (0, 0.0))
         if n:
             per_iter = n / (steps * spec.iters * batches)
             b, f, fv, fm = step_work_split(spec, kind, vox / batches, per_iter, general)
@@ -839,6 +858,9 @@ def main():
     ap.add_argument("--distinct", type=int, default=32,
                     help="vol2048: rendered planes repeated along the plane axis")
     ap.add_argument("--io-threads", type=int, default=8, help="vol2048 --disk: threads per read or write")
+    ap.add_argument("--psf-k", type=int, default=0, help="PSF side (default workload; 0: the workload's)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="untuned launch shapes (MVD_TUNE overrides apply; default workload)")
     ap.add_argument("--psf", default="gauss", choices=["gauss", "lowrank"],
                     help="lowrank: deconvolve with non-separable rank-two PSFs (a main lobe and a weaker, "
                          "wider offset lobe per view; default workload)")
@@ -863,6 +885,8 @@ def main():
     spec = CONFIGS[args.config]
     if args.update:
         spec.update = args.update
+    if args.psf_k:
+        spec.psf_k = args.psf_k
     if spec.name == "vol1024x4":
         bench_stream(args, spec)
         return
@@ -903,7 +927,8 @@ def main():
 
     def make(timing):
         return api.make_run(Y, spec.iters, update=spec.update, boundary=spec.boundary,
-                            obs_dtype=obs_dtype, layout=layout, timing=timing, tune=not args.force_2d,
+                            obs_dtype=obs_dtype, layout=layout, timing=timing,
+                            tune=not (args.force_2d or args.no_tune),
                             force_2d=args.force_2d, normalize=args.normalize, weight_planes=wplanes)
 
     run = make(False)
@@ -989,7 +1014,8 @@ def main():
     d.close()
     del obs, est, ws, runs, wplanes
     torch.cuda.empty_cache()
-    plain = not (args.force_2d or args.normalize or args.pixel_weights or args.update or args.psf != "gauss")
+    plain = not (args.force_2d or args.normalize or args.pixel_weights or args.update or args.psf != "gauss"
+                 or args.psf_k or args.no_tune)
     if spec.name == "vol512" and plain and not args.no_mix:
         out["mix"] = mix_record(args, cpu=not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)

@@ -111,7 +111,9 @@ typedef enum { MVD_INIT_MEAN = 0, MVD_INIT_GIVEN = 1, MVD_INIT_CONST = 2 } mvd_i
                                     in mvd_backward).  Supplementary Note 1 (the update assumes
                                     unit column sums) */
 #define MVD_FLAG_TUNE 0x8u     /* choose launch shapes (row-segment length, views per launch,
-                                  columns per thread, occupancy) by timing candidates on one
+                                  columns per thread, occupancy; for simultaneous two-view runs
+                                  with rank-one PSFs of at most 31 taps also whether each
+                                  iteration runs as one fused launch) by timing candidates on one
                                   iteration of this run's own data at the first run of a workload
                                   shape; the choice is cached for the process.  That first call
                                   synchronises its stream and overwrites est while it times (so
@@ -336,10 +338,13 @@ mvd_status mvd_deconvolve_files(mvd_ctx *ctx, mvd_files *io, const mvd_run *run,
  * summed HIP-event durations (ms) and launch counts per kind.  Kinds: 0 forward
  * pass (blur + ratio), 1 backward pass (back-projection + update), 2 the rest
  * (reslice/convert, ψ^0), 3 reverse-sweep passes (mvd_backward), 4 tap-gradient
- * correlations.  Events are recorded on the run's stream around each launch;
- * this call waits for the last of them.  reset ≠ 0 clears the record.
+ * correlations, 5 fused iterations (forward and backward passes of both views
+ * in one launch: simultaneous two-view runs with rank-one PSFs of at most 31
+ * taps under the zero boundary, without normalisation or weight planes).
+ * Events are recorded on the run's stream around each launch; this call waits
+ * for the last of them.  reset ≠ 0 clears the record.
  * Errors: MVD_ERR_ARG, MVD_ERR_LAUNCH. */
-#define MVD_TIMING_KINDS 5
+#define MVD_TIMING_KINDS 6
 typedef struct {
   uint32_t struct_size;
   int32_t count[MVD_TIMING_KINDS];

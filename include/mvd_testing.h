@@ -38,6 +38,13 @@ int mvd_internal_sep_plan(const mvd_ctx *ctx, int n_planes, int k, int boundary,
  * MVD_ERR_UNSUPPORTED where the form does not apply. */
 int mvd_internal_split_plan(const mvd_ctx *ctx, int n_planes, int k, int *out);
 
+/* The fused iteration (forward and backward passes of both views in one
+ * launch) for a context of ctx's plane size and kernel bucket kb.  out[8]:
+ * bucket, output columns per strip, strips, halo R, forward output margin,
+ * LDS row pitch, LDS bytes, threads per work-group.  MVD_ERR_UNSUPPORTED
+ * where the bucket has no fused form. */
+int mvd_internal_fused_plan(const mvd_ctx *ctx, int kb, int *out);
+
 /* The matrix-core K×K pass for a kz × kx kernel.  out[3]: column steps, input
  * tile row pitch, LDS bytes. */
 int mvd_internal_mfma_plan(int kz, int kx, int *out);

@@ -64,7 +64,7 @@ class MvdRun(ctypes.Structure):
 class MvdTiming(ctypes.Structure):
     """Mirror of ``mvd_timing``."""
 
-    _fields_ = [("struct_size", c_uint32), ("count", c_int32 * 5), ("ms", ctypes.c_double * 5)]
+    _fields_ = [("struct_size", c_uint32), ("count", c_int32 * 6), ("ms", ctypes.c_double * 6)]
 
 
 class MvdItem(ctypes.Structure):

@@ -148,11 +148,11 @@ def mvd_reslice(ctx, stack, n_planes: int, planes, stream=None) -> None:
 
 
 def mvd_get_timing(ctx, reset: bool = True) -> dict:
-    """Summed launch times (ms) and counts of timed runs: forward, backward, other."""
+    """Summed launch times (ms) and counts of timed runs per launch kind."""
     t = N.MvdTiming()
     t.struct_size = ctypes.sizeof(N.MvdTiming)
     N.check(N.lib().mvd_get_timing(ctx, ctypes.byref(t), 1 if reset else 0), ctx)
-    names = ("forward", "backward", "other", "adjoint", "correlation")
+    names = ("forward", "backward", "other", "adjoint", "correlation", "fused")
     return {n: (int(t.count[i]), float(t.ms[i])) for i, n in enumerate(names)}
 
 

@@ -513,6 +513,8 @@ struct Tune {
   int plane_batch = 0;  // > 0: run this many planes through all iterations at a time
   int pq_window = 0;    // persistent batches: planes per window of a volume's items (0: all)
   int pq_zseg_scale = 0;  // persistent batches: segment length × 2^(v − 2) of the planner's (0: × 2)
+  int fused = 0;        // simultaneous two-view runs: one fused launch per iteration where it applies
+                        // (a candidate of the tuner, which keeps it where it is faster)
   int wide = 0;         // rows of 513–1024 columns as one column per thread in up to
                         // 1024-thread work-groups (one-ring passes): 0 where it applies, 2 never
 };
@@ -546,6 +548,7 @@ Tune parse_tune(const char *e) {
       if (k == "wide") r.wide = v;
       if (k == "pq_window") r.pq_window = v;
       if (k == "pq_zseg_scale") r.pq_zseg_scale = v;
+      if (k == "fused") r.fused = v;
     }
     pos = comma + 1;
   }
@@ -1165,6 +1168,73 @@ int plane_batch(const mvd_run *r, const Tune &tn) {
 // independent, so the run may go batch by batch of planes, each batch through
 // all T iterations (a batch that fits the last-level cache keeps its working
 // set there); the results do not depend on the batch size.
+// ---- fused iterations --------------------------------------------------------
+// LDS row pitch of the fused iteration's row-group buffers: the widest ring
+// (the strip ± (RA + R), RA = R rounded up to whole 8-column items) plus the
+// row pass's read-ahead, ≡ 4 (mod 8) floats.
+int fused_pitch(int kb) {
+  const int R = (kb - 1) / 2, RA = (R + 7) / 8 * 8;
+  int pitch = round_up(kFusedStrip + 2 * RA + 2 * R + 4, 4);
+  if (pitch % 8 == 0) pitch += 4;
+  return pitch;
+}
+
+// One launch per iteration (k_fused.hip) for two views updated simultaneously
+// under the zero boundary with rank-one PSFs and back-projectors of at most 31
+// taps, no normalisation or weight planes, rows of whole 8-column items and
+// 16-byte aligned planes and observations.  Returns the common bucket, or 0.
+int fused_bucket_of(const RunState &st, const ObsRef &ob) {
+  const mvd_ctx *c = st.c;
+  if (st.tn->fused == 0 || c->nv != 2 || st.boundary != MVD_BOUNDARY_ZERO || st.force2d || st.normalize || st.wpl)
+    return 0;
+  if (st.g.X % 8 != 0) return 0;
+  const long unit = ob.u16 ? 8 : 4;
+  if (ob.sy % unit != 0 || ob.sz % unit != 0) return 0;
+  int k = 1;
+  for (int v = 0; v < 2; ++v) {
+    const ViewPsf &w = c->views[v];
+    if (!w.sep_p || !w.sep_x || !w.lpz.empty() || !w.lxz.empty()) return 0;
+    k = std::max({k, (int)w.pz.size(), (int)w.px.size(), (int)w.xz.size(), (int)w.xx.size()});
+    if (!aligned16(ob.p[v])) return 0;
+  }
+  const int kb = sep_bucket(k);
+  if (kb < 0 || kb > 31) return 0;
+  if (fused_lds_bytes(kb, fused_pitch(kb)) > kLdsLimit) return 0;
+  return kb;
+}
+
+hipError_t fused_iteration(const RunState &st, const ObsRef &ob, int kb, const float *psi_in, float *psi_out) {
+  const mvd_ctx *c = st.c;
+  FusedArgs fa{};
+  SepPassArgs &a = fa.f;
+  const int R = (kb - 1) / 2;
+  a.g = st.g;
+  a.boundary = MVD_BOUNDARY_ZERO;
+  a.nviews = 2;
+  a.x_out = kFusedStrip;
+  a.nstrip = (st.g.X + kFusedStrip - 1) / kFusedStrip;
+  a.halo = R;
+  a.ncols = kFusedStrip + 2 * R;
+  a.ldsw = fused_pitch(kb);
+  a.vec = 1;
+  a.in[0] = psi_in;
+  a.psi_in = psi_in;
+  a.psi_out = psi_out;
+  a.obs_u16 = ob.u16 ? 1 : 0;
+  a.obs_sy = ob.sy;
+  a.obs_sz = ob.sz;
+  for (int v = 0; v < 2; ++v) {
+    const ViewPsf &w = c->views[v];
+    a.obs[v] = ob.p[v];
+    a.w[v] = weight_of(st, v);
+    put_factor(a.tz[v], w.pz, kb);
+    put_factor(a.tx[v], w.px, kb);
+    put_factor(fa.btz[v], w.xz, kb);
+    put_factor(fa.btx[v], w.xx, kb);
+  }
+  return timed(st, 5, [&] { return launch_fused(fa, kb, st.s); });
+}
+
 hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd_run *r, hipStream_t s,
                        const Tune &tn, bool timing_override = false) {
   // a batch of B planes uses the first B planes of every workspace set
@@ -1216,10 +1286,27 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
       e = timed(rb, 2, [&] { return launch_fill(psi0, nb, r->init_const, s); });
     else if (e == hipSuccess && r->init == MVD_INIT_GIVEN && psi0 != est_b)
       e = timed(rb, 2, [&] { return launch_copy(est_b, psi0, nb, s); });
+    // fused iterations: ψ^t and ψ^{t+1} in different plane sets where the
+    // plane has several strips (a strip reads its neighbours' ψ columns): the
+    // checkpoint slots, or the estimate and the first ratio plane set in turn
+    // (after an odd count ψ^T is copied back to the estimate)
+    const int kbf = r->update == MVD_UPDATE_SIMULTANEOUS && L.n_ratio > 0 && aligned16(est_b) &&
+                            aligned16(rat[0]) && (!r->checkpoints || aligned16(r->checkpoints))
+                        ? fused_bucket_of(rb, ob)
+                        : 0;
+    const bool pingpong = kbf && !r->checkpoints && g.X > kFusedStrip;
     for (int t = 0; t < T && e == hipSuccess; ++t) {
       float *cur = r->checkpoints ? slot(t) : est_b;
       float *nxt = r->checkpoints ? (t + 1 < T ? slot(t + 1) : est_b) : est_b;
-      if (r->update == MVD_UPDATE_SIMULTANEOUS) {
+      if (kbf) {
+        if (pingpong) {
+          cur = t % 2 ? rat[0] : est_b;
+          nxt = t % 2 ? est_b : rat[0];
+        }
+        e = fused_iteration(rb, ob, kbf, cur, nxt);
+        if (e == hipSuccess && pingpong && t == T - 1 && T % 2)
+          e = timed(rb, 2, [&] { return launch_copy(rat[0], est_b, nb, s); });
+      } else if (r->update == MVD_UPDATE_SIMULTANEOUS) {
         e = forward_views(rb, cur, ob, rat.data(), 0, c->nv);
         if (e == hipSuccess) e = backward_views(rb, rat.data(), cur, nxt, 0, c->nv);
       } else {
@@ -1736,7 +1823,9 @@ hipError_t cached_graph(mvd_ctx *c, const void *const *obs, float *est, const mv
 // views, update order, boundary); the fastest is cached for the process.  Each
 // candidate starts from the process-wide overrides.
 std::vector<Tune> tune_candidates() {
-  std::vector<Tune> c(11, tune());
+  std::vector<Tune> c(12, tune());
+  for (Tune &t : c) t.fused = 0;
+  c[11].fused = 1;       // one fused launch per iteration (where it applies)
   c[1].fwd_occ = 2;
   c[2].fwd_views = 1;
   c[3].bwd_vin = 1;      // one ratio plane per backward launch
@@ -1764,12 +1853,15 @@ std::string tune_key(const mvd_ctx *c, const mvd_run *r) {
 std::mutex g_tune_mu;
 std::map<std::string, Tune> g_tune_cache;
 
-// Forward + backward launch time (ms) of the marks recorded since the last drain.
+// Pass launch time (ms: forward, backward and fused launches) of the marks
+// recorded since the last drain: the cost of an iteration.  (The one-iteration
+// probe ends a fused run with the copy back of an odd count, a cost paid once
+// per run, which is left out.)
 double drain_marks(mvd_ctx *c) {
   double ms = 0.0;
   for (auto &m : c->marks) {
     float t = 0.f;
-    if ((m.kind == 0 || m.kind == 1) && hipEventElapsedTime(&t, m.a, m.b) == hipSuccess) ms += t;
+    if ((m.kind == 0 || m.kind == 1 || m.kind == 5) && hipEventElapsedTime(&t, m.a, m.b) == hipSuccess) ms += t;
     c->pool.push_back(m.a);
     c->pool.push_back(m.b);
   }
@@ -2510,6 +2602,21 @@ int mvd_internal_mfma_plan(int kz, int kx, int *out) {
 }
 
 int mvd_internal_version(void) { return MVD_TESTING_VERSION; }
+
+int mvd_internal_fused_plan(const mvd_ctx *c, int kb, int *out) {
+  if (!c || !out) return MVD_ERR_ARG;
+  if (kb != 3 && kb != 7 && kb != 11 && kb != 15 && kb != 21 && kb != 31) return MVD_ERR_UNSUPPORTED;
+  const int R = (kb - 1) / 2, RA = (R + 7) / 8 * 8;
+  out[0] = kb;
+  out[1] = kFusedStrip;
+  out[2] = (c->X + kFusedStrip - 1) / kFusedStrip;
+  out[3] = R;
+  out[4] = RA;
+  out[5] = fused_pitch(kb);
+  out[6] = (int)fused_lds_bytes(kb, out[5]);
+  out[7] = kFusedThreads;
+  return MVD_OK;
+}
 
 int mvd_internal_psf_terms(mvd_ctx *c, int view, int which, float *out, int cap) {
   if (!c || view < 0 || view >= c->nv || !c->derived || (which != 0 && which != 1)) return MVD_ERR_ARG;

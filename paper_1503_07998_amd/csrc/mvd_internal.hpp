@@ -72,6 +72,22 @@ struct SepPassArgs {
   float tx[kSepFwdViews][kMaxK];      // x factor, padded to the bucket
 };
 
+// One fused iteration of the simultaneous two-view update (forward and
+// backward passes in one launch; k_fused.hip).  `f` carries the geometry
+// (x_out: output columns per strip, nstrip, halo = R, ldsw: LDS row pitch),
+// the observations, ψ in (f.psi_in, also f.in[0]) and out (f.psi_out, a
+// different plane set unless nstrip = 1), the weights and the PSF factors
+// (f.tz, f.tx); the back-projector factors follow.
+struct FusedArgs {
+  SepPassArgs f;
+  float btz[kSepFwdViews][kMaxK];
+  float btx[kSepFwdViews][kMaxK];
+};
+constexpr int kFusedStrip = 256;     // output columns per work-group of the fused iteration
+constexpr int kFusedThreads = 960;   // its work-group: three roles of 320 threads
+size_t fused_lds_bytes(int kb, int pitch);
+hipError_t launch_fused(const FusedArgs &a, int kb, hipStream_t s);
+
 // General K×K pass (same semantics as SepPassArgs).
 struct TwoDPassArgs {
   PlaneGeom g;

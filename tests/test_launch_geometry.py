@@ -404,3 +404,122 @@ def test_widest_accepted_plane_geometry_in_bounds(k):
     halos, and every zero-row read inside the static row."""
     for boundary in ("zero", "periodic"):
         check_geometry(1, 3, MAX_PLANE_X, k, boundary, 1)
+
+
+# ---------------------------------------------------------------------------
+# Fused iteration (forward and backward passes of both views in one launch).
+# ---------------------------------------------------------------------------
+FUSED_BUCKETS = [3, 7, 11, 15, 21, 31]
+
+
+def fused_plan(ctx, kb):
+    out = (ctypes.c_int * 8)()
+    lib = N.lib()
+    lib.mvd_internal_fused_plan.restype = ctypes.c_int
+    lib.mvd_internal_fused_plan.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    assert lib.mvd_internal_fused_plan(ctx, kb, out) == 0
+    keys = ["kb", "x_out", "nstrip", "R", "RA", "pitch", "lds", "threads"]
+    return dict(zip(keys, list(out)))
+
+
+def check_fused(Z, X, kb):
+    """Every access of the fused kernel for a Z × X plane, bucket kb."""
+    ctx = api.mvd_create(2, Z, X, N.MVD_DEVICE_NONE)
+    try:
+        p = fused_plan(ctx, kb)
+    finally:
+        api.mvd_destroy(ctx)
+    R, RA, pitch, x_out, T = p["R"], p["RA"], p["pitch"], p["x_out"], p["threads"]
+    assert R == (kb - 1) // 2 and RA % NX == 0 and RA >= R
+    role = T // 3
+    assert role % 64 == 0 and T <= 1024
+    NK = (kb + 3 + 3) // 4 * 4
+    NIN4 = (NX + kb - 1 + 3) // 4
+    M = G * ((2 * G + kb - 1 + G - 1) // G)
+    U = M // G
+    D = (G + R + G - 1) // G
+    assert D * G >= G + R
+    # LDS: three [2][G][pitch] buffers and two [2][8][NK] tap tables
+    setf = 2 * G * pitch
+    assert p["lds"] == 4 * (3 * setf + 2 * 2 * 8 * NK) <= LDS_LIMIT
+    assert pitch % 8 == 4
+    wf, wb = x_out + 2 * RA + 2 * R, x_out + 2 * R
+    assert wf <= role and wb <= role          # one column per ring thread
+    assert p["nstrip"] == -(-X // x_out)
+    # forward row-pass items: threads [0, nfi), view-major, pairs of rows
+    nxbF = (x_out + 2 * RA) // NX
+    nfi = 2 * G * nxbF
+    assert nfi <= 2 * role
+    for it in range(nfi):
+        v = it // (G * nxbF)
+        rem = it - v * G * nxbF
+        pr = rem >> 1
+        gp = pr // nxbF
+        g, ox = 2 * gp + (rem & 1), (pr - gp * nxbF) * NX
+        assert 0 <= v < 2 and 0 <= g < G
+        assert ox + 4 * NIN4 <= pitch            # bufF reads (columns ≥ wf are zeroed pads)
+        assert ox + NX <= x_out + 2 * RA         # bufT writes inside the transferred range
+    # backward row-pass items: threads [2·role, 2·role + nbi)
+    nxbB = x_out // NX
+    nbi = G * nxbB
+    assert nbi <= role and nbi % 64 == 0
+    for it in range(nbi):
+        pr = it >> 1
+        gp = pr // nxbB
+        g, ox = 2 * gp + (it & 1), (pr - gp * nxbB) * NX
+        assert 0 <= g < G and ox + 4 * NIN4 <= pitch
+    # transfer into the r rings: role-B thread tr < wb reads bufT column tr + RA − R
+    assert 0 <= RA - R and wb - 1 + RA - R < x_out + 2 * RA
+    # global accesses per strip: 8-column items lie wholly inside or outside the plane
+    assert X % NX == 0
+    for s in range(p["nstrip"]):
+        x0 = s * x_out
+        for ox in range(0, x_out + 2 * RA, NX):
+            fx = x0 - RA + ox
+            if 0 <= fx < X:
+                assert fx + NX <= X
+        for ox in range(0, x_out, NX):
+            if x0 + ox < X:
+                assert x0 + ox + NX <= X
+    # ring slots over every phase: the forward ring (ψ rows) and the r rings
+    ngroups = -(-Z // G)
+    nphases = ngroups + D
+    fslot = [None] * M
+    for m in range(G + kb - 1):
+        fslot[m] = -R + m
+    rslot = [None] * M
+    for m in range(R):
+        rslot[m] = m - R                         # r rows above the plane (zero)
+    for ph in range(nphases):
+        u = ph % U
+        if ph < ngroups:
+            for g in range(G):                   # prefetch first, then the column pass
+                fslot[((u + 1) * G + kb - 1 + g) % M] = -R + (ph + 1) * G + kb - 1 + g
+            for b in range(G // 4):
+                for k in range(kb + 3):
+                    assert fslot[(u * G + 4 * b + k) % M] == ph * G + 4 * b + k - R
+        j = ph - D
+        if j >= 0:
+            ub = ((u - D) % U + U) % U
+            for b in range(G // 4):
+                for k in range(kb + 3):
+                    assert rslot[(ub * G + 4 * b + k) % M] == j * G + 4 * b + k - R, (ph, b, k)
+        for g in range(G):                       # group ph's r rows join the rings
+            rslot[(u * G + g + R) % M] = ph * G + g
+    # every output row group was back-projected
+    assert nphases - D == ngroups
+
+
+@pytest.mark.parametrize("kb", FUSED_BUCKETS)
+@pytest.mark.parametrize("Z,X", [(512, 512), (37, 264), (8, 64), (2048, 2048), (100, 8), (13, 520)])
+def test_fused_geometry(Z, X, kb):
+    check_fused(Z, X, kb)
+
+
+def test_fused_plan_rejects_wide_kernels():
+    ctx = api.mvd_create(2, 64, 64, N.MVD_DEVICE_NONE)
+    try:
+        out = (ctypes.c_int * 8)()
+        assert N.lib().mvd_internal_fused_plan(ctx, 41, out) == N.MVD_ERR_UNSUPPORTED
+    finally:
+        api.mvd_destroy(ctx)
