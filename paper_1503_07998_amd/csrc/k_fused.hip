@@ -73,69 +73,84 @@ __device__ __forceinline__ FItem fitem(int it, int nxb) {
   return FItem{2 * gp + (it & 1), (pr - gp * nxb) * NX};
 }
 
-// Per-thread constants of a work-group.
+// Per-thread constants of a work-group.  Everything but the item fields is
+// the same across a wave (kept in scalar registers).
 struct FCtx {
-  int t, role, vb;        // role 0 F, 1 B (view vb)
+  int role, vb;                // role 0 F, 1 B (view vb)
   int y, x0, ngroups, nphases;
   int pitch;
   size_t plane_off;
   float *bufF, *bufT, *bufB;   // [2][G][pitch] each
   const float *ttF, *ttB;      // tap tables
-  // forward row-pass item (threads < nfi; lanes past nfi compute on item nfi − 1)
-  bool fwave, fown;
-  int fv, fg, fox, fx;         // view, row, column in bufF / bufT, plane column of the first output
-  // backward row-pass item (threads in [2·kRoleThreads, 2·kRoleThreads + nbi))
-  bool bwave, bown;
-  int bg, box, bx;
+  // a thread's row-pass item: a forward item (waves with threads < nfi; lanes
+  // past nfi compute on item nfi − 1) or a backward item (waves from thread
+  // 2·kRoleThreads on, nbi items); never both
+  int fwave, bwave;
+  bool own;                    // the item is real (else computed on a clamped item, not stored)
+  int iv, ig, iox;             // forward: view; row in the group; first column in the LDS row
 };
 
-template <int U16>
-struct FOps {
-  float f[NX];
-};
-template <>
-struct FOps<1> {
-  uint32_t u[NX / 2];
-};
-
-template <int U16>
-__device__ __forceinline__ void load_phi(KFArg *fa, const FCtx &c, int z, bool in, FOps<U16> &o) {
+// Row-pass operands of one item, loaded a row group before they are used:
+// φ_v for a forward item (uint16 as packed pairs in the first 4 entries) or ψ
+// for a backward item (zeros where the item lies outside the plane).
+template <int KB, int U16>
+__device__ __forceinline__ void load_operands(KFArg *fa, const FCtx &c, int p, float (&o)[NX]) {
   KArg *a = &fa->f;
-  const size_t s = (size_t)c.y * a->obs_sy + (size_t)z * a->obs_sz + c.fx;
-  if constexpr (U16) {
-    uint4 w = make_uint4(0u, 0u, 0u, 0u);
-    if (in) w = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(a->obs[c.fv]) + s);
-    o.u[0] = w.x;
-    o.u[1] = w.y;
-    o.u[2] = w.z;
-    o.u[3] = w.w;
-  } else {
-    float4 p = make_float4(0.f, 0.f, 0.f, 0.f), q = p;
-    if (in) {
-      const float *src = static_cast<const float *>(a->obs[c.fv]) + s;
-      p = *reinterpret_cast<const float4 *>(src);
-      q = *reinterpret_cast<const float4 *>(src + 4);
+  const int Z = a->g.Z, X = a->g.X;
+  float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+  if (c.fwave) {
+    const int z = p * G + c.ig, fx = c.x0 - FShape<KB>::RA + c.iox;   // plane column
+    const bool in = c.own && p < c.ngroups && z < Z && fx >= 0 && fx < X;
+    const size_t s = (size_t)c.y * a->obs_sy + (size_t)z * a->obs_sz + fx;
+    if constexpr (U16) {
+      if (in) {
+        const uint4 w = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(a->obs[c.iv]) + s);
+        lo = make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z), __uint_as_float(w.w));
+      }
+    } else if (in) {
+      const float *src = static_cast<const float *>(a->obs[c.iv]) + s;
+      lo = *reinterpret_cast<const float4 *>(src);
+      hi = *reinterpret_cast<const float4 *>(src + 4);
     }
-    o.f[0] = p.x; o.f[1] = p.y; o.f[2] = p.z; o.f[3] = p.w;
-    o.f[4] = q.x; o.f[5] = q.y; o.f[6] = q.z; o.f[7] = q.w;
   }
+  o[0] = lo.x; o[1] = lo.y; o[2] = lo.z; o[3] = lo.w;
+  o[4] = hi.x; o[5] = hi.y; o[6] = hi.z; o[7] = hi.w;
+}
+
+__device__ __forceinline__ void load_psi(KFArg *fa, const FCtx &c, int j, float (&o)[NX]) {
+  KArg *a = &fa->f;
+  const int Z = a->g.Z, X = a->g.X;
+  const int z = j * G + c.ig;
+  float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+  const int bx = c.x0 + c.iox;
+  if (c.own && j >= 0 && z < Z && bx < X) {
+    const float *src = a->psi_in + c.plane_off + (size_t)z * X + bx;
+    lo = *reinterpret_cast<const float4 *>(src);
+    hi = *reinterpret_cast<const float4 *>(src + 4);
+  }
+  o[0] = lo.x; o[1] = lo.y; o[2] = lo.z; o[3] = lo.w;
+  o[4] = hi.x; o[5] = hi.y; o[6] = hi.z; o[7] = hi.w;
 }
 
 template <int U16>
-__device__ __forceinline__ float phi_at(const FOps<U16> &o, int n) {
+__device__ __forceinline__ float phi_at(const float (&o)[NX], int n) {
   if constexpr (U16)
-    return (float)((o.u[n >> 1] >> (16 * (n & 1))) & 0xffffu);
+    return (float)((__float_as_uint(o[n >> 1]) >> (16 * (n & 1))) & 0xffffu);
   else
-    return fmaxf(o.f[n], 0.f);
+    return fmaxf(o[n], 0.f);
 }
 
 template <int KB, int U16, int u>
 __device__ __forceinline__ void fused_phase(KFArg *fa, const FCtx &c, const Cols<1, Shape<KB>::R> &cl,
-                                            float (&ring)[1][Shape<KB>::M], int p0) {
+                                            float (&ring)[1][Shape<KB>::M], float (&opA)[NX], float (&opB)[NX],
+                                            int p0) {
   using S = Shape<KB>;
   using FS = FShape<KB>;
   constexpr int M = S::M, R = S::R, U = S::U, RA = FS::RA, D = FS::D;
-  constexpr int ub = ((u - D) % U + U) % U;   // ring phase of the backward group
+  // u runs over two ring cycles, so that both the ring phase (u mod U) and the
+  // operand arrays' parity (u mod 2) are compile-time constants
+  constexpr int ur = u % U;
+  constexpr int ub = ((ur - D) % U + U) % U;   // ring phase of the backward group
   KArg *a = &fa->f;
   const int p = p0 + u;
   if (p >= c.nphases) return;   // uniform
@@ -143,31 +158,25 @@ __device__ __forceinline__ void fused_phase(KFArg *fa, const FCtx &c, const Cols
   const bool fon = p < c.ngroups, bon = j >= 0;
   const int Z = a->g.Z, X = a->g.X;
 
-  // 1. loads consumed after the barrier: row-pass operands first (loads retire
-  //    in order), then the forward ring's next rows
-  const int zf = p * G + c.fg;
-  const bool fin = c.fown && fon && zf < Z && c.fx >= 0 && c.fx < X;
-  FOps<U16> ops;
-  if (c.fwave) load_phi<U16>(fa, c, zf, fin, ops);
-  const int zb = j * G + c.bg;
-  const bool bin = c.bown && bon && zb < Z && c.bx < X;
-  float ps[NX];
-  if (c.bwave) {
-#pragma unroll
-    for (int n = 0; n < NX; ++n) ps[n] = 0.f;
-    if (bin) {
-      const float *src = a->psi_in + c.plane_off + (size_t)zb * X + c.bx;
-      const float4 lo = *reinterpret_cast<const float4 *>(src);
-      const float4 hi = *reinterpret_cast<const float4 *>(src + 4);
-      ps[0] = lo.x; ps[1] = lo.y; ps[2] = lo.z; ps[3] = lo.w;
-      ps[4] = hi.x; ps[5] = hi.y; ps[6] = hi.z; ps[7] = hi.w;
-    }
-  }
+  // this group's row-pass operands were loaded a group ago; the next group's
+  // are loaded now (the two arrays swap roles with the phase parity), then the
+  // forward ring's next rows
+  float(&cur)[NX] = (u & 1) ? opB : opA;
+  float(&nxt)[NX] = (u & 1) ? opA : opB;
+  const int zf = p * G + c.ig;
+  const int fx = c.x0 - RA + c.iox, bx = c.x0 + c.iox;   // plane columns (forward / backward item)
+  const bool fin = c.own && fon && zf < Z && fx >= 0 && fx < X;
+  const int zb = j * G + c.ig;
+  const bool bin = c.own && bon && zb < Z && bx < X;
+  if (c.fwave)
+    load_operands<KB, U16>(fa, c, p + 1, nxt);
+  else if (c.bwave)
+    load_psi(fa, c, j + 1, nxt);
   if (c.role == 0 && fon) {
     const float *__restrict__ src = a->psi_in + c.plane_off;
 #pragma unroll
     for (int g = 0; g < G; ++g)
-      load_row<1, R>(src, -R + (p + 1) * G + KB - 1 + g, a, cl, &ring[0][((u + 1) * G + KB - 1 + g) % M], M);
+      load_row<1, R>(src, -R + (p + 1) * G + KB - 1 + g, a, cl, &ring[0][((ur + 1) * G + KB - 1 + g) % M], M);
   }
   // 2. column passes → LDS
   if (c.role == 0) {
@@ -175,7 +184,7 @@ __device__ __forceinline__ void fused_phase(KFArg *fa, const FCtx &c, const Cols
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         float acc[1][G];
-        zpass<KB, 1, u>(ztab<KB>(c.ttF, v), ring, acc);
+        zpass<KB, 1, ur>(ztab<KB>(c.ttF, v), ring, acc);
         store_group<KB, 1>(c.bufF + v * G * c.pitch, a, cl, acc);
       }
     }
@@ -190,31 +199,34 @@ __device__ __forceinline__ void fused_phase(KFArg *fa, const FCtx &c, const Cols
     float r[NX];
     if (fon) {
       float b[NX];
-      xconv<KB>(c.bufF + (c.fv * G + c.fg) * c.pitch + c.fox, xtab<KB>(c.ttF, c.fv), a->tx[c.fv], b);
+      xconv<KB>(c.bufF + (c.iv * G + c.ig) * c.pitch + c.iox, xtab<KB>(c.ttF, c.iv), a->tx[c.iv], b);
 #pragma unroll
-      for (int n = 0; n < NX; ++n) r[n] = fin ? guarded_ratio(phi_at<U16>(ops, n), b[n]) : 0.f;
+      for (int n = 0; n < NX; ++n) r[n] = fin ? guarded_ratio(phi_at<U16>(cur, n), b[n]) : 0.f;
     } else {
 #pragma unroll
       for (int n = 0; n < NX; ++n) r[n] = 0.f;   // rows below the plane: r = 0
     }
-    if (c.fown) {
-      float *dst = c.bufT + (c.fv * G + c.fg) * c.pitch + c.fox;
+    if (c.own) {
+      float *dst = c.bufT + (c.iv * G + c.ig) * c.pitch + c.iox;
       *reinterpret_cast<float4 *>(dst) = make_float4(r[0], r[1], r[2], r[3]);
       *reinterpret_cast<float4 *>(dst + 4) = make_float4(r[4], r[5], r[6], r[7]);
     }
   }
   if (c.bwave && bon) {
     // ψ · c_0 · c_1, view by view as in the two-plane backward pass
+    float ps[NX];
+#pragma unroll
+    for (int n = 0; n < NX; ++n) ps[n] = cur[n];
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
       float q[NX];
-      xconv<KB>(c.bufB + (v * G + c.bg) * c.pitch + c.box, xtab<KB>(c.ttB, v), fa->btx[v], q);
+      xconv<KB>(c.bufB + (v * G + c.ig) * c.pitch + c.iox, xtab<KB>(c.ttB, v), fa->btx[v], q);
       const float w = a->w[v], w1 = 1.f - w;
 #pragma unroll
       for (int n = 0; n < NX; ++n) ps[n] *= fmaf(w, q[n], w1);
     }
     if (bin) {
-      float *dst = a->psi_out + c.plane_off + (size_t)zb * X + c.bx;
+      float *dst = a->psi_out + c.plane_off + (size_t)zb * X + bx;
       *reinterpret_cast<float4 *>(dst) = make_float4(ps[0], ps[1], ps[2], ps[3]);
       *reinterpret_cast<float4 *>(dst + 4) = make_float4(ps[4], ps[5], ps[6], ps[7]);
     }
@@ -224,15 +236,15 @@ __device__ __forceinline__ void fused_phase(KFArg *fa, const FCtx &c, const Cols
   if (c.role != 0 && cl.act[0]) {
     const float *src = c.bufT + c.vb * G * c.pitch + cl.lcol[0] + (RA - R);
 #pragma unroll
-    for (int g = 0; g < G; ++g) ring[0][(u * G + g + R) % M] = src[g * c.pitch];
+    for (int g = 0; g < G; ++g) ring[0][(ur * G + g + R) % M] = src[g * c.pitch];
   }
 }
 
 template <int KB, int U16, int... us>
 __device__ __forceinline__ void fused_phases(KFArg *fa, const FCtx &c, const Cols<1, Shape<KB>::R> &cl,
-                                             float (&ring)[1][Shape<KB>::M], int p0,
-                                             std::integer_sequence<int, us...>) {
-  (fused_phase<KB, U16, us>(fa, c, cl, ring, p0), ...);
+                                             float (&ring)[1][Shape<KB>::M], float (&opA)[NX], float (&opB)[NX],
+                                             int p0, std::integer_sequence<int, us...>) {
+  (fused_phase<KB, U16, us>(fa, c, cl, ring, opA, opB, p0), ...);
 }
 
 template <int KB, int U16>
@@ -246,9 +258,8 @@ __global__ void __launch_bounds__(1024, 4) fused_kernel(const FusedArgs) {
   const int t = threadIdx.x, nt = blockDim.x;
   const int b = logical_block();
   FCtx c;
-  c.t = t;
-  c.role = t < kRoleThreads ? 0 : 1;
-  c.vb = t < 2 * kRoleThreads ? 0 : 1;
+  c.role = __builtin_amdgcn_readfirstlane(t < kRoleThreads ? 0 : 1);
+  c.vb = __builtin_amdgcn_readfirstlane(t < 2 * kRoleThreads ? 0 : 1);
   const int strip = b % a->nstrip;
   c.y = b / a->nstrip;
   c.x0 = strip * a->x_out;
@@ -264,27 +275,26 @@ __global__ void __launch_bounds__(1024, 4) fused_kernel(const FusedArgs) {
   float *ttB = ttF + 2 * 8 * NK;
   c.ttF = ttF;
   c.ttB = ttB;
-  // row-pass items
-  const int nxbF = (a->x_out + 2 * RA) / NX, nfi = 2 * G * nxbF;
-  const int nxbB = a->x_out / NX, nbi = G * nxbB;
-  c.fwave = (t & ~63) < nfi;
-  c.fown = t < nfi;
-  {
-    const int it = min(t, nfi - 1);
-    c.fv = it / (G * nxbF);
-    const FItem fi = fitem(it - c.fv * G * nxbF, nxbF);
-    c.fg = fi.g;
-    c.fox = fi.ox;
-    c.fx = c.x0 - RA + fi.ox;
-  }
+  // row-pass items (the strip width is the compile-time kFusedStrip)
+  constexpr int nxbF = (kFusedStrip + 2 * RA) / NX, nfi = 2 * G * nxbF;
+  constexpr int nxbB = kFusedStrip / NX, nbi = G * nxbB;
+  static_assert(nfi <= 2 * kRoleThreads && nbi <= kRoleThreads, "items fit their threads");
   const int tb = t - 2 * kRoleThreads;
-  c.bwave = tb >= 0 && (tb & ~63) < nbi;
-  c.bown = tb >= 0 && tb < nbi;
-  {
+  c.fwave = __builtin_amdgcn_readfirstlane((t & ~63) < nfi ? 1 : 0);
+  c.bwave = __builtin_amdgcn_readfirstlane(!c.fwave && tb >= 0 && (tb & ~63) < nbi ? 1 : 0);
+  if (c.fwave) {
+    const int it = min(t, nfi - 1);
+    c.own = t < nfi;
+    c.iv = it / (G * nxbF);
+    const FItem fi = fitem(it - c.iv * G * nxbF, nxbF);
+    c.ig = fi.g;
+    c.iox = fi.ox;
+  } else {
     const FItem bi = fitem(max(0, min(tb, nbi - 1)), nxbB);
-    c.bg = bi.g;
-    c.box = bi.ox;
-    c.bx = c.x0 + bi.ox;
+    c.own = tb >= 0 && tb < nbi;
+    c.iv = 0;
+    c.ig = bi.g;
+    c.iox = bi.ox;
   }
   // the columns this thread's ring serves: F the strip ± (RA + R), B_v ± R
   Geo o;
@@ -323,9 +333,15 @@ __global__ void __launch_bounds__(1024, 4) fused_kernel(const FusedArgs) {
 #pragma unroll
     for (int m = 0; m < R; ++m) ring[0][m] = 0.f;   // r rows above the plane
   }
+  // the first group's row-pass operands (phase 0 reads opA)
+  float opA[NX], opB[NX];
+  if (c.fwave)
+    load_operands<KB, U16>(fa, c, 0, opA);
+  else if (c.bwave)
+    load_psi(fa, c, -D, opA);
   lds_sync();
-  for (int p0 = 0; p0 < c.nphases; p0 += U)
-    fused_phases<KB, U16>(fa, c, cl, ring, p0, std::make_integer_sequence<int, U>{});
+  for (int p0 = 0; p0 < c.nphases; p0 += 2 * U)
+    fused_phases<KB, U16>(fa, c, cl, ring, opA, opB, p0, std::make_integer_sequence<int, 2 * U>{});
 }
 
 template <int KB>
@@ -334,7 +350,7 @@ hipError_t fused_bucket(const FusedArgs &fa, hipStream_t s) {
   const SepPassArgs &a = fa.f;
   constexpr int R = (KB - 1) / 2;
   // the geometry the roles assume: whole 8-column items, rings within their role
-  if (a.g.X % NX != 0 || a.x_out % 64 != 0 || a.x_out + 2 * FS::RA + 2 * R > kRoleThreads ||
+  if (a.g.X % NX != 0 || a.x_out != kFusedStrip || a.x_out + 2 * FS::RA + 2 * R > kRoleThreads ||
       a.ldsw < a.x_out + 2 * FS::RA + 2 * R + 4 || a.ldsw % 8 != 4 || a.nviews != 2 || a.boundary != 0 ||
       a.halo != R || a.nstrip != (a.g.X + a.x_out - 1) / a.x_out)
     return hipErrorInvalidValue;

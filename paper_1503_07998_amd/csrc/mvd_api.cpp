@@ -1917,10 +1917,15 @@ hipError_t autotune(mvd_ctx *c, const void *const *obs, float *est, const mvd_ru
   for (const Tune &t : cand) {
     if (e != hipSuccess) break;
     double ms = 0.0;
-    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+    // the first run of a candidate is not counted: it pays the first launch of
+    // kernels the others did not use (code loading, attributes)
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
       e = enqueue_run(c, obs, est, &probe, s, t, true);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e == hipSuccess) ms += drain_marks(c);
+      if (e == hipSuccess) {
+        const double m = drain_marks(c);
+        if (rep > 0) ms += m;
+      }
     }
     if (e == hipSuccess && ms < best) {
       best = ms;
