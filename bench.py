@@ -56,8 +56,10 @@ def step_work(spec, kind, vox, launches_per_iter, general=False):
     return b, f
 
 
-# PSF terms per view (--psf lowrank: a sum of this many rank-one terms)
+# PSF terms per view (--psf lowrank: a sum of this many rank-one terms), and
+# the terms one launch runs (the library pairs them)
 PSF_TERMS = 1
+TERMS_PER_LAUNCH = 2
 
 
 def step_work_split(spec, kind, vox, launches_per_iter, general=False):
@@ -69,7 +71,8 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
     writes r_v and (once per launch) reads ψ; a backward pass reads r_v and
     (once per launch) reads and writes ψ.  Each view's two 1D passes cost
     2 · (kz + kx) flops (FMA = 2); a general K×K pass costs 2 · kz · kx; a PSF
-    of R rank-one terms runs R pairs of 1D passes through a partial-sum plane.
+    of R rank-one terms runs R pairs of 1D passes, two terms per launch, through
+    a partial-sum plane.
     The library may split the V views of an iteration over several launches,
     so the work of one iteration on those voxels is divided by its launches.
     """
@@ -85,11 +88,12 @@ def step_work_split(spec, kind, vox, launches_per_iter, general=False):
         f = V * 2 * 2 * (k + k)
         return vox * b / n, vox * f / n, 0.0, vox * f / n
     if R > 1 and not general:
-        # one launch per view and term: every term reads its input (ψ forward,
-        # r_v backward), terms after the first read and all but the last write
-        # the partial sum; the last adds φ_v (float32) and r_v forward, ψ in and
-        # ψ out backward: 4R + 8(R − 1) + 8 = 12R bytes per voxel and view
-        b = 12 * R * V
+        # L = ⌈R / 2⌉ launches per view and direction: every launch reads its
+        # input (ψ forward, r_v backward), the partial sum crosses each launch
+        # boundary (written, read), the last adds φ_v (float32) and r_v forward,
+        # ψ in and ψ out backward: 4L + 8(L − 1) + 8 = 12L bytes per voxel and view
+        L = -(-R // TERMS_PER_LAUNCH)
+        b = 12 * L * V
     elif kind == "forward":
         phi = 2 if (spec.obs_dtype == "u16" and not general) else 4
         b = (phi + 4) * V + 4 * n
@@ -118,12 +122,13 @@ def kernel_code_hash(*paths):
     return hashlib.sha256("\n".join(parts).encode()).hexdigest()
 
 
-# the pass kernels whose counters the traffic record holds
-PASS_SOURCES = ("k_sep_impl.hpp", "k_fused.hip")
+# the sources of the pass kernels whose counters the traffic record holds: the
+# separable passes, and the fused iteration (which also includes the former)
+PASS_SOURCES = {"sep": ("k_sep_impl.hpp",), "fused": ("k_sep_impl.hpp", "k_fused.hip")}
 
 
-def pass_code_hash():
-    return kernel_code_hash(*[os.path.join(ROOT, "paper_1503_07998_amd", "csrc", f) for f in PASS_SOURCES])
+def pass_code_hash(family="sep"):
+    return kernel_code_hash(*[os.path.join(ROOT, "paper_1503_07998_amd", "csrc", f) for f in PASS_SOURCES[family]])
 
 
 def measured_traffic(name, kind):
@@ -131,12 +136,13 @@ def measured_traffic(name, kind):
     FETCH_SIZE / WRITE_SIZE runs (scaled by the factors a copy of known size
     gives), or None when the kernel code changed since they were taken."""
     path = os.path.join(ROOT, "profiles", f"sep_passes_{name}_traffic.json")
+    family = "fused" if kind == "fused" else "sep"
     try:
         rec = json.load(open(path))
-        h = pass_code_hash()
+        h = pass_code_hash(family)
     except OSError:
         return None
-    if rec.get("kernel_code_sha256") != h:
+    if rec.get("code_sha256", {}).get(family) != h:
         return None
     # the instance of the pass (plain, split-view or fused form) that ran most
     # often in the profiled bench run

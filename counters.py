@@ -89,7 +89,7 @@ def main():
         check = {"kernel": sv[0], "expected_read": 4 * a.voxels, "expected_write": 4 * a.voxels,
                  "read_ratio": kv["fetch_bytes"] / (4 * a.voxels), "write_ratio": kv["write_bytes"] / (4 * a.voxels)}
     rec = {
-        "kernel_code_sha256": bench.pass_code_hash(),
+        "code_sha256": {f: bench.pass_code_hash(f) for f in bench.PASS_SOURCES},
         "calibration": {"kernel": ck[0], "bytes_read": cal_bytes, "bytes_written": cal_bytes,
                         "fetch_kib": cf[ck[0]], "write_kib": cw[ck[0]]},
         "fetch_factor": fetch_factor, "write_factor": write_factor,

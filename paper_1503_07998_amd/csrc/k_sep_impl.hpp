@@ -454,7 +454,8 @@ __device__ __forceinline__ void store_group(float *B, KArg *a, const Cols<C, Sha
 // ---------------------------------------------------------------------------
 template <int EP>
 struct Epi {
-  static constexpr int nops = (EP == kEpBbar || EP == kEpAccumRatio || EP == kEpAccumUpdate) ? 2
+  static constexpr int nops = (EP == kEpBbar || EP == kEpAccumRatio || EP == kEpAccumUpdate ||
+                               EP == kEpTermsRatio || EP == kEpTermsUpdate) ? 2
                               : (EP == kEpStore ? 0 : 1);
   static constexpr int nbuf = nops > 0 ? nops : 1;
 };
@@ -509,6 +510,35 @@ __device__ __forceinline__ float guarded_ratio(float phi, float b) {
 template <int KB, int NV, int EP, int VM>
 __device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const float *tt, const Item &itm,
                                                 bool vec, const Ops<EP, NV> &ops) {
+  if constexpr (ep_terms(EP)) {
+    // the terms of one kernel: their sum (after the partial sum of earlier
+    // terms, in term order) finishes one output; operands in slot 0
+    float s[NX];
+#pragma unroll
+    for (int n = 0; n < NX; ++n) s[n] = ops.f[0][0][n];   // zeros without a partial sum
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      float b[NX];
+      xconv<KB>(buf + (v * G + itm.g) * lds_pitch(a) + itm.ox, xtab<KB>(tt, v), a->tx[v], b);
+#pragma unroll
+      for (int n = 0; n < NX; ++n) s[n] += b[n];
+    }
+    if (!itm.valid) return;
+    float r[NX];
+    if constexpr (EP == kEpTermsSum) {
+#pragma unroll
+      for (int n = 0; n < NX; ++n) r[n] = s[n];
+    } else if constexpr (EP == kEpTermsRatio) {
+#pragma unroll
+      for (int n = 0; n < NX; ++n) r[n] = guarded_ratio(ops.f[0][1][n], s[n]);
+    } else {
+      const float w = a->w[0], w1 = 1.f - w;
+#pragma unroll
+      for (int n = 0; n < NX; ++n) r[n] = ops.f[0][1][n] * fmaf(w, s[n], w1);
+    }
+    store8<VM>(a->out[0] + itm.off, itm.nvalid, vec, r);
+    return;
+  }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     float b[NX];
@@ -553,6 +583,17 @@ __device__ __forceinline__ void single_epilogue(KArg *a, const float *buf, const
 
 template <int NV, int EP, int VM>
 __device__ __forceinline__ void load_ops(KArg *a, const Item &itm, bool vec, Ops<EP, NV> &ops) {
+  if constexpr (ep_terms(EP)) {
+    // one output: the partial sum (aux0, or zeros) and the ratio's φ or the update's ψ (aux1)
+    if (a->aux0[0]) {
+      load8<VM>(a->aux0[0] + itm.off, itm.nvalid, vec, ops.f[0][0]);
+    } else {
+#pragma unroll
+      for (int n = 0; n < NX; ++n) ops.f[0][0][n] = 0.f;
+    }
+    if constexpr (Epi<EP>::nops > 1) load8<VM>(a->aux1[0] + itm.off, itm.nvalid, vec, ops.f[0][1]);
+    return;
+  }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     if constexpr (EP == kEpRatioU16) {
@@ -859,8 +900,27 @@ hipError_t single_ep(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
   return launch_with_lds(sep_forward_kernel<KB, 1, 1, 2, EP, 2>, a, p.threads, lds, s);
 }
 
+// Two terms of one kernel per launch (one column per thread, 128-bit accesses).
+template <int KB, int EP>
+hipError_t terms_ep(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
+  if (p.cols != 1 || !a.vec || p.threads > 2 * kSepMaxThreads) return hipErrorInvalidValue;
+  if constexpr (KB <= 41) {
+    if (p.occ >= 4) return launch_with_lds(sep_forward_kernel<KB, 1, 2, 4, EP, 1>, a, p.threads, lds_bytes<KB>(a, 2), s);
+  }
+  if (p.threads > kSepMaxThreads) return hipErrorInvalidValue;
+  return launch_with_lds(sep_forward_kernel<KB, 1, 2, 2, EP, 1>, a, p.threads, lds_bytes<KB>(a, 2), s);
+}
+
 template <int KB>
 hipError_t single_bucket(const SepPassArgs &a, const SepPlan &p, int ep, hipStream_t s) {
+  if (a.nviews == 2) {
+    switch (ep) {
+      case kEpTermsSum: return terms_ep<KB, kEpTermsSum>(a, p, s);
+      case kEpTermsRatio: return terms_ep<KB, kEpTermsRatio>(a, p, s);
+      case kEpTermsUpdate: return terms_ep<KB, kEpTermsUpdate>(a, p, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (a.nviews != 1) return hipErrorInvalidValue;
   switch (ep) {
     case kEpStore: return single_ep<KB, kEpStore>(a, p, s);

@@ -513,6 +513,7 @@ struct Tune {
   int plane_batch = 0;  // > 0: run this many planes through all iterations at a time
   int pq_window = 0;    // persistent batches: planes per window of a volume's items (0: all)
   int pq_zseg_scale = 0;  // persistent batches: segment length × 2^(v − 2) of the planner's (0: × 2)
+  int terms = 1;        // kernels of several rank-one terms: two terms per launch (0: one)
   int fused = 0;        // simultaneous two-view runs: one fused launch per iteration where it applies
                         // (a candidate of the tuner, which keeps it where it is faster)
   int wide = 0;         // rows of 513–1024 columns as one column per thread in up to
@@ -549,6 +550,7 @@ Tune parse_tune(const char *e) {
       if (k == "pq_window") r.pq_window = v;
       if (k == "pq_zseg_scale") r.pq_zseg_scale = v;
       if (k == "fused") r.fused = v;
+      if (k == "terms") r.terms = v;
     }
     pos = comma + 1;
   }
@@ -1041,13 +1043,84 @@ hipError_t single_pass(const RunState &st, int ep, const float *in, const std::v
   return timed(st, kind, [&] { return launch_sep_single_dispatch(a, sg.plan, ep, st.s); });
 }
 
+// Geometry of a pass over two terms of one kernel (one input ring, both terms'
+// column and row passes, their sum finishing one output): one column per
+// thread and whole 16-byte items, or false (then one term per launch).
+bool terms_geom(const RunState &st, int k, SepGeom *out) {
+  if (st.tn->terms == 0) return false;
+  SepGeom sg = plan_sep(st.c, st.g.Y, sep_bucket(k), st.boundary, *st.tn);
+  sg.plan.occ = (sg.plan.cols == 1 && sg.plan.bucket <= 41) ? 4 : 2;
+  if (sg.plan.cols != 1 || !whole_items(sg, st.g)) return false;
+  if (sg.plan.threads > (sg.plan.occ >= 4 ? 2 * kSepMaxThreads : kSepMaxThreads)) return false;
+  if (sizeof(float) * (2ull * 2 * kRowGroup * sg.ldsw + 2ull * 8 * ((sg.plan.bucket + 3 + 3) / 4 * 4)) > kLdsLimit)
+    return false;
+  *out = sg;
+  return true;
+}
+
+// Terms t and t + 1 of a kernel in one launch with epilogue `ep` (kEpTermsSum,
+// kEpTermsRatio, kEpTermsUpdate): out = finish([aux0 +] conv_t + conv_{t+1}).
+hipError_t terms_pass(const RunState &st, const SepGeom &sg, int ep, const float *in,
+                      const std::vector<float> *fz, const std::vector<float> *fx, float *out, const float *aux0,
+                      const float *aux1, float w, int kind) {
+  SepPassArgs a{};
+  fill_sep_common(a, sg, st.g, st.boundary);
+  a.nviews = 2;
+  a.in[0] = in;
+  a.out[0] = out;
+  a.aux0[0] = aux0;
+  a.aux1[0] = aux1;
+  a.w[0] = w;
+  for (int u = 0; u < 2; ++u) {
+    put_factor(a.tz[u], fz[u], sg.plan.bucket);
+    put_factor(a.tx[u], fx[u], sg.plan.bucket);
+  }
+  a.vec = 1;
+  return timed(st, kind, [&] { return launch_sep_single_dispatch(a, sg.plan, ep, st.s); });
+}
+
+// The terms of one low-rank kernel two per launch, in term order, through the
+// partial-sum planes; a last odd term runs alone with `ep_single`.  Returns
+// hipErrorNotSupported (before any launch) where the paired form does not apply.
+hipError_t lowrank_pairs(const RunState &st, const std::vector<std::vector<float>> &zs,
+                         const std::vector<std::vector<float>> &xs, const float *in, float *out, const float *last_op,
+                         float w, bool forward) {
+  const int R = (int)zs.size();
+  int k = 1;
+  for (int t = 0; t < R; ++t) k = std::max({k, (int)zs[t].size(), (int)xs[t].size()});
+  SepGeom sg;
+  if (!terms_geom(st, k, &sg)) return hipErrorNotSupported;
+  for (const void *p : {(const void *)in, (const void *)out, (const void *)last_op, (const void *)st.acc})
+    if (!aligned16(p)) return hipErrorNotSupported;
+  const int kind = forward ? 0 : 1;
+  hipError_t e = hipSuccess;
+  for (int t = 0; t < R && e == hipSuccess;) {
+    const float *aux0 = t == 0 ? nullptr : st.acc;
+    if (R - t >= 2) {
+      const bool last = R - t == 2;
+      const int ep = !last ? kEpTermsSum : (forward ? kEpTermsRatio : kEpTermsUpdate);
+      const std::vector<float> fz[2] = {zs[t], zs[t + 1]}, fx[2] = {xs[t], xs[t + 1]};
+      e = terms_pass(st, sg, ep, in, fz, fx, last ? out : st.acc, aux0, last ? last_op : nullptr, w, kind);
+      t += 2;
+    } else {
+      e = single_pass(st, forward ? kEpAccumRatio : kEpAccumUpdate, in, zs[t], xs[t], out, nullptr, st.acc, last_op,
+                      nullptr, w, kind);
+      t += 1;
+    }
+  }
+  return e;
+}
+
 // A forward pass of view v whose PSF is a sum of rank-one terms: b = Σ_t ψ ⊛
-// (pz_t ⊗ px_t), term by term into the partial-sum planes, the last term
-// finishing r_v = φ_v / b (φ_v from the staged float32 planes).
+// (pz_t ⊗ px_t), two terms per launch (or term by term) into the partial-sum
+// planes, the last launch finishing r_v = φ_v / b (φ_v from the staged float32
+// planes).
 hipError_t lowrank_forward(const RunState &st, const float *psi, const float *phi, float *rv, int v) {
   const ViewPsf &w = st.c->views[v];
   const int R = (int)w.lpz.size();
   if (R < 2 || !st.acc || !phi) return hipErrorInvalidValue;
+  const hipError_t ep = lowrank_pairs(st, w.lpz, w.lpx, psi, rv, phi, 1.f, true);
+  if (ep != hipErrorNotSupported) return ep;
   for (int t = 0; t < R; ++t) {
     const bool last = t == R - 1;
     const int ep = t == 0 ? kEpStore : (last ? kEpAccumRatio : kEpAccum);
@@ -1059,11 +1132,14 @@ hipError_t lowrank_forward(const RunState &st, const float *psi, const float *ph
 }
 
 // A backward pass of view v whose back-projector is a sum of rank-one terms:
-// q = Σ_t r_v ⊛ (xz_t ⊗ xx_t), the last term finishing ψ_out = ψ_in · (w q + 1 − w).
+// q = Σ_t r_v ⊛ (xz_t ⊗ xx_t), two terms per launch (or term by term), the last
+// launch finishing ψ_out = ψ_in · (w q + 1 − w).
 hipError_t lowrank_backward(const RunState &st, const float *rv, const float *psi_in, float *psi_out, int v) {
   const ViewPsf &w = st.c->views[v];
   const int R = (int)w.lxz.size();
   if (R < 2 || !st.acc) return hipErrorInvalidValue;
+  const hipError_t ep = lowrank_pairs(st, w.lxz, w.lxx, rv, psi_out, psi_in, weight_of(st, v), false);
+  if (ep != hipErrorNotSupported) return ep;
   for (int t = 0; t < R; ++t) {
     const bool last = t == R - 1;
     const int ep = t == 0 ? kEpStore : (last ? kEpAccumUpdate : kEpAccum);

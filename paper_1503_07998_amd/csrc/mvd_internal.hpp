@@ -132,6 +132,12 @@ constexpr int kEpAccum = 4;   // out = aux0 + conv
 // the earlier terms):
 constexpr int kEpAccumRatio = 6;   // b = aux0 + conv; out = φ / b (guarded), φ float32 at aux1
 constexpr int kEpAccumUpdate = 7;  // q = aux0 + conv; out = ψ · (w q + 1 − w), ψ at aux1 (may be out)
+// Two terms of one kernel in one launch (nviews = 2: tz/tx of both terms, one
+// input; the outputs, operands and weight of slot 0; aux0 may be null):
+constexpr int kEpTermsSum = 8;     // out = [aux0 +] conv_0 + conv_1
+constexpr int kEpTermsRatio = 9;   // b = [aux0 +] conv_0 + conv_1; out = φ / b (guarded), φ float32 at aux1
+constexpr int kEpTermsUpdate = 10; // q = [aux0 +] conv_0 + conv_1; out = ψ · (w q + 1 − w), ψ at aux1
+__host__ __device__ constexpr bool ep_terms(int ep) { return ep >= kEpTermsSum && ep <= kEpTermsUpdate; }
 
 // Launch configuration chosen by the host for a separable pass.
 struct SepPlan {

@@ -53,7 +53,7 @@ def test_traffic_record_guard():
     matches; a record for another workload name does not exist."""
     rec = json.load(open(os.path.join(ROOT, "profiles", "sep_passes_vol512_traffic.json")))
     got = bench.measured_traffic("vol512", "backward")
-    same = rec["kernel_code_sha256"] == bench.pass_code_hash()
+    same = rec.get("code_sha256", {}).get("sep") == bench.pass_code_hash("sep")
     assert (got is not None) == same
     if got is not None:
         assert got["bytes"] > 0 and "backward" in got["instance"]

@@ -672,6 +672,32 @@ def test_low_rank_psfs_match_oracle(case):
     assert rel_err(got, kxk) <= 1e-5
 
 
+@pytest.mark.parametrize("case", LOW_RANK_CASES[:4], ids=[f"lr{i}" for i in range(4)])
+def test_low_rank_term_pairs_equal_single_terms(case):
+    """Two terms per launch (their sum after the partial sum, in term order)
+    equals one launch per term bitwise, for ranks 2 to 6 (trailing single terms
+    and middle pairs included)."""
+    import ctypes
+
+    from paper_1503_07998_amd import _native as N
+
+    Y, Z, X, shapes, boundary, update, weights = case
+    _say(f"low rank pairs vs single terms Y={Y} Z={Z} X={X} k={shapes}")
+    rng = np.random.default_rng(zlib.crc32(repr(case).encode()) + 1)
+    psfs = [_low_rank_psf(rng, kz, kx, r) for kz, kx, r in shapes]
+    stacks = [rng.uniform(10.0, 300.0, (Z, Y, X)).astype(np.float32) for _ in shapes]
+    lib = N.lib()
+    lib.mvd_internal_set_tune.argtypes = [ctypes.c_char_p]
+    try:
+        lib.mvd_internal_set_tune(b"terms=0")
+        one = gpu_run(stacks, psfs, 3, boundary=boundary, update=update, weights=weights)
+        lib.mvd_internal_set_tune(b"terms=1")
+        two = gpu_run(stacks, psfs, 3, boundary=boundary, update=update, weights=weights)
+    finally:
+        lib.mvd_internal_set_tune(None)
+    np.testing.assert_array_equal(two, one)
+
+
 def test_low_rank_full_plane_size():
     """Two 512×512 planes of the vol512 shape with rank-two 31×31 PSFs (a main
     lobe and a weaker, wider offset lobe per view), 10 iterations, against the
