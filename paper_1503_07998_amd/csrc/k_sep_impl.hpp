@@ -969,8 +969,8 @@ hipError_t backward_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s
 // first half keeps view 0's ring and second half view 1's, one ring per thread
 // (one column each), so it fits 128 VGPRs and runs 4 waves/SIMD.  With 16-row
 // groups the row pass has one item per thread covering both views:
-// ψ' = ψ · c_0 · c_1 as in the two-plane pass.  Whole rows, one column per
-// thread, X ≤ 512.
+// ψ' = ψ · c_0 · c_1 as in the two-plane pass.  Whole rows of X ≤ 512, or
+// strips with halo columns whose ring columns fit a half.
 // ---------------------------------------------------------------------------
 template <int KB, int VM, int EB, int u>
 __device__ __forceinline__ void bwd_split_group(KArg *a, const Geo &o, const Cols<1, Shape<KB>::R> &cl, float *lds,
@@ -1018,7 +1018,7 @@ __global__ void __launch_bounds__(2 * kSepMaxThreads, 4) sep_backward_split_kern
   const int view = t / half, tc = t - view * half;   // wave-uniform view
   const Geo o = tile_geo(a, logical_block());
   const Cols<1, R> cl(a, o, tc, half);
-  zero_pads<R>(lds, 2 * 2 * G, a, t, nt);
+  if (a->halo == 0) zero_pads<R>(lds, 2 * 2 * G, a, t, nt);
   const int nxb = (o.xout + NX - 1) / NX;
   float *tt = lds + 2 * 2 * G * a->ldsw;
   fill_tap_table<KB>(tt, a, 2, t, nt);
@@ -1034,8 +1034,10 @@ __global__ void __launch_bounds__(2 * kSepMaxThreads, 4) sep_backward_split_kern
 
 template <int KB>
 hipError_t backward_split_bucket(const SepPassArgs &a, const SepPlan &p, hipStream_t s) {
-  // 128-bit row-pass accesses only (the element-wise form would not fit 128 VGPRs)
-  if (p.cols != 1 || p.vin != 2 || a.halo != 0 || a.nviews != 2 || !a.vec) return hipErrorInvalidValue;
+  // 128-bit row-pass accesses only (the element-wise form would not fit 128 VGPRs);
+  // each half holds one ring column per thread
+  if (p.cols != 1 || p.vin != 2 || a.nviews != 2 || !a.vec || a.ncols > (int)(p.threads / 2))
+    return hipErrorInvalidValue;
   const size_t lds = lds_bytes<KB>(a, 2);
   // (the plain update only: no registers are left for the epilogue variants)
   if (a.nsz[0] || a.wpl[0]) return hipErrorInvalidValue;

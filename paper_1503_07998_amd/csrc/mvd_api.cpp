@@ -645,11 +645,12 @@ size_t split_lds_bytes(const SepGeom &sg) {
   return sizeof(float) * (2ull * 2 * kSplitRows * sg.ldsw + 2ull * 8 * ((sg.plan.bucket + 3 + 3) / 4 * 4));
 }
 
-// Geometry of the split-view form from a two-plane plan, or false where it does
-// not apply (strips, several columns per thread, > 31 taps, periodic, LDS).
+// Geometry of the split-view form from a one-column plan (whole rows, or strips
+// with halo columns), or false where it does not apply (several columns per
+// thread, > 31 taps, periodic, LDS).
 bool split_geom(const SepGeom &sg, PlaneGeom g, int boundary, SepGeom *out) {
-  if (sg.halo != 0 || sg.plan.cols != 1 || sg.plan.bucket > 31 || boundary != MVD_BOUNDARY_ZERO ||
-      sg.plan.threads > kSepMaxThreads)
+  if (sg.plan.cols != 1 || sg.plan.bucket > 31 || boundary != MVD_BOUNDARY_ZERO ||
+      sg.plan.threads > kSepMaxThreads || sg.ncols > sg.plan.threads)
     return false;
   SepGeom sp = sg;
   sp.zseg = round_up(sg.zseg, kSplitRows);
@@ -899,15 +900,29 @@ hipError_t backward_views(const RunState &st, const float *const *r, const float
     if (two) sg.plan.occ = 2;   // two rings: 256-VGPR budget
     if (st.tn->bwd_occ && sg.plan.threads <= kSepMaxThreads) sg.plan.occ = st.tn->bwd_occ;
     // split-view form (two planes per launch in one 1024-thread work-group):
-    // whole rows of ≤ 512 columns, zero boundary, ≤ 31 taps, 128-bit accesses
-    SepGeom sp = sg;
+    // rows of ≤ 512 columns, or strips of one ring column per thread, zero
+    // boundary, ≤ 31 taps, 128-bit accesses.  Where the pass's own plan takes
+    // two columns per thread (rows wider than 512), the split form plans its
+    // own one-column strips.
     // (not with the EM normalisation: the split form has no registers left for it)
-    const bool split =
-        two && !st.normalize && !st.wpl && st.tn->bwd_split != 2 && split_geom(sg, st.g, st.boundary, &sp);
+    SepGeom sp = sg;
+    bool split = false;
+    if (n >= 2 && !st.normalize && !st.wpl && st.tn->bwd_split != 2 && st.tn->bwd_vin != 1 &&
+        (two || sg.plan.cols != 1)) {
+      SepGeom base = sg;
+      if (!two) {
+        Tune t1 = *st.tn;
+        t1.cols = 1;
+        base = plan_sep(c, st.g.Y, sep_bucket(kmax), st.boundary, t1);
+      }
+      bool al = aligned16(cur) && aligned16(psi_out);
+      for (int v = v0; v < v0 + n; ++v) al = al && aligned16(r[v]);
+      split = al && split_geom(base, st.g, st.boundary, &sp) && whole_items(sp, st.g);
+    }
+    if (split) sg.plan.vin = 2;
     for (int b = v0; b < v0 + n; b += sg.plan.vin) {
       const int nb = std::min(sg.plan.vin, v0 + n - b);
-      const bool use_split = split && nb == 2 && whole_items(sp, st.g) && aligned16(cur) && aligned16(psi_out) &&
-                             aligned16(r[b]) && aligned16(r[b + 1]);
+      const bool use_split = split && nb == 2;
       const SepGeom &gm = use_split ? sp : sg;
       SepPlan plan = gm.plan;
       plan.vin = nb;
@@ -2788,7 +2803,12 @@ int mvd_internal_corr_plan(int n_planes, int Z, int X, int kz, int kx, long *out
 // plan; returns MVD_ERR_UNSUPPORTED where the form does not apply).
 int mvd_internal_split_plan(const mvd_ctx *c, int n_planes, int k, int *out) {
   if (!c || !out || n_planes < 1 || k < 1 || k > MVD_MAX_K) return MVD_ERR_ARG;
-  const SepGeom sg = plan_sep(c, n_planes, sep_bucket(k), MVD_BOUNDARY_ZERO);
+  SepGeom sg = plan_sep(c, n_planes, sep_bucket(k), MVD_BOUNDARY_ZERO);
+  if (sg.plan.cols != 1) {   // the split form's own one-column strips
+    Tune t1 = tune();
+    t1.cols = 1;
+    sg = plan_sep(c, n_planes, sep_bucket(k), MVD_BOUNDARY_ZERO, t1);
+  }
   SepGeom sp;
   if (!split_geom(sg, PlaneGeom{n_planes, c->Z, c->X}, MVD_BOUNDARY_ZERO, &sp)) return MVD_ERR_UNSUPPORTED;
   const int v[13] = {sp.plan.bucket, sp.plan.cols, sp.plan.threads, sp.plan.occ, sp.zseg, sp.nseg, sp.x_out,

@@ -187,12 +187,14 @@ def test_matrix_core_general_pass_in_bounds(kz):
 
 
 @pytest.mark.parametrize("shape", [(2, 1, 37), (3, 8, 8), (4, 37, 53), (2, 70, 100), (2, 13, 200), (1, 12, 512),
-                                   (32, 128, 128), (512, 512, 512), (256, 256, 256), (3, 33, 511), (2, 41, 1)],
+                                   (32, 128, 128), (512, 512, 512), (256, 256, 256), (3, 33, 511), (2, 41, 1),
+                                   (2, 13, 520), (2, 24, 700), (2, 16, 1100), (3, 64, 2048), (1, 7, 1023)],
                          ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("k", [1, 5, 9, 15, 21, 31])
 def test_split_view_backward_in_bounds(shape, k):
     """The split-view backward form: 1024-thread work-groups, half the threads
-    per view (one column each), 16-row groups, both views' buffers in LDS."""
+    per view (one ring column each), 16-row groups, both views' buffers in LDS;
+    whole rows up to 512 columns, wider rows in strips with halo columns."""
     Y, Z, X = shape
     GS = 16
     ctx = api.mvd_create(1, Z, X, N.MVD_DEVICE_NONE)
@@ -205,9 +207,6 @@ def test_split_view_backward_in_bounds(shape, k):
         st = lib.mvd_internal_split_plan(ctx, Y, k, out)
     finally:
         api.mvd_destroy(ctx)
-    if X > 512:
-        assert st == N.MVD_ERR_UNSUPPORTED
-        return
     assert st == 0
     keys = ["bucket", "cols", "threads", "occ", "zseg", "nseg", "x_out", "nstrip", "halo", "ncols", "ldsw", "vec",
             "lds"]
@@ -215,18 +214,32 @@ def test_split_view_backward_in_bounds(shape, k):
     KB, nt, ldsw = p["bucket"], p["threads"], p["ldsw"]
     R = (KB - 1) // 2
     half = nt // 2
-    assert nt <= 1024 and nt % 128 == 0 and p["halo"] == 0 and p["nstrip"] == 1 and p["cols"] == 1
-    assert half >= X, "each half must hold one column per thread"
+    halo = p["halo"] != 0
+    assert nt <= 1024 and nt % 128 == 0 and p["cols"] == 1 and p["occ"] == 4
     assert p["zseg"] % GS == 0 and p["nseg"] * p["zseg"] >= Z and (p["nseg"] - 1) * p["zseg"] < Z
+    assert p["nstrip"] * p["x_out"] >= X and (p["nstrip"] - 1) * p["x_out"] < X
     NK = (KB + 3 + 3) // 4 * 4
     assert p["lds"] == 4 * (2 * 2 * GS * ldsw + 2 * 8 * NK) <= LDS_LIMIT
-    # columns: LDS column lc + R of each view's rows, pads R and beyond X
-    assert R + X <= ldsw
-    nxb = (X + NX - 1) // NX
-    assert GS * nxb <= nt or True      # items beyond the threads loop
+    if not halo:
+        assert p["nstrip"] == 1 and half >= X and R + X <= ldsw
     NIN4 = (NX + KB - 1 + 3) // 4
-    for xb in range(nxb):
-        assert xb * NX + 4 * NIN4 <= ldsw
+    for strip in range(p["nstrip"]):
+        xo0 = strip * p["x_out"]
+        xout = min(p["x_out"], X - xo0)
+        ncz = xout + 2 * R if halo else xout
+        assert ncz <= half, "each half must hold one ring column per thread"
+        for lc in range(ncz):
+            x = xo0 - R + lc if halo else lc
+            gx = x if 0 <= x < X else 0
+            assert 0 <= gx < X
+            lcol = lc if halo else lc + R
+            assert 0 <= lcol < ldsw
+        nxb = (xout + NX - 1) // NX
+        for xb in range(nxb):
+            ox = xb * NX
+            assert ox + 4 * NIN4 <= ldsw, "row-pass LDS read past the row"
+            if p["vec"]:
+                assert xo0 + ox + NX <= X
     # row-pass LDS rows: (view·16 + g) of buffer (i & 1), g < 16
     assert (2 * GS + GS) * ldsw <= 2 * 2 * GS * ldsw   # view 1, row 15 of buffer 0 within both buffers
 
