@@ -419,11 +419,17 @@ def bench_mix(args):
 
 
 def bench_calibrate(args):
-    """A kernel of known traffic for calibrating the HBM byte counters: the
-    reslice of a float32 camera stack of 1 GiB into float32 planes (every
-    element read once and written once)."""
+    """Kernels of known traffic.  The reslice of a float32 camera stack of
+    1 GiB into float32 planes (every element read once and written once)
+    calibrates the HBM byte counters; a plain copy of the same 1 GiB and a
+    read-only sweep of it (16 bytes per lane, the library's calibration
+    kernels) give the bandwidth a streaming kernel reaches on the device,
+    the yardstick beside the 8 TB/s peak."""
+    import ctypes
+
     import torch
 
+    from paper_1503_07998_amd import _native as N
     from paper_1503_07998_amd import api
 
     Z, Y, X = 1024, 256, 1024    # 2^28 float32 values = 1 GiB
@@ -431,25 +437,45 @@ def bench_calibrate(args):
     g = torch.Generator(device=dev).manual_seed(3)
     stack = torch.rand((Z, Y, X), generator=g, device=dev)
     planes = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
-    ctx = api.mvd_create(1, Z, X, 0)
-    try:
+    nbytes = Z * Y * X * 4
+    lib = N.lib()
+    probe = lib.mvd_internal_stream_probe
+    probe.restype = ctypes.c_int
+    probe.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def run_probe(kind):
+        st = probe(kind, stack.data_ptr(), planes.data_ptr(), nbytes, stream)
+        if st != 0:
+            raise N.MvdError(st, f"stream probe {kind} failed")
+
+    def timed(fn):
         for _ in range(args.warmup):
-            api.mvd_reslice(ctx, stack, Y, planes)
+            fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            api.mvd_reslice(ctx, stack, Y, planes)
+            fn()
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    ctx = api.mvd_create(1, Z, X, 0)
+    try:
+        ms = timed(lambda: api.mvd_reslice(ctx, stack, Y, planes))
     finally:
         api.mvd_destroy(ctx)
-    nbytes = Z * Y * X * 4
-    print(json.dumps({"metric": "GB/s", "value": 2 * nbytes / (ms / 1e3) / 1e9, "unit": "GB/s", "n_gpus": 1,
+    ms_copy = timed(lambda: run_probe(0))
+    ms_read = timed(lambda: run_probe(1))
+    rates = {"reslice_GBps": 2 * nbytes / (ms / 1e3) / 1e9, "copy_GBps": 2 * nbytes / (ms_copy / 1e3) / 1e9,
+             "read_GBps": nbytes / (ms_read / 1e3) / 1e9}
+    log("calibration: " + ", ".join(f"{k} {v:.0f}" for k, v in rates.items()))
+    print(json.dumps({"metric": "GB/s", "value": rates["reslice_GBps"], "unit": "GB/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
                       "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": "reslice of a 1 GiB float32 stack (1024 slices of 256x1024) into "
                                              "planes: counter calibration, 1 GiB read + 1 GiB written per launch"},
-                      "bytes_read": nbytes, "bytes_written": nbytes}), flush=True)
+                      "bytes_read": nbytes, "bytes_written": nbytes, "streaming": rates,
+                      "ms_copy": ms_copy, "ms_read": ms_read}), flush=True)
 
 
 def bench_stream(args, spec):

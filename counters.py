@@ -11,7 +11,8 @@ a 1 GiB float32 stack: 1 GiB read and 1 GiB written per launch).  The counters
 give KiB per dispatch; each is scaled by the factor that makes the calibration
 kernel's reading equal its known traffic.  A second kernel of known size, the
 first kernel of the bench run (ψ^0 from two uint16 views: 4 B read and 4 B
-written per voxel), is reported beside it as a cross-check.
+written per voxel), is reported beside it as a cross-check, and so is the
+calibration run's plain copy of the same 1 GiB.
 """
 from __future__ import annotations
 
@@ -88,12 +89,20 @@ def main():
         kv = kernels[sv[0]]
         check = {"kernel": sv[0], "expected_read": 4 * a.voxels, "expected_write": 4 * a.voxels,
                  "read_ratio": kv["fetch_bytes"] / (4 * a.voxels), "write_ratio": kv["write_bytes"] / (4 * a.voxels)}
+    # second cross-check from the calibration run itself: the plain copy of the
+    # same 1 GiB (probe_copy_kernel), scaled by the reslice's factors
+    copy_check = None
+    pc = [k for k in cf if "probe_copy_kernel" in k and k in cw]
+    if pc:
+        copy_check = {"kernel": pc[0], "read_ratio": cf[pc[0]] * kib * fetch_factor / cal_bytes,
+                      "write_ratio": cw[pc[0]] * kib * write_factor / cal_bytes}
     rec = {
         "code_sha256": {f: bench.pass_code_hash(f) for f in bench.PASS_SOURCES},
         "calibration": {"kernel": ck[0], "bytes_read": cal_bytes, "bytes_written": cal_bytes,
                         "fetch_kib": cf[ck[0]], "write_kib": cw[ck[0]]},
         "fetch_factor": fetch_factor, "write_factor": write_factor,
         "cross_check": check,
+        "copy_check": copy_check,
         "kernels": kernels,
         "commands": a.command,
     }
@@ -105,6 +114,9 @@ def main():
     if check:
         print(f"cross-check {check['kernel'][:60]}: read {check['read_ratio']:.3f}, write {check['write_ratio']:.3f} "
               f"of the known traffic")
+    if copy_check:
+        print(f"copy check {copy_check['kernel'][:60]}: read {copy_check['read_ratio']:.3f}, "
+              f"write {copy_check['write_ratio']:.3f} of the known traffic")
     for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["trace_calls"])[:8]:
         print(f"- `{k[:70]}`: {v['fetch_bytes'] / 1e9:.3f} GB read + {v['write_bytes'] / 1e9:.3f} GB written "
               f"= {v['traffic_bytes'] / 1e9:.3f} GB per launch; {v['trace_calls']} calls, "

@@ -6,7 +6,8 @@
  * tests can check every index the kernels compute against its buffer, and let
  * one process switch the launch-shape overrides that the MVD_TUNE environment
  * variable otherwise sets once.  They may change with MVD_TESTING_VERSION;
- * callers check mvd_internal_version() first.  None of them touches a device.
+ * callers check mvd_internal_version() first.  Only mvd_internal_batch_raise_giveup
+ * and mvd_internal_stream_probe touch a device.
  * Return values are mvd_status codes (0 ok, MVD_ERR_ARG on a bad argument,
  * MVD_ERR_UNSUPPORTED where the asked-for form does not apply).
  */
@@ -21,7 +22,7 @@
 extern "C" {
 #endif
 
-#define MVD_TESTING_VERSION 1
+#define MVD_TESTING_VERSION 2
 
 /* MVD_TESTING_VERSION of the library. */
 int mvd_internal_version(void);
@@ -92,6 +93,16 @@ long mvd_internal_pq_order(int n_jobs, const int *n_planes, const int *nseg, con
  * run, made for MVD_FLAG_TUNE) would use, or 0 when the run makes no probe
  * (n_iters = 0).  Never more than mvd_workspace_bytes() of the same run. */
 int mvd_internal_tune_probe_bytes(const mvd_ctx *ctx, const mvd_run *run, size_t *bytes);
+
+/* Calibration kernels of known traffic, launched on `stream` (a hipStream_t,
+ * NULL for the null stream) of the current device: kind 0 copies `bytes` from
+ * src to dst, reading and writing every byte once; kind 1 only reads them
+ * (dst then receives at most 2048 floats, and only for data holding NaNs).
+ * bytes is a multiple of 16, src and dst 16-byte aligned device buffers.
+ * They give the bandwidth a plain streaming kernel reaches on the device, the
+ * yardstick beside the peak for the passes.  Returns MVD_OK, MVD_ERR_ARG or
+ * MVD_ERR_LAUNCH (asynchronous: completion is the stream's). */
+int mvd_internal_stream_probe(int kind, const void *src, void *dst, size_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

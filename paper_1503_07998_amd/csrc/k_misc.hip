@@ -121,6 +121,47 @@ __global__ void __launch_bounds__(NT) copy_kernel(const float *__restrict__ src,
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) dst[i] = src[i];
 }
 
+// Calibration kernels of known traffic (the bandwidth a plain streaming
+// kernel reaches, against which the passes are judged): a copy that reads and
+// writes every 16-byte unit once, and a read-only sweep whose sums are stored
+// only where they hold the all-ones bit pattern (never, for finite data), so it
+// writes nothing while the compiler must still load every unit.  Each thread
+// moves kProbeU units per step, 16 bytes per lane per access.
+constexpr int kProbeU = 4;
+
+__global__ void __launch_bounds__(NT) probe_copy_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                         size_t n) {
+  const size_t step = (size_t)gridDim.x * NT * kProbeU;
+  size_t i = (size_t)blockIdx.x * NT * kProbeU + threadIdx.x;
+  for (; i + (kProbeU - 1) * NT < n; i += step) {
+    float4 v[kProbeU];
+#pragma unroll
+    for (int u = 0; u < kProbeU; ++u) v[u] = src[i + u * NT];
+#pragma unroll
+    for (int u = 0; u < kProbeU; ++u) dst[i + u * NT] = v[u];
+  }
+  for (; i < n; i += NT) dst[i] = src[i];   // the last partial step
+}
+
+__global__ void __launch_bounds__(NT) probe_read_kernel(const float4 *__restrict__ src, float *__restrict__ dst,
+                                                         size_t n) {
+  const size_t step = (size_t)gridDim.x * NT * kProbeU;
+  size_t i = (size_t)blockIdx.x * NT * kProbeU + threadIdx.x;
+  float s = 0.f;
+  for (; i + (kProbeU - 1) * NT < n; i += step) {
+#pragma unroll
+    for (int u = 0; u < kProbeU; ++u) {
+      const float4 v = src[i + u * NT];
+      s += (v.x + v.y) + (v.z + v.w);
+    }
+  }
+  for (; i < n; i += NT) {
+    const float4 v = src[i];
+    s += (v.x + v.y) + (v.z + v.w);
+  }
+  if (__float_as_uint(s) == 0xffffffffu) dst[blockIdx.x] = s;
+}
+
 unsigned grid_for(size_t work) {
   size_t b = (work + NT - 1) / NT;
   if (b > 65536) b = 65536;   // grid-stride beyond this
@@ -179,6 +220,21 @@ hipError_t launch_fill(float *dst, size_t n, float value, hipStream_t s) {
 
 hipError_t launch_copy(const float *src, float *dst, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(NT), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(int kind, const void *src, void *dst, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 16;
+  if (n == 0) return hipSuccess;
+  // 8 work-groups of NT threads per CU (2048 on 256 CUs), grid-stride beyond
+  const unsigned blocks = (unsigned)std::min<size_t>((n + (size_t)NT * kProbeU - 1) / ((size_t)NT * kProbeU),
+                                                     kProbeBlocks);
+  if (kind == 0)
+    hipLaunchKernelGGL(probe_copy_kernel, dim3(blocks), dim3(NT), 0, s, static_cast<const float4 *>(src),
+                       static_cast<float4 *>(dst), n);
+  else
+    hipLaunchKernelGGL(probe_read_kernel, dim3(blocks), dim3(NT), 0, s, static_cast<const float4 *>(src),
+                       static_cast<float *>(dst), n);
   return hipGetLastError();
 }
 

@@ -2779,6 +2779,16 @@ int mvd_internal_tune_probe_bytes(const mvd_ctx *c, const mvd_run *r, size_t *by
   return MVD_OK;
 }
 
+// Calibration hook (mvd_testing.h): a copy (kind 0) or read-only sweep (kind 1)
+// of `bytes` on the caller's stream.
+int mvd_internal_stream_probe(int kind, const void *src, void *dst, size_t bytes, void *stream) {
+  if ((kind != 0 && kind != 1) || !src || !dst || bytes % 16 != 0 || !aligned16(src) || !aligned16(dst))
+    return MVD_ERR_ARG;
+  return launch_stream_probe(kind, src, dst, bytes, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? MVD_OK
+             : MVD_ERR_LAUNCH;
+}
+
 // Test hook (mvd_testing.h): replace the process-wide launch-shape overrides (the MVD_TUNE
 // syntax; NULL: re-read the environment).  Lets one process compare the
 // alternative forms of a pass; not thread-safe against running calls.

@@ -219,6 +219,11 @@ hipError_t launch_init_mean(const float *const *phis, int nv, size_t n, float *d
                             hipStream_t s);
 hipError_t launch_fill(float *dst, size_t n, float value, hipStream_t s);
 hipError_t launch_copy(const float *src, float *dst, size_t n, hipStream_t s);
+// Calibration kernels: kind 0 copies `bytes` from src to dst, kind 1 reads
+// them (dst: kProbeBlocks floats, written only for non-finite sums).  bytes is
+// a multiple of 16, both pointers 16-byte aligned.
+constexpr int kProbeBlocks = 2048;
+hipError_t launch_stream_probe(int kind, const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // Work-group / LDS parameters of the separable kernels (shared by launchers
 // and the host planner).

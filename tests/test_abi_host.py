@@ -482,6 +482,19 @@ def test_library_exports_every_testing_hook():
     assert lib.mvd_internal_version() == want
 
 
+def test_stream_probe_rejects_bad_arguments():
+    """The calibration hook refuses, before any launch, an unknown kind, null
+    or misaligned buffers and sizes that are not whole 16-byte units."""
+    lib = N.lib()
+    f = lib.mvd_internal_stream_probe
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    a, b = 1 << 20, 1 << 21      # addresses only: never dereferenced on these paths
+    for kind, src, dst, n in ((2, a, b, 64), (-1, a, b, 64), (0, None, b, 64), (1, a, None, 64),
+                              (0, a + 4, b, 64), (1, a, b + 8, 64), (0, a, b, 24), (1, a, b, 17)):
+        assert f(kind, src, dst, n, None) == N.MVD_ERR_ARG, (kind, src, dst, n)
+
+
 def test_tune_probe_fits_the_reported_workspace():
     """The tuner's one-iteration probe never needs more workspace than the run
     reports (a run without iterations makes no probe at all)."""
