@@ -12,6 +12,10 @@ of Supplementary Note 2 §1, with view weights tempering each correction:
 Given ∂L/∂ψ^T this module returns ∂L/∂P_v, ∂L/∂X_v (K×K taps), ∂L/∂w_v and
 ∂L/∂ψ^0 by running the chain rule backwards through every step, recomputing the
 intermediates of iteration t from the stored ψ^t (per-iteration checkpoints).
+A weight w_v may be a per-pixel array (the per-pixel, per-view weights of the
+memory table in Supplementary Note 2, read as the same tempering pixel by
+pixel); its gradient is then the per-pixel array ∂L/∂w_v(pixel) = Σ_t c̄_v·(q_v − 1)
+instead of that array's sum.
 
 Tap derivatives follow from differentiating the convolution sum
 (a ⊛ k)[z][x] = Σ k[j][i] ã[z+Rz−j][x+Rx−i]:  ∂/∂k[j][i] = ã[z+Rz−j][x+Rx−i],
@@ -54,7 +58,8 @@ def _factors(psi, phis, psfs, backs, ws, boundary, method="direct"):
 def _view_adjoint(cbar, psi, phi_parts, p, x, w, boundary, gp, gx, method="direct"):
     """Back-propagate c̄ of one view into ψ̄ (returned) and the tap/weight gradients."""
     b, m, r, q, _ = phi_parts
-    gw = float(np.sum(cbar * (q - 1.0)))
+    # ∂c/∂w = q − 1, pixel by pixel; a scalar weight collects the sum
+    gw = cbar * (q - 1.0) if np.ndim(w) else float(np.sum(cbar * (q - 1.0)))
     qbar = w * cbar
     rbar = conv2d(qbar, flip(x), boundary, method)
     gx += tap_gradient(qbar, r, x.shape, boundary)
@@ -81,11 +86,15 @@ def forward_history(phis, psfs, backs, weights, iters, update=SIMULTANEOUS, boun
 def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, boundary=ZERO,
             psi0=None, history=None, method="direct"):
     """Reverse sweep.  Returns dict(grad_psf=[V×K×K], grad_back=[V×K×K],
-    grad_weights=[V], grad_psi0=array)."""
+    grad_weights=[V], grad_psi0=array).  With a per-pixel weight array among
+    the weights, grad_weights is a list whose entry v is a float for a scalar
+    w_v and an array of w_v's shape for an array w_v."""
     nv = len(phis)
     ps = [np.asarray(p, dtype=np.float64) for p in psfs]
     xs = [np.asarray(x, dtype=np.float64) for x in backs]
-    ws = [1.0] * nv if weights is None else [float(w) for w in weights]
+    ws = [1.0] * nv if weights is None else [np.asarray(w, dtype=np.float64) if np.ndim(w) else float(w)
+                                             for w in weights]
+    per_pixel = any(np.ndim(w) for w in ws)
     hist = history if history is not None else forward_history(phis, ps, xs, ws, iters, update, boundary, psi0,
                                                                method)
     gp = [np.zeros_like(p) for p in ps]
@@ -126,7 +135,7 @@ def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, bo
                 gw[v] += g
         else:
             raise ValueError(update)
-    return dict(grad_psf=gp, grad_back=gx, grad_weights=np.array(gw), grad_psi0=gbar)
+    return dict(grad_psf=gp, grad_back=gx, grad_weights=list(gw) if per_pixel else np.array(gw), grad_psi0=gbar)
 
 
 # ---------------------------------------------------------------------------

@@ -1,6 +1,8 @@
 """Pins of the oracle's reverse sweep: central finite differences in FP64,
 PyTorch CPU float64 autograd through an independent restatement of the forward
-map (torch's own convolution), and exact zeros where a view's weight is 0."""
+map (torch's own convolution), and exact zeros where a view's weight is 0.
+Per-pixel weight arrays are pinned the same ways, and a constant array must
+give, summed, the scalar weight's gradient."""
 import numpy as np
 import pytest
 
@@ -157,3 +159,73 @@ def test_gaussian_derivative_taps_match_differences():
                                atol=1e-9)
     from synthetic import gaussian_psf
     np.testing.assert_allclose(p, gaussian_psf(k, sx, sz), rtol=1e-14)
+
+
+def _pixel_weights(seed, shape, nv):
+    rng = np.random.default_rng(seed)
+    return [rng.uniform(0.3, 1.0, shape) for _ in range(nv)]
+
+
+@pytest.mark.parametrize("update", ["simultaneous", "sequential"])
+@pytest.mark.parametrize("boundary", ["zero", "periodic"])
+def test_pixel_weight_gradients_match_central_differences(update, boundary):
+    phis, psfs, backs, _, gout = _problem(5)
+    ws = _pixel_weights(6, gout.shape, 2)
+    T = 3
+    res = A.adjoint(phis, psfs, backs, ws, T, gout, update, boundary)
+    assert isinstance(res["grad_weights"], list) and res["grad_weights"][0].shape == gout.shape
+    rng = np.random.default_rng(7)
+    h = 1e-6
+    for v in range(2):
+        scale = max(1.0, np.abs(res["grad_weights"][v]).max())
+        for _ in range(5):
+            idx = tuple(int(rng.integers(n)) for n in gout.shape)
+            wp = [w.copy() for w in ws]
+            wm = [w.copy() for w in ws]
+            wp[v][idx] += h
+            wm[v][idx] -= h
+            fd = (_loss(phis, psfs, backs, wp, T, gout, update, boundary)
+                  - _loss(phis, psfs, backs, wm, T, gout, update, boundary)) / (2 * h)
+            assert abs(fd - res["grad_weights"][v][idx]) <= 1e-6 * scale, (v, idx, fd, res["grad_weights"][v][idx])
+        # the taps' gradients under per-pixel weights
+        j, i = 1, 2
+        plus = [t.copy() for t in psfs]
+        minus = [t.copy() for t in psfs]
+        plus[v][j, i] += h
+        minus[v][j, i] -= h
+        fd = (_loss(phis, plus, backs, ws, T, gout, update, boundary)
+              - _loss(phis, minus, backs, ws, T, gout, update, boundary)) / (2 * h)
+        assert abs(fd - res["grad_psf"][v][j, i]) <= 1e-6 * max(1.0, np.abs(res["grad_psf"][v]).max())
+
+
+@pytest.mark.parametrize("update", ["simultaneous", "sequential"])
+def test_pixel_weight_gradients_match_torch_autograd(update):
+    torch = pytest.importorskip("torch")
+    phis, psfs, backs, _, gout = _problem(8, shape=(2, 8, 11), kshapes=((3, 5), (5, 3), (3, 3)))
+    ws = _pixel_weights(9, gout.shape, 3)
+    ws[1] = 0.7                       # scalar and per-pixel weights mixed
+    T = 2
+    res = A.adjoint(phis, psfs, backs, ws, T, gout, update, "zero")
+    tphis = [torch.tensor(p, dtype=torch.float64) for p in phis]
+    tp = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in psfs]
+    tx = [torch.tensor(x, dtype=torch.float64, requires_grad=True) for x in backs]
+    tw = [torch.tensor(w, dtype=torch.float64, requires_grad=True) for w in ws]
+    psi = _torch_forward(torch, tphis, tp, tx, tw, T, update, "zero")
+    (psi * torch.tensor(gout)).sum().backward()
+    for v in range(3):
+        np.testing.assert_allclose(res["grad_psf"][v], tp[v].grad.numpy(), rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(res["grad_back"][v], tx[v].grad.numpy(), rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(res["grad_weights"][v], tw[v].grad.numpy(), rtol=1e-10, atol=1e-12)
+    assert np.ndim(res["grad_weights"][1]) == 0
+
+
+def test_constant_pixel_weights_sum_to_the_scalar_gradient():
+    phis, psfs, backs, _, gout = _problem(10)
+    for update in ("simultaneous", "sequential"):
+        scal = A.adjoint(phis, psfs, backs, [0.8, 0.6], 3, gout, update)
+        arr = A.adjoint(phis, psfs, backs, [np.full(gout.shape, 0.8), np.full(gout.shape, 0.6)], 3, gout, update)
+        for v in range(2):
+            assert abs(arr["grad_weights"][v].sum() - scal["grad_weights"][v]) <= 1e-9 * max(
+                1.0, abs(scal["grad_weights"][v]))
+            np.testing.assert_allclose(arr["grad_psf"][v], scal["grad_psf"][v], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(arr["grad_psi0"], scal["grad_psi0"], rtol=1e-12, atol=1e-14)
