@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define MVD_ABI_VERSION 2
+#define MVD_ABI_VERSION 3
 #define MVD_MAX_VIEWS 8
 #define MVD_MAX_K 63
 #define MVD_DEVICE_NONE (-1) /* host-only context: PSF setup and validation only */
@@ -145,8 +145,8 @@ typedef struct {
                                  per-pixel, per-view weights, Supplementary Note 2; their
                                  formula is not given).  Rank-one back-projectors and
                                  device-resident runs only: MVD_ERR_UNSUPPORTED with
-                                 K×K passes and in mvd_backward, MVD_ERR_ARG for streamed
-                                 runs.  Read only, kept alive until the stream is done. */
+                                 K×K passes, MVD_ERR_ARG for streamed runs.  Read only,
+                                 kept alive until the stream is done. */
 } mvd_run;
 
 /* Library version (MVD_ABI_VERSION). */
@@ -373,13 +373,40 @@ mvd_status mvd_backward_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, 
  *        or NULL.  Outputs are overwritten, in float32 from float64 sums in a
  *        fixed order (bitwise reproducible).
  * Every view's PSF and back-projector must be rank one (MVD_ERR_UNSUPPORTED
- * otherwise, and with MVD_FLAG_FORCE_2D).  Where a run of the same workload
- * was tuned (MVD_FLAG_TUNE) in this process, the passes take its launch shapes.
+ * otherwise, with MVD_FLAG_FORCE_2D and with MVD_FLAG_NORMALIZE).  Per-pixel
+ * weight planes (run->weight_planes) are taken as in the forward call: each
+ * pixel's correction tempered by o = w_v · ω_v(pixel); grad_weights is then
+ * ∂L/∂w_v with the planes held fixed (mvd_backward_grads also returns ∂L/∂ω_v).
+ * Where a run of the same workload was tuned (MVD_FLAG_TUNE) in this process,
+ * the passes take its launch shapes.
  * Errors: MVD_ERR_ARG, MVD_ERR_STATE, MVD_ERR_WORKSPACE, MVD_ERR_UNSUPPORTED,
  * MVD_ERR_DEVICE, MVD_ERR_LAUNCH. */
 mvd_status mvd_backward(mvd_ctx *ctx, const void *const *obs, const float *grad_est,
                         const mvd_run *run, float *const *grad_psf, float *const *grad_back,
                         float *grad_weights, float *grad_init, void *stream);
+
+/* The outputs of a reverse sweep (every field NULL: not computed). */
+typedef struct {
+  uint32_t struct_size;              /* sizeof(mvd_grads) */
+  float *const *grad_psf;            /* host array of V device pointers, float32 [kz][kx] */
+  float *const *grad_back;           /* host array of V device pointers, float32 [kz][kx] */
+  float *grad_weights;               /* device [V] */
+  float *grad_init;                  /* device [Y][Z][X] */
+  float *const *grad_weight_planes;  /* host array of V device pointers, float32 [Y][Z][X]:
+                                        ∂L/∂ω_v pixel by pixel, summed over the iterations
+                                        (float32 sums in iteration order); needs
+                                        run->weight_planes, 16-byte aligned for full speed */
+} mvd_grads;
+
+/* mvd_backward with its outputs in a struct, and the gradient of the
+ * per-pixel weight planes ω_v (the per-pixel, per-view weights of
+ * Supplementary Note 2's memory table, with the forward call's tempering
+ * o = w_v · ω_v): ∂L/∂ω_v(pixel) = Σ_t c̄_v(pixel) (q_v(pixel) − 1) w_v.
+ * Arguments and errors as mvd_backward; MVD_ERR_ARG also for a NULL `out`, a
+ * wrong struct_size, grad_weight_planes without run->weight_planes, or a NULL
+ * entry in it. */
+mvd_status mvd_backward_grads(mvd_ctx *ctx, const void *const *obs, const float *grad_est,
+                              const mvd_run *run, const mvd_grads *out, void *stream);
 
 /* ---- batched form --------------------------------------------------------
  * Several deconvolutions (volumes of different plane sizes, view counts and

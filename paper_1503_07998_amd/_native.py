@@ -97,6 +97,19 @@ class MvdFiles(ctypes.Structure):
     ]
 
 
+class MvdGrads(ctypes.Structure):
+    """Mirror of ``mvd_grads``."""
+
+    _fields_ = [
+        ("struct_size", c_uint32),
+        ("grad_psf", POINTER(c_void_p)),
+        ("grad_back", POINTER(c_void_p)),
+        ("grad_weights", c_void_p),
+        ("grad_init", c_void_p),
+        ("grad_weight_planes", POINTER(c_void_p)),
+    ]
+
+
 class MvdError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"mvd status {status}: {message}")
@@ -120,6 +133,8 @@ SIGNATURES = {
     "mvd_backward_workspace_bytes": (c_int, [c_void_p, POINTER(MvdRun), POINTER(c_size_t)]),
     "mvd_backward": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), POINTER(c_void_p),
                              POINTER(c_void_p), c_void_p, c_void_p, c_void_p]),
+    "mvd_backward_grads": (c_int, [c_void_p, POINTER(c_void_p), c_void_p, POINTER(MvdRun), POINTER(MvdGrads),
+                                   c_void_p]),
     "mvd_batch_create": (c_int, [POINTER(c_void_p), POINTER(MvdItem), c_int, c_uint32, c_void_p]),
     "mvd_batch_launch": (c_int, [c_void_p, c_void_p]),
     "mvd_batch_wait": (c_int, [c_void_p, c_void_p]),

@@ -17,7 +17,7 @@ __all__ = [
     "mvd_version", "mvd_create", "mvd_destroy", "mvd_set_psf", "mvd_get_back_taps",
     "mvd_psf_info", "mvd_workspace_bytes", "mvd_reslice", "mvd_deconvolve_planes",
     "mvd_get_timing", "mvd_last_error", "make_run", "Deconvolver", "deconvolve",
-    "mvd_backward_workspace_bytes", "mvd_backward", "mvd_batch_create", "mvd_batch_launch",
+    "mvd_backward_workspace_bytes", "mvd_backward", "mvd_backward_grads", "mvd_batch_create", "mvd_batch_launch",
     "mvd_batch_tuning", "mvd_batch_destroy", "mvd_batch_run", "Batch",
     "mvd_stream_workspace_bytes", "mvd_deconvolve_stream", "mvd_deconvolve_planes_static",
     "mvd_batch_wait", "mvd_batch_info",
@@ -241,6 +241,23 @@ def mvd_backward(ctx, obs, grad_est, run, grad_psf=None, grad_back=None, grad_we
                                  _dev_ptr(grad_weights) if grad_weights is not None else None,
                                  _dev_ptr(grad_init) if grad_init is not None else None,
                                  _stream_handle(stream)), ctx)
+
+
+def mvd_backward_grads(ctx, obs, grad_est, run, grad_psf=None, grad_back=None, grad_weights=None,
+                       grad_init=None, grad_weight_planes=None, stream=None) -> None:
+    """mvd_backward with the per-pixel weight planes' gradients as well
+    (`grad_weight_planes`: one float32 [Y][Z][X] device tensor per view)."""
+    ptrs = (c_void_p * len(obs))(*[_dev_ptr(o).value for o in obs])
+    keep = [_ptr_array(grad_psf), _ptr_array(grad_back), _ptr_array(grad_weight_planes)]
+    g = N.MvdGrads()
+    g.struct_size = ctypes.sizeof(N.MvdGrads)
+    g.grad_psf = ctypes.cast(keep[0], POINTER(c_void_p)) if keep[0] is not None else None
+    g.grad_back = ctypes.cast(keep[1], POINTER(c_void_p)) if keep[1] is not None else None
+    g.grad_weights = _dev_ptr(grad_weights).value if grad_weights is not None else None
+    g.grad_init = _dev_ptr(grad_init).value if grad_init is not None else None
+    g.grad_weight_planes = ctypes.cast(keep[2], POINTER(c_void_p)) if keep[2] is not None else None
+    N.check(N.lib().mvd_backward_grads(ctx, ptrs, _dev_ptr(grad_est), ctypes.byref(run), ctypes.byref(g),
+                                       _stream_handle(stream)), ctx)
 
 
 def _items(entries):

@@ -6,6 +6,11 @@
 //        c̄_v = ψ̄' · ψ · Π_{u≠v} c_u
 //        q̄_v = w_v c̄_v  (written over q_v)
 //        w̄_v += Σ c̄_v (q_v − 1)           (per-work-group partial sums)
+//    With per-pixel weight planes ω_v the tempering weight of a pixel is
+//    o_v = w_v ω_v (as in the forward update): c_v = o_v q_v + 1 − o_v,
+//    q̄_v = o_v c̄_v, w̄_v += Σ c̄_v (q_v − 1) ω_v and, where asked for,
+//    ω̄_v += c̄_v (q_v − 1) w_v pixel by pixel (summed over the iterations in
+//    the caller's buffer).
 //  * pointwise_seq: the same for one view of the sequential update.
 //  * corr: tap gradient Σ_{y,z,x} ḡ[y][z][x] · ã[y][z+R−j][x+R−i] for every
 //    lag (j, i) of a K×K kernel (ã zero or wrapped outside the plane): each
@@ -63,7 +68,9 @@ __device__ __forceinline__ void stv(float *p, size_t i, const float (&o)[VW]) {
 
 // NV views, VW elements per thread and step (4: every array 16-byte aligned and
 // n a multiple of 4).  Π_{u≠v} c_u is formed as (c_0 ⋯ c_{v−1}) · (c_{v+1} ⋯ c_{NV−1}).
-template <int NV, int VW>
+// WP: 0 scalar weights only, 1 per-pixel weight planes, 2 weight planes and
+// their per-pixel gradients.
+template <int NV, int VW, int WP>
 __global__ void __launch_bounds__(NT) pointwise_sim_kernel(AdjPointArgs a) {
   __shared__ double sh[NT];
   double wsum[NV];
@@ -76,17 +83,28 @@ __global__ void __launch_bounds__(NT) pointwise_sim_kernel(AdjPointArgs a) {
   }
   for (size_t i = ((size_t)blockIdx.x * NT + threadIdx.x) * VW; i < a.n; i += (size_t)gridDim.x * NT * VW) {
     float gin[VW], psi[VW], q[NV][VW], gout[VW];
+    float om[WP ? NV : 1][VW], gw[WP == 2 ? NV : 1][VW];
     ldv<VW>(a.gbar_in, i, gin);
     ldv<VW>(a.psi, i, psi);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) ldv<VW>(a.q[v], i, q[v]);
+    for (int v = 0; v < NV; ++v) {
+      ldv<VW>(a.q[v], i, q[v]);
+      if constexpr (WP >= 1) ldv<VW>(a.wpl[v], i, om[v]);
+      if constexpr (WP == 2) ldv<VW>(a.gwpl[v], i, gw[v]);
+    }
 #pragma unroll
     for (int e = 0; e < VW; ++e) {
-      float c[NV], pre[NV + 1];
+      float c[NV], o[NV], pre[NV + 1];
       pre[0] = 1.f;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        c[v] = fmaf(w[v], q[v][e], w1[v]);
+        if constexpr (WP >= 1) {
+          o[v] = w[v] * om[v][e];
+          c[v] = fmaf(o[v], q[v][e], 1.f - o[v]);
+        } else {
+          o[v] = w[v];
+          c[v] = fmaf(w[v], q[v][e], w1[v]);
+        }
         pre[v + 1] = pre[v] * c[v];
       }
       gout[e] = gin[e] * pre[NV];
@@ -96,13 +114,21 @@ __global__ void __launch_bounds__(NT) pointwise_sim_kernel(AdjPointArgs a) {
       for (int v = NV - 1; v >= 0; --v) {
         const float cbar = gp * (pre[v] * suf);
         suf *= c[v];
-        wsum[v] += (double)cbar * (double)(q[v][e] - 1.f);
-        q[v][e] = w[v] * cbar;
+        const float d = q[v][e] - 1.f;
+        if constexpr (WP >= 1)
+          wsum[v] += (double)cbar * (double)d * (double)om[v][e];
+        else
+          wsum[v] += (double)cbar * (double)d;
+        if constexpr (WP == 2) gw[v][e] += (cbar * d) * w[v];
+        q[v][e] = o[v] * cbar;
       }
     }
     stv<VW>(a.gbar_out, i, gout);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) stv<VW>(a.q[v], i, q[v]);
+    for (int v = 0; v < NV; ++v) {
+      stv<VW>(a.q[v], i, q[v]);
+      if constexpr (WP == 2) stv<VW>(a.gwpl[v], i, gw[v]);
+    }
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -113,26 +139,35 @@ __global__ void __launch_bounds__(NT) pointwise_sim_kernel(AdjPointArgs a) {
 
 // Sequential update, view v: ψ_{v+1} = ψ_v · c_v.  gbar holds ∂L/∂ψ_{v+1} on
 // entry and the direct term ∂L/∂ψ_v = gbar · c_v on exit; q becomes q̄.
-template <int VW>
+template <int VW, int WP>
 __global__ void __launch_bounds__(NT) pointwise_seq_kernel(AdjPointArgs a) {
   __shared__ double sh[NT];
   double wsum = 0.0;
   const float w = a.w[0], w1 = 1.f - w;
   for (size_t i = ((size_t)blockIdx.x * NT + threadIdx.x) * VW; i < a.n; i += (size_t)gridDim.x * NT * VW) {
-    float g[VW], q[VW], psi[VW], go[VW];
+    float g[VW], q[VW], psi[VW], go[VW], om[VW], gw[VW];
     ldv<VW>(a.gbar_in, i, g);
     ldv<VW>(a.q[0], i, q);
     ldv<VW>(a.psi, i, psi);
+    if constexpr (WP >= 1) ldv<VW>(a.wpl[0], i, om);
+    if constexpr (WP == 2) ldv<VW>(a.gwpl[0], i, gw);
 #pragma unroll
     for (int e = 0; e < VW; ++e) {
-      const float c = fmaf(w, q[e], w1);
+      const float o = WP >= 1 ? w * om[e] : w;
+      const float c = WP >= 1 ? fmaf(o, q[e], 1.f - o) : fmaf(w, q[e], w1);
       const float cbar = g[e] * psi[e];
+      const float d = q[e] - 1.f;
       go[e] = g[e] * c;
-      wsum += (double)cbar * (double)(q[e] - 1.f);
-      q[e] = w * cbar;
+      if constexpr (WP >= 1)
+        wsum += (double)cbar * (double)d * (double)om[e];
+      else
+        wsum += (double)cbar * (double)d;
+      if constexpr (WP == 2) gw[e] += (cbar * d) * w;
+      q[e] = o * cbar;
     }
     stv<VW>(a.gbar_out, i, go);
     stv<VW>(a.q[0], i, q);
+    if constexpr (WP == 2) stv<VW>(a.gwpl[0], i, gw);
   }
   const double s = block_sum(wsum, sh);
   if (threadIdx.x == 0) a.wpart[blockIdx.x] = s;
@@ -542,16 +577,39 @@ bool point_vec(const AdjPointArgs &a, int nv) {
   bool ok = a.n % 4 == 0;
   for (const void *p : {(const void *)a.psi, (const void *)a.gbar_in, (const void *)a.gbar_out})
     ok = ok && (uintptr_t)p % 16 == 0;
-  for (int v = 0; v < nv; ++v) ok = ok && (uintptr_t)a.q[v] % 16 == 0;
+  for (int v = 0; v < nv; ++v) {
+    ok = ok && (uintptr_t)a.q[v] % 16 == 0;
+    if (a.wp >= 1) ok = ok && (uintptr_t)a.wpl[v] % 16 == 0;
+    if (a.wp == 2) ok = ok && (uintptr_t)a.gwpl[v] % 16 == 0;
+  }
   return ok;
+}
+
+template <int NV, int WP>
+hipError_t launch_sim_wp(const AdjPointArgs &a, int nblocks, hipStream_t s) {
+  if (point_vec(a, NV))
+    hipLaunchKernelGGL((pointwise_sim_kernel<NV, 4, WP>), dim3(nblocks), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((pointwise_sim_kernel<NV, 1, WP>), dim3(nblocks), dim3(NT), 0, s, a);
+  return hipGetLastError();
 }
 
 template <int NV>
 hipError_t launch_sim_nv(const AdjPointArgs &a, int nblocks, hipStream_t s) {
-  if (point_vec(a, NV))
-    hipLaunchKernelGGL((pointwise_sim_kernel<NV, 4>), dim3(nblocks), dim3(NT), 0, s, a);
+  switch (a.wp) {
+    case 0: return launch_sim_wp<NV, 0>(a, nblocks, s);
+    case 1: return launch_sim_wp<NV, 1>(a, nblocks, s);
+    case 2: return launch_sim_wp<NV, 2>(a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int WP>
+hipError_t launch_seq_wp(const AdjPointArgs &a, int nblocks, hipStream_t s) {
+  if (point_vec(a, 1))
+    hipLaunchKernelGGL((pointwise_seq_kernel<4, WP>), dim3(nblocks), dim3(NT), 0, s, a);
   else
-    hipLaunchKernelGGL((pointwise_sim_kernel<NV, 1>), dim3(nblocks), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((pointwise_seq_kernel<1, WP>), dim3(nblocks), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -570,11 +628,12 @@ hipError_t launch_pointwise_sim(const AdjPointArgs &a, int nblocks, hipStream_t 
 }
 
 hipError_t launch_pointwise_seq(const AdjPointArgs &a, int nblocks, hipStream_t s) {
-  if (point_vec(a, 1))
-    hipLaunchKernelGGL(pointwise_seq_kernel<4>, dim3(nblocks), dim3(NT), 0, s, a);
-  else
-    hipLaunchKernelGGL(pointwise_seq_kernel<1>, dim3(nblocks), dim3(NT), 0, s, a);
-  return hipGetLastError();
+  switch (a.wp) {
+    case 0: return launch_seq_wp<0>(a, nblocks, s);
+    case 1: return launch_seq_wp<1>(a, nblocks, s);
+    case 2: return launch_seq_wp<2>(a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_sum_partials(const double *part, int nblocks, int nv, double *acc, hipStream_t s) {

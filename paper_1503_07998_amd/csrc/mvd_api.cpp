@@ -2843,10 +2843,33 @@ mvd_status mvd_backward_workspace_bytes(const mvd_ctx *cc, const mvd_run *r, siz
 mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_est, const mvd_run *r,
                         float *const *grad_psf, float *const *grad_back, float *grad_weights,
                         float *grad_init, void *stream) {
+  mvd_grads out{};
+  out.struct_size = sizeof(mvd_grads);
+  out.grad_psf = grad_psf;
+  out.grad_back = grad_back;
+  out.grad_weights = grad_weights;
+  out.grad_init = grad_init;
+  return mvd_backward_grads(c, obs, grad_est, r, &out, stream);
+}
+
+mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *grad_est, const mvd_run *r,
+                              const mvd_grads *out, void *stream) {
   if (!c) return fail(nullptr, MVD_ERR_ARG, "ctx is NULL");
   c->err.clear();
+  if (!out || out->struct_size != sizeof(mvd_grads))
+    return fail(c, MVD_ERR_ARG, "out is NULL or its struct_size is not sizeof(mvd_grads)");
+  float *const *grad_psf = out->grad_psf;
+  float *const *grad_back = out->grad_back;
+  float *grad_weights = out->grad_weights;
+  float *grad_init = out->grad_init;
+  float *const *grad_wpl = out->grad_weight_planes;
   mvd_status st = check_run(c, r);
   if (st != MVD_OK) return st;
+  if (grad_wpl) {
+    if (!r->weight_planes) return fail(c, MVD_ERR_ARG, "grad_weight_planes needs run->weight_planes");
+    for (int v = 0; v < c->nv; ++v)
+      if (!grad_wpl[v]) return fail(c, MVD_ERR_ARG, "grad_weight_planes[%d] is NULL", v);
+  }
   if (!obs || !grad_est) return fail(c, MVD_ERR_ARG, "obs or grad_est is NULL");
   for (int v = 0; v < c->nv; ++v)
     if (!obs[v]) return fail(c, MVD_ERR_ARG, "obs[%d] is NULL", v);
@@ -2857,7 +2880,6 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
     return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep runs rank-one kernels only");
   if (r->flags & MVD_FLAG_NORMALIZE)
     return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep has no normalised form");
-  if (r->weight_planes) return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep takes scalar view weights only");
   for (int v = 0; v < c->nv; ++v)
     if (!c->views[v].sep_p || !c->views[v].sep_x)
       return fail(c, MVD_ERR_UNSUPPORTED, "view %d: PSF or back-projector is not rank one", v);
@@ -2883,8 +2905,10 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
     if (it != g_tune_cache.end()) tn = it->second;
   }
   RunState rs{c, g, r->boundary, false, s, r->view_weights, (r->flags & MVD_FLAG_TIMING) != 0, &tn};
+  rs.wpl = r->weight_planes;   // the sequential sub-states are tempered as in the forward call
   const int V = c->nv;
   const bool sim = r->update == MVD_UPDATE_SIMULTANEOUS;
+  const int wp = !r->weight_planes ? 0 : (grad_wpl ? 2 : 1);
   auto plane = [&](size_t off, int k) { return reinterpret_cast<float *>(ws + off + (size_t)k * L.plane_set); };
   double *acc = reinterpret_cast<double *>(ws + L.acc_off);
   double *wpart = reinterpret_cast<double *>(ws + L.wpart_off);
@@ -2900,6 +2924,7 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
   if (e == hipSuccess) e = launch_stage_views(obs, V, r->obs_dtype, r->obs_layout, g, staged.data(), nullptr, s);
   int cur = 0;
   if (e == hipSuccess) e = launch_copy(grad_est, plane(L.g_off, 0), n, s);
+  for (int v = 0; v < V && e == hipSuccess && grad_wpl; ++v) e = launch_fill(grad_wpl[v], n, 0.f, s);
   const int T = r->n_iters;
   for (int t = T - 1; t >= 0 && e == hipSuccess; --t) {
     const float *psi = r->checkpoints + (size_t)t * n;
@@ -2919,7 +2944,10 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
       for (int v = 0; v < V; ++v) {
         pa.q[v] = vb[v].q;
         pa.w[v] = weight_of(rs, v);
+        if (wp >= 1) pa.wpl[v] = r->weight_planes[v];
+        if (wp == 2) pa.gwpl[v] = grad_wpl[v];
       }
+      pa.wp = wp;
       pa.wpart = wpart;
       e = timed(rs, 3, [&] { return launch_pointwise_sim(pa, kPointBlocks, s); });
       if (e == hipSuccess) e = launch_sum_partials(wpart, kPointBlocks, V, acc + acc_w(c), s);
@@ -2950,6 +2978,9 @@ mvd_status mvd_backward(mvd_ctx *c, const void *const *obs, const float *grad_es
         pa.gbar_out = plane(L.g_off, 1 - cur);
         pa.q[0] = vb.q;
         pa.w[0] = weight_of(rs, v);
+        pa.wp = wp;
+        if (wp >= 1) pa.wpl[0] = r->weight_planes[v];
+        if (wp == 2) pa.gwpl[0] = grad_wpl[v];
         pa.wpart = wpart;
         e = timed(rs, 3, [&] { return launch_pointwise_seq(pa, kPointBlocks, s); });
         if (e == hipSuccess) e = launch_sum_partials(wpart, kPointBlocks, 1, acc + acc_w(c) + v, s);

@@ -165,6 +165,9 @@ struct AdjPointArgs {
   float *q[kMaxViews];   // in: q_v, out: q̄_v
   float w[kMaxViews];
   double *wpart;         // [blocks][nv]
+  int wp;                // 0 scalar weights, 1 per-pixel weight planes, 2 planes and their gradients
+  const float *wpl[kMaxViews];   // ω_v (wp ≥ 1)
+  float *gwpl[kMaxViews];        // ∂L/∂ω_v, accumulated (wp = 2)
 };
 
 // Tap-gradient correlation over all planes: part[block][j][i] partial sums of

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_status_strings():
     lib = N.lib()
-    assert lib.mvd_version() == 2
+    assert lib.mvd_version() == 3
     assert lib.mvd_status_string(0) == b"ok"
     assert lib.mvd_status_string(-3) == b"workspace too small"
 
@@ -271,8 +271,25 @@ def test_backward_validation_before_device():
         rng = np.random.default_rng(0)
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, normalize=True)
         assert call(r) == N.MVD_ERR_UNSUPPORTED
+        # weight planes are taken (the device check comes next)
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, weight_planes=[64, 128])
-        assert call(r) == N.MVD_ERR_UNSUPPORTED
+        assert call(r) == N.MVD_ERR_DEVICE
+
+        def grads(run, size=None, gwp=None):
+            out = N.MvdGrads()
+            out.struct_size = ctypes.sizeof(N.MvdGrads) if size is None else size
+            if gwp is not None:
+                arr = (ctypes.c_void_p * 2)(*gwp)
+                out.grad_weight_planes = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+            return lib.mvd_backward_grads(ctx, dummy, g, ctypes.byref(run), ctypes.byref(out), None)
+
+        assert grads(r, size=8) == N.MVD_ERR_ARG
+        assert lib.mvd_backward_grads(ctx, dummy, g, ctypes.byref(r), None, None) == N.MVD_ERR_ARG
+        assert grads(r, gwp=[512, None]) == N.MVD_ERR_ARG              # a NULL entry
+        assert grads(r, gwp=[512, 1024]) == N.MVD_ERR_DEVICE
+        r2 = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need)
+        assert grads(r2, gwp=[512, 1024]) == N.MVD_ERR_ARG            # no weight planes to differentiate
+        assert grads(r2) == N.MVD_ERR_DEVICE
         api.mvd_set_psf(ctx, 1, random_psf(rng, 5, 5).astype(np.float32))   # not rank one
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need)
         assert call(r) == N.MVD_ERR_UNSUPPORTED

@@ -26,7 +26,10 @@ def _say(msg):
 
 
 def gpu_forward_backward(stacks, psfs, T, gout, update="simultaneous", boundary="zero", weights=None,
-                         layout="stack_zyx"):
+                         layout="stack_zyx", weight_planes=None, plane_grads=False):
+    """Forward run with checkpoints, then the reverse sweep.  weight_planes:
+    per-view float32 [Y][Z][X] arrays; plane_grads: also ∂L/∂ω_v (through
+    mvd_backward_grads, else mvd_backward)."""
     from paper_1503_07998_amd import api
 
     torch = _torch()
@@ -43,8 +46,12 @@ def gpu_forward_backward(stacks, psfs, T, gout, update="simultaneous", boundary=
     obs_dtype = "u16" if stacks[0].dtype == np.uint16 else "f32"
     ck = torch.empty((T, Y, Z, X), dtype=torch.float32, device=dev)
     est = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
+    wpl = None
+    if weight_planes is not None:
+        wpl = [torch.from_numpy(np.ascontiguousarray(w.astype(np.float32))).to(dev) for w in weight_planes]
     run = api.make_run(Y, T, update=update, boundary=boundary, weights=weights, checkpoints=ck.data_ptr(),
-                       obs_dtype=obs_dtype, layout=layout)
+                       obs_dtype=obs_dtype, layout=layout,
+                       weight_planes=[w.data_ptr() for w in wpl] if wpl is not None else None)
     nb = api.mvd_workspace_bytes(d.ctx, run)
     ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
     run.workspace = (ws.data_ptr() + 255) // 256 * 256
@@ -59,10 +66,17 @@ def gpu_forward_backward(stacks, psfs, T, gout, update="simultaneous", boundary=
     gb = [torch.empty(p.shape, dtype=torch.float32, device=dev) for p in psfs]
     gw = torch.empty(V, dtype=torch.float32, device=dev)
     gi = torch.empty((Y, Z, X), dtype=torch.float32, device=dev)
-    api.mvd_backward(d.ctx, obs, g, run, gp, gb, gw, gi)
+    gwp = None
+    if plane_grads:
+        gwp = [torch.full((Y, Z, X), -7.0, dtype=torch.float32, device=dev) for _ in range(V)]
+        api.mvd_backward_grads(d.ctx, obs, g, run, gp, gb, gw, gi, gwp)
+    else:
+        api.mvd_backward(d.ctx, obs, g, run, gp, gb, gw, gi)
     torch.cuda.synchronize()
     out = dict(est=est.cpu().numpy(), grad_psf=[x.cpu().numpy() for x in gp],
                grad_back=[x.cpu().numpy() for x in gb], grad_weights=gw.cpu().numpy(), grad_init=gi.cpu().numpy())
+    if gwp is not None:
+        out["grad_weight_planes"] = [x.cpu().numpy() for x in gwp]
     d.close()
     return out
 
@@ -123,6 +137,73 @@ def test_backward_matches_oracle_adjoint(case, corr_form):
         close(got["grad_back"][v], ref["grad_back"][v], f"grad_back[{v}]")
     close(got["grad_weights"], ref["grad_weights"], "grad_weights")
     close(got["grad_init"], ref["grad_psi0"], "grad_init")
+
+
+PLANE_CASES = [
+    # (Y, Z, X, kernel shapes, T, update, boundary, scalar weights)
+    (3, 40, 48, [(9, 7), (7, 9)], 3, "simultaneous", "zero", [0.9, 0.7]),
+    (2, 24, 40, [(7, 5), (5, 7), (3, 3)], 2, "sequential", "periodic", None),
+    (2, 37, 130, [(31, 31), (21, 21)], 2, "sequential", "zero", [0.8, 1.0]),
+    (1, 21, 33, [(5, 5), (3, 7)], 3, "simultaneous", "periodic", None),   # ragged: element-wise kernels
+]
+
+
+@pytest.mark.parametrize("case", PLANE_CASES, ids=[f"w{i}" for i in range(len(PLANE_CASES))])
+def test_backward_with_weight_planes_matches_oracle(case):
+    """Per-pixel weight planes ω_v: the reverse sweep's tap, weight and ψ^0
+    gradients and ∂L/∂ω_v against the oracle's adjoint with per-pixel
+    weights o_v = w_v·ω_v (∂L/∂ω_v = ∂L/∂o_v · w_v, ∂L/∂w_v = Σ ∂L/∂o_v · ω_v)."""
+    Y, Z, X, shapes, T, update, boundary, weights = case
+    V = len(shapes)
+    _say(f"backward with weight planes Y={Y} Z={Z} X={X} k={shapes} T={T} {update} {boundary} w={weights}")
+    rng = np.random.default_rng(Y * 100 + Z + X + 5)
+    psfs = [random_psf(rng, kz, kx, separable=True).astype(np.float32) for kz, kx in shapes]
+    stacks = [rng.uniform(20.0, 300.0, (Z, Y, X)).astype(np.float32) for _ in shapes]
+    planes = [rng.uniform(0.2, 1.0, (Y, Z, X)).astype(np.float32) for _ in shapes]
+    gout = rng.standard_normal((Y, Z, X))
+    got = gpu_forward_backward(stacks, psfs, T, gout, update, boundary, weights, weight_planes=planes,
+                               plane_grads=True)
+    ws = [1.0] * V if weights is None else weights
+    eff = [np.float64(ws[v]) * planes[v].astype(np.float64) for v in range(V)]
+    ref = oracle_adjoint(stacks, psfs, T, gout, update, boundary, eff)
+    for v in range(V):
+        close(got["grad_psf"][v], ref["grad_psf"][v], f"grad_psf[{v}]")
+        close(got["grad_back"][v], ref["grad_back"][v], f"grad_back[{v}]")
+        close(got["grad_weight_planes"][v], ref["grad_weights"][v] * ws[v], f"grad_weight_planes[{v}]")
+    gw_ref = [float(np.sum(ref["grad_weights"][v] * planes[v])) for v in range(V)]
+    close(got["grad_weights"], gw_ref, "grad_weights")
+    close(got["grad_init"], ref["grad_psi0"], "grad_init")
+    # mvd_backward (no plane gradients) gives the same other outputs, bitwise
+    alt = gpu_forward_backward(stacks, psfs, T, gout, update, boundary, weights, weight_planes=planes)
+    for k in ("grad_weights", "grad_init"):
+        np.testing.assert_array_equal(alt[k], got[k])
+    for v in range(V):
+        np.testing.assert_array_equal(alt["grad_psf"][v], got["grad_psf"][v])
+
+
+def test_unit_weight_planes_equal_scalar_weights_bitwise():
+    """ω_v = 1 everywhere: every gradient bitwise that of the scalar-weight run,
+    and ∂L/∂ω_v sums to w_v · ∂L/∂w_v."""
+    _say("backward: unit weight planes")
+    rng = np.random.default_rng(123)
+    shapes = [(9, 9), (7, 11)]
+    psfs = [random_psf(rng, kz, kx, separable=True).astype(np.float32) for kz, kx in shapes]
+    stacks = [rng.uniform(20.0, 300.0, (32, 3, 64)).astype(np.float32) for _ in shapes]
+    gout = rng.standard_normal((3, 32, 64))
+    ones = [np.ones((3, 32, 64), dtype=np.float32) for _ in shapes]
+    for update in ("simultaneous", "sequential"):
+        a = gpu_forward_backward(stacks, psfs, 2, gout, update, weights=[0.8, 0.6])
+        b = gpu_forward_backward(stacks, psfs, 2, gout, update, weights=[0.8, 0.6], weight_planes=ones,
+                                 plane_grads=True)
+        np.testing.assert_array_equal(a["est"], b["est"])
+        for k in ("grad_weights", "grad_init"):
+            np.testing.assert_array_equal(a[k], b[k])
+        for v in range(2):
+            np.testing.assert_array_equal(a["grad_psf"][v], b["grad_psf"][v])
+            np.testing.assert_array_equal(a["grad_back"][v], b["grad_back"][v])
+            gwp = b["grad_weight_planes"][v].astype(np.float64)
+            s, want = float(gwp.sum()), (0.8, 0.6)[v] * float(a["grad_weights"][v])
+            assert abs(s - want) <= 1e-5 * float(np.abs(gwp).sum()), (update, v, s, want)
 
 
 def test_backward_is_deterministic():
