@@ -143,10 +143,12 @@ typedef struct {
                                  pixel's correction is tempered as ω·c + (1 − ω) with
                                  ω = view_weights[v] · ω_v(pixel) (the memory table's
                                  per-pixel, per-view weights, Supplementary Note 2; their
-                                 formula is not given).  Rank-one back-projectors and
-                                 device-resident runs only: MVD_ERR_UNSUPPORTED with
-                                 K×K passes, MVD_ERR_ARG for streamed runs.  Read only,
-                                 kept alive until the stream is done. */
+                                 formula is not given).  Rank-one back-projectors only
+                                 (MVD_ERR_UNSUPPORTED with K×K passes).  Streamed and
+                                 disk-to-disk runs read them in place, each plane batch
+                                 its own planes: there they must be device memory
+                                 (MVD_ERR_ARG otherwise).  Read only, kept alive until
+                                 the stream is done. */
 } mvd_run;
 
 /* Library version (MVD_ABI_VERSION). */

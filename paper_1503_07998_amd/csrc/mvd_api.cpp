@@ -1441,6 +1441,8 @@ StreamLayout stream_layout_of(const mvd_ctx *c, const mvd_run *r, int batch, boo
   return S;
 }
 
+int memory_kind(const void *p);
+
 mvd_status check_stream_run(mvd_ctx *c, const mvd_run *r, int batch) {
   mvd_status st = check_run(c, r);
   if (st != MVD_OK) return st;
@@ -1448,7 +1450,16 @@ mvd_status check_stream_run(mvd_ctx *c, const mvd_run *r, int batch) {
   if (r->obs_layout != MVD_STACK_ZYX) return fail(c, MVD_ERR_ARG, "streamed runs take camera-ordered stacks");
   if (r->checkpoints) return fail(c, MVD_ERR_ARG, "streamed runs keep no checkpoints");
   if (r->flags & MVD_FLAG_GRAPH) return fail(c, MVD_ERR_ARG, "MVD_FLAG_GRAPH is not available for streamed runs");
-  if (r->weight_planes) return fail(c, MVD_ERR_ARG, "streamed runs take no weight planes");
+  return MVD_OK;
+}
+
+// Weight planes of a streamed or disk-to-disk run stay on the device (whole
+// volume [Y][Z][X] per view; each batch reads its planes in place).
+mvd_status check_stream_weights(mvd_ctx *c, const mvd_run *r) {
+  if (!r->weight_planes) return MVD_OK;
+  for (int v = 0; v < c->nv; ++v)
+    if (memory_kind(r->weight_planes[v]) != 2)
+      return fail(c, MVD_ERR_ARG, "weight_planes[%d] must be device memory in streamed runs", v);
   return MVD_OK;
 }
 
@@ -1503,12 +1514,19 @@ struct StreamPipe {
     return e;
   }
 
-  mvd_run batch_run(int ny) const {
+  // The run of one batch of ny planes from plane y0 (its weight planes, if
+  // any, point into the whole volume's: `wb` holds the V pointers).
+  mvd_run batch_run(int y0, int ny, std::vector<const float *> &wb) const {
     mvd_run sub = *r;
     sub.n_planes = ny;
     sub.flags &= ~MVD_FLAG_TUNE;
     sub.workspace = static_cast<char *>(r->workspace) + S.run_off;
     sub.workspace_bytes = S.run_bytes;
+    if (r->weight_planes) {
+      wb.assign(r->weight_planes, r->weight_planes + c->nv);
+      for (const float *&p : wb) p += (size_t)y0 * c->Z * c->X;
+      sub.weight_planes = wb.data();
+    }
     return sub;
   }
 
@@ -1538,14 +1556,11 @@ struct StreamPipe {
     if (e == hipSuccess) e = hipStreamWaitEvent(s, in[k], 0);
     if (e == hipSuccess && est_host && b >= S.slots) e = hipStreamWaitEvent(s, out[k], 0);
     // launch shapes timed on the first batch (full-size batches share its shape)
-    if (e == hipSuccess && b == 0 && (r->flags & MVD_FLAG_TUNE) && r->init != MVD_INIT_GIVEN) {
-      const mvd_run sub = batch_run(ny);
+    std::vector<const float *> wb;
+    const mvd_run sub = batch_run(y0, ny, wb);
+    if (e == hipSuccess && b == 0 && (r->flags & MVD_FLAG_TUNE) && r->init != MVD_INIT_GIVEN)
       e = autotune(c, slab.data(), est_b, &sub, s, &tn);
-    }
-    if (e == hipSuccess) {
-      const mvd_run sub = batch_run(ny);
-      e = enqueue_run(c, slab.data(), est_b, &sub, s, tn);
-    }
+    if (e == hipSuccess) e = enqueue_run(c, slab.data(), est_b, &sub, s, tn);
     if (e == hipSuccess) e = hipEventRecord(done[k], s);
     if (e == hipSuccess && est_host) {
       e = hipStreamWaitEvent(c->d2h, done[k], 0);
@@ -2596,6 +2611,8 @@ mvd_status mvd_deconvolve_stream(mvd_ctx *c, const void *const *obs, float *est,
       return fail(c, MVD_ERR_ARG, "obs[%d] is pageable host memory: use page-locked or device memory", v);
   const int ek = memory_kind(est);
   if (ek == 0) return fail(c, MVD_ERR_ARG, "est is pageable host memory: use page-locked or device memory");
+  st = check_stream_weights(c, r);
+  if (st != MVD_OK) return st;
   const bool est_host = ek == 1;
   const StreamLayout S = stream_layout_of(c, r, batch_planes, est_host);
   if (!r->workspace || r->workspace_bytes < S.total)
@@ -2652,6 +2669,8 @@ mvd_status mvd_deconvolve_files(mvd_ctx *c, mvd_files *io, const mvd_run *r, int
                 r->workspace ? r->workspace_bytes : (size_t)0);
   DeviceGuard dg(c->device);
   if (!dg.ok()) return fail(c, MVD_ERR_DEVICE, "cannot select device %d", c->device);
+  st = check_stream_weights(c, r);
+  if (st != MVD_OK) return st;
   if (stream_resources(c) != hipSuccess) return fail(c, MVD_ERR_ALLOC, "cannot create copy streams or events");
   return run_files(c, io, r, batch_planes, (hipStream_t)stream);
 }

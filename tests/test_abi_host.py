@@ -339,7 +339,9 @@ def test_stream_validation_before_device():
         assert call(api.make_run(4, 2, layout="planes_yzx")) == N.MVD_ERR_ARG
         assert call(api.make_run(4, 2, checkpoints=64)) == N.MVD_ERR_ARG
         assert call(api.make_run(4, 2, graph=True)) == N.MVD_ERR_ARG
-        assert call(api.make_run(4, 2, weight_planes=[64, 128])) == N.MVD_ERR_ARG
+        # weight planes are taken (whether they are device memory is checked on the device)
+        assert call(api.make_run(4, 2, weight_planes=[64, 128])) == N.MVD_ERR_DEVICE
+        assert call(api.make_run(4, 2, weight_planes=[64, 0])) == N.MVD_ERR_ARG        # a NULL plane
         r = api.make_run(4, 2, workspace=256 + 8, workspace_bytes=1 << 20)
         assert call(r) == N.MVD_ERR_ARG                        # misaligned workspace
         r = api.make_run(4, 2, workspace=256, workspace_bytes=1 << 20)

@@ -55,14 +55,14 @@ def _workspace(nbytes):
     return ws, (ws.data_ptr() + 255) // 256 * 256
 
 
-def _plain(d, spec, stacks):
+def _plain(d, spec, stacks, weight_planes=None):
     from paper_1503_07998_amd import api
 
     torch = _torch()
     Z, Y, X = stacks[0].shape
     obs = [torch.from_numpy(s).to("cuda:0") for s in stacks]
     est = torch.empty((Y, Z, X), dtype=torch.float32, device="cuda:0")
-    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype)
+    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype, weight_planes=weight_planes)
     nb = api.mvd_workspace_bytes(d.ctx, run)
     ws, run.workspace = _workspace(nb)
     run.workspace_bytes = nb
@@ -71,7 +71,7 @@ def _plain(d, spec, stacks):
     return est.cpu().numpy()
 
 
-def _files(d, spec, stacks, tmp_path, batch, offsets, est_offset=0, **kw):
+def _files(d, spec, stacks, tmp_path, batch, offsets, est_offset=0, weight_planes=None, **kw):
     """Writes the stacks to files (after `offsets[v]` bytes of 0xEE), runs the
     disk-to-disk form and returns (ψ^T read back, the estimate file's bytes
     before est_offset, the call's statistics)."""
@@ -85,7 +85,7 @@ def _files(d, spec, stacks, tmp_path, batch, offsets, est_offset=0, **kw):
         paths.append(p)
     ep = tmp_path / "est.raw"
     ep.write_bytes(b"\x5a" * est_offset)
-    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype)
+    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype, weight_planes=weight_planes)
     nb = api.mvd_stream_workspace_bytes(d.ctx, run, batch, True)
     ws, run.workspace = _workspace(nb)
     run.workspace_bytes = nb
@@ -141,6 +141,23 @@ def test_files_one_batch_f32_sequential(tmp_path):
     np.testing.assert_array_equal(got, ref)
     np.testing.assert_array_equal(got2, ref)
     assert st["bytes_read"] == 3 * 33 * 13 * 72 * 4
+
+
+def test_files_with_weight_planes_equal_device_run(tmp_path):
+    """Device-resident weight planes in the disk-to-disk form: bitwise the
+    device-resident weighted run, 29 planes in batches of 6."""
+    torch = _torch()
+    _say("disk-to-disk u16 with weight planes, 29 planes of 40x48, batch 6")
+    spec = VolumeSpec("files_w", 29, 40, 48, 9, (1.2, 2.5), (0, 90), 40, "u16", 3, "simultaneous", seed=94)
+    vol = make_volume(spec, truth=False)
+    d = _ctx(spec, vol["psfs"])
+    rng = np.random.default_rng(95)
+    planes = [torch.from_numpy(rng.uniform(0.2, 1.0, (29, 40, 48)).astype(np.float32)).to("cuda:0")
+              for _ in range(2)]
+    ref = _plain(d, spec, vol["stacks"], weight_planes=planes)
+    got, _, _ = _files(d, spec, vol["stacks"], tmp_path, 6, [0, 0], weight_planes=planes)
+    d.close()
+    np.testing.assert_array_equal(got, ref)
 
 
 def test_files_rejects_short_file(tmp_path):

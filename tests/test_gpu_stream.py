@@ -52,7 +52,7 @@ def _pinned(a):
     return t
 
 
-def _plain(d, spec, stacks, init=None):
+def _plain(d, spec, stacks, init=None, weight_planes=None):
     """Whole-volume device-resident run."""
     from paper_1503_07998_amd import api
 
@@ -64,7 +64,8 @@ def _plain(d, spec, stacks, init=None):
     if init is not None:
         est.copy_(torch.from_numpy(init))
         kw["init"] = "given"
-    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype, **kw)
+    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype, weight_planes=weight_planes,
+                       **kw)
     ws, run.workspace = _workspace(api.mvd_workspace_bytes(d.ctx, run))
     run.workspace_bytes = api.mvd_workspace_bytes(d.ctx, run)
     api.mvd_deconvolve_planes(d.ctx, obs, est, run)
@@ -72,7 +73,7 @@ def _plain(d, spec, stacks, init=None):
     return est.cpu().numpy()
 
 
-def _streamed(d, spec, host_obs, batch, est_host, init=None, Y=None, tune=False):
+def _streamed(d, spec, host_obs, batch, est_host, init=None, Y=None, tune=False, weight_planes=None):
     from paper_1503_07998_amd import api
 
     torch = _torch()
@@ -88,7 +89,8 @@ def _streamed(d, spec, host_obs, batch, est_host, init=None, Y=None, tune=False)
         kw["init"] = "given"
     else:
         est.fill_(-7.0)
-    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype, tune=tune, **kw)
+    run = api.make_run(Y, spec.iters, update=spec.update, obs_dtype=spec.obs_dtype, tune=tune,
+                       weight_planes=weight_planes, **kw)
     nb = api.mvd_stream_workspace_bytes(d.ctx, run, batch, est_host)
     ws, run.workspace = _workspace(nb)
     run.workspace_bytes = nb
@@ -110,6 +112,29 @@ def small_case():
     host = [_pinned(s) for s in vol["stacks"]]
     yield dict(vol=vol, d=d, plain=plain, host=host)
     d.close()
+
+
+@pytest.mark.parametrize("batch", [5, 37])
+def test_streamed_weight_planes_equal_plain(small_case, batch):
+    """Per-pixel weight planes stay on the device and each batch reads its
+    own planes: bitwise the device-resident weighted run (and not the
+    unweighted one); host weight planes are refused."""
+    from paper_1503_07998_amd import _native as N
+
+    torch = _torch()
+    _say(f"streamed 37 planes with weight planes, batch={batch}")
+    rng = np.random.default_rng(5)
+    Z, Y, X = small_case["vol"]["stacks"][0].shape
+    planes = [torch.from_numpy(rng.uniform(0.2, 1.0, (Y, Z, X)).astype(np.float32)).to("cuda:0")
+              for _ in range(SMALL.n_views)]
+    ref = _plain(small_case["d"], SMALL, small_case["vol"]["stacks"], weight_planes=planes)
+    got = _streamed(small_case["d"], SMALL, small_case["host"], batch, True, weight_planes=planes)
+    np.testing.assert_array_equal(got, ref)
+    assert not np.array_equal(got, small_case["plain"])
+    host_planes = [_pinned(p.cpu().numpy()) for p in planes]
+    with pytest.raises(N.MvdError) as e:
+        _streamed(small_case["d"], SMALL, small_case["host"], batch, True, weight_planes=host_planes)
+    assert e.value.status == N.MVD_ERR_ARG and "device memory" in str(e.value)
 
 
 @pytest.mark.parametrize("batch", [1, 8, 16, 37, 64])
