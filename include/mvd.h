@@ -374,8 +374,11 @@ mvd_status mvd_backward_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, 
  *   grad_weights: device [V] or NULL.  grad_init: device [Y][Z][X], ∂L/∂ψ^0,
  *        or NULL.  Outputs are overwritten, in float32 from float64 sums in a
  *        fixed order (bitwise reproducible).
- * Every view's PSF and back-projector must be rank one (MVD_ERR_UNSUPPORTED
- * otherwise, with MVD_FLAG_FORCE_2D and with MVD_FLAG_NORMALIZE).  Per-pixel
+ * Every view's PSF and back-projector must be rank one or a sum of a few
+ * rank-one terms (mvd_psf_info ≥ 1: kernels of low rank, whose passes are
+ * summed term by term; the tap gradients cover the whole K×K kernel);
+ * MVD_ERR_UNSUPPORTED for kernels on the K×K passes, with MVD_FLAG_FORCE_2D
+ * and with MVD_FLAG_NORMALIZE.  Per-pixel
  * weight planes (run->weight_planes) are taken as in the forward call: each
  * pixel's correction tempered by o = w_v · ω_v(pixel); grad_weights is then
  * ∂L/∂w_v with the planes held fixed (mvd_backward_grads also returns ∂L/∂ω_v).

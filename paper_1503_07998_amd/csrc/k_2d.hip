@@ -17,15 +17,6 @@ constexpr int TX = 64;
 constexpr int NT = 256;
 constexpr int N4 = 4;   // outputs per thread
 
-// φ / b for b > ε, else 1: reciprocal refined by one Newton-Raphson correction
-// of the quotient (Markstein); within 1 ulp of IEEE, exactly 1 when φ = b.
-__device__ __forceinline__ float guarded_ratio(float phi, float b) {
-  const float y = __builtin_amdgcn_rcpf(b);
-  const float q0 = phi * y;
-  const float q = fmaf(fmaf(-b, q0, phi), y, q0);
-  return b > kEps ? q : 1.f;
-}
-
 __device__ __forceinline__ int wrap2(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;

@@ -12,6 +12,9 @@
 //    ω̄_v += c̄_v (q_v − 1) w_v pixel by pixel (summed over the iterations in
 //    the caller's buffer).
 //  * pointwise_seq: the same for one view of the sequential update.
+//  * ratio_plane / bbar_plane: the pointwise ends of the passes of a kernel
+//    that is a sum of rank-one terms (the sum formed term by term first):
+//    r = φ / b (1 where b ≤ ε) and b̄ = −s · r / b (0 where b ≤ ε).
 //  * corr: tap gradient Σ_{y,z,x} ḡ[y][z][x] · ã[y][z+R−j][x+R−i] for every
 //    lag (j, i) of a K×K kernel (ã zero or wrapped outside the plane): each
 //    thread owns a 4×8 block of lags and slides over 8×64 tiles staged in LDS.
@@ -171,6 +174,23 @@ __global__ void __launch_bounds__(NT) pointwise_seq_kernel(AdjPointArgs a) {
   }
   const double s = block_sum(wsum, sh);
   if (threadIdx.x == 0) a.wpart[blockIdx.x] = s;
+}
+
+// r = φ / b, guarded as in the forward pass's epilogue.
+__global__ void __launch_bounds__(NT) ratio_plane_kernel(const float *__restrict__ phi, const float *__restrict__ b,
+                                                          float *__restrict__ r, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT)
+    r[i] = guarded_ratio(phi[i], b[i]);
+}
+
+// b ← −s · r / b where b > ε, else 0 (b̄ over b, as the single-term epilogue).
+__global__ void __launch_bounds__(NT) bbar_plane_kernel(const float *__restrict__ s, const float *__restrict__ r,
+                                                         float *b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    const float bb = b[i];
+    const float q = nr_quotient(s[i] * r[i], bb);
+    b[i] = bb > kEps ? -q : 0.f;
+  }
 }
 
 // acc[v] += Σ_b part[b][v]: one work-group per view, fixed order.
@@ -634,6 +654,20 @@ hipError_t launch_pointwise_seq(const AdjPointArgs &a, int nblocks, hipStream_t 
     case 2: return launch_seq_wp<2>(a, nblocks, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_ratio_plane(const float *phi, const float *b, float *r, size_t n, hipStream_t s) {
+  const unsigned blocks = (unsigned)std::min<size_t>((n + NT - 1) / NT, 8192);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(ratio_plane_kernel, dim3(blocks), dim3(NT), 0, s, phi, b, r, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bbar_plane(const float *sum, const float *r, float *b, size_t n, hipStream_t s) {
+  const unsigned blocks = (unsigned)std::min<size_t>((n + NT - 1) / NT, 8192);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(bbar_plane_kernel, dim3(blocks), dim3(NT), 0, s, sum, r, b, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_sum_partials(const double *part, int nblocks, int nv, double *acc, hipStream_t s) {

@@ -489,22 +489,6 @@ __device__ __forceinline__ float obs_at(const Ops<EP, NV> &ops, int v, int n) {
     return ops.f[v][0][n];
 }
 
-// Quotient n / d by the reciprocal refined with one Newton-Raphson correction
-// of the quotient (Markstein's method): within 1 ulp of the IEEE quotient for
-// d > ε and finite n, and exactly 1 when n = d (the exact FMA residual then
-// carries the whole error of the first quotient).
-__device__ __forceinline__ float nr_quotient(float n, float d) {
-  const float y = __builtin_amdgcn_rcpf(d);
-  const float q0 = n * y;
-  return fmaf(fmaf(-d, q0, n), y, q0);
-}
-
-// Guarded ratio φ / b for b > ε, else 1.
-__device__ __forceinline__ float guarded_ratio(float phi, float b) {
-  const float q = nr_quotient(phi, b);
-  return b > kEps ? q : 1.f;
-}
-
 // Row pass and epilogue of one item for every view; the row pass runs on every
 // lane (invalid items at clamped addresses), only valid items store.
 template <int KB, int NV, int EP, int VM>

@@ -986,7 +986,9 @@ struct BwdLayout {
   size_t plane_set = 0;
   size_t phi_off = 0, b_off = 0, r_off = 0, q_off = 0, g_off = 0, sub_off = 0, rat_off = 0;
   size_t wpart_off = 0, cpart_off = 0, acc_off = 0, total = 0;
+  size_t tmp_off = 0;   // a plane set for sums of rank-one terms (kernels of low rank), else none
   int nsets = 0, nsub = 0;
+  bool low_rank = false;
 };
 
 // accumulators: per view [psf kz·kx][back kz·kx], then V weights (doubles)
@@ -1016,6 +1018,9 @@ BwdLayout bwd_layout_of(const mvd_ctx *c, const mvd_run *r) {
   off += (size_t)L.nsub * L.plane_set;
   L.rat_off = off;
   if (!sim) off += L.plane_set;
+  L.low_rank = uses_low_rank(c, r);
+  L.tmp_off = off;
+  if (L.low_rank) off += L.plane_set;
   size_t lags = 0;   // padded lags of a partial, either form
   for (auto &w : c->views)
     for (const Kernel *d : {&w.psf, &w.back})
@@ -1202,11 +1207,33 @@ struct ViewBufs {
   float *b, *r, *q;
 };
 
+// out = Σ_t in ⊛ (fz_t ⊗ fx_t), one term per launch (the first stores, the
+// others add in place); `flip` runs every term point-reflected.
+hipError_t terms_sum(const RunState &st, const std::vector<std::vector<float>> &fz,
+                     const std::vector<std::vector<float>> &fx, const float *in, float *out, bool flip, int kind) {
+  hipError_t e = hipSuccess;
+  for (size_t t = 0; t < fz.size() && e == hipSuccess; ++t)
+    e = single_pass(st, t == 0 ? kEpStore : kEpAccum, in, flip ? reversed(fz[t]) : fz[t],
+                    flip ? reversed(fx[t]) : fx[t], out, nullptr, t == 0 ? nullptr : out, nullptr, nullptr, 1.f, kind);
+  return e;
+}
+
+size_t plane_elems(const RunState &st) { return (size_t)st.g.Y * st.g.Z * st.g.X; }
+
+// b = ψ ⊛ P_v with r = φ / b (guarded), then q = r ⊛ X_v.  Kernels of low
+// rank are summed term by term and finished pointwise.
 hipError_t view_recompute(const RunState &st, int v, const float *psi, const float *phi, const ViewBufs &vb) {
   const ViewPsf &w = st.c->views[v];
-  hipError_t e = single_pass(st, kEpBR, psi, w.pz, w.px, vb.b, vb.r, nullptr, nullptr, phi);
-  if (e == hipSuccess) e = single_pass(st, kEpStore, vb.r, w.xz, w.xx, vb.q, nullptr, nullptr, nullptr, nullptr);
-  return e;
+  hipError_t e;
+  if (w.sep_p) {
+    e = single_pass(st, kEpBR, psi, w.pz, w.px, vb.b, vb.r, nullptr, nullptr, phi);
+  } else {
+    e = terms_sum(st, w.lpz, w.lpx, psi, vb.b, false, 3);
+    if (e == hipSuccess) e = timed(st, 3, [&] { return launch_ratio_plane(phi, vb.b, vb.r, plane_elems(st), st.s); });
+  }
+  if (e != hipSuccess) return e;
+  if (w.sep_x) return single_pass(st, kEpStore, vb.r, w.xz, w.xx, vb.q, nullptr, nullptr, nullptr, nullptr);
+  return terms_sum(st, w.lxz, w.lxx, vb.r, vb.q, false, 3);
 }
 
 hipError_t view_backprop(const RunState &st, const BwdLayout &L, char *ws, int v, const float *psi,
@@ -1216,14 +1243,28 @@ hipError_t view_backprop(const RunState &st, const BwdLayout &L, char *ws, int v
   double *acc = reinterpret_cast<double *>(ws + L.acc_off);
   hipError_t e = hipSuccess;
   if (want_back) e = tap_corr(st, L, ws, vb.q, vb.r, w.back.kz, w.back.kx, acc + acc_back(c, v));
-  // b̄ = −(q̄ ⊛ X^*) · r / b  (written over b)
-  if (e == hipSuccess)
-    e = single_pass(st, kEpBbar, vb.q, reversed(w.xz), reversed(w.xx), vb.b, nullptr, vb.r, vb.b, nullptr);
+  // b̄ = −(q̄ ⊛ X^*) · r / b  (written over b; a sum of terms goes through st.acc)
+  if (e == hipSuccess) {
+    if (w.sep_x) {
+      e = single_pass(st, kEpBbar, vb.q, reversed(w.xz), reversed(w.xx), vb.b, nullptr, vb.r, vb.b, nullptr);
+    } else {
+      e = terms_sum(st, w.lxz, w.lxx, vb.q, st.acc, true, 3);
+      if (e == hipSuccess)
+        e = timed(st, 3, [&] { return launch_bbar_plane(st.acc, vb.r, vb.b, plane_elems(st), st.s); });
+    }
+  }
   if (e == hipSuccess && want_psf) e = tap_corr(st, L, ws, vb.b, psi, w.psf.kz, w.psf.kx, acc + acc_psf(c, v));
-  // ψ̄ += b̄ ⊛ P^*
-  if (e == hipSuccess)
-    e = single_pass(st, kEpAccum, vb.b, reversed(w.pz), reversed(w.px), gbar_out, nullptr, gbar_out, nullptr,
-                    nullptr);
+  // ψ̄ += b̄ ⊛ P^*  (term by term for a kernel of low rank)
+  if (e == hipSuccess) {
+    if (w.sep_p) {
+      e = single_pass(st, kEpAccum, vb.b, reversed(w.pz), reversed(w.px), gbar_out, nullptr, gbar_out, nullptr,
+                      nullptr);
+    } else {
+      for (size_t t = 0; t < w.lpz.size() && e == hipSuccess; ++t)
+        e = single_pass(st, kEpAccum, vb.b, reversed(w.lpz[t]), reversed(w.lpx[t]), gbar_out, nullptr, gbar_out,
+                        nullptr, nullptr);
+    }
+  }
   return e;
 }
 
@@ -2899,9 +2940,12 @@ mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *g
     return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep runs rank-one kernels only");
   if (r->flags & MVD_FLAG_NORMALIZE)
     return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep has no normalised form");
-  for (int v = 0; v < c->nv; ++v)
-    if (!c->views[v].sep_p || !c->views[v].sep_x)
-      return fail(c, MVD_ERR_UNSUPPORTED, "view %d: PSF or back-projector is not rank one", v);
+  for (int v = 0; v < c->nv; ++v) {
+    const ViewPsf &w = c->views[v];
+    if ((!w.sep_p && w.lpz.empty()) || (!w.sep_x && w.lxz.empty()))
+      return fail(c, MVD_ERR_UNSUPPORTED,
+                  "view %d: PSF or back-projector is neither rank one nor a sum of a few rank-one terms", v);
+  }
   const BwdLayout L = bwd_layout_of(c, r);
   if (!r->workspace || r->workspace_bytes < L.total)
     return fail(c, MVD_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
@@ -2925,6 +2969,7 @@ mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *g
   }
   RunState rs{c, g, r->boundary, false, s, r->view_weights, (r->flags & MVD_FLAG_TIMING) != 0, &tn};
   rs.wpl = r->weight_planes;   // the sequential sub-states are tempered as in the forward call
+  if (L.low_rank) rs.acc = reinterpret_cast<float *>(ws + L.tmp_off);   // partial sums of terms
   const int V = c->nv;
   const bool sim = r->update == MVD_UPDATE_SIMULTANEOUS;
   const int wp = !r->weight_planes ? 0 : (grad_wpl ? 2 : 1);

@@ -13,6 +13,23 @@ constexpr int kMaxK = 63;
 constexpr int kMaxPlaneX = 65536;   // plane width limit (row of zeros of this size; mvd_create enforces it)
 constexpr float kEps = 1e-6f;   // ratio guard: φ/b where b > kEps, else 1
 
+// Quotient n / d by the reciprocal refined with one Newton-Raphson correction
+// of the quotient (Markstein's method): within 1 ulp of the IEEE quotient for
+// d > ε and finite n, and exactly 1 when n = d (the exact FMA residual then
+// carries the whole error of the first quotient).  Every kernel that forms a
+// ratio uses this one definition, so their results agree bitwise.
+__device__ __forceinline__ float nr_quotient(float n, float d) {
+  const float y = __builtin_amdgcn_rcpf(d);
+  const float q0 = n * y;
+  return fmaf(fmaf(-d, q0, n), y, q0);
+}
+
+// Guarded ratio φ / b for b > ε, else 1.
+__device__ __forceinline__ float guarded_ratio(float phi, float b) {
+  const float q = nr_quotient(phi, b);
+  return b > kEps ? q : 1.f;
+}
+
 // Views handled by one separable pass launch.
 constexpr int kSepFwdViews = 2;
 constexpr int kSepBwdViews = 2;
@@ -187,6 +204,10 @@ hipError_t launch_sep_single_dispatch(const SepPassArgs &a, const SepPlan &p, in
 hipError_t launch_pointwise_sim(const AdjPointArgs &a, int nblocks, hipStream_t s);
 hipError_t launch_pointwise_seq(const AdjPointArgs &a, int nblocks, hipStream_t s);
 hipError_t launch_sum_partials(const double *part, int nblocks, int nv, double *acc, hipStream_t s);
+// Pointwise ends of the reverse sweep's passes for kernels summed term by term:
+// r = φ / b (guarded), and b ← −sum · r / b (0 where b ≤ ε).
+hipError_t launch_ratio_plane(const float *phi, const float *b, float *r, size_t n, hipStream_t s);
+hipError_t launch_bbar_plane(const float *sum, const float *r, float *b, size_t n, hipStream_t s);
 hipError_t launch_corr(const CorrArgs &a, int nblocks, hipStream_t s);
 // Matrix-core form: padded lags, tile width, z-run length and grid from
 // corr_mfma_shape (at most max_blocks work-groups, one resident wave of them).

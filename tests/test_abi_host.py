@@ -290,8 +290,18 @@ def test_backward_validation_before_device():
         r2 = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need)
         assert grads(r2, gwp=[512, 1024]) == N.MVD_ERR_ARG            # no weight planes to differentiate
         assert grads(r2) == N.MVD_ERR_DEVICE
-        api.mvd_set_psf(ctx, 1, random_psf(rng, 5, 5).astype(np.float32))   # not rank one
-        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need)
+        api.mvd_set_psf(ctx, 1, random_psf(rng, 5, 5).astype(np.float32))   # rank 5: a sum of 5 terms
+        assert api.mvd_psf_info(ctx, 1)[0] == 5
+        plain = api.make_run(4, 2, checkpoints=64)
+        need2 = api.mvd_backward_workspace_bytes(ctx, plain)  # + a plane set for the terms' sums
+        assert need2 > need
+        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need2 - 256)
+        assert call(r) == N.MVD_ERR_WORKSPACE
+        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need2)
+        assert call(r) == N.MVD_ERR_DEVICE
+        api.mvd_set_psf(ctx, 1, random_psf(rng, 15, 15).astype(np.float32))   # full rank: K×K passes
+        assert api.mvd_psf_info(ctx, 1)[0] == 0
+        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need2)
         assert call(r) == N.MVD_ERR_UNSUPPORTED
     finally:
         api.mvd_destroy(ctx)
