@@ -374,11 +374,12 @@ mvd_status mvd_backward_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, 
  *   grad_weights: device [V] or NULL.  grad_init: device [Y][Z][X], ∂L/∂ψ^0,
  *        or NULL.  Outputs are overwritten, in float32 from float64 sums in a
  *        fixed order (bitwise reproducible).
- * Every view's PSF and back-projector must be rank one or a sum of a few
- * rank-one terms (mvd_psf_info ≥ 1: kernels of low rank, whose passes are
- * summed term by term; the tap gradients cover the whole K×K kernel);
- * MVD_ERR_UNSUPPORTED for kernels on the K×K passes, with MVD_FLAG_FORCE_2D
- * and with MVD_FLAG_NORMALIZE.  Per-pixel
+ * PSFs and back-projectors of every form are differentiated: rank one,
+ * sums of a few rank-one terms (summed term by term) and general K×K kernels
+ * (the K×K passes); the tap gradients always cover the whole K×K kernel, and
+ * the reverse sweep may use other pass forms than the forward call
+ * (MVD_FLAG_FORCE_2D), which changes float32 rounding only.
+ * MVD_ERR_UNSUPPORTED with MVD_FLAG_NORMALIZE.  Per-pixel
  * weight planes (run->weight_planes) are taken as in the forward call: each
  * pixel's correction tempered by o = w_v · ω_v(pixel); grad_weights is then
  * ∂L/∂w_v with the planes held fixed (mvd_backward_grads also returns ∂L/∂ω_v).

@@ -111,10 +111,7 @@ __global__ void __launch_bounds__(NT) twod_forward_kernel(const TwoDPassArgs a) 
       const size_t off = t.plane_off + (size_t)z * a.g.X + t.x0 + ox;
 #pragma unroll
       for (int n = 0; n < N4; ++n) {
-        if (t.x0 + ox + n < a.g.X) {
-          const float p = a.phi[v][off + n];
-          a.out[v][off + n] = guarded_ratio(p, b[n]);
-        }
+        if (t.x0 + ox + n < a.g.X) a.out[v][off + n] = a.phi[v] ? guarded_ratio(a.phi[v][off + n], b[n]) : b[n];
       }
     }
   }
@@ -263,7 +260,7 @@ __global__ void __launch_bounds__(MNT) twod_mfma_forward_kernel(const TwoDPassAr
         const int z = t.z0 + m0 + 4 * (lane >> 4) + i;
         if (z < a.g.Z && x < a.g.X) {
           const size_t off = t.plane_off + (size_t)z * a.g.X + x;
-          a.out[v][off] = guarded_ratio(a.phi[v][off], acc[blk][i]);
+          a.out[v][off] = a.phi[v] ? guarded_ratio(a.phi[v][off], acc[blk][i]) : acc[blk][i];
         }
       }
     }

@@ -14,7 +14,8 @@
 //  * pointwise_seq: the same for one view of the sequential update.
 //  * ratio_plane / bbar_plane: the pointwise ends of the passes of a kernel
 //    that is a sum of rank-one terms (the sum formed term by term first):
-//    r = φ / b (1 where b ≤ ε) and b̄ = −s · r / b (0 where b ≤ ε).
+//    r = φ / b (1 where b ≤ ε) and b̄ = −s · r / b (0 where b ≤ ε); and
+//    add_plane, ψ̄ += b̄ ⊛ P^* after a K×K pass stored the convolution.
 //  * corr: tap gradient Σ_{y,z,x} ḡ[y][z][x] · ã[y][z+R−j][x+R−i] for every
 //    lag (j, i) of a K×K kernel (ã zero or wrapped outside the plane): each
 //    thread owns a 4×8 block of lags and slides over 8×64 tiles staged in LDS.
@@ -191,6 +192,11 @@ __global__ void __launch_bounds__(NT) bbar_plane_kernel(const float *__restrict_
     const float q = nr_quotient(s[i] * r[i], bb);
     b[i] = bb > kEps ? -q : 0.f;
   }
+}
+
+// dst += src (ψ̄ += b̄ ⊛ P^* after a K×K pass stored the convolution).
+__global__ void __launch_bounds__(NT) add_plane_kernel(float *dst, const float *__restrict__ src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) dst[i] += src[i];
 }
 
 // acc[v] += Σ_b part[b][v]: one work-group per view, fixed order.
@@ -667,6 +673,13 @@ hipError_t launch_bbar_plane(const float *sum, const float *r, float *b, size_t 
   const unsigned blocks = (unsigned)std::min<size_t>((n + NT - 1) / NT, 8192);
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(bbar_plane_kernel, dim3(blocks), dim3(NT), 0, s, sum, r, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_plane(float *dst, const float *src, size_t n, hipStream_t s) {
+  const unsigned blocks = (unsigned)std::min<size_t>((n + NT - 1) / NT, 8192);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(add_plane_kernel, dim3(blocks), dim3(NT), 0, s, dst, src, n);
   return hipGetLastError();
 }
 

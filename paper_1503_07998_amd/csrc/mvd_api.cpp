@@ -278,6 +278,9 @@ std::vector<float> to_f32(const std::vector<double> &v) {
 // Floats of the sensitivity factors (padded so that an 8-wide read past a row end
 // stays inside the allocation).
 // Each [Z] and [X] vector starts on a 16-byte boundary (the passes read 8 at a time).
+// Tap sets per view on the device for the K×K passes (P_v, X_v, P_v^*, X_v^*).
+constexpr int kTapSets = 4;
+
 size_t norm_stride(const mvd_ctx *c) { return (size_t)((c->Z + 3) / 4 * 4) + (size_t)((c->X + 3) / 4 * 4); }
 size_t norm_zlen(const mvd_ctx *c) { return (size_t)((c->Z + 3) / 4 * 4); }
 size_t norm_floats(const mvd_ctx *c) { return (size_t)c->nv * 2 * norm_stride(c) + 16; }
@@ -333,7 +336,7 @@ mvd_status derive(mvd_ctx *c) {
   c->kxpm = (c->kxm + 3) & ~3;
   if (c->device != MVD_DEVICE_NONE) {
     const size_t per = (size_t)c->kzm * c->kxpm;
-    const size_t ntaps = (size_t)c->nv * 2 * per;
+    const size_t ntaps = (size_t)c->nv * kTapSets * per;
     std::vector<float> host(ntaps + norm_floats(c), 0.f);
     // 1 ⊛ X_v for a rank-one X_v = xz ⊗ xx: (Σ_j xz[j] over rows z + Rz − j inside
     // the plane) · (the same along x); periodic: the full sums
@@ -359,14 +362,17 @@ mvd_status derive(mvd_ctx *c) {
       }
     }
     for (int v = 0; v < c->nv; ++v) {
-      for (int which = 0; which < 2; ++which) {
-        const Kernel &k = which == 0 ? c->views[v].psf : c->views[v].back;
-        float *dst = host.data() + ((size_t)v * 2 + which) * per;
+      for (int which = 0; which < kTapSets; ++which) {
+        const Kernel &k = which % 2 == 0 ? c->views[v].psf : c->views[v].back;
+        float *dst = host.data() + ((size_t)v * kTapSets + which) * per;
         const int oz = (c->kzm - k.kz) / 2, ox = (c->kxm - k.kx) / 2;
-        // embedded centred in kzm×kxm, then point-reflected: ft[jj][q] = k[kzm-1-jj][kxm-1-q]
+        // embedded centred in kzm×kxm; sets 0, 1 point-reflected (ft[jj][q] =
+        // k[kzm-1-jj][kxm-1-q]: the passes convolve with k), sets 2, 3 as given
+        // (the passes then convolve with k's point reflection)
         for (int j = 0; j < k.kz; ++j)
           for (int i = 0; i < k.kx; ++i) {
-            const int jj = c->kzm - 1 - (j + oz), q = c->kxm - 1 - (i + ox);
+            const bool refl = which < 2;
+            const int jj = refl ? c->kzm - 1 - (j + oz) : j + oz, q = refl ? c->kxm - 1 - (i + ox) : i + ox;
             dst[(size_t)jj * c->kxpm + q] = (float)k.at(j, i);
           }
       }
@@ -392,7 +398,7 @@ mvd_status derive(mvd_ctx *c) {
 // Device sensitivity factors of view v under `boundary`: [Z] along z, then (at
 // norm_zlen) [X].
 const float *norm_factors(const mvd_ctx *c, int v, int boundary) {
-  const size_t ntaps = (size_t)c->nv * 2 * c->kzm * c->kxpm;
+  const size_t ntaps = (size_t)c->nv * kTapSets * c->kzm * c->kxpm;
   return c->d_taps + ntaps + ((size_t)v * 2 + (boundary == MVD_BOUNDARY_PERIODIC ? 1 : 0)) * norm_stride(c);
 }
 
@@ -730,8 +736,10 @@ hipError_t timed(const RunState &st, int kind, F &&launch) {
 
 float weight_of(const RunState &st, int v) { return st.w ? st.w[v] : 1.f; }
 
+// Device taps of view v for the K×K passes: which = 0 convolves with P_v,
+// 1 with X_v, 2 with P_v^*, 3 with X_v^* (the point reflections).
 const float *dtaps(const mvd_ctx *c, int v, int which) {
-  return c->d_taps + ((size_t)v * 2 + which) * c->kzm * c->kxpm;
+  return c->d_taps + ((size_t)v * kTapSets + which) * c->kzm * c->kxpm;
 }
 
 // Forward pass over views [v0, v0+n): r[v] = φ_v / (psi ⊛ P_v)
@@ -986,9 +994,9 @@ struct BwdLayout {
   size_t plane_set = 0;
   size_t phi_off = 0, b_off = 0, r_off = 0, q_off = 0, g_off = 0, sub_off = 0, rat_off = 0;
   size_t wpart_off = 0, cpart_off = 0, acc_off = 0, total = 0;
-  size_t tmp_off = 0;   // a plane set for sums of rank-one terms (kernels of low rank), else none
+  size_t tmp_off = 0;   // a plane set for convolutions finished pointwise (kernels not rank one), else none
   int nsets = 0, nsub = 0;
-  bool low_rank = false;
+  bool low_rank = false;   // some view's PSF or back-projector is not rank one
 };
 
 // accumulators: per view [psf kz·kx][back kz·kx], then V weights (doubles)
@@ -1018,7 +1026,7 @@ BwdLayout bwd_layout_of(const mvd_ctx *c, const mvd_run *r) {
   off += (size_t)L.nsub * L.plane_set;
   L.rat_off = off;
   if (!sim) off += L.plane_set;
-  L.low_rank = uses_low_rank(c, r);
+  for (const ViewPsf &w : c->views) L.low_rank = L.low_rank || !w.sep_p || !w.sep_x;
   L.tmp_off = off;
   if (L.low_rank) off += L.plane_set;
   size_t lags = 0;   // padded lags of a partial, either form
@@ -1220,20 +1228,38 @@ hipError_t terms_sum(const RunState &st, const std::vector<std::vector<float>> &
 
 size_t plane_elems(const RunState &st) { return (size_t)st.g.Y * st.g.Z * st.g.X; }
 
+// out = in ⊛ k on the K×K passes, the convolution itself stored (tap set
+// `which` of view v: 0 P_v, 1 X_v, 2 P_v^*, 3 X_v^*).
+hipError_t twod_store(const RunState &st, const float *in, int v, int which, float *out) {
+  TwoDPassArgs a{};
+  a.g = st.g;
+  a.boundary = st.boundary;
+  a.nviews = 1;
+  a.kz = st.c->kzm;
+  a.kx = st.c->kxm;
+  a.in[0] = in;
+  a.phi[0] = nullptr;
+  a.out[0] = out;
+  a.taps[0] = dtaps(st.c, v, which);
+  a.mfma = st.tn->valu2d ? 0 : 1;
+  return timed(st, 3, [&] { return launch_2d_forward(a, st.s); });
+}
+
 // b = ψ ⊛ P_v with r = φ / b (guarded), then q = r ⊛ X_v.  Kernels of low
-// rank are summed term by term and finished pointwise.
+// rank are summed term by term, others run on the K×K passes, and both are
+// finished pointwise.
 hipError_t view_recompute(const RunState &st, int v, const float *psi, const float *phi, const ViewBufs &vb) {
   const ViewPsf &w = st.c->views[v];
   hipError_t e;
   if (w.sep_p) {
     e = single_pass(st, kEpBR, psi, w.pz, w.px, vb.b, vb.r, nullptr, nullptr, phi);
   } else {
-    e = terms_sum(st, w.lpz, w.lpx, psi, vb.b, false, 3);
+    e = !w.lpz.empty() ? terms_sum(st, w.lpz, w.lpx, psi, vb.b, false, 3) : twod_store(st, psi, v, 0, vb.b);
     if (e == hipSuccess) e = timed(st, 3, [&] { return launch_ratio_plane(phi, vb.b, vb.r, plane_elems(st), st.s); });
   }
   if (e != hipSuccess) return e;
   if (w.sep_x) return single_pass(st, kEpStore, vb.r, w.xz, w.xx, vb.q, nullptr, nullptr, nullptr, nullptr);
-  return terms_sum(st, w.lxz, w.lxx, vb.r, vb.q, false, 3);
+  return !w.lxz.empty() ? terms_sum(st, w.lxz, w.lxx, vb.r, vb.q, false, 3) : twod_store(st, vb.r, v, 1, vb.q);
 }
 
 hipError_t view_backprop(const RunState &st, const BwdLayout &L, char *ws, int v, const float *psi,
@@ -1248,7 +1274,7 @@ hipError_t view_backprop(const RunState &st, const BwdLayout &L, char *ws, int v
     if (w.sep_x) {
       e = single_pass(st, kEpBbar, vb.q, reversed(w.xz), reversed(w.xx), vb.b, nullptr, vb.r, vb.b, nullptr);
     } else {
-      e = terms_sum(st, w.lxz, w.lxx, vb.q, st.acc, true, 3);
+      e = !w.lxz.empty() ? terms_sum(st, w.lxz, w.lxx, vb.q, st.acc, true, 3) : twod_store(st, vb.q, v, 3, st.acc);
       if (e == hipSuccess)
         e = timed(st, 3, [&] { return launch_bbar_plane(st.acc, vb.r, vb.b, plane_elems(st), st.s); });
     }
@@ -1259,10 +1285,14 @@ hipError_t view_backprop(const RunState &st, const BwdLayout &L, char *ws, int v
     if (w.sep_p) {
       e = single_pass(st, kEpAccum, vb.b, reversed(w.pz), reversed(w.px), gbar_out, nullptr, gbar_out, nullptr,
                       nullptr);
-    } else {
+    } else if (!w.lpz.empty()) {
       for (size_t t = 0; t < w.lpz.size() && e == hipSuccess; ++t)
         e = single_pass(st, kEpAccum, vb.b, reversed(w.lpz[t]), reversed(w.lpx[t]), gbar_out, nullptr, gbar_out,
                         nullptr, nullptr);
+    } else {
+      e = twod_store(st, vb.b, v, 2, st.acc);
+      if (e == hipSuccess)
+        e = timed(st, 3, [&] { return launch_add_plane(gbar_out, st.acc, plane_elems(st), st.s); });
     }
   }
   return e;
@@ -2936,16 +2966,8 @@ mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *g
   if (r->n_iters < 1) return fail(c, MVD_ERR_ARG, "n_iters must be >= 1 for the reverse sweep");
   if (!r->checkpoints) return fail(c, MVD_ERR_ARG, "run->checkpoints must hold psi^0..psi^{T-1}");
   if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
-  if (r->flags & MVD_FLAG_FORCE_2D)
-    return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep runs rank-one kernels only");
   if (r->flags & MVD_FLAG_NORMALIZE)
     return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep has no normalised form");
-  for (int v = 0; v < c->nv; ++v) {
-    const ViewPsf &w = c->views[v];
-    if ((!w.sep_p && w.lpz.empty()) || (!w.sep_x && w.lxz.empty()))
-      return fail(c, MVD_ERR_UNSUPPORTED,
-                  "view %d: PSF or back-projector is neither rank one nor a sum of a few rank-one terms", v);
-  }
   const BwdLayout L = bwd_layout_of(c, r);
   if (!r->workspace || r->workspace_bytes < L.total)
     return fail(c, MVD_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,

@@ -112,7 +112,7 @@ struct TwoDPassArgs {
   int nviews;
   int kz, kx;                          // common (padded) kernel size of this pass
   const float *in[k2dViews];
-  const float *phi[k2dViews];
+  const float *phi[k2dViews];          // forward: φ_v, or null to store the convolution itself
   float *out[k2dViews];
   const float *psi_in;
   float *psi_out;
@@ -208,6 +208,8 @@ hipError_t launch_sum_partials(const double *part, int nblocks, int nv, double *
 // r = φ / b (guarded), and b ← −sum · r / b (0 where b ≤ ε).
 hipError_t launch_ratio_plane(const float *phi, const float *b, float *r, size_t n, hipStream_t s);
 hipError_t launch_bbar_plane(const float *sum, const float *r, float *b, size_t n, hipStream_t s);
+// dst += src, element by element.
+hipError_t launch_add_plane(float *dst, const float *src, size_t n, hipStream_t s);
 hipError_t launch_corr(const CorrArgs &a, int nblocks, hipStream_t s);
 // Matrix-core form: padded lags, tile width, z-run length and grid from
 // corr_mfma_shape (at most max_blocks work-groups, one resident wave of them).

@@ -267,7 +267,7 @@ def test_backward_validation_before_device():
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need)
         assert call(r) == N.MVD_ERR_DEVICE
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, force_2d=True)
-        assert call(r) == N.MVD_ERR_UNSUPPORTED
+        assert call(r) == N.MVD_ERR_DEVICE                     # K×K forward passes: differentiable too
         rng = np.random.default_rng(0)
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, normalize=True)
         assert call(r) == N.MVD_ERR_UNSUPPORTED
@@ -302,7 +302,7 @@ def test_backward_validation_before_device():
         api.mvd_set_psf(ctx, 1, random_psf(rng, 15, 15).astype(np.float32))   # full rank: K×K passes
         assert api.mvd_psf_info(ctx, 1)[0] == 0
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need2)
-        assert call(r) == N.MVD_ERR_UNSUPPORTED
+        assert call(r) == N.MVD_ERR_DEVICE
     finally:
         api.mvd_destroy(ctx)
 

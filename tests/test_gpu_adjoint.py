@@ -1,5 +1,6 @@
 """GPU reverse sweep (mvd_backward, mvd_backward_grads) against the FP64
-oracle's adjoint: rank-one and low-rank PSFs, scalar and per-pixel weights.
+oracle's adjoint: rank-one, low-rank and full-rank (K×K) PSFs, scalar and
+per-pixel weights.
 
 Bar: each gradient array within 1e-3 of the oracle's, relative to that array's
 largest magnitude (float32 recomputation and float64 fixed-order reductions
@@ -27,7 +28,7 @@ def _say(msg):
 
 
 def gpu_forward_backward(stacks, psfs, T, gout, update="simultaneous", boundary="zero", weights=None,
-                         layout="stack_zyx", weight_planes=None, plane_grads=False):
+                         layout="stack_zyx", weight_planes=None, plane_grads=False, force_2d=False):
     """Forward run with checkpoints, then the reverse sweep.  weight_planes:
     per-view float32 [Y][Z][X] arrays; plane_grads: also ∂L/∂ω_v (through
     mvd_backward_grads, else mvd_backward)."""
@@ -51,7 +52,7 @@ def gpu_forward_backward(stacks, psfs, T, gout, update="simultaneous", boundary=
     if weight_planes is not None:
         wpl = [torch.from_numpy(np.ascontiguousarray(w.astype(np.float32))).to(dev) for w in weight_planes]
     run = api.make_run(Y, T, update=update, boundary=boundary, weights=weights, checkpoints=ck.data_ptr(),
-                       obs_dtype=obs_dtype, layout=layout,
+                       obs_dtype=obs_dtype, layout=layout, force_2d=force_2d,
                        weight_planes=[w.data_ptr() for w in wpl] if wpl is not None else None)
     nb = api.mvd_workspace_bytes(d.ctx, run)
     ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
@@ -244,6 +245,45 @@ def test_backward_low_rank_psfs_match_oracle(case):
     stacks = [rng.uniform(20.0, 300.0, (Z, Y, X)).astype(np.float32) for _ in shapes]
     gout = rng.standard_normal((Y, Z, X))
     got = gpu_forward_backward(stacks, psfs, T, gout, update, boundary, weights)
+    ref = oracle_adjoint(stacks, psfs, T, gout, update, boundary, weights)
+    for v in range(len(shapes)):
+        close(got["grad_psf"][v], ref["grad_psf"][v], f"grad_psf[{v}]")
+        close(got["grad_back"][v], ref["grad_back"][v], f"grad_back[{v}]")
+    close(got["grad_weights"], ref["grad_weights"], "grad_weights")
+    close(got["grad_init"], ref["grad_psi0"], "grad_init")
+
+
+KXK_CASES = [
+    # (Y, Z, X, [(kz, kx, full)], T, update, boundary, weights, force_2d); full: a full-rank kernel
+    (2, 30, 40, [(9, 9, True), (7, 11, True)], 2, "simultaneous", "zero", [0.9, 0.8], False),
+    (2, 24, 50, [(15, 15, True), (5, 5, False)], 2, "sequential", "periodic", None, False),
+    (1, 33, 70, [(31, 31, True), (21, 21, True)], 2, "simultaneous", "zero", None, False),
+    (2, 26, 45, [(9, 7, False), (7, 9, False)], 3, "sequential", "zero", [1.0, 0.7], True),   # K×K forced
+]
+
+
+@pytest.mark.parametrize("case", KXK_CASES, ids=[f"kxk{i}" for i in range(len(KXK_CASES))])
+def test_backward_kxk_psfs_match_oracle(case):
+    """Full-rank PSFs (the K×K passes, which store the convolution and finish
+    the ratio, b̄ and ψ̄ pointwise) and runs forced onto the K×K passes,
+    against the oracle's adjoint."""
+    from paper_1503_07998_amd import api
+
+    Y, Z, X, shapes, T, update, boundary, weights, force_2d = case
+    _say(f"backward K×K Y={Y} Z={Z} X={X} k={shapes} T={T} {update} {boundary} w={weights} force_2d={force_2d}")
+    rng = np.random.default_rng(Y * 11 + Z * 5 + X)
+    psfs = [random_psf(rng, kz, kx, separable=not full).astype(np.float32) for kz, kx, full in shapes]
+    ctx = api.mvd_create(len(psfs), Z, X, -1)
+    try:
+        for v, p in enumerate(psfs):
+            api.mvd_set_psf(ctx, v, p)
+        for v, (_, _, full) in enumerate(shapes):
+            assert api.mvd_psf_info(ctx, v) == ((0, 0) if full else (1, 1))
+    finally:
+        api.mvd_destroy(ctx)
+    stacks = [rng.uniform(20.0, 300.0, (Z, Y, X)).astype(np.float32) for _ in shapes]
+    gout = rng.standard_normal((Y, Z, X))
+    got = gpu_forward_backward(stacks, psfs, T, gout, update, boundary, weights, force_2d=force_2d)
     ref = oracle_adjoint(stacks, psfs, T, gout, update, boundary, weights)
     for v in range(len(shapes)):
         close(got["grad_psf"][v], ref["grad_psf"][v], f"grad_psf[{v}]")
