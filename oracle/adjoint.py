@@ -17,6 +17,12 @@ memory table in Supplementary Note 2, read as the same tempering pixel by
 pixel); its gradient is then the per-pixel array ∂L/∂w_v(pixel) = Σ_t c̄_v·(q_v − 1)
 instead of that array's sum.
 
+With the EM-normalised back-projection (``normalize``: q_v / s_v where
+s_v = 1 ⊛ X_v > ε, see ``mvrl.view_factor``) the chain rule also runs through
+s_v: q̄ = q̄'/s_v and s̄_v = −q̄'·q'/s_v where s_v > ε, and since s_v is the
+convolution of a plane of ones with X_v, ∂L/∂X_v gains the tap gradient of s̄_v
+against that plane.
+
 Tap derivatives follow from differentiating the convolution sum
 (a ⊛ k)[z][x] = Σ k[j][i] ã[z+Rz−j][x+Rx−i]:  ∂/∂k[j][i] = ã[z+Rz−j][x+Rx−i],
 so ∂L/∂k[j][i] = Σ_{z,x} ḡ[z][x] ã[z+Rz−j][x+Rx−i] for the upstream gradient ḡ.
@@ -26,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .mvrl import EPS, PERIODIC, SEQUENTIAL, SIMULTANEOUS, ZERO, _extend, conv2d, flip, ratio
+from .mvrl import EPS, PERIODIC, SEQUENTIAL, SIMULTANEOUS, ZERO, _extend, conv2d, flip, ratio, sensitivity
 
 
 def tap_gradient(gbar, a, kshape, boundary=ZERO) -> np.ndarray:
@@ -42,25 +48,37 @@ def tap_gradient(gbar, a, kshape, boundary=ZERO) -> np.ndarray:
     return out
 
 
-def _factors(psi, phis, psfs, backs, ws, boundary, method="direct"):
-    """b, mask, r, q, c of every view from the same ψ."""
+def _factors(psi, phis, psfs, backs, ws, boundary, method="direct", normalize=False):
+    """b, mask, r, q, c, s of every view from the same ψ (q normalised by the
+    sensitivity s where s > ε when ``normalize``; s None otherwise)."""
     out = []
     for phi, p, x, w in zip(phis, psfs, backs, ws):
         b = conv2d(psi, p, boundary, method)
         m = b > EPS
         r = ratio(phi, b)
         q = conv2d(r, x, boundary, method)
+        sens = None
+        if normalize:
+            sens = sensitivity(psi.shape[-2:], x, boundary, method)
+            q = np.where(sens > EPS, q / np.where(sens > EPS, sens, 1.0), q)
         c = w * q + (1.0 - w)
-        out.append((b, m, r, q, c))
+        out.append((b, m, r, q, c, sens))
     return out
 
 
 def _view_adjoint(cbar, psi, phi_parts, p, x, w, boundary, gp, gx, method="direct"):
     """Back-propagate c̄ of one view into ψ̄ (returned) and the tap/weight gradients."""
-    b, m, r, q, _ = phi_parts
+    b, m, r, q, _, sens = phi_parts
     # ∂c/∂w = q − 1, pixel by pixel; a scalar weight collects the sum
     gw = cbar * (q - 1.0) if np.ndim(w) else float(np.sum(cbar * (q - 1.0)))
     qbar = w * cbar
+    if sens is not None:
+        # q = q_raw / s where s > ε: q̄_raw = q̄ / s, s̄ = −q̄ · q / s; s = 1 ⊛ X
+        ok = sens > EPS
+        safe = np.where(ok, sens, 1.0)
+        sbar = np.where(ok, -qbar * q / safe, 0.0)
+        qbar = np.where(ok, qbar / safe, qbar)
+        gx += tap_gradient(sbar, np.ones_like(psi), x.shape, boundary)
     rbar = conv2d(qbar, flip(x), boundary, method)
     gx += tap_gradient(qbar, r, x.shape, boundary)
     safe = np.where(m, b, 1.0)
@@ -71,20 +89,20 @@ def _view_adjoint(cbar, psi, phi_parts, p, x, w, boundary, gp, gx, method="direc
 
 
 def forward_history(phis, psfs, backs, weights, iters, update=SIMULTANEOUS, boundary=ZERO, psi0=None,
-                    method="direct"):
+                    method="direct", normalize=False):
     """[ψ^0, …, ψ^T] with ψ^0 the mean of the observations unless given."""
     from .mvrl import init_estimate, rl_iteration
 
     psi = init_estimate(phis) if psi0 is None else np.asarray(psi0, dtype=np.float64)
     hist = [psi]
     for _ in range(iters):
-        psi = rl_iteration(psi, phis, psfs, backs, weights, update, boundary, method)
+        psi = rl_iteration(psi, phis, psfs, backs, weights, update, boundary, method, normalize)
         hist.append(psi)
     return hist
 
 
 def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, boundary=ZERO,
-            psi0=None, history=None, method="direct"):
+            psi0=None, history=None, method="direct", normalize=False):
     """Reverse sweep.  Returns dict(grad_psf=[V×K×K], grad_back=[V×K×K],
     grad_weights=[V], grad_psi0=array).  With a per-pixel weight array among
     the weights, grad_weights is a list whose entry v is a float for a scalar
@@ -96,7 +114,7 @@ def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, bo
                                              for w in weights]
     per_pixel = any(np.ndim(w) for w in ws)
     hist = history if history is not None else forward_history(phis, ps, xs, ws, iters, update, boundary, psi0,
-                                                               method)
+                                                               method, normalize)
     gp = [np.zeros_like(p) for p in ps]
     gx = [np.zeros_like(x) for x in xs]
     gw = [0.0] * nv
@@ -104,7 +122,7 @@ def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, bo
     for t in range(iters - 1, -1, -1):
         psi = hist[t]
         if update == SIMULTANEOUS:
-            parts = _factors(psi, phis, ps, xs, ws, boundary, method)
+            parts = _factors(psi, phis, ps, xs, ws, boundary, method, normalize)
             cs = [pt[4] for pt in parts]
             prod = np.ones_like(psi)
             for c in cs:
@@ -124,7 +142,7 @@ def adjoint(phis, psfs, backs, weights, iters, grad_out, update=SIMULTANEOUS, bo
             sub = [psi]
             parts = []
             for v in range(nv):
-                pt = _factors(sub[-1], [phis[v]], [ps[v]], [xs[v]], [ws[v]], boundary, method)[0]
+                pt = _factors(sub[-1], [phis[v]], [ps[v]], [xs[v]], [ws[v]], boundary, method, normalize)[0]
                 parts.append(pt)
                 sub.append(sub[-1] * pt[4])
             for v in range(nv - 1, -1, -1):

@@ -2,7 +2,9 @@
 PyTorch CPU float64 autograd through an independent restatement of the forward
 map (torch's own convolution), and exact zeros where a view's weight is 0.
 Per-pixel weight arrays are pinned the same ways, and a constant array must
-give, summed, the scalar weight's gradient."""
+give, summed, the scalar weight's gradient; so is the EM-normalised
+back-projection (whose sensitivity 1 ⊛ X_v depends on the back-projector's
+taps)."""
 import numpy as np
 import pytest
 
@@ -20,8 +22,8 @@ def _problem(seed, shape=(2, 10, 9), kshapes=((5, 3), (3, 5)), weights=(0.8, 0.6
     return phis, psfs, backs, list(weights), gout
 
 
-def _loss(phis, psfs, backs, ws, T, gout, update, boundary):
-    psi = A.forward_history(phis, psfs, backs, ws, T, update, boundary)[-1]
+def _loss(phis, psfs, backs, ws, T, gout, update, boundary, normalize=False):
+    psi = A.forward_history(phis, psfs, backs, ws, T, update, boundary, normalize=normalize)[-1]
     return float(np.sum(gout * psi))
 
 
@@ -59,9 +61,10 @@ def test_adjoint_matches_central_differences(update, boundary):
         assert abs(fd - res["grad_weights"][v]) <= 1e-6 * max(1.0, abs(fd))
 
 
-def _torch_forward(torch, phis, psfs, backs, ws, T, update, boundary):
+def _torch_forward(torch, phis, psfs, backs, ws, T, update, boundary, normalize=False, psi0=None):
     """The forward map restated with torch.nn.functional.conv2d (a correlation:
-    convolving with k is correlating with flip(k))."""
+    convolving with k is correlating with flip(k)); ``normalize`` divides each
+    back-projection by 1 ⊛ X_v where that exceeds ε."""
     F = torch.nn.functional
 
     def conv(a, k):
@@ -74,7 +77,15 @@ def _torch_forward(torch, phis, psfs, backs, ws, T, update, boundary):
             x = F.pad(x, (rx, rx, rz, rz), mode="circular")
         return F.conv2d(x, torch.flip(k, (0, 1)).reshape(1, 1, kz, kx)).squeeze(1)
 
-    psi = sum(phis) / len(phis)
+    def back(r, x):
+        q = conv(r, x)
+        if normalize:
+            sens = conv(torch.ones_like(r), x)
+            ok = sens > oracle.EPS
+            q = torch.where(ok, q / torch.where(ok, sens, torch.ones_like(sens)), q)
+        return q
+
+    psi = sum(phis) / len(phis) if psi0 is None else psi0
     for _ in range(T):
         if update == "simultaneous":
             prod = torch.ones_like(psi)
@@ -82,14 +93,14 @@ def _torch_forward(torch, phis, psfs, backs, ws, T, update, boundary):
                 b = conv(psi, p)
                 r = torch.where(b > oracle.EPS, phi / torch.where(b > oracle.EPS, b, torch.ones_like(b)),
                                 torch.ones_like(b))
-                prod = prod * (w * conv(r, x) + (1 - w))
+                prod = prod * (w * back(r, x) + (1 - w))
             psi = psi * prod
         else:
             for phi, p, x, w in zip(phis, psfs, backs, ws):
                 b = conv(psi, p)
                 r = torch.where(b > oracle.EPS, phi / torch.where(b > oracle.EPS, b, torch.ones_like(b)),
                                 torch.ones_like(b))
-                psi = psi * (w * conv(r, x) + (1 - w))
+                psi = psi * (w * back(r, x) + (1 - w))
     return psi
 
 
@@ -229,3 +240,63 @@ def test_constant_pixel_weights_sum_to_the_scalar_gradient():
                 1.0, abs(scal["grad_weights"][v]))
             np.testing.assert_allclose(arr["grad_psf"][v], scal["grad_psf"][v], rtol=1e-12, atol=1e-14)
         np.testing.assert_allclose(arr["grad_psi0"], scal["grad_psi0"], rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("update", ["simultaneous", "sequential"])
+@pytest.mark.parametrize("boundary", ["zero", "periodic"])
+def test_normalised_adjoint_matches_central_differences(update, boundary):
+    """EM-normalised back-projection: every gradient against FP64 central
+    differences, the back-projector's taps included (they enter through the
+    sensitivity 1 ⊛ X_v as well as through the back-projection)."""
+    phis, psfs, backs, ws, gout = _problem(11)
+    T = 3
+    res = A.adjoint(phis, psfs, backs, ws, T, gout, update, boundary, normalize=True)
+    rng = np.random.default_rng(12)
+    h = 1e-6
+    for v in range(2):
+        for which, taps, grad in (("psf", psfs, res["grad_psf"]), ("back", backs, res["grad_back"])):
+            scale = max(1.0, np.abs(grad[v]).max())
+            for _ in range(4):
+                j = int(rng.integers(taps[v].shape[0]))
+                i = int(rng.integers(taps[v].shape[1]))
+                plus = [t.copy() for t in taps]
+                minus = [t.copy() for t in taps]
+                plus[v][j, i] += h
+                minus[v][j, i] -= h
+                if which == "psf":
+                    lp = _loss(phis, plus, backs, ws, T, gout, update, boundary, True)
+                    lm = _loss(phis, minus, backs, ws, T, gout, update, boundary, True)
+                else:
+                    lp = _loss(phis, psfs, plus, ws, T, gout, update, boundary, True)
+                    lm = _loss(phis, psfs, minus, ws, T, gout, update, boundary, True)
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - grad[v][j, i]) <= 1e-6 * scale, (which, v, j, i, fd, grad[v][j, i])
+        wp = list(ws)
+        wm = list(ws)
+        wp[v] += h
+        wm[v] -= h
+        fd = (_loss(phis, psfs, backs, wp, T, gout, update, boundary, True)
+              - _loss(phis, psfs, backs, wm, T, gout, update, boundary, True)) / (2 * h)
+        assert abs(fd - res["grad_weights"][v]) <= 1e-6 * max(1.0, abs(fd))
+
+
+@pytest.mark.parametrize("update", ["simultaneous", "sequential"])
+@pytest.mark.parametrize("boundary", ["zero", "periodic"])
+def test_normalised_adjoint_matches_torch_autograd(update, boundary):
+    torch = pytest.importorskip("torch")
+    phis, psfs, backs, ws, gout = _problem(13, shape=(2, 8, 11), kshapes=((3, 5), (5, 3), (3, 3)),
+                                           weights=(1.0, 0.7, 0.5))
+    T = 2
+    res = A.adjoint(phis, psfs, backs, ws, T, gout, update, boundary, normalize=True)
+    tphis = [torch.tensor(p, dtype=torch.float64) for p in phis]
+    tp = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in psfs]
+    tx = [torch.tensor(x, dtype=torch.float64, requires_grad=True) for x in backs]
+    tw = [torch.tensor(w, dtype=torch.float64, requires_grad=True) for w in ws]
+    t0 = (sum(tphis) / len(tphis)).detach().requires_grad_(True)
+    psi = _torch_forward(torch, tphis, tp, tx, tw, T, update, boundary, normalize=True, psi0=t0)
+    (psi * torch.tensor(gout)).sum().backward()
+    for v in range(3):
+        np.testing.assert_allclose(res["grad_psf"][v], tp[v].grad.numpy(), rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(res["grad_back"][v], tx[v].grad.numpy(), rtol=1e-10, atol=1e-12)
+        assert abs(res["grad_weights"][v] - tw[v].grad.item()) <= 1e-10 * max(1.0, abs(tw[v].grad.item()))
+    np.testing.assert_allclose(res["grad_psi0"], t0.grad.numpy(), rtol=1e-10, atol=1e-12)
