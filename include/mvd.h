@@ -378,8 +378,9 @@ mvd_status mvd_backward_workspace_bytes(const mvd_ctx *ctx, const mvd_run *run, 
  * sums of a few rank-one terms (summed term by term) and general K×K kernels
  * (the K×K passes); the tap gradients always cover the whole K×K kernel, and
  * the reverse sweep may use other pass forms than the forward call
- * (MVD_FLAG_FORCE_2D), which changes float32 rounding only.
- * MVD_ERR_UNSUPPORTED with MVD_FLAG_NORMALIZE.  Per-pixel
+ * (MVD_FLAG_FORCE_2D), which changes float32 rounding only.  With
+ * MVD_FLAG_NORMALIZE the chain rule also runs through the sensitivity
+ * 1 ⊛ X_v, which depends on the back-projector's taps.  Per-pixel
  * weight planes (run->weight_planes) are taken as in the forward call: each
  * pixel's correction tempered by o = w_v · ω_v(pixel); grad_weights is then
  * ∂L/∂w_v with the planes held fixed (mvd_backward_grads also returns ∂L/∂ω_v).

@@ -10,7 +10,10 @@
 //    o_v = w_v ω_v (as in the forward update): c_v = o_v q_v + 1 − o_v,
 //    q̄_v = o_v c̄_v, w̄_v += Σ c̄_v (q_v − 1) ω_v and, where asked for,
 //    ω̄_v += c̄_v (q_v − 1) w_v pixel by pixel (summed over the iterations in
-//    the caller's buffer).
+//    the caller's buffer).  With the EM-normalised back-projection q_v is
+//    first divided by s_v = 1 ⊛ X_v where s_v > ε (as in the forward pass),
+//    and q̄_v = q̄'_v / s_v, s̄_v = −q̄'_v q_v / s_v are written (s̄_v then
+//    feeds the back-projector's tap gradient through s_v).
 //  * pointwise_seq: the same for one view of the sequential update.
 //  * ratio_plane / bbar_plane: the pointwise ends of the passes of a kernel
 //    that is a sum of rank-one terms (the sum formed term by term first):
@@ -70,6 +73,18 @@ __device__ __forceinline__ void stv(float *p, size_t i, const float (&o)[VW]) {
     p[i] = o[0];
 }
 
+// The normalisation of element i's back-projection: s = nsz[z] · nsx[x]; q is
+// divided by s where s > ε (the forward pass's reciprocal form), and `inv`
+// is 1/s there, 0 elsewhere.
+__device__ __forceinline__ float norm_of(const AdjPointArgs &a, int v, size_t i, float &inv) {
+  const size_t row = i / (size_t)a.X;
+  const int x = (int)(i - row * (size_t)a.X);
+  const int z = (int)(row % (size_t)a.Z);
+  const float sv = a.nsz[v][z] * a.nsx[v][x];
+  inv = sv > kEps ? __builtin_amdgcn_rcpf(sv) : 0.f;
+  return sv;
+}
+
 // NV views, VW elements per thread and step (4: every array 16-byte aligned and
 // n a multiple of 4).  Π_{u≠v} c_u is formed as (c_0 ⋯ c_{v−1}) · (c_{v+1} ⋯ c_{NV−1}).
 // WP: 0 scalar weights only, 1 per-pixel weight planes, 2 weight planes and
@@ -86,7 +101,7 @@ __global__ void __launch_bounds__(NT) pointwise_sim_kernel(AdjPointArgs a) {
     w1[v] = 1.f - w[v];
   }
   for (size_t i = ((size_t)blockIdx.x * NT + threadIdx.x) * VW; i < a.n; i += (size_t)gridDim.x * NT * VW) {
-    float gin[VW], psi[VW], q[NV][VW], gout[VW];
+    float gin[VW], psi[VW], q[NV][VW], gout[VW], inv[NV][VW], sb[NV][VW];
     float om[WP ? NV : 1][VW], gw[WP == 2 ? NV : 1][VW];
     ldv<VW>(a.gbar_in, i, gin);
     ldv<VW>(a.psi, i, psi);
@@ -95,6 +110,13 @@ __global__ void __launch_bounds__(NT) pointwise_sim_kernel(AdjPointArgs a) {
       ldv<VW>(a.q[v], i, q[v]);
       if constexpr (WP >= 1) ldv<VW>(a.wpl[v], i, om[v]);
       if constexpr (WP == 2) ldv<VW>(a.gwpl[v], i, gw[v]);
+      if (a.nrm) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const float sv = norm_of(a, v, i + e, inv[v][e]);
+          if (sv > kEps) q[v][e] *= inv[v][e];
+        }
+      }
     }
 #pragma unroll
     for (int e = 0; e < VW; ++e) {
@@ -124,7 +146,13 @@ __global__ void __launch_bounds__(NT) pointwise_sim_kernel(AdjPointArgs a) {
         else
           wsum[v] += (double)cbar * (double)d;
         if constexpr (WP == 2) gw[v][e] += (cbar * d) * w[v];
-        q[v][e] = o[v] * cbar;
+        const float qb = o[v] * cbar;
+        if (a.nrm) {   // q̄ = q̄'/s and s̄ = −q̄' q / s where s > ε (inv = 0 elsewhere)
+          sb[v][e] = -(qb * q[v][e]) * inv[v][e];
+          q[v][e] = inv[v][e] != 0.f ? qb * inv[v][e] : qb;
+        } else {
+          q[v][e] = qb;
+        }
       }
     }
     stv<VW>(a.gbar_out, i, gout);
@@ -132,6 +160,7 @@ __global__ void __launch_bounds__(NT) pointwise_sim_kernel(AdjPointArgs a) {
     for (int v = 0; v < NV; ++v) {
       stv<VW>(a.q[v], i, q[v]);
       if constexpr (WP == 2) stv<VW>(a.gwpl[v], i, gw[v]);
+      if (a.nrm) stv<VW>(a.sbar[v], i, sb[v]);
     }
   }
 #pragma unroll
@@ -149,12 +178,19 @@ __global__ void __launch_bounds__(NT) pointwise_seq_kernel(AdjPointArgs a) {
   double wsum = 0.0;
   const float w = a.w[0], w1 = 1.f - w;
   for (size_t i = ((size_t)blockIdx.x * NT + threadIdx.x) * VW; i < a.n; i += (size_t)gridDim.x * NT * VW) {
-    float g[VW], q[VW], psi[VW], go[VW], om[VW], gw[VW];
+    float g[VW], q[VW], psi[VW], go[VW], om[VW], gw[VW], inv[VW], sb[VW];
     ldv<VW>(a.gbar_in, i, g);
     ldv<VW>(a.q[0], i, q);
     ldv<VW>(a.psi, i, psi);
     if constexpr (WP >= 1) ldv<VW>(a.wpl[0], i, om);
     if constexpr (WP == 2) ldv<VW>(a.gwpl[0], i, gw);
+    if (a.nrm) {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const float sv = norm_of(a, 0, i + e, inv[e]);
+        if (sv > kEps) q[e] *= inv[e];
+      }
+    }
 #pragma unroll
     for (int e = 0; e < VW; ++e) {
       const float o = WP >= 1 ? w * om[e] : w;
@@ -167,11 +203,18 @@ __global__ void __launch_bounds__(NT) pointwise_seq_kernel(AdjPointArgs a) {
       else
         wsum += (double)cbar * (double)d;
       if constexpr (WP == 2) gw[e] += (cbar * d) * w;
-      q[e] = o * cbar;
+      const float qb = o * cbar;
+      if (a.nrm) {
+        sb[e] = -(qb * q[e]) * inv[e];
+        q[e] = inv[e] != 0.f ? qb * inv[e] : qb;
+      } else {
+        q[e] = qb;
+      }
     }
     stv<VW>(a.gbar_out, i, go);
     stv<VW>(a.q[0], i, q);
     if constexpr (WP == 2) stv<VW>(a.gwpl[0], i, gw);
+    if (a.nrm) stv<VW>(a.sbar[0], i, sb);
   }
   const double s = block_sum(wsum, sh);
   if (threadIdx.x == 0) a.wpart[blockIdx.x] = s;
@@ -607,6 +650,7 @@ bool point_vec(const AdjPointArgs &a, int nv) {
     ok = ok && (uintptr_t)a.q[v] % 16 == 0;
     if (a.wp >= 1) ok = ok && (uintptr_t)a.wpl[v] % 16 == 0;
     if (a.wp == 2) ok = ok && (uintptr_t)a.gwpl[v] % 16 == 0;
+    if (a.nrm) ok = ok && (uintptr_t)a.sbar[v] % 16 == 0;
   }
   return ok;
 }

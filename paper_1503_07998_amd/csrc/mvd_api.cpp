@@ -995,8 +995,10 @@ struct BwdLayout {
   size_t phi_off = 0, b_off = 0, r_off = 0, q_off = 0, g_off = 0, sub_off = 0, rat_off = 0;
   size_t wpart_off = 0, cpart_off = 0, acc_off = 0, total = 0;
   size_t tmp_off = 0;   // a plane set for convolutions finished pointwise (kernels not rank one), else none
+  size_t sbar_off = 0, ones_off = 0;   // normalised runs: s̄ per view (or one), a plane set of ones
   int nsets = 0, nsub = 0;
   bool low_rank = false;   // some view's PSF or back-projector is not rank one
+  bool normalize = false;
 };
 
 // accumulators: per view [psf kz·kx][back kz·kx], then V weights (doubles)
@@ -1029,6 +1031,11 @@ BwdLayout bwd_layout_of(const mvd_ctx *c, const mvd_run *r) {
   for (const ViewPsf &w : c->views) L.low_rank = L.low_rank || !w.sep_p || !w.sep_x;
   L.tmp_off = off;
   if (L.low_rank) off += L.plane_set;
+  L.normalize = (r->flags & MVD_FLAG_NORMALIZE) != 0;
+  L.sbar_off = off;
+  if (L.normalize) off += (size_t)L.nsets * L.plane_set;
+  L.ones_off = off;
+  if (L.normalize) off += L.plane_set;
   size_t lags = 0;   // padded lags of a partial, either form
   for (auto &w : c->views)
     for (const Kernel *d : {&w.psf, &w.back})
@@ -1263,12 +1270,17 @@ hipError_t view_recompute(const RunState &st, int v, const float *psi, const flo
 }
 
 hipError_t view_backprop(const RunState &st, const BwdLayout &L, char *ws, int v, const float *psi,
-                         const ViewBufs &vb, float *gbar_out, bool want_psf, bool want_back) {
+                         const ViewBufs &vb, float *gbar_out, bool want_psf, bool want_back,
+                         const float *sbar = nullptr) {
   mvd_ctx *c = st.c;
   const ViewPsf &w = c->views[v];
   double *acc = reinterpret_cast<double *>(ws + L.acc_off);
   hipError_t e = hipSuccess;
   if (want_back) e = tap_corr(st, L, ws, vb.q, vb.r, w.back.kz, w.back.kx, acc + acc_back(c, v));
+  // normalised runs: s = 1 ⊛ X_v, so ∂L/∂X_v also gains s̄'s correlation with a plane of ones
+  if (e == hipSuccess && want_back && sbar)
+    e = tap_corr(st, L, ws, sbar, reinterpret_cast<const float *>(ws + L.ones_off), w.back.kz, w.back.kx,
+                 acc + acc_back(c, v));
   // b̄ = −(q̄ ⊛ X^*) · r / b  (written over b; a sum of terms goes through st.acc)
   if (e == hipSuccess) {
     if (w.sep_x) {
@@ -2966,8 +2978,6 @@ mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *g
   if (r->n_iters < 1) return fail(c, MVD_ERR_ARG, "n_iters must be >= 1 for the reverse sweep");
   if (!r->checkpoints) return fail(c, MVD_ERR_ARG, "run->checkpoints must hold psi^0..psi^{T-1}");
   if (!c->derived) return fail(c, MVD_ERR_STATE, "not every view has a PSF");
-  if (r->flags & MVD_FLAG_NORMALIZE)
-    return fail(c, MVD_ERR_UNSUPPORTED, "the reverse sweep has no normalised form");
   const BwdLayout L = bwd_layout_of(c, r);
   if (!r->workspace || r->workspace_bytes < L.total)
     return fail(c, MVD_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
@@ -2991,6 +3001,7 @@ mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *g
   }
   RunState rs{c, g, r->boundary, false, s, r->view_weights, (r->flags & MVD_FLAG_TIMING) != 0, &tn};
   rs.wpl = r->weight_planes;   // the sequential sub-states are tempered as in the forward call
+  rs.normalize = L.normalize;  // and normalised
   if (L.low_rank) rs.acc = reinterpret_cast<float *>(ws + L.tmp_off);   // partial sums of terms
   const int V = c->nv;
   const bool sim = r->update == MVD_UPDATE_SIMULTANEOUS;
@@ -3011,6 +3022,17 @@ mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *g
   int cur = 0;
   if (e == hipSuccess) e = launch_copy(grad_est, plane(L.g_off, 0), n, s);
   for (int v = 0; v < V && e == hipSuccess && grad_wpl; ++v) e = launch_fill(grad_wpl[v], n, 0.f, s);
+  if (e == hipSuccess && L.normalize) e = launch_fill(plane(L.ones_off, 0), n, 1.f, s);
+  // the normalisation's factors as the pointwise kernels read them
+  auto set_norm = [&](AdjPointArgs &pa, int slot, int v) {
+    pa.nrm = L.normalize ? 1 : 0;
+    pa.Z = c->Z;
+    pa.X = c->X;
+    if (!L.normalize) return;
+    pa.nsz[slot] = norm_factors(c, v, r->boundary);
+    pa.nsx[slot] = pa.nsz[slot] + norm_zlen(c);
+    pa.sbar[slot] = plane(L.sbar_off, L.nsets > 1 ? v : 0);
+  };
   const int T = r->n_iters;
   for (int t = T - 1; t >= 0 && e == hipSuccess; --t) {
     const float *psi = r->checkpoints + (size_t)t * n;
@@ -3032,13 +3054,15 @@ mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *g
         pa.w[v] = weight_of(rs, v);
         if (wp >= 1) pa.wpl[v] = r->weight_planes[v];
         if (wp == 2) pa.gwpl[v] = grad_wpl[v];
+        set_norm(pa, v, v);
       }
       pa.wp = wp;
       pa.wpart = wpart;
       e = timed(rs, 3, [&] { return launch_pointwise_sim(pa, kPointBlocks, s); });
       if (e == hipSuccess) e = launch_sum_partials(wpart, kPointBlocks, V, acc + acc_w(c), s);
       for (int v = 0; v < V && e == hipSuccess; ++v)
-        e = view_backprop(rs, L, ws, v, psi, vb[v], plane(L.g_off, 1 - cur), want_psf, want_back);
+        e = view_backprop(rs, L, ws, v, psi, vb[v], plane(L.g_off, 1 - cur), want_psf, want_back,
+                          L.normalize ? plane(L.sbar_off, v) : nullptr);
       cur = 1 - cur;
     } else {
       // sub-states ψ_v of the sequential sweep: ψ_0 = ψ^t, ψ_{v+1} = ψ_v · c_v(ψ_v)
@@ -3067,10 +3091,13 @@ mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *g
         pa.wp = wp;
         if (wp >= 1) pa.wpl[0] = r->weight_planes[v];
         if (wp == 2) pa.gwpl[0] = grad_wpl[v];
+        set_norm(pa, 0, v);
         pa.wpart = wpart;
         e = timed(rs, 3, [&] { return launch_pointwise_seq(pa, kPointBlocks, s); });
         if (e == hipSuccess) e = launch_sum_partials(wpart, kPointBlocks, 1, acc + acc_w(c) + v, s);
-        if (e == hipSuccess) e = view_backprop(rs, L, ws, v, sub[v], vb, plane(L.g_off, 1 - cur), want_psf, want_back);
+        if (e == hipSuccess)
+          e = view_backprop(rs, L, ws, v, sub[v], vb, plane(L.g_off, 1 - cur), want_psf, want_back,
+                            L.normalize ? plane(L.sbar_off, 0) : nullptr);
         cur = 1 - cur;
       }
     }

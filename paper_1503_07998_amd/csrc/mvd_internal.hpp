@@ -185,6 +185,13 @@ struct AdjPointArgs {
   int wp;                // 0 scalar weights, 1 per-pixel weight planes, 2 planes and their gradients
   const float *wpl[kMaxViews];   // ω_v (wp ≥ 1)
   float *gwpl[kMaxViews];        // ∂L/∂ω_v, accumulated (wp = 2)
+  // EM-normalised back-projection: q_v holds the raw back-projection, divided
+  // here by s_v(z, x) = nsz_v[z] · nsx_v[x] where that exceeds ε; s̄_v is written
+  int nrm;
+  int Z, X;
+  const float *nsz[kMaxViews];
+  const float *nsx[kMaxViews];
+  float *sbar[kMaxViews];
 };
 
 // Tap-gradient correlation over all planes: part[block][j][i] partial sums of

@@ -270,7 +270,11 @@ def test_backward_validation_before_device():
         assert call(r) == N.MVD_ERR_DEVICE                     # K×K forward passes: differentiable too
         rng = np.random.default_rng(0)
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, normalize=True)
-        assert call(r) == N.MVD_ERR_UNSUPPORTED
+        assert call(r) == N.MVD_ERR_WORKSPACE                  # normalised: s̄ planes and a plane of ones more
+        need_n = api.mvd_backward_workspace_bytes(ctx, r)
+        assert need_n > need
+        r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need_n, normalize=True)
+        assert call(r) == N.MVD_ERR_DEVICE
         # weight planes are taken (the device check comes next)
         r = api.make_run(4, 2, checkpoints=64, workspace=256, workspace_bytes=need, weight_planes=[64, 128])
         assert call(r) == N.MVD_ERR_DEVICE

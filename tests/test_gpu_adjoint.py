@@ -28,7 +28,8 @@ def _say(msg):
 
 
 def gpu_forward_backward(stacks, psfs, T, gout, update="simultaneous", boundary="zero", weights=None,
-                         layout="stack_zyx", weight_planes=None, plane_grads=False, force_2d=False):
+                         layout="stack_zyx", weight_planes=None, plane_grads=False, force_2d=False,
+                         normalize=False):
     """Forward run with checkpoints, then the reverse sweep.  weight_planes:
     per-view float32 [Y][Z][X] arrays; plane_grads: also ∂L/∂ω_v (through
     mvd_backward_grads, else mvd_backward)."""
@@ -52,7 +53,7 @@ def gpu_forward_backward(stacks, psfs, T, gout, update="simultaneous", boundary=
     if weight_planes is not None:
         wpl = [torch.from_numpy(np.ascontiguousarray(w.astype(np.float32))).to(dev) for w in weight_planes]
     run = api.make_run(Y, T, update=update, boundary=boundary, weights=weights, checkpoints=ck.data_ptr(),
-                       obs_dtype=obs_dtype, layout=layout, force_2d=force_2d,
+                       obs_dtype=obs_dtype, layout=layout, force_2d=force_2d, normalize=normalize,
                        weight_planes=[w.data_ptr() for w in wpl] if wpl is not None else None)
     nb = api.mvd_workspace_bytes(d.ctx, run)
     ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
@@ -83,11 +84,12 @@ def gpu_forward_backward(stacks, psfs, T, gout, update="simultaneous", boundary=
     return out
 
 
-def oracle_adjoint(stacks, psfs, T, gout, update="simultaneous", boundary="zero", weights=None, method="direct"):
+def oracle_adjoint(stacks, psfs, T, gout, update="simultaneous", boundary="zero", weights=None, method="direct",
+                   normalize=False):
     phis = [oracle.reslice(s) for s in stacks]
     ps = [p.astype(np.float64) for p in psfs]
     xs = [oracle.flip(p) for p in ps]
-    return OA.adjoint(phis, ps, xs, weights, T, gout, update, boundary, method=method)
+    return OA.adjoint(phis, ps, xs, weights, T, gout, update, boundary, method=method, normalize=normalize)
 
 
 def close(got, ref, name, tol=TOL):
@@ -289,6 +291,46 @@ def test_backward_kxk_psfs_match_oracle(case):
         close(got["grad_psf"][v], ref["grad_psf"][v], f"grad_psf[{v}]")
         close(got["grad_back"][v], ref["grad_back"][v], f"grad_back[{v}]")
     close(got["grad_weights"], ref["grad_weights"], "grad_weights")
+    close(got["grad_init"], ref["grad_psi0"], "grad_init")
+
+
+NORM_CASES = [
+    # (Y, Z, X, [(kz, kx, rank)], T, update, boundary, weights, weight planes); the
+    # normalised form needs rank-one back-projectors, hence rank-one PSFs here
+    (2, 30, 44, [(9, 7, 1), (7, 11, 1)], 3, "simultaneous", "zero", [0.9, 0.8], False),
+    (2, 26, 37, [(11, 11, 1), (5, 9, 1), (7, 7, 1)], 2, "sequential", "zero", None, False),
+    (2, 24, 48, [(9, 13, 1), (7, 7, 1)], 2, "simultaneous", "periodic", None, False),
+    (1, 40, 64, [(31, 31, 1), (21, 21, 1)], 2, "sequential", "zero", [1.0, 0.7], True),
+]
+
+
+@pytest.mark.parametrize("case", NORM_CASES, ids=[f"n{i}" for i in range(len(NORM_CASES))])
+def test_backward_normalised_matches_oracle(case):
+    """EM-normalised back-projection: the chain rule through q / s_v and
+    through s_v = 1 ⊛ X_v (whose tap gradient is s̄'s correlation with a plane
+    of ones), against the oracle's normalised adjoint; with weight planes too."""
+    Y, Z, X, shapes, T, update, boundary, weights, with_planes = case
+    V = len(shapes)
+    _say(f"backward normalised Y={Y} Z={Z} X={X} k={shapes} T={T} {update} {boundary} w={weights} "
+         f"planes={with_planes}")
+    rng = np.random.default_rng(Y * 13 + Z * 7 + X)
+    psfs = [random_psf(rng, kz, kx, separable=True).astype(np.float32) for kz, kx, _ in shapes]
+    stacks = [rng.uniform(20.0, 300.0, (Z, Y, X)).astype(np.float32) for _ in shapes]
+    gout = rng.standard_normal((Y, Z, X))
+    planes = [rng.uniform(0.2, 1.0, (Y, Z, X)).astype(np.float32) for _ in shapes] if with_planes else None
+    got = gpu_forward_backward(stacks, psfs, T, gout, update, boundary, weights, weight_planes=planes,
+                               normalize=True)
+    ws = [1.0] * V if weights is None else weights
+    eff = [np.float64(ws[v]) * planes[v].astype(np.float64) for v in range(V)] if with_planes else weights
+    ref = oracle_adjoint(stacks, psfs, T, gout, update, boundary, eff, normalize=True)
+    for v in range(V):
+        close(got["grad_psf"][v], ref["grad_psf"][v], f"grad_psf[{v}]")
+        close(got["grad_back"][v], ref["grad_back"][v], f"grad_back[{v}]")
+    if with_planes:
+        close(got["grad_weights"], [float(np.sum(ref["grad_weights"][v] * planes[v])) for v in range(V)],
+              "grad_weights")
+    else:
+        close(got["grad_weights"], ref["grad_weights"], "grad_weights")
     close(got["grad_init"], ref["grad_psi0"], "grad_init")
 
 
