@@ -106,10 +106,13 @@ typedef enum { MVD_INIT_MEAN = 0, MVD_INIT_GIVEN = 1, MVD_INIT_CONST = 2 } mvd_i
 #define MVD_FLAG_NORMALIZE 0x10u /* divide each view's back-projection by X_v ⊛ 1 (the
                                     sensitivity Aᵀ1; below the tap sum within R of the edges
                                     under the zero boundary): the EM form of the update for a
-                                    zero-extended convolution.  Rank-one back-projectors only
-                                    (MVD_ERR_UNSUPPORTED otherwise, with MVD_FLAG_FORCE_2D, and
-                                    in mvd_backward).  Supplementary Note 1 (the update assumes
-                                    unit column sums) */
+                                    zero-extended convolution.  Rank-one back-projectors take
+                                    it in the backward pass's epilogue (separable sensitivity);
+                                    others, and MVD_FLAG_FORCE_2D runs, store each view's
+                                    back-projection and divide by a sensitivity plane computed
+                                    by the same pass (more workspace: mvd_workspace_bytes).
+                                    Supplementary Note 1 (the update assumes unit column
+                                    sums) */
 #define MVD_FLAG_TUNE 0x8u     /* choose launch shapes (row-segment length, views per launch,
                                   columns per thread, occupancy; for simultaneous two-view runs
                                   with rank-one PSFs of at most 31 taps also whether each
@@ -143,8 +146,9 @@ typedef struct {
                                  pixel's correction is tempered as ω·c + (1 − ω) with
                                  ω = view_weights[v] · ω_v(pixel) (the memory table's
                                  per-pixel, per-view weights, Supplementary Note 2; their
-                                 formula is not given).  Rank-one back-projectors only
-                                 (MVD_ERR_UNSUPPORTED with K×K passes).  Streamed and
+                                 formula is not given).  Back-projectors that are not rank
+                                 one, and MVD_FLAG_FORCE_2D runs, apply them in a pointwise
+                                 update after storing each view's back-projection.  Streamed and
                                  disk-to-disk runs read them in place, each plane batch
                                  its own planes: there they must be device memory
                                  (MVD_ERR_ARG otherwise).  Read only, kept alive until

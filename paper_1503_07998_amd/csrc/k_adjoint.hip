@@ -73,14 +73,15 @@ __device__ __forceinline__ void stv(float *p, size_t i, const float (&o)[VW]) {
     p[i] = o[0];
 }
 
-// The normalisation of element i's back-projection: s = nsz[z] · nsx[x]; q is
+// The normalisation of element i's back-projection: s = nsz[z] · nsx[x] (or
+// the sensitivity plane's s[z][x]); q is
 // divided by s where s > ε (the forward pass's reciprocal form), and `inv`
 // is 1/s there, 0 elsewhere.
 __device__ __forceinline__ float norm_of(const AdjPointArgs &a, int v, size_t i, float &inv) {
   const size_t row = i / (size_t)a.X;
   const int x = (int)(i - row * (size_t)a.X);
   const int z = (int)(row % (size_t)a.Z);
-  const float sv = a.nsz[v][z] * a.nsx[v][x];
+  const float sv = a.nsp[v] ? a.nsp[v][(size_t)z * a.X + x] : a.nsz[v][z] * a.nsx[v][x];
   inv = sv > kEps ? __builtin_amdgcn_rcpf(sv) : 0.f;
   return sv;
 }

@@ -1,4 +1,5 @@
-// Element-wise kernels: reslice / convert of the observations, ψ^0, fill, copy.
+// Element-wise kernels: reslice / convert of the observations, ψ^0, fill, copy,
+// the pointwise update from a stored back-projection, calibration kernels.
 #include <algorithm>
 
 #include "mvd_internal.hpp"
@@ -162,6 +163,25 @@ __global__ void __launch_bounds__(NT) probe_read_kernel(const float4 *__restrict
   if (__float_as_uint(s) == 0xffffffffu) dst[blockIdx.x] = s;
 }
 
+// ψ_out = ψ_in · (o q' + 1 − o): the update of one view from its stored
+// back-projection q (q' = q / s where s > ε with s the view's sensitivity
+// plane [Z][X], when given; o = w · ω(pixel) with a weight plane, else w).
+// The arithmetic of the separable backward pass's epilogue, element by element.
+__global__ void __launch_bounds__(NT) update_plane_kernel(const float *psi_in, float *psi_out,
+                                                           const float *__restrict__ q,
+                                                           const float *__restrict__ splane, size_t zx,
+                                                           const float *__restrict__ wpl, float w, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    float qq = q[i];
+    if (splane) {
+      const float sv = splane[i % zx];
+      qq = sv > kEps ? qq * __builtin_amdgcn_rcpf(sv) : qq;
+    }
+    const float o = wpl ? w * wpl[i] : w;
+    psi_out[i] = psi_in[i] * fmaf(o, qq, 1.f - o);
+  }
+}
+
 unsigned grid_for(size_t work) {
   size_t b = (work + NT - 1) / NT;
   if (b > 65536) b = 65536;   // grid-stride beyond this
@@ -220,6 +240,14 @@ hipError_t launch_fill(float *dst, size_t n, float value, hipStream_t s) {
 
 hipError_t launch_copy(const float *src, float *dst, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(NT), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_plane(const float *psi_in, float *psi_out, const float *q, const float *splane, size_t zx,
+                               const float *wpl, float w, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(update_plane_kernel, dim3(grid_for(n)), dim3(NT), 0, s, psi_in, psi_out, q, splane, zx, wpl, w,
+                     n);
   return hipGetLastError();
 }
 

@@ -415,6 +415,8 @@ struct Layout {
   size_t phi_off = 0, r_off = 0, acc_off = 0, total = 0;
   int n_ratio = 0;
   bool acc = false;     // a plane set for the partial sums of kernels run as sums of rank-one terms
+  size_t sens_off = 0;  // two [Z][X] planes for the sensitivity of the general update, or none
+  bool sens = false;
 };
 
 // Some pass of the run sums several rank-one terms (a PSF or back-projector
@@ -426,6 +428,19 @@ bool uses_low_rank(const mvd_ctx *c, const mvd_run *r) {
   return false;
 }
 
+// Weight planes or the normalised back-projection with a back-projector that
+// is not rank one (or with the K×K passes forced): the backward pass stores
+// each view's back-projection and updates ψ pointwise.
+bool uses_general_update(const mvd_ctx *c, const mvd_run *r) {
+  if (!c->derived || !(r->weight_planes || (r->flags & MVD_FLAG_NORMALIZE))) return false;
+  if (r->flags & MVD_FLAG_FORCE_2D) return true;
+  for (const ViewPsf &w : c->views)
+    if (!w.sep_x) return true;
+  return false;
+}
+
+size_t sens_plane_bytes(const mvd_ctx *c) { return align_up((size_t)c->Z * c->X * sizeof(float)); }
+
 Layout layout_of(const mvd_ctx *c, const mvd_run *r) {
   Layout L;
   L.plane_set = align_up((size_t)r->n_planes * c->Z * c->X * sizeof(float));
@@ -435,9 +450,13 @@ Layout layout_of(const mvd_ctx *c, const mvd_run *r) {
   off += (size_t)c->nv * L.plane_set;
   L.r_off = off;
   off += (size_t)L.n_ratio * L.plane_set;
-  L.acc = uses_low_rank(c, r);
+  const bool general = uses_general_update(c, r);
+  L.acc = uses_low_rank(c, r) || general;
   L.acc_off = off;
   if (L.acc) off += L.plane_set;
+  L.sens = general && (r->flags & MVD_FLAG_NORMALIZE);
+  L.sens_off = off;
+  if (L.sens) off += 2 * sens_plane_bytes(c);
   L.total = r->n_iters > 0 ? off : (size_t)c->nv * L.plane_set;
   return L;
 }
@@ -462,23 +481,9 @@ mvd_status check_run(mvd_ctx *c, const mvd_run *r) {
     return fail(c, MVD_ERR_ARG, "unknown obs_layout %d", r->obs_layout);
   if (r->flags & ~(MVD_FLAG_FORCE_2D | MVD_FLAG_TIMING | MVD_FLAG_GRAPH | MVD_FLAG_TUNE | MVD_FLAG_NORMALIZE))
     return fail(c, MVD_ERR_ARG, "unknown flags 0x%x", r->flags);
-  if (r->flags & MVD_FLAG_NORMALIZE) {
-    if (r->flags & MVD_FLAG_FORCE_2D)
-      return fail(c, MVD_ERR_UNSUPPORTED, "MVD_FLAG_NORMALIZE needs the rank-one passes");
-    if (c->derived)
-      for (int v = 0; v < c->nv; ++v)
-        if (!c->views[v].sep_x)
-          return fail(c, MVD_ERR_UNSUPPORTED, "MVD_FLAG_NORMALIZE: view %d's back-projector is not rank one", v);
-  }
-  if (r->weight_planes) {
+  if (r->weight_planes)
     for (int v = 0; v < c->nv; ++v)
       if (!r->weight_planes[v]) return fail(c, MVD_ERR_ARG, "weight_planes[%d] is NULL", v);
-    if (r->flags & MVD_FLAG_FORCE_2D) return fail(c, MVD_ERR_UNSUPPORTED, "weight planes need the rank-one passes");
-    if (c->derived)
-      for (int v = 0; v < c->nv; ++v)
-        if (!c->views[v].sep_x)
-          return fail(c, MVD_ERR_UNSUPPORTED, "weight planes: view %d's back-projector is not rank one", v);
-  }
   if (r->view_weights)
     for (int v = 0; v < c->nv; ++v) {
       const float w = r->view_weights[v];
@@ -707,6 +712,7 @@ struct RunState {
   const float *const *wpl = nullptr;   // per-pixel weight planes of the whole volume, or null
   size_t wpl_off = 0;                  // elements from their start to this launch's first plane
   float *acc = nullptr;                // partial sums of low-rank kernels' terms (a plane set), or null
+  float *sens = nullptr;               // two [Z][X] planes: ones, then a sensitivity 1 ⊛ X_v (general update)
 };
 
 hipEvent_t take_event(mvd_ctx *c) {
@@ -857,9 +863,17 @@ hipError_t forward_views(const RunState &st, const float *psi, const ObsRef &ob,
 }
 
 // Backward pass over views [v0, v0+n): psi_out = psi_in · Π (w q + 1 − w)
+hipError_t backward_general(const RunState &st, const float *const *r, const float *psi_in, float *psi_out,
+                            int v0, int n);
+
 hipError_t backward_views(const RunState &st, const float *const *r, const float *psi_in, float *psi_out,
                           int v0, int n) {
   mvd_ctx *c = st.c;
+  if (st.wpl || st.normalize) {   // weights per pixel or normalisation: rank-one passes, else the general update
+    bool general = st.force2d;
+    for (int v = v0; v < v0 + n; ++v) general = general || !c->views[v].sep_x;
+    if (general) return backward_general(st, r, psi_in, psi_out, v0, n);
+  }
   bool sep = !st.force2d;
   int kmax = 1;
   for (int v = v0; v < v0 + n; ++v) {
@@ -996,9 +1010,12 @@ struct BwdLayout {
   size_t wpart_off = 0, cpart_off = 0, acc_off = 0, total = 0;
   size_t tmp_off = 0;   // a plane set for convolutions finished pointwise (kernels not rank one), else none
   size_t sbar_off = 0, ones_off = 0;   // normalised runs: s̄ per view (or one), a plane set of ones
+  size_t sens_off = 0;   // normalised runs with a back-projector not rank one: two scratch [Z][X] planes,
+                         // then one sensitivity plane 1 ⊛ X_v per view
   int nsets = 0, nsub = 0;
   bool low_rank = false;   // some view's PSF or back-projector is not rank one
   bool normalize = false;
+  bool sens = false;
 };
 
 // accumulators: per view [psf kz·kx][back kz·kx], then V weights (doubles)
@@ -1036,6 +1053,10 @@ BwdLayout bwd_layout_of(const mvd_ctx *c, const mvd_run *r) {
   if (L.normalize) off += (size_t)L.nsets * L.plane_set;
   L.ones_off = off;
   if (L.normalize) off += L.plane_set;
+  L.sens = false;
+  for (const ViewPsf &w : c->views) L.sens = L.sens || (L.normalize && !w.sep_x);
+  L.sens_off = off;
+  if (L.sens) off += (size_t)(2 + V) * sens_plane_bytes(c);
   size_t lags = 0;   // padded lags of a partial, either form
   for (auto &w : c->views)
     for (const Kernel *d : {&w.psf, &w.back})
@@ -1237,7 +1258,7 @@ size_t plane_elems(const RunState &st) { return (size_t)st.g.Y * st.g.Z * st.g.X
 
 // out = in ⊛ k on the K×K passes, the convolution itself stored (tap set
 // `which` of view v: 0 P_v, 1 X_v, 2 P_v^*, 3 X_v^*).
-hipError_t twod_store(const RunState &st, const float *in, int v, int which, float *out) {
+hipError_t twod_store(const RunState &st, const float *in, int v, int which, float *out, int kind = 3) {
   TwoDPassArgs a{};
   a.g = st.g;
   a.boundary = st.boundary;
@@ -1249,7 +1270,52 @@ hipError_t twod_store(const RunState &st, const float *in, int v, int which, flo
   a.out[0] = out;
   a.taps[0] = dtaps(st.c, v, which);
   a.mfma = st.tn->valu2d ? 0 : 1;
-  return timed(st, 3, [&] { return launch_2d_forward(a, st.s); });
+  return timed(st, kind, [&] { return launch_2d_forward(a, st.s); });
+}
+
+// q = in ⊛ X_v stored: the rank-one pass, a sum of terms, or the K×K pass
+// (forced K×K runs take the K×K pass for every view).
+hipError_t back_store(const RunState &st, int v, const float *in, float *out, int kind) {
+  const ViewPsf &w = st.c->views[v];
+  if (!st.force2d && w.sep_x)
+    return single_pass(st, kEpStore, in, w.xz, w.xx, out, nullptr, nullptr, nullptr, nullptr, 1.f, kind);
+  if (!st.force2d && !w.lxz.empty()) return terms_sum(st, w.lxz, w.lxx, in, out, false, kind);
+  return twod_store(st, in, v, 1, out, kind);
+}
+
+// s_v = 1 ⊛ X_v over one plane into out [Z][X] (the same pass as the data's,
+// so the same boundary); `ones` is a [Z][X] scratch plane filled here.
+hipError_t sens_plane(const RunState &st, int v, float *ones, float *out) {
+  RunState one = st;
+  one.g.Y = 1;
+  hipError_t e = launch_fill(ones, (size_t)st.g.Z * st.g.X, 1.f, st.s);
+  if (e == hipSuccess) e = back_store(one, v, ones, out, 2);
+  return e;
+}
+
+// The backward pass over views [v0, v0+n) view by view: q_v stored (st.acc),
+// then ψ_out = ψ_in · (o q'_v + 1 − o) pointwise (ψ · c_0 · c_1 …), with
+// q'_v = q_v / s_v under the normalised form (s_v from sens_plane) and
+// o = w_v · ω_v(pixel) with weight planes.
+hipError_t backward_general(const RunState &st, const float *const *r, const float *psi_in, float *psi_out,
+                            int v0, int n) {
+  if (!st.acc || (st.normalize && !st.sens)) return hipErrorInvalidValue;
+  const size_t zx = (size_t)st.g.Z * st.g.X;
+  float *ones = st.sens, *sp = st.sens ? st.sens + sens_plane_bytes(st.c) / sizeof(float) : nullptr;
+  const float *in = psi_in;
+  for (int v = v0; v < v0 + n; ++v) {
+    hipError_t e = back_store(st, v, r[v], st.acc, 1);
+    if (e == hipSuccess && st.normalize) e = sens_plane(st, v, ones, sp);
+    const float *wp = st.wpl ? st.wpl[v] + st.wpl_off : nullptr;
+    if (e == hipSuccess)
+      e = timed(st, 1, [&] {
+        return launch_update_plane(in, psi_out, st.acc, st.normalize ? sp : nullptr, zx, wp, weight_of(st, v),
+                                   plane_elems(st), st.s);
+      });
+    if (e != hipSuccess) return e;
+    in = psi_out;
+  }
+  return hipSuccess;
 }
 
 // b = ψ ⊛ P_v with r = φ / b (guarded), then q = r ⊛ X_v.  Kernels of low
@@ -1424,6 +1490,7 @@ hipError_t enqueue_run(mvd_ctx *c, const void *const *obs, float *est, const mvd
   rs.normalize = (r->flags & MVD_FLAG_NORMALIZE) != 0;
   rs.wpl = r->weight_planes;
   if (L.acc) rs.acc = reinterpret_cast<float *>(ws + L.acc_off);
+  if (L.sens) rs.sens = reinterpret_cast<float *>(ws + L.sens_off);
   // the separable forward passes read the observations as given; only the
   // general K×K passes need them staged as float32 planes
   const bool need_staged = run_needs_2d(rs);
@@ -3023,14 +3090,29 @@ mvd_status mvd_backward_grads(mvd_ctx *c, const void *const *obs, const float *g
   if (e == hipSuccess) e = launch_copy(grad_est, plane(L.g_off, 0), n, s);
   for (int v = 0; v < V && e == hipSuccess && grad_wpl; ++v) e = launch_fill(grad_wpl[v], n, 0.f, s);
   if (e == hipSuccess && L.normalize) e = launch_fill(plane(L.ones_off, 0), n, 1.f, s);
+  // sensitivity planes 1 ⊛ X_v of back-projectors that are not rank one (the
+  // others have separable factors); the first two planes are the sequential
+  // sub-states' scratch
+  auto sens_of = [&](int v) {
+    return reinterpret_cast<float *>(ws + L.sens_off + (size_t)(2 + v) * sens_plane_bytes(c));
+  };
+  if (L.sens) {
+    rs.sens = reinterpret_cast<float *>(ws + L.sens_off);
+    for (int v = 0; v < V && e == hipSuccess; ++v)
+      if (!c->views[v].sep_x) e = sens_plane(rs, v, rs.sens, sens_of(v));
+  }
   // the normalisation's factors as the pointwise kernels read them
   auto set_norm = [&](AdjPointArgs &pa, int slot, int v) {
     pa.nrm = L.normalize ? 1 : 0;
     pa.Z = c->Z;
     pa.X = c->X;
     if (!L.normalize) return;
-    pa.nsz[slot] = norm_factors(c, v, r->boundary);
-    pa.nsx[slot] = pa.nsz[slot] + norm_zlen(c);
+    if (c->views[v].sep_x) {
+      pa.nsz[slot] = norm_factors(c, v, r->boundary);
+      pa.nsx[slot] = pa.nsz[slot] + norm_zlen(c);
+    } else {
+      pa.nsp[slot] = sens_of(v);
+    }
     pa.sbar[slot] = plane(L.sbar_off, L.nsets > 1 ? v : 0);
   };
   const int T = r->n_iters;

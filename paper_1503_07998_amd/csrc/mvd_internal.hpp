@@ -191,6 +191,7 @@ struct AdjPointArgs {
   int Z, X;
   const float *nsz[kMaxViews];
   const float *nsx[kMaxViews];
+  const float *nsp[kMaxViews];   // a sensitivity plane [Z][X] instead of the factors (back-projectors not rank one)
   float *sbar[kMaxViews];
 };
 
@@ -252,6 +253,10 @@ hipError_t launch_init_mean(const float *const *phis, int nv, size_t n, float *d
                             hipStream_t s);
 hipError_t launch_fill(float *dst, size_t n, float value, hipStream_t s);
 hipError_t launch_copy(const float *src, float *dst, size_t n, hipStream_t s);
+// ψ_out = ψ_in · (o q' + 1 − o) over n elements: q' = q / splane[i mod zx] where
+// that exceeds ε (splane null: q), o = w · wpl[i] (wpl null: w).
+hipError_t launch_update_plane(const float *psi_in, float *psi_out, const float *q, const float *splane, size_t zx,
+                               const float *wpl, float w, size_t n, hipStream_t s);
 // Calibration kernels: kind 0 copies `bytes` from src to dst, kind 1 reads
 // them (dst: kProbeBlocks floats, written only for non-finite sums).  bytes is
 // a multiple of 16, both pointers 16-byte aligned.

@@ -207,14 +207,18 @@ def test_run_validation_before_device():
             assert call(r) == N.MVD_ERR_ARG, field
         r = api.make_run(4, 2, init="const", init_const=0.0)
         assert call(r) == N.MVD_ERR_ARG
-        # the EM normalisation runs on the rank-one passes only
+        # the EM normalisation and per-pixel weights with the K×K passes forced:
+        # the general update (stored back-projections), valid so far
         r = api.make_run(4, 2, normalize=True, force_2d=True)
-        assert call(r) == N.MVD_ERR_UNSUPPORTED
-        # per-pixel weights: every view's plane, rank-one passes only
+        assert call(r) == N.MVD_ERR_WORKSPACE
+        plain = api.mvd_workspace_bytes(ctx, api.make_run(4, 2, force_2d=True))
+        general = api.mvd_workspace_bytes(ctx, r)
+        assert general >= plain + 4 * 8 * 8 * 4               # + a plane set for q, two sensitivity planes
+        # per-pixel weights: every view's plane
         r = api.make_run(4, 2, weight_planes=[64, 0])
         assert call(r) == N.MVD_ERR_ARG
         r = api.make_run(4, 2, weight_planes=[64, 128], force_2d=True)
-        assert call(r) == N.MVD_ERR_UNSUPPORTED
+        assert call(r) == N.MVD_ERR_WORKSPACE
         r = api.make_run(4, 2, weight_planes=[64, 128])
         assert call(r) == N.MVD_ERR_WORKSPACE
         r = api.make_run(4, 2, normalize=True)

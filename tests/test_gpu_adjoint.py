@@ -295,12 +295,14 @@ def test_backward_kxk_psfs_match_oracle(case):
 
 
 NORM_CASES = [
-    # (Y, Z, X, [(kz, kx, rank)], T, update, boundary, weights, weight planes); the
-    # normalised form needs rank-one back-projectors, hence rank-one PSFs here
+    # (Y, Z, X, [(kz, kx, rank: 1 separable, 0 full, r low)], T, update, boundary, weights, weight planes)
     (2, 30, 44, [(9, 7, 1), (7, 11, 1)], 3, "simultaneous", "zero", [0.9, 0.8], False),
     (2, 26, 37, [(11, 11, 1), (5, 9, 1), (7, 7, 1)], 2, "sequential", "zero", None, False),
     (2, 24, 48, [(9, 13, 1), (7, 7, 1)], 2, "simultaneous", "periodic", None, False),
     (1, 40, 64, [(31, 31, 1), (21, 21, 1)], 2, "sequential", "zero", [1.0, 0.7], True),
+    # back-projectors that are not rank one (the general update and sensitivity planes)
+    (2, 28, 40, [(9, 9, 3), (7, 7, 0)], 2, "simultaneous", "zero", [0.9, 0.8], False),
+    (2, 25, 36, [(9, 9, 0), (7, 9, 2)], 2, "sequential", "zero", None, True),
 ]
 
 
@@ -314,7 +316,8 @@ def test_backward_normalised_matches_oracle(case):
     _say(f"backward normalised Y={Y} Z={Z} X={X} k={shapes} T={T} {update} {boundary} w={weights} "
          f"planes={with_planes}")
     rng = np.random.default_rng(Y * 13 + Z * 7 + X)
-    psfs = [random_psf(rng, kz, kx, separable=True).astype(np.float32) for kz, kx, _ in shapes]
+    psfs = [(random_psf(rng, kz, kx, separable=(r == 1)) if r <= 1 else _low_rank_psf(rng, kz, kx, r))
+            .astype(np.float32) for kz, kx, r in shapes]
     stacks = [rng.uniform(20.0, 300.0, (Z, Y, X)).astype(np.float32) for _ in shapes]
     gout = rng.standard_normal((Y, Z, X))
     planes = [rng.uniform(0.2, 1.0, (Y, Z, X)).astype(np.float32) for _ in shapes] if with_planes else None
