@@ -457,3 +457,35 @@ def test_autograd_backward_uses_its_own_forward_sigma():
     close(s1.grad.numpy(), ref_gs, "dL/dsigma (first forward)")
     close(w1.grad.numpy(), ref_gw, "dL/dw (first forward)")
     prob.dec.close()
+
+
+@pytest.mark.parametrize("update", ["simultaneous", "sequential"])
+def test_autograd_taps_weight_planes_normalised(update):
+    """torch autograd through the library with PSF taps given directly (one
+    low-rank and one full-rank kernel), per-pixel weight planes and the
+    EM-normalised back-projection: ∂L/∂taps (= ∂L/∂P + flip(∂L/∂X)), ∂L/∂w and
+    ∂L/∂ω against the oracle's adjoint."""
+    from paper_1503_07998_amd.autograd import PlanewiseRL, mv_deconvolve_taps
+
+    torch = _torch()
+    _say(f"autograd: taps, weight planes, normalised, {update}")
+    rng = np.random.default_rng(29)
+    Y, Z, X, k, T = 2, 30, 38, 9, 2
+    psfs = [_low_rank_psf(rng, k, k, 2), random_psf(rng, k, k).astype(np.float32)]
+    stacks = [rng.uniform(20.0, 300.0, (Z, Y, X)).astype(np.float32) for _ in range(2)]
+    om = np.stack([rng.uniform(0.2, 1.0, (Y, Z, X)) for _ in range(2)]).astype(np.float32)
+    ws = [0.9, 0.7]
+    gout = rng.standard_normal((Y, Z, X))
+    prob = PlanewiseRL([torch.from_numpy(s).to("cuda:0") for s in stacks], k, T, update=update, normalize=True)
+    taps = torch.tensor(np.stack(psfs), dtype=torch.float64, requires_grad=True)
+    w = torch.tensor(ws, dtype=torch.float64, requires_grad=True)
+    planes = torch.from_numpy(om).to("cuda:0").requires_grad_(True)
+    psi = mv_deconvolve_taps(taps, w, prob, planes)
+    (psi.double() * torch.from_numpy(gout).to("cuda:0")).sum().backward()
+    eff = [np.float64(ws[v]) * om[v].astype(np.float64) for v in range(2)]
+    ref = oracle_adjoint(stacks, psfs, T, gout, update, "zero", eff, normalize=True)
+    for v in range(2):
+        close(taps.grad[v].numpy(), ref["grad_psf"][v] + oracle.flip(ref["grad_back"][v]), f"dL/dtaps[{v}]")
+        close(planes.grad[v].cpu().numpy(), ref["grad_weights"][v] * ws[v], f"dL/domega[{v}]")
+    close(w.grad.numpy(), [float(np.sum(ref["grad_weights"][v] * om[v])) for v in range(2)], "dL/dw")
+    prob.dec.close()
