@@ -335,3 +335,60 @@ def test_persistent_give_up_is_reported():
     np.testing.assert_array_equal(st["est"].cpu().numpy(), ref)
     b.close()
     st["dec"].close()
+
+
+def test_batch_of_composed_variants_equals_plain():
+    """Items that combine the variants (normalised back-projection, per-pixel
+    weight planes, a low-rank and a full-rank PSF, forced K×K passes) take the
+    graph form and equal their plain runs bitwise."""
+    from paper_1503_07998_amd import api
+    from synthetic import random_psf
+
+    torch = _torch()
+    _say("batch of composed variants")
+    rng = np.random.default_rng(61)
+
+    def low_rank(k, r):
+        p = sum(np.outer(rng.uniform(0.05, 1.0, k), rng.uniform(0.05, 1.0, k)) for _ in range(r))
+        return (p / p.sum()).astype(np.float32)
+
+    specs = [
+        # (nz, ny, nx, psfs, update, kwargs)
+        (30, 3, 40, [low_rank(9, 3), random_psf(rng, 7, 7).astype(np.float32)], "simultaneous",
+         dict(normalize=True)),
+        (26, 2, 48, [random_psf(rng, 9, 9, separable=True).astype(np.float32), low_rank(7, 2)], "sequential",
+         dict(normalize=True, planes=True)),
+        (22, 2, 36, [random_psf(rng, 5, 7, separable=True).astype(np.float32)] * 2, "sequential",
+         dict(planes=True, force_2d=True)),
+    ]
+    setups = []
+    for nz, ny, nx, psfs, update, kw in specs:
+        d = api.Deconvolver(len(psfs), nz, nx, 0)
+        for v, p in enumerate(psfs):
+            d.set_psf(v, p)
+        obs = [torch.from_numpy(rng.uniform(20.0, 400.0, (nz, ny, nx)).astype(np.float32)).to("cuda:0")
+               for _ in psfs]
+        planes = ([torch.from_numpy(rng.uniform(0.2, 1.0, (ny, nz, nx)).astype(np.float32)).to("cuda:0")
+                   for _ in psfs] if kw.get("planes") else None)
+        est = torch.empty((ny, nz, nx), dtype=torch.float32, device="cuda:0")
+        run = api.make_run(ny, 3, update=update, weights=[0.9] * len(psfs), normalize=kw.get("normalize", False),
+                           force_2d=kw.get("force_2d", False), weight_planes=planes)
+        nb = api.mvd_workspace_bytes(d.ctx, run)
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda:0")
+        run.workspace = (ws.data_ptr() + 255) // 256 * 256
+        run.workspace_bytes = nb
+        setups.append(dict(dec=d, obs=obs, est=est, run=run, ws=ws, planes=planes, init="mean"))
+    plain = [_plain(st) for st in setups]
+    b = api.Batch([(st["dec"].ctx, st["obs"], st["est"], st["run"]) for st in setups])
+    assert not b.info()["persistent"]
+    for st in setups:
+        _reset(st)
+    b.launch()
+    b.wait()
+    for st, ref in zip(setups, plain):
+        got = st["est"].cpu().numpy()
+        assert np.all(np.isfinite(got))
+        np.testing.assert_array_equal(got, ref)
+    b.close()
+    for st in setups:
+        st["dec"].close()

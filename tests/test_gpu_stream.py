@@ -240,3 +240,42 @@ def test_streamed_full_size_sampled_planes():
     for i, y in enumerate(sample):
         err = np.abs(est[y] - ref[i]).max() / np.abs(ref[i]).max()
         assert err <= TOL, f"plane {y}: max|d|/max = {err:.3e}"
+
+
+def test_streamed_general_update_equals_plain():
+    """A normalised run with a low-rank and a full-rank PSF and weight planes
+    (the general update: sensitivity planes per batch), streamed in batches
+    of 4 of 13 planes: bitwise the device-resident run."""
+    from paper_1503_07998_amd import api
+    from synthetic import random_psf
+
+    torch = _torch()
+    _say("streamed general update, 13 planes, batch 4")
+    rng = np.random.default_rng(71)
+    Z, Y, X = 28, 13, 36
+    p0 = sum(np.outer(rng.uniform(0.05, 1.0, 9), rng.uniform(0.05, 1.0, 9)) for _ in range(2))
+    psfs = [(p0 / p0.sum()).astype(np.float32), random_psf(rng, 7, 7).astype(np.float32)]
+    d = api.Deconvolver(2, Z, X, 0)
+    for v, p in enumerate(psfs):
+        d.set_psf(v, p)
+    stacks = [rng.uniform(20.0, 400.0, (Z, Y, X)).astype(np.float32) for _ in range(2)]
+    planes = [torch.from_numpy(rng.uniform(0.2, 1.0, (Y, Z, X)).astype(np.float32)).to("cuda:0") for _ in range(2)]
+    obs = [torch.from_numpy(s).to("cuda:0") for s in stacks]
+    est = torch.empty((Y, Z, X), dtype=torch.float32, device="cuda:0")
+    run = api.make_run(Y, 3, update="simultaneous", normalize=True, weight_planes=planes)
+    nb = api.mvd_workspace_bytes(d.ctx, run)
+    ws, run.workspace = _workspace(nb)
+    run.workspace_bytes = nb
+    api.mvd_deconvolve_planes(d.ctx, obs, est, run)
+    torch.cuda.synchronize()
+    ref = est.cpu().numpy()
+    host = [_pinned(s) for s in stacks]
+    est_h = torch.empty((Y, Z, X), dtype=torch.float32, pin_memory=True)
+    run = api.make_run(Y, 3, update="simultaneous", normalize=True, weight_planes=planes)
+    nb = api.mvd_stream_workspace_bytes(d.ctx, run, 4, True)
+    ws2, run.workspace = _workspace(nb)
+    run.workspace_bytes = nb
+    api.mvd_deconvolve_stream(d.ctx, host, est_h, run, 4)
+    torch.cuda.current_stream().synchronize()
+    np.testing.assert_array_equal(est_h.numpy(), ref)
+    d.close()
