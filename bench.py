@@ -370,6 +370,11 @@ def mix_record(args, cpu=True):
     bg.close()
     log("mix: persistent form")
     b = api.Batch(entries)
+    pq_info = b.info()
+    pq_ms, pq_diff = time_batch(b)
+    b.close()
+    log("mix: tuned batch (both forms timed, the faster kept)")
+    b = api.Batch(entries, tune=True)
     info = b.info()
     batch_ms, diff = time_batch(b)
     b.close()
@@ -382,6 +387,8 @@ def mix_record(args, cpu=True):
         "plain_value": vox_it / (plain_ms / 1e3), "plain_ms_per_step": plain_ms,
         "batched_over_plain": plain_ms / batch_ms, "max_rel_diff_batched_vs_plain": diff,
         "batch_form": info,
+        "persistent_form_value": vox_it / (pq_ms / 1e3), "persistent_form_ms_per_step": pq_ms,
+        "persistent_form_max_rel_diff": pq_diff, "persistent_form": pq_info,
         "graph_form_value": vox_it / (graph_ms / 1e3), "graph_form_ms_per_step": graph_ms,
         "graph_form_max_rel_diff": graph_diff,
         "workload": "batched mix: 200 planes 256x384 (2 views, 21x21), 300 planes 512x768 (3 views, 31x31), "

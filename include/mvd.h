@@ -449,7 +449,11 @@ typedef struct mvd_batch mvd_batch;
 #define MVD_BATCH_TUNE 0x1u /* graph form: time launch-shape candidates per item before capture
                                (runs one iteration of each item on `stream`, synchronously;
                                items with MVD_INIT_GIVEN keep the default shapes).  The choice is
-                               cached per workload shape for the process. */
+                               cached per workload shape for the process.  Where the persistent
+                               form applies too, both forms are built and timed (three whole
+                               launches each on `stream`, overwriting the items' estimates) and
+                               the faster is kept; not when an item's ψ^0 is given
+                               (MVD_INIT_GIVEN), which keeps the persistent form. */
 #define MVD_BATCH_GRAPH 0x2u /* use the graph form even where the persistent form applies */
 
 /* Validate every item, optionally autotune, and capture the batch graph.

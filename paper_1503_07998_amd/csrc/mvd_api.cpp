@@ -2403,6 +2403,7 @@ struct mvd_batch {
   bool persistent = false;   // one persistent queue launch instead of the graph
   PqState pq;
   std::string why_graph;      // why the graph form was taken
+  double form_ms[2] = {0.0, 0.0};   // tuned batches: persistent and graph form, ms per launch (0: not timed)
 };
 
 namespace {
@@ -2464,6 +2465,27 @@ hipError_t pq_setup(mvd_batch *b, int window) {
 }
 
 }  // namespace
+
+// One warm-up launch and two timed launches of a batch in its current form on
+// `s`: the mean duration (HIP events) in *ms.
+static mvd_status batch_time_launches(mvd_batch *b, hipStream_t s, double *ms) {
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  mvd_status st = e == hipSuccess ? MVD_OK : MVD_ERR_LAUNCH;
+  if (st == MVD_OK) st = mvd_batch_launch(b, s);
+  if (st == MVD_OK) st = mvd_batch_wait(b, s);
+  if (st == MVD_OK && hipEventRecord(t0, s) != hipSuccess) st = MVD_ERR_LAUNCH;
+  for (int k = 0; k < 2 && st == MVD_OK; ++k) st = mvd_batch_launch(b, s);
+  if (st == MVD_OK && hipEventRecord(t1, s) != hipSuccess) st = MVD_ERR_LAUNCH;
+  if (st == MVD_OK) st = mvd_batch_wait(b, s);
+  float f = 0.f;
+  if (st == MVD_OK && hipEventElapsedTime(&f, t0, t1) != hipSuccess) st = MVD_ERR_LAUNCH;
+  *ms = f / 2.0;
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  return st;
+}
 
 // ===========================================================================
 extern "C" {
@@ -3248,19 +3270,26 @@ mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items,
       b->why_graph = "item " + std::to_string(i) + ": " + why;
     }
   }
+  // with MVD_BATCH_TUNE both forms are built and timed (unless an item's given
+  // ψ^0 would be overwritten by the timing launches)
+  bool both = (flags & MVD_BATCH_TUNE) != 0;
+  for (const auto &it : b->items) both = both && it.run.init != MVD_INIT_GIVEN;
   if (pq) {
     e = pq_setup(b, tune().pq_window);
     if (e == hipSuccess) {
       b->persistent = true;
-      *out = b;
-      return MVD_OK;
+      if (!both) {
+        *out = b;
+        return MVD_OK;
+      }
+    } else {
+      // a batch the persistent form cannot take runs as a graph
+      b->why_graph = std::string("persistent setup: ") + hipGetErrorString(e);
+      if (b->pq.dmem) (void)hipFree(b->pq.dmem);
+      b->pq = PqState{};
+      (void)hipGetLastError();
+      e = hipSuccess;
     }
-    // a batch the persistent form cannot take runs as a graph
-    b->why_graph = std::string("persistent setup: ") + hipGetErrorString(e);
-    if (b->pq.dmem) (void)hipFree(b->pq.dmem);
-    b->pq = PqState{};
-    (void)hipGetLastError();
-    e = hipSuccess;
   }
   if (flags & MVD_BATCH_TUNE) {
     for (auto &it : b->items) {
@@ -3301,6 +3330,33 @@ mvd_status mvd_batch_create(mvd_batch **out, const mvd_item *items, int n_items,
   if (e != hipSuccess) {
     mvd_batch_destroy(b);
     return fail(nullptr, MVD_ERR_LAUNCH, "batch setup failed: %s", hipGetErrorString(e));
+  }
+  if (b->persistent) {
+    // both forms exist: time each (one warm-up and two timed launches) and keep the faster
+    double ms[2] = {0.0, 0.0};
+    mvd_status st = MVD_OK;
+    for (int form = 0; form < 2 && st == MVD_OK; ++form) {
+      b->persistent = form == 0;
+      st = batch_time_launches(b, s, &ms[form]);
+    }
+    if (st != MVD_OK) {
+      const std::string msg = mvd_last_error(nullptr);
+      mvd_batch_destroy(b);
+      return fail(nullptr, st, "batch form timing failed: %s", msg.c_str());
+    }
+    b->form_ms[0] = ms[0];
+    b->form_ms[1] = ms[1];
+    b->persistent = ms[0] <= ms[1];
+    if (b->persistent) {
+      (void)hipGraphExecDestroy(b->exec);
+      (void)hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+    } else {
+      (void)hipFree(b->pq.dmem);
+      b->pq = PqState{};
+      b->why_graph = "tuned: the graph form was faster";
+    }
   }
   *out = b;
   return MVD_OK;

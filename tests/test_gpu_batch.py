@@ -392,3 +392,42 @@ def test_batch_of_composed_variants_equals_plain():
     b.close()
     for st in setups:
         st["dec"].close()
+
+
+def test_tuned_batch_keeps_one_form_and_matches_plain():
+    """MVD_BATCH_TUNE on items the persistent form takes: both forms are built
+    and timed and one is kept; its launches agree with the plain runs (tuned
+    launch shapes change summation orders only) and repeat bitwise; a given
+    ψ^0 keeps the persistent form without timing."""
+    from paper_1503_07998_amd import api
+
+    _say("tuned batch: form choice")
+    cases = _persistent_cases()[:2]
+    setups = [_planes_case(**c) for c in cases]
+    plain = [_plain(st) for st in setups]
+    b = api.Batch([(st["dec"].ctx, st["obs"], st["est"], st["run"]) for st in setups], tune=True)
+    form = b.info()["persistent"]
+    outs = []
+    for _ in range(2):
+        for st in setups:
+            _reset(st)
+        b.launch()
+        b.wait()
+        outs.append([st["est"].cpu().numpy() for st in setups])
+    b.close()
+    for got, ref in zip(outs[0], plain):
+        assert np.abs(got - ref).max() / np.abs(ref).max() <= 1e-5
+    for a, c in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, c)
+    _say(f"tuned batch kept the {'persistent' if form else 'graph'} form")
+    given = _planes_case(**_persistent_cases()[6])
+    ref = _plain(given)
+    b = api.Batch([(given["dec"].ctx, given["obs"], given["est"], given["run"])], tune=True)
+    assert b.info()["persistent"]
+    _reset(given)
+    b.launch()
+    b.wait()
+    np.testing.assert_array_equal(given["est"].cpu().numpy(), ref)
+    b.close()
+    for st in setups + [given]:
+        st["dec"].close()
