@@ -11,6 +11,7 @@ import concurrent.futures as cf
 import os
 import shutil
 import subprocess
+import time
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,23 +32,33 @@ def _hipcc() -> str:
     return exe
 
 
+# units that take longest to compile start first (the build is as long as its
+# slowest unit plus whatever waited for a free worker)
+_FIRST = ("k_sep_41", "k_sep_31", "k_sep_63", "k_pq", "k_sep_21", "k_sep_15", "k_fused", "k_adjoint")
+
+
 def sources():
-    out = []
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".cpp")):
-            out.append(os.path.join(CSRC, name))
-    return out
+    names = [n for n in os.listdir(CSRC) if n.endswith((".hip", ".cpp"))]
+
+    def rank(name):
+        for i, p in enumerate(_FIRST):
+            if name.startswith(p):
+                return (i, name)
+        return (len(_FIRST), name)
+
+    return [os.path.join(CSRC, n) for n in sorted(names, key=rank)]
 
 
-def _compile(src: str) -> str:
+def _compile(src: str) -> tuple[str, float]:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [_hipcc(), *COMMON, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [_hipcc(), *COMMON, "-x", "hip", "-c", src, "-o", obj]
+    t0 = time.perf_counter()
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {os.path.basename(src)}:\n{res.stderr[-6000:]}")
-    return obj
+    return obj, time.perf_counter() - t0
 
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
@@ -56,7 +67,11 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        done = list(ex.map(_compile, srcs))
+    objs = [o for o, _ in done]
+    if verbose:
+        slow = sorted(zip(srcs, (t for _, t in done)), key=lambda st: -st[1])[:6]
+        print("slowest: " + ", ".join(f"{os.path.basename(n)} {t:.0f} s" for n, t in slow), flush=True)
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)

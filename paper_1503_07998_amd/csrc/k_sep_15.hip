@@ -1,4 +1,6 @@
-// Separable pass kernels for kernel sizes up to 15 (one bucket per file).
+// Separable forward pass kernels for kernel sizes up to 15 (the bucket's
+// backward and single-input passes: k_sep_15_bwd.hip, k_sep_15_single.hip).
 #include "k_sep_impl.hpp"
+#include "k_sep_units.hpp"
 
-MVD_SEP_INSTANTIATE(15)
+MVD_SEP_INSTANTIATE_FWD(15)

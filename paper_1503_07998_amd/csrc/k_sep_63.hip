@@ -1,4 +1,6 @@
-// Separable pass kernels for kernel sizes up to 63 (one bucket per file).
+// Separable forward pass kernels for kernel sizes up to 63 (the bucket's
+// backward and single-input passes: k_sep_63_bwd.hip, k_sep_63_single.hip).
 #include "k_sep_impl.hpp"
+#include "k_sep_units.hpp"
 
-MVD_SEP_INSTANTIATE(63)
+MVD_SEP_INSTANTIATE_FWD(63)
