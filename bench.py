@@ -908,8 +908,8 @@ def main():
     WEIGHT_PLANES = args.pixel_weights
     PSF_TERMS = 2 if args.psf == "lowrank" else 1
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}), flush=True)
+        print(json.dumps({"error": "the benchmark measures one GPU (no multi-GPU path is built); "
+                                   "--gpus must be 1", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
     if args.config == "mix":
