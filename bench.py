@@ -278,10 +278,12 @@ def cpu_baseline(spec, vol, iters, normalize=False):
 
 def mix_record(args, cpu=True):
     """Three uneven volumes: plain per-volume calls vs one batched launch (the
-    persistent work-queue kernel; the graph form is timed beside it).
+    tuned batch, which times the persistent work-queue form and the graph form
+    and keeps the faster; both forms are also timed on their own).
     Returns a dict: batched and plain rates, their ratio, the largest relative
-    difference between the two estimates, the roofline of the mix's dominant
-    kernel (from HIP-event timings of the plain calls) and the CPU baseline."""
+    difference between the two estimates, both forms' rates, the roofline of
+    the mix's dominant kernel (from HIP-event timings of the plain calls) and
+    the CPU baseline."""
     import numpy as np
 
     from synthetic import CONFIGS, make_volume
