@@ -378,6 +378,7 @@ def mix_record(args, cpu=True):
     log("mix: tuned batch (both forms timed, the faster kept)")
     b = api.Batch(entries, tune=True)
     info = b.info()
+    form_times = b.form_times()
     batch_ms, diff = time_batch(b)
     b.close()
     # the dominant kernel of the mix: the (volume, pass) with the largest total launch time
@@ -388,7 +389,7 @@ def mix_record(args, cpu=True):
         "value": vox_it / (batch_ms / 1e3), "unit": "voxel-iterations/s", "ms_per_step": batch_ms,
         "plain_value": vox_it / (plain_ms / 1e3), "plain_ms_per_step": plain_ms,
         "batched_over_plain": plain_ms / batch_ms, "max_rel_diff_batched_vs_plain": diff,
-        "batch_form": info,
+        "batch_form": info, "batch_form_timed_ms": {"persistent": form_times[0], "graph": form_times[1]},
         "persistent_form_value": vox_it / (pq_ms / 1e3), "persistent_form_ms_per_step": pq_ms,
         "persistent_form_max_rel_diff": pq_diff, "persistent_form": pq_info,
         "graph_form_value": vox_it / (graph_ms / 1e3), "graph_form_ms_per_step": graph_ms,

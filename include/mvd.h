@@ -479,6 +479,12 @@ mvd_status mvd_batch_wait(mvd_batch *b, void *stream);
  * work-groups of the persistent launch, its LDS bytes per work-group. */
 mvd_status mvd_batch_info(const mvd_batch *b, int *out);
 
+/* Launch durations (ms, HIP events, mean of two launches) that a batch made
+ * with MVD_BATCH_TUNE measured for its two forms when it chose between them:
+ * out[0] persistent, out[1] graph; both 0 where no choice was timed.
+ * Errors: MVD_ERR_ARG. */
+mvd_status mvd_batch_form_times(const mvd_batch *b, double *out);
+
 /* Launch shapes chosen for item `item`: out[5] = forward occupancy, forward
  * views per launch, backward inputs per launch, segment scale, columns per
  * thread (0 = default in every field). */

@@ -139,6 +139,7 @@ SIGNATURES = {
     "mvd_batch_launch": (c_int, [c_void_p, c_void_p]),
     "mvd_batch_wait": (c_int, [c_void_p, c_void_p]),
     "mvd_batch_info": (c_int, [c_void_p, POINTER(c_int)]),
+    "mvd_batch_form_times": (c_int, [c_void_p, POINTER(ctypes.c_double)]),
     "mvd_batch_tuning": (c_int, [c_void_p, c_int, POINTER(c_int)]),
     "mvd_batch_destroy": (None, [c_void_p]),
     "mvd_batch_run": (c_int, [POINTER(MvdItem), c_int, c_void_p]),

@@ -20,7 +20,7 @@ __all__ = [
     "mvd_backward_workspace_bytes", "mvd_backward", "mvd_backward_grads", "mvd_batch_create", "mvd_batch_launch",
     "mvd_batch_tuning", "mvd_batch_destroy", "mvd_batch_run", "Batch",
     "mvd_stream_workspace_bytes", "mvd_deconvolve_stream", "mvd_deconvolve_planes_static",
-    "mvd_batch_wait", "mvd_batch_info",
+    "mvd_batch_wait", "mvd_batch_info", "mvd_batch_form_times",
 ]
 
 
@@ -297,6 +297,13 @@ def mvd_batch_info(b):
     return dict(persistent=bool(out[0]), items=out[1], work_groups=out[2], lds_bytes=out[3])
 
 
+def mvd_batch_form_times(b):
+    """(persistent ms, graph ms) measured by a tuned batch choosing its form, or (0, 0)."""
+    out = (ctypes.c_double * 2)()
+    N.check(N.lib().mvd_batch_form_times(b, out))
+    return float(out[0]), float(out[1])
+
+
 def mvd_batch_tuning(b, item: int):
     out = (c_int * 5)()
     N.check(N.lib().mvd_batch_tuning(b, int(item), out))
@@ -331,6 +338,9 @@ class Batch:
 
     def tuning(self, item):
         return mvd_batch_tuning(self.handle, item)
+
+    def form_times(self):
+        return mvd_batch_form_times(self.handle)
 
     def close(self):
         if self.handle is not None:

@@ -3415,6 +3415,13 @@ mvd_status mvd_batch_info(const mvd_batch *b, int *out) {
   return MVD_OK;
 }
 
+mvd_status mvd_batch_form_times(const mvd_batch *b, double *out) {
+  if (!b || !out) return fail(nullptr, MVD_ERR_ARG, "batch or out is NULL");
+  out[0] = b->form_ms[0];
+  out[1] = b->form_ms[1];
+  return MVD_OK;
+}
+
 mvd_status mvd_batch_tuning(const mvd_batch *b, int item, int *out) {
   if (!b || !out || item < 0 || item >= (int)b->items.size()) return fail(nullptr, MVD_ERR_ARG, "bad batch item");
   const Tune &t = b->items[item].tn;

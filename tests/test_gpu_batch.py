@@ -407,6 +407,8 @@ def test_tuned_batch_keeps_one_form_and_matches_plain():
     plain = [_plain(st) for st in setups]
     b = api.Batch([(st["dec"].ctx, st["obs"], st["est"], st["run"]) for st in setups], tune=True)
     form = b.info()["persistent"]
+    t_pq, t_graph = b.form_times()
+    assert t_pq > 0 and t_graph > 0 and form == (t_pq <= t_graph)
     outs = []
     for _ in range(2):
         for st in setups:
@@ -423,7 +425,7 @@ def test_tuned_batch_keeps_one_form_and_matches_plain():
     given = _planes_case(**_persistent_cases()[6])
     ref = _plain(given)
     b = api.Batch([(given["dec"].ctx, given["obs"], given["est"], given["run"])], tune=True)
-    assert b.info()["persistent"]
+    assert b.info()["persistent"] and b.form_times() == (0.0, 0.0)
     _reset(given)
     b.launch()
     b.wait()
